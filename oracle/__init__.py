@@ -1,0 +1,184 @@
+"""Plain FP64 CPU oracle for the messenger-field Wiener filter.
+
+TEST INFRASTRUCTURE.  Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline
+leg of ``bench.py`` may import this package.  It shares no code with the HIP library: the
+C file ``mfwf_oracle.c`` re-derives geometry, Legendre functions, phi transforms, the SHT,
+the messenger iteration and chi^2 from the paper and textbook definitions, and
+``dense.py`` builds explicit matrices at tiny sizes from SciPy's spherical harmonics.
+
+Array conventions: maps are HEALPix RING order float64; alm are complex128, m-major
+packing (m, l = m..lmax).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mfwf_oracle.c")
+_SO = os.path.join(_HERE, "liboracle.so")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain C99, OpenMP, no FMA contraction)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=gnu99", "-fopenmp", "-ffp-contract=off",
+                               "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib_handle = None
+
+
+def lib():
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        L.or_npix.restype = ctypes.c_long
+        L.or_nalm.restype = ctypes.c_long
+        L.or_tau.restype = ctypes.c_double
+        L.or_ring.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.POINTER(ctypes.c_long),
+                              ctypes.POINTER(ctypes.c_int), _dp]
+        L.or_legendre.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp]
+        L.or_dft.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp]
+        L.or_fft.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp]
+        L.or_alm2map.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int]
+        L.or_map2alm.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int]
+        L.or_tau.argtypes = [ctypes.c_long, _dp]
+        L.or_solve.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, _dp,
+                               ctypes.c_int, _dp, _dp, _dp]
+        L.or_fluct_rho.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp,
+                                   ctypes.c_int]
+        _lib_handle = L
+    return _lib_handle
+
+
+def _p(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _c128(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def num_threads() -> int:
+    return lib().or_num_threads()
+
+
+def nalm(lmax):
+    return (lmax + 1) * (lmax + 2) // 2
+
+
+def ring(nside: int, i: int):
+    """(z, sin theta, start pixel, n_phi, phi_0) of ring i = 1..4 nside - 1."""
+    z, s, p0 = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    st, n = ctypes.c_long(), ctypes.c_int()
+    lib().or_ring(nside, i, ctypes.byref(z), ctypes.byref(s), ctypes.byref(st), ctypes.byref(n),
+                  ctypes.byref(p0))
+    return z.value, s.value, st.value, n.value, p0.value
+
+
+def rings(nside: int):
+    """Arrays over all rings: z, sin theta, start, n_phi, phi_0."""
+    out = [ring(nside, i) for i in range(1, 4 * nside)]
+    return tuple(np.array(c) for c in zip(*out))
+
+
+def pixel_angles(nside: int):
+    """(theta, phi) of every RING-ordered pixel centre, from the oracle geometry."""
+    z, s, start, nphi, phi0 = rings(nside)
+    th, ph = [], []
+    for k in range(len(z)):
+        j = np.arange(nphi[k])
+        th.append(np.full(nphi[k], np.arctan2(s[k], z[k])))
+        ph.append(phi0[k] + 2.0 * np.pi * j / nphi[k])
+    return np.concatenate(th), np.concatenate(ph)
+
+
+def legendre(lmax: int, m: int, z: float, sth: float | None = None) -> np.ndarray:
+    """lambda_lm(z) for l = m..lmax (orthonormal, Condon-Shortley phase)."""
+    if sth is None:
+        sth = float(np.sqrt((1.0 - z) * (1.0 + z)))
+    out = np.zeros(lmax - m + 1)
+    lib().or_legendre(lmax, m, float(z), float(sth), _p(out))
+    return out
+
+
+def dft(x, sign=-1):
+    x = _c128(x)
+    out = np.zeros_like(x)
+    lib().or_dft(len(x), sign, _p(x.view(np.float64)), _p(out.view(np.float64)))
+    return out
+
+
+def fft(x, sign=-1):
+    x = _c128(x)
+    out = np.zeros_like(x)
+    lib().or_fft(len(x), sign, _p(x.view(np.float64)), _p(out.view(np.float64)))
+    return out
+
+
+def alm2map(nside, lmax, alm, direct=False):
+    alm = _c128(alm)
+    assert alm.shape == (nalm(lmax),)
+    out = np.zeros(12 * nside * nside)
+    lib().or_alm2map(nside, lmax, _p(alm.view(np.float64)), _p(out), int(direct))
+    return out
+
+
+def map2alm(nside, lmax, m, direct=False):
+    m = _f64(m)
+    assert m.shape == (12 * nside * nside,)
+    out = np.zeros(nalm(lmax), dtype=np.complex128)
+    lib().or_map2alm(nside, lmax, _p(m), _p(out.view(np.float64)), int(direct))
+    return out
+
+
+def tau(M):
+    M = _f64(M)
+    return lib().or_tau(len(M), _p(M))
+
+
+def solve(nside, lmax, cl, M, rho, niter=None, lam=None, direct=False, diag=False):
+    """Run the messenger iteration; returns (s_alm, s_map[, diag[niter, 4]]).
+
+    lam: per-iteration lambda schedule (default lambda = 1 for niter iterations).
+    diag columns: chi^2(s_k, lambda_k), its harmonic part, |s_k - s_{k-1}|, |s_k|.
+    """
+    if lam is None:
+        lam = np.ones(niter)
+    lam = _f64(lam)
+    niter = len(lam)
+    cl, M, rho = _f64(cl), _f64(M), _f64(rho)
+    npix = 12 * nside * nside
+    assert cl.shape == (lmax + 1,) and M.shape == (npix,) and rho.shape == (npix,)
+    s_alm = np.zeros(nalm(lmax), dtype=np.complex128)
+    s_map = np.zeros(npix)
+    dg = np.zeros((niter, 4)) if diag else None
+    rc = lib().or_solve(nside, lmax, _p(cl), _p(M), _p(rho), niter, _p(lam), int(direct),
+                        _p(s_alm.view(np.float64)), _p(s_map), _p(dg) if diag else None)
+    if rc != 0:
+        raise ValueError("oracle solve failed with status %d (no observed pixel)" % rc)
+    return (s_alm, s_map, dg) if diag else (s_alm, s_map)
+
+
+def fluct_rho(nside, lmax, cl, M, g1, h, direct=False):
+    """Constrained-realisation source rho = M^{1/2} g1 + Omega Y(C^{-1/2} h) (Eq. 9)."""
+    cl, M, g1, h = _f64(cl), _f64(M), _f64(g1), _c128(h)
+    out = np.zeros(12 * nside * nside)
+    lib().or_fluct_rho(nside, lmax, _p(cl), _p(M), _p(g1), _p(h.view(np.float64)), _p(out),
+                       int(direct))
+    return out

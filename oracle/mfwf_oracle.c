@@ -1,0 +1,472 @@
+/*
+ * Plain FP64 CPU oracle for the messenger-field Wiener filter
+ * (Elsner & Wandelt, "Efficient Wiener filtering without preconditioning").
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the benchmark's CPU
+ * baseline may load this library.  It shares no code with the HIP path: geometry,
+ * Legendre recurrence, phi transforms, SHT, messenger iteration and chi^2 are all written
+ * here again, slowly and directly, from the paper and the textbook definitions.
+ *
+ * Conventions (all readings are listed in the design notes):
+ *   maps   HEALPix RING order, double[npix]
+ *   alm    complex m-major packing (m, l = m..lmax), stored as interleaved re/im doubles
+ *   Y      synthesis: f(p) = sum_{l, |m|<=l} a_lm Y_lm(theta_p, phi_p), a_{l,-m} = (-1)^m conj(a_lm)
+ *   A      analysis: a_lm = Omega * sum_p f(p) conj(Y_lm(theta_p, phi_p)),  Omega = 4 pi / npix
+ *          (uniform pixel weights: A is exactly Omega * Y^T in the real harmonic basis)
+ *
+ * Precision: every quantity is double.  Associated-Legendre seeds carry an explicit
+ * power-of-two exponent so that sin(theta)^m never underflows before the l-recurrence has
+ * grown it back into range.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------------------------
+ * HEALPix RING geometry (Gorski et al. 2005, the pixelisation used in Sect. 3).
+ * Rings are numbered i = 1 .. 4 nside - 1 from north to south.
+ *   north cap  i < nside        : z = 1 - i^2/(3 nside^2), 4i pixels, phi_0 = pi/(4i)
+ *   belt       nside <= i <= 3ns: z = 4/3 - 2i/(3 nside), 4 nside pixels,
+ *                                 phi_0 = pi/(4 nside) if (i - nside) even, else 0
+ *   south cap  mirror of the north cap (z -> -z)
+ * Pixel j of a ring sits at phi_0 + 2 pi j / n_phi.
+ * sin(theta) is returned separately, computed from 1 - |z| without cancellation.
+ * ------------------------------------------------------------------------------------ */
+long or_npix(int nside) { return 12L * nside * nside; }
+int or_nrings(int nside) { return 4 * nside - 1; }
+
+void or_ring(int nside, int i, double *z, double *sth, long *start, int *nphi, double *phi0)
+{
+    long ns = nside, npix = 12L * ns * ns;
+    if (i < nside) {
+        double omz = (double)i * i / (3.0 * ns * ns); /* 1 - z */
+        *z = 1.0 - omz;
+        *sth = sqrt(omz * (2.0 - omz));
+        *nphi = 4 * i;
+        *start = 2L * i * (i - 1);
+        *phi0 = M_PI / (4.0 * i);
+    } else if (i <= 3 * nside) {
+        *z = 4.0 / 3.0 - 2.0 * i / (3.0 * ns);
+        *sth = sqrt((1.0 - *z) * (1.0 + *z));
+        *nphi = 4 * nside;
+        *start = 2L * ns * (ns - 1) + (long)(i - nside) * 4L * ns;
+        *phi0 = ((i - nside) % 2 == 0) ? M_PI / (4.0 * ns) : 0.0;
+    } else {
+        int k = 4 * nside - i;
+        double omz = (double)k * k / (3.0 * ns * ns);
+        *z = -(1.0 - omz);
+        *sth = sqrt(omz * (2.0 - omz));
+        *nphi = 4 * k;
+        *start = npix - 2L * k * (k + 1);
+        *phi0 = M_PI / (4.0 * k);
+    }
+}
+
+long or_nalm(int lmax) { return (long)(lmax + 1) * (lmax + 2) / 2; }
+static long aidx(int lmax, int l, int m) { return (long)m * (2 * lmax + 3 - m) / 2 + (l - m); }
+
+/* ------------------------------------------------------------------------------------
+ * Orthonormal associated Legendre functions with the Condon-Shortley phase,
+ *   Y_lm(theta, phi) = lambda_lm(cos theta) e^{i m phi},
+ *   lambda_mm     = (-1)^m sqrt(1/(4 pi)) prod_{k=1..m} sqrt((2k+1)/(2k)) sin(theta)
+ *   lambda_{m+1,m}= sqrt(2m+3) z lambda_mm
+ *   lambda_lm     = (z lambda_{l-1,m} - eps_{l-1,m} lambda_{l-2,m}) / eps_lm,
+ *   eps_lm        = sqrt((l^2 - m^2)/(4 l^2 - 1)).
+ * The running pair is held as (mantissa, shared power-of-two exponent); values are written
+ * out with ldexp, so anything below the double range becomes 0.
+ * eps must hold eps_lm for l = 0..lmax (eps[l] for the given m; eps[m] = 0).
+ * ------------------------------------------------------------------------------------ */
+static void legendre_eps(int lmax, int m, double *eps)
+{
+    for (int l = 0; l <= lmax; l++)
+        eps[l] = (l <= m) ? 0.0 : sqrt(((double)l * l - (double)m * m) / (4.0 * l * l - 1.0));
+}
+
+static void legendre_with_eps(int lmax, int m, double z, double sth, const double *eps,
+                              double *out)
+{
+    int ex;
+    long e = 0;
+    double r = sqrt(1.0 / (4.0 * M_PI));
+    for (int k = 1; k <= m; k++) {
+        r *= -sqrt((2.0 * k + 1.0) / (2.0 * k)) * sth;
+        r = frexp(r, &ex);
+        e += ex;
+    }
+    double p2 = 0.0, p1 = r; /* scaled lambda_{l-2}, lambda_{l-1} */
+    out[0] = ldexp(p1, (int)(e < -2000 ? -2000 : e));
+    for (int l = m + 1; l <= lmax; l++) {
+        double cur = (z * p1 - eps[l - 1] * p2) / eps[l];
+        p2 = p1;
+        p1 = cur;
+        if (fabs(p1) > 0x1p+300) {
+            p1 = ldexp(p1, -300);
+            p2 = ldexp(p2, -300);
+            e += 300;
+        }
+        out[l - m] = ldexp(p1, (int)(e < -2000 ? -2000 : e));
+    }
+}
+
+/* lambda_lm(z), l = m..lmax, written to out[0 .. lmax-m]. */
+void or_legendre(int lmax, int m, double z, double sth, double *out)
+{
+    double *eps = (double *)malloc(sizeof(double) * (lmax + 1));
+    legendre_eps(lmax, m, eps);
+    legendre_with_eps(lmax, m, z, sth, eps, out);
+    free(eps);
+}
+
+/* ------------------------------------------------------------------------------------
+ * Complex DFT, X_k = sum_j x_j exp(sign * 2 pi i j k / n).
+ * or_dft: the definition summed directly, O(n^2).
+ * or_fft: textbook recursive Cooley-Tukey decimation in time over the smallest prime
+ *         factor; a prime length falls back to the direct sum.
+ * ------------------------------------------------------------------------------------ */
+void or_dft(int n, int sign, const double *xin, double *xout)
+{
+    const cplx *x = (const cplx *)xin;
+    cplx *X = (cplx *)xout;
+    for (int k = 0; k < n; k++) {
+        cplx acc = 0;
+        for (int j = 0; j < n; j++) {
+            long jk = ((long)j * k) % n;
+            double a = sign * 2.0 * M_PI * (double)jk / n;
+            acc += x[j] * (cos(a) + I * sin(a));
+        }
+        X[k] = acc;
+    }
+}
+
+static void fft_rec(int n, long stride, const cplx *in, cplx *out, int sign, cplx *scratch)
+{
+    if (n == 1) {
+        out[0] = in[0];
+        return;
+    }
+    int p = n;
+    for (int f = 2; (long)f * f <= n; f++)
+        if (n % f == 0) {
+            p = f;
+            break;
+        }
+    if (p == n) { /* prime length: direct sum */
+        for (int k = 0; k < n; k++) {
+            cplx acc = 0;
+            for (int j = 0; j < n; j++) {
+                long jk = ((long)j * k) % n;
+                double a = sign * 2.0 * M_PI * (double)jk / n;
+                acc += in[j * stride] * (cos(a) + I * sin(a));
+            }
+            out[k] = acc;
+        }
+        return;
+    }
+    int q = n / p;
+    /* sub-transforms of the p decimated sequences x[p*j + r], stored out[r*q + k] */
+    for (int r = 0; r < p; r++)
+        fft_rec(q, stride * p, in + r * stride, out + (long)r * q, sign, scratch + n);
+    /* combine: X[k + q s] = sum_r exp(sign 2 pi i r (k + q s)/n) Y_r[k] */
+    for (int k = 0; k < q; k++)
+        for (int s = 0; s < p; s++) {
+            int kk = k + q * s;
+            cplx acc = 0;
+            for (int r = 0; r < p; r++) {
+                long e = ((long)r * kk) % n;
+                double a = sign * 2.0 * M_PI * (double)e / n;
+                acc += out[(long)r * q + k] * (cos(a) + I * sin(a));
+            }
+            scratch[kk] = acc;
+        }
+    memcpy(out, scratch, sizeof(cplx) * n);
+}
+
+void or_fft(int n, int sign, const double *xin, double *xout)
+{
+    /* scratch: the recursion uses one n-sized block per level, sum over levels <= 2n */
+    cplx *scratch = (cplx *)malloc(sizeof(cplx) * (2 * (size_t)n + 2));
+    fft_rec(n, 1, (const cplx *)xin, (cplx *)xout, sign, scratch);
+    free(scratch);
+}
+
+/* ------------------------------------------------------------------------------------
+ * phi step for one ring.
+ * Synthesis: f_j = sum_{m=-lmax}^{lmax} F(m) e^{i m phi_j},  F(-m) = conj F(m).
+ * Analysis:  G(m) = sum_j t_j e^{-i m phi_j},  m = 0..lmax.
+ * direct = 1: evaluate the sums as written (cos/sin of m phi_j).
+ * direct = 0: fold the harmonics into the n_phi DFT bins (m mod n_phi) with the ring
+ *             offset phase e^{i m phi_0}, then one length-n_phi DFT.
+ * ------------------------------------------------------------------------------------ */
+static void ring_synth(int lmax, int nphi, double phi0, const cplx *F, double *f, int direct)
+{
+    if (direct) {
+        for (int j = 0; j < nphi; j++) {
+            double phi = phi0 + 2.0 * M_PI * j / nphi;
+            double acc = creal(F[0]);
+            for (int m = 1; m <= lmax; m++)
+                acc += 2.0 * (creal(F[m]) * cos(m * phi) - cimag(F[m]) * sin(m * phi));
+            f[j] = acc;
+        }
+        return;
+    }
+    cplx *B = (cplx *)calloc(nphi, sizeof(cplx));
+    cplx *x = (cplx *)malloc(sizeof(cplx) * nphi);
+    for (int m = 0; m <= lmax; m++) {
+        cplx ph = cos(m * phi0) + I * sin(m * phi0);
+        B[m % nphi] += F[m] * ph;
+        if (m > 0)
+            B[(nphi - m % nphi) % nphi] += conj(F[m] * ph);
+    }
+    or_fft(nphi, +1, (const double *)B, (double *)x);
+    for (int j = 0; j < nphi; j++)
+        f[j] = creal(x[j]);
+    free(B);
+    free(x);
+}
+
+static void ring_analysis(int lmax, int nphi, double phi0, const double *t, cplx *G, int direct)
+{
+    if (direct) {
+        for (int m = 0; m <= lmax; m++) {
+            cplx acc = 0;
+            for (int j = 0; j < nphi; j++) {
+                double a = m * (phi0 + 2.0 * M_PI * j / nphi);
+                acc += t[j] * (cos(a) - I * sin(a));
+            }
+            G[m] = acc;
+        }
+        return;
+    }
+    cplx *x = (cplx *)malloc(sizeof(cplx) * nphi);
+    cplx *X = (cplx *)malloc(sizeof(cplx) * nphi);
+    for (int j = 0; j < nphi; j++)
+        x[j] = t[j];
+    or_fft(nphi, -1, (const double *)x, (double *)X);
+    for (int m = 0; m <= lmax; m++)
+        G[m] = X[m % nphi] * (cos(m * phi0) - I * sin(m * phi0));
+    free(x);
+    free(X);
+}
+
+/* ------------------------------------------------------------------------------------
+ * Spin-0 SHT.  Every ring is handled on its own (no north/south pairing).
+ * ------------------------------------------------------------------------------------ */
+void or_alm2map(int nside, int lmax, const double *alm_in, double *map, int direct)
+{
+    const cplx *alm = (const cplx *)alm_in;
+    int nr = or_nrings(nside);
+#pragma omp parallel
+    {
+        double *lam = (double *)malloc(sizeof(double) * (lmax + 1));
+        double *eps = (double *)malloc(sizeof(double) * (lmax + 1));
+        cplx *F = (cplx *)malloc(sizeof(cplx) * (lmax + 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int i = 1; i <= nr; i++) {
+            double z, sth, phi0;
+            long start;
+            int nphi;
+            or_ring(nside, i, &z, &sth, &start, &nphi, &phi0);
+            for (int m = 0; m <= lmax; m++) {
+                legendre_eps(lmax, m, eps);
+                legendre_with_eps(lmax, m, z, sth, eps, lam);
+                cplx acc = 0;
+                for (int l = m; l <= lmax; l++)
+                    acc += lam[l - m] * alm[aidx(lmax, l, m)];
+                F[m] = acc;
+            }
+            ring_synth(lmax, nphi, phi0, F, map + start, direct);
+        }
+        free(lam);
+        free(eps);
+        free(F);
+    }
+}
+
+void or_map2alm(int nside, int lmax, const double *map, double *alm_out, int direct)
+{
+    cplx *alm = (cplx *)alm_out;
+    int nr = or_nrings(nside);
+    double omega = 4.0 * M_PI / (double)or_npix(nside);
+    cplx *G = (cplx *)malloc(sizeof(cplx) * (size_t)nr * (lmax + 1));
+    double *zr = (double *)malloc(sizeof(double) * nr);
+    double *sr = (double *)malloc(sizeof(double) * nr);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 1; i <= nr; i++) {
+        double phi0;
+        long start;
+        int nphi;
+        or_ring(nside, i, &zr[i - 1], &sr[i - 1], &start, &nphi, &phi0);
+        ring_analysis(lmax, nphi, phi0, map + start, G + (size_t)(i - 1) * (lmax + 1), direct);
+    }
+#pragma omp parallel
+    {
+        double *lam = (double *)malloc(sizeof(double) * (lmax + 1));
+        double *eps = (double *)malloc(sizeof(double) * (lmax + 1));
+        cplx *acc = (cplx *)malloc(sizeof(cplx) * (lmax + 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int m = 0; m <= lmax; m++) {
+            legendre_eps(lmax, m, eps);
+            for (int l = m; l <= lmax; l++)
+                acc[l - m] = 0;
+            for (int r = 0; r < nr; r++) {
+                legendre_with_eps(lmax, m, zr[r], sr[r], eps, lam);
+                cplx g = G[(size_t)r * (lmax + 1) + m];
+                for (int l = m; l <= lmax; l++)
+                    acc[l - m] += lam[l - m] * g;
+            }
+            for (int l = m; l <= lmax; l++)
+                alm[aidx(lmax, l, m)] = omega * acc[l - m];
+        }
+        free(lam);
+        free(eps);
+        free(acc);
+    }
+    free(G);
+    free(zr);
+    free(sr);
+}
+
+/* ------------------------------------------------------------------------------------
+ * Messenger-field iteration (Sect. 2.1, Eqs. 3 and 4), temperature.
+ *
+ * M = N^{-1} per pixel (0 in masked pixels), tau = min diag N over observed pixels
+ * = 1 / max M.  With rho = M d (Wiener filter) or the fluctuation source (Eq. 9),
+ * Eq. (3) solved for t and multiplied through by N gives, per pixel,
+ *     t = [lambda tau rho + (1 - tau M) s] / [1 + (lambda - 1) tau M],
+ * which needs no inverse of Nbar = N - tau and is continuous into the mask.
+ * The harmonic-space messenger covariance is tau * Omega (the analysis A = Omega Y^T maps
+ * pixel-white variance tau to tau Omega per real harmonic dof), so Eq. (4) gives
+ *     s_lm = C_l / (C_l + lambda tau Omega) * (A t)_lm,   s_lm = 0 where C_l = 0.
+ * Start s = t = 0, t-update first.  lam[k] is lambda for iteration k.
+ *
+ * diag (optional, [niter][4]) per iteration: chi^2(s, lambda_k) (Eq. 6), its harmonic
+ * part, |s_k - s_{k-1}|, |s_k|, all over the real harmonic dof (m > 0 counted twice).
+ * chi^2 pixel part: sum over M > 0 of (d - s)^2 M / (1 + (lambda-1) tau M) with d = rho/M.
+ * Returns 0, or -4 if max M <= 0 (tau undefined).
+ * ------------------------------------------------------------------------------------ */
+static double alm_dot_w(int lmax, const cplx *a, const cplx *b, const double *w)
+{
+    double acc = 0.0;
+    for (int m = 0; m <= lmax; m++)
+        for (int l = m; l <= lmax; l++) {
+            long k = aidx(lmax, l, m);
+            double wt = (w ? w[l] : 1.0) * (m == 0 ? 1.0 : 2.0);
+            acc += wt * creal(conj(a[k]) * b[k]);
+        }
+    return acc;
+}
+
+double or_tau(long npix, const double *M)
+{
+    double mx = 0.0;
+    for (long p = 0; p < npix; p++)
+        if (M[p] > mx)
+            mx = M[p];
+    return mx > 0.0 ? 1.0 / mx : 0.0;
+}
+
+int or_solve(int nside, int lmax, const double *cl, const double *M, const double *rho,
+             int niter, const double *lam, int direct, double *s_alm_out, double *s_map_out,
+             double *diag)
+{
+    long npix = or_npix(nside), nalm = or_nalm(lmax);
+    double tau = or_tau(npix, M);
+    if (tau <= 0.0)
+        return -4;
+    double omega = 4.0 * M_PI / (double)npix;
+    double *s_map = (double *)calloc(npix, sizeof(double));
+    double *t = (double *)malloc(sizeof(double) * npix);
+    cplx *a = (cplx *)malloc(sizeof(cplx) * nalm);
+    cplx *s = (cplx *)calloc(nalm, sizeof(cplx));
+    cplx *s_old = (cplx *)calloc(nalm, sizeof(cplx));
+    double *icl = (double *)malloc(sizeof(double) * (lmax + 1));
+    for (int l = 0; l <= lmax; l++)
+        icl[l] = cl[l] > 0.0 ? 1.0 / cl[l] : 0.0;
+
+    for (int k = 0; k < niter; k++) {
+        double L = lam[k];
+        for (long p = 0; p < npix; p++)
+            t[p] = (L * tau * rho[p] + (1.0 - tau * M[p]) * s_map[p]) / (1.0 + (L - 1.0) * tau * M[p]);
+        or_map2alm(nside, lmax, t, (double *)a, direct);
+        memcpy(s_old, s, sizeof(cplx) * nalm);
+        for (int m = 0; m <= lmax; m++)
+            for (int l = m; l <= lmax; l++) {
+                long i = aidx(lmax, l, m);
+                s[i] = cl[l] > 0.0 ? cl[l] / (cl[l] + L * tau * omega) * a[i] : 0.0;
+            }
+        or_alm2map(nside, lmax, (const double *)s, s_map, direct);
+        if (diag) {
+            double harm = alm_dot_w(lmax, s, s, icl);
+            double pix = 0.0;
+            for (long p = 0; p < npix; p++)
+                if (M[p] > 0.0) {
+                    double r = rho[p] / M[p] - s_map[p];
+                    pix += r * r * M[p] / (1.0 + (L - 1.0) * tau * M[p]);
+                }
+            for (long i = 0; i < nalm; i++)
+                s_old[i] = s[i] - s_old[i];
+            diag[4 * k + 0] = harm + pix;
+            diag[4 * k + 1] = harm;
+            diag[4 * k + 2] = sqrt(alm_dot_w(lmax, s_old, s_old, NULL));
+            diag[4 * k + 3] = sqrt(alm_dot_w(lmax, s, s, NULL));
+        }
+    }
+    if (s_alm_out)
+        memcpy(s_alm_out, s, sizeof(cplx) * nalm);
+    if (s_map_out)
+        memcpy(s_map_out, s_map, sizeof(double) * npix);
+    free(s_map);
+    free(t);
+    free(a);
+    free(s);
+    free(s_old);
+    free(icl);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Fluctuation source (Sect. 2.3, Eq. 9).  The replacement Nbar^{-1} d ->
+ * Nbar^{-1} N (N^{-1/2} g1 + S^{-1/2} g2) is, in the per-pixel form above, the source
+ *     rho = M^{1/2} g1 + Omega * Y(C^{-1/2} h),
+ * with h unit-white in the real harmonic basis and C^{-1/2} := 0 where C_l = 0.  The
+ * factor Omega makes Y^T rho_2 = (Omega Y^T Y) C^{-1/2} h ~ C^{-1/2} h.  In masked pixels
+ * (M = 0) the update becomes t = s + lambda tau rho, the identity replacement of
+ * Nbar^{-1} N the paper prescribes there.
+ * ------------------------------------------------------------------------------------ */
+void or_fluct_rho(int nside, int lmax, const double *cl, const double *M, const double *g1,
+                  const double *h_in, double *rho, int direct)
+{
+    long npix = or_npix(nside), nalm = or_nalm(lmax);
+    const cplx *h = (const cplx *)h_in;
+    cplx *x = (cplx *)malloc(sizeof(cplx) * nalm);
+    for (int m = 0; m <= lmax; m++)
+        for (int l = m; l <= lmax; l++) {
+            long i = aidx(lmax, l, m);
+            x[i] = cl[l] > 0.0 ? h[i] / sqrt(cl[l]) : 0.0;
+        }
+    or_alm2map(nside, lmax, (const double *)x, rho, direct);
+    double omega = 4.0 * M_PI / (double)npix;
+    for (long p = 0; p < npix; p++)
+        rho[p] = sqrt(M[p]) * g1[p] + omega * rho[p];
+    free(x);
+}
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
