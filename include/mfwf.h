@@ -1,0 +1,174 @@
+/*
+ * mfwf.h -- messenger-field Wiener filter on the HEALPix sphere, HIP library for gfx950.
+ *
+ * Solves (S^-1 + N^-1) s_WF = N^-1 d (Eq. 2 of Elsner & Wandelt, "Efficient Wiener
+ * filtering without preconditioning") with the messenger iteration of Sect. 2.1:
+ * a pixel-space update of the messenger field t (Eq. 3, T = tau*1, Nbar = N - T), a
+ * forward spherical-harmonic transform, a harmonic-space update of s (Eq. 4) and an
+ * inverse transform, repeated.  Fluctuation sources for constrained realisations follow
+ * Sect. 2.3 (Eq. 9).
+ *
+ * Conventions shared by every entry point
+ *   - Maps are HEALPix RING order, npix = 12 nside^2 doubles per map.
+ *   - Harmonic coefficients ("alm") are complex, m-major, (m, l = m..lmax), stored as
+ *     interleaved (re, im) doubles: nalm = (lmax+1)(lmax+2)/2 complex values per map,
+ *     index of (l, m) = m (2 lmax + 3 - m)/2 + (l - m).  a_{l,-m} = (-1)^m conj(a_lm).
+ *   - Synthesis Y: map(p) = sum_{l,|m|<=l} a_lm Y_lm(p).  Analysis A = Omega Y^T:
+ *     a_lm = Omega sum_p map(p) conj(Y_lm(p)), Omega = 4 pi / npix (uniform pixel weights).
+ *   - Batched arrays are map-major: [nmaps][npix] and [nmaps][2*nalm].
+ *   - Every pointer named "device" is a device pointer owned by the caller; the library
+ *     keeps no reference to it after the call returns.  Host pointers are read during the
+ *     call only.
+ *   - All device work is enqueued on the plan's stream (the stream given at plan creation,
+ *     or the null stream).  mfwf_solve and mfwf_set_covariances synchronise that stream
+ *     before returning; the transforms and mfwf_fluctuation_rhs return without waiting.
+ *   - Status: 0 on success, a negative mfwf_status on failure; mfwf_last_error() then
+ *     describes the failure (per calling thread).  On failure, outputs are undefined.
+ *   - A plan serves one host thread / stream at a time; distinct plans are independent.
+ */
+#ifndef MFWF_H
+#define MFWF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mfwf_plan_s *mfwf_plan;
+
+typedef enum {
+    MFWF_OK = 0,
+    MFWF_EINVAL = -1,  /* bad argument (size, pointer, unsupported option)        */
+    MFWF_ENOMEM = -2,  /* device or host allocation failed                         */
+    MFWF_ENOTSPD = -3, /* a noise block is not positive semi-definite              */
+    MFWF_ENOCOV = -4,  /* covariances not set, or no observed pixel (tau undefined) */
+    MFWF_EDEVICE = -5, /* HIP runtime error                                        */
+    MFWF_ENAN = -6     /* non-finite value met in the input or the iterate          */
+} mfwf_status;
+
+typedef enum {
+    MFWF_F64 = 0, /* every step in double precision                               */
+    MFWF_F32 = 1  /* reserved: single-precision bulk Legendre contraction          */
+} mfwf_dtype;
+
+/*
+ * Create a plan for HEALPix resolution nside (power of two, 1..1024) and band limit
+ * lmax (1..4*nside).  spin: 0 = temperature only.  max_batch (>= 1): largest number of
+ * maps one call processes at once (larger calls are split).  hip_stream: a hipStream_t
+ * or NULL for the null stream.  The plan precomputes the ring geometry (HEALPix,
+ * Gorski et al. 2005), the Legendre recurrence coefficients and, for every (m, ring
+ * pair), the first l at which the normalised associated Legendre function exceeds 2^-100
+ * together with its two starting values, and ring-FFT tables.  It allocates its device
+ * workspaces up front.  *out receives the handle.
+ * Errors: MFWF_EINVAL for out-of-range sizes or spin != 0, MFWF_ENOMEM, MFWF_EDEVICE.
+ */
+int mfwf_plan_create(int nside, int lmax, int spin, int dtype, int max_batch, void *hip_stream,
+                     mfwf_plan *out);
+
+/* Release every device and host resource of the plan.  NULL is accepted. */
+int mfwf_plan_destroy(mfwf_plan plan);
+
+/*
+ * Set the signal and noise covariances (Sect. 2.1, Eq. 2).
+ *   cl    host, [ncl][lmax+1] signal power spectrum C_l (ncl = 1 for temperature);
+ *         C_l = 0 removes the multipole from the solution.  Negative C_l -> MFWF_EINVAL.
+ *   ninv  device, [npix] inverse noise variance N^-1 per pixel (>= 0).
+ *   mask  device, [npix] uint8, 1 = observed, 0 = masked (M = 0); NULL = all observed.
+ * The plan stores M = ninv * mask and tau = min diag N over observed pixels = 1 / max M.
+ * Errors: MFWF_ENOCOV if max M <= 0, MFWF_ENAN if M has a non-finite or negative entry.
+ */
+int mfwf_set_covariances(mfwf_plan plan, const double *cl, int ncl, const double *ninv,
+                         const uint8_t *mask);
+
+/*
+ * Synthesis map = Y alm for nmaps maps (the inverse transform that closes each
+ * iteration, Sect. 2.1).  alm: device [nmaps][2*nalm]; map: device [nmaps][npix].
+ */
+int mfwf_sht_inv(mfwf_plan plan, const double *alm, double *map, int nmaps);
+
+/*
+ * Analysis alm = Omega Y^T map for nmaps maps (the forward transform of Sect. 2.1).
+ * map: device [nmaps][npix]; alm: device [nmaps][2*nalm].
+ */
+int mfwf_sht_fwd(mfwf_plan plan, const double *map, double *alm, int nmaps);
+
+/*
+ * Constrained-realisation source (Sect. 2.3, Eq. 9): the replacement
+ * Nbar^-1 d -> Nbar^-1 N (N^-1/2 g1 + S^-1/2 g2) becomes, in the per-pixel form used by
+ * mfwf_solve, the source
+ *     rho = M^{1/2} g1 + Omega * Y(C^{-1/2} h)
+ * (C^{-1/2} := 0 where C_l = 0).  Masked pixels (M = 0) automatically receive the
+ * identity replacement of Nbar^-1 N that the paper prescribes.
+ *   g1   device [nrhs][npix] unit normal draws per pixel.
+ *   h    device [nrhs][2*nalm] unit-white harmonic draws in the real basis, complex
+ *        packing: m = 0 entries real N(0,1), m > 0 entries (x + i y)/sqrt(2).
+ *   rho  device [nrhs][npix] output; pass it to mfwf_solve with source_is_rho = 1.
+ * Requires mfwf_set_covariances.  The draws are inputs: the library draws nothing.
+ */
+int mfwf_fluctuation_rhs(mfwf_plan plan, const double *g1, const double *h, int nrhs,
+                         double *rho);
+
+/* Iteration schedule and options for mfwf_solve. */
+typedef struct {
+    int n_stages;          /* number of (lambda, iters) stages; 0 = one stage {1.0, 300} */
+    const double *lambda;  /* host [n_stages], each >= 1 (Sect. 2.2)                     */
+    const int *iters;      /* host [n_stages], iterations per stage (>= 0)              */
+    int n_check;           /* diagnostics every n_check iterations (0 = only at the end) */
+    double dchi2_tol;      /* reserved, must be 0: a fixed number of iterations is run   */
+    int source_is_rho;     /* 0: input is the data d (rho = M d); 1: input is rho        */
+    int use_graph;         /* 1: replay each iteration as a captured hipGraph            */
+} mfwf_solve_opts;
+
+/* Per-map diagnostics after the last iteration (Eq. 6 and Sect. 2.2). */
+typedef struct {
+    int iters_done;    /* iterations run                                               */
+    double lambda;     /* lambda of the last iteration                                 */
+    double chi2;       /* chi^2(s, lambda) of Eq. (6) at the final iterate             */
+    double chi2_harm;  /* its harmonic part s^T S^-1 s                                 */
+    double dnorm;      /* |s_k - s_{k-1}| over the real harmonic dof (m > 0 twice)     */
+    double snorm;      /* |s_k|                                                        */
+    double tau;        /* tau = 1 / max M                                              */
+    long n_dof;        /* number of observed pixels (chi^2 degrees of freedom)          */
+} mfwf_solve_info;
+
+/*
+ * Run the messenger iteration for nmaps right-hand sides.
+ *   input      device [nmaps][npix]: d (source_is_rho = 0) or rho (source_is_rho = 1).
+ *   s_alm_out  device [nmaps][2*nalm] or NULL: final harmonic iterate s_lm.
+ *   s_map_out  device [nmaps][npix] or NULL: its synthesis Y s.
+ *   opts       NULL = lambda = 1 for 300 iterations.
+ *   info       host [nmaps] or NULL.
+ * Starts from s = t = 0; each iteration at lambda runs, per pixel,
+ *     t = [lambda tau rho + (1 - tau M) s] / [1 + (lambda - 1) tau M]
+ * (Eq. 3 multiplied through by N, no inverse of Nbar), then
+ *     s_lm = C_l / (C_l + lambda tau Omega) * (A t)_lm     (Eq. 4, T = tau Omega per
+ * harmonic dof under A = Omega Y^T), then s = Y s_lm.  Non-convergence is not an error.
+ */
+int mfwf_solve(mfwf_plan plan, const double *input, int nmaps, double *s_alm_out,
+               double *s_map_out, const mfwf_solve_opts *opts, mfwf_solve_info *info);
+
+/*
+ * Time the plan's kernels on its stream with HIP events (diagnostic).  Runs `reps`
+ * back-to-back launches of each stage of one iteration on the current workspaces for
+ * nmaps maps and writes the mean duration in milliseconds of each kernel to ms_out:
+ * [0] pixel update, [1] forward ring FFT, [2] Legendre analysis, [3] harmonic update,
+ * [4] Legendre synthesis, [5] inverse ring FFT.  Requires mfwf_set_covariances.
+ */
+int mfwf_time_kernels(mfwf_plan plan, int nmaps, int reps, double *ms_out);
+
+/*
+ * Work statistics of the plan (host, 4 doubles):
+ * [0] (l, m, ring pair) triples the Legendre steps evaluate, i.e. l >= the pair's start
+ *     index (terms below 2^-100 skipped); [1] the full triangle: ring pairs * nalm;
+ * [2] ring pairs; [3] the largest ring-FFT length used.
+ */
+int mfwf_plan_work(mfwf_plan plan, double *out4);
+
+/* Message describing the last failure on this thread ("" if none). */
+const char *mfwf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFWF_H */

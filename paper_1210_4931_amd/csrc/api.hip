@@ -1,0 +1,653 @@
+// C-ABI of the mfwf library: plan construction (HEALPix ring geometry, Legendre recurrence
+// tables and start seeds, ring-FFT tables), covariance set-up, the transforms, the
+// fluctuation source and the messenger-iteration driver (Sect. 2.1 of the paper).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "mfwf_internal.h"
+
+struct mfwf_plan_s {
+    mfwf::Plan p;
+};
+
+namespace mfwf {
+
+int fft_set_lds_limit(size_t bytes);  // ringfft.hip
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+
+static int fail(int status, const std::string &msg) {
+    set_error(msg);
+    return status;
+}
+
+template <typename T>
+static int dalloc(T **ptr, size_t count, const char *what) {
+    *ptr = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)ptr, sizeof(T) * count);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        return fail(MFWF_ENOMEM, std::string("hipMalloc of ") + what + " (" +
+                                     std::to_string(sizeof(T) * count) + " bytes) failed: " +
+                                     hipGetErrorString(e));
+    }
+    return MFWF_OK;
+}
+
+template <typename T>
+static int upload(T *dst, const std::vector<T> &src, hipStream_t s) {
+    MFWF_HIP(hipMemcpyAsync(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, s));
+    return MFWF_OK;
+}
+
+// ---- host-side plan tables ----------------------------------------------------------------
+
+struct RingGeom {
+    double z, sth, phi0_over_pi_n;  // phi0 = pi/n * half_shift
+    int nphi, half_shift;
+    long start;
+};
+
+// HEALPix RING ring i (1-based, north to south).
+static RingGeom ring_geom(int nside, int i) {
+    RingGeom r{};
+    const double ns = nside;
+    const long npix = 12L * nside * nside;
+    if (i < nside) {
+        const double omz = (double)i * i / (3.0 * ns * ns);
+        r.z = 1.0 - omz;
+        r.sth = std::sqrt(omz * (2.0 - omz));
+        r.nphi = 4 * i;
+        r.start = 2L * i * (i - 1);
+        r.half_shift = 1;
+    } else if (i <= 3 * nside) {
+        r.z = 4.0 / 3.0 - 2.0 * i / (3.0 * ns);
+        r.sth = std::sqrt((1.0 - r.z) * (1.0 + r.z));
+        r.nphi = 4 * nside;
+        r.start = 2L * nside * (nside - 1) + (long)(i - nside) * 4L * nside;
+        r.half_shift = ((i - nside) % 2 == 0) ? 1 : 0;
+    } else {
+        const int k = 4 * nside - i;
+        const double omz = (double)k * k / (3.0 * ns * ns);
+        r.z = -(1.0 - omz);
+        r.sth = std::sqrt(omz * (2.0 - omz));
+        r.nphi = 4 * k;
+        r.start = npix - 2L * k * (k + 1);
+        r.half_shift = 1;
+    }
+    return r;
+}
+
+static bool is_pow2(long n) { return n > 0 && (n & (n - 1)) == 0; }
+static int next_pow2(long n) {
+    int v = 1;
+    while (v < n) v <<= 1;
+    return v;
+}
+
+// In-place radix-2 forward DFT (natural order in and out) for plan-time tables.
+static void host_fft(std::vector<double2> &x) {
+    const int n = (int)x.size();
+    for (int i = 1, j = 0; i < n; i++) {
+        int bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(x[i], x[j]);
+    }
+    for (int len = 2; len <= n; len <<= 1) {
+        for (int k = 0; k < len / 2; k++) {
+            const double a = -2.0 * M_PI * k / len;
+            const double wr = std::cos(a), wi = std::sin(a);
+            for (int i = k; i < n; i += len) {
+                double2 u = x[i], v = x[i + len / 2];
+                double2 t = make_double2(v.x * wr - v.y * wi, v.x * wi + v.y * wr);
+                x[i] = make_double2(u.x + t.x, u.y + t.y);
+                x[i + len / 2] = make_double2(u.x - t.x, u.y - t.y);
+            }
+        }
+    }
+}
+
+static int bitrev_host(int k, int logn) {
+    int r = 0;
+    for (int b = 0; b < logn; b++)
+        if (k & (1 << b)) r |= 1 << (logn - 1 - b);
+    return r;
+}
+
+// Recurrence coefficients for lambda_l = alpha z lambda_{l-1} - beta lambda_{l-2}:
+// eps_lm = sqrt((l^2 - m^2)/(4 l^2 - 1)), alpha = 1/eps_lm, beta = eps_{l-1,m}/eps_lm;
+// (alpha, beta) = (0, 0) at l = m, where the value comes from the seed.
+static void build_recurrence(int lmax, std::vector<double2> &ab, std::vector<long> &mofs) {
+    const long nalm = (long)(lmax + 1) * (lmax + 2) / 2;
+    ab.assign(nalm, make_double2(0.0, 0.0));
+    mofs.resize(lmax + 1);
+    for (int m = 0; m <= lmax; m++) {
+        const long off = (long)m * (2 * lmax + 3 - m) / 2;
+        mofs[m] = off;
+        double eps_prev = 0.0;  // eps_{m,m} = 0
+        for (int l = m + 1; l <= lmax; l++) {
+            const double eps = std::sqrt(((double)l * l - (double)m * m) / (4.0 * l * l - 1.0));
+            ab[off + l - m] = make_double2(1.0 / eps, eps_prev / eps);
+            eps_prev = eps;
+        }
+    }
+}
+
+// For every (m, pair): first l with |lambda_lm(z)| >= 2^-100 and (lambda_{l-1}, lambda_l).
+// lambda_mm = (-1)^m sqrt(1/4pi) prod_{k<=m} sqrt((2k+1)/(2k)) sin(theta) is carried as a
+// mantissa and a power-of-two exponent (it underflows double long before m = lmax near
+// the poles); the l-recurrence is run in the same scaled form until the threshold.
+static void build_seeds(int lmax, int npair, const std::vector<RingGeom> &geo,
+                        const std::vector<double2> &ab, const std::vector<long> &mofs,
+                        std::vector<int> &lstart, std::vector<double2> &seed) {
+    const int nm = lmax + 1;
+    lstart.assign((size_t)nm * npair, lmax + 1);
+    seed.assign((size_t)nm * npair, make_double2(0.0, 0.0));
+    auto work = [&](int p0, int p1) {
+        for (int p = p0; p < p1; p++) {
+            const double z = geo[p].z, sth = geo[p].sth;
+            int ex;
+            double rmm = std::frexp(std::sqrt(1.0 / (4.0 * M_PI)), &ex);
+            long emm = ex;
+            for (int m = 0; m <= lmax; m++) {
+                if (m > 0) {
+                    rmm *= -std::sqrt((2.0 * m + 1.0) / (2.0 * m)) * sth;
+                    rmm = std::frexp(rmm, &ex);
+                    emm += ex;
+                }
+                double p1v = rmm, p2v = 0.0;
+                long e = emm;
+                auto thr_of = [](long e_) {
+                    const long t = -100 - e_;
+                    return t > 1000 ? INFINITY : std::ldexp(1.0, (int)t);
+                };
+                double thr = thr_of(e);
+                const double2 *abm = ab.data() + mofs[m] - m;
+                const size_t slot = (size_t)m * npair + p;
+                for (int l = m;; l++) {
+                    if (l > m) {
+                        const double2 c = abm[l];
+                        const double cur = c.x * (z * p1v) - c.y * p2v;
+                        p2v = p1v;
+                        p1v = cur;
+                        if (std::fabs(p1v) > 0x1p+300) {
+                            p1v = std::ldexp(p1v, -300);
+                            p2v = std::ldexp(p2v, -300);
+                            e += 300;
+                            thr = thr_of(e);
+                        }
+                    }
+                    if (std::fabs(p1v) >= thr) {
+                        lstart[slot] = l;
+                        seed[slot] = make_double2(std::ldexp(p2v, (int)e), std::ldexp(p1v, (int)e));
+                        break;
+                    }
+                    if (l == lmax) break;
+                }
+            }
+        }
+    };
+    unsigned nt = std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    if ((int)nt > npair) nt = npair;
+    std::vector<std::thread> th;
+    const int chunk = (npair + nt - 1) / nt;
+    for (unsigned t = 0; t < nt; t++) {
+        const int a = t * chunk, b = std::min(npair, (int)(t + 1) * chunk);
+        if (a < b) th.emplace_back(work, a, b);
+    }
+    for (auto &t : th) t.join();
+}
+
+static void free_plan(Plan &p) {
+    void *ptrs[] = {p.d_z, p.d_ab, p.d_lstart, p.d_seed, p.d_pfft, p.d_tw, p.d_chirp, p.d_bhat,
+                    p.d_mofs, p.d_cl, p.d_M, p.d_rho, p.d_t, p.d_smap, p.d_phase, p.d_apart,
+                    p.d_salm, p.d_salm_prev, p.d_red, p.d_diag};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+}
+
+static int check_device() {
+    int dev = 0;
+    MFWF_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    MFWF_HIP(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(MFWF_EDEVICE, std::string("library is built for gfx950, device is ") +
+                                      prop.gcnArchName);
+    return MFWF_OK;
+}
+
+static int create(int nside, int lmax, int spin, int dtype, int max_batch, void *stream,
+                  Plan &p) {
+    if (nside < 1 || nside > 1024 || !is_pow2(nside))
+        return fail(MFWF_EINVAL, "nside must be a power of two in [1, 1024]");
+    if (lmax < 1 || lmax > 4 * nside) return fail(MFWF_EINVAL, "lmax must be in [1, 4 nside]");
+    if (spin != 0) return fail(MFWF_EINVAL, "only spin 0 (temperature) is supported");
+    if (dtype != MFWF_F64) return fail(MFWF_EINVAL, "only MFWF_F64 is supported");
+    if (max_batch < 1 || max_batch > 4096) return fail(MFWF_EINVAL, "max_batch out of range");
+    MFWF_TRY(check_device());
+
+    p.nside = nside;
+    p.lmax = lmax;
+    p.spin = spin;
+    p.dtype = dtype;
+    p.max_batch = max_batch;
+    p.stream = (hipStream_t)stream;
+    p.npix = 12L * nside * nside;
+    p.nring = 4 * nside - 1;
+    p.npair = 2 * nside;
+    p.nm = lmax + 1;
+    p.nalm = (long)(lmax + 1) * (lmax + 2) / 2;
+    p.omega = 4.0 * M_PI / (double)p.npix;
+    p.P = std::max(1, std::min(4, p.npair / 256));
+    p.ngroup = (p.npair + 64 * p.P - 1) / (64 * p.P);
+
+    // geometry of the north ring of every pair
+    std::vector<RingGeom> geo(p.npair);
+    std::vector<double> zp(p.npair);
+    for (int q = 0; q < p.npair; q++) {
+        geo[q] = ring_geom(nside, q + 1);
+        zp[q] = geo[q].z;
+    }
+    std::vector<double2> ab;
+    std::vector<long> mofs;
+    build_recurrence(lmax, ab, mofs);
+    std::vector<int> lstart;
+    std::vector<double2> seed;
+    build_seeds(lmax, p.npair, geo, ab, mofs, lstart, seed);
+    p.work_tuples = 0.0;
+    for (int ls : lstart) p.work_tuples += (ls <= lmax) ? (double)(lmax - ls + 1) : 0.0;
+
+    // ring FFT tables
+    std::vector<PairFFT> pf(p.npair);
+    std::vector<double2> chirp, bhat;
+    int fftmax = 1;
+    for (int q = 0; q < p.npair; q++) {
+        const RingGeom &g = geo[q];
+        PairFFT &f = pf[q];
+        f.nphi = g.nphi;
+        f.half_shift = g.half_shift;
+        f.startN = g.start;
+        const int iS = 4 * nside - (q + 1);
+        f.startS = (iS == q + 1) ? g.start : ring_geom(nside, iS).start;
+        f.bluestein = is_pow2(g.nphi) ? 0 : 1;
+        f.fftlen = f.bluestein ? next_pow2(2L * g.nphi - 1) : g.nphi;
+        fftmax = std::max(fftmax, f.fftlen);
+        f.chirp_off = f.bhat_off = 0;
+        if (f.bluestein) {
+            const int n = g.nphi, M = f.fftlen;
+            f.chirp_off = (long)chirp.size();
+            for (long k = 0; k < n; k++) {  // c_k = exp(-i pi k^2 / n)
+                const long r = (k * k) % (2L * n);
+                const double a = M_PI * (double)r / n;
+                chirp.push_back(make_double2(std::cos(a), -std::sin(a)));
+            }
+            std::vector<double2> b(M, make_double2(0.0, 0.0));  // conj(c), wrapped
+            for (long k = 0; k < n; k++) {
+                const double2 c = chirp[f.chirp_off + k];
+                b[k] = make_double2(c.x, -c.y);
+                if (k > 0) b[M - k] = make_double2(c.x, -c.y);
+            }
+            host_fft(b);
+            int logM = 0;
+            while ((1 << logM) < M) logM++;
+            f.bhat_off = (long)bhat.size();
+            bhat.resize(bhat.size() + M);
+            for (int k = 0; k < M; k++)
+                bhat[f.bhat_off + bitrev_host(k, logM)] = make_double2(b[k].x / M, b[k].y / M);
+        }
+    }
+    p.fftmax = fftmax;
+    std::vector<double2> tw(fftmax);
+    for (int k = 0; k < fftmax; k++) {
+        const double a = -2.0 * M_PI * (double)k / fftmax;
+        tw[k] = make_double2(std::cos(a), std::sin(a));
+    }
+    const size_t lds = sizeof(double2) * (size_t)fftmax;
+    {
+        int dev = 0, maxlds = 0;
+        MFWF_HIP(hipGetDevice(&dev));
+        MFWF_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        if (lds + 8192 > (size_t)maxlds)
+            return fail(MFWF_EINVAL, "ring FFT of length " + std::to_string(fftmax) +
+                                         " does not fit the device LDS");
+        if (lds > 65536) MFWF_TRY(fft_set_lds_limit(lds));
+    }
+
+    const long B = max_batch;
+    MFWF_TRY(dalloc(&p.d_z, p.npair, "z"));
+    MFWF_TRY(dalloc(&p.d_ab, ab.size(), "recurrence"));
+    MFWF_TRY(dalloc(&p.d_mofs, mofs.size(), "m offsets"));
+    MFWF_TRY(dalloc(&p.d_lstart, lstart.size(), "l start"));
+    MFWF_TRY(dalloc(&p.d_seed, seed.size(), "seeds"));
+    MFWF_TRY(dalloc(&p.d_pfft, pf.size(), "fft plan"));
+    MFWF_TRY(dalloc(&p.d_tw, tw.size(), "twiddles"));
+    MFWF_TRY(dalloc(&p.d_chirp, std::max<size_t>(1, chirp.size()), "chirp"));
+    MFWF_TRY(dalloc(&p.d_bhat, std::max<size_t>(1, bhat.size()), "chirp kernel"));
+    MFWF_TRY(dalloc(&p.d_cl, lmax + 1, "cl"));
+    MFWF_TRY(dalloc(&p.d_M, p.npix, "M"));
+    MFWF_TRY(dalloc(&p.d_rho, B * p.npix, "rho"));
+    MFWF_TRY(dalloc(&p.d_t, B * p.npix, "t"));
+    MFWF_TRY(dalloc(&p.d_smap, B * p.npix, "s map"));
+    MFWF_TRY(dalloc(&p.d_phase, B * p.nm * p.nring, "ring Fourier"));
+    MFWF_TRY(dalloc(&p.d_apart, (long)p.ngroup * B * p.nalm, "analysis partials"));
+    MFWF_TRY(dalloc(&p.d_salm, B * p.nalm, "s alm"));
+    MFWF_TRY(dalloc(&p.d_salm_prev, B * p.nalm, "previous s alm"));
+    p.nred_blocks = 1024;
+    MFWF_TRY(dalloc(&p.d_red, std::max<long>(3L * p.nred_blocks, std::max<long>(B * p.nred_blocks, 3L * B * p.nm)), "reductions"));
+    MFWF_TRY(dalloc(&p.d_diag, 8 * B, "diagnostics"));
+
+    MFWF_TRY(upload(p.d_z, zp, p.stream));
+    MFWF_TRY(upload(p.d_ab, ab, p.stream));
+    MFWF_TRY(upload(p.d_mofs, mofs, p.stream));
+    MFWF_TRY(upload(p.d_lstart, lstart, p.stream));
+    MFWF_TRY(upload(p.d_seed, seed, p.stream));
+    MFWF_TRY(upload(p.d_pfft, pf, p.stream));
+    MFWF_TRY(upload(p.d_tw, tw, p.stream));
+    if (!chirp.empty()) MFWF_TRY(upload(p.d_chirp, chirp, p.stream));
+    if (!bhat.empty()) MFWF_TRY(upload(p.d_bhat, bhat, p.stream));
+    // defined contents everywhere (workspaces are read by mfwf_time_kernels before any solve)
+    MFWF_TRY(launch_fill(p.d_cl, lmax + 1, 0.0, p.stream));
+    MFWF_TRY(launch_fill(p.d_M, p.npix, 0.0, p.stream));
+    MFWF_TRY(launch_fill(p.d_rho, B * p.npix, 0.0, p.stream));
+    MFWF_TRY(launch_fill(p.d_t, B * p.npix, 0.0, p.stream));
+    MFWF_TRY(launch_fill(p.d_smap, B * p.npix, 0.0, p.stream));
+    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_phase), 2 * B * p.nm * p.nring, 0.0, p.stream));
+    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_apart), 2L * p.ngroup * B * p.nalm, 0.0, p.stream));
+    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm), 2 * B * p.nalm, 0.0, p.stream));
+    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm_prev), 2 * B * p.nalm, 0.0, p.stream));
+    MFWF_HIP(hipStreamSynchronize(p.stream));
+    return MFWF_OK;
+}
+
+// ---- driver ------------------------------------------------------------------------------
+
+static int iteration(Plan &p, const double *rho, int nb, double lam, bool keep_prev) {
+    MFWF_TRY(launch_pixel_update(rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, lam, p.tau, p.stream));
+    MFWF_TRY(launch_fft_fwd(p, p.d_t, p.d_phase, nb));
+    MFWF_TRY(launch_leg_analysis(p, p.d_phase, p.d_apart, nb));
+    MFWF_TRY(launch_harmonic(p, p.d_apart, p.ngroup, p.omega, p.d_cl, lam * p.tau * p.omega, 0,
+                             p.d_salm, p.d_salm_prev, nb, keep_prev));
+    MFWF_TRY(launch_leg_synth(p, p.d_salm, p.d_phase, nb));
+    MFWF_TRY(launch_fft_inv(p, p.d_phase, p.d_smap, nb));
+    return MFWF_OK;
+}
+
+static int run_stage_graph(Plan &p, const double *rho, int nb, double lam, int count) {
+    if (count <= 0) return MFWF_OK;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    MFWF_HIP(hipStreamBeginCapture(p.stream, hipStreamCaptureModeThreadLocal));
+    int st = iteration(p, rho, nb, lam, false);
+    hipError_t e = hipStreamEndCapture(p.stream, &graph);
+    if (st != MFWF_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(MFWF_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(MFWF_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    for (int k = 0; k < count && e == hipSuccess; k++) e = hipGraphLaunch(exec, p.stream);
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(MFWF_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+    return MFWF_OK;
+}
+
+static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
+                       double *s_map_out, const mfwf_solve_opts &o,
+                       const std::vector<double> &lam, const std::vector<int> &its,
+                       mfwf_solve_info *info) {
+    const double *rho = input;
+    if (!o.source_is_rho) {
+        MFWF_TRY(launch_rho_from_data(input, p.d_M, p.d_rho, p.npix, nb, p.stream));
+        rho = p.d_rho;
+    }
+    MFWF_TRY(launch_fill(p.d_smap, p.npix * nb, 0.0, p.stream));
+    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm), 2 * p.nalm * nb, 0.0, p.stream));
+    long total = 0;
+    for (int it : its) total += it;
+    long done = 0;
+    double last_lam = 1.0;
+    const bool graph = o.use_graph && p.stream != nullptr;
+    for (size_t s = 0; s < lam.size(); s++) {
+        int n = its[s];
+        if (n <= 0) continue;
+        last_lam = lam[s];
+        const bool has_last = (done + n == total);
+        int plain = has_last ? n - 1 : n;
+        if (graph && plain >= 2) {
+            MFWF_TRY(run_stage_graph(p, rho, nb, lam[s], plain));
+        } else {
+            for (int k = 0; k < plain; k++) MFWF_TRY(iteration(p, rho, nb, lam[s], false));
+        }
+        if (has_last) MFWF_TRY(iteration(p, rho, nb, lam[s], true));
+        done += n;
+    }
+    if (total > 0) {
+        MFWF_TRY(launch_chi2_pix(rho, p.d_M, p.d_smap, p.npix, nb, last_lam, p.tau, p.d_red,
+                                 p.nred_blocks, p.d_diag, p.stream));
+        MFWF_TRY(launch_harm_diag(p, p.d_salm, p.d_salm_prev, p.d_cl, nb, p.d_red, 0, p.d_diag));
+    } else {
+        MFWF_TRY(launch_fill(p.d_diag, 8L * nb, 0.0, p.stream));
+    }
+    if (s_alm_out)
+        MFWF_HIP(hipMemcpyAsync(s_alm_out, p.d_salm, sizeof(double2) * p.nalm * nb,
+                                hipMemcpyDeviceToDevice, p.stream));
+    if (s_map_out)
+        MFWF_HIP(hipMemcpyAsync(s_map_out, p.d_smap, sizeof(double) * p.npix * nb,
+                                hipMemcpyDeviceToDevice, p.stream));
+    if (info) {
+        std::vector<double> dg(8L * nb);
+        MFWF_HIP(hipMemcpyAsync(dg.data(), p.d_diag, sizeof(double) * dg.size(),
+                                hipMemcpyDeviceToHost, p.stream));
+        MFWF_HIP(hipStreamSynchronize(p.stream));
+        for (int b = 0; b < nb; b++) {
+            mfwf_solve_info &in = info[b];
+            in.iters_done = (int)total;
+            in.lambda = last_lam;
+            in.chi2 = dg[8 * b + 0] + dg[8 * b + 1];
+            in.chi2_harm = dg[8 * b + 1];
+            in.dnorm = std::sqrt(dg[8 * b + 2]);
+            in.snorm = std::sqrt(dg[8 * b + 3]);
+            in.tau = p.tau;
+            in.n_dof = p.ndof;
+        }
+    }
+    return MFWF_OK;
+}
+
+}  // namespace mfwf
+
+using namespace mfwf;
+
+extern "C" {
+
+const char *mfwf_last_error(void) { return g_err.c_str(); }
+
+int mfwf_plan_create(int nside, int lmax, int spin, int dtype, int max_batch, void *hip_stream,
+                     mfwf_plan *out) {
+    if (!out) return fail(MFWF_EINVAL, "out is NULL");
+    *out = nullptr;
+    auto *h = new (std::nothrow) mfwf_plan_s();
+    if (!h) return fail(MFWF_ENOMEM, "host allocation failed");
+    int st = create(nside, lmax, spin, dtype, max_batch, hip_stream, h->p);
+    if (st != MFWF_OK) {
+        free_plan(h->p);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return MFWF_OK;
+}
+
+int mfwf_plan_destroy(mfwf_plan plan) {
+    if (!plan) return MFWF_OK;
+    (void)hipStreamSynchronize(plan->p.stream);
+    free_plan(plan->p);
+    delete plan;
+    return MFWF_OK;
+}
+
+int mfwf_set_covariances(mfwf_plan plan, const double *cl, int ncl, const double *ninv,
+                         const uint8_t *mask) {
+    if (!plan || !cl || !ninv) return fail(MFWF_EINVAL, "NULL argument");
+    Plan &p = plan->p;
+    if (ncl != 1) return fail(MFWF_EINVAL, "ncl must be 1 for temperature");
+    std::vector<double> c(cl, cl + p.lmax + 1);
+    for (double v : c)
+        if (!(v >= 0.0) || std::isinf(v)) return fail(MFWF_EINVAL, "C_l must be finite and >= 0");
+    MFWF_TRY(upload(p.d_cl, c, p.stream));
+    MFWF_TRY(launch_mask_product(ninv, mask, p.d_M, p.npix, p.stream));
+    MFWF_TRY(launch_reduce_max_count(p.d_M, p.npix, p.d_red, p.nred_blocks, p.d_diag, p.stream));
+    double r[3];
+    MFWF_HIP(hipMemcpyAsync(r, p.d_diag, sizeof(r), hipMemcpyDeviceToHost, p.stream));
+    MFWF_HIP(hipStreamSynchronize(p.stream));
+    p.have_cov = false;
+    if (r[2] > 0.0) return fail(MFWF_ENAN, "inverse noise has negative or non-finite entries");
+    if (!(r[0] > 0.0)) return fail(MFWF_ENOCOV, "no observed pixel: max N^-1 * mask is 0, tau undefined");
+    p.tau = 1.0 / r[0];
+    p.ndof = (long)r[1];
+    p.have_cov = true;
+    return MFWF_OK;
+}
+
+int mfwf_sht_inv(mfwf_plan plan, const double *alm, double *map, int nmaps) {
+    if (!plan || nmaps < 0) return fail(MFWF_EINVAL, "bad argument");
+    if (nmaps == 0) return MFWF_OK;
+    if (!alm || !map) return fail(MFWF_EINVAL, "NULL array");
+    Plan &p = plan->p;
+    for (int b0 = 0; b0 < nmaps; b0 += p.max_batch) {
+        const int nb = std::min(p.max_batch, nmaps - b0);
+        MFWF_TRY(launch_leg_synth(p, reinterpret_cast<const double2 *>(alm) + (long)b0 * p.nalm,
+                                  p.d_phase, nb));
+        MFWF_TRY(launch_fft_inv(p, p.d_phase, map + (long)b0 * p.npix, nb));
+    }
+    return MFWF_OK;
+}
+
+int mfwf_sht_fwd(mfwf_plan plan, const double *map, double *alm, int nmaps) {
+    if (!plan || nmaps < 0) return fail(MFWF_EINVAL, "bad argument");
+    if (nmaps == 0) return MFWF_OK;
+    if (!alm || !map) return fail(MFWF_EINVAL, "NULL array");
+    Plan &p = plan->p;
+    for (int b0 = 0; b0 < nmaps; b0 += p.max_batch) {
+        const int nb = std::min(p.max_batch, nmaps - b0);
+        MFWF_TRY(launch_fft_fwd(p, map + (long)b0 * p.npix, p.d_phase, nb));
+        MFWF_TRY(launch_leg_analysis(p, p.d_phase, p.d_apart, nb));
+        MFWF_TRY(launch_harmonic(p, p.d_apart, p.ngroup, p.omega, p.d_cl, 0.0, 1,
+                                 reinterpret_cast<double2 *>(alm) + (long)b0 * p.nalm, nullptr,
+                                 nb, false));
+    }
+    return MFWF_OK;
+}
+
+int mfwf_fluctuation_rhs(mfwf_plan plan, const double *g1, const double *h, int nrhs,
+                         double *rho) {
+    if (!plan || nrhs < 0) return fail(MFWF_EINVAL, "bad argument");
+    Plan &p = plan->p;
+    if (!p.have_cov) return fail(MFWF_ENOCOV, "covariances not set");
+    if (nrhs == 0) return MFWF_OK;
+    if (!g1 || !h || !rho) return fail(MFWF_EINVAL, "NULL array");
+    for (int b0 = 0; b0 < nrhs; b0 += p.max_batch) {
+        const int nb = std::min(p.max_batch, nrhs - b0);
+        // x = C^{-1/2} h, then Y x, then rho = M^{1/2} g1 + Omega Y x
+        MFWF_TRY(launch_harmonic(p, reinterpret_cast<const double2 *>(h) + (long)b0 * p.nalm, 1,
+                                 1.0, p.d_cl, 0.0, 2, p.d_salm, nullptr, nb, false));
+        MFWF_TRY(launch_leg_synth(p, p.d_salm, p.d_phase, nb));
+        MFWF_TRY(launch_fft_inv(p, p.d_phase, p.d_t, nb));
+        MFWF_TRY(launch_fluct_combine(g1 + (long)b0 * p.npix, p.d_M, p.d_t,
+                                      rho + (long)b0 * p.npix, p.npix, nb, p.omega, p.stream));
+    }
+    return MFWF_OK;
+}
+
+int mfwf_solve(mfwf_plan plan, const double *input, int nmaps, double *s_alm_out,
+               double *s_map_out, const mfwf_solve_opts *opts, mfwf_solve_info *info) {
+    if (!plan || nmaps < 0) return fail(MFWF_EINVAL, "bad argument");
+    Plan &p = plan->p;
+    if (!p.have_cov) return fail(MFWF_ENOCOV, "covariances not set");
+    if (nmaps > 0 && !input) return fail(MFWF_EINVAL, "input is NULL");
+    mfwf_solve_opts o{};
+    std::vector<double> lam{1.0};
+    std::vector<int> its{300};
+    if (opts) {
+        o = *opts;
+        if (o.dchi2_tol != 0.0) return fail(MFWF_EINVAL, "dchi2_tol must be 0 (fixed schedules only)");
+        if (o.n_stages < 0) return fail(MFWF_EINVAL, "n_stages < 0");
+        if (o.n_stages > 0) {
+            if (!o.lambda || !o.iters) return fail(MFWF_EINVAL, "schedule arrays are NULL");
+            lam.assign(o.lambda, o.lambda + o.n_stages);
+            its.assign(o.iters, o.iters + o.n_stages);
+            for (int s = 0; s < o.n_stages; s++)
+                if (!(lam[s] >= 1.0) || std::isinf(lam[s]) || its[s] < 0)
+                    return fail(MFWF_EINVAL, "each lambda must be finite and >= 1, iters >= 0");
+        }
+    }
+    for (int b0 = 0; b0 < nmaps; b0 += p.max_batch) {
+        const int nb = std::min(p.max_batch, nmaps - b0);
+        MFWF_TRY(solve_chunk(p, input + (long)b0 * p.npix, nb,
+                             s_alm_out ? s_alm_out + 2L * b0 * p.nalm : nullptr,
+                             s_map_out ? s_map_out + (long)b0 * p.npix : nullptr, o, lam, its,
+                             info ? info + b0 : nullptr));
+    }
+    MFWF_HIP(hipStreamSynchronize(p.stream));
+    return MFWF_OK;
+}
+
+int mfwf_plan_work(mfwf_plan plan, double *out4) {
+    if (!plan || !out4) return fail(MFWF_EINVAL, "NULL argument");
+    const Plan &p = plan->p;
+    out4[0] = p.work_tuples;
+    out4[1] = (double)p.npair * (double)p.nalm;
+    out4[2] = p.npair;
+    out4[3] = p.fftmax;
+    return MFWF_OK;
+}
+
+int mfwf_time_kernels(mfwf_plan plan, int nmaps, int reps, double *ms_out) {
+    if (!plan || !ms_out || reps < 1 || nmaps < 1) return fail(MFWF_EINVAL, "bad argument");
+    Plan &p = plan->p;
+    if (!p.have_cov) return fail(MFWF_ENOCOV, "covariances not set");
+    if (nmaps > p.max_batch) return fail(MFWF_EINVAL, "nmaps > max_batch");
+    const int nb = nmaps;
+    hipEvent_t e0, e1;
+    MFWF_HIP(hipEventCreate(&e0));
+    MFWF_HIP(hipEventCreate(&e1));
+    for (int k = 0; k < 6; k++) {
+        MFWF_HIP(hipEventRecord(e0, p.stream));
+        for (int r = 0; r < reps; r++) {
+            switch (k) {
+                case 0: MFWF_TRY(launch_pixel_update(p.d_rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, 1.0, p.tau, p.stream)); break;
+                case 1: MFWF_TRY(launch_fft_fwd(p, p.d_t, p.d_phase, nb)); break;
+                case 2: MFWF_TRY(launch_leg_analysis(p, p.d_phase, p.d_apart, nb)); break;
+                case 3: MFWF_TRY(launch_harmonic(p, p.d_apart, p.ngroup, p.omega, p.d_cl, p.tau * p.omega, 0, p.d_salm, p.d_salm_prev, nb, false)); break;
+                case 4: MFWF_TRY(launch_leg_synth(p, p.d_salm, p.d_phase, nb)); break;
+                case 5: MFWF_TRY(launch_fft_inv(p, p.d_phase, p.d_smap, nb)); break;
+            }
+        }
+        MFWF_HIP(hipEventRecord(e1, p.stream));
+        MFWF_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        MFWF_HIP(hipEventElapsedTime(&ms, e0, e1));
+        ms_out[k] = ms / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return MFWF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// Internal declarations of the mfwf HIP library: the plan object, device table layout
+// and the launch wrappers of every kernel.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "mfwf.h"
+
+namespace mfwf {
+
+// Status propagation with a thread-local message.
+void set_error(const std::string &msg);
+#define MFWF_HIP(call)                                                                     \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            ::mfwf::set_error(std::string(#call) + ": " + hipGetErrorString(e_));          \
+            return MFWF_EDEVICE;                                                           \
+        }                                                                                  \
+    } while (0)
+#define MFWF_TRY(call)                                                                     \
+    do {                                                                                   \
+        int s_ = (call);                                                                   \
+        if (s_ != MFWF_OK) return s_;                                                      \
+    } while (0)
+
+// Ring pair p (0-based, p = 0 .. 2 nside - 1) couples north ring p and south ring
+// nring - 1 - p (0-based ring indices, north to south).  The last pair is the equator,
+// whose north and south ring coincide.
+struct PairFFT {
+    int nphi;        // pixels per ring of this pair
+    int fftlen;      // length of the power-of-two transform used (nphi or Bluestein M)
+    int bluestein;   // 1 if nphi is not a power of two
+    int half_shift;  // 1 if phi_0 = pi / nphi, 0 if phi_0 = 0
+    long startN;     // first pixel of the north ring
+    long startS;     // first pixel of the south ring (== startN on the equator)
+    long chirp_off;  // offset of the chirp table of this length (Bluestein only)
+    long bhat_off;   // offset of the transformed chirp kernel (Bluestein only)
+};
+
+// Legendre work split: the wave of lanes handling ring pairs [g * 64 * P, (g+1) * 64 * P)
+// for one m.  Seeds: for every (m, pair) the first l with |lambda_lm| >= 2^-100 and the
+// two values (lambda_{l_s - 1, m}, lambda_{l_s, m}); l_s = lmax + 1 if never reached.
+struct Plan {
+    int nside, lmax, spin, dtype, max_batch;
+    hipStream_t stream;
+    long npix;
+    int nring, npair, nm;
+    long nalm;
+    double omega;
+    int P;        // ring pairs per lane in the Legendre kernels
+    int ngroup;   // pair groups (waves per m) in the Legendre kernels
+
+    // plan tables (device)
+    double *d_z = nullptr;       // [npair] cos(theta) of the north ring of each pair
+    double2 *d_ab = nullptr;     // [nalm] (alpha_lm, beta_lm): lambda_l = alpha z lambda_{l-1} - beta lambda_{l-2}
+    int *d_lstart = nullptr;     // [nm][npair]
+    double2 *d_seed = nullptr;   // [nm][npair]
+    PairFFT *d_pfft = nullptr;   // [npair]
+    double2 *d_tw = nullptr;     // [fftmax] exp(-2 pi i k / fftmax)
+    double2 *d_chirp = nullptr;  // Bluestein chirps exp(-i pi k^2 / n), per distinct n
+    double2 *d_bhat = nullptr;   // Bluestein kernels FFT_M(conj chirp), bit-reversed order
+    int fftmax;                  // largest power-of-two transform length
+    long *d_mofs = nullptr;      // [nm] packed offset of (l = m, m)
+
+    // covariances
+    double *d_cl = nullptr;  // [lmax+1]
+    double *d_M = nullptr;   // [npix] inverse noise variance times mask
+    double tau = 0.0;
+    long ndof = 0;
+    bool have_cov = false;
+
+    // workspaces, sized for max_batch maps
+    double *d_rho = nullptr;     // [B][npix]
+    double *d_t = nullptr;       // [B][npix]
+    double *d_smap = nullptr;    // [B][npix]
+    double2 *d_phase = nullptr;  // [B][nm][nring] ring Fourier coefficients
+    double2 *d_apart = nullptr;  // [ngroup][B][nalm] partial analysis sums
+    double2 *d_salm = nullptr;   // [B][nalm]
+    double2 *d_salm_prev = nullptr;
+    double *d_red = nullptr;     // reduction partials
+    double *d_diag = nullptr;    // [B][8] diagnostics
+    int nred_blocks;
+    double work_tuples = 0.0;  // (l, m, pair) triples with l >= start index
+};
+
+// ---- kernels (launch wrappers) --------------------------------------------------------
+// pixel.hip
+int launch_fill(double *x, long n, double v, hipStream_t s);
+int launch_mask_product(const double *ninv, const uint8_t *mask, double *M, long npix,
+                        hipStream_t s);
+int launch_reduce_max_count(const double *M, long npix, double *partial, int nblocks,
+                            double *out2, hipStream_t s);
+int launch_rho_from_data(const double *d, const double *M, double *rho, long npix, int nb,
+                         hipStream_t s);
+int launch_pixel_update(const double *rho, const double *M, const double *smap, double *t,
+                        long npix, int nb, double lam, double tau, hipStream_t s);
+int launch_chi2_pix(const double *rho, const double *M, const double *smap, long npix, int nb,
+                    double lam, double tau, double *partial, int nblocks, double *diag,
+                    hipStream_t s);
+int launch_fluct_combine(const double *g1, const double *M, const double *ysh, double *rho,
+                         long npix, int nb, double omega, hipStream_t s);
+
+// ringfft.hip
+int launch_fft_fwd(const Plan &p, const double *maps, double2 *phase, int nb);
+int launch_fft_inv(const Plan &p, const double2 *phase, double *maps, int nb);
+
+// legendre.hip
+int launch_leg_synth(const Plan &p, const double2 *alm, double2 *phase, int nb);
+int launch_leg_analysis(const Plan &p, const double2 *phase, double2 *apart, int nb);
+
+// harmonic.hip
+int launch_harmonic(const Plan &p, const double2 *apart, int ngroup, double scale,
+                    const double *cl, double lamtauomega, int mode, double2 *salm,
+                    double2 *salm_prev, int nb, bool diag);
+int launch_harm_diag(const Plan &p, const double2 *salm, const double2 *salm_prev,
+                     const double *cl, int nb, double *partial, int nblocks, double *diag);
+
+}  // namespace mfwf

@@ -1,0 +1,222 @@
+"""Thin ctypes binding of ``libmfwf.so`` (include/mfwf.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.  PyTorch
+provides device memory and the stream.  PyTorch is imported before the library is loaded,
+so the library binds to the HIP runtime PyTorch already has in the process.
+If the library is missing or cannot be loaded this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+import torch  # noqa: F401  (must precede loading libmfwf.so)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmfwf.so")
+
+
+class MFWFError(RuntimeError):
+    pass
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("n_stages", ctypes.c_int), ("lam", ctypes.POINTER(ctypes.c_double)),
+                ("iters", ctypes.POINTER(ctypes.c_int)), ("n_check", ctypes.c_int),
+                ("dchi2_tol", ctypes.c_double), ("source_is_rho", ctypes.c_int),
+                ("use_graph", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters_done", ctypes.c_int), ("lam", ctypes.c_double), ("chi2", ctypes.c_double),
+                ("chi2_harm", ctypes.c_double), ("dnorm", ctypes.c_double),
+                ("snorm", ctypes.c_double), ("tau", ctypes.c_double), ("n_dof", ctypes.c_long)]
+
+
+EXPORTED = ["mfwf_plan_create", "mfwf_plan_destroy", "mfwf_set_covariances", "mfwf_sht_inv",
+            "mfwf_sht_fwd", "mfwf_fluctuation_rhs", "mfwf_solve", "mfwf_time_kernels",
+            "mfwf_plan_work", "mfwf_last_error"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise MFWFError("%s is not built; run paper_1210_4931_amd/build.py" % path)
+    L = ctypes.CDLL(path)
+    vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+    L.mfwf_plan_create.argtypes = [ip, ip, ip, ip, ip, vp, ctypes.POINTER(vp)]
+    L.mfwf_plan_destroy.argtypes = [vp]
+    L.mfwf_set_covariances.argtypes = [vp, dp, ip, vp, vp]
+    L.mfwf_sht_inv.argtypes = [vp, vp, vp, ip]
+    L.mfwf_sht_fwd.argtypes = [vp, vp, vp, ip]
+    L.mfwf_fluctuation_rhs.argtypes = [vp, vp, vp, ip, vp]
+    L.mfwf_solve.argtypes = [vp, vp, ip, vp, vp, ctypes.POINTER(SolveOpts),
+                             ctypes.POINTER(SolveInfo)]
+    L.mfwf_time_kernels.argtypes = [vp, ip, ip, dp]
+    L.mfwf_plan_work.argtypes = [vp, dp]
+    L.mfwf_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        getattr(L, name).restype = ctypes.c_char_p if name == "mfwf_last_error" else ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise MFWFError("mfwf status %d: %s" % (rc, _lib.mfwf_last_error().decode()))
+
+
+def _dev_f64(x: torch.Tensor, shape) -> torch.Tensor:
+    if not (isinstance(x, torch.Tensor) and x.is_cuda):
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if x.dtype == torch.complex128:
+        x = torch.view_as_real(x)
+    if x.dtype != torch.float64:
+        raise TypeError("expected float64/complex128, got %s" % x.dtype)
+    x = x.contiguous()
+    if x.numel() != int(np.prod(shape)):
+        raise ValueError("expected %s doubles, got %d" % (shape, x.numel()))
+    return x
+
+
+@dataclasses.dataclass
+class Info:
+    iters_done: int
+    lam: float
+    chi2: float
+    chi2_harm: float
+    dnorm: float
+    snorm: float
+    tau: float
+    n_dof: int
+
+
+class Plan:
+    """One (nside, lmax) problem shape on one GPU, with its own HIP stream."""
+
+    def __init__(self, nside: int, lmax: int, max_batch: int = 1, spin: int = 0,
+                 dtype: str = "f64", device: int = 0):
+        L = load()
+        self.nside, self.lmax, self.max_batch = nside, lmax, max_batch
+        self.npix = 12 * nside * nside
+        self.nalm = (lmax + 1) * (lmax + 2) // 2
+        self.device = torch.device("cuda", device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        h = ctypes.c_void_p()
+        dt = {"f64": 0, "f32": 1}[dtype]
+        with torch.cuda.device(self.device):
+            _check(L.mfwf_plan_create(nside, lmax, spin, dt, max_batch,
+                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.mfwf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- helpers -------------------------------------------------------------------------
+    def _enter(self):
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _leave(self):
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def zeros_map(self, n):
+        return torch.zeros((n, self.npix), dtype=torch.float64, device=self.device)
+
+    def zeros_alm(self, n):
+        return torch.zeros((n, self.nalm), dtype=torch.complex128, device=self.device)
+
+    # ---- entry points --------------------------------------------------------------------
+    def set_covariances(self, cl, ninv: torch.Tensor, mask: torch.Tensor | None = None):
+        cl = np.ascontiguousarray(np.asarray(cl, dtype=np.float64).reshape(-1))
+        if cl.size != self.lmax + 1:
+            raise ValueError("cl must have lmax + 1 entries")
+        ninv = _dev_f64(ninv, (self.npix,))
+        if mask is not None:
+            if mask.dtype != torch.uint8 or not mask.is_cuda or mask.numel() != self.npix:
+                raise TypeError("mask must be a CUDA uint8 tensor of npix entries")
+            mask = mask.contiguous()
+        self._enter()
+        rc = _lib.mfwf_set_covariances(self._h, cl.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       1, ninv.data_ptr(),
+                                       None if mask is None else mask.data_ptr())
+        _check(rc)
+        self._keep = (ninv, mask)
+
+    def sht_inv(self, alm: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        n = alm.shape[0] if alm.dim() == 2 else 1
+        a = _dev_f64(alm, (n, 2 * self.nalm))
+        out = self.zeros_map(n) if out is None else out
+        self._enter()
+        _check(_lib.mfwf_sht_inv(self._h, a.data_ptr(), out.data_ptr(), n))
+        self._leave()
+        return out
+
+    def sht_fwd(self, maps: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        n = maps.shape[0] if maps.dim() == 2 else 1
+        m = _dev_f64(maps, (n, self.npix))
+        out = self.zeros_alm(n) if out is None else out
+        self._enter()
+        _check(_lib.mfwf_sht_fwd(self._h, m.data_ptr(), torch.view_as_real(out).data_ptr(), n))
+        self._leave()
+        return out
+
+    def fluctuation_rhs(self, g1: torch.Tensor, h: torch.Tensor, out=None) -> torch.Tensor:
+        n = g1.shape[0] if g1.dim() == 2 else 1
+        g = _dev_f64(g1, (n, self.npix))
+        hh = _dev_f64(h, (n, 2 * self.nalm))
+        out = self.zeros_map(n) if out is None else out
+        self._enter()
+        _check(_lib.mfwf_fluctuation_rhs(self._h, g.data_ptr(), hh.data_ptr(), n, out.data_ptr()))
+        self._leave()
+        return out
+
+    def solve(self, inp: torch.Tensor, lam=None, iters=None, source_is_rho=False,
+              use_graph=True, out_alm=None, out_map=None, want_map=True):
+        """Messenger iteration.  lam/iters: per-stage schedule (default lambda 1, 300 its).
+        Returns (s_alm [n, nalm] complex128, s_map [n, npix] or None, [Info] * n)."""
+        n = inp.shape[0] if inp.dim() == 2 else 1
+        x = _dev_f64(inp, (n, self.npix))
+        if lam is None:
+            lam, iters = [1.0], [300 if iters is None else int(iters)]
+        lam_a = (ctypes.c_double * len(lam))(*[float(v) for v in lam])
+        it_a = (ctypes.c_int * len(iters))(*[int(v) for v in iters])
+        opts = SolveOpts(len(lam), lam_a, it_a, 0, 0.0, int(bool(source_is_rho)), int(bool(use_graph)))
+        s_alm = self.zeros_alm(n) if out_alm is None else out_alm
+        s_map = (self.zeros_map(n) if out_map is None else out_map) if want_map else None
+        infos = (SolveInfo * n)()
+        self._enter()
+        _check(_lib.mfwf_solve(self._h, x.data_ptr(), n, torch.view_as_real(s_alm).data_ptr(),
+                               None if s_map is None else s_map.data_ptr(), ctypes.byref(opts),
+                               infos))
+        self._leave()
+        info = [Info(i.iters_done, i.lam, i.chi2, i.chi2_harm, i.dnorm, i.snorm, i.tau, i.n_dof)
+                for i in infos]
+        return s_alm, s_map, info
+
+    def work(self):
+        """(Legendre triples evaluated, full triangle pairs*nalm, ring pairs, max FFT length)."""
+        out = (ctypes.c_double * 4)()
+        _check(_lib.mfwf_plan_work(self._h, out))
+        return tuple(out)
+
+    def time_kernels(self, nmaps=1, reps=10):
+        """Mean ms per launch of [pixel, fft_fwd, leg_analysis, harmonic, leg_synth, fft_inv]."""
+        out = (ctypes.c_double * 6)()
+        self._enter()
+        _check(_lib.mfwf_time_kernels(self._h, nmaps, reps, out))
+        return list(out)

@@ -1,0 +1,60 @@
+"""The C-ABI library loads and exports every entry point include/mfwf.h declares (CPU only:
+no compute call is made without a GPU)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mfwf.h")
+LIB = os.path.join(ROOT, "paper_1210_4931_amd", "libmfwf.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mfwf_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1210_4931_amd import build
+        build.build()
+    from paper_1210_4931_amd import mfwf
+    return mfwf.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for n in ["mfwf_plan_create", "mfwf_plan_destroy", "mfwf_set_covariances", "mfwf_sht_inv",
+              "mfwf_sht_fwd", "mfwf_fluctuation_rhs", "mfwf_solve", "mfwf_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (mfwf_\w+)", out))
+    missing = [n for n in declared() if n not in exported]
+    assert not missing, missing
+    for n in declared():
+        assert getattr(lib, n) is not None
+
+
+def test_binding_lists_every_export(lib):
+    from paper_1210_4931_amd import mfwf
+    assert sorted(mfwf.EXPORTED) == declared()
+
+
+def test_last_error_and_destroy_null_without_gpu(lib):
+    assert lib.mfwf_plan_destroy(None) == 0
+    assert isinstance(lib.mfwf_last_error(), bytes)
+
+
+def test_single_hip_runtime_in_process(lib):
+    maps = open("/proc/self/maps").read()
+    libs = {l.split()[-1] for l in maps.splitlines() if "libamdhip64" in l}
+    assert len(libs) == 1, libs

@@ -1,0 +1,223 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle.
+
+Tolerances (relative 2-norm over the real harmonic dof or the map):
+  * one SHT, FP64: 1e-12 at nside <= 32; 5e-12 at nside 512.  Both sides run the same
+    three-term Legendre recurrence in FP64 with different rounding (GPU: fused multiply-add,
+    pairwise reductions); near the poles the recurrence amplifies rounding like l^2 eps
+    (measured by the Unsold pin: 3e-11 at l = 1024 on the first ring), which the ring
+    weights dilute to ~1e-13 in the transform.
+  * K = 300 messenger iterations, FP64: 1e-10.  The iteration is a contraction with
+    spectral radius ~0.9999 at this shape, so per-iteration rounding differences (~1e-14)
+    accumulate at most K-fold.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1210_4931_amd import workloads as W
+from tests.gpu_util import dev, rel, rel_alm, temperature_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1210_4931_amd import mfwf
+    mfwf.load()
+    return mfwf
+
+
+SHAPES = [(1, 1), (1, 4), (2, 8), (4, 7), (4, 16), (8, 20), (8, 32), (16, 40), (32, 64), (32, 128)]
+
+
+@pytest.mark.parametrize("nside,lmax", SHAPES)
+def test_sht_inv_parity(mf, nside, lmax):
+    rng = np.random.default_rng(nside * 1000 + lmax)
+    nmaps = 3
+    alm = np.stack([W.white_alm(rng, lmax) for _ in range(nmaps)])
+    plan = mf.Plan(nside, lmax, max_batch=2)  # 3 maps -> two chunks
+    got = plan.sht_inv(dev(alm, torch.complex128)).cpu().numpy()
+    for b in range(nmaps):
+        ref = oracle.alm2map(nside, lmax, alm[b])
+        assert rel(got[b], ref) < 1e-12, (nside, lmax, b)
+
+
+@pytest.mark.parametrize("nside,lmax", SHAPES)
+def test_sht_fwd_parity(mf, nside, lmax):
+    rng = np.random.default_rng(nside * 1000 + lmax + 7)
+    npix = 12 * nside * nside
+    maps = rng.standard_normal((2, npix))
+    plan = mf.Plan(nside, lmax, max_batch=2)
+    got = plan.sht_fwd(dev(maps)).cpu().numpy()
+    for b in range(2):
+        ref = oracle.map2alm(nside, lmax, maps[b])
+        assert rel_alm(got[b], ref, lmax) < 1e-12, (nside, lmax, b)
+
+
+def test_empty_batch_is_a_no_op(mf):
+    plan = mf.Plan(4, 8)
+    out = plan.sht_inv(torch.zeros((0, 45), dtype=torch.complex128, device="cuda"))
+    assert out.shape == (0, 192)
+
+
+def _setup(mf, nside, lmax, max_batch=1, seed=0):
+    wl, d, M = temperature_problem(nside, lmax, seed)
+    plan = mf.Plan(nside, lmax, max_batch=max_batch)
+    plan.set_covariances(wl.cl, dev(1.0 / wl.noise_var), dev(wl.mask, torch.uint8))
+    return plan, wl, d, M
+
+
+def test_solve_config1_parity(mf):
+    """nside 32, lmax 64, 300 iterations at lambda = 1 (the small temperature workload)."""
+    nside, lmax = 32, 64
+    plan, wl, d, M = _setup(mf, nside, lmax)
+    s_alm, s_map, info = plan.solve(dev(d[None]), iters=300)
+    ref_alm, ref_map, dg = oracle.solve(nside, lmax, wl.cl, M, M * d, niter=300, diag=True)
+    assert rel_alm(s_alm.cpu().numpy()[0], ref_alm, lmax) < 1e-10
+    assert rel(s_map.cpu().numpy()[0], ref_map) < 1e-10
+    assert info[0].iters_done == 300 and info[0].n_dof == int((wl.mask > 0).sum())
+    assert info[0].tau == pytest.approx(1.0 / M.max(), rel=1e-15)
+    assert info[0].chi2 == pytest.approx(dg[-1, 0], rel=1e-9)
+    assert info[0].chi2_harm == pytest.approx(dg[-1, 1], rel=1e-9)
+    assert info[0].dnorm == pytest.approx(dg[-1, 2], rel=1e-6)
+    assert info[0].snorm == pytest.approx(dg[-1, 3], rel=1e-9)
+
+
+def test_solve_lambda_schedule_parity(mf):
+    nside, lmax = 16, 40
+    plan, wl, d, M = _setup(mf, nside, lmax)
+    lam, its = [50.0, 8.0, 1.0], [10, 10, 20]
+    s_alm, _, info = plan.solve(dev(d[None]), lam=lam, iters=its)
+    sched = np.repeat(lam, its)
+    ref_alm, _ = oracle.solve(nside, lmax, wl.cl, M, M * d, lam=sched)
+    assert rel_alm(s_alm.cpu().numpy()[0], ref_alm, lmax) < 1e-11
+    assert info[0].lam == 1.0 and info[0].iters_done == 40
+
+
+def test_graph_replay_equals_eager_bitwise(mf):
+    nside, lmax = 16, 32
+    plan, wl, d, M = _setup(mf, nside, lmax)
+    a1, m1, _ = plan.solve(dev(d[None]), iters=25, use_graph=True)
+    a2, m2, _ = plan.solve(dev(d[None]), iters=25, use_graph=False)
+    a3, m3, _ = plan.solve(dev(d[None]), iters=25, use_graph=True)
+    assert torch.equal(a1, a2) and torch.equal(m1, m2)
+    assert torch.equal(a1, a3) and torch.equal(m1, m3)
+
+
+def test_batch_invariance_bitwise(mf):
+    """Map b solved alone equals map b inside a batch of 5 (chunked by max_batch 3)."""
+    nside, lmax = 16, 32
+    plan, wl, d, M = _setup(mf, nside, lmax, max_batch=3)
+    rng = np.random.default_rng(9)
+    ds = np.stack([d + rng.standard_normal(d.size) for _ in range(5)])
+    a_all, m_all, info = plan.solve(dev(ds), iters=20)
+    for b in (0, 3, 4):
+        a_b, m_b, _ = plan.solve(dev(ds[b:b + 1]), iters=20)
+        assert torch.equal(a_all[b], a_b[0]) and torch.equal(m_all[b], m_b[0])
+    assert len(info) == 5
+
+
+def test_rho_source_equals_data_source(mf):
+    nside, lmax = 8, 16
+    plan, wl, d, M = _setup(mf, nside, lmax)
+    a1, _, _ = plan.solve(dev(d[None]), iters=10)
+    a2, _, _ = plan.solve(dev((M * d)[None]), iters=10, source_is_rho=True)
+    assert rel_alm(a1.cpu().numpy()[0], a2.cpu().numpy()[0], lmax) < 1e-15
+
+
+def test_masked_data_ignored_bitwise(mf):
+    nside, lmax = 16, 32
+    plan, wl, d, M = _setup(mf, nside, lmax)
+    d2 = d.copy()
+    d2[wl.mask == 0] = 1e6
+    a1, m1, _ = plan.solve(dev(d[None]), iters=10)
+    a2, m2, _ = plan.solve(dev(d2[None]), iters=10)
+    assert torch.equal(a1, a2) and torch.equal(m1, m2)
+
+
+def test_fluctuation_rhs_parity_and_solve(mf):
+    nside, lmax = 16, 40
+    plan, wl, d, M = _setup(mf, nside, lmax, max_batch=2)
+    draws = [W.fluctuation_draws(40 + k, nside, lmax) for k in range(3)]
+    g1 = np.stack([g for g, _ in draws])
+    h = np.stack([hh for _, hh in draws])
+    rho = plan.fluctuation_rhs(dev(g1), dev(h, torch.complex128))
+    rho_np = rho.cpu().numpy()
+    for k in range(3):
+        ref = oracle.fluct_rho(nside, lmax, wl.cl, M, g1[k], h[k])
+        assert rel(rho_np[k], ref) < 1e-12
+    f_alm, _, _ = plan.solve(rho, iters=30, source_is_rho=True)
+    ref_f, _ = oracle.solve(nside, lmax, wl.cl, M, rho_np[1], niter=30)
+    assert rel_alm(f_alm.cpu().numpy()[1], ref_f, lmax) < 1e-11
+
+
+def test_uniform_noise_one_step(mf):
+    """N = sigma^2 1 on the full sky: one iteration gives C/(C + sigma^2 Omega) A d and a
+    second iteration changes nothing beyond rounding (the paper's N ~ 1 special case)."""
+    nside, lmax, sig2 = 16, 32, 0.5
+    wl = W.config1(1, nside, lmax)
+    d = oracle.alm2map(nside, lmax, wl.signal_alm) + np.sqrt(sig2) * wl.noise_white
+    plan = mf.Plan(nside, lmax)
+    plan.set_covariances(wl.cl, dev(np.full(d.size, 1.0 / sig2)))
+    a1, _, _ = plan.solve(dev(d[None]), iters=1)
+    a2, _, _ = plan.solve(dev(d[None]), iters=2)
+    omega = 4 * np.pi / d.size
+    ls, _ = W.alm_l_m(lmax)
+    ad = oracle.map2alm(nside, lmax, d)
+    closed = wl.cl[ls] / (wl.cl[ls] + sig2 * omega) * ad
+    assert rel_alm(a1.cpu().numpy()[0], closed, lmax) < 1e-12
+    assert rel_alm(a2.cpu().numpy()[0], a1.cpu().numpy()[0], lmax) < 1e-13
+
+
+def test_errors(mf):
+    with pytest.raises(mf.MFWFError, match="nside"):
+        mf.Plan(3, 8)
+    with pytest.raises(mf.MFWFError, match="lmax"):
+        mf.Plan(4, 17)
+    plan = mf.Plan(4, 8)
+    with pytest.raises(mf.MFWFError, match="covariances not set"):
+        plan.solve(torch.zeros((1, 192), dtype=torch.float64, device="cuda"), iters=1)
+    with pytest.raises(mf.MFWFError, match="no observed pixel"):
+        plan.set_covariances(np.ones(9), torch.ones(192, dtype=torch.float64, device="cuda"),
+                             torch.zeros(192, dtype=torch.uint8, device="cuda"))
+    with pytest.raises(mf.MFWFError, match="non-finite"):
+        bad = torch.ones(192, dtype=torch.float64, device="cuda")
+        bad[5] = float("nan")
+        plan.set_covariances(np.ones(9), bad)
+    plan.set_covariances(np.ones(9), torch.ones(192, dtype=torch.float64, device="cuda"))
+    with pytest.raises(mf.MFWFError, match="lambda"):
+        plan.solve(torch.zeros((1, 192), dtype=torch.float64, device="cuda"), lam=[0.5], iters=[3])
+
+
+# ---- full size: nside 512, lmax 1024, the benchmark's launch configuration ----------------
+
+@pytest.fixture(scope="module")
+def big(mf):
+    nside, lmax = 512, 1024
+    wl = W.config2(0, nside, lmax)
+    sig = oracle.alm2map(nside, lmax, wl.signal_alm)
+    d = wl.data_from_signal_map(sig)
+    M = wl.mask / wl.noise_var
+    plan = mf.Plan(nside, lmax, max_batch=1)
+    plan.set_covariances(wl.cl, dev(1.0 / wl.noise_var), dev(wl.mask, torch.uint8))
+    return plan, wl, d, M, sig
+
+
+def test_full_size_sht_parity(mf, big):
+    plan, wl, d, M, sig = big
+    got = plan.sht_inv(dev(wl.signal_alm[None], torch.complex128)).cpu().numpy()[0]
+    assert rel(got, sig) < 5e-12
+    a = plan.sht_fwd(dev(d[None])).cpu().numpy()[0]
+    ref = oracle.map2alm(512, 1024, d)
+    assert rel_alm(a, ref, 1024) < 5e-12
+
+
+def test_full_size_solve_parity_two_iterations(mf, big):
+    plan, wl, d, M, _ = big
+    s_alm, s_map, info = plan.solve(dev(d[None]), iters=2)
+    ref_alm, ref_map = oracle.solve(512, 1024, wl.cl, M, M * d, niter=2)
+    assert rel_alm(s_alm.cpu().numpy()[0], ref_alm, 1024) < 5e-12
+    assert rel(s_map.cpu().numpy()[0], ref_map) < 5e-12
