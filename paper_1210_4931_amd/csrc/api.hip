@@ -1,13 +1,18 @@
 // C-ABI of the mfwf library: plan construction (HEALPix ring geometry, Legendre recurrence
-// tables and start seeds, ring-FFT tables), covariance set-up, the transforms, the
-// fluctuation source and the messenger-iteration driver (Sect. 2.1 of the paper).
+// tables and start seeds, ring-FFT tables, kernel-variant autotuning), covariance set-up,
+// the transforms, the fluctuation source and the messenger-iteration driver (Sect. 2.1).
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <functional>
 #include <memory>
 #include <new>
+#include <sstream>
 #include <string>
+#include <sys/stat.h>
 #include <thread>
 #include <vector>
 
@@ -20,6 +25,7 @@ struct mfwf_plan_s {
 namespace mfwf {
 
 int fft_set_lds_limit(size_t bytes);  // ringfft.hip
+int fft_max_length();                 // ringfft.hip
 
 static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
@@ -52,8 +58,8 @@ static int upload(T *dst, const std::vector<T> &src, hipStream_t s) {
 // ---- host-side plan tables ----------------------------------------------------------------
 
 struct RingGeom {
-    double z, sth, phi0_over_pi_n;  // phi0 = pi/n * half_shift
-    int nphi, half_shift;
+    double z, sth;
+    int nphi, half_shift;  // phi_0 = pi / nphi if half_shift, else 0
     long start;
 };
 
@@ -117,19 +123,16 @@ static void host_fft(std::vector<double2> &x) {
     }
 }
 
-static int bitrev_host(int k, int logn) {
-    int r = 0;
-    for (int b = 0; b < logn; b++)
-        if (k & (1 << b)) r |= 1 << (logn - 1 - b);
-    return r;
-}
-
-// Recurrence coefficients for lambda_l = alpha z lambda_{l-1} - beta lambda_{l-2}:
-// eps_lm = sqrt((l^2 - m^2)/(4 l^2 - 1)), alpha = 1/eps_lm, beta = eps_{l-1,m}/eps_lm;
-// (alpha, beta) = (0, 0) at l = m, where the value comes from the seed.
-static void build_recurrence(int lmax, std::vector<double2> &ab, std::vector<long> &mofs) {
+// Orthonormal recurrence lambda_l = alpha_l z lambda_{l-1} - beta_l lambda_{l-2} with
+// eps_lm = sqrt((l^2 - m^2)/(4 l^2 - 1)), alpha = 1/eps_lm, beta = eps_{l-1,m}/eps_lm, and its
+// rescaled form lambda_l = c_l mu_l, c_m = c_{m+1} = 1, c_l = beta_l c_{l-2}:
+//   mu_l = A_l z mu_{l-1} - mu_{l-2},  A_l = alpha_l c_{l-1} / c_l  (A_m = 0: seed value).
+static void build_recurrence(int lmax, std::vector<double2> &ab, std::vector<double> &A,
+                             std::vector<double> &c, std::vector<long> &mofs) {
     const long nalm = (long)(lmax + 1) * (lmax + 2) / 2;
     ab.assign(nalm, make_double2(0.0, 0.0));
+    A.assign(nalm, 0.0);
+    c.assign(nalm, 1.0);
     mofs.resize(lmax + 1);
     for (int m = 0; m <= lmax; m++) {
         const long off = (long)m * (2 * lmax + 3 - m) / 2;
@@ -137,19 +140,23 @@ static void build_recurrence(int lmax, std::vector<double2> &ab, std::vector<lon
         double eps_prev = 0.0;  // eps_{m,m} = 0
         for (int l = m + 1; l <= lmax; l++) {
             const double eps = std::sqrt(((double)l * l - (double)m * m) / (4.0 * l * l - 1.0));
-            ab[off + l - m] = make_double2(1.0 / eps, eps_prev / eps);
+            const double alpha = 1.0 / eps, beta = eps_prev / eps;
+            ab[off + l - m] = make_double2(alpha, beta);
+            if (l >= m + 2) c[off + l - m] = beta * c[off + l - m - 2];
+            A[off + l - m] = alpha * c[off + l - m - 1] / c[off + l - m];
             eps_prev = eps;
         }
     }
 }
 
-// For every (m, pair): first l with |lambda_lm(z)| >= 2^-100 and (lambda_{l-1}, lambda_l).
+// For every (m, pair): first l with |lambda_lm(z)| >= 2^-100 and (mu_{l-1}, mu_l) there.
 // lambda_mm = (-1)^m sqrt(1/4pi) prod_{k<=m} sqrt((2k+1)/(2k)) sin(theta) is carried as a
 // mantissa and a power-of-two exponent (it underflows double long before m = lmax near
-// the poles); the l-recurrence is run in the same scaled form until the threshold.
+// the poles); the l-recurrence runs in the same scaled form until the threshold.
 static void build_seeds(int lmax, int npair, const std::vector<RingGeom> &geo,
-                        const std::vector<double2> &ab, const std::vector<long> &mofs,
-                        std::vector<int> &lstart, std::vector<double2> &seed) {
+                        const std::vector<double2> &ab, const std::vector<double> &c,
+                        const std::vector<long> &mofs, std::vector<int> &lstart,
+                        std::vector<double2> &seed) {
     const int nm = lmax + 1;
     lstart.assign((size_t)nm * npair, lmax + 1);
     seed.assign((size_t)nm * npair, make_double2(0.0, 0.0));
@@ -173,11 +180,12 @@ static void build_seeds(int lmax, int npair, const std::vector<RingGeom> &geo,
                 };
                 double thr = thr_of(e);
                 const double2 *abm = ab.data() + mofs[m] - m;
+                const double *cm = c.data() + mofs[m] - m;
                 const size_t slot = (size_t)m * npair + p;
                 for (int l = m;; l++) {
                     if (l > m) {
-                        const double2 c = abm[l];
-                        const double cur = c.x * (z * p1v) - c.y * p2v;
+                        const double2 cc = abm[l];
+                        const double cur = cc.x * (z * p1v) - cc.y * p2v;
                         p2v = p1v;
                         p1v = cur;
                         if (std::fabs(p1v) > 0x1p+300) {
@@ -189,7 +197,9 @@ static void build_seeds(int lmax, int npair, const std::vector<RingGeom> &geo,
                     }
                     if (std::fabs(p1v) >= thr) {
                         lstart[slot] = l;
-                        seed[slot] = make_double2(std::ldexp(p2v, (int)e), std::ldexp(p1v, (int)e));
+                        const double lam_prev = std::ldexp(p2v, (int)e);
+                        const double lam = std::ldexp(p1v, (int)e);
+                        seed[slot] = make_double2(l > m ? lam_prev / cm[l - 1] : 0.0, lam / cm[l]);
                         break;
                     }
                     if (l == lmax) break;
@@ -209,21 +219,131 @@ static void build_seeds(int lmax, int npair, const std::vector<RingGeom> &geo,
 }
 
 static void free_plan(Plan &p) {
-    void *ptrs[] = {p.d_z, p.d_ab, p.d_lstart, p.d_seed, p.d_pfft, p.d_tw, p.d_chirp, p.d_bhat,
-                    p.d_mofs, p.d_cl, p.d_M, p.d_rho, p.d_t, p.d_smap, p.d_phase, p.d_apart,
-                    p.d_salm, p.d_salm_prev, p.d_red, p.d_diag};
+    void *ptrs[] = {p.d_z,    p.d_A,    p.d_c,     p.d_lstart, p.d_seed,  p.d_pfft, p.d_plist,
+                    p.d_tw,   p.d_chirp, p.d_bhat, p.d_mofs,   p.d_cl,    p.d_M,
+                    p.d_rho,  p.d_t,    p.d_smap,  p.d_phase,  p.d_apart, p.d_salm,
+                    p.d_salm_prev, p.d_sp, p.d_red, p.d_diag};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
 }
 
-static int check_device() {
+static int device_name(std::string &name) {
     int dev = 0;
     MFWF_HIP(hipGetDevice(&dev));
     hipDeviceProp_t prop;
     MFWF_HIP(hipGetDeviceProperties(&prop, dev));
-    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-        return fail(MFWF_EDEVICE, std::string("library is built for gfx950, device is ") +
-                                      prop.gcnArchName);
+    name = prop.gcnArchName;
+    if (name.compare(0, 6, "gfx950") != 0)
+        return fail(MFWF_EDEVICE, "library is built for gfx950, device is " + name);
+    return MFWF_OK;
+}
+
+// ---- kernel-variant autotuning ----------------------------------------------------------
+// The Legendre kernels come in variants (ring pairs per lane, coefficient block length,
+// prefetch of the next block).  With MFWF_AUTOTUNE != 0 (default) the plan times every
+// variant on its own stream and keeps the fastest; the choice is cached per
+// (device, nside, lmax) in $MFWF_TUNE_CACHE (default ~/.cache/mfwf/legendre_tune.txt), so
+// later plans of the same shape reuse it without timing.
+
+static std::string tune_cache_path() {
+    if (const char *e = std::getenv("MFWF_TUNE_CACHE")) return e;
+    const char *home = std::getenv("HOME");
+    return std::string(home ? home : "/tmp") + "/.cache/mfwf/legendre_tune.txt";
+}
+
+static bool tune_lookup(const std::string &key, int &sv, int &av) {
+    std::ifstream f(tune_cache_path());
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string k;
+        int s, a;
+        if (is >> k >> s >> a && k == key && s >= 0 && s < leg_synth_variants() && a >= 0 &&
+            a < leg_analysis_variants()) {
+            sv = s;
+            av = a;
+            found = true;
+        }
+    }
+    return found;
+}
+
+static void tune_store(const std::string &key, int sv, int av) {
+    const std::string path = tune_cache_path();
+    const size_t slash = path.find_last_of('/');
+    if (slash != std::string::npos) {
+        std::string dir = path.substr(0, slash);
+        for (size_t i = 1; i <= dir.size(); i++)
+            if (i == dir.size() || dir[i] == '/') (void)mkdir(dir.substr(0, i).c_str(), 0755);
+    }
+    std::ofstream f(path, std::ios::app);
+    if (f) f << key << " " << sv << " " << av << "\n";
+}
+
+static int time_launches(Plan &p, int reps, const std::function<int()> &launch, float &ms) {
+    hipEvent_t e0, e1;
+    MFWF_HIP(hipEventCreate(&e0));
+    MFWF_HIP(hipEventCreate(&e1));
+    int st = launch();  // warm-up
+    if (st == MFWF_OK) st = (hipEventRecord(e0, p.stream) == hipSuccess) ? MFWF_OK : MFWF_EDEVICE;
+    for (int r = 0; r < reps && st == MFWF_OK; r++) st = launch();
+    if (st == MFWF_OK) st = (hipEventRecord(e1, p.stream) == hipSuccess) ? MFWF_OK : MFWF_EDEVICE;
+    if (st == MFWF_OK) st = (hipEventSynchronize(e1) == hipSuccess) ? MFWF_OK : MFWF_EDEVICE;
+    if (st == MFWF_OK) st = (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) ? MFWF_OK : MFWF_EDEVICE;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == MFWF_EDEVICE && g_err.empty()) set_error("event timing failed");
+    return st;
+}
+
+static int autotune(Plan &p, const std::string &devname) {
+    const std::string key = devname.substr(0, 6) + ":" + std::to_string(p.nside) + ":" +
+                            std::to_string(p.lmax);
+    int sv, av;
+    if (tune_lookup(key, sv, av)) {
+        p.synth_variant = sv;
+        p.ana_variant = av;
+        return MFWF_OK;
+    }
+    float best = INFINITY;
+    for (int v = 0; v < leg_synth_variants(); v++) {
+        p.synth_variant = v;
+        float ms = 0.f;
+        MFWF_TRY(time_launches(p, 3, [&] { return launch_leg_synth(p, p.d_sp, p.d_phase, 1); }, ms));
+        if (ms < best) {
+            best = ms;
+            sv = v;
+        }
+    }
+    best = INFINITY;
+    for (int v = 0; v < leg_analysis_variants(); v++) {
+        p.ana_variant = v;
+        float ms = 0.f;
+        MFWF_TRY(time_launches(p, 3, [&] { return launch_leg_analysis(p, p.d_phase, p.d_apart, 1); }, ms));
+        if (ms < best) {
+            best = ms;
+            av = v;
+        }
+    }
+    p.synth_variant = sv;
+    p.ana_variant = av;
+    tune_store(key, sv, av);
+    return MFWF_OK;
+}
+
+static void default_variants(Plan &p) {
+    // pairs per lane 4 / 2 / 1 by problem size, prefetched 8-wide blocks
+    const int P = p.npair >= 1024 ? 4 : (p.npair >= 512 ? 2 : 1);
+    for (int v = 0; v < leg_synth_variants(); v++)
+        if (leg_synth_pairs_per_lane(v) == P && v >= 3 && v < 6) p.synth_variant = v;
+    for (int v = 0; v < leg_analysis_variants(); v++)
+        if (leg_analysis_pairs_per_lane(v) == P && v >= 3) p.ana_variant = v;
+}
+
+static int set_groups(Plan &p) {
+    const int P = leg_analysis_pairs_per_lane(p.ana_variant);
+    p.ngroup = (p.npair + 64 * P - 1) / (64 * P);
     return MFWF_OK;
 }
 
@@ -235,7 +355,8 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     if (spin != 0) return fail(MFWF_EINVAL, "only spin 0 (temperature) is supported");
     if (dtype != MFWF_F64) return fail(MFWF_EINVAL, "only MFWF_F64 is supported");
     if (max_batch < 1 || max_batch > 4096) return fail(MFWF_EINVAL, "max_batch out of range");
-    MFWF_TRY(check_device());
+    std::string devname;
+    MFWF_TRY(device_name(devname));
 
     p.nside = nside;
     p.lmax = lmax;
@@ -249,8 +370,7 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     p.nm = lmax + 1;
     p.nalm = (long)(lmax + 1) * (lmax + 2) / 2;
     p.omega = 4.0 * M_PI / (double)p.npix;
-    p.P = std::max(1, std::min(4, p.npair / 256));
-    p.ngroup = (p.npair + 64 * p.P - 1) / (64 * p.P);
+    p.ngroup_max = (p.npair + 63) / 64;  // pairs-per-lane 1 has the most groups
 
     // geometry of the north ring of every pair
     std::vector<RingGeom> geo(p.npair);
@@ -260,11 +380,12 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
         zp[q] = geo[q].z;
     }
     std::vector<double2> ab;
+    std::vector<double> Atab, ctab;
     std::vector<long> mofs;
-    build_recurrence(lmax, ab, mofs);
+    build_recurrence(lmax, ab, Atab, ctab, mofs);
     std::vector<int> lstart;
     std::vector<double2> seed;
-    build_seeds(lmax, p.npair, geo, ab, mofs, lstart, seed);
+    build_seeds(lmax, p.npair, geo, ab, ctab, mofs, lstart, seed);
     p.work_tuples = 0.0;
     for (int ls : lstart) p.work_tuples += (ls <= lmax) ? (double)(lmax - ls + 1) : 0.0;
 
@@ -294,17 +415,13 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
             }
             std::vector<double2> b(M, make_double2(0.0, 0.0));  // conj(c), wrapped
             for (long k = 0; k < n; k++) {
-                const double2 c = chirp[f.chirp_off + k];
-                b[k] = make_double2(c.x, -c.y);
-                if (k > 0) b[M - k] = make_double2(c.x, -c.y);
+                const double2 cc = chirp[f.chirp_off + k];
+                b[k] = make_double2(cc.x, -cc.y);
+                if (k > 0) b[M - k] = make_double2(cc.x, -cc.y);
             }
             host_fft(b);
-            int logM = 0;
-            while ((1 << logM) < M) logM++;
             f.bhat_off = (long)bhat.size();
-            bhat.resize(bhat.size() + M);
-            for (int k = 0; k < M; k++)
-                bhat[f.bhat_off + bitrev_host(k, logM)] = make_double2(b[k].x / M, b[k].y / M);
+            for (int k = 0; k < M; k++) bhat.push_back(make_double2(b[k].x / M, b[k].y / M));
         }
     }
     p.fftmax = fftmax;
@@ -313,12 +430,30 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
         const double a = -2.0 * M_PI * (double)k / fftmax;
         tw[k] = make_double2(std::cos(a), std::sin(a));
     }
-    const size_t lds = sizeof(double2) * (size_t)fftmax;
+    // FFT classes: pairs whose transform fits half of the largest length, and the rest
+    std::vector<int> plist;
+    p.fft_class_len[0] = 1;
+    for (int c = 0; c < 2; c++) {
+        p.fft_class_off[c] = (int)plist.size();
+        for (int q = 0; q < p.npair; q++) {
+            const bool small = 2 * pf[q].fftlen <= fftmax;
+            if ((c == 0) == small) {
+                plist.push_back(q);
+                if (c == 0) p.fft_class_len[0] = std::max(p.fft_class_len[0], pf[q].fftlen);
+            }
+        }
+        p.fft_class_count[c] = (int)plist.size() - p.fft_class_off[c];
+    }
+    p.fft_class_len[1] = fftmax;
+    if (fftmax > fft_max_length())
+        return fail(MFWF_EINVAL, "ring FFT length " + std::to_string(fftmax) + " above the supported " +
+                                     std::to_string(fft_max_length()));
+    const size_t lds = sizeof(double2) * ((size_t)fftmax + 1024);  // FFT area + alias partials
     {
         int dev = 0, maxlds = 0;
         MFWF_HIP(hipGetDevice(&dev));
         MFWF_HIP(hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-        if (lds + 8192 > (size_t)maxlds)
+        if (lds > (size_t)maxlds)
             return fail(MFWF_EINVAL, "ring FFT of length " + std::to_string(fftmax) +
                                          " does not fit the device LDS");
         if (lds > 65536) MFWF_TRY(fft_set_lds_limit(lds));
@@ -326,11 +461,13 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
 
     const long B = max_batch;
     MFWF_TRY(dalloc(&p.d_z, p.npair, "z"));
-    MFWF_TRY(dalloc(&p.d_ab, ab.size(), "recurrence"));
+    MFWF_TRY(dalloc(&p.d_A, Atab.size(), "recurrence A"));
+    MFWF_TRY(dalloc(&p.d_c, ctab.size(), "recurrence scale"));
     MFWF_TRY(dalloc(&p.d_mofs, mofs.size(), "m offsets"));
     MFWF_TRY(dalloc(&p.d_lstart, lstart.size(), "l start"));
     MFWF_TRY(dalloc(&p.d_seed, seed.size(), "seeds"));
     MFWF_TRY(dalloc(&p.d_pfft, pf.size(), "fft plan"));
+    MFWF_TRY(dalloc(&p.d_plist, plist.size(), "fft pair list"));
     MFWF_TRY(dalloc(&p.d_tw, tw.size(), "twiddles"));
     MFWF_TRY(dalloc(&p.d_chirp, std::max<size_t>(1, chirp.size()), "chirp"));
     MFWF_TRY(dalloc(&p.d_bhat, std::max<size_t>(1, bhat.size()), "chirp kernel"));
@@ -340,32 +477,50 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     MFWF_TRY(dalloc(&p.d_t, B * p.npix, "t"));
     MFWF_TRY(dalloc(&p.d_smap, B * p.npix, "s map"));
     MFWF_TRY(dalloc(&p.d_phase, B * p.nm * p.nring, "ring Fourier"));
-    MFWF_TRY(dalloc(&p.d_apart, (long)p.ngroup * B * p.nalm, "analysis partials"));
+    MFWF_TRY(dalloc(&p.d_apart, (long)p.ngroup_max * B * p.nalm, "analysis partials"));
     MFWF_TRY(dalloc(&p.d_salm, B * p.nalm, "s alm"));
     MFWF_TRY(dalloc(&p.d_salm_prev, B * p.nalm, "previous s alm"));
+    MFWF_TRY(dalloc(&p.d_sp, B * p.nalm, "scaled synthesis input"));
     p.nred_blocks = 1024;
     MFWF_TRY(dalloc(&p.d_red, std::max<long>(3L * p.nred_blocks, std::max<long>(B * p.nred_blocks, 3L * B * p.nm)), "reductions"));
     MFWF_TRY(dalloc(&p.d_diag, 8 * B, "diagnostics"));
 
     MFWF_TRY(upload(p.d_z, zp, p.stream));
-    MFWF_TRY(upload(p.d_ab, ab, p.stream));
+    MFWF_TRY(upload(p.d_A, Atab, p.stream));
+    MFWF_TRY(upload(p.d_c, ctab, p.stream));
     MFWF_TRY(upload(p.d_mofs, mofs, p.stream));
     MFWF_TRY(upload(p.d_lstart, lstart, p.stream));
     MFWF_TRY(upload(p.d_seed, seed, p.stream));
     MFWF_TRY(upload(p.d_pfft, pf, p.stream));
+    MFWF_TRY(upload(p.d_plist, plist, p.stream));
     MFWF_TRY(upload(p.d_tw, tw, p.stream));
     if (!chirp.empty()) MFWF_TRY(upload(p.d_chirp, chirp, p.stream));
     if (!bhat.empty()) MFWF_TRY(upload(p.d_bhat, bhat, p.stream));
-    // defined contents everywhere (workspaces are read by mfwf_time_kernels before any solve)
+    // defined contents everywhere (workspaces are read by autotuning and mfwf_time_kernels)
     MFWF_TRY(launch_fill(p.d_cl, lmax + 1, 0.0, p.stream));
     MFWF_TRY(launch_fill(p.d_M, p.npix, 0.0, p.stream));
     MFWF_TRY(launch_fill(p.d_rho, B * p.npix, 0.0, p.stream));
     MFWF_TRY(launch_fill(p.d_t, B * p.npix, 0.0, p.stream));
     MFWF_TRY(launch_fill(p.d_smap, B * p.npix, 0.0, p.stream));
     MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_phase), 2 * B * p.nm * p.nring, 0.0, p.stream));
-    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_apart), 2L * p.ngroup * B * p.nalm, 0.0, p.stream));
+    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_apart), 2L * p.ngroup_max * B * p.nalm, 0.0, p.stream));
     MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm), 2 * B * p.nalm, 0.0, p.stream));
     MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm_prev), 2 * B * p.nalm, 0.0, p.stream));
+    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_sp), 2 * B * p.nalm, 0.0, p.stream));
+
+    default_variants(p);
+    if (const char *env = std::getenv("MFWF_LEG_VARIANTS")) {  // "synth,analysis" override
+        int sv = -1, av = -1;
+        if (std::sscanf(env, "%d,%d", &sv, &av) != 2 || sv < 0 || sv >= leg_synth_variants() ||
+            av < 0 || av >= leg_analysis_variants())
+            return fail(MFWF_EINVAL, "MFWF_LEG_VARIANTS must be 'synth,analysis' variant indices");
+        p.synth_variant = sv;
+        p.ana_variant = av;
+    } else {
+        const char *at = std::getenv("MFWF_AUTOTUNE");
+        if (!(at && std::strcmp(at, "0") == 0) && p.npair >= 256) MFWF_TRY(autotune(p, devname));
+    }
+    MFWF_TRY(set_groups(p));
     MFWF_HIP(hipStreamSynchronize(p.stream));
     return MFWF_OK;
 }
@@ -376,9 +531,9 @@ static int iteration(Plan &p, const double *rho, int nb, double lam, bool keep_p
     MFWF_TRY(launch_pixel_update(rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, lam, p.tau, p.stream));
     MFWF_TRY(launch_fft_fwd(p, p.d_t, p.d_phase, nb));
     MFWF_TRY(launch_leg_analysis(p, p.d_phase, p.d_apart, nb));
-    MFWF_TRY(launch_harmonic(p, p.d_apart, p.ngroup, p.omega, p.d_cl, lam * p.tau * p.omega, 0,
-                             p.d_salm, p.d_salm_prev, nb, keep_prev));
-    MFWF_TRY(launch_leg_synth(p, p.d_salm, p.d_phase, nb));
+    MFWF_TRY(launch_harmonic(p, p.d_apart, p.ngroup, p.omega, lam * p.tau * p.omega, kHarmWiener,
+                             p.d_salm, p.d_sp, keep_prev ? p.d_salm_prev : nullptr, nb));
+    MFWF_TRY(launch_leg_synth(p, p.d_sp, p.d_phase, nb));
     MFWF_TRY(launch_fft_inv(p, p.d_phase, p.d_smap, nb));
     return MFWF_OK;
 }
@@ -440,7 +595,7 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
     if (total > 0) {
         MFWF_TRY(launch_chi2_pix(rho, p.d_M, p.d_smap, p.npix, nb, last_lam, p.tau, p.d_red,
                                  p.nred_blocks, p.d_diag, p.stream));
-        MFWF_TRY(launch_harm_diag(p, p.d_salm, p.d_salm_prev, p.d_cl, nb, p.d_red, 0, p.d_diag));
+        MFWF_TRY(launch_harm_diag(p, p.d_salm, p.d_salm_prev, nb, p.d_red, p.d_diag));
     } else {
         MFWF_TRY(launch_fill(p.d_diag, 8L * nb, 0.0, p.stream));
     }
@@ -532,8 +687,9 @@ int mfwf_sht_inv(mfwf_plan plan, const double *alm, double *map, int nmaps) {
     Plan &p = plan->p;
     for (int b0 = 0; b0 < nmaps; b0 += p.max_batch) {
         const int nb = std::min(p.max_batch, nmaps - b0);
-        MFWF_TRY(launch_leg_synth(p, reinterpret_cast<const double2 *>(alm) + (long)b0 * p.nalm,
-                                  p.d_phase, nb));
+        MFWF_TRY(launch_harmonic(p, reinterpret_cast<const double2 *>(alm) + (long)b0 * p.nalm, 1,
+                                 1.0, 0.0, kHarmCopy, nullptr, p.d_sp, nullptr, nb));
+        MFWF_TRY(launch_leg_synth(p, p.d_sp, p.d_phase, nb));
         MFWF_TRY(launch_fft_inv(p, p.d_phase, map + (long)b0 * p.npix, nb));
     }
     return MFWF_OK;
@@ -548,9 +704,9 @@ int mfwf_sht_fwd(mfwf_plan plan, const double *map, double *alm, int nmaps) {
         const int nb = std::min(p.max_batch, nmaps - b0);
         MFWF_TRY(launch_fft_fwd(p, map + (long)b0 * p.npix, p.d_phase, nb));
         MFWF_TRY(launch_leg_analysis(p, p.d_phase, p.d_apart, nb));
-        MFWF_TRY(launch_harmonic(p, p.d_apart, p.ngroup, p.omega, p.d_cl, 0.0, 1,
+        MFWF_TRY(launch_harmonic(p, p.d_apart, p.ngroup, p.omega, 0.0, kHarmAnalysis,
                                  reinterpret_cast<double2 *>(alm) + (long)b0 * p.nalm, nullptr,
-                                 nb, false));
+                                 nullptr, nb));
     }
     return MFWF_OK;
 }
@@ -566,8 +722,8 @@ int mfwf_fluctuation_rhs(mfwf_plan plan, const double *g1, const double *h, int 
         const int nb = std::min(p.max_batch, nrhs - b0);
         // x = C^{-1/2} h, then Y x, then rho = M^{1/2} g1 + Omega Y x
         MFWF_TRY(launch_harmonic(p, reinterpret_cast<const double2 *>(h) + (long)b0 * p.nalm, 1,
-                                 1.0, p.d_cl, 0.0, 2, p.d_salm, nullptr, nb, false));
-        MFWF_TRY(launch_leg_synth(p, p.d_salm, p.d_phase, nb));
+                                 1.0, 0.0, kHarmInvSqrtC, nullptr, p.d_sp, nullptr, nb));
+        MFWF_TRY(launch_leg_synth(p, p.d_sp, p.d_phase, nb));
         MFWF_TRY(launch_fft_inv(p, p.d_phase, p.d_t, nb));
         MFWF_TRY(launch_fluct_combine(g1 + (long)b0 * p.npix, p.d_M, p.d_t,
                                       rho + (long)b0 * p.npix, p.npix, nb, p.omega, p.stream));
@@ -624,29 +780,20 @@ int mfwf_time_kernels(mfwf_plan plan, int nmaps, int reps, double *ms_out) {
     if (!p.have_cov) return fail(MFWF_ENOCOV, "covariances not set");
     if (nmaps > p.max_batch) return fail(MFWF_EINVAL, "nmaps > max_batch");
     const int nb = nmaps;
-    hipEvent_t e0, e1;
-    MFWF_HIP(hipEventCreate(&e0));
-    MFWF_HIP(hipEventCreate(&e1));
     for (int k = 0; k < 6; k++) {
-        MFWF_HIP(hipEventRecord(e0, p.stream));
-        for (int r = 0; r < reps; r++) {
-            switch (k) {
-                case 0: MFWF_TRY(launch_pixel_update(p.d_rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, 1.0, p.tau, p.stream)); break;
-                case 1: MFWF_TRY(launch_fft_fwd(p, p.d_t, p.d_phase, nb)); break;
-                case 2: MFWF_TRY(launch_leg_analysis(p, p.d_phase, p.d_apart, nb)); break;
-                case 3: MFWF_TRY(launch_harmonic(p, p.d_apart, p.ngroup, p.omega, p.d_cl, p.tau * p.omega, 0, p.d_salm, p.d_salm_prev, nb, false)); break;
-                case 4: MFWF_TRY(launch_leg_synth(p, p.d_salm, p.d_phase, nb)); break;
-                case 5: MFWF_TRY(launch_fft_inv(p, p.d_phase, p.d_smap, nb)); break;
-            }
+        std::function<int()> f;
+        switch (k) {
+            case 0: f = [&] { return launch_pixel_update(p.d_rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, 1.0, p.tau, p.stream); }; break;
+            case 1: f = [&] { return launch_fft_fwd(p, p.d_t, p.d_phase, nb); }; break;
+            case 2: f = [&] { return launch_leg_analysis(p, p.d_phase, p.d_apart, nb); }; break;
+            case 3: f = [&] { return launch_harmonic(p, p.d_apart, p.ngroup, p.omega, p.tau * p.omega, kHarmWiener, p.d_salm, p.d_sp, nullptr, nb); }; break;
+            case 4: f = [&] { return launch_leg_synth(p, p.d_sp, p.d_phase, nb); }; break;
+            default: f = [&] { return launch_fft_inv(p, p.d_phase, p.d_smap, nb); }; break;
         }
-        MFWF_HIP(hipEventRecord(e1, p.stream));
-        MFWF_HIP(hipEventSynchronize(e1));
         float ms = 0.f;
-        MFWF_HIP(hipEventElapsedTime(&ms, e0, e1));
+        MFWF_TRY(time_launches(p, reps, f, ms));
         ms_out[k] = ms / reps;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     return MFWF_OK;
 }
 

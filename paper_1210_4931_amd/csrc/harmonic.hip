@@ -4,6 +4,8 @@
 // real harmonic degree of freedom is tau * Omega, so Eq. (4),
 //   (S^-1 + (lambda T)^-1) s = (lambda T)^-1 t,  reads  s_lm = C_l / (C_l + lambda tau Omega) a_lm
 // with a = A t.  S^-1 is never formed; C_l = 0 gives s_lm = 0.
+// The Legendre kernels work with lambda_lm = c_lm mu_lm: partial analysis sums are
+// multiplied by c_lm here, and the synthesis input is written pre-multiplied by c_lm.
 // Grid (m, map): one block per m row of the packed alm, threads over l.
 #include "mfwf_internal.h"
 
@@ -11,40 +13,47 @@ namespace mfwf {
 
 static constexpr int kHT = 256;
 
-// mode 0: s = C/(C + lto) * scale * sum_g apart_g        (Wiener-filter update, Eq. 4)
-// mode 1: s = scale * sum_g apart_g                       (plain analysis, scale = Omega)
-// mode 2: s = C^{-1/2} * apart_0  (C = 0 -> 0)            (fluctuation source h -> C^-1/2 h)
-// keep_prev: copy the old s into prev before overwriting (for |s_k - s_{k-1}|).
+// mode 0: s = C/(C + lto) * scale * c * sum_g in_g        (Wiener-filter update, Eq. 4)
+// mode 1: s = scale * c * sum_g in_g                       (analysis, scale = Omega)
+// mode 2: s = C^{-1/2} * in  (C = 0 -> 0)                  (fluctuation source, h -> C^-1/2 h)
+// mode 3: s = in                                           (synthesis input)
+// out_s (nullable) <- s;  out_sp (nullable) <- c * s;  prev (nullable) <- old out_s.
 __global__ void __launch_bounds__(kHT)
-k_harmonic(const double2 *__restrict__ apart, int ngroup, long nalm, int nb,
-           const long *__restrict__ mofs, const double *__restrict__ cl, int lmax, double scale,
-           double lto, int mode, double2 *__restrict__ out, double2 *__restrict__ prev) {
+k_harmonic(const double2 *__restrict__ in, int ngroup, long nalm, int nb,
+           const long *__restrict__ mofs, const double *__restrict__ cl,
+           const double *__restrict__ ctab, int lmax, double scale, double lto, int mode,
+           double2 *__restrict__ out_s, double2 *__restrict__ out_sp,
+           double2 *__restrict__ prev) {
     const int m = blockIdx.x, b = blockIdx.y;
-    const long base = (long)b * nalm + mofs[m] - m;
+    const long toff = mofs[m] - m;
+    const long base = (long)b * nalm + toff;
     for (int l = m + threadIdx.x; l <= lmax; l += kHT) {
         const long i = base + l;
-        double2 a = apart[i];
+        const double c = ctab[toff + l];
+        double2 a = in[i];
         for (int g = 1; g < ngroup; g++) {
-            const double2 q = apart[(long)g * nb * nalm + i];
+            const double2 q = in[(long)g * nb * nalm + i];
             a.x += q.x;
             a.y += q.y;
         }
-        const double c = cl[l];
+        const double C = cl[l];
         double f;
-        if (mode == 0) f = c > 0.0 ? c / (c + lto) * scale : 0.0;
-        else if (mode == 1) f = scale;
-        else f = c > 0.0 ? 1.0 / sqrt(c) : 0.0;
-        if (prev) prev[i] = out[i];
-        out[i] = make_double2(f * a.x, f * a.y);
+        if (mode == 0) f = C > 0.0 ? C / (C + lto) * scale * c : 0.0;
+        else if (mode == 1) f = scale * c;
+        else if (mode == 2) f = C > 0.0 ? 1.0 / sqrt(C) : 0.0;
+        else f = 1.0;
+        const double2 s = make_double2(f * a.x, f * a.y);
+        if (prev) prev[i] = out_s[i];
+        if (out_s) out_s[i] = s;
+        if (out_sp) out_sp[i] = make_double2(c * s.x, c * s.y);
     }
 }
 
-int launch_harmonic(const Plan &p, const double2 *apart, int ngroup, double scale,
-                    const double *cl, double lamtauomega, int mode, double2 *salm,
-                    double2 *salm_prev, int nb, bool keep_prev) {
-    hipLaunchKernelGGL(k_harmonic, dim3(p.nm, nb), dim3(kHT), 0, p.stream, apart, ngroup, p.nalm,
-                       nb, p.d_mofs, cl, p.lmax, scale, lamtauomega, mode, salm,
-                       keep_prev ? salm_prev : nullptr);
+int launch_harmonic(const Plan &p, const double2 *in, int ngroup, double scale, double lto,
+                    int mode, double2 *out_s, double2 *out_sp, double2 *prev, int nb) {
+    hipLaunchKernelGGL(k_harmonic, dim3(p.nm, nb), dim3(kHT), 0, p.stream, in, ngroup, p.nalm,
+                       nb, p.d_mofs, p.d_cl, p.d_c, p.lmax, scale, lto, mode, out_s, out_sp,
+                       prev);
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }
@@ -95,10 +104,10 @@ __global__ void k_harm_diag_final(const double *__restrict__ partial, int nm, in
     diag[8 * b + 3] = n;
 }
 
-int launch_harm_diag(const Plan &p, const double2 *salm, const double2 *salm_prev,
-                     const double *cl, int nb, double *partial, int /*nblocks*/, double *diag) {
+int launch_harm_diag(const Plan &p, const double2 *salm, const double2 *salm_prev, int nb,
+                     double *partial, double *diag) {
     hipLaunchKernelGGL(k_harm_diag, dim3(p.nm, nb), dim3(kHT), 0, p.stream, salm, salm_prev,
-                       p.nalm, p.d_mofs, cl, p.lmax, p.nm, partial);
+                       p.nalm, p.d_mofs, p.d_cl, p.lmax, p.nm, partial);
     MFWF_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_harm_diag_final, dim3((nb + 63) / 64), dim3(64), 0, p.stream, partial,
                        p.nm, nb, diag);

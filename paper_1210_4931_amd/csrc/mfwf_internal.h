@@ -51,19 +51,24 @@ struct Plan {
     int nring, npair, nm;
     long nalm;
     double omega;
-    int P;        // ring pairs per lane in the Legendre kernels
-    int ngroup;   // pair groups (waves per m) in the Legendre kernels
+    int synth_variant = 0;  // index into the Legendre synthesis kernel variants
+    int ana_variant = 0;    // index into the Legendre analysis kernel variants
+    int ngroup;             // pair groups (waves per m) of the chosen analysis variant
+    int ngroup_max;         // largest pair-group count of any analysis variant
 
     // plan tables (device)
     double *d_z = nullptr;       // [npair] cos(theta) of the north ring of each pair
-    double2 *d_ab = nullptr;     // [nalm] (alpha_lm, beta_lm): lambda_l = alpha z lambda_{l-1} - beta lambda_{l-2}
+    double *d_A = nullptr;       // [nalm] A_lm of mu_l = A z mu_{l-1} - mu_{l-2}
+    double *d_c = nullptr;       // [nalm] c_lm, lambda_lm = c_lm mu_lm
     int *d_lstart = nullptr;     // [nm][npair]
-    double2 *d_seed = nullptr;   // [nm][npair]
+    double2 *d_seed = nullptr;   // [nm][npair] (mu_{l_s - 1}, mu_{l_s})
     PairFFT *d_pfft = nullptr;   // [npair]
     double2 *d_tw = nullptr;     // [fftmax] exp(-2 pi i k / fftmax)
     double2 *d_chirp = nullptr;  // Bluestein chirps exp(-i pi k^2 / n), per distinct n
     double2 *d_bhat = nullptr;   // Bluestein kernels FFT_M(conj chirp), bit-reversed order
     int fftmax;                  // largest power-of-two transform length
+    int *d_plist = nullptr;      // [npair] pair indices grouped by FFT class
+    int fft_class_off[2] = {0, 0}, fft_class_count[2] = {0, 0}, fft_class_len[2] = {1, 1};
     long *d_mofs = nullptr;      // [nm] packed offset of (l = m, m)
 
     // covariances
@@ -77,10 +82,11 @@ struct Plan {
     double *d_rho = nullptr;     // [B][npix]
     double *d_t = nullptr;       // [B][npix]
     double *d_smap = nullptr;    // [B][npix]
-    double2 *d_phase = nullptr;  // [B][nm][nring] ring Fourier coefficients
+    double2 *d_phase = nullptr;  // [B][nring][nm] ring Fourier coefficients
     double2 *d_apart = nullptr;  // [ngroup][B][nalm] partial analysis sums
     double2 *d_salm = nullptr;   // [B][nalm]
     double2 *d_salm_prev = nullptr;
+    double2 *d_sp = nullptr;     // [B][nalm] c_lm-scaled synthesis input
     double *d_red = nullptr;     // reduction partials
     double *d_diag = nullptr;    // [B][8] diagnostics
     int nred_blocks;
@@ -108,15 +114,19 @@ int launch_fluct_combine(const double *g1, const double *M, const double *ysh, d
 int launch_fft_fwd(const Plan &p, const double *maps, double2 *phase, int nb);
 int launch_fft_inv(const Plan &p, const double2 *phase, double *maps, int nb);
 
-// legendre.hip
-int launch_leg_synth(const Plan &p, const double2 *alm, double2 *phase, int nb);
+// legendre.hip (alm_scaled: c_lm-scaled coefficients; apart: sums of mu_lm X)
+int launch_leg_synth(const Plan &p, const double2 *alm_scaled, double2 *phase, int nb);
 int launch_leg_analysis(const Plan &p, const double2 *phase, double2 *apart, int nb);
+int leg_synth_variants();
+int leg_analysis_variants();
+int leg_synth_pairs_per_lane(int v);
+int leg_analysis_pairs_per_lane(int v);
 
 // harmonic.hip
-int launch_harmonic(const Plan &p, const double2 *apart, int ngroup, double scale,
-                    const double *cl, double lamtauomega, int mode, double2 *salm,
-                    double2 *salm_prev, int nb, bool diag);
-int launch_harm_diag(const Plan &p, const double2 *salm, const double2 *salm_prev,
-                     const double *cl, int nb, double *partial, int nblocks, double *diag);
+enum HarmMode { kHarmWiener = 0, kHarmAnalysis = 1, kHarmInvSqrtC = 2, kHarmCopy = 3 };
+int launch_harmonic(const Plan &p, const double2 *in, int ngroup, double scale, double lto,
+                    int mode, double2 *out_s, double2 *out_sp, double2 *prev, int nb);
+int launch_harm_diag(const Plan &p, const double2 *salm, const double2 *salm_prev, int nb,
+                     double *partial, double *diag);
 
 }  // namespace mfwf

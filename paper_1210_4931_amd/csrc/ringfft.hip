@@ -4,22 +4,29 @@
 // length n and offset phi_0, so they travel together as one complex sequence
 // x = t_N + i t_S and one length-n complex DFT serves both.
 //
-// Power-of-two n: in-LDS radix-2 transform.  The forward transform is decimation in
-// frequency (natural order in, bit-reversed out), so no permutation pass is needed.
-// Other n (polar rings n = 4i): Bluestein's chirp-z algorithm turns the length-n DFT into a
-// circular convolution of power-of-two length M >= 2n - 1, done as DIF -> pointwise product
-// with the precomputed transformed chirp (stored bit-reversed) -> DIT (bit-reversed in,
-// natural out).  Twiddles come from one table of the largest length.
+// Power-of-two n: in-LDS self-sorting (Stockham) transform with radix-8 passes (a final
+// radix-4 or radix-2 pass when needed): each thread keeps its butterflies' inputs in
+// registers across a barrier, so the passes run in place in one LDS buffer, and the output
+// is in natural order.  Other n (polar rings n = 4i): Bluestein's chirp-z algorithm turns
+// the length-n DFT into a circular convolution of power-of-two length M >= 2n - 1 (forward
+// transform, pointwise product with the precomputed transformed chirp, and a second forward
+// transform of the conjugate).  Twiddles come from one table of the largest length.
 //
-// Forward (analysis, a_lm side):  G_r(m) = sum_j t_{r,j} e^{-i m phi_{r,j}}, m = 0..lmax,
-// read from DFT bin m mod n (phase e^{-i m phi_0}).  Inverse (synthesis): the harmonics
-// F_r(m), m = -lmax..lmax with F(-m) = conj F(m), are folded into the n DFT bins and
-// transformed back.  Layout of the ring-Fourier array: [map][m][ring] complex.
+// Forward (analysis side):  G_r(m) = sum_j t_{r,j} e^{-i m phi_{r,j}}, m = 0..lmax, read
+// from DFT bin k = m mod n.  Inverse (synthesis): F_r(m), m = -lmax..lmax with
+// F(-m) = conj F(m), folded into the n bins and transformed back.  With phi_0 = pi/n
+// ("half shift"), e^{i m phi_0} = e^{i pi k / n} (-1)^q for m = k + q n, so each bin needs one
+// phase factor and its aliases only a sign.
+//
+// Ring-Fourier layout: [map][ring][m] complex, so both kernels stream contiguous rows.
+// Pairs are launched in two classes by transform length: most pairs need at most half the
+// largest length (less LDS, more workgroups per CU); the long Bluestein transforms of the
+// largest polar rings get twice the threads.
 #include "mfwf_internal.h"
 
 namespace mfwf {
 
-static constexpr int kFFTThreads = 256;
+static constexpr int kMaxEPT = 16;  // transform elements per thread
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -31,147 +38,207 @@ __device__ __forceinline__ double2 cadd(double2 a, double2 b) {
 __device__ __forceinline__ double2 csub(double2 a, double2 b) {
     return make_double2(a.x - b.x, a.y - b.y);
 }
+__device__ __forceinline__ double2 cscale(double2 a, double s) {
+    return make_double2(a.x * s, a.y * s);
+}
+__device__ __forceinline__ double2 mul_minus_i(double2 a) { return make_double2(a.y, -a.x); }
 
-// Forward DFT, decimation in frequency, natural order in -> bit-reversed order out.
-__device__ void fft_dif(double2 *buf, int len, const double2 *__restrict__ tw, int fftmax) {
-    for (int span = len; span >= 2; span >>= 1) {
-        const int half = span >> 1;
-        const int tstride = fftmax / span;
-        for (int b = threadIdx.x; b < (len >> 1); b += kFFTThreads) {
-            const int grp = b / half, k = b - grp * half;
-            const int i = grp * span + k, j = i + half;
-            double2 u = buf[i], v = buf[j];
-            buf[i] = cadd(u, v);
-            buf[j] = cmul(csub(u, v), tw[k * tstride]);
+// Forward R-point DFT in registers, natural order in and out (R = 2, 4, 8).
+template <int R>
+__device__ __forceinline__ void small_dft(double2 (&v)[R]) {
+    if constexpr (R == 2) {
+        const double2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+        const double2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+        const double2 s13 = cadd(v[1], v[3]), d13 = mul_minus_i(csub(v[1], v[3]));
+        v[0] = cadd(s02, s13);
+        v[2] = csub(s02, s13);
+        v[1] = cadd(d02, d13);
+        v[3] = csub(d02, d13);
+    } else {
+        double2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+        small_dft<4>(e);
+        small_dft<4>(o);
+        const double h = 0.70710678118654752440;  // W8 = (1 - i)/sqrt 2
+        o[1] = make_double2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));
+        o[2] = mul_minus_i(o[2]);
+        o[3] = make_double2(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            v[k] = cadd(e[k], o[k]);
+            v[k + 4] = csub(e[k], o[k]);
         }
-        __syncthreads();
     }
 }
 
-// Forward DFT, decimation in time, bit-reversed order in -> natural order out.
-__device__ void fft_dit(double2 *buf, int len, const double2 *__restrict__ tw, int fftmax) {
-    for (int span = 2; span <= len; span <<= 1) {
-        const int half = span >> 1;
-        const int tstride = fftmax / span;
-        for (int b = threadIdx.x; b < (len >> 1); b += kFFTThreads) {
-            const int grp = b / half, k = b - grp * half;
-            const int i = grp * span + k, j = i + half;
-            double2 u = buf[i], v = cmul(buf[j], tw[k * tstride]);
-            buf[i] = cadd(u, v);
-            buf[j] = csub(u, v);
+// One Stockham pass of radix R over buf[0..n): inputs j + r n/R, output (j/Ns) Ns R + j%Ns
+// + r Ns, twiddle exp(-2 pi i (j%Ns) r / (Ns R)).  All reads precede all writes.
+template <int TPB, int R>
+__device__ __forceinline__ void stockham_pass(double2 *buf, int n, int Ns,
+                                              const double2 *__restrict__ tw, int fftmax) {
+    constexpr int MAXB = kMaxEPT / R;
+    const int nbf = n / R;
+    double2 v[MAXB][R];
+#pragma unroll
+    for (int b = 0; b < MAXB; b++) {
+        const int j = threadIdx.x + b * TPB;
+        if (j < nbf) {
+#pragma unroll
+            for (int r = 0; r < R; r++) v[b][r] = buf[j + r * nbf];
         }
-        __syncthreads();
     }
+    __syncthreads();
+    const int ts = fftmax / (Ns * R);
+#pragma unroll
+    for (int b = 0; b < MAXB; b++) {
+        const int j = threadIdx.x + b * TPB;
+        if (j < nbf) {
+            const int kk = j & (Ns - 1);
+            if (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; r++) v[b][r] = cmul(v[b][r], tw[kk * r * ts]);
+            }
+            small_dft<R>(v[b]);
+            const int base = (j - kk) * R + kk;
+#pragma unroll
+            for (int r = 0; r < R; r++) buf[base + r * Ns] = v[b][r];
+        }
+    }
+    __syncthreads();
 }
 
-__device__ __forceinline__ int bitrev(int k, int logn) {
-    return logn == 0 ? 0 : (int)(__brev((unsigned)k) >> (32 - logn));
+// Forward DFT of buf[0..n), n a power of two <= kMaxEPT * TPB, natural order in and out.
+template <int TPB>
+__device__ void fft_stockham(double2 *buf, int n, const double2 *__restrict__ tw, int fftmax) {
+    int Ns = 1;
+    while (Ns < n) {
+        const int left = n / Ns;
+        if (left >= 8) {
+            stockham_pass<TPB, 8>(buf, n, Ns, tw, fftmax);
+            Ns *= 8;
+        } else if (left == 4) {
+            stockham_pass<TPB, 4>(buf, n, Ns, tw, fftmax);
+            Ns *= 4;
+        } else {
+            stockham_pass<TPB, 2>(buf, n, Ns, tw, fftmax);
+            Ns *= 2;
+        }
+    }
 }
 
 // Length-n forward DFT of buf[0..n) in place.  On return the transform value of bin k is
-// read with dft_bin(): buf[bitrev(k)] for power-of-two n, c_k conj(buf[k]) for Bluestein.
+// read with dft_bin(): buf[k] for power-of-two n, c_k conj(buf[k]) for Bluestein.
+template <int TPB>
 __device__ void ring_dft(double2 *buf, const PairFFT &pf, const double2 *__restrict__ tw,
                          int fftmax, const double2 *__restrict__ chirp,
                          const double2 *__restrict__ bhat) {
     const int n = pf.nphi, M = pf.fftlen;
     if (!pf.bluestein) {
-        fft_dif(buf, n, tw, fftmax);
+        fft_stockham<TPB>(buf, n, tw, fftmax);
         return;
     }
     const double2 *c = chirp + pf.chirp_off;
-    for (int j = threadIdx.x; j < M; j += kFFTThreads)
+    for (int j = threadIdx.x; j < M; j += TPB)
         buf[j] = (j < n) ? cmul(buf[j], c[j]) : make_double2(0.0, 0.0);
     __syncthreads();
-    fft_dif(buf, M, tw, fftmax);
-    const double2 *bh = bhat + pf.bhat_off;  // bit-reversed, already divided by M
-    for (int j = threadIdx.x; j < M; j += kFFTThreads) buf[j] = cconj(cmul(buf[j], bh[j]));
+    fft_stockham<TPB>(buf, M, tw, fftmax);
+    const double2 *bh = bhat + pf.bhat_off;  // transformed conj chirp, already divided by M
+    for (int j = threadIdx.x; j < M; j += TPB) buf[j] = cconj(cmul(buf[j], bh[j]));
     __syncthreads();
-    fft_dit(buf, M, tw, fftmax);
+    fft_stockham<TPB>(buf, M, tw, fftmax);
 }
 
-__device__ __forceinline__ double2 dft_bin(const double2 *buf, const PairFFT &pf, int logn,
+__device__ __forceinline__ double2 dft_bin(const double2 *buf, const PairFFT &pf,
                                            const double2 *__restrict__ chirp, int k) {
-    if (!pf.bluestein) return buf[bitrev(k, logn)];
+    if (!pf.bluestein) return buf[k];
     return cmul(chirp[pf.chirp_off + k], cconj(buf[k]));
 }
 
-// e^{i m phi_0}: phi_0 = pi / n (half_shift) or 0
-__device__ __forceinline__ double2 ring_phase(int m, int n, int half_shift) {
-    if (!half_shift) return make_double2(1.0, 0.0);
+// e^{i pi k / n}
+__device__ __forceinline__ double2 half_bin_phase(int k, int n) {
     double s, c;
-    sincospi((double)(m % (2 * n)) / (double)n, &s, &c);
+    sincospi((double)k / (double)n, &s, &c);
     return make_double2(c, s);
 }
 
-__global__ void __launch_bounds__(kFFTThreads)
+template <int TPB>
+__global__ void __launch_bounds__(TPB)
 k_fft_fwd(const double *__restrict__ maps, double2 *__restrict__ phase,
-          const PairFFT *__restrict__ pfft, const double2 *__restrict__ tw, int fftmax,
-          const double2 *__restrict__ chirp, const double2 *__restrict__ bhat, long npix,
-          int nring, int nm, int lmax) {
+          const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
+          const double2 *__restrict__ tw, int fftmax, const double2 *__restrict__ chirp,
+          const double2 *__restrict__ bhat, long npix, int nring, int nm, int lmax) {
     extern __shared__ double2 buf[];
-    const int p = blockIdx.x, b = blockIdx.y;
+    const int p = plist[blockIdx.x], b = blockIdx.y;
     const PairFFT pf = pfft[p];
     const int n = pf.nphi;
     const bool equator = (pf.startS == pf.startN);
     const double *tN = maps + (long)b * npix + pf.startN;
     const double *tS = maps + (long)b * npix + pf.startS;
-    for (int j = threadIdx.x; j < n; j += kFFTThreads)
+    for (int j = threadIdx.x; j < n; j += TPB)
         buf[j] = make_double2(tN[j], equator ? 0.0 : tS[j]);
     __syncthreads();
-    ring_dft(buf, pf, tw, fftmax, chirp, bhat);
-    const int logn = 31 - __clz(n);
-    const int rN = p, rS = nring - 1 - p;
-    double2 *out = phase + (long)b * nm * nring;
-    for (int m = threadIdx.x; m <= lmax; m += kFFTThreads) {
-        const int k = m % n;
-        const int kr = (n - k) % n;
-        const double2 X = dft_bin(buf, pf, logn, chirp, k);
-        const double2 Y = cconj(dft_bin(buf, pf, logn, chirp, kr));
-        const double2 ph = cconj(ring_phase(m, n, pf.half_shift));
+    ring_dft<TPB>(buf, pf, tw, fftmax, chirp, bhat);
+    double2 *outN = phase + ((long)b * nring + p) * nm;
+    double2 *outS = phase + ((long)b * nring + (nring - 1 - p)) * nm;
+    for (int m = threadIdx.x; m <= lmax; m += TPB) {
+        const int q = m / n, k = m - q * n;
+        const int kr = (k == 0) ? 0 : n - k;
+        const double2 X = dft_bin(buf, pf, chirp, k);
+        const double2 Y = cconj(dft_bin(buf, pf, chirp, kr));
+        // e^{-i m phi0} = (-1)^q e^{-i pi k / n} with a half shift, 1 otherwise
+        double2 ph = make_double2(1.0, 0.0);
+        if (pf.half_shift) ph = cscale(cconj(half_bin_phase(k, n)), (q & 1) ? -1.0 : 1.0);
         // X_N = (X_k + conj X_{-k}) / 2,  X_S = (X_k - conj X_{-k}) / (2i)
         const double2 gN = make_double2(0.5 * (X.x + Y.x), 0.5 * (X.y + Y.y));
-        out[(long)m * nring + rN] = cmul(gN, ph);
+        outN[m] = cmul(gN, ph);
         if (!equator) {
             const double2 gS = make_double2(0.5 * (X.y - Y.y), -0.5 * (X.x - Y.x));
-            out[(long)m * nring + rS] = cmul(gS, ph);
+            outS[m] = cmul(gS, ph);
         }
     }
 }
 
-__global__ void __launch_bounds__(kFFTThreads)
+template <int TPB>
+__global__ void __launch_bounds__(TPB)
 k_fft_inv(const double2 *__restrict__ phase, double *__restrict__ maps,
-          const PairFFT *__restrict__ pfft, const double2 *__restrict__ tw, int fftmax,
-          const double2 *__restrict__ chirp, const double2 *__restrict__ bhat, long npix,
-          int nring, int nm, int lmax) {
+          const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
+          const double2 *__restrict__ tw, int fftmax, const double2 *__restrict__ chirp,
+          const double2 *__restrict__ bhat, long npix, int nring, int nm, int lmax) {
     extern __shared__ double2 buf[];
-    __shared__ double2 partN[kFFTThreads], partS[kFFTThreads];
-    const int p = blockIdx.x, b = blockIdx.y;
+    const int p = plist[blockIdx.x], b = blockIdx.y;
     const PairFFT pf = pfft[p];
     const int n = pf.nphi;
+    double2 *partN = buf + pf.fftlen;  // [TPB] alias-sum partials after the FFT area
+    double2 *partS = partN + TPB;
     const bool equator = (pf.startS == pf.startN);
-    const int rN = p, rS = nring - 1 - p;
-    const double2 *F = phase + (long)b * nm * nring;
+    const double2 *FN = phase + ((long)b * nring + p) * nm;
+    const double2 *FS = phase + ((long)b * nring + (nring - 1 - p)) * nm;
 
-    // Fold harmonics into bins: B(k) = sum_{m = k mod n} F(m) e^{i m phi0}
-    //                                 + sum_{m >= 1, m = -k mod n} conj(F(m) e^{i m phi0}).
+    // Fold harmonics into bins: S(k) = sum_q sgn_q F(k + q n) over |k + q n| <= lmax with
+    // F(-m) = conj F(m) and sgn_q = (-1)^q under a half shift; then B(k) = e^{i pi k/n} S(k).
     // T threads per bin split the alias sum; partials are combined in a fixed order.
-    int T = kFFTThreads / n;
+    int T = TPB / n;
     if (T < 1) T = 1;
-    const int nbins_pass = kFFTThreads / T;  // bins handled per pass
+    const int nbins_pass = TPB / T;
+    const double sgn_step = pf.half_shift ? -1.0 : 1.0;
+    const double sg_stride = (T & 1) ? sgn_step : 1.0;
     for (int k0 = 0; k0 < n; k0 += nbins_pass) {
         const int k = k0 + threadIdx.x / T, t = threadIdx.x % T;
         double2 sN = make_double2(0.0, 0.0), sS = make_double2(0.0, 0.0);
         if (k < n && (int)threadIdx.x < nbins_pass * T) {
-            for (int m = k + t * n; m <= lmax; m += T * n) {
-                const double2 ph = ring_phase(m, n, pf.half_shift);
-                sN = cadd(sN, cmul(F[(long)m * nring + rN], ph));
-                if (!equator) sS = cadd(sS, cmul(F[(long)m * nring + rS], ph));
+            // m = k + q n >= 0, q = t, t + T, ...
+            double sg = (t & 1) ? sgn_step : 1.0;
+            for (int m = k + t * n; m <= lmax; m += T * n, sg *= sg_stride) {
+                sN = cadd(sN, cscale(FN[m], sg));
+                if (!equator) sS = cadd(sS, cscale(FS[m], sg));
             }
-            const int mneg0 = (k == 0) ? n : n - k;
-            for (int m = mneg0 + t * n; m <= lmax; m += T * n) {
-                const double2 ph = ring_phase(m, n, pf.half_shift);
-                sN = cadd(sN, cconj(cmul(F[(long)m * nring + rN], ph)));
-                if (!equator) sS = cadd(sS, cconj(cmul(F[(long)m * nring + rS], ph)));
+            // m = k + q n < 0, q = -1 - t, -1 - t - T, ...: F(m) = conj F(-m)
+            sg = ((t + 1) & 1) ? sgn_step : 1.0;
+            for (int mm = (t + 1) * n - k; mm <= lmax; mm += T * n, sg *= sg_stride) {
+                sN = cadd(sN, cscale(cconj(FN[mm]), sg));
+                if (!equator) sS = cadd(sS, cscale(cconj(FS[mm]), sg));
             }
         }
         if (T > 1) {
@@ -186,45 +253,80 @@ k_fft_inv(const double2 *__restrict__ phase, double *__restrict__ maps,
             }
             __syncthreads();
         }
-        // x_j = sum_k X_k e^{+2 pi i j k/n} = conj(DFT(conj X))_j with X = B_N + i B_S
-        if (t == 0 && k < n) buf[k] = cconj(make_double2(sN.x - sS.y, sN.y + sS.x));
+        if (t == 0 && k < n) {
+            if (pf.half_shift) {
+                const double2 ph = half_bin_phase(k, n);
+                sN = cmul(sN, ph);
+                sS = cmul(sS, ph);
+            }
+            // x_j = sum_k X_k e^{+2 pi i j k/n} = conj(DFT(conj X))_j with X = B_N + i B_S
+            buf[k] = cconj(make_double2(sN.x - sS.y, sN.y + sS.x));
+        }
     }
     __syncthreads();
-    ring_dft(buf, pf, tw, fftmax, chirp, bhat);
-    const int logn = 31 - __clz(n);
+    ring_dft<TPB>(buf, pf, tw, fftmax, chirp, bhat);
     double *sNmap = maps + (long)b * npix + pf.startN;
     double *sSmap = maps + (long)b * npix + pf.startS;
-    for (int j = threadIdx.x; j < n; j += kFFTThreads) {
-        const double2 x = cconj(dft_bin(buf, pf, logn, chirp, j));
+    for (int j = threadIdx.x; j < n; j += TPB) {
+        const double2 x = cconj(dft_bin(buf, pf, chirp, j));
         sNmap[j] = x.x;
         if (!equator) sSmap[j] = x.y;
     }
 }
 
+// threads per workgroup of a class: enough for kMaxEPT elements per thread
+static int class_tpb(const Plan &p, int c) { return p.fft_class_len[c] > kMaxEPT * 256 ? 512 : 256; }
+
+static size_t class_lds(const Plan &p, int c) {
+    return sizeof(double2) * ((size_t)p.fft_class_len[c] + 2 * class_tpb(p, c));
+}
+
+template <int TPB>
+static void fwd_launch(const Plan &p, int c, const double *maps, double2 *phase, int nb) {
+    hipLaunchKernelGGL(k_fft_fwd<TPB>, dim3(p.fft_class_count[c], nb), dim3(TPB), class_lds(p, c),
+                       p.stream, maps, phase, p.d_pfft, p.d_plist + p.fft_class_off[c], p.d_tw,
+                       p.fftmax, p.d_chirp, p.d_bhat, p.npix, p.nring, p.nm, p.lmax);
+}
+
+template <int TPB>
+static void inv_launch(const Plan &p, int c, const double2 *phase, double *maps, int nb) {
+    hipLaunchKernelGGL(k_fft_inv<TPB>, dim3(p.fft_class_count[c], nb), dim3(TPB), class_lds(p, c),
+                       p.stream, phase, maps, p.d_pfft, p.d_plist + p.fft_class_off[c], p.d_tw,
+                       p.fftmax, p.d_chirp, p.d_bhat, p.npix, p.nring, p.nm, p.lmax);
+}
+
 int launch_fft_fwd(const Plan &p, const double *maps, double2 *phase, int nb) {
-    size_t lds = sizeof(double2) * (size_t)p.fftmax;
-    hipLaunchKernelGGL(k_fft_fwd, dim3(p.npair, nb), dim3(kFFTThreads), lds, p.stream, maps,
-                       phase, p.d_pfft, p.d_tw, p.fftmax, p.d_chirp, p.d_bhat, p.npix, p.nring,
-                       p.nm, p.lmax);
-    MFWF_HIP(hipGetLastError());
+    for (int c = 1; c >= 0; c--) {  // long transforms first
+        if (p.fft_class_count[c] == 0) continue;
+        if (class_tpb(p, c) == 512)
+            fwd_launch<512>(p, c, maps, phase, nb);
+        else
+            fwd_launch<256>(p, c, maps, phase, nb);
+        MFWF_HIP(hipGetLastError());
+    }
     return MFWF_OK;
 }
 
 int launch_fft_inv(const Plan &p, const double2 *phase, double *maps, int nb) {
-    size_t lds = sizeof(double2) * (size_t)p.fftmax;
-    hipLaunchKernelGGL(k_fft_inv, dim3(p.npair, nb), dim3(kFFTThreads), lds, p.stream, phase,
-                       maps, p.d_pfft, p.d_tw, p.fftmax, p.d_chirp, p.d_bhat, p.npix, p.nring,
-                       p.nm, p.lmax);
-    MFWF_HIP(hipGetLastError());
+    for (int c = 1; c >= 0; c--) {
+        if (p.fft_class_count[c] == 0) continue;
+        if (class_tpb(p, c) == 512)
+            inv_launch<512>(p, c, phase, maps, nb);
+        else
+            inv_launch<256>(p, c, phase, maps, nb);
+        MFWF_HIP(hipGetLastError());
+    }
     return MFWF_OK;
 }
 
+int fft_max_length() { return kMaxEPT * 512; }
+
 // Maximum dynamic LDS the FFT kernels may request (set once per process).
 int fft_set_lds_limit(size_t bytes) {
-    MFWF_HIP(hipFuncSetAttribute((const void *)k_fft_fwd,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-    MFWF_HIP(hipFuncSetAttribute((const void *)k_fft_inv,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    const void *fns[] = {(const void *)k_fft_fwd<256>, (const void *)k_fft_fwd<512>,
+                         (const void *)k_fft_inv<256>, (const void *)k_fft_inv<512>};
+    for (const void *f : fns)
+        MFWF_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     return MFWF_OK;
 }
 
