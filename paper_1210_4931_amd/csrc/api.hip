@@ -222,7 +222,9 @@ static void free_plan(Plan &p) {
     void *ptrs[] = {p.d_z,    p.d_A,    p.d_c,     p.d_lstart, p.d_seed,  p.d_pfft, p.d_plist,
                     p.d_tw,   p.d_chirp, p.d_bhat, p.d_mofs,   p.d_cl,    p.d_M,
                     p.d_rho,  p.d_t,    p.d_smap,  p.d_phase,  p.d_apart, p.d_salm,
-                    p.d_salm_prev, p.d_sp, p.d_red, p.d_diag};
+                    p.d_salm_prev, p.d_sp, p.d_red, p.d_diag, p.d_lam, p.d_loff, p.d_Lp,
+                    p.d_minls32, p.d_minls64, p.d_ana_items, p.d_lofi, p.d_ph32, p.d_a32,
+                    p.d_s32};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
 }
@@ -341,6 +343,59 @@ static void default_variants(Plan &p) {
         if (leg_analysis_pairs_per_lane(v) == P && v >= 3) p.ana_variant = v;
 }
 
+// Batched FP32 form: lambda table (filled on the device from the FP64 recurrence), skip
+// tables, work items, column-major work arrays.
+static int setup_batched(Plan &p, const std::vector<int> &lstart, const std::vector<long> &mofs) {
+    p.Rp = ((p.npair + 63) / 64) * 64;
+    p.Bp = ((p.max_batch + 15) / 16) * 16;
+    p.C2 = 2 * p.Bp;
+    std::vector<long> loff(p.nm);
+    std::vector<int> Lp(p.nm);
+    long tot = 0;
+    for (int m = 0; m < p.nm; m++) {
+        Lp[m] = ((p.lmax - m + 1 + 63) / 64) * 64;
+        loff[m] = tot;
+        tot += (long)p.Rp * Lp[m];
+    }
+    const int n32 = p.Rp / 32, n64 = p.Rp / 64;
+    std::vector<int> mn32((size_t)p.nm * n32, p.lmax + 1), mn64((size_t)p.nm * n64, p.lmax + 1);
+    for (int m = 0; m < p.nm; m++)
+        for (int q = 0; q < p.npair; q++) {
+            const int ls = lstart[(size_t)m * p.npair + q];
+            int &a = mn32[(size_t)m * n32 + q / 32], &b = mn64[(size_t)m * n64 + q / 64];
+            a = std::min(a, ls);
+            b = std::min(b, ls);
+        }
+    std::vector<int2> items;
+    for (int m = 0; m < p.nm; m++)
+        for (int t = 0; 64 * t < p.lmax - m + 1; t++) items.push_back(make_int2(m, t));
+    p.n_ana_items = (int)items.size();
+    std::vector<int> lofi(p.nalm);
+    for (int m = 0; m < p.nm; m++)
+        for (int l = m; l <= p.lmax; l++) lofi[mofs[m] + l - m] = l;
+    MFWF_TRY(dalloc(&p.d_lam, tot, "lambda table"));
+    MFWF_TRY(dalloc(&p.d_loff, loff.size(), "lambda offsets"));
+    MFWF_TRY(dalloc(&p.d_Lp, Lp.size(), "lambda row lengths"));
+    MFWF_TRY(dalloc(&p.d_minls32, mn32.size(), "start table 32"));
+    MFWF_TRY(dalloc(&p.d_minls64, mn64.size(), "start table 64"));
+    MFWF_TRY(dalloc(&p.d_ana_items, items.size(), "analysis items"));
+    MFWF_TRY(dalloc(&p.d_lofi, lofi.size(), "l of index"));
+    MFWF_TRY(dalloc(&p.d_ph32, (size_t)p.nring * p.nm * p.C2, "ring Fourier FP32"));
+    MFWF_TRY(dalloc(&p.d_a32, (size_t)p.nalm * p.C2, "analysis FP32"));
+    MFWF_TRY(dalloc(&p.d_s32, (size_t)p.nalm * p.C2, "synthesis input FP32"));
+    MFWF_TRY(upload(p.d_loff, loff, p.stream));
+    MFWF_TRY(upload(p.d_Lp, Lp, p.stream));
+    MFWF_TRY(upload(p.d_minls32, mn32, p.stream));
+    MFWF_TRY(upload(p.d_minls64, mn64, p.stream));
+    MFWF_TRY(upload(p.d_ana_items, items, p.stream));
+    MFWF_TRY(upload(p.d_lofi, lofi, p.stream));
+    MFWF_HIP(hipMemsetAsync(p.d_ph32, 0, sizeof(float) * (size_t)p.nring * p.nm * p.C2, p.stream));
+    MFWF_HIP(hipMemsetAsync(p.d_a32, 0, sizeof(float) * (size_t)p.nalm * p.C2, p.stream));
+    MFWF_HIP(hipMemsetAsync(p.d_s32, 0, sizeof(float) * (size_t)p.nalm * p.C2, p.stream));
+    MFWF_TRY(launch_lam_table(p));
+    return MFWF_OK;
+}
+
 static int set_groups(Plan &p) {
     const int P = leg_analysis_pairs_per_lane(p.ana_variant);
     p.ngroup = (p.npair + 64 * P - 1) / (64 * P);
@@ -353,8 +408,9 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
         return fail(MFWF_EINVAL, "nside must be a power of two in [1, 1024]");
     if (lmax < 1 || lmax > 4 * nside) return fail(MFWF_EINVAL, "lmax must be in [1, 4 nside]");
     if (spin != 0) return fail(MFWF_EINVAL, "only spin 0 (temperature) is supported");
-    if (dtype != MFWF_F64) return fail(MFWF_EINVAL, "only MFWF_F64 is supported");
+    if (dtype != MFWF_F64 && dtype != MFWF_F32) return fail(MFWF_EINVAL, "dtype must be MFWF_F64 or MFWF_F32");
     if (max_batch < 1 || max_batch > 4096) return fail(MFWF_EINVAL, "max_batch out of range");
+    if (dtype == MFWF_F32 && max_batch > 512) return fail(MFWF_EINVAL, "MFWF_F32 plans take max_batch <= 512");
     std::string devname;
     MFWF_TRY(device_name(devname));
 
@@ -456,10 +512,15 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
         if (lds > (size_t)maxlds)
             return fail(MFWF_EINVAL, "ring FFT of length " + std::to_string(fftmax) +
                                          " does not fit the device LDS");
-        if (lds > 65536) MFWF_TRY(fft_set_lds_limit(lds));
+        if (lds > 65536) {
+            MFWF_TRY(fft_set_lds_limit(lds));
+            MFWF_TRY(batched_set_lds_limit(lds));
+        }
     }
 
     const long B = max_batch;
+    const bool f32 = (dtype == MFWF_F32);
+    const long B64 = f32 ? 1 : B;  // the FP32 form has its own column-major work arrays
     MFWF_TRY(dalloc(&p.d_z, p.npair, "z"));
     MFWF_TRY(dalloc(&p.d_A, Atab.size(), "recurrence A"));
     MFWF_TRY(dalloc(&p.d_c, ctab.size(), "recurrence scale"));
@@ -476,8 +537,8 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     MFWF_TRY(dalloc(&p.d_rho, B * p.npix, "rho"));
     MFWF_TRY(dalloc(&p.d_t, B * p.npix, "t"));
     MFWF_TRY(dalloc(&p.d_smap, B * p.npix, "s map"));
-    MFWF_TRY(dalloc(&p.d_phase, B * p.nm * p.nring, "ring Fourier"));
-    MFWF_TRY(dalloc(&p.d_apart, (long)p.ngroup_max * B * p.nalm, "analysis partials"));
+    MFWF_TRY(dalloc(&p.d_phase, B64 * p.nm * p.nring, "ring Fourier"));
+    MFWF_TRY(dalloc(&p.d_apart, (long)p.ngroup_max * B64 * p.nalm, "analysis partials"));
     MFWF_TRY(dalloc(&p.d_salm, B * p.nalm, "s alm"));
     MFWF_TRY(dalloc(&p.d_salm_prev, B * p.nalm, "previous s alm"));
     MFWF_TRY(dalloc(&p.d_sp, B * p.nalm, "scaled synthesis input"));
@@ -502,14 +563,16 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     MFWF_TRY(launch_fill(p.d_rho, B * p.npix, 0.0, p.stream));
     MFWF_TRY(launch_fill(p.d_t, B * p.npix, 0.0, p.stream));
     MFWF_TRY(launch_fill(p.d_smap, B * p.npix, 0.0, p.stream));
-    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_phase), 2 * B * p.nm * p.nring, 0.0, p.stream));
-    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_apart), 2L * p.ngroup_max * B * p.nalm, 0.0, p.stream));
+    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_phase), 2 * B64 * p.nm * p.nring, 0.0, p.stream));
+    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_apart), 2L * p.ngroup_max * B64 * p.nalm, 0.0, p.stream));
     MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm), 2 * B * p.nalm, 0.0, p.stream));
     MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm_prev), 2 * B * p.nalm, 0.0, p.stream));
     MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_sp), 2 * B * p.nalm, 0.0, p.stream));
 
     default_variants(p);
-    if (const char *env = std::getenv("MFWF_LEG_VARIANTS")) {  // "synth,analysis" override
+    if (f32) {
+        MFWF_TRY(setup_batched(p, lstart, mofs));
+    } else if (const char *env = std::getenv("MFWF_LEG_VARIANTS")) {  // "synth,analysis" override
         int sv = -1, av = -1;
         if (std::sscanf(env, "%d,%d", &sv, &av) != 2 || sv < 0 || sv >= leg_synth_variants() ||
             av < 0 || av >= leg_analysis_variants())
@@ -527,7 +590,21 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
 
 // ---- driver ------------------------------------------------------------------------------
 
+// FP32 form: Legendre steps as MFMA GEMMs over the batch (Eqs. 3-4 unchanged)
+static int iteration_b(Plan &p, const double *rho, int nb, double lam, bool keep_prev) {
+    MFWF_TRY(launch_pixel_update(rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, lam, p.tau, p.stream));
+    MFWF_TRY(launch_fft_fwd_b(p, p.d_t, nb));
+    MFWF_TRY(launch_gemm_analysis(p, nb));
+    if (keep_prev) MFWF_TRY(launch_cols_to_alm(p, p.d_s32, p.d_salm_prev, nb, 1.0));
+    MFWF_TRY(launch_harmonic_b(p, p.omega, lam * p.tau * p.omega, nb));
+    if (keep_prev) MFWF_TRY(launch_cols_to_alm(p, p.d_s32, p.d_salm, nb, 1.0));
+    MFWF_TRY(launch_gemm_synthesis(p, nb));
+    MFWF_TRY(launch_fft_inv_b(p, p.d_smap, nb));
+    return MFWF_OK;
+}
+
 static int iteration(Plan &p, const double *rho, int nb, double lam, bool keep_prev) {
+    if (p.dtype == MFWF_F32) return iteration_b(p, rho, nb, lam, keep_prev);
     MFWF_TRY(launch_pixel_update(rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, lam, p.tau, p.stream));
     MFWF_TRY(launch_fft_fwd(p, p.d_t, p.d_phase, nb));
     MFWF_TRY(launch_leg_analysis(p, p.d_phase, p.d_apart, nb));
@@ -573,6 +650,8 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
     }
     MFWF_TRY(launch_fill(p.d_smap, p.npix * nb, 0.0, p.stream));
     MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm), 2 * p.nalm * nb, 0.0, p.stream));
+    if (p.dtype == MFWF_F32)  // previous harmonic iterate = 0 (outside any graph capture)
+        MFWF_HIP(hipMemsetAsync(p.d_s32, 0, sizeof(float) * (size_t)p.nalm * p.C2, p.stream));
     long total = 0;
     for (int it : its) total += it;
     long done = 0;
@@ -687,6 +766,13 @@ int mfwf_sht_inv(mfwf_plan plan, const double *alm, double *map, int nmaps) {
     Plan &p = plan->p;
     for (int b0 = 0; b0 < nmaps; b0 += p.max_batch) {
         const int nb = std::min(p.max_batch, nmaps - b0);
+        if (p.dtype == MFWF_F32) {
+            MFWF_TRY(launch_alm_to_cols(p, reinterpret_cast<const double2 *>(alm) + (long)b0 * p.nalm,
+                                        p.d_s32, nb, kHarmCopy));
+            MFWF_TRY(launch_gemm_synthesis(p, nb));
+            MFWF_TRY(launch_fft_inv_b(p, map + (long)b0 * p.npix, nb));
+            continue;
+        }
         MFWF_TRY(launch_harmonic(p, reinterpret_cast<const double2 *>(alm) + (long)b0 * p.nalm, 1,
                                  1.0, 0.0, kHarmCopy, nullptr, p.d_sp, nullptr, nb));
         MFWF_TRY(launch_leg_synth(p, p.d_sp, p.d_phase, nb));
@@ -702,6 +788,13 @@ int mfwf_sht_fwd(mfwf_plan plan, const double *map, double *alm, int nmaps) {
     Plan &p = plan->p;
     for (int b0 = 0; b0 < nmaps; b0 += p.max_batch) {
         const int nb = std::min(p.max_batch, nmaps - b0);
+        if (p.dtype == MFWF_F32) {
+            MFWF_TRY(launch_fft_fwd_b(p, map + (long)b0 * p.npix, nb));
+            MFWF_TRY(launch_gemm_analysis(p, nb));
+            MFWF_TRY(launch_cols_to_alm(p, p.d_a32, reinterpret_cast<double2 *>(alm) + (long)b0 * p.nalm,
+                                        nb, p.omega));
+            continue;
+        }
         MFWF_TRY(launch_fft_fwd(p, map + (long)b0 * p.npix, p.d_phase, nb));
         MFWF_TRY(launch_leg_analysis(p, p.d_phase, p.d_apart, nb));
         MFWF_TRY(launch_harmonic(p, p.d_apart, p.ngroup, p.omega, 0.0, kHarmAnalysis,
@@ -721,10 +814,17 @@ int mfwf_fluctuation_rhs(mfwf_plan plan, const double *g1, const double *h, int 
     for (int b0 = 0; b0 < nrhs; b0 += p.max_batch) {
         const int nb = std::min(p.max_batch, nrhs - b0);
         // x = C^{-1/2} h, then Y x, then rho = M^{1/2} g1 + Omega Y x
-        MFWF_TRY(launch_harmonic(p, reinterpret_cast<const double2 *>(h) + (long)b0 * p.nalm, 1,
-                                 1.0, 0.0, kHarmInvSqrtC, nullptr, p.d_sp, nullptr, nb));
-        MFWF_TRY(launch_leg_synth(p, p.d_sp, p.d_phase, nb));
-        MFWF_TRY(launch_fft_inv(p, p.d_phase, p.d_t, nb));
+        if (p.dtype == MFWF_F32) {
+            MFWF_TRY(launch_alm_to_cols(p, reinterpret_cast<const double2 *>(h) + (long)b0 * p.nalm,
+                                        p.d_s32, nb, kHarmInvSqrtC));
+            MFWF_TRY(launch_gemm_synthesis(p, nb));
+            MFWF_TRY(launch_fft_inv_b(p, p.d_t, nb));
+        } else {
+            MFWF_TRY(launch_harmonic(p, reinterpret_cast<const double2 *>(h) + (long)b0 * p.nalm, 1,
+                                     1.0, 0.0, kHarmInvSqrtC, nullptr, p.d_sp, nullptr, nb));
+            MFWF_TRY(launch_leg_synth(p, p.d_sp, p.d_phase, nb));
+            MFWF_TRY(launch_fft_inv(p, p.d_phase, p.d_t, nb));
+        }
         MFWF_TRY(launch_fluct_combine(g1 + (long)b0 * p.npix, p.d_M, p.d_t,
                                       rho + (long)b0 * p.npix, p.npix, nb, p.omega, p.stream));
     }
@@ -780,8 +880,23 @@ int mfwf_time_kernels(mfwf_plan plan, int nmaps, int reps, double *ms_out) {
     if (!p.have_cov) return fail(MFWF_ENOCOV, "covariances not set");
     if (nmaps > p.max_batch) return fail(MFWF_EINVAL, "nmaps > max_batch");
     const int nb = nmaps;
+    const bool f32 = (p.dtype == MFWF_F32);
     for (int k = 0; k < 6; k++) {
         std::function<int()> f;
+        if (f32) {
+            switch (k) {
+                case 0: f = [&] { return launch_pixel_update(p.d_rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, 1.0, p.tau, p.stream); }; break;
+                case 1: f = [&] { return launch_fft_fwd_b(p, p.d_t, nb); }; break;
+                case 2: f = [&] { return launch_gemm_analysis(p, nb); }; break;
+                case 3: f = [&] { return launch_harmonic_b(p, p.omega, p.tau * p.omega, nb); }; break;
+                case 4: f = [&] { return launch_gemm_synthesis(p, nb); }; break;
+                default: f = [&] { return launch_fft_inv_b(p, p.d_smap, nb); }; break;
+            }
+            float ms = 0.f;
+            MFWF_TRY(time_launches(p, reps, f, ms));
+            ms_out[k] = ms / reps;
+            continue;
+        }
         switch (k) {
             case 0: f = [&] { return launch_pixel_update(p.d_rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, 1.0, p.tau, p.stream); }; break;
             case 1: f = [&] { return launch_fft_fwd(p, p.d_t, p.d_phase, nb); }; break;

@@ -91,6 +91,22 @@ struct Plan {
     double *d_diag = nullptr;    // [B][8] diagnostics
     int nred_blocks;
     double work_tuples = 0.0;  // (l, m, pair) triples with l >= start index
+
+    // batched FP32 form (dtype MFWF_F32): lambda table and column-major work arrays
+    int Rp = 0;                  // ring pairs padded to 64
+    int Bp = 0;                  // maps padded to 16
+    int C2 = 0;                  // columns = 2 Bp (re, im of each map)
+    float *d_lam = nullptr;      // lambda_lm(z_p) FP32, rows [m][pair][l - m] padded to 64
+    long *d_loff = nullptr;      // [nm] offset of m's rows
+    int *d_Lp = nullptr;         // [nm] padded row length
+    int *d_minls32 = nullptr;    // [nm][Rp/32] smallest start index in each 32-pair chunk
+    int *d_minls64 = nullptr;    // [nm][Rp/64] smallest start index in each 64-pair tile
+    int2 *d_ana_items = nullptr; // (m, l tile) work items of the analysis GEMM
+    int n_ana_items = 0;
+    int *d_lofi = nullptr;       // [nalm] l of each packed index
+    float *d_ph32 = nullptr;     // [nring][nm][C2] ring-Fourier, maps innermost
+    float *d_a32 = nullptr;      // [nalm][C2] analysis output
+    float *d_s32 = nullptr;      // [nalm][C2] synthesis input
 };
 
 // ---- kernels (launch wrappers) --------------------------------------------------------
@@ -121,6 +137,17 @@ int leg_synth_variants();
 int leg_analysis_variants();
 int leg_synth_pairs_per_lane(int v);
 int leg_analysis_pairs_per_lane(int v);
+
+// batched.hip (FP32 form)
+int launch_lam_table(const Plan &p);
+int launch_fft_fwd_b(const Plan &p, const double *maps, int nb);
+int launch_fft_inv_b(const Plan &p, double *maps, int nb);
+int launch_gemm_analysis(const Plan &p, int nb);
+int launch_gemm_synthesis(const Plan &p, int nb);
+int launch_harmonic_b(const Plan &p, double scale, double lto, int nb);
+int launch_alm_to_cols(const Plan &p, const double2 *alm, float *x32, int nb, int mode);
+int launch_cols_to_alm(const Plan &p, const float *x32, double2 *alm, int nb, double scale);
+int batched_set_lds_limit(size_t bytes);
 
 // harmonic.hip
 enum HarmMode { kHarmWiener = 0, kHarmAnalysis = 1, kHarmInvSqrtC = 2, kHarmCopy = 3 };

@@ -22,146 +22,9 @@
 // Pairs are launched in two classes by transform length: most pairs need at most half the
 // largest length (less LDS, more workgroups per CU); the long Bluestein transforms of the
 // largest polar rings get twice the threads.
-#include "mfwf_internal.h"
+#include "fft_core.h"
 
 namespace mfwf {
-
-static constexpr int kMaxEPT = 16;  // transform elements per thread
-
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
-    return make_double2(a.x + b.x, a.y + b.y);
-}
-__device__ __forceinline__ double2 csub(double2 a, double2 b) {
-    return make_double2(a.x - b.x, a.y - b.y);
-}
-__device__ __forceinline__ double2 cscale(double2 a, double s) {
-    return make_double2(a.x * s, a.y * s);
-}
-__device__ __forceinline__ double2 mul_minus_i(double2 a) { return make_double2(a.y, -a.x); }
-
-// Forward R-point DFT in registers, natural order in and out (R = 2, 4, 8).
-template <int R>
-__device__ __forceinline__ void small_dft(double2 (&v)[R]) {
-    if constexpr (R == 2) {
-        const double2 a = v[0], b = v[1];
-        v[0] = cadd(a, b);
-        v[1] = csub(a, b);
-    } else if constexpr (R == 4) {
-        const double2 s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
-        const double2 s13 = cadd(v[1], v[3]), d13 = mul_minus_i(csub(v[1], v[3]));
-        v[0] = cadd(s02, s13);
-        v[2] = csub(s02, s13);
-        v[1] = cadd(d02, d13);
-        v[3] = csub(d02, d13);
-    } else {
-        double2 e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
-        small_dft<4>(e);
-        small_dft<4>(o);
-        const double h = 0.70710678118654752440;  // W8 = (1 - i)/sqrt 2
-        o[1] = make_double2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));
-        o[2] = mul_minus_i(o[2]);
-        o[3] = make_double2(h * (o[3].y - o[3].x), -h * (o[3].x + o[3].y));
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            v[k] = cadd(e[k], o[k]);
-            v[k + 4] = csub(e[k], o[k]);
-        }
-    }
-}
-
-// One Stockham pass of radix R over buf[0..n): inputs j + r n/R, output (j/Ns) Ns R + j%Ns
-// + r Ns, twiddle exp(-2 pi i (j%Ns) r / (Ns R)).  All reads precede all writes.
-template <int TPB, int R>
-__device__ __forceinline__ void stockham_pass(double2 *buf, int n, int Ns,
-                                              const double2 *__restrict__ tw, int fftmax) {
-    constexpr int MAXB = kMaxEPT / R;
-    const int nbf = n / R;
-    double2 v[MAXB][R];
-#pragma unroll
-    for (int b = 0; b < MAXB; b++) {
-        const int j = threadIdx.x + b * TPB;
-        if (j < nbf) {
-#pragma unroll
-            for (int r = 0; r < R; r++) v[b][r] = buf[j + r * nbf];
-        }
-    }
-    __syncthreads();
-    const int ts = fftmax / (Ns * R);
-#pragma unroll
-    for (int b = 0; b < MAXB; b++) {
-        const int j = threadIdx.x + b * TPB;
-        if (j < nbf) {
-            const int kk = j & (Ns - 1);
-            if (Ns > 1) {
-#pragma unroll
-                for (int r = 1; r < R; r++) v[b][r] = cmul(v[b][r], tw[kk * r * ts]);
-            }
-            small_dft<R>(v[b]);
-            const int base = (j - kk) * R + kk;
-#pragma unroll
-            for (int r = 0; r < R; r++) buf[base + r * Ns] = v[b][r];
-        }
-    }
-    __syncthreads();
-}
-
-// Forward DFT of buf[0..n), n a power of two <= kMaxEPT * TPB, natural order in and out.
-template <int TPB>
-__device__ void fft_stockham(double2 *buf, int n, const double2 *__restrict__ tw, int fftmax) {
-    int Ns = 1;
-    while (Ns < n) {
-        const int left = n / Ns;
-        if (left >= 8) {
-            stockham_pass<TPB, 8>(buf, n, Ns, tw, fftmax);
-            Ns *= 8;
-        } else if (left == 4) {
-            stockham_pass<TPB, 4>(buf, n, Ns, tw, fftmax);
-            Ns *= 4;
-        } else {
-            stockham_pass<TPB, 2>(buf, n, Ns, tw, fftmax);
-            Ns *= 2;
-        }
-    }
-}
-
-// Length-n forward DFT of buf[0..n) in place.  On return the transform value of bin k is
-// read with dft_bin(): buf[k] for power-of-two n, c_k conj(buf[k]) for Bluestein.
-template <int TPB>
-__device__ void ring_dft(double2 *buf, const PairFFT &pf, const double2 *__restrict__ tw,
-                         int fftmax, const double2 *__restrict__ chirp,
-                         const double2 *__restrict__ bhat) {
-    const int n = pf.nphi, M = pf.fftlen;
-    if (!pf.bluestein) {
-        fft_stockham<TPB>(buf, n, tw, fftmax);
-        return;
-    }
-    const double2 *c = chirp + pf.chirp_off;
-    for (int j = threadIdx.x; j < M; j += TPB)
-        buf[j] = (j < n) ? cmul(buf[j], c[j]) : make_double2(0.0, 0.0);
-    __syncthreads();
-    fft_stockham<TPB>(buf, M, tw, fftmax);
-    const double2 *bh = bhat + pf.bhat_off;  // transformed conj chirp, already divided by M
-    for (int j = threadIdx.x; j < M; j += TPB) buf[j] = cconj(cmul(buf[j], bh[j]));
-    __syncthreads();
-    fft_stockham<TPB>(buf, M, tw, fftmax);
-}
-
-__device__ __forceinline__ double2 dft_bin(const double2 *buf, const PairFFT &pf,
-                                           const double2 *__restrict__ chirp, int k) {
-    if (!pf.bluestein) return buf[k];
-    return cmul(chirp[pf.chirp_off + k], cconj(buf[k]));
-}
-
-// e^{i pi k / n}
-__device__ __forceinline__ double2 half_bin_phase(int k, int n) {
-    double s, c;
-    sincospi((double)k / (double)n, &s, &c);
-    return make_double2(c, s);
-}
 
 template <int TPB>
 __global__ void __launch_bounds__(TPB)

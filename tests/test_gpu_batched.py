@@ -1,0 +1,114 @@
+"""Batched FP32 form (MFMA Legendre contractions) against the FP64 oracle.
+
+Tolerance: 1e-5 relative error per result (the stated accuracy target of the FP32 form), over
+the real harmonic dof or the map.  The FP32 pieces are the tabulated lambda_lm, the
+ring-Fourier coefficients and the harmonic coefficients fed to the matrix cores; each
+rounding is ~6e-8 relative and the sums run over at most a few hundred terms per output with
+FP32 accumulation, so one transform lands near 1e-6; the measured error of 300 iterations is
+reported by the tests' assertion messages.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1210_4931_amd import workloads as W
+from tests.gpu_util import dev, rel, rel_alm, temperature_problem
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def mf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1210_4931_amd import mfwf
+    mfwf.load()
+    return mfwf
+
+
+@pytest.mark.parametrize("nside,lmax,nmaps", [(2, 8, 3), (8, 20, 5), (16, 64, 17), (32, 128, 33),
+                                             (64, 200, 40)])
+def test_f32_sht_pair_parity(mf, nside, lmax, nmaps):
+    rng = np.random.default_rng(nside + lmax)
+    alm = np.stack([W.white_alm(rng, lmax) for _ in range(nmaps)])
+    plan = mf.Plan(nside, lmax, max_batch=32, dtype="f32")
+    maps = plan.sht_inv(dev(alm, torch.complex128)).cpu().numpy()
+    back = plan.sht_fwd(dev(maps)).cpu().numpy()
+    for b in range(0, nmaps, max(1, nmaps // 4)):
+        ref = oracle.alm2map(nside, lmax, alm[b])
+        assert rel(maps[b], ref) < TOL, ("synthesis", b, rel(maps[b], ref))
+        refa = oracle.map2alm(nside, lmax, maps[b])
+        assert rel_alm(back[b], refa, lmax) < TOL, ("analysis", b, rel_alm(back[b], refa, lmax))
+
+
+def _setup(mf, nside, lmax, max_batch, seed=0):
+    wl, d, M = temperature_problem(nside, lmax, seed)
+    plan = mf.Plan(nside, lmax, max_batch=max_batch, dtype="f32")
+    plan.set_covariances(wl.cl, dev(1.0 / wl.noise_var), dev(wl.mask, torch.uint8))
+    return plan, wl, d, M
+
+
+def test_f32_wf_and_cr_batch_parity_300_iterations(mf):
+    """The batched workload at a small size: 8 Wiener-filter data sets and 8 fluctuation
+    sources in one batch, 300 iterations, each against the oracle iterate."""
+    nside, lmax = 32, 64
+    plan, wl, d, M = _setup(mf, nside, lmax, max_batch=16)
+    rng = np.random.default_rng(4)
+    ds = np.stack([d + rng.standard_normal(d.size) * np.sqrt(wl.noise_var) for _ in range(8)])
+    draws = [W.fluctuation_draws(100 + k, nside, lmax) for k in range(8)]
+    rho_cr = plan.fluctuation_rhs(dev(np.stack([g for g, _ in draws])),
+                                  dev(np.stack([h for _, h in draws]), torch.complex128))
+    rho = torch.cat([dev(M[None] * ds), rho_cr], 0)
+    s_alm, s_map, info = plan.solve(rho, iters=300, source_is_rho=True)
+    s_alm, s_map, rho_np = s_alm.cpu().numpy(), s_map.cpu().numpy(), rho.cpu().numpy()
+    errs = []
+    for b in (0, 5, 8, 15):
+        if b >= 8:
+            g1, h = draws[b - 8]
+            ref_rho = oracle.fluct_rho(nside, lmax, wl.cl, M, g1, h)
+            assert rel(rho_np[b], ref_rho) < TOL
+        ref_alm, ref_map = oracle.solve(nside, lmax, wl.cl, M, rho_np[b], niter=300)
+        errs.append((rel_alm(s_alm[b], ref_alm, lmax), rel(s_map[b], ref_map)))
+    assert max(max(e) for e in errs) < TOL, errs
+
+
+def test_f32_batch_invariance_and_graph(mf):
+    nside, lmax = 16, 40
+    plan, wl, d, M = _setup(mf, nside, lmax, max_batch=20)
+    rng = np.random.default_rng(2)
+    ds = np.stack([d + rng.standard_normal(d.size) for _ in range(20)])
+    a_all, m_all, _ = plan.solve(dev(ds), iters=15)
+    a_one, m_one, _ = plan.solve(dev(ds[7:8]), iters=15)
+    assert torch.equal(a_all[7], a_one[0]) and torch.equal(m_all[7], m_one[0])
+    a_eg, m_eg, _ = plan.solve(dev(ds), iters=15, use_graph=False)
+    assert torch.equal(a_all, a_eg) and torch.equal(m_all, m_eg)
+
+
+def test_f32_diagnostics(mf):
+    nside, lmax = 16, 40
+    plan, wl, d, M = _setup(mf, nside, lmax, max_batch=4)
+    _, _, info = plan.solve(dev(d[None]), iters=20)
+    _, _, dg = oracle.solve(nside, lmax, wl.cl, M, M * d, niter=20, diag=True)
+    assert info[0].chi2 == pytest.approx(dg[-1, 0], rel=1e-5)
+    assert info[0].snorm == pytest.approx(dg[-1, 3], rel=1e-5)
+
+
+def test_f32_full_size_sampled(mf):
+    """nside 256, lmax 512, 64 right-hand sides (the batched benchmark shape): two sampled
+    maps against the oracle after 2 iterations."""
+    nside, lmax, B = 256, 512, 64
+    wl = W.config2(0, nside, lmax)
+    M = wl.mask * (4.0 / wl.noise_var)
+    plan = mf.Plan(nside, lmax, max_batch=B, dtype="f32")
+    plan.set_covariances(wl.cl, dev(4.0 / wl.noise_var), dev(wl.mask, torch.uint8))
+    rng = np.random.default_rng(0)
+    sig = plan.sht_inv(dev(wl.signal_alm[None], torch.complex128))
+    noise = torch.as_tensor(rng.standard_normal((B, wl.npix)) * np.sqrt(wl.noise_var / 4.0)).cuda()
+    d = sig + noise
+    s_alm, _, _ = plan.solve(d, iters=2)
+    d_np, s_np = d.cpu().numpy(), s_alm.cpu().numpy()
+    for b in (0, B - 1):
+        ref, _ = oracle.solve(nside, lmax, wl.cl, M, M * d_np[b], niter=2)
+        assert rel_alm(s_np[b], ref, lmax) < TOL
