@@ -2,17 +2,20 @@
 
 Workload (the nside 512 temperature problem): HEALPix nside 512, lmax 1024,
 C_l = 6000/(l(l+1)) exp(-(l/800)^2), noise variance 30^2/hits with hits = 1 + 19 cos^2 theta
-(5 % seeded jitter), |z| < 0.15 band plus 100 discs of 3 deg masked.  One step = one Wiener
-filter solve of 300 messenger iterations at lambda = 1 in FP64 (each iteration: pixel
-update, forward SHT, harmonic update, inverse SHT), one map, inputs resident in HBM.
+(5 % seeded jitter), |z| < 0.15 band plus 100 discs of 3 deg masked.  One solve = 300
+messenger iterations at lambda = 1 (each: pixel update, forward SHT, harmonic update, inverse
+SHT) from s = 0; inputs are resident in HBM before timing.
 
-Prints one JSON line.  Besides solves/s it reports the SHT-pair FLOP/s, per-solve latency
-percentiles, the roofline position of the dominant kernel (timed with HIP events on the
-plan's stream) and the CPU oracle timed on a bounded sample on the host cores.
+Headline form: the batched FP32 form -- `--batch` right-hand sides (one signal, independent
+seeded noise draws) solved together, Legendre contractions on the matrix cores, FP64 maps and
+FFTs; its accuracy against the FP64 oracle (1e-5 relative) is checked by the GPU tests.  One
+step = one batched solve, value = solved maps per second.  Reported beside it: the plain FP64
+single-solve path (1 map, every step FP64) with its latency, the SHT-pair FLOP/s of both
+forms, the roofline position of each form's dominant kernel (HIP events on the plan's stream)
+and the CPU oracle on a bounded sample of the same solve.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -23,7 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "WF solves/s & SHT-pair FLOP/s at nside=512; p50/p99 latency at 1e-5 rel err"
-PEAK_FP64_VALU = 256 * 4 * 16 * 2 * 2.4e9   # CUs x SIMDs x lanes x (FMA = 2 flop) x clock
+PEAK_FP64_VALU = 256 * 4 * 16 * 2 * 2.4e9     # 78.6 TFLOP/s: CUs x SIMDs x lanes x FMA x clock
+PEAK_FP32_MFMA = 157.3e12                      # dense FP32 matrix-core peak
 KERNELS = ["pixel_update", "fft_fwd", "leg_analysis", "harmonic", "leg_synth", "fft_inv"]
 
 
@@ -37,18 +41,36 @@ def cpu_baseline(nside, lmax, iters_sample, wl, d_host, M):
     per_iter = dt / iters_sample
     return {"value": 1.0 / (per_iter * 300.0), "unit": "solves/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": "%d of the 300 messenger iterations of the nside 512 / lmax 1024 solve "
-                      "(%.1f s, FFT phi step), extrapolated to one solve" % (iters_sample, dt)}
+            "sample": "%d of the 300 messenger iterations of one nside %d / lmax %d solve "
+                      "(%.1f s, FFT phi step), extrapolated to one solve" % (iters_sample, nside,
+                                                                           lmax, dt)}
+
+
+def timed_solves(plan, d, K, steps, warmup, use_graph):
+    import torch
+    for _ in range(warmup):
+        plan.solve(d, iters=K, use_graph=use_graph, want_map=False)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        plan.solve(d, iters=K, use_graph=use_graph, want_map=False)  # synchronises its stream
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, lat
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--iters", type=int, default=300, help="messenger iterations per solve")
     ap.add_argument("--nside", type=int, default=512)
     ap.add_argument("--lmax", type=int, default=1024)
+    ap.add_argument("--batch", type=int, default=64, help="maps per batched FP32 solve")
+    ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-graph", action="store_true")
@@ -62,72 +84,83 @@ def main():
     from paper_1210_4931_amd import mfwf
     from paper_1210_4931_amd import workloads as W
 
-    nside, lmax, K = args.nside, args.lmax, args.iters
+    nside, lmax, K, B = args.nside, args.lmax, args.iters, args.batch
+    use_graph = not args.no_graph
     wl = W.config2(0, nside, lmax)
     dev = torch.device("cuda:0")
-    plan = mfwf.Plan(nside, lmax, max_batch=1)
     t = lambda x, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(x)).to(dev, dt)  # noqa
-    plan.set_covariances(wl.cl, t(1.0 / wl.noise_var), t(wl.mask, torch.uint8))
-    # d = Y(signal alm) + noise, built on the device with the library's own synthesis
-    sig = plan.sht_inv(t(wl.signal_alm[None], torch.complex128))
-    d = sig + t(np.sqrt(wl.noise_var) * wl.noise_white)[None]
-    torch.cuda.synchronize()
+    ninv, mask = t(1.0 / wl.noise_var), t(wl.mask, torch.uint8)
 
-    use_graph = not args.no_graph
-    for _ in range(args.warmup):
-        plan.solve(d, iters=K, use_graph=use_graph, want_map=False)
-    torch.cuda.synchronize()
-    lat = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        plan.solve(d, iters=K, use_graph=use_graph, want_map=False)  # synchronises its stream
-        lat.append(time.perf_counter() - ts)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = 1e3 * elapsed / args.steps
+    # ---- plain FP64 single-solve path --------------------------------------------------
+    p64 = mfwf.Plan(nside, lmax, max_batch=1, dtype="f64")
+    p64.set_covariances(wl.cl, ninv, mask)
+    sig = p64.sht_inv(t(wl.signal_alm[None], torch.complex128))  # signal map Y a
+    sigma = t(np.sqrt(wl.noise_var))
+    d1 = sig + sigma[None] * t(wl.noise_white)[None]
+    el64, lat64 = timed_solves(p64, d1, K, args.fp64_steps, 1, use_graph)
+    kt64 = dict(zip(KERNELS, p64.time_kernels(1, 20)))
+    work, full, npair, fftmax = p64.work()
+    leg_flops = 7.0 * work          # per map and direction: 3 recurrence + 4 complex-by-real FMA
+    dom64 = max(("leg_analysis", "leg_synth"), key=lambda k: kt64[k])
+    pair64 = kt64["fft_fwd"] + kt64["leg_analysis"] + kt64["leg_synth"] + kt64["fft_inv"]
+    fp64 = {"solves_per_s": args.fp64_steps / el64, "ms_per_solve": 1e3 * el64 / args.fp64_steps,
+            "latency_ms": {"p50": 1e3 * float(np.percentile(lat64, 50)),
+                           "p99": 1e3 * float(np.percentile(lat64, 99))},
+            "iteration_ms": 1e3 * el64 / args.fp64_steps / K,
+            "sht_pair_tflops": 2 * leg_flops / (pair64 * 1e-3) / 1e12,
+            "kernel_ms": kt64,
+            "roofline": {"bound": "alu", "kernel": dom64,
+                         "achieved": leg_flops / (kt64[dom64] * 1e-3) / 1e12,
+                         "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
+                         "frac": leg_flops / (kt64[dom64] * 1e-3) / PEAK_FP64_VALU}}
+    del p64
 
-    # per-kernel mean durations with HIP events on the plan's stream
-    kt = plan.time_kernels(nmaps=1, reps=20)
-    work, full, npair, fftmax = plan.work()
-    leg_flops = 7.0 * work        # per direction: 3 (FP64 recurrence) + 4 (complex x real FMA)
-    sht_pair_flops = 2.0 * leg_flops
-    ktimes = dict(zip(KERNELS, kt))
-    dom = max(("leg_analysis", "leg_synth"), key=lambda k: ktimes[k])
-    achieved = leg_flops / (ktimes[dom] * 1e-3)
-    iter_ms = ms_per_step / K
-    pair_ms = ktimes["fft_fwd"] + ktimes["leg_analysis"] + ktimes["leg_synth"] + ktimes["fft_inv"]
+    # ---- batched FP32 form (headline) --------------------------------------------------
+    p32 = mfwf.Plan(nside, lmax, max_batch=B, dtype="f32")
+    p32.set_covariances(wl.cl, ninv, mask)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1)
+    dB = sig + sigma[None] * torch.randn((B, wl.npix), generator=gen, device=dev,
+                                         dtype=torch.float64)
+    torch.cuda.synchronize()
+    el32, lat32 = timed_solves(p32, dB, K, args.steps, args.warmup, use_graph)
+    kt32 = dict(zip(KERNELS, p32.time_kernels(B, 5)))
+    gemm_flops = 2.0 * work * 2 * B   # one FMA per (l, m, ring pair) and column, 2 columns a map
+    dom32 = max(("leg_analysis", "leg_synth"), key=lambda k: kt32[k])
+    pair32 = kt32["fft_fwd"] + kt32["leg_analysis"] + kt32["leg_synth"] + kt32["fft_inv"]
+    achieved = gemm_flops / (kt32[dom32] * 1e-3)
 
     out = {
         "metric": METRIC,
-        "value": args.steps / elapsed,
+        "value": B * args.steps / el32,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": 1e3 * el32 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "temperature Wiener filter, HEALPix nside %d, lmax %d, %d "
-                               "messenger iterations at lambda=1, 1 map, FP64" % (nside, lmax, K),
-                   "nside": nside, "lmax": lmax, "iterations": K, "batch": 1,
-                   "graph": use_graph},
-        "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
-                       "p99": 1e3 * float(np.percentile(lat, 99))},
-        "iteration_ms": iter_ms,
-        "sht_pair_tflops": sht_pair_flops / (pair_ms * 1e-3) / 1e12,
-        "kernel_ms": ktimes,
+                               "messenger iterations at lambda=1, %d maps per batched solve, "
+                               "FP32 matrix-core Legendre steps, FP64 maps/FFTs" % (nside, lmax, K, B),
+                   "nside": nside, "lmax": lmax, "iterations": K, "batch": B, "graph": use_graph},
+        "latency_ms": {"p50": 1e3 * float(np.percentile(lat32, 50)),
+                       "p99": 1e3 * float(np.percentile(lat32, 99))},
+        "iteration_ms": 1e3 * el32 / args.steps / K,
+        "sht_pair_tflops": 2 * gemm_flops / (pair32 * 1e-3) / 1e12,
+        "kernel_ms": kt32,
         "legendre_triples": {"evaluated": work, "full_triangle": full},
-        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12,
-                     "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_VALU, "traffic": None},
+        "roofline": {"bound": "mfma", "kernel": "gemm_" + dom32.split("_")[1],
+                     "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": None},
+        "fp64_single": fp64,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(nside, lmax, args.cpu_iters, wl,
-                                           d.cpu().numpy()[0], wl.mask / wl.noise_var)
+        out["cpu_baseline"] = cpu_baseline(nside, lmax, args.cpu_iters, wl, d1.cpu().numpy()[0],
+                                           wl.mask / wl.noise_var)
     print(json.dumps(out), flush=True)
 
 

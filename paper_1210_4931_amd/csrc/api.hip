@@ -220,7 +220,7 @@ static void build_seeds(int lmax, int npair, const std::vector<RingGeom> &geo,
 
 static void free_plan(Plan &p) {
     void *ptrs[] = {p.d_z,    p.d_A,    p.d_c,     p.d_lstart, p.d_seed,  p.d_pfft, p.d_plist,
-                    p.d_tw,   p.d_chirp, p.d_bhat, p.d_mofs,   p.d_cl,    p.d_M,
+                    p.d_tw,   p.d_twlo, p.d_twhi, p.d_chirp, p.d_bhat, p.d_mofs,   p.d_cl,    p.d_M,
                     p.d_rho,  p.d_t,    p.d_smap,  p.d_phase,  p.d_apart, p.d_salm,
                     p.d_salm_prev, p.d_sp, p.d_red, p.d_diag, p.d_lam, p.d_loff, p.d_Lp,
                     p.d_minls32, p.d_minls64, p.d_ana_items, p.d_lofi, p.d_ph32, p.d_a32,
@@ -486,6 +486,17 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
         const double a = -2.0 * M_PI * (double)k / fftmax;
         tw[k] = make_double2(std::cos(a), std::sin(a));
     }
+    // two-level twiddle table: W^t = hi[t / 64] lo[t % 64]
+    p.fft_ntwhi = std::max(1, fftmax / 64);
+    std::vector<double2> twlo(64), twhi(p.fft_ntwhi);
+    for (int t = 0; t < 64; t++) {
+        const double a = -2.0 * M_PI * (double)t / fftmax;
+        twlo[t] = make_double2(std::cos(a), std::sin(a));
+    }
+    for (int h = 0; h < p.fft_ntwhi; h++) {
+        const double a = -2.0 * M_PI * (double)(64L * h) / fftmax;
+        twhi[h] = make_double2(std::cos(a), std::sin(a));
+    }
     // FFT classes: pairs whose transform fits half of the largest length, and the rest
     std::vector<int> plist;
     p.fft_class_len[0] = 1;
@@ -504,7 +515,8 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     if (fftmax > fft_max_length())
         return fail(MFWF_EINVAL, "ring FFT length " + std::to_string(fftmax) + " above the supported " +
                                      std::to_string(fft_max_length()));
-    const size_t lds = sizeof(double2) * ((size_t)fftmax + 1024);  // FFT area + alias partials
+    // FFT area + alias partials + twiddle tables of the largest class
+    const size_t lds = sizeof(double2) * ((size_t)fftmax + 1024 + 64 + p.fft_ntwhi);
     {
         int dev = 0, maxlds = 0;
         MFWF_HIP(hipGetDevice(&dev));
@@ -530,6 +542,8 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     MFWF_TRY(dalloc(&p.d_pfft, pf.size(), "fft plan"));
     MFWF_TRY(dalloc(&p.d_plist, plist.size(), "fft pair list"));
     MFWF_TRY(dalloc(&p.d_tw, tw.size(), "twiddles"));
+    MFWF_TRY(dalloc(&p.d_twlo, twlo.size(), "twiddles lo"));
+    MFWF_TRY(dalloc(&p.d_twhi, twhi.size(), "twiddles hi"));
     MFWF_TRY(dalloc(&p.d_chirp, std::max<size_t>(1, chirp.size()), "chirp"));
     MFWF_TRY(dalloc(&p.d_bhat, std::max<size_t>(1, bhat.size()), "chirp kernel"));
     MFWF_TRY(dalloc(&p.d_cl, lmax + 1, "cl"));
@@ -555,6 +569,8 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     MFWF_TRY(upload(p.d_pfft, pf, p.stream));
     MFWF_TRY(upload(p.d_plist, plist, p.stream));
     MFWF_TRY(upload(p.d_tw, tw, p.stream));
+    MFWF_TRY(upload(p.d_twlo, twlo, p.stream));
+    MFWF_TRY(upload(p.d_twhi, twhi, p.stream));
     if (!chirp.empty()) MFWF_TRY(upload(p.d_chirp, chirp, p.stream));
     if (!bhat.empty()) MFWF_TRY(upload(p.d_bhat, bhat, p.stream));
     // defined contents everywhere (workspaces are read by autotuning and mfwf_time_kernels)

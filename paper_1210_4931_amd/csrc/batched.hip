@@ -66,18 +66,19 @@ k_lam_table(const double *__restrict__ Atab, const double *__restrict__ ctab,
 // Batched ring FFTs: workgroup = (ring pair, group of maps); FP32 ring-Fourier
 // [ring][m][C2], column 2b (re) and 2b + 1 (im) of map b.
 // ---------------------------------------------------------------------------------------
-template <int TPB>
+template <int TPB, int EPT>
 __global__ void __launch_bounds__(TPB)
 k_fft_fwd_b(const double *__restrict__ maps, float *__restrict__ ph32,
             const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
-            const double2 *__restrict__ tw, int fftmax, const double2 *__restrict__ chirp,
-            const double2 *__restrict__ bhat, long npix, int nring, int nm, int lmax, int nb,
-            int C2) {
+            const double2 *__restrict__ twlo, const double2 *__restrict__ twhi, int ntwhi,
+            int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
+            long npix, int nring, int nm, int lmax, int fftlen_class, int nb, int C2) {
     extern __shared__ double2 buf[];
     const int p = plist[blockIdx.x];
     const PairFFT pf = pfft[p];
     const int n = pf.nphi;
     const bool equator = (pf.startS == pf.startN);
+    const Twiddles tw = load_twiddles(buf, fftlen_class, TPB, twlo, twhi, ntwhi);
     float *outN = ph32 + (long)p * nm * C2;
     float *outS = ph32 + (long)(nring - 1 - p) * nm * C2;
     const int b0 = blockIdx.y * kMapsPerFFTBlock;
@@ -89,14 +90,14 @@ k_fft_fwd_b(const double *__restrict__ maps, float *__restrict__ ph32,
         for (int j = threadIdx.x; j < n; j += TPB)
             buf[j] = make_double2(tN[j], equator ? 0.0 : tS[j]);
         __syncthreads();
-        ring_dft<TPB>(buf, pf, tw, fftmax, chirp, bhat);
+        ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
         for (int m = threadIdx.x; m <= lmax; m += TPB) {
             const int q = m / n, k = m - q * n;
             const int kr = (k == 0) ? 0 : n - k;
             const double2 X = dft_bin(buf, pf, chirp, k);
             const double2 Y = cconj(dft_bin(buf, pf, chirp, kr));
             double2 ph = make_double2(1.0, 0.0);
-            if (pf.half_shift) ph = cscale(cconj(half_bin_phase(k, n)), (q & 1) ? -1.0 : 1.0);
+            if (pf.half_shift) ph = cscale(cconj(half_bin_phase(k, n, tw, fftmax)), (q & 1) ? -1.0 : 1.0);
             const double2 gN = cmul(make_double2(0.5 * (X.x + Y.x), 0.5 * (X.y + Y.y)), ph);
             *reinterpret_cast<float2 *>(outN + (long)m * C2 + 2 * b) = make_float2((float)gN.x, (float)gN.y);
             if (!equator) {
@@ -108,20 +109,21 @@ k_fft_fwd_b(const double *__restrict__ maps, float *__restrict__ ph32,
     }
 }
 
-template <int TPB>
+template <int TPB, int EPT>
 __global__ void __launch_bounds__(TPB)
 k_fft_inv_b(const float *__restrict__ ph32, double *__restrict__ maps,
             const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
-            const double2 *__restrict__ tw, int fftmax, const double2 *__restrict__ chirp,
-            const double2 *__restrict__ bhat, long npix, int nring, int nm, int lmax, int nb,
-            int C2) {
+            const double2 *__restrict__ twlo, const double2 *__restrict__ twhi, int ntwhi,
+            int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
+            long npix, int nring, int nm, int lmax, int fftlen_class, int nb, int C2) {
     extern __shared__ double2 buf[];
     const int p = plist[blockIdx.x];
     const PairFFT pf = pfft[p];
     const int n = pf.nphi;
-    double2 *partN = buf + pf.fftlen;
+    double2 *partN = buf + fftlen_class;
     double2 *partS = partN + TPB;
     const bool equator = (pf.startS == pf.startN);
+    const Twiddles tw = load_twiddles(buf, fftlen_class, TPB, twlo, twhi, ntwhi);
     const float *FN = ph32 + (long)p * nm * C2;
     const float *FS = ph32 + (long)(nring - 1 - p) * nm * C2;
     int T = TPB / n;
@@ -166,7 +168,7 @@ k_fft_inv_b(const float *__restrict__ ph32, double *__restrict__ maps,
             }
             if (t == 0 && k < n) {
                 if (pf.half_shift) {
-                    const double2 ph = half_bin_phase(k, n);
+                    const double2 ph = half_bin_phase(k, n, tw, fftmax);
                     sN = cmul(sN, ph);
                     sS = cmul(sS, ph);
                 }
@@ -174,7 +176,7 @@ k_fft_inv_b(const float *__restrict__ ph32, double *__restrict__ maps,
             }
         }
         __syncthreads();
-        ring_dft<TPB>(buf, pf, tw, fftmax, chirp, bhat);
+        ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
         double *sNmap = maps + (long)b * npix + pf.startN;
         double *sSmap = maps + (long)b * npix + pf.startS;
         for (int j = threadIdx.x; j < n; j += TPB) {
@@ -407,24 +409,25 @@ int launch_lam_table(const Plan &p) {
     return MFWF_OK;
 }
 
-static int fft_class_tpb(const Plan &p, int c) { return p.fft_class_len[c] > kMaxEPT * 256 ? 512 : 256; }
-static size_t fft_class_lds(const Plan &p, int c) {
-    return sizeof(double2) * ((size_t)p.fft_class_len[c] + 2 * fft_class_tpb(p, c));
-}
+#define MFWF_FFTB_ARGS(c)                                                                       \
+    p.d_pfft, p.d_plist + p.fft_class_off[c], p.d_twlo, p.d_twhi, p.fft_ntwhi, p.fftmax,        \
+        p.d_chirp, p.d_bhat, p.npix, p.nring, p.nm, p.lmax, p.fft_class_len[c], nb, p.C2
 
 int launch_fft_fwd_b(const Plan &p, const double *maps, int nb) {
     const int ng = (nb + kMapsPerFFTBlock - 1) / kMapsPerFFTBlock;
     for (int c = 1; c >= 0; c--) {
         const int cnt = p.fft_class_count[c];
         if (cnt == 0) continue;
-        if (fft_class_tpb(p, c) == 512)
-            hipLaunchKernelGGL(k_fft_fwd_b<512>, dim3(cnt, ng), dim3(512), fft_class_lds(p, c), p.stream,
-                               maps, p.d_ph32, p.d_pfft, p.d_plist + p.fft_class_off[c], p.d_tw,
-                               p.fftmax, p.d_chirp, p.d_bhat, p.npix, p.nring, p.nm, p.lmax, nb, p.C2);
+        int ept;
+        const int tpb = fft_class_shape(p, c, ept);
+        const dim3 grid(cnt, ng);
+        const size_t lds = fft_class_lds(p, c);
+        if (ept == 8)
+            hipLaunchKernelGGL((k_fft_fwd_b<256, 8>), grid, dim3(256), lds, p.stream, maps, p.d_ph32, MFWF_FFTB_ARGS(c));
+        else if (tpb == 256)
+            hipLaunchKernelGGL((k_fft_fwd_b<256, 16>), grid, dim3(256), lds, p.stream, maps, p.d_ph32, MFWF_FFTB_ARGS(c));
         else
-            hipLaunchKernelGGL(k_fft_fwd_b<256>, dim3(cnt, ng), dim3(256), fft_class_lds(p, c), p.stream,
-                               maps, p.d_ph32, p.d_pfft, p.d_plist + p.fft_class_off[c], p.d_tw,
-                               p.fftmax, p.d_chirp, p.d_bhat, p.npix, p.nring, p.nm, p.lmax, nb, p.C2);
+            hipLaunchKernelGGL((k_fft_fwd_b<512, 16>), grid, dim3(512), lds, p.stream, maps, p.d_ph32, MFWF_FFTB_ARGS(c));
         MFWF_HIP(hipGetLastError());
     }
     return MFWF_OK;
@@ -435,14 +438,16 @@ int launch_fft_inv_b(const Plan &p, double *maps, int nb) {
     for (int c = 1; c >= 0; c--) {
         const int cnt = p.fft_class_count[c];
         if (cnt == 0) continue;
-        if (fft_class_tpb(p, c) == 512)
-            hipLaunchKernelGGL(k_fft_inv_b<512>, dim3(cnt, ng), dim3(512), fft_class_lds(p, c), p.stream,
-                               p.d_ph32, maps, p.d_pfft, p.d_plist + p.fft_class_off[c], p.d_tw,
-                               p.fftmax, p.d_chirp, p.d_bhat, p.npix, p.nring, p.nm, p.lmax, nb, p.C2);
+        int ept;
+        const int tpb = fft_class_shape(p, c, ept);
+        const dim3 grid(cnt, ng);
+        const size_t lds = fft_class_lds(p, c);
+        if (ept == 8)
+            hipLaunchKernelGGL((k_fft_inv_b<256, 8>), grid, dim3(256), lds, p.stream, p.d_ph32, maps, MFWF_FFTB_ARGS(c));
+        else if (tpb == 256)
+            hipLaunchKernelGGL((k_fft_inv_b<256, 16>), grid, dim3(256), lds, p.stream, p.d_ph32, maps, MFWF_FFTB_ARGS(c));
         else
-            hipLaunchKernelGGL(k_fft_inv_b<256>, dim3(cnt, ng), dim3(256), fft_class_lds(p, c), p.stream,
-                               p.d_ph32, maps, p.d_pfft, p.d_plist + p.fft_class_off[c], p.d_tw,
-                               p.fftmax, p.d_chirp, p.d_bhat, p.npix, p.nring, p.nm, p.lmax, nb, p.C2);
+            hipLaunchKernelGGL((k_fft_inv_b<512, 16>), grid, dim3(512), lds, p.stream, p.d_ph32, maps, MFWF_FFTB_ARGS(c));
         MFWF_HIP(hipGetLastError());
     }
     return MFWF_OK;
@@ -490,8 +495,9 @@ int launch_cols_to_alm(const Plan &p, const float *x32, double2 *alm, int nb, do
 }
 
 int batched_set_lds_limit(size_t bytes) {
-    const void *fns[] = {(const void *)k_fft_fwd_b<256>, (const void *)k_fft_fwd_b<512>,
-                         (const void *)k_fft_inv_b<256>, (const void *)k_fft_inv_b<512>};
+    const void *fns[] = {(const void *)k_fft_fwd_b<256, 8>, (const void *)k_fft_fwd_b<256, 16>,
+                         (const void *)k_fft_fwd_b<512, 16>, (const void *)k_fft_inv_b<256, 8>,
+                         (const void *)k_fft_inv_b<256, 16>, (const void *)k_fft_inv_b<512, 16>};
     for (const void *f : fns)
         MFWF_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     return MFWF_OK;

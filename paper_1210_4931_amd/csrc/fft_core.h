@@ -1,14 +1,12 @@
 // Device routines of the ring phi transforms, shared by the FP64 per-map kernels
 // (ringfft.hip) and the batched kernels (batched.hip): complex helpers, small in-register
-// DFTs, in-place Stockham passes in LDS, and the Bluestein wrapper for non-power-of-two
-// ring lengths.
+// DFTs, in-place Stockham passes in LDS, twiddles from a two-level table in LDS, and the
+// Bluestein wrapper for non-power-of-two ring lengths.
 #pragma once
 
 #include "mfwf_internal.h"
 
 namespace mfwf {
-
-static constexpr int kMaxEPT = 16;  // transform elements per thread
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -24,6 +22,26 @@ __device__ __forceinline__ double2 cscale(double2 a, double s) {
     return make_double2(a.x * s, a.y * s);
 }
 __device__ __forceinline__ double2 mul_minus_i(double2 a) { return make_double2(a.y, -a.x); }
+
+// W_N^t = exp(-2 pi i t / N) for the plan's largest transform length N, as
+// hi[t / 64] * lo[t % 64] from two short tables held in LDS.
+struct Twiddles {
+    const double2 *lo, *hi;
+    __device__ __forceinline__ double2 operator()(int t) const { return cmul(hi[t >> 6], lo[t & 63]); }
+};
+
+// Dynamic LDS of one ring-transform workgroup: [fftlen][2 TPB partials][64 lo][N/64 hi].
+__device__ __forceinline__ Twiddles load_twiddles(double2 *lds, int fftlen, int tpb,
+                                                  const double2 *__restrict__ glo,
+                                                  const double2 *__restrict__ ghi, int nhi) {
+    double2 *lo = lds + fftlen + 2 * tpb, *hi = lo + 64;
+    for (int j = threadIdx.x; j < 64 + nhi; j += blockDim.x) {
+        if (j < 64) lo[j] = glo[j];
+        else hi[j - 64] = ghi[j - 64];
+    }
+    __syncthreads();
+    return Twiddles{lo, hi};
+}
 
 // Forward R-point DFT in registers, natural order in and out (R = 2, 4, 8).
 template <int R>
@@ -57,10 +75,11 @@ __device__ __forceinline__ void small_dft(double2 (&v)[R]) {
 
 // One Stockham pass of radix R over buf[0..n): inputs j + r n/R, output (j/Ns) Ns R + j%Ns
 // + r Ns, twiddle exp(-2 pi i (j%Ns) r / (Ns R)).  All reads precede all writes.
-template <int TPB, int R>
-__device__ __forceinline__ void stockham_pass(double2 *buf, int n, int Ns,
-                                              const double2 *__restrict__ tw, int fftmax) {
-    constexpr int MAXB = kMaxEPT / R;
+// EPT: most transform elements one thread handles (n <= EPT * TPB).
+template <int TPB, int EPT, int R>
+__device__ __forceinline__ void stockham_pass(double2 *buf, int n, int Ns, const Twiddles &tw,
+                                              int fftmax) {
+    constexpr int MAXB = EPT / R;
     const int nbf = n / R;
     double2 v[MAXB][R];
 #pragma unroll
@@ -80,7 +99,7 @@ __device__ __forceinline__ void stockham_pass(double2 *buf, int n, int Ns,
             const int kk = j & (Ns - 1);
             if (Ns > 1) {
 #pragma unroll
-                for (int r = 1; r < R; r++) v[b][r] = cmul(v[b][r], tw[kk * r * ts]);
+                for (int r = 1; r < R; r++) v[b][r] = cmul(v[b][r], tw(kk * r * ts));
             }
             small_dft<R>(v[b]);
             const int base = (j - kk) * R + kk;
@@ -91,20 +110,20 @@ __device__ __forceinline__ void stockham_pass(double2 *buf, int n, int Ns,
     __syncthreads();
 }
 
-// Forward DFT of buf[0..n), n a power of two <= kMaxEPT * TPB, natural order in and out.
-template <int TPB>
-__device__ __forceinline__ void fft_stockham(double2 *buf, int n, const double2 *__restrict__ tw, int fftmax) {
+// Forward DFT of buf[0..n), n a power of two <= EPT * TPB, natural order in and out.
+template <int TPB, int EPT>
+__device__ __forceinline__ void fft_stockham(double2 *buf, int n, const Twiddles &tw, int fftmax) {
     int Ns = 1;
     while (Ns < n) {
         const int left = n / Ns;
         if (left >= 8) {
-            stockham_pass<TPB, 8>(buf, n, Ns, tw, fftmax);
+            stockham_pass<TPB, EPT, 8>(buf, n, Ns, tw, fftmax);
             Ns *= 8;
         } else if (left == 4) {
-            stockham_pass<TPB, 4>(buf, n, Ns, tw, fftmax);
+            stockham_pass<TPB, EPT, 4>(buf, n, Ns, tw, fftmax);
             Ns *= 4;
         } else {
-            stockham_pass<TPB, 2>(buf, n, Ns, tw, fftmax);
+            stockham_pass<TPB, EPT, 2>(buf, n, Ns, tw, fftmax);
             Ns *= 2;
         }
     }
@@ -112,24 +131,24 @@ __device__ __forceinline__ void fft_stockham(double2 *buf, int n, const double2 
 
 // Length-n forward DFT of buf[0..n) in place.  On return the transform value of bin k is
 // read with dft_bin(): buf[k] for power-of-two n, c_k conj(buf[k]) for Bluestein.
-template <int TPB>
-__device__ __forceinline__ void ring_dft(double2 *buf, const PairFFT &pf, const double2 *__restrict__ tw,
-                         int fftmax, const double2 *__restrict__ chirp,
-                         const double2 *__restrict__ bhat) {
+template <int TPB, int EPT>
+__device__ __forceinline__ void ring_dft(double2 *buf, const PairFFT &pf, const Twiddles &tw,
+                                         int fftmax, const double2 *__restrict__ chirp,
+                                         const double2 *__restrict__ bhat) {
     const int n = pf.nphi, M = pf.fftlen;
     if (!pf.bluestein) {
-        fft_stockham<TPB>(buf, n, tw, fftmax);
+        fft_stockham<TPB, EPT>(buf, n, tw, fftmax);
         return;
     }
     const double2 *c = chirp + pf.chirp_off;
     for (int j = threadIdx.x; j < M; j += TPB)
         buf[j] = (j < n) ? cmul(buf[j], c[j]) : make_double2(0.0, 0.0);
     __syncthreads();
-    fft_stockham<TPB>(buf, M, tw, fftmax);
+    fft_stockham<TPB, EPT>(buf, M, tw, fftmax);
     const double2 *bh = bhat + pf.bhat_off;  // transformed conj chirp, already divided by M
     for (int j = threadIdx.x; j < M; j += TPB) buf[j] = cconj(cmul(buf[j], bh[j]));
     __syncthreads();
-    fft_stockham<TPB>(buf, M, tw, fftmax);
+    fft_stockham<TPB, EPT>(buf, M, tw, fftmax);
 }
 
 __device__ __forceinline__ double2 dft_bin(const double2 *buf, const PairFFT &pf,
@@ -138,8 +157,9 @@ __device__ __forceinline__ double2 dft_bin(const double2 *buf, const PairFFT &pf
     return cmul(chirp[pf.chirp_off + k], cconj(buf[k]));
 }
 
-// e^{i pi k / n}
-__device__ __forceinline__ double2 half_bin_phase(int k, int n) {
+// e^{i pi k / n}: from the twiddle table when 2n divides the largest length, else sincospi
+__device__ __forceinline__ double2 half_bin_phase(int k, int n, const Twiddles &tw, int fftmax) {
+    if (fftmax % (2 * n) == 0) return cconj(tw(k * (fftmax / (2 * n))));
     double s, c;
     sincospi((double)k / (double)n, &s, &c);
     return make_double2(c, s);

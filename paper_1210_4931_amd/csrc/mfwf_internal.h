@@ -64,6 +64,9 @@ struct Plan {
     double2 *d_seed = nullptr;   // [nm][npair] (mu_{l_s - 1}, mu_{l_s})
     PairFFT *d_pfft = nullptr;   // [npair]
     double2 *d_tw = nullptr;     // [fftmax] exp(-2 pi i k / fftmax)
+    double2 *d_twlo = nullptr;   // [64] exp(-2 pi i t / fftmax)
+    double2 *d_twhi = nullptr;   // [fft_ntwhi] exp(-2 pi i 64 h / fftmax)
+    int fft_ntwhi = 1;
     double2 *d_chirp = nullptr;  // Bluestein chirps exp(-i pi k^2 / n), per distinct n
     double2 *d_bhat = nullptr;   // Bluestein kernels FFT_M(conj chirp), bit-reversed order
     int fftmax;                  // largest power-of-two transform length
@@ -129,6 +132,8 @@ int launch_fluct_combine(const double *g1, const double *M, const double *ysh, d
 // ringfft.hip
 int launch_fft_fwd(const Plan &p, const double *maps, double2 *phase, int nb);
 int launch_fft_inv(const Plan &p, const double2 *phase, double *maps, int nb);
+int fft_class_shape(const Plan &p, int c, int &ept);  // threads per workgroup of class c
+size_t fft_class_lds(const Plan &p, int c);           // dynamic LDS bytes of class c
 
 // legendre.hip (alm_scaled: c_lm-scaled coefficients; apart: sums of mu_lm X)
 int launch_leg_synth(const Plan &p, const double2 *alm_scaled, double2 *phase, int nb);

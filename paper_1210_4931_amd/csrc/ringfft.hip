@@ -10,7 +10,7 @@
 // is in natural order.  Other n (polar rings n = 4i): Bluestein's chirp-z algorithm turns
 // the length-n DFT into a circular convolution of power-of-two length M >= 2n - 1 (forward
 // transform, pointwise product with the precomputed transformed chirp, and a second forward
-// transform of the conjugate).  Twiddles come from one table of the largest length.
+// transform of the conjugate).  Twiddles come from a two-level table held in LDS.
 //
 // Forward (analysis side):  G_r(m) = sum_j t_{r,j} e^{-i m phi_{r,j}}, m = 0..lmax, read
 // from DFT bin k = m mod n.  Inverse (synthesis): F_r(m), m = -lmax..lmax with
@@ -20,29 +20,31 @@
 //
 // Ring-Fourier layout: [map][ring][m] complex, so both kernels stream contiguous rows.
 // Pairs are launched in two classes by transform length: most pairs need at most half the
-// largest length (less LDS, more workgroups per CU); the long Bluestein transforms of the
-// largest polar rings get twice the threads.
+// largest length (less LDS and fewer registers per thread, more workgroups per CU); the long
+// Bluestein transforms of the largest polar rings form the second class.
 #include "fft_core.h"
 
 namespace mfwf {
 
-template <int TPB>
+template <int TPB, int EPT>
 __global__ void __launch_bounds__(TPB)
 k_fft_fwd(const double *__restrict__ maps, double2 *__restrict__ phase,
           const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
-          const double2 *__restrict__ tw, int fftmax, const double2 *__restrict__ chirp,
-          const double2 *__restrict__ bhat, long npix, int nring, int nm, int lmax) {
+          const double2 *__restrict__ twlo, const double2 *__restrict__ twhi, int ntwhi,
+          int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
+          long npix, int nring, int nm, int lmax, int fftlen_class) {
     extern __shared__ double2 buf[];
     const int p = plist[blockIdx.x], b = blockIdx.y;
     const PairFFT pf = pfft[p];
     const int n = pf.nphi;
     const bool equator = (pf.startS == pf.startN);
+    const Twiddles tw = load_twiddles(buf, fftlen_class, TPB, twlo, twhi, ntwhi);
     const double *tN = maps + (long)b * npix + pf.startN;
     const double *tS = maps + (long)b * npix + pf.startS;
     for (int j = threadIdx.x; j < n; j += TPB)
         buf[j] = make_double2(tN[j], equator ? 0.0 : tS[j]);
     __syncthreads();
-    ring_dft<TPB>(buf, pf, tw, fftmax, chirp, bhat);
+    ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
     double2 *outN = phase + ((long)b * nring + p) * nm;
     double2 *outS = phase + ((long)b * nring + (nring - 1 - p)) * nm;
     for (int m = threadIdx.x; m <= lmax; m += TPB) {
@@ -52,7 +54,7 @@ k_fft_fwd(const double *__restrict__ maps, double2 *__restrict__ phase,
         const double2 Y = cconj(dft_bin(buf, pf, chirp, kr));
         // e^{-i m phi0} = (-1)^q e^{-i pi k / n} with a half shift, 1 otherwise
         double2 ph = make_double2(1.0, 0.0);
-        if (pf.half_shift) ph = cscale(cconj(half_bin_phase(k, n)), (q & 1) ? -1.0 : 1.0);
+        if (pf.half_shift) ph = cscale(cconj(half_bin_phase(k, n, tw, fftmax)), (q & 1) ? -1.0 : 1.0);
         // X_N = (X_k + conj X_{-k}) / 2,  X_S = (X_k - conj X_{-k}) / (2i)
         const double2 gN = make_double2(0.5 * (X.x + Y.x), 0.5 * (X.y + Y.y));
         outN[m] = cmul(gN, ph);
@@ -63,19 +65,21 @@ k_fft_fwd(const double *__restrict__ maps, double2 *__restrict__ phase,
     }
 }
 
-template <int TPB>
+template <int TPB, int EPT>
 __global__ void __launch_bounds__(TPB)
 k_fft_inv(const double2 *__restrict__ phase, double *__restrict__ maps,
           const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
-          const double2 *__restrict__ tw, int fftmax, const double2 *__restrict__ chirp,
-          const double2 *__restrict__ bhat, long npix, int nring, int nm, int lmax) {
+          const double2 *__restrict__ twlo, const double2 *__restrict__ twhi, int ntwhi,
+          int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
+          long npix, int nring, int nm, int lmax, int fftlen_class) {
     extern __shared__ double2 buf[];
     const int p = plist[blockIdx.x], b = blockIdx.y;
     const PairFFT pf = pfft[p];
     const int n = pf.nphi;
-    double2 *partN = buf + pf.fftlen;  // [TPB] alias-sum partials after the FFT area
+    double2 *partN = buf + fftlen_class;  // [TPB] alias-sum partials after the FFT area
     double2 *partS = partN + TPB;
     const bool equator = (pf.startS == pf.startN);
+    const Twiddles tw = load_twiddles(buf, fftlen_class, TPB, twlo, twhi, ntwhi);
     const double2 *FN = phase + ((long)b * nring + p) * nm;
     const double2 *FS = phase + ((long)b * nring + (nring - 1 - p)) * nm;
 
@@ -118,7 +122,7 @@ k_fft_inv(const double2 *__restrict__ phase, double *__restrict__ maps,
         }
         if (t == 0 && k < n) {
             if (pf.half_shift) {
-                const double2 ph = half_bin_phase(k, n);
+                const double2 ph = half_bin_phase(k, n, tw, fftmax);
                 sN = cmul(sN, ph);
                 sS = cmul(sS, ph);
             }
@@ -127,7 +131,7 @@ k_fft_inv(const double2 *__restrict__ phase, double *__restrict__ maps,
         }
     }
     __syncthreads();
-    ring_dft<TPB>(buf, pf, tw, fftmax, chirp, bhat);
+    ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
     double *sNmap = maps + (long)b * npix + pf.startN;
     double *sSmap = maps + (long)b * npix + pf.startS;
     for (int j = threadIdx.x; j < n; j += TPB) {
@@ -137,34 +141,42 @@ k_fft_inv(const double2 *__restrict__ phase, double *__restrict__ maps,
     }
 }
 
-// threads per workgroup of a class: enough for kMaxEPT elements per thread
-static int class_tpb(const Plan &p, int c) { return p.fft_class_len[c] > kMaxEPT * 256 ? 512 : 256; }
-
-static size_t class_lds(const Plan &p, int c) {
-    return sizeof(double2) * ((size_t)p.fft_class_len[c] + 2 * class_tpb(p, c));
+// (threads per workgroup, elements per thread) of a class: 2048 -> (256, 8),
+// 4096 -> (256, 16), 8192 -> (512, 16)
+int fft_class_shape(const Plan &p, int c, int &ept) {
+    const int len = p.fft_class_len[c];
+    if (len <= 2048) {
+        ept = 8;
+        return 256;
+    }
+    ept = 16;
+    return len <= 4096 ? 256 : 512;
 }
 
-template <int TPB>
-static void fwd_launch(const Plan &p, int c, const double *maps, double2 *phase, int nb) {
-    hipLaunchKernelGGL(k_fft_fwd<TPB>, dim3(p.fft_class_count[c], nb), dim3(TPB), class_lds(p, c),
-                       p.stream, maps, phase, p.d_pfft, p.d_plist + p.fft_class_off[c], p.d_tw,
-                       p.fftmax, p.d_chirp, p.d_bhat, p.npix, p.nring, p.nm, p.lmax);
+size_t fft_class_lds(const Plan &p, int c) {
+    int ept;
+    const int tpb = fft_class_shape(p, c, ept);
+    return sizeof(double2) * ((size_t)p.fft_class_len[c] + 2 * tpb + 64 + p.fft_ntwhi);
 }
 
-template <int TPB>
-static void inv_launch(const Plan &p, int c, const double2 *phase, double *maps, int nb) {
-    hipLaunchKernelGGL(k_fft_inv<TPB>, dim3(p.fft_class_count[c], nb), dim3(TPB), class_lds(p, c),
-                       p.stream, phase, maps, p.d_pfft, p.d_plist + p.fft_class_off[c], p.d_tw,
-                       p.fftmax, p.d_chirp, p.d_bhat, p.npix, p.nring, p.nm, p.lmax);
-}
+#define MFWF_FFT_ARGS(c)                                                                        \
+    p.d_pfft, p.d_plist + p.fft_class_off[c], p.d_twlo, p.d_twhi, p.fft_ntwhi, p.fftmax,        \
+        p.d_chirp, p.d_bhat, p.npix, p.nring, p.nm, p.lmax, p.fft_class_len[c]
 
 int launch_fft_fwd(const Plan &p, const double *maps, double2 *phase, int nb) {
     for (int c = 1; c >= 0; c--) {  // long transforms first
-        if (p.fft_class_count[c] == 0) continue;
-        if (class_tpb(p, c) == 512)
-            fwd_launch<512>(p, c, maps, phase, nb);
+        const int cnt = p.fft_class_count[c];
+        if (cnt == 0) continue;
+        int ept;
+        const int tpb = fft_class_shape(p, c, ept);
+        const dim3 grid(cnt, nb);
+        const size_t lds = fft_class_lds(p, c);
+        if (ept == 8)
+            hipLaunchKernelGGL((k_fft_fwd<256, 8>), grid, dim3(256), lds, p.stream, maps, phase, MFWF_FFT_ARGS(c));
+        else if (tpb == 256)
+            hipLaunchKernelGGL((k_fft_fwd<256, 16>), grid, dim3(256), lds, p.stream, maps, phase, MFWF_FFT_ARGS(c));
         else
-            fwd_launch<256>(p, c, maps, phase, nb);
+            hipLaunchKernelGGL((k_fft_fwd<512, 16>), grid, dim3(512), lds, p.stream, maps, phase, MFWF_FFT_ARGS(c));
         MFWF_HIP(hipGetLastError());
     }
     return MFWF_OK;
@@ -172,22 +184,30 @@ int launch_fft_fwd(const Plan &p, const double *maps, double2 *phase, int nb) {
 
 int launch_fft_inv(const Plan &p, const double2 *phase, double *maps, int nb) {
     for (int c = 1; c >= 0; c--) {
-        if (p.fft_class_count[c] == 0) continue;
-        if (class_tpb(p, c) == 512)
-            inv_launch<512>(p, c, phase, maps, nb);
+        const int cnt = p.fft_class_count[c];
+        if (cnt == 0) continue;
+        int ept;
+        const int tpb = fft_class_shape(p, c, ept);
+        const dim3 grid(cnt, nb);
+        const size_t lds = fft_class_lds(p, c);
+        if (ept == 8)
+            hipLaunchKernelGGL((k_fft_inv<256, 8>), grid, dim3(256), lds, p.stream, phase, maps, MFWF_FFT_ARGS(c));
+        else if (tpb == 256)
+            hipLaunchKernelGGL((k_fft_inv<256, 16>), grid, dim3(256), lds, p.stream, phase, maps, MFWF_FFT_ARGS(c));
         else
-            inv_launch<256>(p, c, phase, maps, nb);
+            hipLaunchKernelGGL((k_fft_inv<512, 16>), grid, dim3(512), lds, p.stream, phase, maps, MFWF_FFT_ARGS(c));
         MFWF_HIP(hipGetLastError());
     }
     return MFWF_OK;
 }
 
-int fft_max_length() { return kMaxEPT * 512; }
+int fft_max_length() { return 16 * 512; }
 
 // Maximum dynamic LDS the FFT kernels may request (set once per process).
 int fft_set_lds_limit(size_t bytes) {
-    const void *fns[] = {(const void *)k_fft_fwd<256>, (const void *)k_fft_fwd<512>,
-                         (const void *)k_fft_inv<256>, (const void *)k_fft_inv<512>};
+    const void *fns[] = {(const void *)k_fft_fwd<256, 8>, (const void *)k_fft_fwd<256, 16>,
+                         (const void *)k_fft_fwd<512, 16>, (const void *)k_fft_inv<256, 8>,
+                         (const void *)k_fft_inv<256, 16>, (const void *)k_fft_inv<512, 16>};
     for (const void *f : fns)
         MFWF_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     return MFWF_OK;
