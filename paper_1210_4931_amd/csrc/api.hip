@@ -223,7 +223,7 @@ static void free_plan(Plan &p) {
                     p.d_tw,   p.d_twlo, p.d_twhi, p.d_chirp, p.d_bhat, p.d_mofs,   p.d_cl,    p.d_M,
                     p.d_rho,  p.d_t,    p.d_smap,  p.d_phase,  p.d_apart, p.d_salm,
                     p.d_salm_prev, p.d_sp, p.d_red, p.d_diag, p.d_lam, p.d_loff, p.d_Lp,
-                    p.d_minls32, p.d_minls64, p.d_ana_items, p.d_lofi, p.d_ph32, p.d_a32,
+                    p.d_minls32, p.d_ana_items, p.d_syn_items, p.d_ana_tab, p.d_syn_tab, p.d_lofi, p.d_phf, p.d_ph32, p.d_a32,
                     p.d_s32};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -345,6 +345,38 @@ static void default_variants(Plan &p) {
 
 // Batched FP32 form: lambda table (filled on the device from the FP64 recurrence), skip
 // tables, work items, column-major work arrays.
+// Distributes tiles over the 8 XCD lists: all tiles of one m go to one list (they share
+// an operand block in that XCD's L2), m-groups largest first onto the least-loaded list.
+// Returns the list length; tab = [8][length] item indices, -1 where a list is shorter.
+static int balance_xcd(const std::vector<int2> &items, const std::vector<double> &work, int nm,
+                       std::vector<int> &tab) {
+    std::vector<double> wm(nm, 0.0);
+    std::vector<std::vector<int>> of_m(nm);
+    for (size_t i = 0; i < items.size(); i++) {
+        wm[items[i].x] += work[i];
+        of_m[items[i].x].push_back((int)i);
+    }
+    std::vector<int> order(nm);
+    for (int m = 0; m < nm; m++) order[m] = m;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return wm[a] > wm[b]; });
+    std::vector<std::vector<int>> lists(8);
+    double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int m : order) {
+        if (of_m[m].empty()) continue;
+        int x = 0;
+        for (int k = 1; k < 8; k++)
+            if (load[k] < load[x]) x = k;
+        lists[x].insert(lists[x].end(), of_m[m].begin(), of_m[m].end());
+        load[x] += wm[m];
+    }
+    size_t per = 0;
+    for (auto &l : lists) per = std::max(per, l.size());
+    tab.assign(8 * per, -1);
+    for (int x = 0; x < 8; x++)
+        for (size_t k = 0; k < lists[x].size(); k++) tab[x * per + k] = lists[x][k];
+    return (int)per;
+}
+
 static int setup_batched(Plan &p, const std::vector<int> &lstart, const std::vector<long> &mofs) {
     p.Rp = ((p.npair + 63) / 64) * 64;
     p.Bp = ((p.max_batch + 15) / 16) * 16;
@@ -353,23 +385,39 @@ static int setup_batched(Plan &p, const std::vector<int> &lstart, const std::vec
     std::vector<int> Lp(p.nm);
     long tot = 0;
     for (int m = 0; m < p.nm; m++) {
-        Lp[m] = ((p.lmax - m + 1 + 63) / 64) * 64;
+        Lp[m] = ((p.lmax - m + 1 + 127) / 128) * 128;
         loff[m] = tot;
         tot += (long)p.Rp * Lp[m];
     }
-    const int n32 = p.Rp / 32, n64 = p.Rp / 64;
-    std::vector<int> mn32((size_t)p.nm * n32, p.lmax + 1), mn64((size_t)p.nm * n64, p.lmax + 1);
+    const int n32 = p.Rp / 32;
+    std::vector<int> mn32((size_t)p.nm * n32, p.lmax + 1);
     for (int m = 0; m < p.nm; m++)
         for (int q = 0; q < p.npair; q++) {
-            const int ls = lstart[(size_t)m * p.npair + q];
-            int &a = mn32[(size_t)m * n32 + q / 32], &b = mn64[(size_t)m * n64 + q / 64];
-            a = std::min(a, ls);
-            b = std::min(b, ls);
+            int &a = mn32[(size_t)m * n32 + q / 32];
+            a = std::min(a, lstart[(size_t)m * p.npair + q]);
         }
-    std::vector<int2> items;
-    for (int m = 0; m < p.nm; m++)
-        for (int t = 0; 64 * t < p.lmax - m + 1; t++) items.push_back(make_int2(m, t));
-    p.n_ana_items = (int)items.size();
+    // analysis tiles (m, 128 values of l) and synthesis tiles (m, 64 ring pairs), with their
+    // work in active K chunks (chunks whose pairs all start above the tile are skipped)
+    std::vector<int2> ana, syn;
+    std::vector<double> wana, wsyn;
+    for (int m = 0; m < p.nm; m++) {
+        const int Lm = p.lmax - m + 1;
+        for (int t = 0; 128 * t < Lm; t++) {
+            int act = 0;
+            for (int pc = 0; pc < n32; pc++) act += mn32[(size_t)m * n32 + pc] <= m + 128 * t + 127;
+            ana.push_back(make_int2(m, t));
+            wana.push_back(1.0 + act);
+        }
+        for (int pt = 0; pt < p.Rp / 64; pt++) {
+            const int ls = std::min(mn32[(size_t)m * n32 + 2 * pt], mn32[(size_t)m * n32 + 2 * pt + 1]);
+            const int first = std::max(0, ls - m) / 64, nrc = (Lm + 63) / 64;
+            syn.push_back(make_int2(m, pt));
+            wsyn.push_back(1.0 + std::max(0, nrc - first));
+        }
+    }
+    std::vector<int> ana_tab, syn_tab;
+    p.ana_per_xcd = balance_xcd(ana, wana, p.nm, ana_tab);
+    p.syn_per_xcd = balance_xcd(syn, wsyn, p.nm, syn_tab);
     std::vector<int> lofi(p.nalm);
     for (int m = 0; m < p.nm; m++)
         for (int l = m; l <= p.lmax; l++) lofi[mofs[m] + l - m] = l;
@@ -377,17 +425,22 @@ static int setup_batched(Plan &p, const std::vector<int> &lstart, const std::vec
     MFWF_TRY(dalloc(&p.d_loff, loff.size(), "lambda offsets"));
     MFWF_TRY(dalloc(&p.d_Lp, Lp.size(), "lambda row lengths"));
     MFWF_TRY(dalloc(&p.d_minls32, mn32.size(), "start table 32"));
-    MFWF_TRY(dalloc(&p.d_minls64, mn64.size(), "start table 64"));
-    MFWF_TRY(dalloc(&p.d_ana_items, items.size(), "analysis items"));
+    MFWF_TRY(dalloc(&p.d_ana_items, ana.size(), "analysis items"));
+    MFWF_TRY(dalloc(&p.d_syn_items, syn.size(), "synthesis items"));
+    MFWF_TRY(dalloc(&p.d_ana_tab, ana_tab.size(), "analysis XCD lists"));
+    MFWF_TRY(dalloc(&p.d_syn_tab, syn_tab.size(), "synthesis XCD lists"));
     MFWF_TRY(dalloc(&p.d_lofi, lofi.size(), "l of index"));
+    MFWF_TRY(dalloc(&p.d_phf, (size_t)p.max_batch * p.nring * p.nm, "ring Fourier rows FP32"));
     MFWF_TRY(dalloc(&p.d_ph32, (size_t)p.nring * p.nm * p.C2, "ring Fourier FP32"));
     MFWF_TRY(dalloc(&p.d_a32, (size_t)p.nalm * p.C2, "analysis FP32"));
     MFWF_TRY(dalloc(&p.d_s32, (size_t)p.nalm * p.C2, "synthesis input FP32"));
     MFWF_TRY(upload(p.d_loff, loff, p.stream));
     MFWF_TRY(upload(p.d_Lp, Lp, p.stream));
     MFWF_TRY(upload(p.d_minls32, mn32, p.stream));
-    MFWF_TRY(upload(p.d_minls64, mn64, p.stream));
-    MFWF_TRY(upload(p.d_ana_items, items, p.stream));
+    MFWF_TRY(upload(p.d_ana_items, ana, p.stream));
+    MFWF_TRY(upload(p.d_syn_items, syn, p.stream));
+    MFWF_TRY(upload(p.d_ana_tab, ana_tab, p.stream));
+    MFWF_TRY(upload(p.d_syn_tab, syn_tab, p.stream));
     MFWF_TRY(upload(p.d_lofi, lofi, p.stream));
     MFWF_HIP(hipMemsetAsync(p.d_ph32, 0, sizeof(float) * (size_t)p.nring * p.nm * p.C2, p.stream));
     MFWF_HIP(hipMemsetAsync(p.d_a32, 0, sizeof(float) * (size_t)p.nalm * p.C2, p.stream));
@@ -526,7 +579,6 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
                                          " does not fit the device LDS");
         if (lds > 65536) {
             MFWF_TRY(fft_set_lds_limit(lds));
-            MFWF_TRY(batched_set_lds_limit(lds));
         }
     }
 
@@ -608,14 +660,16 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
 
 // FP32 form: Legendre steps as MFMA GEMMs over the batch (Eqs. 3-4 unchanged)
 static int iteration_b(Plan &p, const double *rho, int nb, double lam, bool keep_prev) {
-    MFWF_TRY(launch_pixel_update(rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, lam, p.tau, p.stream));
-    MFWF_TRY(launch_fft_fwd_b(p, p.d_t, nb));
-    MFWF_TRY(launch_gemm_analysis(p, nb));
+    // pixel update (Eq. 3) applied inside the forward ring transforms
+    MFWF_TRY(launch_fft_fwd_f32(p, p.d_smap, rho, lam, p.d_phf, nb));
+    MFWF_TRY(launch_rows_to_cols(p, nb));
     if (keep_prev) MFWF_TRY(launch_cols_to_alm(p, p.d_s32, p.d_salm_prev, nb, 1.0));
-    MFWF_TRY(launch_harmonic_b(p, p.omega, lam * p.tau * p.omega, nb));
+    // analysis with the harmonic update (Eq. 4) applied in its epilogue
+    MFWF_TRY(launch_gemm_analysis(p, nb, nullptr, p.d_s32, p.omega, lam * p.tau * p.omega));
     if (keep_prev) MFWF_TRY(launch_cols_to_alm(p, p.d_s32, p.d_salm, nb, 1.0));
     MFWF_TRY(launch_gemm_synthesis(p, nb));
-    MFWF_TRY(launch_fft_inv_b(p, p.d_smap, nb));
+    MFWF_TRY(launch_cols_to_rows(p, nb));
+    MFWF_TRY(launch_fft_inv_f32(p, p.d_phf, p.d_smap, nb));
     return MFWF_OK;
 }
 
@@ -786,7 +840,8 @@ int mfwf_sht_inv(mfwf_plan plan, const double *alm, double *map, int nmaps) {
             MFWF_TRY(launch_alm_to_cols(p, reinterpret_cast<const double2 *>(alm) + (long)b0 * p.nalm,
                                         p.d_s32, nb, kHarmCopy));
             MFWF_TRY(launch_gemm_synthesis(p, nb));
-            MFWF_TRY(launch_fft_inv_b(p, map + (long)b0 * p.npix, nb));
+            MFWF_TRY(launch_cols_to_rows(p, nb));
+            MFWF_TRY(launch_fft_inv_f32(p, p.d_phf, map + (long)b0 * p.npix, nb));
             continue;
         }
         MFWF_TRY(launch_harmonic(p, reinterpret_cast<const double2 *>(alm) + (long)b0 * p.nalm, 1,
@@ -805,8 +860,9 @@ int mfwf_sht_fwd(mfwf_plan plan, const double *map, double *alm, int nmaps) {
     for (int b0 = 0; b0 < nmaps; b0 += p.max_batch) {
         const int nb = std::min(p.max_batch, nmaps - b0);
         if (p.dtype == MFWF_F32) {
-            MFWF_TRY(launch_fft_fwd_b(p, map + (long)b0 * p.npix, nb));
-            MFWF_TRY(launch_gemm_analysis(p, nb));
+            MFWF_TRY(launch_fft_fwd_f32(p, map + (long)b0 * p.npix, nullptr, 1.0, p.d_phf, nb));
+            MFWF_TRY(launch_rows_to_cols(p, nb));
+            MFWF_TRY(launch_gemm_analysis(p, nb, p.d_a32, nullptr, 0.0, 0.0));
             MFWF_TRY(launch_cols_to_alm(p, p.d_a32, reinterpret_cast<double2 *>(alm) + (long)b0 * p.nalm,
                                         nb, p.omega));
             continue;
@@ -834,7 +890,8 @@ int mfwf_fluctuation_rhs(mfwf_plan plan, const double *g1, const double *h, int 
             MFWF_TRY(launch_alm_to_cols(p, reinterpret_cast<const double2 *>(h) + (long)b0 * p.nalm,
                                         p.d_s32, nb, kHarmInvSqrtC));
             MFWF_TRY(launch_gemm_synthesis(p, nb));
-            MFWF_TRY(launch_fft_inv_b(p, p.d_t, nb));
+            MFWF_TRY(launch_cols_to_rows(p, nb));
+            MFWF_TRY(launch_fft_inv_f32(p, p.d_phf, p.d_t, nb));
         } else {
             MFWF_TRY(launch_harmonic(p, reinterpret_cast<const double2 *>(h) + (long)b0 * p.nalm, 1,
                                      1.0, 0.0, kHarmInvSqrtC, nullptr, p.d_sp, nullptr, nb));
@@ -901,12 +958,12 @@ int mfwf_time_kernels(mfwf_plan plan, int nmaps, int reps, double *ms_out) {
         std::function<int()> f;
         if (f32) {
             switch (k) {
-                case 0: f = [&] { return launch_pixel_update(p.d_rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, 1.0, p.tau, p.stream); }; break;
-                case 1: f = [&] { return launch_fft_fwd_b(p, p.d_t, nb); }; break;
-                case 2: f = [&] { return launch_gemm_analysis(p, nb); }; break;
-                case 3: f = [&] { return launch_harmonic_b(p, p.omega, p.tau * p.omega, nb); }; break;
+                case 0: ms_out[k] = 0.0; continue;  // pixel update runs inside the forward transforms
+                case 1: f = [&] { MFWF_TRY(launch_fft_fwd_f32(p, p.d_smap, p.d_rho, 1.0, p.d_phf, nb)); return launch_rows_to_cols(p, nb); }; break;
+                case 2: f = [&] { return launch_gemm_analysis(p, nb, nullptr, p.d_s32, p.omega, p.tau * p.omega); }; break;
+                case 3: ms_out[k] = 0.0; continue;  // harmonic update runs inside the analysis
                 case 4: f = [&] { return launch_gemm_synthesis(p, nb); }; break;
-                default: f = [&] { return launch_fft_inv_b(p, p.d_smap, nb); }; break;
+                default: f = [&] { MFWF_TRY(launch_cols_to_rows(p, nb)); return launch_fft_inv_f32(p, p.d_phf, p.d_smap, nb); }; break;
             }
             float ms = 0.f;
             MFWF_TRY(time_launches(p, reps, f, ms));

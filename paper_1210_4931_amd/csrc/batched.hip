@@ -8,19 +8,17 @@
 //   analysis   a[l][c] = sum_p lambda_lm(z_p) X_{(l+m) mod 2}[p][c],
 //              X_0 = G_N + G_S, X_1 = G_N - G_S              ([L x pairs] x [pairs x cols])
 // lambda_lm is tabulated once per plan in FP32 (computed from the FP64 recurrence and start
-// seeds, zero below each pair's start index), as rows [m][pair][l - m] padded to 64 values of
+// seeds, zero below each pair's start index), as rows [m][pair][l - m] padded to 128 values of
 // l and 64 pairs.  The products run on v_mfma_f32_32x32x2f32 with FP32 accumulation; the
 // ring-Fourier array ([ring][m][cols]) and the coefficients ([alm][cols]) are FP32 with the
 // maps innermost, so tiles of columns are contiguous.  Maps, the pixel update and every
-// diagnostic stay FP64.  The ring FFTs are the FP64 transforms of the per-map path; one
-// workgroup runs several maps of a ring pair in turn.
+// diagnostic stay FP64.  The ring FFTs are the FP64 transforms of the per-map path with
+// FP32 per-map output rows, regrouped into the column layout by LDS-tiled transposes.
 #include "fft_core.h"
 
 namespace mfwf {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
-
-static constexpr int kMapsPerFFTBlock = 16;
 
 // ---------------------------------------------------------------------------------------
 // lambda table: one lane per ring pair, one workgroup per (pair tile of 64, m).
@@ -63,215 +61,212 @@ k_lam_table(const double *__restrict__ Atab, const double *__restrict__ ctab,
 }
 
 // ---------------------------------------------------------------------------------------
-// Batched ring FFTs: workgroup = (ring pair, group of maps); FP32 ring-Fourier
-// [ring][m][C2], column 2b (re) and 2b + 1 (im) of map b.
+// Layout changes between the per-map ring-Fourier rows of the ring transforms,
+// [map][ring][m] (FP32 complex), and the contraction layout [m][ring][C2] with columns 2b
+// (re) and 2b + 1 (im) of map b.  One workgroup moves a tile of 64 values of m x 64 maps
+// of one ring through LDS, so that both sides read and write 512-byte rows.
 // ---------------------------------------------------------------------------------------
-template <int TPB, int EPT>
-__global__ void __launch_bounds__(TPB)
-k_fft_fwd_b(const double *__restrict__ maps, float *__restrict__ ph32,
-            const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
-            const double2 *__restrict__ twlo, const double2 *__restrict__ twhi, int ntwhi,
-            int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
-            long npix, int nring, int nm, int lmax, int fftlen_class, int nb, int C2) {
-    extern __shared__ double2 buf[];
-    const int p = plist[blockIdx.x];
-    const PairFFT pf = pfft[p];
-    const int n = pf.nphi;
-    const bool equator = (pf.startS == pf.startN);
-    const Twiddles tw = load_twiddles(buf, fftlen_class, TPB, twlo, twhi, ntwhi);
-    float *outN = ph32 + (long)p * nm * C2;
-    float *outS = ph32 + (long)(nring - 1 - p) * nm * C2;
-    const int b0 = blockIdx.y * kMapsPerFFTBlock;
-    for (int g = 0; g < kMapsPerFFTBlock; g++) {
-        const int b = b0 + g;
-        if (b >= nb) break;
-        const double *tN = maps + (long)b * npix + pf.startN;
-        const double *tS = maps + (long)b * npix + pf.startS;
-        for (int j = threadIdx.x; j < n; j += TPB)
-            buf[j] = make_double2(tN[j], equator ? 0.0 : tS[j]);
-        __syncthreads();
-        ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
-        for (int m = threadIdx.x; m <= lmax; m += TPB) {
-            const int q = m / n, k = m - q * n;
-            const int kr = (k == 0) ? 0 : n - k;
-            const double2 X = dft_bin(buf, pf, chirp, k);
-            const double2 Y = cconj(dft_bin(buf, pf, chirp, kr));
-            double2 ph = make_double2(1.0, 0.0);
-            if (pf.half_shift) ph = cscale(cconj(half_bin_phase(k, n, tw, fftmax)), (q & 1) ? -1.0 : 1.0);
-            const double2 gN = cmul(make_double2(0.5 * (X.x + Y.x), 0.5 * (X.y + Y.y)), ph);
-            *reinterpret_cast<float2 *>(outN + (long)m * C2 + 2 * b) = make_float2((float)gN.x, (float)gN.y);
-            if (!equator) {
-                const double2 gS = cmul(make_double2(0.5 * (X.y - Y.y), -0.5 * (X.x - Y.x)), ph);
-                *reinterpret_cast<float2 *>(outS + (long)m * C2 + 2 * b) = make_float2((float)gS.x, (float)gS.y);
-            }
-        }
-        __syncthreads();
+__global__ void __launch_bounds__(256)
+k_rows_to_cols(const float2 *__restrict__ phf, float *__restrict__ ph32, int nring, int nm,
+               int nb, int Bp, int C2) {
+    __shared__ float2 tile[64][64 + 1];  // [map][m]
+    const int ring = blockIdx.x, m0 = 64 * blockIdx.y, b0 = 64 * blockIdx.z;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int bb = e >> 6, mm = e & 63, b = b0 + bb, m = m0 + mm;
+        tile[bb][mm] = (b < nb && m < nm) ? phf[((long)b * nring + ring) * nm + m] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int mm = e >> 6, bb = e & 63, b = b0 + bb, m = m0 + mm;
+        if (b < Bp && m < nm)
+            *reinterpret_cast<float2 *>(ph32 + ((long)m * nring + ring) * C2 + 2 * b) = tile[bb][mm];
     }
 }
 
-template <int TPB, int EPT>
-__global__ void __launch_bounds__(TPB)
-k_fft_inv_b(const float *__restrict__ ph32, double *__restrict__ maps,
-            const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
-            const double2 *__restrict__ twlo, const double2 *__restrict__ twhi, int ntwhi,
-            int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
-            long npix, int nring, int nm, int lmax, int fftlen_class, int nb, int C2) {
-    extern __shared__ double2 buf[];
-    const int p = plist[blockIdx.x];
-    const PairFFT pf = pfft[p];
-    const int n = pf.nphi;
-    double2 *partN = buf + fftlen_class;
-    double2 *partS = partN + TPB;
-    const bool equator = (pf.startS == pf.startN);
-    const Twiddles tw = load_twiddles(buf, fftlen_class, TPB, twlo, twhi, ntwhi);
-    const float *FN = ph32 + (long)p * nm * C2;
-    const float *FS = ph32 + (long)(nring - 1 - p) * nm * C2;
-    int T = TPB / n;
-    if (T < 1) T = 1;
-    const int nbins_pass = TPB / T;
-    const double sgn_step = pf.half_shift ? -1.0 : 1.0;
-    const double sg_stride = (T & 1) ? sgn_step : 1.0;
-    const int b0 = blockIdx.y * kMapsPerFFTBlock;
-    for (int g = 0; g < kMapsPerFFTBlock; g++) {
-        const int b = b0 + g;
-        if (b >= nb) break;
-        auto ld = [&](const float *F, int m) {
-            const float2 v = *reinterpret_cast<const float2 *>(F + (long)m * C2 + 2 * b);
-            return make_double2(v.x, v.y);
-        };
-        for (int k0 = 0; k0 < n; k0 += nbins_pass) {
-            const int k = k0 + threadIdx.x / T, t = threadIdx.x % T;
-            double2 sN = make_double2(0.0, 0.0), sS = make_double2(0.0, 0.0);
-            if (k < n && (int)threadIdx.x < nbins_pass * T) {
-                double sg = (t & 1) ? sgn_step : 1.0;
-                for (int m = k + t * n; m <= lmax; m += T * n, sg *= sg_stride) {
-                    sN = cadd(sN, cscale(ld(FN, m), sg));
-                    if (!equator) sS = cadd(sS, cscale(ld(FS, m), sg));
-                }
-                sg = ((t + 1) & 1) ? sgn_step : 1.0;
-                for (int mm = (t + 1) * n - k; mm <= lmax; mm += T * n, sg *= sg_stride) {
-                    sN = cadd(sN, cscale(cconj(ld(FN, mm)), sg));
-                    if (!equator) sS = cadd(sS, cscale(cconj(ld(FS, mm)), sg));
-                }
-            }
-            if (T > 1) {
-                partN[threadIdx.x] = sN;
-                partS[threadIdx.x] = sS;
-                __syncthreads();
-                if (t == 0 && k < n) {
-                    for (int u = 1; u < T; u++) {
-                        sN = cadd(sN, partN[threadIdx.x + u]);
-                        sS = cadd(sS, partS[threadIdx.x + u]);
-                    }
-                }
-                __syncthreads();
-            }
-            if (t == 0 && k < n) {
-                if (pf.half_shift) {
-                    const double2 ph = half_bin_phase(k, n, tw, fftmax);
-                    sN = cmul(sN, ph);
-                    sS = cmul(sS, ph);
-                }
-                buf[k] = cconj(make_double2(sN.x - sS.y, sN.y + sS.x));
-            }
-        }
-        __syncthreads();
-        ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
-        double *sNmap = maps + (long)b * npix + pf.startN;
-        double *sSmap = maps + (long)b * npix + pf.startS;
-        for (int j = threadIdx.x; j < n; j += TPB) {
-            const double2 x = cconj(dft_bin(buf, pf, chirp, j));
-            sNmap[j] = x.x;
-            if (!equator) sSmap[j] = x.y;
-        }
-        __syncthreads();
+__global__ void __launch_bounds__(256)
+k_cols_to_rows(const float *__restrict__ ph32, float2 *__restrict__ phf, int nring, int nm,
+               int nb, int C2) {
+    __shared__ float2 tile[64][64 + 1];  // [m][map]
+    const int ring = blockIdx.x, m0 = 64 * blockIdx.y, b0 = 64 * blockIdx.z;
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int mm = e >> 6, bb = e & 63, b = b0 + bb, m = m0 + mm;
+        tile[mm][bb] = (b < nb && m < nm)
+                           ? *reinterpret_cast<const float2 *>(ph32 + ((long)m * nring + ring) * C2 + 2 * b)
+                           : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+        const int bb = e >> 6, mm = e & 63, b = b0 + bb, m = m0 + mm;
+        if (b < nb && m < nm) phf[((long)b * nring + ring) * nm + m] = tile[mm][bb];
     }
 }
 
 // ---------------------------------------------------------------------------------------
-// MFMA GEMMs.  Workgroup of 4 waves; wave w owns columns [128 cg + 32 w, +32).
-// v_mfma_f32_32x32x2f32 operands: A[i][k] in lane i + 32k, B[k][j] in lane j + 32k,
-// accumulator register r of lane L holds D[8 (r/4) + 4 (L/32) + r%4][L%32].
+// MFMA GEMMs.  Workgroup of 4 waves.  v_mfma_f32_32x32x2f32 operands: A[i][k] in lane
+// i + 32k, B[k][j] in lane j + 32k; accumulator register r of lane L holds
+// D[8 (r/4) + 4 (L/32) + r%4][L%32].
+//
+// Workgroup i of a launch is dispatched to XCD i mod 8.  Each XCD takes its tiles from its
+// own list, so that all tiles of one m, which read the same ring-Fourier (analysis) or
+// coefficient (synthesis) block, run on one XCD and share its L2 instead of fetching the
+// block from HBM once per XCD; the lists are balanced by the number of active K chunks.
+// Global loads of the next K chunk are issued before the matrix products of the current
+// one (register double buffering).
 // ---------------------------------------------------------------------------------------
 __device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
 
-// analysis: workgroup = (m, tile of 64 values of l); K loop over pair chunks of 32.
+// Tile of workgroup bid: XCD x = bid mod 8 works through its own list tab[x][*] of tiles
+// (balanced by work on the host, tiles of one m adjacent); columns groups innermost.
+struct XcdTile {
+    int item, cg;
+};
+__device__ __forceinline__ XcdTile xcd_tile(const int *__restrict__ tab, int per_xcd, int ncg) {
+    const int x = blockIdx.x & 7, s = blockIdx.x >> 3;
+    const int k = s / ncg;
+    XcdTile r;
+    r.cg = s - k * ncg;
+    r.item = (k < per_xcd) ? tab[x * per_xcd + k] : -1;
+    return r;
+}
+
+__device__ __forceinline__ float4 f4add(float4 a, float4 b) { return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w); }
+__device__ __forceinline__ float4 f4sub(float4 a, float4 b) { return make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w); }
+
+static constexpr int kAnaRows = 128;  // values of l per analysis tile
+static constexpr int kColTile = 128;  // columns per workgroup
+
+// analysis: tile = (m, 128 values of l, 128 columns); K loop over chunks of 32 ring pairs.
+// Wave w: rows 64 (w & 1) .. +63 of the tile (32 even, 32 odd l + m), columns 64 (w >> 1)
+// .. +63.  Output: raw sums a (if a_out) and/or the Wiener-filtered coefficients
+// s = scale_s C_l / (C_l + lto) a (if s_out), rows [alm][C2].
 __global__ void __launch_bounds__(256)
 k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
                 const int *__restrict__ Lp, const int *__restrict__ minls32,
-                const int2 *__restrict__ items, const float *__restrict__ ph32,
-                const long *__restrict__ mofs, float *__restrict__ a32, int lmax, int npair,
-                int Rp, int nring, int nm, int C2, int ncols) {
-    __shared__ float sl[32][64 + 1];        // lambda tile [pair][l]
-    __shared__ float sx[2][32][128 + 4];    // X_0, X_1 tiles [pair][col]
-    const int2 it = items[blockIdx.x];
-    const int m = it.x, t = it.y, cg = blockIdx.y;
+                const int2 *__restrict__ items, const int *__restrict__ tab, int per_xcd,
+                const float *__restrict__ ph32, const long *__restrict__ mofs,
+                const double *__restrict__ cl, float *__restrict__ a_out,
+                float *__restrict__ s_out, double scale_s, double lto, int lmax, int npair,
+                int Rp, int nring, int nm, int C2, int ncols, int ncg) {
+    __shared__ float sl[32][kAnaRows + 4];       // lambda tile [pair][row]
+    __shared__ float sx[2][32][kColTile + 4];    // X_0, X_1 tiles [pair][col]
+    const XcdTile xt = xcd_tile(tab, per_xcd, ncg);
+    if (xt.item < 0) return;
+    const int2 it = items[xt.item];
+    const int m = it.x, t = it.y, cg = xt.cg;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lh = w & 1, ch = w >> 1;
     const int L = Lp[m];
-    const int lhi = m + 64 * t + 63;  // last l of the tile
+    const int lhi = m + kAnaRows * t + kAnaRows - 1;  // last l of the tile
+    const int lhi_w = m + kAnaRows * t + 64 * lh + 63;  // last l of this wave's rows
     const int nchunk = Rp / 32;
-    floatx16 ce, co;
+    const int *ms = minls32 + m * nchunk;
+    floatx16 acc[2][2];  // [parity][column tile]
 #pragma unroll
-    for (int r = 0; r < 16; r++) ce[r] = co[r] = 0.f;
-    const float *lrow = lam + loff[m];
-    const bool active = (128 * cg + 32 * w) < ncols;
-    for (int pc = 0; pc < nchunk; pc++) {
-        if (minls32[m * nchunk + pc] > lhi) continue;  // no pair of the chunk starts yet
-        __syncthreads();
-        for (int e = threadIdx.x; e < 32 * 64; e += 256) {
-            const int pp = e >> 6, rr = e & 63;
-            sl[pp][rr] = lrow[(long)(32 * pc + pp) * L + 64 * t + rr];
-        }
-        for (int e = threadIdx.x; e < 32 * 128; e += 256) {
-            const int pp = e >> 7, c = e & 127, col = 128 * cg + c;
-            const int p = 32 * pc + pp;
-            float gn = 0.f, gs = 0.f;
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int b = 0; b < 2; b++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) acc[a][b][r] = 0.f;
+    const float *lrow = lam + loff[m] + kAnaRows * t;
+    const bool wave_on = (kColTile * cg + 64 * ch) < ncols;
+    float4 rl[4], rn[4], rs[4];
+    auto load = [&](int pc) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int e = threadIdx.x + 256 * u, pp = e >> 5, c4 = e & 31;
+            const int p = 32 * pc + pp, col = kColTile * cg + 4 * c4;
+            rl[u] = *reinterpret_cast<const float4 *>(lrow + (long)p * L + 4 * c4);
+            float4 gn = make_float4(0.f, 0.f, 0.f, 0.f), gs = gn;
             if (p < npair && col < ncols) {
-                gn = ph32[((long)p * nm + m) * C2 + col];
-                if (nring - 1 - p != p) gs = ph32[((long)(nring - 1 - p) * nm + m) * C2 + col];
+                gn = *reinterpret_cast<const float4 *>(ph32 + ((long)m * nring + p) * C2 + col);
+                if (nring - 1 - p != p)
+                    gs = *reinterpret_cast<const float4 *>(ph32 + ((long)m * nring + (nring - 1 - p)) * C2 + col);
             }
-            sx[0][pp][c] = gn + gs;
-            sx[1][pp][c] = gn - gs;
+            rn[u] = gn;
+            rs[u] = gs;
+        }
+    };
+    auto next_active = [&](int pc) {
+        while (pc < nchunk && ms[pc] > lhi) pc++;
+        return pc;
+    };
+    int pc = next_active(0);
+    if (pc < nchunk) load(pc);
+    while (pc < nchunk) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int e = threadIdx.x + 256 * u, pp = e >> 5, c4 = e & 31;
+            *reinterpret_cast<float4 *>(&sl[pp][4 * c4]) = rl[u];
+            *reinterpret_cast<float4 *>(&sx[0][pp][4 * c4]) = f4add(rn[u], rs[u]);
+            *reinterpret_cast<float4 *>(&sx[1][pp][4 * c4]) = f4sub(rn[u], rs[u]);
         }
         __syncthreads();
-        if (active) {
+        const int pn = next_active(pc + 1);
+        if (pn < nchunk) load(pn);
+        if (wave_on && ms[pc] <= lhi_w) {
             const int i = lane & 31, kq = lane >> 5;
 #pragma unroll 4
             for (int kk = 0; kk < 16; kk++) {
                 const int pp = 2 * kk + kq;
-                const float ae = sl[pp][2 * i], ao = sl[pp][2 * i + 1];
-                const float be = sx[0][pp][32 * w + i], bo = sx[1][pp][32 * w + i];
-                ce = __builtin_amdgcn_mfma_f32_32x32x2f32(ae, be, ce, 0, 0, 0);
-                co = __builtin_amdgcn_mfma_f32_32x32x2f32(ao, bo, co, 0, 0, 0);
+                const float2 a = *reinterpret_cast<const float2 *>(&sl[pp][64 * lh + 2 * i]);
+                const float b00 = sx[0][pp][64 * ch + i], b01 = sx[0][pp][64 * ch + 32 + i];
+                const float b10 = sx[1][pp][64 * ch + i], b11 = sx[1][pp][64 * ch + 32 + i];
+                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b00, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b01, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b10, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b11, acc[1][1], 0, 0, 0);
             }
         }
+        pc = pn;
     }
-    if (!active) return;
+    if (!wave_on) return;
     const long base = mofs[m] - m;
-    const int col = 128 * cg + 32 * w + (lane & 31);
 #pragma unroll
-    for (int r = 0; r < 16; r++) {
-        const int i = acc_row(r, lane);
-        const int le = m + 64 * t + 2 * i, lo = le + 1;
-        if (le <= lmax) a32[(base + le) * C2 + col] = ce[r];
-        if (lo <= lmax) a32[(base + lo) * C2 + col] = co[r];
+    for (int ct = 0; ct < 2; ct++) {
+        const int col = kColTile * cg + 64 * ch + 32 * ct + (lane & 31);
+        if (col >= ncols) continue;
+#pragma unroll
+        for (int r = 0; r < 16; r++)
+#pragma unroll
+            for (int par = 0; par < 2; par++) {
+                const int l = m + kAnaRows * t + 64 * lh + 2 * acc_row(r, lane) + par;
+                if (l > lmax) continue;
+                const float v = acc[par][ct][r];
+                const long idx = (base + l) * C2 + col;
+                if (a_out) a_out[idx] = v;
+                if (s_out) {
+                    const double C = cl[l];
+                    const double f = C > 0.0 ? C / (C + lto) * scale_s : 0.0;
+                    s_out[idx] = (float)(f * (double)v);
+                }
+            }
     }
 }
 
-// synthesis: workgroup = (m, tile of 64 ring pairs); K loop over chunks of 64 values of l.
+// synthesis: tile = (m, 64 ring pairs, 128 columns); K loop over chunks of 64 values of l.
+// Wave w: pairs 32 (w & 1) .. +31 of the tile, columns 64 (w >> 1) .. +63.
 __global__ void __launch_bounds__(256)
 k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
-                 const int *__restrict__ Lp, const int *__restrict__ minls64,
+                 const int *__restrict__ Lp, const int *__restrict__ minls32,
+                 const int2 *__restrict__ items, const int *__restrict__ tab, int per_xcd,
                  const float *__restrict__ s32, const long *__restrict__ mofs,
                  float *__restrict__ ph32, int lmax, int npair, int Rp, int nring, int nm,
-                 int C2, int ncols) {
-    __shared__ float sl[64][64 + 1];    // lambda tile [pair][l]
-    __shared__ float ss[64][128 + 4];   // coefficient tile [l][col]
-    const int m = blockIdx.x / (Rp / 64), pt = blockIdx.x % (Rp / 64), cg = blockIdx.y;
+                 int C2, int ncols, int ncg) {
+    __shared__ float sl[64][64 + 4];            // lambda tile [pair][l]
+    __shared__ float ss[64][kColTile + 4];      // coefficient tile [l][col]
+    const XcdTile xt = xcd_tile(tab, per_xcd, ncg);
+    if (xt.item < 0) return;
+    const int2 it = items[xt.item];
+    const int m = it.x, pt = it.y, cg = xt.cg;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int rt = w & 1, ch = w >> 1;
     const int L = Lp[m], Lm = lmax - m + 1;
-    const bool active = (128 * cg + 32 * w) < ncols;
-    floatx16 acc[2][2];  // [parity][pair tile of 32]
+    const int nchunk32 = Rp / 32;
+    const int ls_tile = min(minls32[m * nchunk32 + 2 * pt], minls32[m * nchunk32 + 2 * pt + 1]);
+    const int ls_wave = minls32[m * nchunk32 + 2 * pt + rt];
+    const bool wave_on = (kColTile * cg + 64 * ch) < ncols;
+    floatx16 acc[2][2];  // [parity][column tile]
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
@@ -280,70 +275,76 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
             for (int r = 0; r < 16; r++) acc[a][b][r] = 0.f;
     const float *lrow = lam + loff[m] + (long)(64 * pt) * L;
     const long base = mofs[m];
-    const int first = max(0, minls64[m * (Rp / 64) + pt] - m) / 64;  // first chunk with lambda != 0
-    for (int rc = first; rc * 64 < Lm; rc++) {
-        __syncthreads();
-        for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-            const int pp = e >> 6, rr = e & 63;
-            sl[pp][rr] = lrow[(long)pp * L + 64 * rc + rr];
+    float4 rl[4], rv[8];
+    auto load = [&](int rc) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int e = threadIdx.x + 256 * u, pp = e >> 4, c4 = e & 15;
+            rl[u] = *reinterpret_cast<const float4 *>(lrow + (long)pp * L + 64 * rc + 4 * c4);
         }
-        for (int e = threadIdx.x; e < 64 * 128; e += 256) {
-            const int rr = e >> 7, c = e & 127, col = 128 * cg + c;
-            const int r = 64 * rc + rr;
-            ss[rr][c] = (r < Lm && col < ncols) ? s32[(base + r) * C2 + col] : 0.f;
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int e = threadIdx.x + 256 * u, rr = e >> 5, c4 = e & 31;
+            const int r = 64 * rc + rr, col = kColTile * cg + 4 * c4;
+            rv[u] = (r < Lm && col < ncols)
+                        ? *reinterpret_cast<const float4 *>(s32 + (base + r) * C2 + col)
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    const int first = max(0, ls_tile - m) / 64;  // first chunk with a nonzero lambda
+    const int nrc = (Lm + 63) / 64;
+    if (first < nrc) load(first);
+    for (int rc = first; rc < nrc; rc++) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int e = threadIdx.x + 256 * u, pp = e >> 4, c4 = e & 15;
+            *reinterpret_cast<float4 *>(&sl[pp][4 * c4]) = rl[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int e = threadIdx.x + 256 * u, rr = e >> 5, c4 = e & 31;
+            *reinterpret_cast<float4 *>(&ss[rr][4 * c4]) = rv[u];
         }
         __syncthreads();
-        if (active) {
+        if (rc + 1 < nrc) load(rc + 1);
+        if (wave_on && ls_wave <= m + 64 * rc + 63) {
             const int i = lane & 31, kq = lane >> 5;
 #pragma unroll
             for (int par = 0; par < 2; par++) {
 #pragma unroll 4
                 for (int kk = 0; kk < 16; kk++) {
                     const int rr = 4 * kk + 2 * kq + par;  // two same-parity l per step
-                    const float bv = ss[rr][32 * w + i];
-                    const float a0 = sl[i][rr], a1 = sl[32 + i][rr];
-                    acc[par][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, bv, acc[par][0], 0, 0, 0);
-                    acc[par][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, bv, acc[par][1], 0, 0, 0);
+                    const float a = sl[32 * rt + i][rr];
+                    const float b0 = ss[rr][64 * ch + i], b1 = ss[rr][64 * ch + 32 + i];
+                    acc[par][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, acc[par][0], 0, 0, 0);
+                    acc[par][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, acc[par][1], 0, 0, 0);
                 }
             }
         }
     }
-    if (!active) return;
+    if (!wave_on) return;
     // rows are relative l = m + r: parity of r equals parity of l + m
-    const int col = 128 * cg + 32 * w + (lane & 31);
 #pragma unroll
-    for (int tt = 0; tt < 2; tt++)
+    for (int ct = 0; ct < 2; ct++) {
+        const int col = kColTile * cg + 64 * ch + 32 * ct + (lane & 31);
+        if (col >= ncols) continue;
 #pragma unroll
         for (int r = 0; r < 16; r++) {
-            const int p = 64 * pt + 32 * tt + acc_row(r, lane);
+            const int p = 64 * pt + 32 * rt + acc_row(r, lane);
             if (p >= npair) continue;
-            const float E = acc[0][tt][r], O = acc[1][tt][r];
-            ph32[((long)p * nm + m) * C2 + col] = E + O;
+            const float E = acc[0][ct][r], O = acc[1][ct][r];
+            ph32[((long)m * nring + p) * C2 + col] = E + O;
             const int rS = nring - 1 - p;
-            if (rS != p) ph32[((long)rS * nm + m) * C2 + col] = E - O;
+            if (rS != p) ph32[((long)m * nring + rS) * C2 + col] = E - O;
         }
-}
-
-// ---------------------------------------------------------------------------------------
-// Harmonic update on [alm][C2] FP32 rows (Eq. 4), and conversions to / from the FP64
-// per-map alm layout [map][nalm] complex through LDS-transposed tiles.
-// ---------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
-k_harmonic_b(const float *__restrict__ a32, float *__restrict__ s32, const long *__restrict__ mofs,
-             const double *__restrict__ cl, int lmax, double scale, double lto, int C2,
-             int ncols) {
-    const int m = blockIdx.x;
-    const long base = mofs[m] - m;
-    const long n = (long)(lmax - m + 1) * ncols;
-    for (long e = threadIdx.x; e < n; e += 256) {
-        const int l = m + (int)(e / ncols);
-        const double C = cl[l];
-        const double f = C > 0.0 ? C / (C + lto) * scale : 0.0;
-        const long i = (base + l) * C2 + e % ncols;
-        s32[i] = (float)(f * (double)a32[i]);
     }
 }
 
+// ---------------------------------------------------------------------------------------
+// Conversions between the FP32 rows [alm][C2] and the FP64 per-map alm layout
+// [map][nalm] complex, through LDS-transposed tiles.
+// ---------------------------------------------------------------------------------------
 // alm FP64 [nb][nalm] (complex) -> x32 [nalm][C2] FP32, times f(l) (mode: 3 copy, 2 C^-1/2)
 __global__ void __launch_bounds__(256)
 k_alm_to_cols(const double2 *__restrict__ alm, float *__restrict__ x32,
@@ -409,73 +410,39 @@ int launch_lam_table(const Plan &p) {
     return MFWF_OK;
 }
 
-#define MFWF_FFTB_ARGS(c)                                                                       \
-    p.d_pfft, p.d_plist + p.fft_class_off[c], p.d_twlo, p.d_twhi, p.fft_ntwhi, p.fftmax,        \
-        p.d_chirp, p.d_bhat, p.npix, p.nring, p.nm, p.lmax, p.fft_class_len[c], nb, p.C2
-
-int launch_fft_fwd_b(const Plan &p, const double *maps, int nb) {
-    const int ng = (nb + kMapsPerFFTBlock - 1) / kMapsPerFFTBlock;
-    for (int c = 1; c >= 0; c--) {
-        const int cnt = p.fft_class_count[c];
-        if (cnt == 0) continue;
-        int ept;
-        const int tpb = fft_class_shape(p, c, ept);
-        const dim3 grid(cnt, ng);
-        const size_t lds = fft_class_lds(p, c);
-        if (ept == 8)
-            hipLaunchKernelGGL((k_fft_fwd_b<256, 8>), grid, dim3(256), lds, p.stream, maps, p.d_ph32, MFWF_FFTB_ARGS(c));
-        else if (tpb == 256)
-            hipLaunchKernelGGL((k_fft_fwd_b<256, 16>), grid, dim3(256), lds, p.stream, maps, p.d_ph32, MFWF_FFTB_ARGS(c));
-        else
-            hipLaunchKernelGGL((k_fft_fwd_b<512, 16>), grid, dim3(512), lds, p.stream, maps, p.d_ph32, MFWF_FFTB_ARGS(c));
-        MFWF_HIP(hipGetLastError());
-    }
+int launch_rows_to_cols(const Plan &p, int nb) {
+    hipLaunchKernelGGL(k_rows_to_cols, dim3(p.nring, (p.nm + 63) / 64, (p.Bp + 63) / 64), dim3(256), 0,
+                       p.stream, p.d_phf, p.d_ph32, p.nring, p.nm, nb, p.Bp, p.C2);
+    MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }
 
-int launch_fft_inv_b(const Plan &p, double *maps, int nb) {
-    const int ng = (nb + kMapsPerFFTBlock - 1) / kMapsPerFFTBlock;
-    for (int c = 1; c >= 0; c--) {
-        const int cnt = p.fft_class_count[c];
-        if (cnt == 0) continue;
-        int ept;
-        const int tpb = fft_class_shape(p, c, ept);
-        const dim3 grid(cnt, ng);
-        const size_t lds = fft_class_lds(p, c);
-        if (ept == 8)
-            hipLaunchKernelGGL((k_fft_inv_b<256, 8>), grid, dim3(256), lds, p.stream, p.d_ph32, maps, MFWF_FFTB_ARGS(c));
-        else if (tpb == 256)
-            hipLaunchKernelGGL((k_fft_inv_b<256, 16>), grid, dim3(256), lds, p.stream, p.d_ph32, maps, MFWF_FFTB_ARGS(c));
-        else
-            hipLaunchKernelGGL((k_fft_inv_b<512, 16>), grid, dim3(512), lds, p.stream, p.d_ph32, maps, MFWF_FFTB_ARGS(c));
-        MFWF_HIP(hipGetLastError());
-    }
+int launch_cols_to_rows(const Plan &p, int nb) {
+    hipLaunchKernelGGL(k_cols_to_rows, dim3(p.nring, (p.nm + 63) / 64, (nb + 63) / 64), dim3(256), 0,
+                       p.stream, p.d_ph32, p.d_phf, p.nring, p.nm, nb, p.C2);
+    MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }
 
 static int active_cols(int nb) { return 32 * ((2 * nb + 31) / 32); }
 
-int launch_gemm_analysis(const Plan &p, int nb) {
-    const int nc = active_cols(nb);
-    hipLaunchKernelGGL(k_gemm_analysis, dim3(p.n_ana_items, (nc + 127) / 128), dim3(256), 0,
-                       p.stream, p.d_lam, p.d_loff, p.d_Lp, p.d_minls32, p.d_ana_items, p.d_ph32,
-                       p.d_mofs, p.d_a32, p.lmax, p.npair, p.Rp, p.nring, p.nm, p.C2, nc);
+int launch_gemm_analysis(const Plan &p, int nb, float *a_out, float *s_out, double scale_s,
+                         double lto) {
+    const int nc = active_cols(nb), ncg = (nc + kColTile - 1) / kColTile;
+    hipLaunchKernelGGL(k_gemm_analysis, dim3(8 * p.ana_per_xcd * ncg), dim3(256), 0, p.stream,
+                       p.d_lam, p.d_loff, p.d_Lp, p.d_minls32, p.d_ana_items, p.d_ana_tab,
+                       p.ana_per_xcd, p.d_ph32, p.d_mofs, p.d_cl, a_out, s_out, scale_s, lto,
+                       p.lmax, p.npair, p.Rp, p.nring, p.nm, p.C2, nc, ncg);
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }
 
 int launch_gemm_synthesis(const Plan &p, int nb) {
-    const int nc = active_cols(nb);
-    hipLaunchKernelGGL(k_gemm_synthesis, dim3(p.nm * (p.Rp / 64), (nc + 127) / 128), dim3(256), 0,
-                       p.stream, p.d_lam, p.d_loff, p.d_Lp, p.d_minls64, p.d_s32, p.d_mofs,
-                       p.d_ph32, p.lmax, p.npair, p.Rp, p.nring, p.nm, p.C2, nc);
-    MFWF_HIP(hipGetLastError());
-    return MFWF_OK;
-}
-
-int launch_harmonic_b(const Plan &p, double scale, double lto, int nb) {
-    hipLaunchKernelGGL(k_harmonic_b, dim3(p.nm), dim3(256), 0, p.stream, p.d_a32, p.d_s32,
-                       p.d_mofs, p.d_cl, p.lmax, scale, lto, p.C2, active_cols(nb));
+    const int nc = active_cols(nb), ncg = (nc + kColTile - 1) / kColTile;
+    hipLaunchKernelGGL(k_gemm_synthesis, dim3(8 * p.syn_per_xcd * ncg), dim3(256), 0, p.stream,
+                       p.d_lam, p.d_loff, p.d_Lp, p.d_minls32, p.d_syn_items, p.d_syn_tab,
+                       p.syn_per_xcd, p.d_s32, p.d_mofs, p.d_ph32, p.lmax, p.npair, p.Rp,
+                       p.nring, p.nm, p.C2, nc, ncg);
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }
@@ -491,15 +458,6 @@ int launch_cols_to_alm(const Plan &p, const float *x32, double2 *alm, int nb, do
     hipLaunchKernelGGL(k_cols_to_alm, dim3((p.nalm + 63) / 64, (p.C2 + 63) / 64), dim3(256), 0,
                        p.stream, x32, alm, p.nalm, nb, p.C2, scale);
     MFWF_HIP(hipGetLastError());
-    return MFWF_OK;
-}
-
-int batched_set_lds_limit(size_t bytes) {
-    const void *fns[] = {(const void *)k_fft_fwd_b<256, 8>, (const void *)k_fft_fwd_b<256, 16>,
-                         (const void *)k_fft_fwd_b<512, 16>, (const void *)k_fft_inv_b<256, 8>,
-                         (const void *)k_fft_inv_b<256, 16>, (const void *)k_fft_inv_b<512, 16>};
-    for (const void *f : fns)
-        MFWF_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     return MFWF_OK;
 }
 

@@ -99,15 +99,18 @@ struct Plan {
     int Rp = 0;                  // ring pairs padded to 64
     int Bp = 0;                  // maps padded to 16
     int C2 = 0;                  // columns = 2 Bp (re, im of each map)
-    float *d_lam = nullptr;      // lambda_lm(z_p) FP32, rows [m][pair][l - m] padded to 64
+    float *d_lam = nullptr;      // lambda_lm(z_p) FP32, rows [m][pair][l - m] padded to 128
     long *d_loff = nullptr;      // [nm] offset of m's rows
     int *d_Lp = nullptr;         // [nm] padded row length
     int *d_minls32 = nullptr;    // [nm][Rp/32] smallest start index in each 32-pair chunk
-    int *d_minls64 = nullptr;    // [nm][Rp/64] smallest start index in each 64-pair tile
-    int2 *d_ana_items = nullptr; // (m, l tile) work items of the analysis GEMM
-    int n_ana_items = 0;
+    int2 *d_ana_items = nullptr; // (m, 128-row l tile) work items of the analysis GEMM
+    int2 *d_syn_items = nullptr; // (m, 64-pair tile) work items of the synthesis GEMM
+    int *d_ana_tab = nullptr;    // [8][ana_per_xcd] item list of each XCD (-1 = none)
+    int *d_syn_tab = nullptr;    // [8][syn_per_xcd]
+    int ana_per_xcd = 0, syn_per_xcd = 0;
     int *d_lofi = nullptr;       // [nalm] l of each packed index
-    float *d_ph32 = nullptr;     // [nring][nm][C2] ring-Fourier, maps innermost
+    float2 *d_phf = nullptr;     // [B][nring][nm] ring-Fourier rows of the transforms
+    float *d_ph32 = nullptr;     // [nm][nring][C2] ring-Fourier, maps innermost
     float *d_a32 = nullptr;      // [nalm][C2] analysis output
     float *d_s32 = nullptr;      // [nalm][C2] synthesis input
 };
@@ -132,6 +135,11 @@ int launch_fluct_combine(const double *g1, const double *M, const double *ysh, d
 // ringfft.hip
 int launch_fft_fwd(const Plan &p, const double *maps, double2 *phase, int nb);
 int launch_fft_inv(const Plan &p, const double2 *phase, double *maps, int nb);
+// FP32 rows [map][ring][m]; with rho the input is the messenger field of Eq. (3) built from
+// rho, M and s = maps on the fly
+int launch_fft_fwd_f32(const Plan &p, const double *maps, const double *rho, double lam,
+                       float2 *phase, int nb);
+int launch_fft_inv_f32(const Plan &p, const float2 *phase, double *maps, int nb);
 int fft_class_shape(const Plan &p, int c, int &ept);  // threads per workgroup of class c
 size_t fft_class_lds(const Plan &p, int c);           // dynamic LDS bytes of class c
 
@@ -145,14 +153,13 @@ int leg_analysis_pairs_per_lane(int v);
 
 // batched.hip (FP32 form)
 int launch_lam_table(const Plan &p);
-int launch_fft_fwd_b(const Plan &p, const double *maps, int nb);
-int launch_fft_inv_b(const Plan &p, double *maps, int nb);
-int launch_gemm_analysis(const Plan &p, int nb);
+int launch_rows_to_cols(const Plan &p, int nb);  // d_phf -> d_ph32
+int launch_cols_to_rows(const Plan &p, int nb);  // d_ph32 -> d_phf
+int launch_gemm_analysis(const Plan &p, int nb, float *a_out, float *s_out, double scale_s,
+                         double lto);
 int launch_gemm_synthesis(const Plan &p, int nb);
-int launch_harmonic_b(const Plan &p, double scale, double lto, int nb);
 int launch_alm_to_cols(const Plan &p, const double2 *alm, float *x32, int nb, int mode);
 int launch_cols_to_alm(const Plan &p, const float *x32, double2 *alm, int nb, double scale);
-int batched_set_lds_limit(size_t bytes);
 
 // harmonic.hip
 enum HarmMode { kHarmWiener = 0, kHarmAnalysis = 1, kHarmInvSqrtC = 2, kHarmCopy = 3 };

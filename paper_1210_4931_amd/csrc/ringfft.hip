@@ -18,7 +18,10 @@
 // ("half shift"), e^{i m phi_0} = e^{i pi k / n} (-1)^q for m = k + q n, so each bin needs one
 // phase factor and its aliases only a sign.
 //
-// Ring-Fourier layout: [map][ring][m] complex, so both kernels stream contiguous rows.
+// Ring-Fourier layout: [map][ring][m] complex, so both kernels stream contiguous rows; the
+// values are FP64 (per-map path) or FP32 (batched form, which rounds once on the way to the
+// FP32 contractions; the transforms themselves always run in FP64).  The forward transform
+// can apply the messenger pixel update (Eq. 3) to its input as it reads it.
 // Pairs are launched in two classes by transform length: most pairs need at most half the
 // largest length (less LDS and fewer registers per thread, more workgroups per CU); the long
 // Bluestein transforms of the largest polar rings form the second class.
@@ -26,9 +29,20 @@
 
 namespace mfwf {
 
-template <int TPB, int EPT>
+__device__ __forceinline__ void put_c(double2 *q, double2 v) { *q = v; }
+__device__ __forceinline__ void put_c(float2 *q, double2 v) { *q = make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ double2 get_c(const double2 *q) { return *q; }
+__device__ __forceinline__ double2 get_c(const float2 *q) {
+    const float2 v = *q;
+    return make_double2(v.x, v.y);
+}
+
+// Forward transform of maps[b] (PIX = false) or of the messenger field of Eq. (3),
+// t = [lam tau rho + (1 - tau M) s] / [1 + (lam - 1) tau M], with s = maps[b], rho = rho[b].
+template <int TPB, int EPT, typename OutT, bool PIX>
 __global__ void __launch_bounds__(TPB)
-k_fft_fwd(const double *__restrict__ maps, double2 *__restrict__ phase,
+k_fft_fwd(const double *__restrict__ maps, const double *__restrict__ rho,
+          const double *__restrict__ M, double lam, double tau, OutT *__restrict__ phase,
           const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
           const double2 *__restrict__ twlo, const double2 *__restrict__ twhi, int ntwhi,
           int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
@@ -39,14 +53,23 @@ k_fft_fwd(const double *__restrict__ maps, double2 *__restrict__ phase,
     const int n = pf.nphi;
     const bool equator = (pf.startS == pf.startN);
     const Twiddles tw = load_twiddles(buf, fftlen_class, TPB, twlo, twhi, ntwhi);
-    const double *tN = maps + (long)b * npix + pf.startN;
-    const double *tS = maps + (long)b * npix + pf.startS;
+    const double lt = lam * tau, l1t = (lam - 1.0) * tau;
+    auto pix = [&](long i) {  // i: pixel index within the map
+        const double x = maps[(long)b * npix + i];
+        if constexpr (!PIX) {
+            return x;
+        } else {
+            const double m = M[i];
+            const double num = lt * rho[(long)b * npix + i] + (1.0 - tau * m) * x;
+            return (lam == 1.0) ? num : num / (1.0 + l1t * m);
+        }
+    };
     for (int j = threadIdx.x; j < n; j += TPB)
-        buf[j] = make_double2(tN[j], equator ? 0.0 : tS[j]);
+        buf[j] = make_double2(pix(pf.startN + j), equator ? 0.0 : pix(pf.startS + j));
     __syncthreads();
     ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
-    double2 *outN = phase + ((long)b * nring + p) * nm;
-    double2 *outS = phase + ((long)b * nring + (nring - 1 - p)) * nm;
+    OutT *outN = phase + ((long)b * nring + p) * nm;
+    OutT *outS = phase + ((long)b * nring + (nring - 1 - p)) * nm;
     for (int m = threadIdx.x; m <= lmax; m += TPB) {
         const int q = m / n, k = m - q * n;
         const int kr = (k == 0) ? 0 : n - k;
@@ -57,17 +80,17 @@ k_fft_fwd(const double *__restrict__ maps, double2 *__restrict__ phase,
         if (pf.half_shift) ph = cscale(cconj(half_bin_phase(k, n, tw, fftmax)), (q & 1) ? -1.0 : 1.0);
         // X_N = (X_k + conj X_{-k}) / 2,  X_S = (X_k - conj X_{-k}) / (2i)
         const double2 gN = make_double2(0.5 * (X.x + Y.x), 0.5 * (X.y + Y.y));
-        outN[m] = cmul(gN, ph);
+        put_c(outN + m, cmul(gN, ph));
         if (!equator) {
             const double2 gS = make_double2(0.5 * (X.y - Y.y), -0.5 * (X.x - Y.x));
-            outS[m] = cmul(gS, ph);
+            put_c(outS + m, cmul(gS, ph));
         }
     }
 }
 
-template <int TPB, int EPT>
+template <int TPB, int EPT, typename InT>
 __global__ void __launch_bounds__(TPB)
-k_fft_inv(const double2 *__restrict__ phase, double *__restrict__ maps,
+k_fft_inv(const InT *__restrict__ phase, double *__restrict__ maps,
           const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
           const double2 *__restrict__ twlo, const double2 *__restrict__ twhi, int ntwhi,
           int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
@@ -80,8 +103,8 @@ k_fft_inv(const double2 *__restrict__ phase, double *__restrict__ maps,
     double2 *partS = partN + TPB;
     const bool equator = (pf.startS == pf.startN);
     const Twiddles tw = load_twiddles(buf, fftlen_class, TPB, twlo, twhi, ntwhi);
-    const double2 *FN = phase + ((long)b * nring + p) * nm;
-    const double2 *FS = phase + ((long)b * nring + (nring - 1 - p)) * nm;
+    const InT *FN = phase + ((long)b * nring + p) * nm;
+    const InT *FS = phase + ((long)b * nring + (nring - 1 - p)) * nm;
 
     // Fold harmonics into bins: S(k) = sum_q sgn_q F(k + q n) over |k + q n| <= lmax with
     // F(-m) = conj F(m) and sgn_q = (-1)^q under a half shift; then B(k) = e^{i pi k/n} S(k).
@@ -98,14 +121,14 @@ k_fft_inv(const double2 *__restrict__ phase, double *__restrict__ maps,
             // m = k + q n >= 0, q = t, t + T, ...
             double sg = (t & 1) ? sgn_step : 1.0;
             for (int m = k + t * n; m <= lmax; m += T * n, sg *= sg_stride) {
-                sN = cadd(sN, cscale(FN[m], sg));
-                if (!equator) sS = cadd(sS, cscale(FS[m], sg));
+                sN = cadd(sN, cscale(get_c(FN + m), sg));
+                if (!equator) sS = cadd(sS, cscale(get_c(FS + m), sg));
             }
             // m = k + q n < 0, q = -1 - t, -1 - t - T, ...: F(m) = conj F(-m)
             sg = ((t + 1) & 1) ? sgn_step : 1.0;
             for (int mm = (t + 1) * n - k; mm <= lmax; mm += T * n, sg *= sg_stride) {
-                sN = cadd(sN, cscale(cconj(FN[mm]), sg));
-                if (!equator) sS = cadd(sS, cscale(cconj(FS[mm]), sg));
+                sN = cadd(sN, cscale(cconj(get_c(FN + mm)), sg));
+                if (!equator) sS = cadd(sS, cscale(cconj(get_c(FS + mm)), sg));
             }
         }
         if (T > 1) {
@@ -163,7 +186,9 @@ size_t fft_class_lds(const Plan &p, int c) {
     p.d_pfft, p.d_plist + p.fft_class_off[c], p.d_twlo, p.d_twhi, p.fft_ntwhi, p.fftmax,        \
         p.d_chirp, p.d_bhat, p.npix, p.nring, p.nm, p.lmax, p.fft_class_len[c]
 
-int launch_fft_fwd(const Plan &p, const double *maps, double2 *phase, int nb) {
+template <typename OutT, bool PIX>
+static int fwd_classes(const Plan &p, const double *maps, const double *rho, double lam,
+                       OutT *out, int nb) {
     for (int c = 1; c >= 0; c--) {  // long transforms first
         const int cnt = p.fft_class_count[c];
         if (cnt == 0) continue;
@@ -172,17 +197,18 @@ int launch_fft_fwd(const Plan &p, const double *maps, double2 *phase, int nb) {
         const dim3 grid(cnt, nb);
         const size_t lds = fft_class_lds(p, c);
         if (ept == 8)
-            hipLaunchKernelGGL((k_fft_fwd<256, 8>), grid, dim3(256), lds, p.stream, maps, phase, MFWF_FFT_ARGS(c));
+            hipLaunchKernelGGL((k_fft_fwd<256, 8, OutT, PIX>), grid, dim3(256), lds, p.stream, maps, rho, p.d_M, lam, p.tau, out, MFWF_FFT_ARGS(c));
         else if (tpb == 256)
-            hipLaunchKernelGGL((k_fft_fwd<256, 16>), grid, dim3(256), lds, p.stream, maps, phase, MFWF_FFT_ARGS(c));
+            hipLaunchKernelGGL((k_fft_fwd<256, 16, OutT, PIX>), grid, dim3(256), lds, p.stream, maps, rho, p.d_M, lam, p.tau, out, MFWF_FFT_ARGS(c));
         else
-            hipLaunchKernelGGL((k_fft_fwd<512, 16>), grid, dim3(512), lds, p.stream, maps, phase, MFWF_FFT_ARGS(c));
+            hipLaunchKernelGGL((k_fft_fwd<512, 16, OutT, PIX>), grid, dim3(512), lds, p.stream, maps, rho, p.d_M, lam, p.tau, out, MFWF_FFT_ARGS(c));
         MFWF_HIP(hipGetLastError());
     }
     return MFWF_OK;
 }
 
-int launch_fft_inv(const Plan &p, const double2 *phase, double *maps, int nb) {
+template <typename InT>
+static int inv_classes(const Plan &p, const InT *in, double *maps, int nb) {
     for (int c = 1; c >= 0; c--) {
         const int cnt = p.fft_class_count[c];
         if (cnt == 0) continue;
@@ -191,25 +217,61 @@ int launch_fft_inv(const Plan &p, const double2 *phase, double *maps, int nb) {
         const dim3 grid(cnt, nb);
         const size_t lds = fft_class_lds(p, c);
         if (ept == 8)
-            hipLaunchKernelGGL((k_fft_inv<256, 8>), grid, dim3(256), lds, p.stream, phase, maps, MFWF_FFT_ARGS(c));
+            hipLaunchKernelGGL((k_fft_inv<256, 8, InT>), grid, dim3(256), lds, p.stream, in, maps, MFWF_FFT_ARGS(c));
         else if (tpb == 256)
-            hipLaunchKernelGGL((k_fft_inv<256, 16>), grid, dim3(256), lds, p.stream, phase, maps, MFWF_FFT_ARGS(c));
+            hipLaunchKernelGGL((k_fft_inv<256, 16, InT>), grid, dim3(256), lds, p.stream, in, maps, MFWF_FFT_ARGS(c));
         else
-            hipLaunchKernelGGL((k_fft_inv<512, 16>), grid, dim3(512), lds, p.stream, phase, maps, MFWF_FFT_ARGS(c));
+            hipLaunchKernelGGL((k_fft_inv<512, 16, InT>), grid, dim3(512), lds, p.stream, in, maps, MFWF_FFT_ARGS(c));
         MFWF_HIP(hipGetLastError());
     }
     return MFWF_OK;
 }
 
+int launch_fft_fwd(const Plan &p, const double *maps, double2 *phase, int nb) {
+    return fwd_classes<double2, false>(p, maps, nullptr, 1.0, phase, nb);
+}
+
+int launch_fft_fwd_f32(const Plan &p, const double *maps, const double *rho, double lam,
+                       float2 *phase, int nb) {
+    if (rho) return fwd_classes<float2, true>(p, maps, rho, lam, phase, nb);
+    return fwd_classes<float2, false>(p, maps, nullptr, 1.0, phase, nb);
+}
+
+int launch_fft_inv(const Plan &p, const double2 *phase, double *maps, int nb) {
+    return inv_classes<double2>(p, phase, maps, nb);
+}
+
+int launch_fft_inv_f32(const Plan &p, const float2 *phase, double *maps, int nb) {
+    return inv_classes<float2>(p, phase, maps, nb);
+}
+
 int fft_max_length() { return 16 * 512; }
 
 // Maximum dynamic LDS the FFT kernels may request (set once per process).
-int fft_set_lds_limit(size_t bytes) {
-    const void *fns[] = {(const void *)k_fft_fwd<256, 8>, (const void *)k_fft_fwd<256, 16>,
-                         (const void *)k_fft_fwd<512, 16>, (const void *)k_fft_inv<256, 8>,
-                         (const void *)k_fft_inv<256, 16>, (const void *)k_fft_inv<512, 16>};
+template <typename OutT, bool PIX>
+static int fwd_lds(int bytes) {
+    const void *fns[] = {(const void *)k_fft_fwd<256, 8, OutT, PIX>,
+                         (const void *)k_fft_fwd<256, 16, OutT, PIX>,
+                         (const void *)k_fft_fwd<512, 16, OutT, PIX>};
     for (const void *f : fns)
-        MFWF_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+        MFWF_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    return MFWF_OK;
+}
+template <typename InT>
+static int inv_lds(int bytes) {
+    const void *fns[] = {(const void *)k_fft_inv<256, 8, InT>, (const void *)k_fft_inv<256, 16, InT>,
+                         (const void *)k_fft_inv<512, 16, InT>};
+    for (const void *f : fns)
+        MFWF_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    return MFWF_OK;
+}
+
+int fft_set_lds_limit(size_t bytes) {
+    MFWF_TRY((fwd_lds<double2, false>((int)bytes)));
+    MFWF_TRY((fwd_lds<float2, false>((int)bytes)));
+    MFWF_TRY((fwd_lds<float2, true>((int)bytes)));
+    MFWF_TRY(inv_lds<double2>((int)bytes));
+    MFWF_TRY(inv_lds<float2>((int)bytes));
     return MFWF_OK;
 }
 
