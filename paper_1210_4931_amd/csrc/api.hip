@@ -568,8 +568,7 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     if (fftmax > fft_max_length())
         return fail(MFWF_EINVAL, "ring FFT length " + std::to_string(fftmax) + " above the supported " +
                                      std::to_string(fft_max_length()));
-    // FFT area + alias partials + twiddle tables of the largest class
-    const size_t lds = sizeof(double2) * ((size_t)fftmax + 1024 + 64 + p.fft_ntwhi);
+    const size_t lds = std::max(fft_class_lds(p, 0), fft_class_lds(p, 1));
     {
         int dev = 0, maxlds = 0;
         MFWF_HIP(hipGetDevice(&dev));

@@ -253,7 +253,7 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
                  const float *__restrict__ s32, const long *__restrict__ mofs,
                  float *__restrict__ ph32, int lmax, int npair, int Rp, int nring, int nm,
                  int C2, int ncols, int ncg) {
-    __shared__ float sl[64][64 + 4];            // lambda tile [pair][l]
+    __shared__ float sl[64][64 + 1];            // lambda tile [pair][l] (odd stride: no bank conflicts)
     __shared__ float ss[64][kColTile + 4];      // coefficient tile [l][col]
     const XcdTile xt = xcd_tile(tab, per_xcd, ncg);
     if (xt.item < 0) return;
@@ -299,7 +299,10 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const int e = threadIdx.x + 256 * u, pp = e >> 4, c4 = e & 15;
-            *reinterpret_cast<float4 *>(&sl[pp][4 * c4]) = rl[u];
+            sl[pp][4 * c4] = rl[u].x;
+            sl[pp][4 * c4 + 1] = rl[u].y;
+            sl[pp][4 * c4 + 2] = rl[u].z;
+            sl[pp][4 * c4 + 3] = rl[u].w;
         }
 #pragma unroll
         for (int u = 0; u < 8; u++) {

@@ -23,6 +23,18 @@ __device__ __forceinline__ double2 cscale(double2 a, double s) {
 }
 __device__ __forceinline__ double2 mul_minus_i(double2 a) { return make_double2(a.y, -a.x); }
 
+// Transform element i lives at LDS slot i + i/8: one pad slot per 8 elements spreads the
+// strided butterfly writes of the first passes (element strides of 8 and 64) over all LDS
+// banks.
+__host__ __device__ __forceinline__ constexpr int lds_ix(int i) { return i + (i >> 3); }
+
+// Transform slots of a workgroup with TPB threads and transforms up to fftlen: the padded
+// transform, and at least room for the inverse transform's alias-sum partials (2 TPB
+// slots after the padded first TPB/2 elements, used only for rings of n <= TPB/2).
+__host__ __device__ __forceinline__ constexpr int fft_area(int fftlen, int tpb) {
+    return lds_ix(fftlen) > lds_ix(tpb / 2) + 2 * tpb ? lds_ix(fftlen) : lds_ix(tpb / 2) + 2 * tpb;
+}
+
 // W_N^t = exp(-2 pi i t / N) for the plan's largest transform length N, as
 // hi[t / 64] * lo[t % 64] from two short tables held in LDS.
 struct Twiddles {
@@ -30,11 +42,11 @@ struct Twiddles {
     __device__ __forceinline__ double2 operator()(int t) const { return cmul(hi[t >> 6], lo[t & 63]); }
 };
 
-// Dynamic LDS of one ring-transform workgroup: [fftlen][2 TPB partials][64 lo][N/64 hi].
-__device__ __forceinline__ Twiddles load_twiddles(double2 *lds, int fftlen, int tpb,
+// Dynamic LDS of one ring-transform workgroup: [area transform slots][64 lo][N/64 hi].
+__device__ __forceinline__ Twiddles load_twiddles(double2 *lds, int area,
                                                   const double2 *__restrict__ glo,
                                                   const double2 *__restrict__ ghi, int nhi) {
-    double2 *lo = lds + fftlen + 2 * tpb, *hi = lo + 64;
+    double2 *lo = lds + area, *hi = lo + 64;
     for (int j = threadIdx.x; j < 64 + nhi; j += blockDim.x) {
         if (j < 64) lo[j] = glo[j];
         else hi[j - 64] = ghi[j - 64];
@@ -87,7 +99,7 @@ __device__ __forceinline__ void stockham_pass(double2 *buf, int n, int Ns, const
         const int j = threadIdx.x + b * TPB;
         if (j < nbf) {
 #pragma unroll
-            for (int r = 0; r < R; r++) v[b][r] = buf[j + r * nbf];
+            for (int r = 0; r < R; r++) v[b][r] = buf[lds_ix(j + r * nbf)];
         }
     }
     __syncthreads();
@@ -98,13 +110,18 @@ __device__ __forceinline__ void stockham_pass(double2 *buf, int n, int Ns, const
         if (j < nbf) {
             const int kk = j & (Ns - 1);
             if (Ns > 1) {
+                // one table twiddle w per butterfly; w^r as products (a few ulp in FP64)
+                double2 wr[R];
+                wr[1] = tw(kk * ts);
 #pragma unroll
-                for (int r = 1; r < R; r++) v[b][r] = cmul(v[b][r], tw(kk * r * ts));
+                for (int r = 2; r < R; r++) wr[r] = cmul(wr[r / 2], wr[r - r / 2]);
+#pragma unroll
+                for (int r = 1; r < R; r++) v[b][r] = cmul(v[b][r], wr[r]);
             }
             small_dft<R>(v[b]);
             const int base = (j - kk) * R + kk;
 #pragma unroll
-            for (int r = 0; r < R; r++) buf[base + r * Ns] = v[b][r];
+            for (int r = 0; r < R; r++) buf[lds_ix(base + r * Ns)] = v[b][r];
         }
     }
     __syncthreads();
@@ -129,8 +146,8 @@ __device__ __forceinline__ void fft_stockham(double2 *buf, int n, const Twiddles
     }
 }
 
-// Length-n forward DFT of buf[0..n) in place.  On return the transform value of bin k is
-// read with dft_bin(): buf[k] for power-of-two n, c_k conj(buf[k]) for Bluestein.
+// Length-n forward DFT of elements 0..n-1 in place.  On return the transform value of bin k
+// is read with dft_bin(): element k for power-of-two n, c_k conj(element k) for Bluestein.
 template <int TPB, int EPT>
 __device__ __forceinline__ void ring_dft(double2 *buf, const PairFFT &pf, const Twiddles &tw,
                                          int fftmax, const double2 *__restrict__ chirp,
@@ -142,19 +159,19 @@ __device__ __forceinline__ void ring_dft(double2 *buf, const PairFFT &pf, const 
     }
     const double2 *c = chirp + pf.chirp_off;
     for (int j = threadIdx.x; j < M; j += TPB)
-        buf[j] = (j < n) ? cmul(buf[j], c[j]) : make_double2(0.0, 0.0);
+        buf[lds_ix(j)] = (j < n) ? cmul(buf[lds_ix(j)], c[j]) : make_double2(0.0, 0.0);
     __syncthreads();
     fft_stockham<TPB, EPT>(buf, M, tw, fftmax);
     const double2 *bh = bhat + pf.bhat_off;  // transformed conj chirp, already divided by M
-    for (int j = threadIdx.x; j < M; j += TPB) buf[j] = cconj(cmul(buf[j], bh[j]));
+    for (int j = threadIdx.x; j < M; j += TPB) buf[lds_ix(j)] = cconj(cmul(buf[lds_ix(j)], bh[j]));
     __syncthreads();
     fft_stockham<TPB, EPT>(buf, M, tw, fftmax);
 }
 
 __device__ __forceinline__ double2 dft_bin(const double2 *buf, const PairFFT &pf,
                                            const double2 *__restrict__ chirp, int k) {
-    if (!pf.bluestein) return buf[k];
-    return cmul(chirp[pf.chirp_off + k], cconj(buf[k]));
+    if (!pf.bluestein) return buf[lds_ix(k)];
+    return cmul(chirp[pf.chirp_off + k], cconj(buf[lds_ix(k)]));
 }
 
 // e^{i pi k / n}: from the twiddle table when 2n divides the largest length, else sincospi

@@ -52,7 +52,7 @@ k_fft_fwd(const double *__restrict__ maps, const double *__restrict__ rho,
     const PairFFT pf = pfft[p];
     const int n = pf.nphi;
     const bool equator = (pf.startS == pf.startN);
-    const Twiddles tw = load_twiddles(buf, fftlen_class, TPB, twlo, twhi, ntwhi);
+    const Twiddles tw = load_twiddles(buf, fft_area(fftlen_class, TPB), twlo, twhi, ntwhi);
     const double lt = lam * tau, l1t = (lam - 1.0) * tau;
     auto pix = [&](long i) {  // i: pixel index within the map
         const double x = maps[(long)b * npix + i];
@@ -65,7 +65,7 @@ k_fft_fwd(const double *__restrict__ maps, const double *__restrict__ rho,
         }
     };
     for (int j = threadIdx.x; j < n; j += TPB)
-        buf[j] = make_double2(pix(pf.startN + j), equator ? 0.0 : pix(pf.startS + j));
+        buf[lds_ix(j)] = make_double2(pix(pf.startN + j), equator ? 0.0 : pix(pf.startS + j));
     __syncthreads();
     ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
     OutT *outN = phase + ((long)b * nring + p) * nm;
@@ -99,10 +99,11 @@ k_fft_inv(const InT *__restrict__ phase, double *__restrict__ maps,
     const int p = plist[blockIdx.x], b = blockIdx.y;
     const PairFFT pf = pfft[p];
     const int n = pf.nphi;
-    double2 *partN = buf + fftlen_class;  // [TPB] alias-sum partials after the FFT area
+    // alias-sum partials, used only with T > 1, i.e. n <= TPB / 2: after element TPB / 2
+    double2 *partN = buf + lds_ix(TPB / 2);
     double2 *partS = partN + TPB;
     const bool equator = (pf.startS == pf.startN);
-    const Twiddles tw = load_twiddles(buf, fftlen_class, TPB, twlo, twhi, ntwhi);
+    const Twiddles tw = load_twiddles(buf, fft_area(fftlen_class, TPB), twlo, twhi, ntwhi);
     const InT *FN = phase + ((long)b * nring + p) * nm;
     const InT *FS = phase + ((long)b * nring + (nring - 1 - p)) * nm;
 
@@ -150,7 +151,7 @@ k_fft_inv(const InT *__restrict__ phase, double *__restrict__ maps,
                 sS = cmul(sS, ph);
             }
             // x_j = sum_k X_k e^{+2 pi i j k/n} = conj(DFT(conj X))_j with X = B_N + i B_S
-            buf[k] = cconj(make_double2(sN.x - sS.y, sN.y + sS.x));
+            buf[lds_ix(k)] = cconj(make_double2(sN.x - sS.y, sN.y + sS.x));
         }
     }
     __syncthreads();
@@ -179,7 +180,7 @@ int fft_class_shape(const Plan &p, int c, int &ept) {
 size_t fft_class_lds(const Plan &p, int c) {
     int ept;
     const int tpb = fft_class_shape(p, c, ept);
-    return sizeof(double2) * ((size_t)p.fft_class_len[c] + 2 * tpb + 64 + p.fft_ntwhi);
+    return sizeof(double2) * ((size_t)fft_area(p.fft_class_len[c], tpb) + 64 + p.fft_ntwhi);
 }
 
 #define MFWF_FFT_ARGS(c)                                                                        \
