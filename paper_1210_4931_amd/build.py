@@ -39,11 +39,34 @@ def torch_lib_dir() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *HIPFLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *HIPFLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj,
+           "-Rpass-analysis=kernel-resource-usage"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr))
+    # per-kernel register, LDS and scratch figures of the compiler, kept next to the objects
+    with open(os.path.join(BUILD, os.path.splitext(src)[0] + ".resources.txt"), "w") as f:
+        f.write("\n".join(l for l in r.stderr.splitlines() if "remark:" in l))
     return obj
+
+
+def resource_usage() -> dict:
+    """{kernel symbol: {field: value}} from the last build's compiler remarks."""
+    out = {}
+    for src in SOURCES:
+        path = os.path.join(BUILD, os.path.splitext(src)[0] + ".resources.txt")
+        if not os.path.exists(path):
+            continue
+        cur = None
+        for line in open(path):
+            body = line.split("remark:", 1)[1].strip()
+            if body.startswith("Function Name:"):
+                cur = body.split(":", 1)[1].strip().split()[0]
+                out[cur] = {}
+            elif cur and ":" in body:
+                k, v = body.split(":", 1)
+                out[cur][k.strip()] = v.strip().split()[0]
+    return out
 
 
 def build(verbose: bool = False) -> str:

@@ -19,6 +19,9 @@
 namespace mfwf {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+// Native 4-vectors for the prefetch registers: copies of the HIP float4 struct into LDS are
+// aggregate copies that keep the source array in scratch memory.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------------------
 // lambda table: one lane per ring pair, one workgroup per (pair tile of 64, m).
@@ -129,8 +132,11 @@ __device__ __forceinline__ XcdTile xcd_tile(const int *__restrict__ tab, int per
     return r;
 }
 
-__device__ __forceinline__ float4 f4add(float4 a, float4 b) { return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w); }
-__device__ __forceinline__ float4 f4sub(float4 a, float4 b) { return make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w); }
+__device__ __forceinline__ floatx4 ld4(const float *q) { return *reinterpret_cast<const floatx4 *>(q); }
+__device__ __forceinline__ void st4(float *q, floatx4 v) { *reinterpret_cast<floatx4 *>(q) = v; }
+// v if c, else zeros (a value select; a conditional load would become a load through a
+// selected pointer and force a stack copy)
+__device__ __forceinline__ floatx4 keep4(bool c, floatx4 v) { return c ? v : floatx4{0.f, 0.f, 0.f, 0.f}; }
 
 static constexpr int kAnaRows = 128;  // values of l per analysis tile
 static constexpr int kColTile = 128;  // columns per workgroup
@@ -147,8 +153,10 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
                 const double *__restrict__ cl, float *__restrict__ a_out,
                 float *__restrict__ s_out, double scale_s, double lto, int lmax, int npair,
                 int Rp, int nring, int nm, int C2, int ncols, int ncg) {
-    __shared__ float sl[32][kAnaRows + 4];       // lambda tile [pair][row]
-    __shared__ float sx[2][32][kColTile + 4];    // X_0, X_1 tiles [pair][col]
+    // lambda tile [pair][row] and X_0, X_1 tiles [pair][col]; reused by the epilogue
+    __shared__ __align__(16) float lds[32 * (kAnaRows + 4) + 2 * 32 * (kColTile + 4)];
+    float (*sl)[kAnaRows + 4] = reinterpret_cast<float (*)[kAnaRows + 4]>(lds);
+    float (*sx)[32][kColTile + 4] = reinterpret_cast<float (*)[32][kColTile + 4]>(lds + 32 * (kAnaRows + 4));
     const XcdTile xt = xcd_tile(tab, per_xcd, ncg);
     if (xt.item < 0) return;
     const int2 it = items[xt.item];
@@ -169,24 +177,21 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
             for (int r = 0; r < 16; r++) acc[a][b][r] = 0.f;
     const float *lrow = lam + loff[m] + kAnaRows * t;
     const bool wave_on = (kColTile * cg + 64 * ch) < ncols;
-    float4 rl[4], rn[4], rs[4];
-    auto load = [&](int pc) {
+    floatx4 rl[4], rn[4], rs[4];
+    auto load = [&](int pc) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const int e = threadIdx.x + 256 * u, pp = e >> 5, c4 = e & 31;
             const int p = 32 * pc + pp, col = kColTile * cg + 4 * c4;
-            rl[u] = *reinterpret_cast<const float4 *>(lrow + (long)p * L + 4 * c4);
-            float4 gn = make_float4(0.f, 0.f, 0.f, 0.f), gs = gn;
-            if (p < npair && col < ncols) {
-                gn = *reinterpret_cast<const float4 *>(ph32 + ((long)m * nring + p) * C2 + col);
-                if (nring - 1 - p != p)
-                    gs = *reinterpret_cast<const float4 *>(ph32 + ((long)m * nring + (nring - 1 - p)) * C2 + col);
-            }
-            rn[u] = gn;
-            rs[u] = gs;
+            rl[u] = ld4(lrow + (long)p * L + 4 * c4);
+            // loads from clamped in-range addresses, then a value select
+            const bool on = p < npair && col < ncols, south = on && (nring - 1 - p != p);
+            const int pq = min(p, npair - 1), cq = min(col, ncols - 4);
+            rn[u] = keep4(on, ld4(ph32 + ((long)m * nring + pq) * C2 + cq));
+            rs[u] = keep4(south, ld4(ph32 + ((long)m * nring + (nring - 1 - pq)) * C2 + cq));
         }
     };
-    auto next_active = [&](int pc) {
+    auto next_active = [&](int pc) __attribute__((always_inline)) {
         while (pc < nchunk && ms[pc] > lhi) pc++;
         return pc;
     };
@@ -197,9 +202,9 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const int e = threadIdx.x + 256 * u, pp = e >> 5, c4 = e & 31;
-            *reinterpret_cast<float4 *>(&sl[pp][4 * c4]) = rl[u];
-            *reinterpret_cast<float4 *>(&sx[0][pp][4 * c4]) = f4add(rn[u], rs[u]);
-            *reinterpret_cast<float4 *>(&sx[1][pp][4 * c4]) = f4sub(rn[u], rs[u]);
+            st4(&sl[pp][4 * c4], rl[u]);
+            st4(&sx[0][pp][4 * c4], rn[u] + rs[u]);
+            st4(&sx[1][pp][4 * c4], rn[u] - rs[u]);
         }
         __syncthreads();
         const int pn = next_active(pc + 1);
@@ -220,41 +225,52 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
         }
         pc = pn;
     }
-    if (!wave_on) return;
+    // Epilogue through LDS: per column half, every wave parks its 64 rows x 32 columns
+    // ([row][36]) and stores whole 128-byte row segments with 16-byte stores.
     const long base = mofs[m] - m;
+    float (*stage)[36] = reinterpret_cast<float (*)[36]>(lds) + 64 * w;
 #pragma unroll
     for (int ct = 0; ct < 2; ct++) {
-        const int col = kColTile * cg + 64 * ch + 32 * ct + (lane & 31);
-        if (col >= ncols) continue;
+        __syncthreads();
 #pragma unroll
         for (int r = 0; r < 16; r++)
 #pragma unroll
-            for (int par = 0; par < 2; par++) {
-                const int l = m + kAnaRows * t + 64 * lh + 2 * acc_row(r, lane) + par;
-                if (l > lmax) continue;
-                const float v = acc[par][ct][r];
-                const long idx = (base + l) * C2 + col;
-                if (a_out) a_out[idx] = v;
-                if (s_out) {
-                    const double C = cl[l];
-                    const double f = C > 0.0 ? C / (C + lto) * scale_s : 0.0;
-                    s_out[idx] = (float)(f * (double)v);
-                }
+            for (int par = 0; par < 2; par++) stage[2 * acc_row(r, lane) + par][lane & 31] = acc[par][ct][r];
+        __syncthreads();
+        const int col = kColTile * cg + 64 * ch + 32 * ct + 4 * (lane & 7);
+        if (!wave_on || col >= ncols) continue;
+#pragma unroll
+        for (int it = 0; it < 8; it++) {
+            const int row = 8 * it + (lane >> 3);
+            const int l = m + kAnaRows * t + 64 * lh + row;
+            if (l > lmax) continue;
+            const float4 v = *reinterpret_cast<const float4 *>(&stage[row][4 * (lane & 7)]);
+            const long idx = (base + l) * C2 + col;
+            if (a_out) *reinterpret_cast<float4 *>(a_out + idx) = v;
+            if (s_out) {
+                const double C = cl[l];
+                const double f = C > 0.0 ? C / (C + lto) * scale_s : 0.0;
+                *reinterpret_cast<float4 *>(s_out + idx) =
+                    make_float4((float)(f * v.x), (float)(f * v.y), (float)(f * v.z), (float)(f * v.w));
             }
+        }
     }
 }
 
 // synthesis: tile = (m, 64 ring pairs, 128 columns); K loop over chunks of 64 values of l.
 // Wave w: pairs 32 (w & 1) .. +31 of the tile, columns 64 (w >> 1) .. +63.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 3)
 k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
                  const int *__restrict__ Lp, const int *__restrict__ minls32,
                  const int2 *__restrict__ items, const int *__restrict__ tab, int per_xcd,
                  const float *__restrict__ s32, const long *__restrict__ mofs,
                  float *__restrict__ ph32, int lmax, int npair, int Rp, int nring, int nm,
                  int C2, int ncols, int ncg) {
-    __shared__ float sl[64][64 + 1];            // lambda tile [pair][l] (odd stride: no bank conflicts)
-    __shared__ float ss[64][kColTile + 4];      // coefficient tile [l][col]
+    // lambda tile [pair][l] (odd stride: no bank conflicts) and coefficient tile [l][col];
+    // reused by the epilogue
+    __shared__ __align__(16) float lds[64 * (64 + 1) + 64 * (kColTile + 4)];
+    float (*sl)[64 + 1] = reinterpret_cast<float (*)[64 + 1]>(lds);
+    float (*ss)[kColTile + 4] = reinterpret_cast<float (*)[kColTile + 4]>(lds + 64 * (64 + 1));
     const XcdTile xt = xcd_tile(tab, per_xcd, ncg);
     if (xt.item < 0) return;
     const int2 it = items[xt.item];
@@ -275,20 +291,18 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
             for (int r = 0; r < 16; r++) acc[a][b][r] = 0.f;
     const float *lrow = lam + loff[m] + (long)(64 * pt) * L;
     const long base = mofs[m];
-    float4 rl[4], rv[8];
-    auto load = [&](int rc) {
+    floatx4 rl[4], rv[8];
+    auto load = [&](int rc) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const int e = threadIdx.x + 256 * u, pp = e >> 4, c4 = e & 15;
-            rl[u] = *reinterpret_cast<const float4 *>(lrow + (long)pp * L + 64 * rc + 4 * c4);
+            rl[u] = ld4(lrow + (long)pp * L + 64 * rc + 4 * c4);
         }
 #pragma unroll
         for (int u = 0; u < 8; u++) {
             const int e = threadIdx.x + 256 * u, rr = e >> 5, c4 = e & 31;
             const int r = 64 * rc + rr, col = kColTile * cg + 4 * c4;
-            rv[u] = (r < Lm && col < ncols)
-                        ? *reinterpret_cast<const float4 *>(s32 + (base + r) * C2 + col)
-                        : make_float4(0.f, 0.f, 0.f, 0.f);
+            rv[u] = keep4(r < Lm && col < ncols, ld4(s32 + (base + min(r, Lm - 1)) * C2 + min(col, ncols - 4)));
         }
     };
     const int first = max(0, ls_tile - m) / 64;  // first chunk with a nonzero lambda
@@ -307,7 +321,7 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
 #pragma unroll
         for (int u = 0; u < 8; u++) {
             const int e = threadIdx.x + 256 * u, rr = e >> 5, c4 = e & 31;
-            *reinterpret_cast<float4 *>(&ss[rr][4 * c4]) = rv[u];
+            st4(&ss[rr][4 * c4], rv[u]);
         }
         __syncthreads();
         if (rc + 1 < nrc) load(rc + 1);
@@ -326,20 +340,32 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
             }
         }
     }
-    if (!wave_on) return;
-    // rows are relative l = m + r: parity of r equals parity of l + m
+    // Epilogue through LDS: per column half, every wave parks F_N = E + O and F_S = E - O
+    // of its 32 pairs x 32 columns ([2][pair][36]) and stores whole 128-byte row segments.
+    // Rows are relative l = m + r, so the parity of r equals the parity of l + m.
+    float (*stage)[32][36] = reinterpret_cast<float (*)[32][36]>(lds) + 2 * w;
 #pragma unroll
     for (int ct = 0; ct < 2; ct++) {
-        const int col = kColTile * cg + 64 * ch + 32 * ct + (lane & 31);
-        if (col >= ncols) continue;
+        __syncthreads();
 #pragma unroll
         for (int r = 0; r < 16; r++) {
-            const int p = 64 * pt + 32 * rt + acc_row(r, lane);
-            if (p >= npair) continue;
             const float E = acc[0][ct][r], O = acc[1][ct][r];
-            ph32[((long)m * nring + p) * C2 + col] = E + O;
-            const int rS = nring - 1 - p;
-            if (rS != p) ph32[((long)m * nring + rS) * C2 + col] = E - O;
+            stage[0][acc_row(r, lane)][lane & 31] = E + O;
+            stage[1][acc_row(r, lane)][lane & 31] = E - O;
+        }
+        __syncthreads();
+        const int col = kColTile * cg + 64 * ch + 32 * ct + 4 * (lane & 7);
+        if (!wave_on || col >= ncols) continue;
+#pragma unroll
+        for (int it = 0; it < 8; it++) {
+            const int q = 8 * it + (lane >> 3);  // 0..63: hemisphere q / 32, pair row q % 32
+            const int hs = q >> 5, row = q & 31;
+            const int p = 64 * pt + 32 * rt + row;
+            if (p >= npair) continue;
+            const int ring = hs ? nring - 1 - p : p;
+            if (hs && ring == p) continue;  // equator: one ring
+            const float4 v = *reinterpret_cast<const float4 *>(&stage[hs][row][4 * (lane & 7)]);
+            *reinterpret_cast<float4 *>(ph32 + ((long)m * nring + ring) * C2 + col) = v;
         }
     }
 }

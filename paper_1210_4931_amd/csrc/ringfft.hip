@@ -1,6 +1,6 @@
 // Ring phi steps of the SHT (Sect. 2.1 basis change; HEALPix rings, Gorski et al. 2005).
 //
-// One workgroup per (ring pair, map).  The north and south rings of a pair have the same
+// One workgroup per (map, ring pair).  The north and south rings of a pair have the same
 // length n and offset phi_0, so they travel together as one complex sequence
 // x = t_N + i t_S and one length-n complex DFT serves both.
 //
@@ -22,6 +22,8 @@
 // values are FP64 (per-map path) or FP32 (batched form, which rounds once on the way to the
 // FP32 contractions; the transforms themselves always run in FP64).  The forward transform
 // can apply the messenger pixel update (Eq. 3) to its input as it reads it.
+// Grid (map, pair): the workgroups of one ring pair run back to back, so the pair's chirp
+// tables and noise precision are fetched into L2 once for all maps.
 // Pairs are launched in two classes by transform length: most pairs need at most half the
 // largest length (less LDS and fewer registers per thread, more workgroups per CU); the long
 // Bluestein transforms of the largest polar rings form the second class.
@@ -48,7 +50,7 @@ k_fft_fwd(const double *__restrict__ maps, const double *__restrict__ rho,
           int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
           long npix, int nring, int nm, int lmax, int fftlen_class) {
     extern __shared__ double2 buf[];
-    const int p = plist[blockIdx.x], b = blockIdx.y;
+    const int p = plist[blockIdx.y], b = blockIdx.x;
     const PairFFT pf = pfft[p];
     const int n = pf.nphi;
     const bool equator = (pf.startS == pf.startN);
@@ -96,7 +98,7 @@ k_fft_inv(const InT *__restrict__ phase, double *__restrict__ maps,
           int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
           long npix, int nring, int nm, int lmax, int fftlen_class) {
     extern __shared__ double2 buf[];
-    const int p = plist[blockIdx.x], b = blockIdx.y;
+    const int p = plist[blockIdx.y], b = blockIdx.x;
     const PairFFT pf = pfft[p];
     const int n = pf.nphi;
     // alias-sum partials, used only with T > 1, i.e. n <= TPB / 2: after element TPB / 2
@@ -165,16 +167,13 @@ k_fft_inv(const InT *__restrict__ phase, double *__restrict__ maps,
     }
 }
 
-// (threads per workgroup, elements per thread) of a class: 2048 -> (256, 8),
-// 4096 -> (256, 16), 8192 -> (512, 16)
+// (threads per workgroup, elements per thread) of a class: 8 elements (one radix-8
+// butterfly per pass) per thread and as many threads as the length needs, so that a
+// workgroup of a long class still brings 8 to 16 waves.
 int fft_class_shape(const Plan &p, int c, int &ept) {
     const int len = p.fft_class_len[c];
-    if (len <= 2048) {
-        ept = 8;
-        return 256;
-    }
-    ept = 16;
-    return len <= 4096 ? 256 : 512;
+    ept = 8;
+    return len <= 2048 ? 256 : len / 8;
 }
 
 size_t fft_class_lds(const Plan &p, int c) {
@@ -195,14 +194,14 @@ static int fwd_classes(const Plan &p, const double *maps, const double *rho, dou
         if (cnt == 0) continue;
         int ept;
         const int tpb = fft_class_shape(p, c, ept);
-        const dim3 grid(cnt, nb);
+        const dim3 grid(nb, cnt);  // maps of one pair adjacent: its tables and M stay in L2
         const size_t lds = fft_class_lds(p, c);
-        if (ept == 8)
+        if (tpb == 256)
             hipLaunchKernelGGL((k_fft_fwd<256, 8, OutT, PIX>), grid, dim3(256), lds, p.stream, maps, rho, p.d_M, lam, p.tau, out, MFWF_FFT_ARGS(c));
-        else if (tpb == 256)
-            hipLaunchKernelGGL((k_fft_fwd<256, 16, OutT, PIX>), grid, dim3(256), lds, p.stream, maps, rho, p.d_M, lam, p.tau, out, MFWF_FFT_ARGS(c));
+        else if (tpb == 512)
+            hipLaunchKernelGGL((k_fft_fwd<512, 8, OutT, PIX>), grid, dim3(512), lds, p.stream, maps, rho, p.d_M, lam, p.tau, out, MFWF_FFT_ARGS(c));
         else
-            hipLaunchKernelGGL((k_fft_fwd<512, 16, OutT, PIX>), grid, dim3(512), lds, p.stream, maps, rho, p.d_M, lam, p.tau, out, MFWF_FFT_ARGS(c));
+            hipLaunchKernelGGL((k_fft_fwd<1024, 8, OutT, PIX>), grid, dim3(1024), lds, p.stream, maps, rho, p.d_M, lam, p.tau, out, MFWF_FFT_ARGS(c));
         MFWF_HIP(hipGetLastError());
     }
     return MFWF_OK;
@@ -215,14 +214,14 @@ static int inv_classes(const Plan &p, const InT *in, double *maps, int nb) {
         if (cnt == 0) continue;
         int ept;
         const int tpb = fft_class_shape(p, c, ept);
-        const dim3 grid(cnt, nb);
+        const dim3 grid(nb, cnt);  // maps of one pair adjacent: its tables and M stay in L2
         const size_t lds = fft_class_lds(p, c);
-        if (ept == 8)
+        if (tpb == 256)
             hipLaunchKernelGGL((k_fft_inv<256, 8, InT>), grid, dim3(256), lds, p.stream, in, maps, MFWF_FFT_ARGS(c));
-        else if (tpb == 256)
-            hipLaunchKernelGGL((k_fft_inv<256, 16, InT>), grid, dim3(256), lds, p.stream, in, maps, MFWF_FFT_ARGS(c));
+        else if (tpb == 512)
+            hipLaunchKernelGGL((k_fft_inv<512, 8, InT>), grid, dim3(512), lds, p.stream, in, maps, MFWF_FFT_ARGS(c));
         else
-            hipLaunchKernelGGL((k_fft_inv<512, 16, InT>), grid, dim3(512), lds, p.stream, in, maps, MFWF_FFT_ARGS(c));
+            hipLaunchKernelGGL((k_fft_inv<1024, 8, InT>), grid, dim3(1024), lds, p.stream, in, maps, MFWF_FFT_ARGS(c));
         MFWF_HIP(hipGetLastError());
     }
     return MFWF_OK;
@@ -246,22 +245,22 @@ int launch_fft_inv_f32(const Plan &p, const float2 *phase, double *maps, int nb)
     return inv_classes<float2>(p, phase, maps, nb);
 }
 
-int fft_max_length() { return 16 * 512; }
+int fft_max_length() { return 8 * 1024; }
 
 // Maximum dynamic LDS the FFT kernels may request (set once per process).
 template <typename OutT, bool PIX>
 static int fwd_lds(int bytes) {
     const void *fns[] = {(const void *)k_fft_fwd<256, 8, OutT, PIX>,
-                         (const void *)k_fft_fwd<256, 16, OutT, PIX>,
-                         (const void *)k_fft_fwd<512, 16, OutT, PIX>};
+                         (const void *)k_fft_fwd<512, 8, OutT, PIX>,
+                         (const void *)k_fft_fwd<1024, 8, OutT, PIX>};
     for (const void *f : fns)
         MFWF_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
     return MFWF_OK;
 }
 template <typename InT>
 static int inv_lds(int bytes) {
-    const void *fns[] = {(const void *)k_fft_inv<256, 8, InT>, (const void *)k_fft_inv<256, 16, InT>,
-                         (const void *)k_fft_inv<512, 16, InT>};
+    const void *fns[] = {(const void *)k_fft_inv<256, 8, InT>, (const void *)k_fft_inv<512, 8, InT>,
+                         (const void *)k_fft_inv<1024, 8, InT>};
     for (const void *f : fns)
         MFWF_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
     return MFWF_OK;

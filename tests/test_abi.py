@@ -58,3 +58,15 @@ def test_single_hip_runtime_in_process(lib):
     maps = open("/proc/self/maps").read()
     libs = {l.split()[-1] for l in maps.splitlines() if "libamdhip64" in l}
     assert len(libs) == 1, libs
+
+
+def test_no_kernel_uses_scratch_memory(lib):
+    """Every kernel keeps its working set in registers and LDS: a stack object (scratch) in
+    a hot loop turns register traffic into HBM traffic."""
+    from paper_1210_4931_amd import build
+    usage = build.resource_usage()
+    kernels = {k: v for k, v in usage.items() if k.startswith("_ZN4mfwf")}
+    assert kernels, "no resource report; build the library first"
+    bad = {k: v.get("ScratchSize [bytes/lane]") for k, v in kernels.items()
+           if v.get("ScratchSize [bytes/lane]", "0") != "0"}
+    assert not bad, bad
