@@ -30,20 +30,38 @@ PEAK_FP64_VALU = 256 * 4 * 16 * 2 * 2.4e9     # 78.6 TFLOP/s: CUs x SIMDs x lane
 PEAK_FP32_MFMA = 157.3e12                      # dense FP32 matrix-core peak
 KERNELS = ["pixel_update", "fft_fwd", "leg_analysis", "harmonic", "leg_synth", "fft_inv"]
 
+# HBM bytes per launch of the analysis GEMM (batched FP32 form, nside 512, lmax 1024, 64 maps)
+# from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the factors a 256 MiB copy gives
+# (x2.0 and x1.0): profiles/gemm_analysis_nside512_lmax1024_b64_hbm_traffic.md.  Valid only
+# for the kernel source they were taken on, identified by the SHA-256 of batched.hip.
+GEMM_TRAFFIC = {"bytes": 4.862e9,
+                "source_sha256": "9e156ef2eef3426aa6b60f49b21257cc37d765fbc38aca695cc24feb58ca8d3e"}
 
-def cpu_baseline(nside, lmax, iters_sample, wl, d_host, M):
-    """The FP64 oracle as it stands, all host cores, a bounded number of iterations."""
+
+def measured_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_1210_4931_amd", "csrc", "batched.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    return GEMM_TRAFFIC["bytes"] if h == GEMM_TRAFFIC["source_sha256"] else None
+
+
+def cpu_baseline(nside, lmax, K, wl, d_host, M):
+    """The FP64 oracle as it stands, all host cores: one solve with 1 and with 3 iterations;
+    the difference gives the cost of an iteration, the rest the set-up; extrapolated to K."""
     import oracle
     oracle.build()
     t0 = time.perf_counter()
-    oracle.solve(nside, lmax, wl.cl, M, M * d_host, niter=iters_sample)
-    dt = time.perf_counter() - t0
-    per_iter = dt / iters_sample
-    return {"value": 1.0 / (per_iter * 300.0), "unit": "solves/s", "cores": oracle.num_threads(),
+    oracle.solve(nside, lmax, wl.cl, M, M * d_host, niter=1)
+    t1 = time.perf_counter()
+    oracle.solve(nside, lmax, wl.cl, M, M * d_host, niter=3)
+    t2 = time.perf_counter()
+    per_iter = max((t2 - t1) - (t1 - t0), 1e-9) / 2.0
+    setup = max((t1 - t0) - per_iter, 0.0)
+    return {"value": 1.0 / (setup + K * per_iter), "unit": "solves/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": "%d of the 300 messenger iterations of one nside %d / lmax %d solve "
-                      "(%.1f s, FFT phi step), extrapolated to one solve" % (iters_sample, nside,
-                                                                           lmax, dt)}
+            "sample": "one solve of the nside %d / lmax %d problem with 1 and with 3 messenger "
+                      "iterations (%.1f s in all; %.2f s per iteration, %.2f s set-up), "
+                      "extrapolated to %d iterations" % (nside, lmax, t2 - t0, per_iter, setup, K)}
 
 
 def timed_solves(plan, d, K, steps, warmup, use_graph):
@@ -72,7 +90,6 @@ def main():
     ap.add_argument("--batch", type=int, default=64, help="maps per batched FP32 solve")
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--no-graph", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -152,14 +169,18 @@ def main():
         "iteration_ms": 1e3 * el32 / args.steps / K,
         "sht_pair_tflops": 2 * gemm_flops / (pair32 * 1e-3) / 1e12,
         "kernel_ms": kt32,
+        "fused": {"pixel_update": "inside fft_fwd", "harmonic": "inside leg_analysis",
+                  "note": "fft_fwd / fft_inv include the layout transposes to and from the "
+                          "matrix-core column layout"},
         "legendre_triples": {"evaluated": work, "full_triangle": full},
         "roofline": {"bound": "mfma", "kernel": "gemm_" + dom32.split("_")[1],
                      "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA, "traffic": None},
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
+                     "traffic": measured_traffic() if dom32 == "leg_analysis" else None},
         "fp64_single": fp64,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(nside, lmax, args.cpu_iters, wl, d1.cpu().numpy()[0],
+        out["cpu_baseline"] = cpu_baseline(nside, lmax, K, wl, d1.cpu().numpy()[0],
                                            wl.mask / wl.noise_var)
     print(json.dumps(out), flush=True)
 

@@ -49,7 +49,12 @@ typedef enum {
 
 typedef enum {
     MFWF_F64 = 0, /* every step in double precision                               */
-    MFWF_F32 = 1  /* reserved: single-precision bulk Legendre contraction          */
+    MFWF_F32 = 1  /* batched form: the Legendre contractions (Sect. 3's transform
+                     cost) run as FP32 matrix-core products over all maps of a call,
+                     from an FP32 table of lambda_lm; maps, the pixel update, the ring
+                     transforms, the harmonic filter's arithmetic and all norms stay
+                     FP64.  ~1e-7 relative error per transform, 8e-6 after 300
+                     iterations at nside 512 / lmax 1024                          */
 } mfwf_dtype;
 
 /*
@@ -60,7 +65,9 @@ typedef enum {
  * Gorski et al. 2005), the Legendre recurrence coefficients and, for every (m, ring
  * pair), the first l at which the normalised associated Legendre function exceeds 2^-100
  * together with its two starting values, and ring-FFT tables.  It allocates its device
- * workspaces up front.  *out receives the handle.
+ * workspaces up front (MFWF_F32 adds the FP32 lambda table, 4 bytes x ring pairs x
+ * (lmax+1)(lmax+2)/2 roughly: 2.2 GB at nside 512 / lmax 1024, and column-major work
+ * arrays for max_batch maps).  *out receives the handle.
  * Errors: MFWF_EINVAL for out-of-range sizes or spin != 0, MFWF_ENOMEM, MFWF_EDEVICE.
  */
 int mfwf_plan_create(int nside, int lmax, int spin, int dtype, int max_batch, void *hip_stream,
