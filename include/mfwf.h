@@ -125,6 +125,12 @@ typedef struct {
     double dchi2_tol;      /* reserved, must be 0: a fixed number of iterations is run   */
     int source_is_rho;     /* 0: input is the data d (rho = M d); 1: input is rho        */
     int use_graph;         /* 1: replay each iteration as a captured hipGraph            */
+    double *history;       /* host [history_rows][nmaps][5] or NULL: at every check,
+                              (iteration k, lambda, chi^2 of Eq. 6, |s_k - s_{k-1}|,
+                              |s_k|) per map; checks at k = n_check, 2 n_check, ... and
+                              at the last iteration; rows beyond history_rows are not
+                              written                                                    */
+    int history_rows;      /* capacity of history in rows                                */
 } mfwf_solve_opts;
 
 /* Per-map diagnostics after the last iteration (Eq. 6 and Sect. 2.2). */
@@ -137,6 +143,8 @@ typedef struct {
     double snorm;      /* |s_k|                                                        */
     double tau;        /* tau = 1 / max M                                              */
     long n_dof;        /* number of observed pixels (chi^2 degrees of freedom)          */
+    int n_checks;      /* diagnostic checks made (rows of opts->history filled, up to
+                          its capacity)                                                 */
 } mfwf_solve_info;
 
 /*

@@ -684,34 +684,37 @@ static int iteration(Plan &p, const double *rho, int nb, double lam, bool keep_p
     return MFWF_OK;
 }
 
-static int run_stage_graph(Plan &p, const double *rho, int nb, double lam, int count) {
-    if (count <= 0) return MFWF_OK;
+// One captured iteration of a stage, replayed as often as needed.
+struct StageGraph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    MFWF_HIP(hipStreamBeginCapture(p.stream, hipStreamCaptureModeThreadLocal));
-    int st = iteration(p, rho, nb, lam, false);
-    hipError_t e = hipStreamEndCapture(p.stream, &graph);
-    if (st != MFWF_OK) {
+    ~StageGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
-        return st;
     }
-    if (e != hipSuccess) return fail(MFWF_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        (void)hipGraphDestroy(graph);
-        return fail(MFWF_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    int capture(Plan &p, const double *rho, int nb, double lam) {
+        MFWF_HIP(hipStreamBeginCapture(p.stream, hipStreamCaptureModeThreadLocal));
+        int st = iteration(p, rho, nb, lam, false);
+        hipError_t e = hipStreamEndCapture(p.stream, &graph);
+        if (st != MFWF_OK) return st;
+        if (e != hipSuccess) return fail(MFWF_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return fail(MFWF_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+        return MFWF_OK;
     }
-    for (int k = 0; k < count && e == hipSuccess; k++) e = hipGraphLaunch(exec, p.stream);
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) return fail(MFWF_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
-    return MFWF_OK;
-}
+    int launch(Plan &p, int count) {
+        for (int k = 0; k < count; k++) {
+            hipError_t e = hipGraphLaunch(exec, p.stream);
+            if (e != hipSuccess) return fail(MFWF_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+        }
+        return MFWF_OK;
+    }
+};
 
 static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
                        double *s_map_out, const mfwf_solve_opts &o,
                        const std::vector<double> &lam, const std::vector<int> &its,
-                       mfwf_solve_info *info) {
+                       mfwf_solve_info *info, int hist_maps, int hist_b0) {
     const double *rho = input;
     if (!o.source_is_rho) {
         MFWF_TRY(launch_rho_from_data(input, p.d_M, p.d_rho, p.npix, nb, p.stream));
@@ -723,30 +726,60 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
         MFWF_HIP(hipMemsetAsync(p.d_s32, 0, sizeof(float) * (size_t)p.nalm * p.C2, p.stream));
     long total = 0;
     for (int it : its) total += it;
+    const long nchk = o.n_check > 0 ? o.n_check : 0;
     long done = 0;
+    int rows = 0;
     double last_lam = 1.0;
     const bool graph = o.use_graph && p.stream != nullptr;
-    for (size_t s = 0; s < lam.size(); s++) {
-        int n = its[s];
-        if (n <= 0) continue;
-        last_lam = lam[s];
-        const bool has_last = (done + n == total);
-        int plain = has_last ? n - 1 : n;
-        if (graph && plain >= 2) {
-            MFWF_TRY(run_stage_graph(p, rho, nb, lam[s], plain));
-        } else {
-            for (int k = 0; k < plain; k++) MFWF_TRY(iteration(p, rho, nb, lam[s], false));
-        }
-        if (has_last) MFWF_TRY(iteration(p, rho, nb, lam[s], true));
-        done += n;
-    }
-    if (total > 0) {
-        MFWF_TRY(launch_chi2_pix(rho, p.d_M, p.d_smap, p.npix, nb, last_lam, p.tau, p.d_red,
+    std::vector<double> dg(8L * nb);
+    auto diagnostics = [&](double lam_k) -> int {
+        MFWF_TRY(launch_chi2_pix(rho, p.d_M, p.d_smap, p.npix, nb, lam_k, p.tau, p.d_red,
                                  p.nred_blocks, p.d_diag, p.stream));
-        MFWF_TRY(launch_harm_diag(p, p.d_salm, p.d_salm_prev, nb, p.d_red, p.d_diag));
-    } else {
-        MFWF_TRY(launch_fill(p.d_diag, 8L * nb, 0.0, p.stream));
+        return launch_harm_diag(p, p.d_salm, p.d_salm_prev, nb, p.d_red, p.d_diag);
+    };
+    for (size_t s = 0; s < lam.size(); s++) {
+        long remaining = its[s];
+        if (remaining <= 0) continue;
+        last_lam = lam[s];
+        std::unique_ptr<StageGraph> sg;
+        while (remaining > 0) {
+            // run up to the next check point: a multiple of n_check, or the last iteration
+            const long next = nchk ? std::min(total, (done / nchk + 1) * nchk) : total;
+            const long run = std::min(remaining, next - done);
+            const bool check = (done + run == next);
+            const long plain = check ? run - 1 : run;
+            if (graph && plain >= 2) {
+                if (!sg) {
+                    sg.reset(new StageGraph());
+                    MFWF_TRY(sg->capture(p, rho, nb, lam[s]));
+                }
+                MFWF_TRY(sg->launch(p, (int)plain));
+            } else {
+                for (long k = 0; k < plain; k++) MFWF_TRY(iteration(p, rho, nb, lam[s], false));
+            }
+            if (check) {
+                MFWF_TRY(iteration(p, rho, nb, lam[s], true));
+                MFWF_TRY(diagnostics(lam[s]));
+                if (o.history && rows < o.history_rows) {
+                    MFWF_HIP(hipMemcpyAsync(dg.data(), p.d_diag, sizeof(double) * dg.size(),
+                                            hipMemcpyDeviceToHost, p.stream));
+                    MFWF_HIP(hipStreamSynchronize(p.stream));
+                    for (int b = 0; b < nb; b++) {
+                        double *row = o.history + ((long)rows * hist_maps + hist_b0 + b) * 5;
+                        row[0] = (double)(done + run);
+                        row[1] = lam[s];
+                        row[2] = dg[8 * b + 0] + dg[8 * b + 1];
+                        row[3] = std::sqrt(dg[8 * b + 2]);
+                        row[4] = std::sqrt(dg[8 * b + 3]);
+                    }
+                }
+                rows++;
+            }
+            done += run;
+            remaining -= run;
+        }
     }
+    if (total == 0) MFWF_TRY(launch_fill(p.d_diag, 8L * nb, 0.0, p.stream));
     if (s_alm_out)
         MFWF_HIP(hipMemcpyAsync(s_alm_out, p.d_salm, sizeof(double2) * p.nalm * nb,
                                 hipMemcpyDeviceToDevice, p.stream));
@@ -754,7 +787,6 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
         MFWF_HIP(hipMemcpyAsync(s_map_out, p.d_smap, sizeof(double) * p.npix * nb,
                                 hipMemcpyDeviceToDevice, p.stream));
     if (info) {
-        std::vector<double> dg(8L * nb);
         MFWF_HIP(hipMemcpyAsync(dg.data(), p.d_diag, sizeof(double) * dg.size(),
                                 hipMemcpyDeviceToHost, p.stream));
         MFWF_HIP(hipStreamSynchronize(p.stream));
@@ -768,6 +800,7 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
             in.snorm = std::sqrt(dg[8 * b + 3]);
             in.tau = p.tau;
             in.n_dof = p.ndof;
+            in.n_checks = std::min(rows, o.history ? o.history_rows : rows);
         }
     }
     return MFWF_OK;
@@ -916,6 +949,8 @@ int mfwf_solve(mfwf_plan plan, const double *input, int nmaps, double *s_alm_out
         o = *opts;
         if (o.dchi2_tol != 0.0) return fail(MFWF_EINVAL, "dchi2_tol must be 0 (fixed schedules only)");
         if (o.n_stages < 0) return fail(MFWF_EINVAL, "n_stages < 0");
+        if (o.n_check < 0) return fail(MFWF_EINVAL, "n_check < 0");
+        if (o.history && o.history_rows < 0) return fail(MFWF_EINVAL, "history_rows < 0");
         if (o.n_stages > 0) {
             if (!o.lambda || !o.iters) return fail(MFWF_EINVAL, "schedule arrays are NULL");
             lam.assign(o.lambda, o.lambda + o.n_stages);
@@ -930,7 +965,7 @@ int mfwf_solve(mfwf_plan plan, const double *input, int nmaps, double *s_alm_out
         MFWF_TRY(solve_chunk(p, input + (long)b0 * p.npix, nb,
                              s_alm_out ? s_alm_out + 2L * b0 * p.nalm : nullptr,
                              s_map_out ? s_map_out + (long)b0 * p.npix : nullptr, o, lam, its,
-                             info ? info + b0 : nullptr));
+                             info ? info + b0 : nullptr, nmaps, b0));
     }
     MFWF_HIP(hipStreamSynchronize(p.stream));
     return MFWF_OK;

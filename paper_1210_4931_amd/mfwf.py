@@ -26,13 +26,15 @@ class SolveOpts(ctypes.Structure):
     _fields_ = [("n_stages", ctypes.c_int), ("lam", ctypes.POINTER(ctypes.c_double)),
                 ("iters", ctypes.POINTER(ctypes.c_int)), ("n_check", ctypes.c_int),
                 ("dchi2_tol", ctypes.c_double), ("source_is_rho", ctypes.c_int),
-                ("use_graph", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("history", ctypes.POINTER(ctypes.c_double)),
+                ("history_rows", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iters_done", ctypes.c_int), ("lam", ctypes.c_double), ("chi2", ctypes.c_double),
                 ("chi2_harm", ctypes.c_double), ("dnorm", ctypes.c_double),
-                ("snorm", ctypes.c_double), ("tau", ctypes.c_double), ("n_dof", ctypes.c_long)]
+                ("snorm", ctypes.c_double), ("tau", ctypes.c_double), ("n_dof", ctypes.c_long),
+                ("n_checks", ctypes.c_int)]
 
 
 EXPORTED = ["mfwf_plan_create", "mfwf_plan_destroy", "mfwf_set_covariances", "mfwf_sht_inv",
@@ -96,6 +98,7 @@ class Info:
     snorm: float
     tau: float
     n_dof: int
+    n_checks: int = 0
 
 
 class Plan:
@@ -186,16 +189,24 @@ class Plan:
         return out
 
     def solve(self, inp: torch.Tensor, lam=None, iters=None, source_is_rho=False,
-              use_graph=True, out_alm=None, out_map=None, want_map=True):
+              use_graph=True, out_alm=None, out_map=None, want_map=True, n_check=0):
         """Messenger iteration.  lam/iters: per-stage schedule (default lambda 1, 300 its).
-        Returns (s_alm [n, nalm] complex128, s_map [n, npix] or None, [Info] * n)."""
+        Returns (s_alm [n, nalm] complex128, s_map [n, npix] or None, [Info] * n); with
+        n_check > 0 a fourth item, the diagnostics history as a numpy array
+        [checks][n][5] of (iteration, lambda, chi^2, |s_k - s_{k-1}|, |s_k|)."""
+        import numpy as np
         n = inp.shape[0] if inp.dim() == 2 else 1
         x = _dev_f64(inp, (n, self.npix))
         if lam is None:
             lam, iters = [1.0], [300 if iters is None else int(iters)]
         lam_a = (ctypes.c_double * len(lam))(*[float(v) for v in lam])
         it_a = (ctypes.c_int * len(iters))(*[int(v) for v in iters])
-        opts = SolveOpts(len(lam), lam_a, it_a, 0, 0.0, int(bool(source_is_rho)), int(bool(use_graph)))
+        total = sum(int(v) for v in iters)
+        rows = (total // n_check + 1) if n_check > 0 else 0
+        hist = np.zeros((rows, n, 5)) if rows else None
+        hptr = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if rows else None
+        opts = SolveOpts(len(lam), lam_a, it_a, int(n_check), 0.0, int(bool(source_is_rho)),
+                         int(bool(use_graph)), hptr, rows)
         s_alm = self.zeros_alm(n) if out_alm is None else out_alm
         s_map = (self.zeros_map(n) if out_map is None else out_map) if want_map else None
         infos = (SolveInfo * n)()
@@ -204,8 +215,10 @@ class Plan:
                                None if s_map is None else s_map.data_ptr(), ctypes.byref(opts),
                                infos))
         self._leave()
-        info = [Info(i.iters_done, i.lam, i.chi2, i.chi2_harm, i.dnorm, i.snorm, i.tau, i.n_dof)
-                for i in infos]
+        info = [Info(i.iters_done, i.lam, i.chi2, i.chi2_harm, i.dnorm, i.snorm, i.tau, i.n_dof,
+                     i.n_checks) for i in infos]
+        if n_check > 0:
+            return s_alm, s_map, info, hist[:infos[0].n_checks] if n else hist
         return s_alm, s_map, info
 
     def work(self):

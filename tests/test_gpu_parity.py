@@ -97,6 +97,32 @@ def test_solve_lambda_schedule_parity(mf):
     assert info[0].lam == 1.0 and info[0].iters_done == 40
 
 
+def test_periodic_diagnostics_history(mf):
+    """Checks every n_check iterations (across a change of lambda) against the oracle's
+    per-iteration chi^2 of Eq. (6), |s_k - s_{k-1}| and |s_k|; checks do not change the
+    iterate, with or without graph replay."""
+    nside, lmax = 16, 40
+    plan, wl, d, M = _setup(mf, nside, lmax)
+    rng = np.random.default_rng(9)
+    ds = np.stack([d, d + rng.standard_normal(d.size) * np.sqrt(wl.noise_var)])
+    lam, its = [3.0, 1.0], [25, 20]
+    s_alm, _, info, hist = plan.solve(dev(ds), lam=lam, iters=its, n_check=7)
+    ks = [7, 14, 21, 28, 35, 42, 45]
+    assert hist.shape == (len(ks), 2, 5) and info[0].n_checks == len(ks)
+    sched = np.repeat(lam, its)
+    for b in range(2):
+        _, _, dg = oracle.solve(nside, lmax, wl.cl, M, M * ds[b], lam=sched, diag=True)
+        for r, k in enumerate(ks):
+            assert hist[r, b, 0] == k and hist[r, b, 1] == sched[k - 1]
+            assert hist[r, b, 2] == pytest.approx(dg[k - 1, 0], rel=1e-9)
+            assert hist[r, b, 3] == pytest.approx(dg[k - 1, 2], rel=1e-6)
+            assert hist[r, b, 4] == pytest.approx(dg[k - 1, 3], rel=1e-9)
+    plain, _, _ = plan.solve(dev(ds), lam=lam, iters=its)
+    eager, _, _, hist_e = plan.solve(dev(ds), lam=lam, iters=its, n_check=7, use_graph=False)
+    assert torch.equal(s_alm, plain) and torch.equal(s_alm, eager)
+    assert np.array_equal(hist, hist_e)
+
+
 def test_graph_replay_equals_eager_bitwise(mf):
     nside, lmax = 16, 32
     plan, wl, d, M = _setup(mf, nside, lmax)
