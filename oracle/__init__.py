@@ -1,9 +1,10 @@
-"""Plain FP64 CPU oracle for the messenger-field Wiener filter.
+"""Plain FP64 CPU oracle for the messenger-field Wiener filter (temperature and T, Q, U).
 
 TEST INFRASTRUCTURE.  Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline
 leg of ``bench.py`` may import this package.  It shares no code with the HIP library: the
-C file ``mfwf_oracle.c`` re-derives geometry, Legendre functions, phi transforms, the SHT,
-the messenger iteration and chi^2 from the paper and textbook definitions, and
+C file ``mfwf_oracle.c`` re-derives geometry, Legendre and spin-2 functions, phi transforms,
+the spin-0 and polarized SHT, the messenger iteration (temperature and T, Q, U with 3x3
+noise blocks), chi^2 and the fluctuation sources from the paper and textbook definitions, and
 ``dense.py`` builds explicit matrices at tiny sizes from SciPy's spherical harmonics.
 
 Array conventions: maps are HEALPix RING order float64; alm are complex128, m-major
@@ -58,6 +59,14 @@ def lib():
                                ctypes.c_int, _dp, _dp, _dp]
         L.or_fluct_rho.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp,
                                    ctypes.c_int]
+        L.or_spin2.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp,
+                               _dp]
+        L.or_alm2map_pol.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int]
+        L.or_map2alm_pol.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, ctypes.c_int]
+        L.or_solve_pol.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, ctypes.c_double,
+                                   ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, _dp]
+        L.or_fluct_rho_pol.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp,
+                                       ctypes.c_int]
         _lib_handle = L
     return _lib_handle
 
@@ -181,4 +190,76 @@ def fluct_rho(nside, lmax, cl, M, g1, h, direct=False):
     out = np.zeros(12 * nside * nside)
     lib().or_fluct_rho(nside, lmax, _p(cl), _p(M), _p(g1), _p(h.view(np.float64)), _p(out),
                        int(direct))
+    return out
+
+
+# ---- polarization (T, Q, U maps [3][npix]; T, E, B alm [3][nalm]) -------------------------
+
+def spin2(lmax, m, z, sth=None):
+    """(F+, F-) for l = m..lmax at z: F+- = (2lambda_lm +- (-2)lambda_lm) / 2."""
+    if sth is None:
+        sth = np.sqrt((1.0 - z) * (1.0 + z))
+    fp, fm = np.zeros(lmax - m + 1), np.zeros(lmax - m + 1)
+    lib().or_spin2(lmax, m, float(z), float(sth), _p(fp), _p(fm))
+    return fp, fm
+
+
+def alm2map_pol(nside, lmax, alm, direct=False):
+    """(T, E, B) alm [3][nalm] -> (T, Q, U) maps [3][npix]."""
+    alm = _c128(alm)
+    assert alm.shape == (3, nalm(lmax))
+    out = np.zeros((3, 12 * nside * nside))
+    lib().or_alm2map_pol(nside, lmax, _p(alm.view(np.float64)), _p(out), int(direct))
+    return out
+
+
+def map2alm_pol(nside, lmax, maps, direct=False):
+    """(T, Q, U) maps -> (T, E, B) alm with the analysis Omega Y^T."""
+    maps = _f64(maps)
+    assert maps.shape == (3, 12 * nside * nside)
+    out = np.zeros((3, nalm(lmax)), dtype=np.complex128)
+    lib().or_map2alm_pol(nside, lmax, _p(maps), _p(out.view(np.float64)), int(direct))
+    return out
+
+
+def tau_pol(M6):
+    """tau = 1 / max_p lambda_max(M_p) over the packed 3x3 blocks [npix][6] (0 if none)."""
+    M6 = _f64(M6)
+    A = np.empty((M6.shape[0], 3, 3))
+    A[:, 0, 0], A[:, 0, 1], A[:, 0, 2] = M6[:, 0], M6[:, 1], M6[:, 2]
+    A[:, 1, 0], A[:, 1, 1], A[:, 1, 2] = M6[:, 1], M6[:, 3], M6[:, 4]
+    A[:, 2, 0], A[:, 2, 1], A[:, 2, 2] = M6[:, 2], M6[:, 4], M6[:, 5]
+    mx = np.linalg.eigvalsh(A)[:, -1].max()
+    return 1.0 / mx if mx > 0 else 0.0
+
+
+def solve_pol(nside, lmax, cl4, M6, rho, niter=None, lam=None, direct=False, diag=False):
+    """Messenger iteration with T, Q, U.  cl4 [4][lmax+1] = TT, EE, BB, TE; M6 [npix][6]
+    packed inverse noise blocks; rho [3][npix].  Returns (s_alm [3][nalm], s_map [3][npix]
+    [, diag[niter, 4]])."""
+    if lam is None:
+        lam = np.ones(niter)
+    lam = _f64(lam)
+    niter = len(lam)
+    cl4, M6, rho = _f64(cl4), _f64(M6), _f64(rho)
+    npix = 12 * nside * nside
+    assert cl4.shape == (4, lmax + 1) and M6.shape == (npix, 6) and rho.shape == (3, npix)
+    tau = tau_pol(M6)
+    s_alm = np.zeros((3, nalm(lmax)), dtype=np.complex128)
+    s_map = np.zeros((3, npix))
+    dg = np.zeros((niter, 4)) if diag else None
+    rc = lib().or_solve_pol(nside, lmax, _p(cl4), _p(M6), _p(rho), tau, niter, _p(lam),
+                            int(direct), _p(s_alm.view(np.float64)), _p(s_map),
+                            _p(dg) if diag else None)
+    if rc != 0:
+        raise ValueError("oracle polarized solve failed with status %d" % rc)
+    return (s_alm, s_map, dg) if diag else (s_alm, s_map)
+
+
+def fluct_rho_pol(nside, lmax, cl4, M6, g1, h, direct=False):
+    """rho = L_p g1 + Omega Y_pol(K_l h) with M_p = L_p L_p^T and K_l K_l^T = S_l^{-1}."""
+    cl4, M6, g1, h = _f64(cl4), _f64(M6), _f64(g1), _c128(h)
+    out = np.zeros((3, 12 * nside * nside))
+    lib().or_fluct_rho_pol(nside, lmax, _p(cl4), _p(M6), _p(g1), _p(h.view(np.float64)),
+                           _p(out), int(direct))
     return out

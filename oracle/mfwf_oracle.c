@@ -462,6 +462,455 @@ void or_fluct_rho(int nside, int lmax, const double *cl, const double *M, const 
     free(x);
 }
 
+/* ------------------------------------------------------------------------------------
+ * Spin-2 functions (polarization, HEALPix / Zaldarriaga-Seljak convention).
+ *   Q + iU = sum 2a_lm 2Y_lm,  Q - iU = sum (-2)a_lm (-2)Y_lm,
+ *   a_E = -(2a + (-2)a) / 2,   a_B = i (2a - (-2)a) / 2,
+ *   (+-2)Y_lm = sqrt((l-2)!/(l+2)!) (eth or eth-bar)^2 Y_lm,  (s)Y_lm = (s)lambda_lm e^{i m phi}.
+ * With F+ = (2lambda + (-2)lambda)/2 and F- = (2lambda - (-2)lambda)/2, working out the
+ * two eth operators on lambda_lm e^{i m phi} (and the Legendre equation) gives
+ *   F+_lm = N_l/s^2 [(2m^2 - l(l+1) + l(l-1) z^2) lambda_lm + 2 c_lm z lambda_{l-1,m}]
+ *   F-_lm = 2 m N_l/s^2 [c_lm lambda_{l-1,m} - (l-1) z lambda_lm]
+ *   N_l = 1/sqrt((l-1) l (l+1) (l+2)),  c_lm = sqrt((2l+1)(l^2 - m^2)/(2l-1)),
+ * s = sin(theta); both vanish for l < 2.  Near the poles the bracket of F+ cancels by up to
+ * s^4 for m = 0, so the values are formed in long double (64-bit mantissa) from a long
+ * double recurrence at the point (z, s = sqrt((1-z)(1+z))), then rounded.
+ * Out: fp[l-m], fm[l-m] for l = m..lmax.
+ * ------------------------------------------------------------------------------------ */
+void or_spin2(int lmax, int m, double z_in, double sth_in, double *fp, double *fm)
+{
+    /* evaluate at the point z_in exactly: s^2 = (1 - z)(1 + z) in long double (the bracket
+       of F+ cancels to O(s^4) near the poles, so z and s must lie on the unit circle to
+       the working precision; a separately rounded sin(theta) would break that) */
+    (void)sth_in;
+    long double z = z_in, s2 = (1.0L - z) * (1.0L + z), s = sqrtl(s2);
+    int ex;
+    long e = 0;
+    long double r = sqrtl(1.0L / (4.0L * (long double)M_PI));
+    for (int k = 1; k <= m; k++) {
+        r *= -sqrtl((2.0L * k + 1.0L) / (2.0L * k)) * s;
+        r = frexpl(r, &ex);
+        e += ex;
+    }
+    long double prev = 0.0L, cur = r; /* scaled lambda_{l-1,m}, lambda_{l,m} at l = m */
+    for (int l = m; l <= lmax; l++) {
+        if (l > m) {
+            long double eps_l = sqrtl(((long double)l * l - (long double)m * m) / (4.0L * l * l - 1.0L));
+            long double eps_l1 = (l - 1 > m)
+                ? sqrtl(((long double)(l - 1) * (l - 1) - (long double)m * m) / (4.0L * (l - 1) * (l - 1) - 1.0L))
+                : 0.0L;
+            long double nxt = (z * cur - eps_l1 * prev) / eps_l;
+            prev = cur;
+            cur = nxt;
+            if (fabsl(cur) > 0x1p+300L) {
+                cur = ldexpl(cur, -300);
+                prev = ldexpl(prev, -300);
+                e += 300;
+            }
+        }
+        if (l < 2) {
+            fp[l - m] = fm[l - m] = 0.0;
+            continue;
+        }
+        long double L = l, mm = m;
+        long double N = 1.0L / sqrtl((L - 1.0L) * L * (L + 1.0L) * (L + 2.0L));
+        long double c = (l > m) ? sqrtl((2.0L * L + 1.0L) * (L * L - mm * mm) / (2.0L * L - 1.0L)) : 0.0L;
+        long double bp = (2.0L * mm * mm - L * (L + 1.0L) + L * (L - 1.0L) * z * z) * cur + 2.0L * c * z * prev;
+        long double bm = c * prev - (L - 1.0L) * z * cur;
+        long double vp = N / s2 * bp, vm = 2.0L * mm * N / s2 * bm;
+        int ee = (int)(e < -20000 ? -20000 : e);
+        fp[l - m] = (double)ldexpl(vp, ee);
+        fm[l - m] = (double)ldexpl(vm, ee);
+    }
+}
+
+/* ------------------------------------------------------------------------------------
+ * Polarized SHT, maps [3][npix] (T, Q, U), alm [3][nalm] (T, E, B).  T is the spin-0
+ * transform.  Per ring and m, from the definitions above (sums over m >= 0 folded with
+ * F(-m) = conj F(m) as for spin 0):
+ *   synthesis  FQ(m) = -sum_l (aE F+ + i aB F-),   FU(m) = -sum_l (aB F+ - i aE F-)
+ *   analysis   aE = -Omega sum_rings (F+ GQ + i F- GU),  aB = -Omega sum_rings (F+ GU - i F- GQ)
+ * (the analysis is the adjoint of the synthesis, times Omega).  Every ring on its own.
+ * ------------------------------------------------------------------------------------ */
+void or_alm2map_pol(int nside, int lmax, const double *alm_in, double *map, int direct)
+{
+    long npix = or_npix(nside), nalm = or_nalm(lmax);
+    or_alm2map(nside, lmax, alm_in, map, direct);
+    const cplx *aE = (const cplx *)alm_in + nalm, *aB = (const cplx *)alm_in + 2 * nalm;
+    int nr = or_nrings(nside);
+#pragma omp parallel
+    {
+        double *fp = (double *)malloc(sizeof(double) * (lmax + 1));
+        double *fm = (double *)malloc(sizeof(double) * (lmax + 1));
+        cplx *FQ = (cplx *)malloc(sizeof(cplx) * (lmax + 1));
+        cplx *FU = (cplx *)malloc(sizeof(cplx) * (lmax + 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int i = 1; i <= nr; i++) {
+            double z, sth, phi0;
+            long start;
+            int nphi;
+            or_ring(nside, i, &z, &sth, &start, &nphi, &phi0);
+            for (int m = 0; m <= lmax; m++) {
+                or_spin2(lmax, m, z, sth, fp, fm);
+                cplx q = 0, u = 0;
+                for (int l = m; l <= lmax; l++) {
+                    long k = aidx(lmax, l, m);
+                    q += -(aE[k] * fp[l - m] + I * aB[k] * fm[l - m]);
+                    u += -(aB[k] * fp[l - m] - I * aE[k] * fm[l - m]);
+                }
+                FQ[m] = q;
+                FU[m] = u;
+            }
+            ring_synth(lmax, nphi, phi0, FQ, map + npix + start, direct);
+            ring_synth(lmax, nphi, phi0, FU, map + 2 * npix + start, direct);
+        }
+        free(fp);
+        free(fm);
+        free(FQ);
+        free(FU);
+    }
+}
+
+void or_map2alm_pol(int nside, int lmax, const double *map, double *alm_out, int direct)
+{
+    long npix = or_npix(nside), nalm = or_nalm(lmax);
+    or_map2alm(nside, lmax, map, alm_out, direct);
+    cplx *aE = (cplx *)alm_out + nalm, *aB = (cplx *)alm_out + 2 * nalm;
+    int nr = or_nrings(nside);
+    double omega = 4.0 * M_PI / (double)npix;
+    cplx *GQ = (cplx *)malloc(sizeof(cplx) * (size_t)nr * (lmax + 1));
+    cplx *GU = (cplx *)malloc(sizeof(cplx) * (size_t)nr * (lmax + 1));
+    double *zr = (double *)malloc(sizeof(double) * nr);
+    double *sr = (double *)malloc(sizeof(double) * nr);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 1; i <= nr; i++) {
+        double phi0;
+        long start;
+        int nphi;
+        or_ring(nside, i, &zr[i - 1], &sr[i - 1], &start, &nphi, &phi0);
+        ring_analysis(lmax, nphi, phi0, map + npix + start, GQ + (size_t)(i - 1) * (lmax + 1), direct);
+        ring_analysis(lmax, nphi, phi0, map + 2 * npix + start, GU + (size_t)(i - 1) * (lmax + 1), direct);
+    }
+#pragma omp parallel
+    {
+        double *fp = (double *)malloc(sizeof(double) * (lmax + 1));
+        double *fm = (double *)malloc(sizeof(double) * (lmax + 1));
+        cplx *accE = (cplx *)malloc(sizeof(cplx) * (lmax + 1));
+        cplx *accB = (cplx *)malloc(sizeof(cplx) * (lmax + 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int m = 0; m <= lmax; m++) {
+            for (int l = m; l <= lmax; l++)
+                accE[l - m] = accB[l - m] = 0;
+            for (int r = 0; r < nr; r++) {
+                or_spin2(lmax, m, zr[r], sr[r], fp, fm);
+                cplx gq = GQ[(size_t)r * (lmax + 1) + m], gu = GU[(size_t)r * (lmax + 1) + m];
+                for (int l = m; l <= lmax; l++) {
+                    accE[l - m] += -(fp[l - m] * gq + I * fm[l - m] * gu);
+                    accB[l - m] += -(fp[l - m] * gu - I * fm[l - m] * gq);
+                }
+            }
+            for (int l = m; l <= lmax; l++) {
+                aE[aidx(lmax, l, m)] = omega * accE[l - m];
+                aB[aidx(lmax, l, m)] = omega * accB[l - m];
+            }
+        }
+        free(fp);
+        free(fm);
+        free(accE);
+        free(accB);
+    }
+    free(GQ);
+    free(GU);
+    free(zr);
+    free(sr);
+}
+
+/* ------------------------------------------------------------------------------------
+ * Small dense linear algebra for the 3x3 blocks: Gaussian elimination with partial
+ * pivoting (textbook), real and complex right-hand sides.  Returns 0, or -1 if singular.
+ * ------------------------------------------------------------------------------------ */
+static int solve3(const double Ain[9], const double bin[3], double x[3])
+{
+    double A[9], b[3];
+    memcpy(A, Ain, sizeof A);
+    memcpy(b, bin, sizeof b);
+    for (int c = 0; c < 3; c++) {
+        int piv = c;
+        for (int r = c + 1; r < 3; r++)
+            if (fabs(A[3 * r + c]) > fabs(A[3 * piv + c]))
+                piv = r;
+        if (A[3 * piv + c] == 0.0)
+            return -1;
+        if (piv != c) {
+            for (int k = 0; k < 3; k++) {
+                double t = A[3 * c + k];
+                A[3 * c + k] = A[3 * piv + k];
+                A[3 * piv + k] = t;
+            }
+            double t = b[c];
+            b[c] = b[piv];
+            b[piv] = t;
+        }
+        for (int r = c + 1; r < 3; r++) {
+            double f = A[3 * r + c] / A[3 * c + c];
+            for (int k = c; k < 3; k++)
+                A[3 * r + k] -= f * A[3 * c + k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = 2; r >= 0; r--) {
+        double acc = b[r];
+        for (int k = r + 1; k < 3; k++)
+            acc -= A[3 * r + k] * x[k];
+        x[r] = acc / A[3 * r + r];
+    }
+    return 0;
+}
+
+/* M_p packed (TT, TQ, TU, QQ, QU, UU) -> full 3x3 */
+static void unpack6(const double *m6, double A[9])
+{
+    A[0] = m6[0]; A[1] = m6[1]; A[2] = m6[2];
+    A[3] = m6[1]; A[4] = m6[3]; A[5] = m6[4];
+    A[6] = m6[2]; A[7] = m6[4]; A[8] = m6[5];
+}
+
+/* S_l for (T, E, B): TT, EE, BB, TE from cl[4][lmax+1]; no TB, EB */
+static void signal3(int lmax, const double *cl, int l, double S[9])
+{
+    double TT = cl[l], EE = cl[lmax + 1 + l], BB = cl[2 * (lmax + 1) + l], TE = cl[3 * (lmax + 1) + l];
+    S[0] = TT; S[1] = TE; S[2] = 0.0;
+    S[3] = TE; S[4] = EE; S[5] = 0.0;
+    S[6] = 0.0; S[7] = 0.0; S[8] = BB;
+}
+
+/* x^T S^+ x over the components with positive power: the (T, E) block inverted where both
+ * have power (else the one that has), B where BB > 0. */
+static double quad_sinv(const double S[9], const double x[3])
+{
+    double acc = 0.0;
+    double TT = S[0], EE = S[4], TE = S[1], BB = S[8];
+    if (TT > 0.0 && EE > 0.0) {
+        double det = TT * EE - TE * TE;
+        acc += (EE * x[0] * x[0] - 2.0 * TE * x[0] * x[1] + TT * x[1] * x[1]) / det;
+    } else if (TT > 0.0) {
+        acc += x[0] * x[0] / TT;
+    } else if (EE > 0.0) {
+        acc += x[1] * x[1] / EE;
+    }
+    if (BB > 0.0)
+        acc += x[2] * x[2] / BB;
+    return acc;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Messenger iteration with T, Q, U (Sect. 2.1, Eqs. 3-4 with 3x3 blocks).
+ *   M    [npix][6] packed N_p^{-1} (zero in masked pixels)
+ *   cl   [4][lmax+1]: TT, EE, BB, TE
+ *   rho  [3][npix], tau given (= 1 / max_p lambda_max(M_p))
+ * Per pixel: t = [I + (lam-1) tau M]^{-1} [lam tau rho + (I - tau M) s]   (3x3 solve)
+ * Per (l, m): s = S_l (S_l + lam tau Omega I)^{-1} a, i.e. s = S_l x with
+ *             (S_l + lam tau Omega I) x = a   (real and imaginary parts separately).
+ * diag per iteration: chi^2 = sum_lm w_m (s^T S^+ s) + sum_{p observed} q^T [M + (lam-1) tau M^2]^{-1} q
+ * with q = rho - M s (observed: det M_p > 0), its harmonic part, |s_k - s_{k-1}|, |s_k|
+ * (real harmonic dof of all three components).
+ * ------------------------------------------------------------------------------------ */
+int or_solve_pol(int nside, int lmax, const double *cl, const double *M, const double *rho,
+                 double tau, int niter, const double *lam, int direct, double *s_alm_out,
+                 double *s_map_out, double *diag)
+{
+    long npix = or_npix(nside), nalm = or_nalm(lmax);
+    if (!(tau > 0.0))
+        return -4;
+    double omega = 4.0 * M_PI / (double)npix;
+    double *s_map = (double *)calloc(3 * npix, sizeof(double));
+    double *t = (double *)malloc(sizeof(double) * 3 * npix);
+    cplx *a = (cplx *)malloc(sizeof(cplx) * 3 * nalm);
+    cplx *s = (cplx *)calloc(3 * nalm, sizeof(cplx));
+    cplx *s_old = (cplx *)calloc(3 * nalm, sizeof(cplx));
+    int rc = 0;
+    for (int k = 0; k < niter && rc == 0; k++) {
+        double Lk = lam[k];
+        for (long p = 0; p < npix; p++) {
+            double Mp[9], A[9], b[3], x[3];
+            unpack6(M + 6 * p, Mp);
+            for (int i = 0; i < 3; i++) {
+                double acc = Lk * tau * rho[i * npix + p] + s_map[i * npix + p];
+                for (int j = 0; j < 3; j++) {
+                    acc -= tau * Mp[3 * i + j] * s_map[j * npix + p];
+                    A[3 * i + j] = (i == j ? 1.0 : 0.0) + (Lk - 1.0) * tau * Mp[3 * i + j];
+                }
+                b[i] = acc;
+            }
+            if (solve3(A, b, x) != 0)
+                rc = -3;
+            for (int i = 0; i < 3; i++)
+                t[i * npix + p] = x[i];
+        }
+        or_map2alm_pol(nside, lmax, t, (double *)a, direct);
+        memcpy(s_old, s, sizeof(cplx) * 3 * nalm);
+        for (int l = 0; l <= lmax; l++) {
+            double S[9], A[9];
+            signal3(lmax, cl, l, S);
+            for (int i = 0; i < 9; i++)
+                A[i] = S[i] + ((i % 4 == 0) ? Lk * tau * omega : 0.0);
+            for (int m = 0; m <= l; m++) {
+                long i0 = aidx(lmax, l, m);
+                double re[3], im[3], xr[3], xi[3];
+                for (int c = 0; c < 3; c++) {
+                    re[c] = creal(a[c * nalm + i0]);
+                    im[c] = cimag(a[c * nalm + i0]);
+                }
+                solve3(A, re, xr);
+                solve3(A, im, xi);
+                for (int c = 0; c < 3; c++) {
+                    double sr = 0.0, si = 0.0;
+                    for (int j = 0; j < 3; j++) {
+                        sr += S[3 * c + j] * xr[j];
+                        si += S[3 * c + j] * xi[j];
+                    }
+                    s[c * nalm + i0] = sr + I * si;
+                }
+            }
+        }
+        or_alm2map_pol(nside, lmax, (const double *)s, s_map, direct);
+        if (diag) {
+            double harm = 0.0, pix = 0.0, dn = 0.0, sn = 0.0;
+            for (int l = 0; l <= lmax; l++) {
+                double S[9];
+                signal3(lmax, cl, l, S);
+                for (int m = 0; m <= l; m++) {
+                    long i0 = aidx(lmax, l, m);
+                    double w = (m == 0) ? 1.0 : 2.0, xr[3], xi[3];
+                    for (int c = 0; c < 3; c++) {
+                        cplx v = s[c * nalm + i0], d = v - s_old[c * nalm + i0];
+                        xr[c] = creal(v);
+                        xi[c] = cimag(v);
+                        dn += w * creal(conj(d) * d);
+                        sn += w * creal(conj(v) * v);
+                    }
+                    harm += w * (quad_sinv(S, xr) + quad_sinv(S, xi));
+                }
+            }
+            for (long p = 0; p < npix; p++) {
+                double Mp[9], B[9], q[3], y[3];
+                unpack6(M + 6 * p, Mp);
+                double det = Mp[0] * (Mp[4] * Mp[8] - Mp[5] * Mp[7]) - Mp[1] * (Mp[3] * Mp[8] - Mp[5] * Mp[6]) +
+                             Mp[2] * (Mp[3] * Mp[7] - Mp[4] * Mp[6]);
+                if (!(det > 0.0))
+                    continue;
+                for (int i = 0; i < 3; i++) {
+                    double acc = rho[i * npix + p];
+                    for (int j = 0; j < 3; j++) {
+                        acc -= Mp[3 * i + j] * s_map[j * npix + p];
+                        double m2 = 0.0;
+                        for (int k2 = 0; k2 < 3; k2++)
+                            m2 += Mp[3 * i + k2] * Mp[3 * k2 + j];
+                        B[3 * i + j] = Mp[3 * i + j] + (Lk - 1.0) * tau * m2;
+                    }
+                    q[i] = acc;
+                }
+                solve3(B, q, y);
+                pix += q[0] * y[0] + q[1] * y[1] + q[2] * y[2];
+            }
+            diag[4 * k + 0] = harm + pix;
+            diag[4 * k + 1] = harm;
+            diag[4 * k + 2] = sqrt(dn);
+            diag[4 * k + 3] = sqrt(sn);
+        }
+    }
+    if (s_alm_out)
+        memcpy(s_alm_out, s, sizeof(cplx) * 3 * nalm);
+    if (s_map_out)
+        memcpy(s_map_out, s_map, sizeof(double) * 3 * npix);
+    free(s_map);
+    free(t);
+    free(a);
+    free(s);
+    free(s_old);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Fluctuation source with T, Q, U (Eq. 9 with blocks):
+ *   rho = L_p g1 + Omega * Y_pol(K_l h),   M_p = L_p L_p^T (Cholesky; 0 in masked pixels),
+ *   K_l = L_S^{-T} with S_l = L_S L_S^T over the components with positive power (so that
+ *   K K^T = S_l^{-1} there), 0 elsewhere.
+ * g1 [3][npix], h [3][nalm] complex unit-white.
+ * ------------------------------------------------------------------------------------ */
+static void chol3(const double A[9], double L[9])
+{
+    memset(L, 0, 9 * sizeof(double));
+    for (int j = 0; j < 3; j++) {
+        double d = A[3 * j + j];
+        for (int k = 0; k < j; k++)
+            d -= L[3 * j + k] * L[3 * j + k];
+        if (!(d > 0.0))
+            return; /* zero (masked) or non-definite block: remaining column stays 0 */
+        L[3 * j + j] = sqrt(d);
+        for (int i = j + 1; i < 3; i++) {
+            double v = A[3 * i + j];
+            for (int k = 0; k < j; k++)
+                v -= L[3 * i + k] * L[3 * j + k];
+            L[3 * i + j] = v / L[3 * j + j];
+        }
+    }
+}
+
+void or_fluct_rho_pol(int nside, int lmax, const double *cl, const double *M, const double *g1,
+                      const double *h_in, double *rho, int direct)
+{
+    long npix = or_npix(nside), nalm = or_nalm(lmax);
+    const cplx *h = (const cplx *)h_in;
+    cplx *x = (cplx *)calloc(3 * nalm, sizeof(cplx));
+    for (int l = 0; l <= lmax; l++) {
+        double S[9];
+        signal3(lmax, cl, l, S);
+        /* K on the (T, E) block: positive-power components only */
+        double TT = S[0], EE = S[4], TE = S[1], BB = S[8];
+        double K[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (TT > 0.0 && EE > 0.0) {
+            /* S = L L^T, L = [[a, 0], [b, c]]; K = L^{-T} = [[1/a, -b/(a c)], [0, 1/c]] */
+            double aa = sqrt(TT), bb = TE / aa, cc = sqrt(EE - bb * bb);
+            K[0] = 1.0 / aa;
+            K[1] = -bb / (aa * cc);
+            K[4] = 1.0 / cc;
+        } else if (TT > 0.0) {
+            K[0] = 1.0 / sqrt(TT);
+        } else if (EE > 0.0) {
+            K[4] = 1.0 / sqrt(EE);
+        }
+        if (BB > 0.0)
+            K[8] = 1.0 / sqrt(BB);
+        for (int m = 0; m <= l; m++) {
+            long i0 = aidx(lmax, l, m);
+            for (int c = 0; c < 3; c++) {
+                cplx acc = 0;
+                for (int j = 0; j < 3; j++)
+                    acc += K[3 * c + j] * h[j * nalm + i0];
+                x[c * nalm + i0] = acc;
+            }
+        }
+    }
+    or_alm2map_pol(nside, lmax, (const double *)x, rho, direct);
+    double omega = 4.0 * M_PI / (double)npix;
+    for (long p = 0; p < npix; p++) {
+        double Mp[9], L[9];
+        unpack6(M + 6 * p, Mp);
+        chol3(Mp, L);
+        double v[3];
+        for (int i = 0; i < 3; i++) {
+            double acc = 0.0;
+            for (int j = 0; j < 3; j++)
+                acc += L[3 * i + j] * g1[j * npix + p];
+            v[i] = acc;
+        }
+        for (int i = 0; i < 3; i++)
+            rho[i * npix + p] = v[i] + omega * rho[i * npix + p];
+    }
+    free(x);
+}
+
 int or_num_threads(void)
 {
 #ifdef _OPENMP

@@ -178,3 +178,77 @@ def fluctuation_draws(seed: int, nside: int, lmax: int):
     h = white_alm(rng, lmax)
     g1 = rng.standard_normal(12 * nside * nside)
     return g1, h
+
+
+# ---- temperature + polarization (T, Q, U) -----------------------------------------------
+
+def pol_cls(cl_tt):
+    """[4][lmax+1] = TT, EE, BB, TE with EE = 0.05 TT, TE = 0.5 cos(2 pi l / 300)
+    sqrt(TT EE), BB = 0.01 EE (l < 2 all zero, as TT)."""
+    lmax = len(cl_tt) - 1
+    ell = np.arange(lmax + 1, dtype=np.float64)
+    ee = 0.05 * cl_tt
+    te = 0.5 * np.cos(2.0 * np.pi * ell / 300.0) * np.sqrt(cl_tt * ee)
+    return np.stack([cl_tt, ee, 0.01 * ee, te])
+
+
+def pack_sym3(A):
+    """[..., 3, 3] symmetric -> [..., 6] = (TT, TQ, TU, QQ, QU, UU)."""
+    return np.stack([A[..., 0, 0], A[..., 0, 1], A[..., 0, 2], A[..., 1, 1], A[..., 1, 2],
+                     A[..., 2, 2]], axis=-1)
+
+
+@dataclasses.dataclass
+class PolWorkload:
+    """Inputs of one T, Q, U Wiener-filter problem."""
+    name: str
+    nside: int
+    lmax: int
+    cl4: np.ndarray           # [4][lmax+1] TT, EE, BB, TE
+    signal_alm: np.ndarray    # [3][nalm] complex T, E, B signal draw
+    noise_white: np.ndarray   # [3][npix] unit normals
+    noise_chol: np.ndarray    # [npix][3][3] lower factor of N_p (pixel noise = chol @ white)
+    ninv6: np.ndarray         # [npix][6] packed N_p^{-1} (observed pixels; all pixels)
+    mask: np.ndarray          # [npix] uint8, 1 = observed
+
+    @property
+    def npix(self):
+        return 12 * self.nside * self.nside
+
+    def M6(self):
+        """Packed N^{-1} with masked pixels zeroed."""
+        return self.ninv6 * self.mask[:, None]
+
+    def data_from_signal_maps(self, signal_maps):
+        """d = s + n (Eq. 1) with n_p = chol(N_p) g_p."""
+        n = np.einsum("pij,jp->ip", self.noise_chol, self.noise_white)
+        return signal_maps + n
+
+
+def config3(seed: int = 0, nside: int = 512, lmax: int = 1024, lscale: float = 800.0,
+            ndisc: int = 100, band_z: float = 0.15, nu: int = 10) -> PolWorkload:
+    """T, Q, U problem: C^TT as the nside 512 temperature problem, EE/TE/BB from pol_cls,
+    noise N_p = (30^2 / hits_p) W_p / nu with W_p ~ Wishart(nu, diag(1, 2, 2)), the same
+    mask for T and P.  Signal (T, E, B) alm = L_l h with L_l L_l^T the 3x3 signal block.
+    Draw order: signal, pixel noise, disc centres, hit jitter, Wishart draws."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    npix = 12 * nside * nside
+    cl4 = pol_cls(cl_damped(lmax, lscale))
+    h = np.stack([white_alm(rng, lmax) for _ in range(3)])
+    g = rng.standard_normal((3, npix))
+    centres = _unit_vectors(rng, ndisc)
+    xi = rng.uniform(-1.0, 1.0, npix)
+    z, phi = pixel_centres(nside)
+    mask = disc_mask(z, phi, centres, math.radians(3.0), band_z)
+    hits = scan_hits(z, xi)
+    x = rng.standard_normal((npix, nu, 3)) * np.sqrt(np.array([1.0, 2.0, 2.0]))
+    W = np.einsum("pki,pkj->pij", x, x)
+    N = (900.0 / hits)[:, None, None] * W / nu
+    ls, _ = alm_l_m(lmax)
+    tt, ee, bb, te = cl4[0][ls], cl4[1][ls], cl4[2][ls], cl4[3][ls]
+    a = np.sqrt(tt)
+    b = np.where(a > 0, te / np.where(a > 0, a, 1.0), 0.0)
+    c = np.sqrt(np.maximum(ee - b * b, 0.0))
+    sig = np.stack([a * h[0], b * h[0] + c * h[1], np.sqrt(bb) * h[2]])
+    return PolWorkload(f"nside{nside}_lmax{lmax}_TQU", nside, lmax, cl4, sig, g,
+                       np.linalg.cholesky(N), pack_sym3(np.linalg.inv(N)), mask)
