@@ -67,6 +67,8 @@ def lib():
                                    ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, _dp]
         L.or_fluct_rho_pol.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp,
                                        ctypes.c_int]
+        L.or_alm2map_pol_ring.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp]
+        L.or_map2alm_pol_m.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp]
         _lib_handle = L
     return _lib_handle
 
@@ -262,4 +264,21 @@ def fluct_rho_pol(nside, lmax, cl4, M6, g1, h, direct=False):
     out = np.zeros((3, 12 * nside * nside))
     lib().or_fluct_rho_pol(nside, lmax, _p(cl4), _p(M6), _p(g1), _p(h.view(np.float64)),
                            _p(out), int(direct))
+    return out
+
+
+def alm2map_pol_ring(nside, lmax, alm, ring):
+    """T, Q, U of one ring (1-based ring index) of the polarized synthesis: [3][n_phi]."""
+    alm = _c128(alm)
+    z, s, start, nphi, phi0 = rings(nside)
+    out = np.zeros((3, int(nphi[ring - 1])))
+    lib().or_alm2map_pol_ring(nside, lmax, _p(alm.view(np.float64)), ring, _p(out))
+    return out
+
+
+def map2alm_pol_m(nside, lmax, maps, m):
+    """aT, aE, aB for one m, l = m..lmax, of the polarized analysis: [3][lmax - m + 1]."""
+    maps = _f64(maps)
+    out = np.zeros((3, lmax - m + 1), dtype=np.complex128)
+    lib().or_map2alm_pol_m(nside, lmax, _p(maps), m, _p(out.view(np.float64)))
     return out

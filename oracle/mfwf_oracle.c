@@ -625,6 +625,94 @@ void or_map2alm_pol(int nside, int lmax, const double *map, double *alm_out, int
     free(sr);
 }
 
+/* Sampled outputs of the same transforms, for checks at sizes where the whole transform
+ * would take minutes: T, Q, U of one ring (1-based ring index i; out[3][n_phi]) and
+ * aT, aE, aB of one m (out[3][lmax - m + 1]). */
+void or_alm2map_pol_ring(int nside, int lmax, const double *alm_in, int i, double *out)
+{
+    long nalm = or_nalm(lmax);
+    const cplx *aT = (const cplx *)alm_in, *aE = aT + nalm, *aB = aT + 2 * nalm;
+    double z, sth, phi0;
+    long start;
+    int nphi;
+    or_ring(nside, i, &z, &sth, &start, &nphi, &phi0);
+    double *lam = (double *)malloc(sizeof(double) * (lmax + 1));
+    double *eps = (double *)malloc(sizeof(double) * (lmax + 1));
+    double *fp = (double *)malloc(sizeof(double) * (lmax + 1));
+    double *fm = (double *)malloc(sizeof(double) * (lmax + 1));
+    cplx *F = (cplx *)malloc(sizeof(cplx) * 3 * (lmax + 1));
+    for (int m = 0; m <= lmax; m++) {
+        legendre_eps(lmax, m, eps);
+        legendre_with_eps(lmax, m, z, sth, eps, lam);
+        or_spin2(lmax, m, z, sth, fp, fm);
+        cplx t = 0, q = 0, u = 0;
+        for (int l = m; l <= lmax; l++) {
+            long k = aidx(lmax, l, m);
+            t += lam[l - m] * aT[k];
+            q += -(aE[k] * fp[l - m] + I * aB[k] * fm[l - m]);
+            u += -(aB[k] * fp[l - m] - I * aE[k] * fm[l - m]);
+        }
+        F[m] = t;
+        F[lmax + 1 + m] = q;
+        F[2 * (lmax + 1) + m] = u;
+    }
+    for (int c = 0; c < 3; c++)
+        ring_synth(lmax, nphi, phi0, F + c * (lmax + 1), out + (long)c * nphi, 0);
+    free(lam);
+    free(eps);
+    free(fp);
+    free(fm);
+    free(F);
+}
+
+void or_map2alm_pol_m(int nside, int lmax, const double *map, int m, double *out_in)
+{
+    long npix = or_npix(nside);
+    cplx *out = (cplx *)out_in;
+    int nr = or_nrings(nside), nl = lmax - m + 1;
+    double omega = 4.0 * M_PI / (double)npix;
+    for (int k = 0; k < 3 * nl; k++)
+        out[k] = 0;
+#pragma omp parallel
+    {
+        double *lam = (double *)malloc(sizeof(double) * (lmax + 1));
+        double *eps = (double *)malloc(sizeof(double) * (lmax + 1));
+        double *fp = (double *)malloc(sizeof(double) * (lmax + 1));
+        double *fm = (double *)malloc(sizeof(double) * (lmax + 1));
+        cplx *G = (cplx *)malloc(sizeof(cplx) * 3 * (lmax + 1));
+        cplx *acc = (cplx *)calloc(3 * nl, sizeof(cplx));
+        legendre_eps(lmax, m, eps);
+#pragma omp for schedule(dynamic, 4)
+        for (int i = 1; i <= nr; i++) {
+            double z, sth, phi0;
+            long start;
+            int nphi;
+            or_ring(nside, i, &z, &sth, &start, &nphi, &phi0);
+            for (int c = 0; c < 3; c++)
+                ring_analysis(lmax, nphi, phi0, map + c * npix + start, G + c * (lmax + 1), 0);
+            legendre_with_eps(lmax, m, z, sth, eps, lam);
+            or_spin2(lmax, m, z, sth, fp, fm);
+            cplx gt = G[m], gq = G[lmax + 1 + m], gu = G[2 * (lmax + 1) + m];
+            for (int l = m; l <= lmax; l++) {
+                acc[l - m] += lam[l - m] * gt;
+                acc[nl + l - m] += -(fp[l - m] * gq + I * fm[l - m] * gu);
+                acc[2 * nl + l - m] += -(fp[l - m] * gu - I * fm[l - m] * gq);
+            }
+        }
+#pragma omp critical
+        for (int k = 0; k < 3 * nl; k++)
+            out[k] += acc[k];
+        free(lam);
+        free(eps);
+        free(fp);
+        free(fm);
+        free(G);
+        free(acc);
+    }
+    for (int k = 0; k < 3 * nl; k++)
+        out[k] *= omega;
+}
+
 /* ------------------------------------------------------------------------------------
  * Small dense linear algebra for the 3x3 blocks: Gaussian elimination with partial
  * pivoting (textbook), real and complex right-hand sides.  Returns 0, or -1 if singular.

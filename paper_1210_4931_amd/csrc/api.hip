@@ -220,7 +220,7 @@ static void build_seeds(int lmax, int npair, const std::vector<RingGeom> &geo,
 
 static void free_plan(Plan &p) {
     void *ptrs[] = {p.d_z,    p.d_A,    p.d_c,     p.d_lstart, p.d_seed,  p.d_pfft, p.d_plist,
-                    p.d_tw,   p.d_twlo, p.d_twhi, p.d_chirp, p.d_bhat, p.d_mofs,   p.d_cl,    p.d_M,
+                    p.d_tw,   p.d_twlo, p.d_twhi, p.d_chirp, p.d_bhat, p.d_mofs,   p.d_cl,    p.d_M, p.d_pc,
                     p.d_rho,  p.d_t,    p.d_smap,  p.d_phase,  p.d_apart, p.d_salm,
                     p.d_salm_prev, p.d_sp, p.d_red, p.d_diag, p.d_lam, p.d_loff, p.d_Lp,
                     p.d_minls32, p.d_ana_items, p.d_syn_items, p.d_ana_tab, p.d_syn_tab, p.d_lofi, p.d_phf, p.d_ph32, p.d_a32,
@@ -455,12 +455,37 @@ static int set_groups(Plan &p) {
     return MFWF_OK;
 }
 
+// Spin-2 coefficients per (l, m) of the rescaled recurrence (lambda = c mu), such that
+//   s^2 F+ = (pc0 + pc1 z^2) mu_l + pc2 z mu_{l-1},  s^2 F- = pc3 mu_{l-1} + pc4 z mu_l,
+// from s^2 F+ = N [(2m^2 - l(l+1) + l(l-1) z^2) lambda_l + 2 c_lm z lambda_{l-1}] and
+// s^2 F- = 2 m N [c_lm lambda_{l-1} - (l-1) z lambda_l], N = ((l-1) l (l+1) (l+2))^-1/2,
+// c_lm = ((2l+1)(l^2 - m^2)/(2l-1))^1/2 (both zero below l = 2).
+static void build_spin2_table(int lmax, const std::vector<double> &ctab,
+                              const std::vector<long> &mofs, std::vector<double> &pc) {
+    const long nalm = (long)(lmax + 1) * (lmax + 2) / 2;
+    pc.assign(5 * nalm, 0.0);
+    for (int m = 0; m <= lmax; m++)
+        for (int l = std::max(m, 2); l <= lmax; l++) {
+            const long i = mofs[m] + l - m;
+            const double L = l, M = m;
+            const double N = 1.0 / std::sqrt((L - 1.0) * L * (L + 1.0) * (L + 2.0));
+            const double clm = (l > m) ? std::sqrt((2.0 * L + 1.0) * (L * L - M * M) / (2.0 * L - 1.0)) : 0.0;
+            const double c0 = ctab[i], c1 = (l > m) ? ctab[i - 1] : 0.0;
+            pc[5 * i + 0] = N * (2.0 * M * M - L * (L + 1.0)) * c0;
+            pc[5 * i + 1] = N * L * (L - 1.0) * c0;
+            pc[5 * i + 2] = 2.0 * N * clm * c1;
+            pc[5 * i + 3] = 2.0 * M * N * clm * c1;
+            pc[5 * i + 4] = -2.0 * M * N * (L - 1.0) * c0;
+        }
+}
+
 static int create(int nside, int lmax, int spin, int dtype, int max_batch, void *stream,
                   Plan &p) {
     if (nside < 1 || nside > 1024 || !is_pow2(nside))
         return fail(MFWF_EINVAL, "nside must be a power of two in [1, 1024]");
     if (lmax < 1 || lmax > 4 * nside) return fail(MFWF_EINVAL, "lmax must be in [1, 4 nside]");
-    if (spin != 0) return fail(MFWF_EINVAL, "only spin 0 (temperature) is supported");
+    if (spin != 0 && spin != 2) return fail(MFWF_EINVAL, "spin must be 0 (T) or 2 (T, Q, U)");
+    if (spin == 2 && dtype != MFWF_F64) return fail(MFWF_EINVAL, "spin 2 plans run in MFWF_F64");
     if (dtype != MFWF_F64 && dtype != MFWF_F32) return fail(MFWF_EINVAL, "dtype must be MFWF_F64 or MFWF_F32");
     if (max_batch < 1 || max_batch > 4096) return fail(MFWF_EINVAL, "max_batch out of range");
     if (dtype == MFWF_F32 && max_batch > 512) return fail(MFWF_EINVAL, "MFWF_F32 plans take max_batch <= 512");
@@ -470,6 +495,7 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     p.nside = nside;
     p.lmax = lmax;
     p.spin = spin;
+    p.ncomp = (spin == 2) ? 3 : 1;
     p.dtype = dtype;
     p.max_batch = max_batch;
     p.stream = (hipStream_t)stream;
@@ -584,6 +610,9 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     const long B = max_batch;
     const bool f32 = (dtype == MFWF_F32);
     const long B64 = f32 ? 1 : B;  // the FP32 form has its own column-major work arrays
+    const long nc = p.ncomp;
+    const long ncl = (spin == 2) ? 4 : 1, nmw = (spin == 2) ? 6 : 1;
+    const long apart = (spin == 2) ? (long)pol_ngroup(p) * B * 3 * p.nalm : (long)p.ngroup_max * B64 * p.nalm;
     MFWF_TRY(dalloc(&p.d_z, p.npair, "z"));
     MFWF_TRY(dalloc(&p.d_A, Atab.size(), "recurrence A"));
     MFWF_TRY(dalloc(&p.d_c, ctab.size(), "recurrence scale"));
@@ -597,19 +626,25 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     MFWF_TRY(dalloc(&p.d_twhi, twhi.size(), "twiddles hi"));
     MFWF_TRY(dalloc(&p.d_chirp, std::max<size_t>(1, chirp.size()), "chirp"));
     MFWF_TRY(dalloc(&p.d_bhat, std::max<size_t>(1, bhat.size()), "chirp kernel"));
-    MFWF_TRY(dalloc(&p.d_cl, lmax + 1, "cl"));
-    MFWF_TRY(dalloc(&p.d_M, p.npix, "M"));
-    MFWF_TRY(dalloc(&p.d_rho, B * p.npix, "rho"));
-    MFWF_TRY(dalloc(&p.d_t, B * p.npix, "t"));
-    MFWF_TRY(dalloc(&p.d_smap, B * p.npix, "s map"));
-    MFWF_TRY(dalloc(&p.d_phase, B64 * p.nm * p.nring, "ring Fourier"));
-    MFWF_TRY(dalloc(&p.d_apart, (long)p.ngroup_max * B64 * p.nalm, "analysis partials"));
-    MFWF_TRY(dalloc(&p.d_salm, B * p.nalm, "s alm"));
-    MFWF_TRY(dalloc(&p.d_salm_prev, B * p.nalm, "previous s alm"));
-    MFWF_TRY(dalloc(&p.d_sp, B * p.nalm, "scaled synthesis input"));
+    MFWF_TRY(dalloc(&p.d_cl, ncl * (lmax + 1), "cl"));
+    MFWF_TRY(dalloc(&p.d_M, nmw * p.npix, "M"));
+    MFWF_TRY(dalloc(&p.d_rho, B * nc * p.npix, "rho"));
+    MFWF_TRY(dalloc(&p.d_t, B * nc * p.npix, "t"));
+    MFWF_TRY(dalloc(&p.d_smap, B * nc * p.npix, "s map"));
+    MFWF_TRY(dalloc(&p.d_phase, B64 * nc * p.nm * p.nring, "ring Fourier"));
+    MFWF_TRY(dalloc(&p.d_apart, apart, "analysis partials"));
+    MFWF_TRY(dalloc(&p.d_salm, B * nc * p.nalm, "s alm"));
+    MFWF_TRY(dalloc(&p.d_salm_prev, B * nc * p.nalm, "previous s alm"));
+    MFWF_TRY(dalloc(&p.d_sp, B * nc * p.nalm, "scaled synthesis input"));
     p.nred_blocks = 1024;
     MFWF_TRY(dalloc(&p.d_red, std::max<long>(3L * p.nred_blocks, std::max<long>(B * p.nred_blocks, 3L * B * p.nm)), "reductions"));
     MFWF_TRY(dalloc(&p.d_diag, 8 * B, "diagnostics"));
+    if (spin == 2) {
+        std::vector<double> pc;
+        build_spin2_table(lmax, ctab, mofs, pc);
+        MFWF_TRY(dalloc(&p.d_pc, pc.size(), "spin-2 coefficients"));
+        MFWF_TRY(upload(p.d_pc, pc, p.stream));
+    }
 
     MFWF_TRY(upload(p.d_z, zp, p.stream));
     MFWF_TRY(upload(p.d_A, Atab, p.stream));
@@ -625,16 +660,16 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     if (!chirp.empty()) MFWF_TRY(upload(p.d_chirp, chirp, p.stream));
     if (!bhat.empty()) MFWF_TRY(upload(p.d_bhat, bhat, p.stream));
     // defined contents everywhere (workspaces are read by autotuning and mfwf_time_kernels)
-    MFWF_TRY(launch_fill(p.d_cl, lmax + 1, 0.0, p.stream));
-    MFWF_TRY(launch_fill(p.d_M, p.npix, 0.0, p.stream));
-    MFWF_TRY(launch_fill(p.d_rho, B * p.npix, 0.0, p.stream));
-    MFWF_TRY(launch_fill(p.d_t, B * p.npix, 0.0, p.stream));
-    MFWF_TRY(launch_fill(p.d_smap, B * p.npix, 0.0, p.stream));
-    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_phase), 2 * B64 * p.nm * p.nring, 0.0, p.stream));
-    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_apart), 2L * p.ngroup_max * B64 * p.nalm, 0.0, p.stream));
-    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm), 2 * B * p.nalm, 0.0, p.stream));
-    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm_prev), 2 * B * p.nalm, 0.0, p.stream));
-    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_sp), 2 * B * p.nalm, 0.0, p.stream));
+    MFWF_TRY(launch_fill(p.d_cl, ncl * (lmax + 1), 0.0, p.stream));
+    MFWF_TRY(launch_fill(p.d_M, nmw * p.npix, 0.0, p.stream));
+    MFWF_TRY(launch_fill(p.d_rho, B * nc * p.npix, 0.0, p.stream));
+    MFWF_TRY(launch_fill(p.d_t, B * nc * p.npix, 0.0, p.stream));
+    MFWF_TRY(launch_fill(p.d_smap, B * nc * p.npix, 0.0, p.stream));
+    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_phase), 2 * B64 * nc * p.nm * p.nring, 0.0, p.stream));
+    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_apart), 2L * apart, 0.0, p.stream));
+    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm), 2 * B * nc * p.nalm, 0.0, p.stream));
+    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm_prev), 2 * B * nc * p.nalm, 0.0, p.stream));
+    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_sp), 2 * B * nc * p.nalm, 0.0, p.stream));
 
     default_variants(p);
     if (f32) {
@@ -648,7 +683,8 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
         p.ana_variant = av;
     } else {
         const char *at = std::getenv("MFWF_AUTOTUNE");
-        if (!(at && std::strcmp(at, "0") == 0) && p.npair >= 256) MFWF_TRY(autotune(p, devname));
+        if (!(at && std::strcmp(at, "0") == 0) && p.npair >= 256 && spin == 0)
+            MFWF_TRY(autotune(p, devname));
     }
     MFWF_TRY(set_groups(p));
     MFWF_HIP(hipStreamSynchronize(p.stream));
@@ -672,8 +708,21 @@ static int iteration_b(Plan &p, const double *rho, int nb, double lam, bool keep
     return MFWF_OK;
 }
 
+// T, Q, U: 3x3 pixel update, transforms of 3 nb maps, spin-2 Legendre steps, 3x3 filter
+static int iteration_pol(Plan &p, const double *rho, int nb, double lam, bool keep_prev) {
+    MFWF_TRY(launch_pixel_update_pol(rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, lam, p.tau, p.stream));
+    MFWF_TRY(launch_fft_fwd(p, p.d_t, p.d_phase, 3 * nb));
+    MFWF_TRY(launch_leg_analysis_pol(p, p.d_phase, p.d_apart, nb));
+    MFWF_TRY(launch_harmonic_pol(p, p.d_apart, pol_ngroup(p), p.omega, lam * p.tau * p.omega,
+                                 kHarmWiener, p.d_salm, p.d_sp, keep_prev ? p.d_salm_prev : nullptr, nb));
+    MFWF_TRY(launch_leg_synth_pol(p, p.d_sp, p.d_phase, nb));
+    MFWF_TRY(launch_fft_inv(p, p.d_phase, p.d_smap, 3 * nb));
+    return MFWF_OK;
+}
+
 static int iteration(Plan &p, const double *rho, int nb, double lam, bool keep_prev) {
     if (p.dtype == MFWF_F32) return iteration_b(p, rho, nb, lam, keep_prev);
+    if (p.spin == 2) return iteration_pol(p, rho, nb, lam, keep_prev);
     MFWF_TRY(launch_pixel_update(rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, lam, p.tau, p.stream));
     MFWF_TRY(launch_fft_fwd(p, p.d_t, p.d_phase, nb));
     MFWF_TRY(launch_leg_analysis(p, p.d_phase, p.d_apart, nb));
@@ -716,12 +765,16 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
                        const std::vector<double> &lam, const std::vector<int> &its,
                        mfwf_solve_info *info, int hist_maps, int hist_b0) {
     const double *rho = input;
+    const long nc = p.ncomp;
     if (!o.source_is_rho) {
-        MFWF_TRY(launch_rho_from_data(input, p.d_M, p.d_rho, p.npix, nb, p.stream));
+        if (p.spin == 2)
+            MFWF_TRY(launch_rho_from_data_pol(input, p.d_M, p.d_rho, p.npix, nb, p.stream));
+        else
+            MFWF_TRY(launch_rho_from_data(input, p.d_M, p.d_rho, p.npix, nb, p.stream));
         rho = p.d_rho;
     }
-    MFWF_TRY(launch_fill(p.d_smap, p.npix * nb, 0.0, p.stream));
-    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm), 2 * p.nalm * nb, 0.0, p.stream));
+    MFWF_TRY(launch_fill(p.d_smap, nc * p.npix * nb, 0.0, p.stream));
+    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm), 2 * nc * p.nalm * nb, 0.0, p.stream));
     if (p.dtype == MFWF_F32)  // previous harmonic iterate = 0 (outside any graph capture)
         MFWF_HIP(hipMemsetAsync(p.d_s32, 0, sizeof(float) * (size_t)p.nalm * p.C2, p.stream));
     long total = 0;
@@ -733,6 +786,11 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
     const bool graph = o.use_graph && p.stream != nullptr;
     std::vector<double> dg(8L * nb);
     auto diagnostics = [&](double lam_k) -> int {
+        if (p.spin == 2) {
+            MFWF_TRY(launch_chi2_pix_pol(rho, p.d_M, p.d_smap, p.npix, nb, lam_k, p.tau, p.d_red,
+                                         p.nred_blocks, p.d_diag, p.stream));
+            return launch_harm_diag_pol(p, p.d_salm, p.d_salm_prev, nb, p.d_red, p.d_diag);
+        }
         MFWF_TRY(launch_chi2_pix(rho, p.d_M, p.d_smap, p.npix, nb, lam_k, p.tau, p.d_red,
                                  p.nred_blocks, p.d_diag, p.stream));
         return launch_harm_diag(p, p.d_salm, p.d_salm_prev, nb, p.d_red, p.d_diag);
@@ -781,10 +839,10 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
     }
     if (total == 0) MFWF_TRY(launch_fill(p.d_diag, 8L * nb, 0.0, p.stream));
     if (s_alm_out)
-        MFWF_HIP(hipMemcpyAsync(s_alm_out, p.d_salm, sizeof(double2) * p.nalm * nb,
+        MFWF_HIP(hipMemcpyAsync(s_alm_out, p.d_salm, sizeof(double2) * nc * p.nalm * nb,
                                 hipMemcpyDeviceToDevice, p.stream));
     if (s_map_out)
-        MFWF_HIP(hipMemcpyAsync(s_map_out, p.d_smap, sizeof(double) * p.npix * nb,
+        MFWF_HIP(hipMemcpyAsync(s_map_out, p.d_smap, sizeof(double) * nc * p.npix * nb,
                                 hipMemcpyDeviceToDevice, p.stream));
     if (info) {
         MFWF_HIP(hipMemcpyAsync(dg.data(), p.d_diag, sizeof(double) * dg.size(),
@@ -842,6 +900,31 @@ int mfwf_set_covariances(mfwf_plan plan, const double *cl, int ncl, const double
                          const uint8_t *mask) {
     if (!plan || !cl || !ninv) return fail(MFWF_EINVAL, "NULL argument");
     Plan &p = plan->p;
+    p.have_cov = false;
+    if (p.spin == 2) {
+        if (ncl != 4) return fail(MFWF_EINVAL, "ncl must be 4 (TT, EE, BB, TE) for spin 2");
+        const int L1 = p.lmax + 1;
+        std::vector<double> c(cl, cl + 4L * L1);
+        for (int l = 0; l < L1; l++) {
+            const double TT = c[l], EE = c[L1 + l], BB = c[2 * L1 + l], TE = c[3 * L1 + l];
+            if (!(TT >= 0.0) || !(EE >= 0.0) || !(BB >= 0.0) || std::isinf(TT) || std::isinf(EE) ||
+                std::isinf(BB) || !std::isfinite(TE) || TE * TE > TT * EE)
+                return fail(MFWF_EINVAL, "each S_l must be finite and positive semi-definite");
+        }
+        MFWF_TRY(upload(p.d_cl, c, p.stream));
+        MFWF_TRY(launch_pol_covariance(ninv, mask, p.d_M, p.npix, p.d_red, p.nred_blocks, p.d_diag,
+                                       p.stream));
+        double r[3];
+        MFWF_HIP(hipMemcpyAsync(r, p.d_diag, sizeof(r), hipMemcpyDeviceToHost, p.stream));
+        MFWF_HIP(hipStreamSynchronize(p.stream));
+        if (r[2] > 0.0)
+            return fail(MFWF_ENOTSPD, "a 3x3 noise block is not finite and positive semi-definite");
+        if (!(r[0] > 0.0)) return fail(MFWF_ENOCOV, "no observed pixel: all blocks are 0, tau undefined");
+        p.tau = 1.0 / r[0];  // 1 / max_p lambda_max(M_p)
+        p.ndof = 3 * (long)r[1];
+        p.have_cov = true;
+        return MFWF_OK;
+    }
     if (ncl != 1) return fail(MFWF_EINVAL, "ncl must be 1 for temperature");
     std::vector<double> c(cl, cl + p.lmax + 1);
     for (double v : c)
@@ -852,7 +935,6 @@ int mfwf_set_covariances(mfwf_plan plan, const double *cl, int ncl, const double
     double r[3];
     MFWF_HIP(hipMemcpyAsync(r, p.d_diag, sizeof(r), hipMemcpyDeviceToHost, p.stream));
     MFWF_HIP(hipStreamSynchronize(p.stream));
-    p.have_cov = false;
     if (r[2] > 0.0) return fail(MFWF_ENAN, "inverse noise has negative or non-finite entries");
     if (!(r[0] > 0.0)) return fail(MFWF_ENOCOV, "no observed pixel: max N^-1 * mask is 0, tau undefined");
     p.tau = 1.0 / r[0];
@@ -868,6 +950,13 @@ int mfwf_sht_inv(mfwf_plan plan, const double *alm, double *map, int nmaps) {
     Plan &p = plan->p;
     for (int b0 = 0; b0 < nmaps; b0 += p.max_batch) {
         const int nb = std::min(p.max_batch, nmaps - b0);
+        if (p.spin == 2) {
+            MFWF_TRY(launch_harmonic_pol(p, reinterpret_cast<const double2 *>(alm) + 3L * b0 * p.nalm,
+                                         1, 1.0, 0.0, kHarmCopy, nullptr, p.d_sp, nullptr, nb));
+            MFWF_TRY(launch_leg_synth_pol(p, p.d_sp, p.d_phase, nb));
+            MFWF_TRY(launch_fft_inv(p, p.d_phase, map + 3L * b0 * p.npix, 3 * nb));
+            continue;
+        }
         if (p.dtype == MFWF_F32) {
             MFWF_TRY(launch_alm_to_cols(p, reinterpret_cast<const double2 *>(alm) + (long)b0 * p.nalm,
                                         p.d_s32, nb, kHarmCopy));
@@ -891,6 +980,14 @@ int mfwf_sht_fwd(mfwf_plan plan, const double *map, double *alm, int nmaps) {
     Plan &p = plan->p;
     for (int b0 = 0; b0 < nmaps; b0 += p.max_batch) {
         const int nb = std::min(p.max_batch, nmaps - b0);
+        if (p.spin == 2) {
+            MFWF_TRY(launch_fft_fwd(p, map + 3L * b0 * p.npix, p.d_phase, 3 * nb));
+            MFWF_TRY(launch_leg_analysis_pol(p, p.d_phase, p.d_apart, nb));
+            MFWF_TRY(launch_harmonic_pol(p, p.d_apart, pol_ngroup(p), p.omega, 0.0, kHarmAnalysis,
+                                         reinterpret_cast<double2 *>(alm) + 3L * b0 * p.nalm,
+                                         nullptr, nullptr, nb));
+            continue;
+        }
         if (p.dtype == MFWF_F32) {
             MFWF_TRY(launch_fft_fwd_f32(p, map + (long)b0 * p.npix, nullptr, 1.0, p.d_phf, nb));
             MFWF_TRY(launch_rows_to_cols(p, nb));
@@ -918,6 +1015,15 @@ int mfwf_fluctuation_rhs(mfwf_plan plan, const double *g1, const double *h, int 
     for (int b0 = 0; b0 < nrhs; b0 += p.max_batch) {
         const int nb = std::min(p.max_batch, nrhs - b0);
         // x = C^{-1/2} h, then Y x, then rho = M^{1/2} g1 + Omega Y x
+        if (p.spin == 2) {
+            MFWF_TRY(launch_harmonic_pol(p, reinterpret_cast<const double2 *>(h) + 3L * b0 * p.nalm,
+                                         1, 1.0, 0.0, kHarmInvSqrtC, nullptr, p.d_sp, nullptr, nb));
+            MFWF_TRY(launch_leg_synth_pol(p, p.d_sp, p.d_phase, nb));
+            MFWF_TRY(launch_fft_inv(p, p.d_phase, p.d_t, 3 * nb));
+            MFWF_TRY(launch_fluct_combine_pol(g1 + 3L * b0 * p.npix, p.d_M, p.d_t,
+                                              rho + 3L * b0 * p.npix, p.npix, nb, p.omega, p.stream));
+            continue;
+        }
         if (p.dtype == MFWF_F32) {
             MFWF_TRY(launch_alm_to_cols(p, reinterpret_cast<const double2 *>(h) + (long)b0 * p.nalm,
                                         p.d_s32, nb, kHarmInvSqrtC));
@@ -962,9 +1068,10 @@ int mfwf_solve(mfwf_plan plan, const double *input, int nmaps, double *s_alm_out
     }
     for (int b0 = 0; b0 < nmaps; b0 += p.max_batch) {
         const int nb = std::min(p.max_batch, nmaps - b0);
-        MFWF_TRY(solve_chunk(p, input + (long)b0 * p.npix, nb,
-                             s_alm_out ? s_alm_out + 2L * b0 * p.nalm : nullptr,
-                             s_map_out ? s_map_out + (long)b0 * p.npix : nullptr, o, lam, its,
+        const long nc = p.ncomp;
+        MFWF_TRY(solve_chunk(p, input + nc * b0 * p.npix, nb,
+                             s_alm_out ? s_alm_out + 2L * nc * b0 * p.nalm : nullptr,
+                             s_map_out ? s_map_out + nc * b0 * p.npix : nullptr, o, lam, its,
                              info ? info + b0 : nullptr, nmaps, b0));
     }
     MFWF_HIP(hipStreamSynchronize(p.stream));
@@ -998,6 +1105,20 @@ int mfwf_time_kernels(mfwf_plan plan, int nmaps, int reps, double *ms_out) {
                 case 3: ms_out[k] = 0.0; continue;  // harmonic update runs inside the analysis
                 case 4: f = [&] { return launch_gemm_synthesis(p, nb); }; break;
                 default: f = [&] { MFWF_TRY(launch_cols_to_rows(p, nb)); return launch_fft_inv_f32(p, p.d_phf, p.d_smap, nb); }; break;
+            }
+            float ms = 0.f;
+            MFWF_TRY(time_launches(p, reps, f, ms));
+            ms_out[k] = ms / reps;
+            continue;
+        }
+        if (p.spin == 2) {
+            switch (k) {
+                case 0: f = [&] { return launch_pixel_update_pol(p.d_rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, 1.0, p.tau, p.stream); }; break;
+                case 1: f = [&] { return launch_fft_fwd(p, p.d_t, p.d_phase, 3 * nb); }; break;
+                case 2: f = [&] { return launch_leg_analysis_pol(p, p.d_phase, p.d_apart, nb); }; break;
+                case 3: f = [&] { return launch_harmonic_pol(p, p.d_apart, pol_ngroup(p), p.omega, p.tau * p.omega, kHarmWiener, p.d_salm, p.d_sp, nullptr, nb); }; break;
+                case 4: f = [&] { return launch_leg_synth_pol(p, p.d_sp, p.d_phase, nb); }; break;
+                default: f = [&] { return launch_fft_inv(p, p.d_phase, p.d_smap, 3 * nb); }; break;
             }
             float ms = 0.f;
             MFWF_TRY(time_launches(p, reps, f, ms));

@@ -1,0 +1,73 @@
+// Per-lane state of the rescaled Legendre recurrence shared by the temperature and the
+// polarization kernels: mu_l = A_lm z mu_{l-1} - mu_{l-2}, lambda_lm = c_lm mu_lm, started
+// at each (m, ring pair)'s first non-negligible l from two stored values.
+#pragma once
+
+#include "mfwf_internal.h"
+
+namespace mfwf {
+
+static constexpr int kW = 64;  // wavefront
+
+__device__ __forceinline__ int wave_min_uniform(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ int wave_max_uniform(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+template <int P>
+struct PairState {
+    double z[P], u1[P], u2[P];  // mu_{l-1}, mu_{l-2}
+    double2 sd[P];              // (mu_{l_s - 1}, mu_{l_s})
+    int ls[P];
+    int lo, hi;  // wave-uniform: smallest start, largest start <= lmax (m if none)
+
+    __device__ __forceinline__ void load(int m, int g, int npair, int lmax,
+                                         const double *__restrict__ zp,
+                                         const int *__restrict__ lstart,
+                                         const double2 *__restrict__ seed) {
+        int mylo = lmax + 1, myhi = m;
+#pragma unroll
+        for (int k = 0; k < P; k++) {
+            const int p = g * kW * P + k * kW + (int)threadIdx.x;
+            const bool valid = p < npair;
+            z[k] = valid ? zp[p] : 0.0;
+            ls[k] = valid ? lstart[(long)m * npair + p] : lmax + 1;
+            sd[k] = valid ? seed[(long)m * npair + p] : make_double2(0.0, 0.0);
+            u1[k] = 0.0;
+            u2[k] = 0.0;
+            mylo = min(mylo, ls[k]);
+            if (ls[k] <= lmax) myhi = max(myhi, ls[k]);
+        }
+        lo = wave_min_uniform(mylo);
+        hi = wave_max_uniform(myhi);
+    }
+
+    // mu_l for every pair, injecting the seeds at each pair's own start.  The two forms
+    // associate A z mu differently on purpose: the blocks with and without injection then
+    // share no subexpression, so the compiler cannot hoist a whole block's A z products
+    // above the branch (that costs 2 U P registers and halves occupancy).
+    template <bool INJ>
+    __device__ __forceinline__ void step(int l, double A, double (&cur)[P]) {
+#pragma unroll
+        for (int k = 0; k < P; k++) {
+            double v;
+            if (INJ) {
+                v = fma(A * z[k], u1[k], -u2[k]);
+                const bool start = (l == ls[k]);
+                v = start ? sd[k].y : v;
+                u1[k] = start ? sd[k].x : u1[k];
+            } else {
+                v = fma(A, z[k] * u1[k], -u2[k]);
+            }
+            u2[k] = u1[k];
+            u1[k] = v;
+            cur[k] = v;
+        }
+    }
+};
+
+}  // namespace mfwf

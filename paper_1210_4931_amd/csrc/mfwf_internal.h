@@ -46,6 +46,7 @@ struct PairFFT {
 // two values (lambda_{l_s - 1, m}, lambda_{l_s, m}); l_s = lmax + 1 if never reached.
 struct Plan {
     int nside, lmax, spin, dtype, max_batch;
+    int ncomp = 1;  // components per map: 1 (T) or 3 (T, Q, U / T, E, B)
     hipStream_t stream;
     long npix;
     int nring, npair, nm;
@@ -73,10 +74,11 @@ struct Plan {
     int *d_plist = nullptr;      // [npair] pair indices grouped by FFT class
     int fft_class_off[2] = {0, 0}, fft_class_count[2] = {0, 0}, fft_class_len[2] = {1, 1};
     long *d_mofs = nullptr;      // [nm] packed offset of (l = m, m)
+    double *d_pc = nullptr;      // [nalm][5] spin-2 coefficients of mu_l, mu_{l-1} (spin 2)
 
     // covariances
-    double *d_cl = nullptr;  // [lmax+1]
-    double *d_M = nullptr;   // [npix] inverse noise variance times mask
+    double *d_cl = nullptr;  // [lmax+1], or [4][lmax+1] TT, EE, BB, TE (spin 2)
+    double *d_M = nullptr;   // [npix] inverse noise variance times mask, or [npix][6] blocks
     double tau = 0.0;
     long ndof = 0;
     bool have_cov = false;
@@ -160,6 +162,26 @@ int launch_gemm_analysis(const Plan &p, int nb, float *a_out, float *s_out, doub
 int launch_gemm_synthesis(const Plan &p, int nb);
 int launch_alm_to_cols(const Plan &p, const double2 *alm, float *x32, int nb, int mode);
 int launch_cols_to_alm(const Plan &p, const float *x32, double2 *alm, int nb, double scale);
+
+// polar.hip (spin 2: maps [B][3][npix], alm [B][3][nalm], rows [3B][nring][nm])
+int pol_ngroup(const Plan &p);
+int launch_leg_synth_pol(const Plan &p, const double2 *alm_scaled, double2 *phase, int nb);
+int launch_leg_analysis_pol(const Plan &p, const double2 *phase, double2 *apart, int nb);
+int launch_harmonic_pol(const Plan &p, const double2 *in, int ngroup, double scale, double lto,
+                        int mode, double2 *out_s, double2 *out_sp, double2 *prev, int nb);
+int launch_pol_covariance(const double *ninv6, const uint8_t *mask, double *M6, long npix,
+                          double *partial, int nblocks, double *out3, hipStream_t s);
+int launch_rho_from_data_pol(const double *d, const double *M6, double *rho, long npix, int nb,
+                             hipStream_t s);
+int launch_pixel_update_pol(const double *rho, const double *M6, const double *smap, double *t,
+                            long npix, int nb, double lam, double tau, hipStream_t s);
+int launch_chi2_pix_pol(const double *rho, const double *M6, const double *smap, long npix,
+                        int nb, double lam, double tau, double *partial, int nblocks,
+                        double *diag, hipStream_t s);
+int launch_harm_diag_pol(const Plan &p, const double2 *salm, const double2 *salm_prev, int nb,
+                         double *partial, double *diag);
+int launch_fluct_combine_pol(const double *g1, const double *M6, const double *ysh, double *rho,
+                             long npix, int nb, double omega, hipStream_t s);
 
 // harmonic.hip
 enum HarmMode { kHarmWiener = 0, kHarmAnalysis = 1, kHarmInvSqrtC = 2, kHarmCopy = 3 };

@@ -102,12 +102,17 @@ class Info:
 
 
 class Plan:
-    """One (nside, lmax) problem shape on one GPU, with its own HIP stream."""
+    """One (nside, lmax) problem shape on one GPU, with its own HIP stream.
+
+    spin 0: maps [n][npix], alm [n][nalm].  spin 2 (T, Q, U): maps [n][3][npix], alm
+    [n][3][nalm] (T, E, B), spectra [4][lmax+1] (TT, EE, BB, TE), inverse noise [npix][6]
+    packed 3x3 blocks (TT, TQ, TU, QQ, QU, UU)."""
 
     def __init__(self, nside: int, lmax: int, max_batch: int = 1, spin: int = 0,
                  dtype: str = "f64", device: int = 0):
         L = load()
         self.nside, self.lmax, self.max_batch = nside, lmax, max_batch
+        self.spin, self.ncomp = spin, (3 if spin == 2 else 1)
         self.npix = 12 * nside * nside
         self.nalm = (lmax + 1) * (lmax + 2) // 2
         self.device = torch.device("cuda", device)
@@ -137,32 +142,40 @@ class Plan:
     def _leave(self):
         torch.cuda.current_stream(self.device).wait_stream(self.stream)
 
+    def _shape(self, n, size):
+        return (n, size) if self.ncomp == 1 else (n, self.ncomp, size)
+
+    def _count(self, x):
+        """maps or alm in this plan's per-map shape, with or without the leading n"""
+        return x.shape[0] if x.dim() == (2 if self.ncomp == 1 else 3) else 1
+
     def zeros_map(self, n):
-        return torch.zeros((n, self.npix), dtype=torch.float64, device=self.device)
+        return torch.zeros(self._shape(n, self.npix), dtype=torch.float64, device=self.device)
 
     def zeros_alm(self, n):
-        return torch.zeros((n, self.nalm), dtype=torch.complex128, device=self.device)
+        return torch.zeros(self._shape(n, self.nalm), dtype=torch.complex128, device=self.device)
 
     # ---- entry points --------------------------------------------------------------------
     def set_covariances(self, cl, ninv: torch.Tensor, mask: torch.Tensor | None = None):
         cl = np.ascontiguousarray(np.asarray(cl, dtype=np.float64).reshape(-1))
-        if cl.size != self.lmax + 1:
-            raise ValueError("cl must have lmax + 1 entries")
-        ninv = _dev_f64(ninv, (self.npix,))
+        ncl = 4 if self.spin == 2 else 1
+        if cl.size != ncl * (self.lmax + 1):
+            raise ValueError("cl must have %d x (lmax + 1) entries" % ncl)
+        ninv = _dev_f64(ninv, (self.npix * (6 if self.spin == 2 else 1),))
         if mask is not None:
             if mask.dtype != torch.uint8 or not mask.is_cuda or mask.numel() != self.npix:
                 raise TypeError("mask must be a CUDA uint8 tensor of npix entries")
             mask = mask.contiguous()
         self._enter()
         rc = _lib.mfwf_set_covariances(self._h, cl.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                       1, ninv.data_ptr(),
+                                       ncl, ninv.data_ptr(),
                                        None if mask is None else mask.data_ptr())
         _check(rc)
         self._keep = (ninv, mask)
 
     def sht_inv(self, alm: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        n = alm.shape[0] if alm.dim() == 2 else 1
-        a = _dev_f64(alm, (n, 2 * self.nalm))
+        n = self._count(alm)
+        a = _dev_f64(alm, (n, self.ncomp, 2 * self.nalm))
         out = self.zeros_map(n) if out is None else out
         self._enter()
         _check(_lib.mfwf_sht_inv(self._h, a.data_ptr(), out.data_ptr(), n))
@@ -170,8 +183,8 @@ class Plan:
         return out
 
     def sht_fwd(self, maps: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        n = maps.shape[0] if maps.dim() == 2 else 1
-        m = _dev_f64(maps, (n, self.npix))
+        n = self._count(maps)
+        m = _dev_f64(maps, (n, self.ncomp, self.npix))
         out = self.zeros_alm(n) if out is None else out
         self._enter()
         _check(_lib.mfwf_sht_fwd(self._h, m.data_ptr(), torch.view_as_real(out).data_ptr(), n))
@@ -179,9 +192,9 @@ class Plan:
         return out
 
     def fluctuation_rhs(self, g1: torch.Tensor, h: torch.Tensor, out=None) -> torch.Tensor:
-        n = g1.shape[0] if g1.dim() == 2 else 1
-        g = _dev_f64(g1, (n, self.npix))
-        hh = _dev_f64(h, (n, 2 * self.nalm))
+        n = self._count(g1)
+        g = _dev_f64(g1, (n, self.ncomp, self.npix))
+        hh = _dev_f64(h, (n, self.ncomp, 2 * self.nalm))
         out = self.zeros_map(n) if out is None else out
         self._enter()
         _check(_lib.mfwf_fluctuation_rhs(self._h, g.data_ptr(), hh.data_ptr(), n, out.data_ptr()))
@@ -195,8 +208,8 @@ class Plan:
         n_check > 0 a fourth item, the diagnostics history as a numpy array
         [checks][n][5] of (iteration, lambda, chi^2, |s_k - s_{k-1}|, |s_k|)."""
         import numpy as np
-        n = inp.shape[0] if inp.dim() == 2 else 1
-        x = _dev_f64(inp, (n, self.npix))
+        n = self._count(inp)
+        x = _dev_f64(inp, (n, self.ncomp, self.npix))
         if lam is None:
             lam, iters = [1.0], [300 if iters is None else int(iters)]
         lam_a = (ctypes.c_double * len(lam))(*[float(v) for v in lam])
