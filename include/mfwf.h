@@ -16,6 +16,12 @@
  *   - Synthesis Y: map(p) = sum_{l,|m|<=l} a_lm Y_lm(p).  Analysis A = Omega Y^T:
  *     a_lm = Omega sum_p map(p) conj(Y_lm(p)), Omega = 4 pi / npix (uniform pixel weights).
  *   - Batched arrays are map-major: [nmaps][npix] and [nmaps][2*nalm].
+ *   - Polarization (plans with spin = 2): every map is (T, Q, U) and every coefficient set
+ *     (T, E, B), component-major within a map: [nmaps][3][npix] and [nmaps][3][2*nalm].
+ *     Q, U follow the HEALPix / Zaldarriaga-Seljak convention: Q + iU = sum 2a_lm 2Y_lm,
+ *     a_E = -(2a + (-2)a)/2, a_B = i (2a - (-2)a)/2, spin-weighted harmonics from the
+ *     spin-raising operator, (+-2)Y_lm = sqrt((l-2)!/(l+2)!) (eth or eth-bar)^2 Y_lm.
+ *     The analysis is again Omega times the adjoint of the synthesis.
  *   - Every pointer named "device" is a device pointer owned by the caller; the library
  *     keeps no reference to it after the call returns.  Host pointers are read during the
  *     call only.
@@ -59,7 +65,9 @@ typedef enum {
 
 /*
  * Create a plan for HEALPix resolution nside (power of two, 1..1024) and band limit
- * lmax (1..4*nside).  spin: 0 = temperature only.  max_batch (>= 1): largest number of
+ * lmax (1..4*nside).  spin: 0 = temperature only, 2 = temperature and polarization (T, Q, U
+ * maps, T, E, B coefficients, 3x3 noise and signal blocks; MFWF_F64 only).  max_batch (>= 1):
+ * largest number of
  * maps one call processes at once (larger calls are split).  hip_stream: a hipStream_t
  * or NULL for the null stream.  The plan precomputes the ring geometry (HEALPix,
  * Gorski et al. 2005), the Legendre recurrence coefficients and, for every (m, ring
@@ -68,7 +76,8 @@ typedef enum {
  * workspaces up front (MFWF_F32 adds the FP32 lambda table, 4 bytes x ring pairs x
  * (lmax+1)(lmax+2)/2 roughly: 2.2 GB at nside 512 / lmax 1024, and column-major work
  * arrays for max_batch maps).  *out receives the handle.
- * Errors: MFWF_EINVAL for out-of-range sizes or spin != 0, MFWF_ENOMEM, MFWF_EDEVICE.
+ * Errors: MFWF_EINVAL for out-of-range sizes, spin not 0 or 2, or spin 2 with MFWF_F32;
+ * MFWF_ENOMEM, MFWF_EDEVICE.
  */
 int mfwf_plan_create(int nside, int lmax, int spin, int dtype, int max_batch, void *hip_stream,
                      mfwf_plan *out);
@@ -80,23 +89,30 @@ int mfwf_plan_destroy(mfwf_plan plan);
  * Set the signal and noise covariances (Sect. 2.1, Eq. 2).
  *   cl    host, [ncl][lmax+1] signal power spectrum C_l (ncl = 1 for temperature);
  *         C_l = 0 removes the multipole from the solution.  Negative C_l -> MFWF_EINVAL.
- *   ninv  device, [npix] inverse noise variance N^-1 per pixel (>= 0).
+ *         spin 2: ncl = 4, rows TT, EE, BB, TE; S_l = [[TT, TE, 0], [TE, EE, 0], [0, 0, BB]]
+ *         must be positive semi-definite (TE^2 <= TT EE), else MFWF_EINVAL.
+ *   ninv  device, [npix] inverse noise variance N^-1 per pixel (>= 0); spin 2: [npix][6],
+ *         the symmetric 3x3 block N_p^-1 of (T, Q, U) packed (TT, TQ, TU, QQ, QU, UU).
  *   mask  device, [npix] uint8, 1 = observed, 0 = masked (M = 0); NULL = all observed.
- * The plan stores M = ninv * mask and tau = min diag N over observed pixels = 1 / max M.
- * Errors: MFWF_ENOCOV if max M <= 0, MFWF_ENAN if M has a non-finite or negative entry.
+ * The plan stores M = ninv * mask and tau = min diag N over observed pixels = 1 / max M
+ * (spin 2: tau = 1 / max_p lambda_max(M_p), the largest T = tau 1 with N - T >= 0 in every
+ * pixel; the chi^2 degrees of freedom count 3 per pixel with det M_p > 0).
+ * Errors: MFWF_ENOCOV if max M <= 0, MFWF_ENAN if M has a non-finite or negative entry;
+ * spin 2: MFWF_ENOTSPD if a block is non-finite or not positive semi-definite.
  */
 int mfwf_set_covariances(mfwf_plan plan, const double *cl, int ncl, const double *ninv,
                          const uint8_t *mask);
 
 /*
  * Synthesis map = Y alm for nmaps maps (the inverse transform that closes each
- * iteration, Sect. 2.1).  alm: device [nmaps][2*nalm]; map: device [nmaps][npix].
+ * iteration, Sect. 2.1).  alm: device [nmaps][2*nalm]; map: device [nmaps][npix]
+ * (spin 2: [nmaps][3][2*nalm] T, E, B -> [nmaps][3][npix] T, Q, U).
  */
 int mfwf_sht_inv(mfwf_plan plan, const double *alm, double *map, int nmaps);
 
 /*
  * Analysis alm = Omega Y^T map for nmaps maps (the forward transform of Sect. 2.1).
- * map: device [nmaps][npix]; alm: device [nmaps][2*nalm].
+ * map: device [nmaps][npix]; alm: device [nmaps][2*nalm] (spin 2: [nmaps][3][...]).
  */
 int mfwf_sht_fwd(mfwf_plan plan, const double *map, double *alm, int nmaps);
 
@@ -111,6 +127,9 @@ int mfwf_sht_fwd(mfwf_plan plan, const double *map, double *alm, int nmaps);
  *   h    device [nrhs][2*nalm] unit-white harmonic draws in the real basis, complex
  *        packing: m = 0 entries real N(0,1), m > 0 entries (x + i y)/sqrt(2).
  *   rho  device [nrhs][npix] output; pass it to mfwf_solve with source_is_rho = 1.
+ * spin 2: g1, rho [nrhs][3][npix], h [nrhs][3][2*nalm]; M^{1/2} is the Cholesky factor
+ * L_p (L_p L_p^T = M_p) and C^{-1/2} the factor K_l = L_S^{-T} of S_l = L_S L_S^T on the
+ * components with power (K K^T = S_l^{-1} there).
  * Requires mfwf_set_covariances.  The draws are inputs: the library draws nothing.
  */
 int mfwf_fluctuation_rhs(mfwf_plan plan, const double *g1, const double *h, int nrhs,
@@ -159,6 +178,10 @@ typedef struct {
  * (Eq. 3 multiplied through by N, no inverse of Nbar), then
  *     s_lm = C_l / (C_l + lambda tau Omega) * (A t)_lm     (Eq. 4, T = tau Omega per
  * harmonic dof under A = Omega Y^T), then s = Y s_lm.  Non-convergence is not an error.
+ * spin 2: input and s_map_out [nmaps][3][npix], s_alm_out [nmaps][3][2*nalm]; the pixel
+ * update solves the 3x3 system [I + (lambda - 1) tau M_p] t = lambda tau rho +
+ * (I - tau M_p) s per pixel and the harmonic update is s = S_l (S_l + lambda tau Omega I)^-1 a
+ * per (l, m) on (T, E, B).
  */
 int mfwf_solve(mfwf_plan plan, const double *input, int nmaps, double *s_alm_out,
                double *s_map_out, const mfwf_solve_opts *opts, mfwf_solve_info *info);
