@@ -64,6 +64,39 @@ def cpu_baseline(nside, lmax, K, wl, d_host, M):
                       "extrapolated to %d iterations" % (nside, lmax, t2 - t0, per_iter, setup, K)}
 
 
+def tqu_fp64(nside, lmax, K, steps, use_graph):
+    """T, Q, U Wiener filter (FP64, one map of 3 components): Wishart 3x3 noise blocks, the
+    temperature problem's mask, EE/TE/BB spectra from TT; per-kernel times and the FP64
+    roofline position of the spin-2 Legendre analysis."""
+    import torch
+    from paper_1210_4931_amd import mfwf
+    from paper_1210_4931_amd import workloads as W
+    w = W.config3(0, nside, lmax)
+    dev = torch.device("cuda:0")
+    plan = mfwf.Plan(nside, lmax, max_batch=1, spin=2)
+    plan.set_covariances(w.cl4, torch.as_tensor(w.ninv6).to(dev),
+                         torch.as_tensor(w.mask).to(dev))
+    sig = plan.sht_inv(torch.as_tensor(w.signal_alm[None]).to(dev)).cpu().numpy()[0]
+    d = torch.as_tensor(w.data_from_signal_maps(sig)[None]).to(dev)
+    el, lat = timed_solves(plan, d, K, steps, 1, use_graph)
+    kt = dict(zip(KERNELS, plan.time_kernels(1, 5)))
+    work = plan.work()[0]
+    # per evaluated (l, m, pair) and direction: 3 recurrence, 6 forming F+ and F- from it,
+    # 4 for T and 16 for E, B (complex-by-real products with the ring-Fourier values)
+    flops = 29.0 * work
+    dom = max(("leg_analysis", "leg_synth"), key=lambda k: kt[k])
+    return {"workload": "T, Q, U Wiener filter, nside %d, lmax %d, %d iterations, 3x3 Wishart "
+                        "noise blocks" % (nside, lmax, K),
+            "solves_per_s": steps / el, "ms_per_solve": 1e3 * el / steps,
+            "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
+                           "p99": 1e3 * float(np.percentile(lat, 99))},
+            "kernel_ms": kt,
+            "roofline": {"bound": "alu", "kernel": dom + "_pol",
+                         "achieved": flops / (kt[dom] * 1e-3) / 1e12,
+                         "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
+                         "frac": flops / (kt[dom] * 1e-3) / PEAK_FP64_VALU}}
+
+
 def timed_solves(plan, d, K, steps, warmup, use_graph):
     import torch
     for _ in range(warmup):
@@ -91,6 +124,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-tqu", action="store_true", help="skip the T, Q, U measurement")
+    ap.add_argument("--tqu-steps", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the solver on a single MI355X "
@@ -179,6 +214,9 @@ def main():
                      "traffic": measured_traffic() if dom32 == "leg_analysis" else None},
         "fp64_single": fp64,
     }
+    del p32
+    if not args.no_tqu:
+        out["tqu_fp64"] = tqu_fp64(nside, lmax, K, args.tqu_steps, use_graph)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nside, lmax, K, wl, d1.cpu().numpy()[0],
                                            wl.mask / wl.noise_var)
