@@ -203,6 +203,66 @@ int mfwf_time_kernels(mfwf_plan plan, int nmaps, int reps, double *ms_out);
  */
 int mfwf_plan_work(mfwf_plan plan, double *out4);
 
+/*
+ * ---- Serving: many independent requests on one GPU (continuous batching) --------------
+ * Each request is one temperature Wiener-filter solve with its own data, noise variance
+ * map and mask.  Requests with the same (nside, lmax, dtype, lambda, C_l) share a pool: a
+ * plan with `slots` map slots, each holding its own M = N^-1 mask and tau = 1 / max M.  A
+ * worker thread admits queued requests into free slots between iterations, runs one
+ * messenger iteration (Eqs. 3-4) over the occupied slots of every busy pool (pools on
+ * separate streams overlap on the GPU), and retires a request after its `iters`
+ * iterations by copying s_lm and Y s into the caller's buffers.  Pools are created on
+ * demand while their estimated device footprint fits the HBM budget; idle pools are
+ * evicted (least recently used first) to make room.  Results equal those of mfwf_solve on
+ * the same inputs (starting from s = 0).
+ */
+typedef struct mfwf_server_s *mfwf_server;
+
+typedef struct {
+    int nside, lmax;        /* as in mfwf_plan_create (temperature)                       */
+    int dtype;              /* MFWF_F64 or MFWF_F32                                        */
+    int iters;              /* messenger iterations (>= 1)                                 */
+    double lambda;          /* constant lambda of Sect. 2.2 (>= 1)                         */
+    const double *cl;       /* host [lmax+1], copied by mfwf_server_submit                 */
+    const double *ninv;     /* device [npix] inverse noise variance (>= 0)                 */
+    const uint8_t *mask;    /* device [npix], 1 = observed; NULL = all observed            */
+    const double *data;     /* device [npix] data d                                        */
+    double *s_alm_out;      /* device [2*nalm] or NULL: final s_lm                         */
+    double *s_map_out;      /* device [npix] or NULL: Y s                                  */
+} mfwf_request;
+
+/* Device bytes a pool of this shape is charged against the HBM budget (an estimate of
+ * its plan's allocations, with a fixed allowance for tables and workspaces), so callers
+ * can size the budget.  Host only, no device call.  Errors: MFWF_EINVAL. */
+int mfwf_server_pool_bytes(int nside, int lmax, int dtype, int slots, double *bytes);
+
+/* Start a server on the current device with `slots` map slots per pool and a device
+ * memory budget (GB) for its pools.  Errors: MFWF_EINVAL, MFWF_ENOMEM, MFWF_EDEVICE. */
+int mfwf_server_create(int slots, double hbm_budget_gb, mfwf_server *out);
+
+/* Queue one request; *id receives its handle.  The device arrays must hold their final
+ * contents when this is called and stay valid until mfwf_server_wait returns for the
+ * request (they are read when it is admitted and written when it retires).  ninv * mask
+ * is checked here: MFWF_ENAN (negative or non-finite) or MFWF_ENOCOV (no observed pixel);
+ * MFWF_EINVAL for bad sizes or options. */
+int mfwf_server_submit(mfwf_server s, const mfwf_request *req, uint64_t *id);
+
+/* *done = 1 once the request's results are in the caller's buffers. */
+int mfwf_server_poll(mfwf_server s, uint64_t id, int *done);
+
+/* Block until the request is done; *latency_s (nullable) receives the time from
+ * submission to the completion of the result copies.  Returns the request's status (e.g.
+ * MFWF_ENOMEM when no pool of its shape fits the budget); the id is released. */
+int mfwf_server_wait(mfwf_server s, uint64_t id, double *latency_s);
+
+/* Counters (host, 8 doubles): [0] requests completed, [1] submitted but not yet seen by
+ * the worker, [2] occupied slots, [3] pools, [4] budgeted bytes of the pools,
+ * [5] iterations launched (summed over pools), [6] pools created, [7] pools evicted. */
+int mfwf_server_stats(mfwf_server s, double *out8);
+
+/* Finish every queued request, stop the worker and release the pools. */
+int mfwf_server_destroy(mfwf_server s);
+
 /* Message describing the last failure on this thread ("" if none). */
 const char *mfwf_last_error(void);
 

@@ -30,7 +30,7 @@ int fft_max_length();                 // ringfft.hip
 static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
 
-static int fail(int status, const std::string &msg) {
+int fail(int status, const std::string &msg) {
     set_error(msg);
     return status;
 }
@@ -220,7 +220,7 @@ static void build_seeds(int lmax, int npair, const std::vector<RingGeom> &geo,
 
 static void free_plan(Plan &p) {
     void *ptrs[] = {p.d_z,    p.d_A,    p.d_c,     p.d_lstart, p.d_seed,  p.d_pfft, p.d_plist,
-                    p.d_tw,   p.d_twlo, p.d_twhi, p.d_chirp, p.d_bhat, p.d_mofs,   p.d_cl,    p.d_M, p.d_pc,
+                    p.d_tw,   p.d_twlo, p.d_twhi, p.d_chirp, p.d_bhat, p.d_mofs,   p.d_cl,    p.d_M, p.d_pc, p.d_tau,
                     p.d_rho,  p.d_t,    p.d_smap,  p.d_phase,  p.d_apart, p.d_salm,
                     p.d_salm_prev, p.d_sp, p.d_red, p.d_diag, p.d_lam, p.d_loff, p.d_Lp,
                     p.d_minls32, p.d_ana_items, p.d_syn_items, p.d_ana_tab, p.d_syn_tab, p.d_lofi, p.d_phf, p.d_ph32, p.d_a32,
@@ -700,7 +700,8 @@ static int iteration_b(Plan &p, const double *rho, int nb, double lam, bool keep
     MFWF_TRY(launch_rows_to_cols(p, nb));
     if (keep_prev) MFWF_TRY(launch_cols_to_alm(p, p.d_s32, p.d_salm_prev, nb, 1.0));
     // analysis with the harmonic update (Eq. 4) applied in its epilogue
-    MFWF_TRY(launch_gemm_analysis(p, nb, nullptr, p.d_s32, p.omega, lam * p.tau * p.omega));
+    MFWF_TRY(launch_gemm_analysis(p, nb, nullptr, p.d_s32, p.omega, lam * p.omega * p.tau,
+                                  lam * p.omega));
     if (keep_prev) MFWF_TRY(launch_cols_to_alm(p, p.d_s32, p.d_salm, nb, 1.0));
     MFWF_TRY(launch_gemm_synthesis(p, nb));
     MFWF_TRY(launch_cols_to_rows(p, nb));
@@ -723,14 +724,58 @@ static int iteration_pol(Plan &p, const double *rho, int nb, double lam, bool ke
 static int iteration(Plan &p, const double *rho, int nb, double lam, bool keep_prev) {
     if (p.dtype == MFWF_F32) return iteration_b(p, rho, nb, lam, keep_prev);
     if (p.spin == 2) return iteration_pol(p, rho, nb, lam, keep_prev);
-    MFWF_TRY(launch_pixel_update(rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, lam, p.tau, p.stream));
+    MFWF_TRY(launch_pixel_update(rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, lam, p.tau, p.stream,
+                                 p.mstride, p.d_tau));
     MFWF_TRY(launch_fft_fwd(p, p.d_t, p.d_phase, nb));
     MFWF_TRY(launch_leg_analysis(p, p.d_phase, p.d_apart, nb));
-    MFWF_TRY(launch_harmonic(p, p.d_apart, p.ngroup, p.omega, lam * p.tau * p.omega, kHarmWiener,
-                             p.d_salm, p.d_sp, keep_prev ? p.d_salm_prev : nullptr, nb));
+    MFWF_TRY(launch_harmonic(p, p.d_apart, p.ngroup, p.omega, lam * p.omega * p.tau, kHarmWiener,
+                             p.d_salm, p.d_sp, keep_prev ? p.d_salm_prev : nullptr, nb,
+                             lam * p.omega));
     MFWF_TRY(launch_leg_synth(p, p.d_sp, p.d_phase, nb));
     MFWF_TRY(launch_fft_inv(p, p.d_phase, p.d_smap, nb));
     return MFWF_OK;
+}
+
+// ---- plan internals used by the serving runtime ----------------------------------------
+int plan_create(int nside, int lmax, int spin, int dtype, int max_batch, void *stream,
+                bool per_slot, Plan &p) {
+    int st = create(nside, lmax, spin, dtype, max_batch, stream, p);
+    if (st != MFWF_OK || !per_slot) return st;
+    if (spin != 0) return fail(MFWF_EINVAL, "serving slots are temperature only");
+    // one M row and one tau per slot, set when a request is admitted
+    (void)hipFree(p.d_M);
+    p.d_M = nullptr;
+    MFWF_TRY(dalloc(&p.d_M, (long)max_batch * p.npix, "per-slot M"));
+    // tau covers the padded batch Bp: the batched analysis epilogue reads it for every
+    // active column pair, including the zero columns past the last slot
+    MFWF_TRY(dalloc(&p.d_tau, p.Bp, "per-slot tau"));
+    MFWF_TRY(launch_fill(p.d_M, (long)max_batch * p.npix, 0.0, p.stream));
+    MFWF_TRY(launch_fill(p.d_tau, p.Bp, 0.0, p.stream));
+    p.mstride = p.npix;
+    p.tau = 0.0;
+    p.have_cov = true;
+    MFWF_HIP(hipStreamSynchronize(p.stream));
+    return MFWF_OK;
+}
+
+void plan_destroy(Plan &p) { free_plan(p); }
+
+int plan_iteration(Plan &p, const double *rho, int nb, double lam) {
+    return iteration(p, rho, nb, lam, false);
+}
+
+// After the last iteration: the FP32 form keeps s in its column layout; bring maps 0..nb-1
+// back to the FP64 per-map alm array (the FP64 path writes it every iteration).
+int plan_finish_alm(Plan &p, int nb) {
+    if (p.dtype == MFWF_F32) return launch_cols_to_alm(p, p.d_s32, p.d_salm, nb, 1.0);
+    return MFWF_OK;
+}
+
+int plan_set_cl(Plan &p, const double *cl) {
+    std::vector<double> c(cl, cl + p.lmax + 1);
+    for (double v : c)
+        if (!(v >= 0.0) || std::isinf(v)) return fail(MFWF_EINVAL, "C_l must be finite and >= 0");
+    return upload(p.d_cl, c, p.stream);
 }
 
 // One captured iteration of a stage, replayed as often as needed.
@@ -1101,7 +1146,7 @@ int mfwf_time_kernels(mfwf_plan plan, int nmaps, int reps, double *ms_out) {
             switch (k) {
                 case 0: ms_out[k] = 0.0; continue;  // pixel update runs inside the forward transforms
                 case 1: f = [&] { MFWF_TRY(launch_fft_fwd_f32(p, p.d_smap, p.d_rho, 1.0, p.d_phf, nb)); return launch_rows_to_cols(p, nb); }; break;
-                case 2: f = [&] { return launch_gemm_analysis(p, nb, nullptr, p.d_s32, p.omega, p.tau * p.omega); }; break;
+                case 2: f = [&] { return launch_gemm_analysis(p, nb, nullptr, p.d_s32, p.omega, p.omega * p.tau, p.omega); }; break;
                 case 3: ms_out[k] = 0.0; continue;  // harmonic update runs inside the analysis
                 case 4: f = [&] { return launch_gemm_synthesis(p, nb); }; break;
                 default: f = [&] { MFWF_TRY(launch_cols_to_rows(p, nb)); return launch_fft_inv_f32(p, p.d_phf, p.d_smap, nb); }; break;
@@ -1126,10 +1171,10 @@ int mfwf_time_kernels(mfwf_plan plan, int nmaps, int reps, double *ms_out) {
             continue;
         }
         switch (k) {
-            case 0: f = [&] { return launch_pixel_update(p.d_rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, 1.0, p.tau, p.stream); }; break;
+            case 0: f = [&] { return launch_pixel_update(p.d_rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, 1.0, p.tau, p.stream, p.mstride, p.d_tau); }; break;
             case 1: f = [&] { return launch_fft_fwd(p, p.d_t, p.d_phase, nb); }; break;
             case 2: f = [&] { return launch_leg_analysis(p, p.d_phase, p.d_apart, nb); }; break;
-            case 3: f = [&] { return launch_harmonic(p, p.d_apart, p.ngroup, p.omega, p.tau * p.omega, kHarmWiener, p.d_salm, p.d_sp, nullptr, nb); }; break;
+            case 3: f = [&] { return launch_harmonic(p, p.d_apart, p.ngroup, p.omega, p.omega * p.tau, kHarmWiener, p.d_salm, p.d_sp, nullptr, nb, p.omega); }; break;
             case 4: f = [&] { return launch_leg_synth(p, p.d_sp, p.d_phase, nb); }; break;
             default: f = [&] { return launch_fft_inv(p, p.d_phase, p.d_smap, nb); }; break;
         }

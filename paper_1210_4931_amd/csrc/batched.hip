@@ -152,7 +152,8 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
                 const float *__restrict__ ph32, const long *__restrict__ mofs,
                 const double *__restrict__ cl, float *__restrict__ a_out,
                 float *__restrict__ s_out, double scale_s, double lto, int lmax, int npair,
-                int Rp, int nring, int nm, int C2, int ncols, int ncg) {
+                int Rp, int nring, int nm, int C2, int ncols, int ncg,
+                const double *__restrict__ tau_b, double lto_per_tau) {
     // lambda tile [pair][row] and X_0, X_1 tiles [pair][col]; reused by the epilogue
     __shared__ __align__(16) float lds[32 * (kAnaRows + 4) + 2 * 32 * (kColTile + 4)];
     float (*sl)[kAnaRows + 4] = reinterpret_cast<float (*)[kAnaRows + 4]>(lds);
@@ -249,9 +250,14 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
             if (a_out) *reinterpret_cast<float4 *>(a_out + idx) = v;
             if (s_out) {
                 const double C = cl[l];
-                const double f = C > 0.0 ? C / (C + lto) * scale_s : 0.0;
+                // per-map tau (serving slots): columns 2b and 2b + 1 belong to map b, so the
+                // four columns of this store span maps col / 2 and col / 2 + 1
+                const double lt0 = tau_b ? lto_per_tau * tau_b[col >> 1] : lto;
+                const double lt1 = tau_b ? lto_per_tau * tau_b[(col >> 1) + 1] : lto;
+                const double f0 = C > 0.0 ? C / (C + lt0) * scale_s : 0.0;
+                const double f1 = C > 0.0 ? C / (C + lt1) * scale_s : 0.0;
                 *reinterpret_cast<float4 *>(s_out + idx) =
-                    make_float4((float)(f * v.x), (float)(f * v.y), (float)(f * v.z), (float)(f * v.w));
+                    make_float4((float)(f0 * v.x), (float)(f0 * v.y), (float)(f1 * v.z), (float)(f1 * v.w));
             }
         }
     }
@@ -456,12 +462,13 @@ int launch_cols_to_rows(const Plan &p, int nb) {
 static int active_cols(int nb) { return 32 * ((2 * nb + 31) / 32); }
 
 int launch_gemm_analysis(const Plan &p, int nb, float *a_out, float *s_out, double scale_s,
-                         double lto) {
+                         double lto, double lto_per_tau) {
     const int nc = active_cols(nb), ncg = (nc + kColTile - 1) / kColTile;
     hipLaunchKernelGGL(k_gemm_analysis, dim3(8 * p.ana_per_xcd * ncg), dim3(256), 0, p.stream,
                        p.d_lam, p.d_loff, p.d_Lp, p.d_minls32, p.d_ana_items, p.d_ana_tab,
                        p.ana_per_xcd, p.d_ph32, p.d_mofs, p.d_cl, a_out, s_out, scale_s, lto,
-                       p.lmax, p.npair, p.Rp, p.nring, p.nm, p.C2, nc, ncg);
+                       p.lmax, p.npair, p.Rp, p.nring, p.nm, p.C2, nc, ncg,
+                       s_out ? p.d_tau : nullptr, lto_per_tau);
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }

@@ -23,8 +23,9 @@ k_harmonic(const double2 *__restrict__ in, int ngroup, long nalm, int nb,
            const long *__restrict__ mofs, const double *__restrict__ cl,
            const double *__restrict__ ctab, int lmax, double scale, double lto, int mode,
            double2 *__restrict__ out_s, double2 *__restrict__ out_sp,
-           double2 *__restrict__ prev) {
+           double2 *__restrict__ prev, const double *__restrict__ tau_b, double lto_per_tau) {
     const int m = blockIdx.x, b = blockIdx.y;
+    if (tau_b) lto = lto_per_tau * tau_b[b];  // per-map tau (serving slots)
     const long toff = mofs[m] - m;
     const long base = (long)b * nalm + toff;
     for (int l = m + threadIdx.x; l <= lmax; l += kHT) {
@@ -50,10 +51,11 @@ k_harmonic(const double2 *__restrict__ in, int ngroup, long nalm, int nb,
 }
 
 int launch_harmonic(const Plan &p, const double2 *in, int ngroup, double scale, double lto,
-                    int mode, double2 *out_s, double2 *out_sp, double2 *prev, int nb) {
+                    int mode, double2 *out_s, double2 *out_sp, double2 *prev, int nb,
+                    double lto_per_tau) {
     hipLaunchKernelGGL(k_harmonic, dim3(p.nm, nb), dim3(kHT), 0, p.stream, in, ngroup, p.nalm,
                        nb, p.d_mofs, p.d_cl, p.d_c, p.lmax, scale, lto, mode, out_s, out_sp,
-                       prev);
+                       prev, mode == 0 ? p.d_tau : nullptr, lto_per_tau);
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }

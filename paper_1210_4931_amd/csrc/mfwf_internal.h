@@ -82,6 +82,10 @@ struct Plan {
     double tau = 0.0;
     long ndof = 0;
     bool have_cov = false;
+    // serving slots: one M row and one tau per map (mstride = npix, d_tau [B]); otherwise
+    // one M for all maps (mstride = 0, d_tau null)
+    long mstride = 0;
+    double *d_tau = nullptr;
 
     // workspaces, sized for max_batch maps
     double *d_rho = nullptr;     // [B][npix]
@@ -117,6 +121,15 @@ struct Plan {
     float *d_s32 = nullptr;      // [nalm][C2] synthesis input
 };
 
+// ---- plan internals (api.hip) used by the serving runtime -------------------------------
+int plan_create(int nside, int lmax, int spin, int dtype, int max_batch, void *stream,
+                bool per_slot, Plan &p);
+void plan_destroy(Plan &p);
+int plan_iteration(Plan &p, const double *rho, int nb, double lam);
+int plan_finish_alm(Plan &p, int nb);
+int plan_set_cl(Plan &p, const double *cl);
+int fail(int status, const std::string &msg);
+
 // ---- kernels (launch wrappers) --------------------------------------------------------
 // pixel.hip
 int launch_fill(double *x, long n, double v, hipStream_t s);
@@ -127,7 +140,8 @@ int launch_reduce_max_count(const double *M, long npix, double *partial, int nbl
 int launch_rho_from_data(const double *d, const double *M, double *rho, long npix, int nb,
                          hipStream_t s);
 int launch_pixel_update(const double *rho, const double *M, const double *smap, double *t,
-                        long npix, int nb, double lam, double tau, hipStream_t s);
+                        long npix, int nb, double lam, double tau, hipStream_t s,
+                        long mstride = 0, const double *tau_b = nullptr);
 int launch_chi2_pix(const double *rho, const double *M, const double *smap, long npix, int nb,
                     double lam, double tau, double *partial, int nblocks, double *diag,
                     hipStream_t s);
@@ -158,7 +172,7 @@ int launch_lam_table(const Plan &p);
 int launch_rows_to_cols(const Plan &p, int nb);  // d_phf -> d_ph32
 int launch_cols_to_rows(const Plan &p, int nb);  // d_ph32 -> d_phf
 int launch_gemm_analysis(const Plan &p, int nb, float *a_out, float *s_out, double scale_s,
-                         double lto);
+                         double lto, double lto_per_tau = 0.0);
 int launch_gemm_synthesis(const Plan &p, int nb);
 int launch_alm_to_cols(const Plan &p, const double2 *alm, float *x32, int nb, int mode);
 int launch_cols_to_alm(const Plan &p, const float *x32, double2 *alm, int nb, double scale);
@@ -185,8 +199,10 @@ int launch_fluct_combine_pol(const double *g1, const double *M6, const double *y
 
 // harmonic.hip
 enum HarmMode { kHarmWiener = 0, kHarmAnalysis = 1, kHarmInvSqrtC = 2, kHarmCopy = 3 };
+// mode 0 filter: C_l / (C_l + lto), or with p.d_tau set, lto = lto_per_tau * tau_b[map]
 int launch_harmonic(const Plan &p, const double2 *in, int ngroup, double scale, double lto,
-                    int mode, double2 *out_s, double2 *out_sp, double2 *prev, int nb);
+                    int mode, double2 *out_s, double2 *out_sp, double2 *prev, int nb,
+                    double lto_per_tau = 0.0);
 int launch_harm_diag(const Plan &p, const double2 *salm, const double2 *salm_prev, int nb,
                      double *partial, double *diag);
 

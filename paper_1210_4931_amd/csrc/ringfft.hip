@@ -44,7 +44,8 @@ __device__ __forceinline__ double2 get_c(const float2 *q) {
 template <int TPB, int EPT, typename OutT, bool PIX>
 __global__ void __launch_bounds__(TPB)
 k_fft_fwd(const double *__restrict__ maps, const double *__restrict__ rho,
-          const double *__restrict__ M, double lam, double tau, OutT *__restrict__ phase,
+          const double *__restrict__ M, double lam, double tau, long mstride,
+          const double *__restrict__ tau_b, OutT *__restrict__ phase,
           const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
           const double2 *__restrict__ twlo, const double2 *__restrict__ twhi, int ntwhi,
           int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
@@ -55,13 +56,14 @@ k_fft_fwd(const double *__restrict__ maps, const double *__restrict__ rho,
     const int n = pf.nphi;
     const bool equator = (pf.startS == pf.startN);
     const Twiddles tw = load_twiddles(buf, fft_area(fftlen_class, TPB), twlo, twhi, ntwhi);
+    if (PIX && tau_b) tau = tau_b[b];  // per-map tau and M rows (serving slots)
     const double lt = lam * tau, l1t = (lam - 1.0) * tau;
     auto pix = [&](long i) {  // i: pixel index within the map
         const double x = maps[(long)b * npix + i];
         if constexpr (!PIX) {
             return x;
         } else {
-            const double m = M[i];
+            const double m = M[(long)b * mstride + i];
             const double num = lt * rho[(long)b * npix + i] + (1.0 - tau * m) * x;
             return (lam == 1.0) ? num : num / (1.0 + l1t * m);
         }
@@ -197,11 +199,11 @@ static int fwd_classes(const Plan &p, const double *maps, const double *rho, dou
         const dim3 grid(nb, cnt);  // maps of one pair adjacent: its tables and M stay in L2
         const size_t lds = fft_class_lds(p, c);
         if (tpb == 256)
-            hipLaunchKernelGGL((k_fft_fwd<256, 8, OutT, PIX>), grid, dim3(256), lds, p.stream, maps, rho, p.d_M, lam, p.tau, out, MFWF_FFT_ARGS(c));
+            hipLaunchKernelGGL((k_fft_fwd<256, 8, OutT, PIX>), grid, dim3(256), lds, p.stream, maps, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, out, MFWF_FFT_ARGS(c));
         else if (tpb == 512)
-            hipLaunchKernelGGL((k_fft_fwd<512, 8, OutT, PIX>), grid, dim3(512), lds, p.stream, maps, rho, p.d_M, lam, p.tau, out, MFWF_FFT_ARGS(c));
+            hipLaunchKernelGGL((k_fft_fwd<512, 8, OutT, PIX>), grid, dim3(512), lds, p.stream, maps, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, out, MFWF_FFT_ARGS(c));
         else
-            hipLaunchKernelGGL((k_fft_fwd<1024, 8, OutT, PIX>), grid, dim3(1024), lds, p.stream, maps, rho, p.d_M, lam, p.tau, out, MFWF_FFT_ARGS(c));
+            hipLaunchKernelGGL((k_fft_fwd<1024, 8, OutT, PIX>), grid, dim3(1024), lds, p.stream, maps, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, out, MFWF_FFT_ARGS(c));
         MFWF_HIP(hipGetLastError());
     }
     return MFWF_OK;

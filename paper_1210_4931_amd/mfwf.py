@@ -39,7 +39,17 @@ class SolveInfo(ctypes.Structure):
 
 EXPORTED = ["mfwf_plan_create", "mfwf_plan_destroy", "mfwf_set_covariances", "mfwf_sht_inv",
             "mfwf_sht_fwd", "mfwf_fluctuation_rhs", "mfwf_solve", "mfwf_time_kernels",
-            "mfwf_plan_work", "mfwf_last_error"]
+            "mfwf_plan_work", "mfwf_last_error", "mfwf_server_create", "mfwf_server_submit",
+            "mfwf_server_poll", "mfwf_server_wait", "mfwf_server_stats", "mfwf_server_destroy",
+            "mfwf_server_pool_bytes"]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("nside", ctypes.c_int), ("lmax", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("iters", ctypes.c_int), ("lam", ctypes.c_double),
+                ("cl", ctypes.POINTER(ctypes.c_double)), ("ninv", ctypes.c_void_p),
+                ("mask", ctypes.c_void_p), ("data", ctypes.c_void_p),
+                ("s_alm_out", ctypes.c_void_p), ("s_map_out", ctypes.c_void_p)]
 
 _lib = None
 
@@ -63,6 +73,13 @@ def load(path: str = LIB_PATH):
                              ctypes.POINTER(SolveInfo)]
     L.mfwf_time_kernels.argtypes = [vp, ip, ip, dp]
     L.mfwf_plan_work.argtypes = [vp, dp]
+    L.mfwf_server_create.argtypes = [ip, ctypes.c_double, ctypes.POINTER(vp)]
+    L.mfwf_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    L.mfwf_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
+    L.mfwf_server_wait.argtypes = [vp, ctypes.c_uint64, dp]
+    L.mfwf_server_stats.argtypes = [vp, dp]
+    L.mfwf_server_destroy.argtypes = [vp]
+    L.mfwf_server_pool_bytes.argtypes = [ip, ip, ip, ip, dp]
     L.mfwf_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         getattr(L, name).restype = ctypes.c_char_p if name == "mfwf_last_error" else ctypes.c_int
@@ -246,3 +263,84 @@ class Plan:
         self._enter()
         _check(_lib.mfwf_time_kernels(self._h, nmaps, reps, out))
         return list(out)
+
+
+class Server:
+    """Continuous-batching server for independent temperature Wiener-filter requests (each
+    with its own data, noise variance map and mask).  submit() returns an id and the output
+    tensors (filled when the request completes); wait(id) blocks and returns the latency in
+    seconds from submission to results ready."""
+
+    def __init__(self, slots: int = 64, hbm_gb: float = 200.0, device: int = 0):
+        L = load()
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.mfwf_server_create(slots, float(hbm_gb), ctypes.byref(h)))
+        self._h = h
+        self._live = {}
+
+    def submit(self, nside, lmax, cl, ninv, data, mask=None, dtype="f64", iters=300, lam=1.0,
+               want_map=True):
+        npix, nalm = 12 * nside * nside, (lmax + 1) * (lmax + 2) // 2
+        cl = np.ascontiguousarray(np.asarray(cl, dtype=np.float64).reshape(-1))
+        if cl.size != lmax + 1:
+            raise ValueError("cl must have lmax + 1 entries")
+        ninv = _dev_f64(ninv, (npix,))
+        data = _dev_f64(data, (npix,))
+        if mask is not None:
+            if mask.dtype != torch.uint8 or not mask.is_cuda or mask.numel() != npix:
+                raise TypeError("mask must be a CUDA uint8 tensor of npix entries")
+            mask = mask.contiguous()
+        s_alm = torch.zeros(nalm, dtype=torch.complex128, device=self.device)
+        s_map = torch.zeros(npix, dtype=torch.float64, device=self.device) if want_map else None
+        torch.cuda.current_stream(self.device).synchronize()  # inputs complete before submission
+        req = Request(nside, lmax, {"f64": 0, "f32": 1}[dtype], int(iters), float(lam),
+                      cl.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ninv.data_ptr(),
+                      None if mask is None else mask.data_ptr(), data.data_ptr(),
+                      torch.view_as_real(s_alm).data_ptr(),
+                      None if s_map is None else s_map.data_ptr())
+        rid = ctypes.c_uint64()
+        _check(_lib.mfwf_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)))
+        self._live[rid.value] = (ninv, mask, data, s_alm, s_map)
+        return rid.value, s_alm, s_map
+
+    @staticmethod
+    def pool_bytes(nside, lmax, dtype="f64", slots=64) -> float:
+        """Bytes a pool of this shape is charged against the server's HBM budget."""
+        out = ctypes.c_double()
+        _check(load().mfwf_server_pool_bytes(nside, lmax, {"f64": 0, "f32": 1}[dtype], slots,
+                                             ctypes.byref(out)))
+        return out.value
+
+    def done(self, rid) -> bool:
+        d = ctypes.c_int()
+        _check(_lib.mfwf_server_poll(self._h, rid, ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, rid) -> float:
+        lat = ctypes.c_double()
+        try:
+            _check(_lib.mfwf_server_wait(self._h, rid, ctypes.byref(lat)))
+        finally:
+            self._live.pop(rid, None)
+        return lat.value
+
+    def stats(self) -> dict:
+        out = (ctypes.c_double * 8)()
+        _check(_lib.mfwf_server_stats(self._h, out))
+        keys = ["completed", "queued", "occupied_slots", "pools", "pool_bytes", "iterations",
+                "pools_created", "pools_evicted"]
+        return dict(zip(keys, list(out)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.mfwf_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

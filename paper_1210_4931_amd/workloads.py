@@ -252,3 +252,47 @@ def config3(seed: int = 0, nside: int = 512, lmax: int = 1024, lscale: float = 8
     sig = np.stack([a * h[0], b * h[0] + c * h[1], np.sqrt(bb) * h[2]])
     return PolWorkload(f"nside{nside}_lmax{lmax}_TQU", nside, lmax, cl4, sig, g,
                        np.linalg.cholesky(N), pack_sym3(np.linalg.inv(N)), mask)
+
+
+
+# ---- serving requests ----------------------------------------------------------------------
+
+@dataclasses.dataclass
+class ServeRequest:
+    """One independent temperature Wiener-filter request."""
+    rid: int
+    nside: int
+    lmax: int
+    dtype: str
+    cl: np.ndarray
+    noise_var: np.ndarray
+    mask: np.ndarray
+    signal_alm: np.ndarray
+    noise_white: np.ndarray
+
+
+def serve_request(rid: int, nsides=(128, 256, 512, 1024), lscale: float = 1500.0,
+                  ndisc: int = 50) -> ServeRequest:
+    """A serving request seeded by its id: nside uniform over `nsides`, lmax = 2 nside,
+    C_l = 6000/(l(l+1)) exp(-(l/1500)^2), hits = 10^(3u) (a 1000x span), noise variance
+    30^2/hits, a sky cut f ~ U[0.10, 0.30] made of the band |z| < 0.75 f and `ndisc` discs
+    whose common radius gives the rest, 2 pi (1 - cos r) ndisc = 0.25 f 4 pi (overlaps
+    ignored), dtype FP32 or FP64 with probability 1/2.  Draw order: shape, dtype, cut,
+    signal, noise, disc centres, hits."""
+    rng = np.random.Generator(np.random.PCG64(rid))
+    nside = int(nsides[rng.integers(len(nsides))])
+    dtype = "f32" if rng.random() < 0.5 else "f64"
+    f = rng.uniform(0.10, 0.30)
+    lmax = 2 * nside
+    npix = 12 * nside * nside
+    cl = cl_damped(lmax, lscale)
+    h = white_alm(rng, lmax)
+    g = rng.standard_normal(npix)
+    centres = _unit_vectors(rng, ndisc)
+    u = rng.random(npix)
+    radius = math.acos(1.0 - 0.5 * f / ndisc)
+    z, phi = pixel_centres(nside)
+    mask = disc_mask(z, phi, centres, radius, 0.75 * f)
+    ls, _ = alm_l_m(lmax)
+    return ServeRequest(rid, nside, lmax, dtype, cl, 900.0 / 10.0 ** (3.0 * u), mask,
+                        np.sqrt(cl[ls]) * h, g)

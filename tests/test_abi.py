@@ -70,3 +70,14 @@ def test_no_kernel_uses_scratch_memory(lib):
     bad = {k: v.get("ScratchSize [bytes/lane]") for k, v in kernels.items()
            if v.get("ScratchSize [bytes/lane]", "0") != "0"}
     assert not bad, bad
+
+
+def test_server_pool_bytes_is_host_only_and_validates(lib):
+    from paper_1210_4931_amd.mfwf import MFWFError, Server
+    b16 = Server.pool_bytes(16, 32, "f64", 2)
+    assert b16 > 64 * 2**20  # fixed allowance for tables and workspaces
+    assert Server.pool_bytes(512, 1024, "f64", 64) > Server.pool_bytes(512, 1024, "f64", 8)
+    assert Server.pool_bytes(256, 512, "f32", 16) > Server.pool_bytes(128, 256, "f32", 16)
+    for args in [(24, 48, "f64", 2), (16, 65, "f64", 2), (16, 32, "f64", 0), (2048, 4096, "f64", 1)]:
+        with pytest.raises(MFWFError):
+            Server.pool_bytes(*args)
