@@ -11,8 +11,10 @@ seeded noise draws) solved together, Legendre contractions on the matrix cores, 
 FFTs; its accuracy against the FP64 oracle (1e-5 relative) is checked by the GPU tests.  One
 step = one batched solve, value = solved maps per second.  Reported beside it: the plain FP64
 single-solve path (1 map, every step FP64) with its latency, the SHT-pair FLOP/s of both
-forms, the roofline position of each form's dominant kernel (HIP events on the plan's stream)
-and the CPU oracle on a bounded sample of the same solve.
+forms, the roofline position of each form's dominant kernel (HIP events on the plan's stream),
+the T, Q, U form, a serving stream of mixed-shape requests (solves/s and p50/p99 latency at
+saturation and under Poisson arrivals at 0.8 of it) and the CPU oracle on a bounded sample
+of the same solve.
 """
 import argparse
 import json
@@ -126,6 +128,9 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-tqu", action="store_true", help="skip the T, Q, U measurement")
     ap.add_argument("--tqu-steps", type=int, default=2)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=100,
+                    help="requests per serving phase (saturation, Poisson at 0.8 of it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the solver on a single MI355X "
@@ -217,6 +222,10 @@ def main():
     del p32
     if not args.no_tqu:
         out["tqu_fp64"] = tqu_fp64(nside, lmax, K, args.tqu_steps, use_graph)
+    if not args.no_serve:
+        from paper_1210_4931_amd.serving_bench import run_serving
+        out["serving"] = run_serving(nsides=(128, 256, 512), requests=args.serve_requests,
+                                     loads=(0.8,), K=K)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nside, lmax, K, wl, d1.cpu().numpy()[0],
                                            wl.mask / wl.noise_var)

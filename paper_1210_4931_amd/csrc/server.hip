@@ -5,9 +5,12 @@
 // `slots` map slots, each slot holding its own M row and tau.  A worker thread
 //   - admits queued requests into free slots at iteration boundaries (M = N^-1 mask,
 //     tau = 1 / max M, rho = M d and s = 0 written into the slot on the pool's stream),
-//   - launches one messenger iteration (Eqs. 3-4) over the occupied slot range of every busy
-//     pool, each pool on its own stream so that pools overlap on the GPU (the iteration is
-//     captured once per slot count and replayed as a hipGraph),
+//   - launches messenger iterations (Eqs. 3-4) over the occupied slot range of busy pools (the
+//     iteration is captured once per slot count and replayed as a hipGraph).  Pools run on a
+//     few server-owned lanes (streams), so that pools on different lanes overlap on the GPU.
+//     Within a lane the worker picks the busy pool that has used the least GPU time (start-
+//     time fair queueing on each iteration's measured duration), so a small pool runs many
+//     iterations while a large one runs one instead of advancing in lockstep with it,
 //   - retires a slot after its K-th iteration, copying s_lm and Y s into the caller's
 //     buffers, and frees the slot for the next request,
 //   - creates a pool when a request needs a new shape and its estimated footprint fits the
@@ -31,6 +34,13 @@
 namespace mfwf {
 
 using Clock = std::chrono::steady_clock;
+
+// Lanes: streams the worker schedules pools onto.  The process has few hardware queues (4
+// by default) and streams beyond them share queues in FIFO order, so the server keeps its
+// own small number of streams and orders the work on each itself.
+static constexpr int kLanes = 2;
+// iterations in flight per lane (host run-ahead bound)
+static constexpr int kLaneDepth = 4;
 
 struct SrvRequest {
     uint64_t id = 0;
@@ -65,21 +75,45 @@ struct Pool {
     std::vector<std::shared_ptr<SrvRequest>> slot;
     std::vector<int> done_iters;
     std::map<int, SlotGraph> graphs;  // by slot count
-    std::deque<hipEvent_t> inflight;  // one event per launched iteration (host run-ahead bound)
     size_t bytes = 0;
     int active = 0;
     Clock::time_point last_used;
+    int lane = 0;                    // index of the server lane whose stream the plan uses
+    double weight = 0.0;             // static cost guess used to balance pools over lanes
+    double vtime = 0.0;              // GPU milliseconds charged to this pool (fair queueing)
+    std::map<int, double> cost_ms;   // measured iteration time by slot count (moving average)
 
     ~Pool() {
+        // iterations and result copies may still be in flight on the lane's stream, which the
+        // server owns
+        if (plan.stream) (void)hipStreamSynchronize(plan.stream);
         for (auto &g : graphs) {
             if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
             if (g.second.graph) (void)hipGraphDestroy(g.second.graph);
         }
-        for (hipEvent_t e : inflight) (void)hipEventDestroy(e);
-        hipStream_t s = plan.stream;
         if (plan_ok) plan_destroy(plan);
-        if (s) (void)hipStreamDestroy(s);
     }
+
+    // expected milliseconds of one iteration over nb slots
+    double est_cost(int nb) const {
+        if (cost_ms.empty()) return 1.0;
+        auto it = cost_ms.lower_bound(nb);
+        if (it != cost_ms.end() && it->first == nb) return it->second;
+        if (it == cost_ms.end()) --it;  // nearest measured slot count, scaled linearly
+        return it->second * (double)nb / (double)it->first;
+    }
+};
+
+// one launched iteration: timing events around its graph
+struct Launch {
+    Pool *pool;
+    int nb;
+    hipEvent_t t0, t1;
+};
+
+struct Lane {
+    hipStream_t stream = nullptr;
+    std::deque<Launch> inflight;
 };
 
 struct Finishing {
@@ -124,6 +158,8 @@ struct mfwf_server_s {
     std::deque<std::shared_ptr<SrvRequest>> pending;          // seen, waiting for a slot
     std::vector<std::unique_ptr<Pool>> pools;
     std::vector<Finishing> finishing;
+    Lane lanes[kLanes];
+    std::vector<hipEvent_t> spare_events;  // timing events for reuse
     // request validation (caller threads)
     std::mutex vmu;
     hipStream_t vstream = nullptr;
@@ -172,8 +208,17 @@ static int pool_graph(Pool &P, int nb, hipGraphExec_t &exec) {
 }
 
 // Put request q into free slot b of pool P (all on the pool's stream, after any earlier step).
-static int admit(Pool &P, int b, const std::shared_ptr<SrvRequest> &q) {
+static int admit(mfwf_server s, Pool &P, int b, const std::shared_ptr<SrvRequest> &q) {
     Plan &p = P.plan;
+    if (P.active == 0) {
+        // a pool that wakes up joins at the least GPU time of the busy pools on its lane, so
+        // that time it spent idle is not credited to it
+        double vmin = -1.0;
+        for (auto &Q : s->pools)
+            if (Q.get() != &P && Q->lane == P.lane && Q->active > 0 && (vmin < 0.0 || Q->vtime < vmin))
+                vmin = Q->vtime;
+        if (vmin > P.vtime) P.vtime = vmin;
+    }
     const long off = (long)b * p.npix;
     MFWF_TRY(launch_mask_product(q->r.ninv, q->r.mask, p.d_M + off, p.npix, p.stream));
     MFWF_TRY(launch_fill(p.d_tau + b, 1, q->tau, p.stream));
@@ -203,6 +248,41 @@ static int retire(mfwf_server s, Pool &P, int b) {
     return MFWF_OK;
 }
 
+static hipEvent_t take_event(mfwf_server s) {
+    hipEvent_t e = nullptr;
+    if (!s->spare_events.empty()) {
+        e = s->spare_events.back();
+        s->spare_events.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+    }
+    return e;
+}
+
+static void fail_pool(mfwf_server s, Pool &P, const std::string &err);
+
+// Retire the finished iterations at the head of a lane: each one's measured duration updates
+// its pool's cost for that slot count.
+static void reap_lane(mfwf_server s, Lane &L) {
+    while (!L.inflight.empty()) {
+        Launch &x = L.inflight.front();
+        const hipError_t e = hipEventQuery(x.t1);
+        if (e == hipErrorNotReady) break;
+        float ms = 0.f;
+        if (e == hipSuccess && hipEventElapsedTime(&ms, x.t0, x.t1) == hipSuccess && ms > 0.f) {
+            auto it = x.pool->cost_ms.find(x.nb);
+            if (it == x.pool->cost_ms.end())
+                x.pool->cost_ms[x.nb] = ms;
+            else
+                it->second = 0.7 * it->second + 0.3 * ms;
+        }
+        if (e != hipSuccess) fail_pool(s, *x.pool, hipGetErrorString(e));
+        s->spare_events.push_back(x.t0);
+        s->spare_events.push_back(x.t1);
+        L.inflight.pop_front();
+    }
+}
+
 static Pool *find_or_create_pool(mfwf_server s, const PoolKey &key, std::string &err, int &status) {
     for (auto &P : s->pools)
         if (P->key == key) return P.get();
@@ -219,7 +299,10 @@ static Pool *find_or_create_pool(mfwf_server s, const PoolKey &key, std::string 
             if (Q.active == 0 && (victim < 0 || Q.last_used < s->pools[victim]->last_used)) victim = (int)i;
         }
         if (victim < 0) return nullptr;  // wait for slots to drain
-        (void)hipStreamSynchronize(s->pools[victim]->plan.stream);
+        // drain the victim's lane so that no launch record refers to it any more
+        Lane &L = s->lanes[s->pools[victim]->lane];
+        (void)hipStreamSynchronize(L.stream);
+        reap_lane(s, L);
         s->used -= s->pools[victim]->bytes;
         s->pools.erase(s->pools.begin() + victim);
         std::lock_guard<std::mutex> lk(s->mu);
@@ -229,14 +312,15 @@ static Pool *find_or_create_pool(mfwf_server s, const PoolKey &key, std::string 
     }
     std::unique_ptr<Pool> P(new Pool());
     P->key = key;
-    hipStream_t st = nullptr;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-        status = MFWF_EDEVICE;
-        err = "stream creation failed";
-        return nullptr;
-    }
-    P->plan.stream = st;  // the pool owns the stream; ~Pool releases plan and stream
-    P->plan_ok = true;    // free whatever a failed creation allocated
+    // the lane with the least static load (maps x pixels x l per slot, FP64 counted twice)
+    P->weight = (double)key.nside * key.nside * key.lmax * (key.dtype == MFWF_F64 ? 2.0 : 1.0);
+    double load[kLanes] = {};
+    for (auto &Q : s->pools) load[Q->lane] += Q->weight;
+    for (int l = 1; l < kLanes; l++)
+        if (load[l] < load[P->lane]) P->lane = l;
+    hipStream_t st = s->lanes[P->lane].stream;
+    P->plan.stream = st;
+    P->plan_ok = true;  // free whatever a failed creation allocated
     status = plan_create(key.nside, key.lmax, 0, key.dtype, s->slots, st, true, P->plan);
     if (status == MFWF_OK) status = plan_set_cl(P->plan, key.cl.data());
     if (status != MFWF_OK) {
@@ -305,56 +389,63 @@ static void worker_main(mfwf_server s) {
                 ++it;
                 continue;
             }
-            st = admit(*P, b, q);
+            st = admit(s, *P, b, q);
             if (st != MFWF_OK) {
                 finish_request(s, q, st, mfwf_last_error());
             }
             it = s->pending.erase(it);
         }
-        // one iteration on every busy pool; retire slots that reach their K
-        for (auto &Pp : s->pools) {
-            Pool &P = *Pp;
-            if (P.active == 0) continue;
-            int nb = 0;
-            for (int k = 0; k < s->slots; k++)
-                if (P.slot[k]) nb = k + 1;
-            hipGraphExec_t exec = nullptr;
-            int st = pool_graph(P, nb, exec);
-            if (st == MFWF_OK && hipGraphLaunch(exec, P.plan.stream) != hipSuccess)
-                st = fail(MFWF_EDEVICE, "graph launch failed");
-            if (st != MFWF_OK) {
-                fail_pool(s, P, mfwf_last_error());
-                continue;
+        // Fill every lane up to kLaneDepth iterations, each time with the busy pool of that
+        // lane that has been charged the least GPU time.
+        bool launched = false;
+        for (int l = 0; l < kLanes; l++) {
+            Lane &L = s->lanes[l];
+            reap_lane(s, L);
+            while ((int)L.inflight.size() < kLaneDepth) {
+                Pool *best = nullptr;
+                for (auto &Q : s->pools)
+                    if (Q->lane == l && Q->active > 0 && (!best || Q->vtime < best->vtime)) best = Q.get();
+                if (!best) break;
+                Pool &P = *best;
+                int nb = 0;
+                for (int k = 0; k < s->slots; k++)
+                    if (P.slot[k]) nb = k + 1;
+                hipGraphExec_t exec = nullptr;
+                int st = pool_graph(P, nb, exec);
+                Launch x{&P, nb, take_event(s), take_event(s)};
+                if (st == MFWF_OK && (!x.t0 || !x.t1))
+                    st = fail(MFWF_EDEVICE, "event creation failed");
+                if (st == MFWF_OK && (hipEventRecord(x.t0, L.stream) != hipSuccess ||
+                                      hipGraphLaunch(exec, L.stream) != hipSuccess ||
+                                      hipEventRecord(x.t1, L.stream) != hipSuccess))
+                    st = fail(MFWF_EDEVICE, "graph launch failed");
+                if (st != MFWF_OK) {
+                    if (x.t0) s->spare_events.push_back(x.t0);
+                    if (x.t1) s->spare_events.push_back(x.t1);
+                    fail_pool(s, P, mfwf_last_error());
+                    continue;
+                }
+                L.inflight.push_back(x);
+                launched = true;
+                P.vtime += P.est_cost(nb);
+                P.last_used = Clock::now();
+                bool any_retire = false;
+                for (int k = 0; k < nb; k++)
+                    if (P.slot[k] && ++P.done_iters[k] >= P.slot[k]->r.iters) any_retire = true;
+                if (any_retire) {
+                    st = plan_finish_alm(P.plan, nb);
+                    for (int k = 0; k < nb && st == MFWF_OK; k++)
+                        if (P.slot[k] && P.done_iters[k] >= P.slot[k]->r.iters) st = retire(s, P, k);
+                    if (st != MFWF_OK) fail_pool(s, P, mfwf_last_error());
+                }
+                int act = 0;
+                for (auto &Q : s->pools) act += Q->active;
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->stat[5] += 1;
+                s->stat[2] = act;
             }
-            P.last_used = Clock::now();
-            bool any_retire = false;
-            for (int k = 0; k < nb; k++)
-                if (P.slot[k] && ++P.done_iters[k] >= P.slot[k]->r.iters) any_retire = true;
-            if (any_retire) {
-                st = plan_finish_alm(P.plan, nb);
-                for (int k = 0; k < nb && st == MFWF_OK; k++)
-                    if (P.slot[k] && P.done_iters[k] >= P.slot[k]->r.iters) st = retire(s, P, k);
-                if (st != MFWF_OK) fail_pool(s, P, mfwf_last_error());
-            }
-            hipEvent_t ev;
-            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
-                (void)hipEventRecord(ev, P.plan.stream);
-                P.inflight.push_back(ev);
-            }
-            while (P.inflight.size() > 3) {  // bound how far the host runs ahead of this pool
-                (void)hipEventSynchronize(P.inflight.front());
-                (void)hipEventDestroy(P.inflight.front());
-                P.inflight.pop_front();
-            }
-            int act = 0;
-            for (auto &Q : s->pools) act += Q->active;
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->stat[5] += 1;
-            s->stat[2] = act;
         }
         // completed copies
-        bool stepped = false;
-        for (auto &P : s->pools) stepped = stepped || P->active > 0;
         for (size_t i = 0; i < s->finishing.size();) {
             hipError_t e = hipEventQuery(s->finishing[i].ev);
             if (e == hipErrorNotReady) {
@@ -366,14 +457,30 @@ static void worker_main(mfwf_server s) {
                            e == hipSuccess ? "" : hipGetErrorString(e));
             s->finishing.erase(s->finishing.begin() + i);
         }
-        if (!stepped && !s->finishing.empty())
-            std::this_thread::sleep_for(std::chrono::microseconds(50));
+        // nothing launched: every lane with busy pools holds kLaneDepth iterations, or only
+        // result copies are outstanding
+        if (!launched) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
-    for (auto &P : s->pools) (void)hipStreamSynchronize(P->plan.stream);
+    for (auto &L : s->lanes) {
+        (void)hipStreamSynchronize(L.stream);
+        reap_lane(s, L);
+    }
     s->pools.clear();
 }
 
 }  // namespace mfwf
+
+// device resources of a server whose worker has stopped (or never started)
+static void release(mfwf_server s) {
+    if (s->vscratch) (void)hipFree(s->vscratch);
+    if (s->vpart) (void)hipFree(s->vpart);
+    if (s->vout) (void)hipFree(s->vout);
+    if (s->vstream) (void)hipStreamDestroy(s->vstream);
+    for (auto &L : s->lanes)
+        if (L.stream) (void)hipStreamDestroy(L.stream);
+    for (hipEvent_t e : s->spare_events) (void)hipEventDestroy(e);
+    delete s;
+}
 
 extern "C" {
 
@@ -397,11 +504,14 @@ int mfwf_server_create(int slots, double hbm_budget_gb, mfwf_server *out) {
     if (!s) return fail(MFWF_ENOMEM, "host allocation failed");
     s->slots = slots;
     s->budget = (size_t)(hbm_budget_gb * 1e9);
-    if (hipGetDevice(&s->device) != hipSuccess ||
-        hipStreamCreateWithFlags(&s->vstream, hipStreamNonBlocking) != hipSuccess ||
-        hipMalloc((void **)&s->vpart, sizeof(double) * 3 * 1024) != hipSuccess ||
-        hipMalloc((void **)&s->vout, sizeof(double) * 8) != hipSuccess) {
-        delete s;
+    bool ok = hipGetDevice(&s->device) == hipSuccess &&
+              hipStreamCreateWithFlags(&s->vstream, hipStreamNonBlocking) == hipSuccess &&
+              hipMalloc((void **)&s->vpart, sizeof(double) * 3 * 1024) == hipSuccess &&
+              hipMalloc((void **)&s->vout, sizeof(double) * 8) == hipSuccess;
+    for (auto &L : s->lanes)
+        ok = ok && hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) == hipSuccess;
+    if (!ok) {
+        release(s);
         return fail(MFWF_EDEVICE, "server set-up failed");
     }
     s->worker = std::thread(worker_main, s);
@@ -495,11 +605,7 @@ int mfwf_server_destroy(mfwf_server s) {
         s->cv_work.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
-    if (s->vscratch) (void)hipFree(s->vscratch);
-    if (s->vpart) (void)hipFree(s->vpart);
-    if (s->vout) (void)hipFree(s->vout);
-    if (s->vstream) (void)hipStreamDestroy(s->vstream);
-    delete s;
+    release(s);
     return MFWF_OK;
 }
 
