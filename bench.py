@@ -37,7 +37,7 @@ KERNELS = ["pixel_update", "fft_fwd", "leg_analysis", "harmonic", "leg_synth", "
 # (x2.0 and x1.0): profiles/gemm_analysis_nside512_lmax1024_b64_hbm_traffic.md.  Valid only
 # for the kernel source they were taken on, identified by the SHA-256 of batched.hip.
 GEMM_TRAFFIC = {"bytes": 4.862e9,
-                "source_sha256": "9e156ef2eef3426aa6b60f49b21257cc37d765fbc38aca695cc24feb58ca8d3e"}
+                "source_sha256": "771752b68a266fa0ffa8179e94e6de4734f980f5e62500789ca1fceffadf63f0"}
 
 
 def measured_traffic():
