@@ -58,18 +58,39 @@ k_fft_fwd(const double *__restrict__ maps, const double *__restrict__ rho,
     const Twiddles tw = load_twiddles(buf, fft_area(fftlen_class, TPB), twlo, twhi, ntwhi);
     if (PIX && tau_b) tau = tau_b[b];  // per-map tau and M rows (serving slots)
     const double lt = lam * tau, l1t = (lam - 1.0) * tau;
-    auto pix = [&](long i) {  // i: pixel index within the map
-        const double x = maps[(long)b * npix + i];
+    // Every class has n <= EPT * TPB, so each thread reads at most EPT pixels of each ring.
+    // All of them are loaded (clamped to the ring, so every address is valid) before any is
+    // used: one memory latency per workgroup instead of one per pixel row.
+    const double *sp = maps + (long)b * npix;
+    const double *rp = rho + (long)b * npix;
+    const double *mp = M + (long)b * mstride;
+    double xN[EPT], xS[EPT], mN[EPT], mS[EPT], rN[EPT], rS[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; u++) {
+        const int j = min((int)threadIdx.x + u * TPB, n - 1);
+        xN[u] = sp[pf.startN + j];
+        xS[u] = sp[pf.startS + j];
+        if constexpr (PIX) {
+            mN[u] = mp[pf.startN + j];
+            mS[u] = mp[pf.startS + j];
+            rN[u] = rp[pf.startN + j];
+            rS[u] = rp[pf.startS + j];
+        }
+    }
+    auto pix = [&](double x, double m, double r) {
         if constexpr (!PIX) {
             return x;
         } else {
-            const double m = M[(long)b * mstride + i];
-            const double num = lt * rho[(long)b * npix + i] + (1.0 - tau * m) * x;
+            const double num = lt * r + (1.0 - tau * m) * x;
             return (lam == 1.0) ? num : num / (1.0 + l1t * m);
         }
     };
-    for (int j = threadIdx.x; j < n; j += TPB)
-        buf[lds_ix(j)] = make_double2(pix(pf.startN + j), equator ? 0.0 : pix(pf.startS + j));
+#pragma unroll
+    for (int u = 0; u < EPT; u++) {
+        const int j = threadIdx.x + u * TPB;
+        if (j < n)
+            buf[lds_ix(j)] = make_double2(pix(xN[u], mN[u], rN[u]), equator ? 0.0 : pix(xS[u], mS[u], rS[u]));
+    }
     __syncthreads();
     ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
     OutT *outN = phase + ((long)b * nring + p) * nm;
@@ -119,7 +140,58 @@ k_fft_inv(const InT *__restrict__ phase, double *__restrict__ maps,
     const int nbins_pass = TPB / T;
     const double sgn_step = pf.half_shift ? -1.0 : 1.0;
     const double sg_stride = (T & 1) ? sgn_step : 1.0;
-    for (int k0 = 0; k0 < n; k0 += nbins_pass) {
+    if (T == 1) {
+        // n > TPB / 2: thread i folds bins k = i + u TPB (n <= EPT * TPB).  The first
+        // positive alias (m = k) and the first negative one (m = k - n, read as conj F(n - k))
+        // of every bin, the only ones when n > lmax, are loaded together (clamped addresses,
+        // values selected); further aliases (rings with n <= lmax) are added after them in
+        // alias order.
+        // bins in flight per thread: FP64 input holds 4 (16 registers each), FP32 input 8
+        constexpr int CH = sizeof(InT) == sizeof(double2) ? 4 : 8;
+        const double2 zero = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int u0 = 0; u0 < EPT; u0 += CH) {
+            InT aN[CH], aS[CH], cN[CH], cS[CH];
+#pragma unroll
+            for (int v = 0; v < CH; v++) {
+                const int kc = min((int)threadIdx.x + (u0 + v) * TPB, n - 1);
+                const int mpos = min(kc, lmax), mneg = min(n - kc, lmax);
+                aN[v] = FN[mpos];
+                aS[v] = FS[mpos];
+                cN[v] = FN[mneg];
+                cS[v] = FS[mneg];
+            }
+#pragma unroll
+            for (int v = 0; v < CH; v++) {
+                const int k = threadIdx.x + (u0 + v) * TPB;
+                if (k >= n) continue;
+                const bool vp = k <= lmax, vn = n - k <= lmax;
+                double2 sN = cadd(vp ? get_c(&aN[v]) : zero, vn ? cscale(cconj(get_c(&cN[v])), sgn_step) : zero);
+                double2 sS = cadd(vp ? get_c(&aS[v]) : zero, vn ? cscale(cconj(get_c(&cS[v])), sgn_step) : zero);
+                if (n <= lmax) {
+                    double sg = sgn_step;
+                    for (int m = k + n; m <= lmax; m += n, sg *= sgn_step) {
+                        sN = cadd(sN, cscale(get_c(FN + m), sg));
+                        sS = cadd(sS, cscale(get_c(FS + m), sg));
+                    }
+                    sg = 1.0;  // sgn_step^2
+                    for (int mm = 2 * n - k; mm <= lmax; mm += n) {
+                        sN = cadd(sN, cscale(cconj(get_c(FN + mm)), sg));
+                        sS = cadd(sS, cscale(cconj(get_c(FS + mm)), sg));
+                        sg *= sgn_step;
+                    }
+                }
+                if (equator) sS = zero;
+                if (pf.half_shift) {
+                    const double2 ph = half_bin_phase(k, n, tw, fftmax);
+                    sN = cmul(sN, ph);
+                    sS = cmul(sS, ph);
+                }
+                buf[lds_ix(k)] = cconj(make_double2(sN.x - sS.y, sN.y + sS.x));
+            }
+        }
+    }
+    for (int k0 = 0; T > 1 && k0 < n; k0 += nbins_pass) {
         const int k = k0 + threadIdx.x / T, t = threadIdx.x % T;
         double2 sN = make_double2(0.0, 0.0), sS = make_double2(0.0, 0.0);
         if (k < n && (int)threadIdx.x < nbins_pass * T) {
