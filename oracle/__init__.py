@@ -69,6 +69,8 @@ def lib():
                                        ctypes.c_int]
         L.or_alm2map_pol_ring.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp]
         L.or_map2alm_pol_m.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp]
+        L.or_alm2map_ring.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp]
+        L.or_map2alm_m.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _dp]
         _lib_handle = L
     return _lib_handle
 
@@ -281,4 +283,21 @@ def map2alm_pol_m(nside, lmax, maps, m):
     maps = _f64(maps)
     out = np.zeros((3, lmax - m + 1), dtype=np.complex128)
     lib().or_map2alm_pol_m(nside, lmax, _p(maps), m, _p(out.view(np.float64)))
+    return out
+
+
+def alm2map_ring(nside, lmax, alm, ring):
+    """The temperature map on one ring (1-based ring index) of the synthesis: [n_phi]."""
+    alm = _c128(alm)
+    z, s, start, nphi, phi0 = rings(nside)
+    out = np.zeros(int(nphi[ring - 1]))
+    lib().or_alm2map_ring(nside, lmax, _p(alm.view(np.float64)), ring, _p(out))
+    return out
+
+
+def map2alm_m(nside, lmax, m_map, m):
+    """a_lm for one m, l = m..lmax, of the temperature analysis (Omega included)."""
+    m_map = _f64(m_map)
+    out = np.zeros(lmax - m + 1, dtype=np.complex128)
+    lib().or_map2alm_m(nside, lmax, _p(m_map), m, _p(out.view(np.float64)))
     return out

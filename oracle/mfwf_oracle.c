@@ -665,6 +665,75 @@ void or_alm2map_pol_ring(int nside, int lmax, const double *alm_in, int i, doubl
     free(F);
 }
 
+/* Sampled outputs of the temperature transforms (Sect. 2.1 basis change): the map on one
+ * ring (1-based ring index i; out[n_phi]) and the coefficients of one m (out[lmax - m + 1],
+ * Omega included).  The per-m analysis takes G_r(m) straight from its definition,
+ * sum_j t_j e^{-i m phi_j}, with the phase argument reduced as (m j mod n_phi). */
+void or_alm2map_ring(int nside, int lmax, const double *alm_in, int i, double *out)
+{
+    const cplx *alm = (const cplx *)alm_in;
+    double z, sth, phi0;
+    long start;
+    int nphi;
+    or_ring(nside, i, &z, &sth, &start, &nphi, &phi0);
+    double *lam = (double *)malloc(sizeof(double) * (lmax + 1));
+    double *eps = (double *)malloc(sizeof(double) * (lmax + 1));
+    cplx *F = (cplx *)malloc(sizeof(cplx) * (lmax + 1));
+    for (int m = 0; m <= lmax; m++) {
+        legendre_eps(lmax, m, eps);
+        legendre_with_eps(lmax, m, z, sth, eps, lam);
+        cplx t = 0;
+        for (int l = m; l <= lmax; l++)
+            t += lam[l - m] * alm[aidx(lmax, l, m)];
+        F[m] = t;
+    }
+    ring_synth(lmax, nphi, phi0, F, out, 0);
+    free(lam);
+    free(eps);
+    free(F);
+}
+
+void or_map2alm_m(int nside, int lmax, const double *map, int m, double *out_in)
+{
+    long npix = or_npix(nside);
+    cplx *out = (cplx *)out_in;
+    int nr = or_nrings(nside), nl = lmax - m + 1;
+    double omega = 4.0 * M_PI / (double)npix;
+    for (int k = 0; k < nl; k++)
+        out[k] = 0;
+#pragma omp parallel
+    {
+        double *lam = (double *)malloc(sizeof(double) * (lmax + 1));
+        double *eps = (double *)malloc(sizeof(double) * (lmax + 1));
+        cplx *acc = (cplx *)calloc(nl, sizeof(cplx));
+        legendre_eps(lmax, m, eps);
+#pragma omp for schedule(dynamic, 16)
+        for (int i = 1; i <= nr; i++) {
+            double z, sth, phi0;
+            long start;
+            int nphi;
+            or_ring(nside, i, &z, &sth, &start, &nphi, &phi0);
+            cplx g = 0;
+            for (int j = 0; j < nphi; j++) {
+                long mj = ((long)m * j) % nphi;
+                double ang = -(double)m * phi0 - 2.0 * M_PI * (double)mj / (double)nphi;
+                g += map[start + j] * (cos(ang) + I * sin(ang));
+            }
+            legendre_with_eps(lmax, m, z, sth, eps, lam);
+            for (int l = m; l <= lmax; l++)
+                acc[l - m] += lam[l - m] * g;
+        }
+#pragma omp critical
+        for (int k = 0; k < nl; k++)
+            out[k] += acc[k];
+        free(lam);
+        free(eps);
+        free(acc);
+    }
+    for (int k = 0; k < nl; k++)
+        out[k] *= omega;
+}
+
 void or_map2alm_pol_m(int nside, int lmax, const double *map, int m, double *out_in)
 {
     long npix = or_npix(nside);

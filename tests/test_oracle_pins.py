@@ -167,6 +167,34 @@ def test_analysis_is_omega_Y_transpose(nside, lmax, direct):
     assert rel(am, ref) < 1e-13
 
 
+@pytest.mark.parametrize("nside,lmax", [(2, 8), (4, 16), (8, 20)])
+def test_sampled_ring_and_m_transforms_vs_scipy(nside, lmax):
+    """The one-ring synthesis and one-m analysis (used for checks at large sizes) against
+    the rows and columns of SciPy's dense Y; lmax = 4 nside folds aliases on every ring.
+    They also equal the T component of the polarized sampled transforms."""
+    rng = np.random.default_rng(nside + 31 * lmax)
+    npix = 12 * nside * nside
+    alm = W.white_alm(rng, lmax)
+    mp = rng.standard_normal(npix)
+    Y = dense.synthesis_matrix(nside, lmax)
+    full = Y @ dense.alm_to_real(alm, lmax)
+    ana = dense.real_to_alm(FOURPI / npix * Y.T @ mp, lmax)
+    z, s, start, nphi, phi0 = oracle.rings(nside)
+    a3 = np.zeros((3, alm.size), complex)
+    a3[0] = alm
+    m3 = np.zeros((3, npix))
+    m3[0] = mp
+    for r in range(1, 4 * nside):
+        got = oracle.alm2map_ring(nside, lmax, alm, r)
+        assert rel(got, full[start[r - 1]:start[r - 1] + nphi[r - 1]]) < 1e-13, r
+        assert rel(got, oracle.alm2map_pol_ring(nside, lmax, a3, r)[0]) < 1e-13, r
+    _, ms = W.alm_l_m(lmax)
+    for m in range(lmax + 1):
+        got = oracle.map2alm_m(nside, lmax, mp, m)
+        assert rel(got, ana[ms == m]) < 1e-12, m
+        assert rel(got, oracle.map2alm_pol_m(nside, lmax, m3, m)[0]) < 1e-12, m
+
+
 def test_monopole():
     nside, lmax = 8, 12
     a = oracle.map2alm(nside, lmax, np.ones(12 * nside * nside))
