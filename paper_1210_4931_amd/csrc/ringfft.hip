@@ -27,6 +27,8 @@
 // Pairs are launched in two classes by transform length: most pairs need at most half the
 // largest length (less LDS and fewer registers per thread, more workgroups per CU); the long
 // Bluestein transforms of the largest polar rings form the second class.
+#include <mutex>
+
 #include "fft_core.h"
 
 namespace mfwf {
@@ -340,7 +342,15 @@ static int inv_lds(int bytes) {
     return MFWF_OK;
 }
 
+// The attribute belongs to the kernel functions, so it is shared by every plan in the
+// process: it only ever rises, so that a plan created later with shorter transforms cannot
+// lower it below what an existing plan's launches ask for.
 int fft_set_lds_limit(size_t bytes) {
+    static std::mutex mu;
+    static size_t current = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    if (bytes <= current) return MFWF_OK;
+    current = bytes;
     MFWF_TRY((fwd_lds<double2, false>((int)bytes)));
     MFWF_TRY((fwd_lds<float2, false>((int)bytes)));
     MFWF_TRY((fwd_lds<float2, true>((int)bytes)));
