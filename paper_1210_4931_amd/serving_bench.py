@@ -18,6 +18,7 @@ Run alone: python -m paper_1210_4931_amd.serving_bench --nsides 128 256 512 --re
 """
 import argparse
 import json
+import sys
 import threading
 import time
 
@@ -61,17 +62,25 @@ def _stats(lat):
             "p99_ms": 1e3 * float(np.percentile(lat, 99)), "mean_ms": 1e3 * float(lat.mean())}
 
 
-def _run(srv, bank, reqs, K, arrivals=None):
+def _log(msg):
+    print("[serving] " + msg, file=sys.stderr, flush=True)
+
+
+def _run(srv, bank, reqs, K, arrivals=None, tag=""):
     """Submit `reqs` (all at once, or at the given arrival times in seconds) and wait for
     them; returns (latencies by request, makespan from the first submission)."""
     ids = [None] * len(reqs)
     lat = [None] * len(reqs)
     ready = threading.Semaphore(0)
+    t_start = time.perf_counter()
 
     def waiter():
         for i in range(len(reqs)):
             ready.acquire()
             lat[i] = srv.wait(ids[i])
+            if tag and (i + 1) % 25 == 0:
+                _log("%s: %d/%d done after %.1f s" % (tag, i + 1, len(reqs),
+                                                     time.perf_counter() - t_start))
 
     th = threading.Thread(target=waiter)
     th.start()
@@ -106,13 +115,15 @@ def run_serving(nsides=(128, 256, 512), requests=120, loads=(0.8,), K=300, slots
     mf = mfwf
     mf.load()
     dev = torch.device("cuda:0")
+    _log("inputs for nside %s" % (list(nsides),))
     bank = _bank(mf, dev, nsides, per_nside)
     srv = mf.Server(slots=slots, hbm_gb=hbm_gb)
     try:
+        _log("warm-up: one pool per (nside, dtype)")
         warm = [(n, dt, 0) for n in nsides for dt in ("f32", "f64")]
         _run(srv, bank, warm, 2)
         reqs = _draw(seed, requests, nsides, per_nside)
-        lat, span = _run(srv, bank, reqs, K)
+        lat, span = _run(srv, bank, reqs, K, tag="saturation")
         sat = _summary(reqs, lat, span)
         rate = sat["solves_per_s"]
         out = {"workload": "serving stream: nside uniform over %s, lmax = 2 nside, FP32/FP64 "
@@ -125,7 +136,7 @@ def run_serving(nsides=(128, 256, 512), requests=120, loads=(0.8,), K=300, slots
             arr = np.cumsum(g.exponential(1.0 / (f * rate), size=requests))
             arr -= arr[0]
             reqs = _draw(seed + (j + 1) * requests, requests, nsides, per_nside)
-            lat, span = _run(srv, bank, reqs, K, arr)
+            lat, span = _run(srv, bank, reqs, K, arr, tag="poisson %.2f" % f)
             out["poisson"][str(f)] = {"offered_per_s": f * rate, **_summary(reqs, lat, span)}
         st = srv.stats()
         out["pools"] = int(st["pools"])
