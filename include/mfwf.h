@@ -66,7 +66,7 @@ typedef enum {
 /*
  * Create a plan for HEALPix resolution nside (power of two, 1..1024) and band limit
  * lmax (1..4*nside).  spin: 0 = temperature only, 2 = temperature and polarization (T, Q, U
- * maps, T, E, B coefficients, 3x3 noise and signal blocks; MFWF_F64 only).  max_batch (>= 1):
+ * maps, T, E, B coefficients, 3x3 noise and signal blocks).  max_batch (>= 1):
  * largest number of
  * maps one call processes at once (larger calls are split).  hip_stream: a hipStream_t
  * or NULL for the null stream.  The plan precomputes the ring geometry (HEALPix,
@@ -75,9 +75,10 @@ typedef enum {
  * together with its two starting values, and ring-FFT tables.  It allocates its device
  * workspaces up front (MFWF_F32 adds the FP32 lambda table, 4 bytes x ring pairs x
  * (lmax+1)(lmax+2)/2 roughly: 2.2 GB at nside 512 / lmax 1024, and column-major work
- * arrays for max_batch maps).  *out receives the handle.
- * Errors: MFWF_EINVAL for out-of-range sizes, spin not 0 or 2, or spin 2 with MFWF_F32;
- * MFWF_ENOMEM, MFWF_EDEVICE.
+ * arrays for max_batch maps; with spin 2 also FP32 tables of the spin-2 functions
+ * F+-_lm = ((2)lambda_lm +- (-2)lambda_lm)/2, two more tables of that size).  *out receives
+ * the handle.
+ * Errors: MFWF_EINVAL for out-of-range sizes or spin not 0 or 2; MFWF_ENOMEM, MFWF_EDEVICE.
  */
 int mfwf_plan_create(int nside, int lmax, int spin, int dtype, int max_batch, void *hip_stream,
                      mfwf_plan *out);

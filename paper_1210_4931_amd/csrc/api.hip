@@ -224,7 +224,7 @@ static void free_plan(Plan &p) {
                     p.d_rho,  p.d_t,    p.d_smap,  p.d_phase,  p.d_apart, p.d_salm,
                     p.d_salm_prev, p.d_sp, p.d_red, p.d_diag, p.d_lam, p.d_loff, p.d_Lp,
                     p.d_minls32, p.d_ana_items, p.d_syn_items, p.d_ana_tab, p.d_syn_tab, p.d_lofi, p.d_phf, p.d_ph32, p.d_a32,
-                    p.d_s32};
+                    p.d_s32, p.d_fp, p.d_fm, p.d_ph32p, p.d_ph32r, p.d_ap32, p.d_ar32, p.d_seb32};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
 }
@@ -430,7 +430,7 @@ static int setup_batched(Plan &p, const std::vector<int> &lstart, const std::vec
     MFWF_TRY(dalloc(&p.d_ana_tab, ana_tab.size(), "analysis XCD lists"));
     MFWF_TRY(dalloc(&p.d_syn_tab, syn_tab.size(), "synthesis XCD lists"));
     MFWF_TRY(dalloc(&p.d_lofi, lofi.size(), "l of index"));
-    MFWF_TRY(dalloc(&p.d_phf, (size_t)p.max_batch * p.nring * p.nm, "ring Fourier rows FP32"));
+    MFWF_TRY(dalloc(&p.d_phf, (size_t)p.ncomp * p.max_batch * p.nring * p.nm, "ring Fourier rows FP32"));
     MFWF_TRY(dalloc(&p.d_ph32, (size_t)p.nring * p.nm * p.C2, "ring Fourier FP32"));
     MFWF_TRY(dalloc(&p.d_a32, (size_t)p.nalm * p.C2, "analysis FP32"));
     MFWF_TRY(dalloc(&p.d_s32, (size_t)p.nalm * p.C2, "synthesis input FP32"));
@@ -445,7 +445,24 @@ static int setup_batched(Plan &p, const std::vector<int> &lstart, const std::vec
     MFWF_HIP(hipMemsetAsync(p.d_ph32, 0, sizeof(float) * (size_t)p.nring * p.nm * p.C2, p.stream));
     MFWF_HIP(hipMemsetAsync(p.d_a32, 0, sizeof(float) * (size_t)p.nalm * p.C2, p.stream));
     MFWF_HIP(hipMemsetAsync(p.d_s32, 0, sizeof(float) * (size_t)p.nalm * p.C2, p.stream));
-    MFWF_TRY(launch_lam_table(p));
+    if (p.spin == 2) {
+        // F+ and F- tables and the four-column arrays of Q, U (E, B)
+        const size_t ph = (size_t)p.nring * p.nm * 2 * p.C2, al = (size_t)p.nalm * 2 * p.C2;
+        MFWF_TRY(dalloc(&p.d_fp, tot, "F+ table"));
+        MFWF_TRY(dalloc(&p.d_fm, tot, "F- table"));
+        MFWF_TRY(dalloc(&p.d_ph32p, ph, "Q, U ring Fourier FP32"));
+        MFWF_TRY(dalloc(&p.d_ph32r, ph, "F- synthesis FP32"));
+        MFWF_TRY(dalloc(&p.d_ap32, al, "F+ analysis FP32"));
+        MFWF_TRY(dalloc(&p.d_ar32, al, "F- analysis FP32"));
+        MFWF_TRY(dalloc(&p.d_seb32, al, "E, B synthesis input FP32"));
+        float *zs[] = {p.d_ph32p, p.d_ph32r};
+        for (float *q : zs) MFWF_HIP(hipMemsetAsync(q, 0, sizeof(float) * ph, p.stream));
+        float *za[] = {p.d_ap32, p.d_ar32, p.d_seb32};
+        for (float *q : za) MFWF_HIP(hipMemsetAsync(q, 0, sizeof(float) * al, p.stream));
+        MFWF_TRY(launch_pol_tables(p));
+    } else {
+        MFWF_TRY(launch_lam_table(p));
+    }
     return MFWF_OK;
 }
 
@@ -485,7 +502,6 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
         return fail(MFWF_EINVAL, "nside must be a power of two in [1, 1024]");
     if (lmax < 1 || lmax > 4 * nside) return fail(MFWF_EINVAL, "lmax must be in [1, 4 nside]");
     if (spin != 0 && spin != 2) return fail(MFWF_EINVAL, "spin must be 0 (T) or 2 (T, Q, U)");
-    if (spin == 2 && dtype != MFWF_F64) return fail(MFWF_EINVAL, "spin 2 plans run in MFWF_F64");
     if (dtype != MFWF_F64 && dtype != MFWF_F32) return fail(MFWF_EINVAL, "dtype must be MFWF_F64 or MFWF_F32");
     if (max_batch < 1 || max_batch > 4096) return fail(MFWF_EINVAL, "max_batch out of range");
     if (dtype == MFWF_F32 && max_batch > 512) return fail(MFWF_EINVAL, "MFWF_F32 plans take max_batch <= 512");
@@ -612,7 +628,7 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     const long B64 = f32 ? 1 : B;  // the FP32 form has its own column-major work arrays
     const long nc = p.ncomp;
     const long ncl = (spin == 2) ? 4 : 1, nmw = (spin == 2) ? 6 : 1;
-    const long apart = (spin == 2) ? (long)pol_ngroup(p) * B * 3 * p.nalm : (long)p.ngroup_max * B64 * p.nalm;
+    const long apart = (spin == 2) ? (long)pol_ngroup(p) * B64 * 3 * p.nalm : (long)p.ngroup_max * B64 * p.nalm;
     MFWF_TRY(dalloc(&p.d_z, p.npair, "z"));
     MFWF_TRY(dalloc(&p.d_A, Atab.size(), "recurrence A"));
     MFWF_TRY(dalloc(&p.d_c, ctab.size(), "recurrence scale"));
@@ -721,7 +737,22 @@ static int iteration_pol(Plan &p, const double *rho, int nb, double lam, bool ke
     return MFWF_OK;
 }
 
+// T, Q, U in the batched FP32 form: FP64 3x3 pixel update, transforms of 3 nb maps with FP32
+// rows, three analysis GEMMs and the 3x3 filter, three synthesis GEMMs
+static int iteration_pol_b(Plan &p, const double *rho, int nb, double lam, bool keep_prev) {
+    MFWF_TRY(launch_pixel_update_pol(rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, lam, p.tau, p.stream));
+    MFWF_TRY(launch_fft_fwd_f32(p, p.d_t, nullptr, 1.0, p.d_phf, 3 * nb));
+    MFWF_TRY(launch_rows_to_cols_pol(p, nb));
+    if (keep_prev) MFWF_TRY(launch_cols_to_alm_pol(p, p.d_salm_prev, nb));
+    MFWF_TRY(pol_analysis_b(p, nb, lam * p.tau * p.omega, kPolFilter));
+    if (keep_prev) MFWF_TRY(launch_cols_to_alm_pol(p, p.d_salm, nb));
+    MFWF_TRY(pol_synthesis_b(p, nb));
+    MFWF_TRY(launch_fft_inv_f32(p, p.d_phf, p.d_smap, 3 * nb));
+    return MFWF_OK;
+}
+
 static int iteration(Plan &p, const double *rho, int nb, double lam, bool keep_prev) {
+    if (p.dtype == MFWF_F32 && p.spin == 2) return iteration_pol_b(p, rho, nb, lam, keep_prev);
     if (p.dtype == MFWF_F32) return iteration_b(p, rho, nb, lam, keep_prev);
     if (p.spin == 2) return iteration_pol(p, rho, nb, lam, keep_prev);
     MFWF_TRY(launch_pixel_update(rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, lam, p.tau, p.stream,
@@ -820,8 +851,11 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
     }
     MFWF_TRY(launch_fill(p.d_smap, nc * p.npix * nb, 0.0, p.stream));
     MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm), 2 * nc * p.nalm * nb, 0.0, p.stream));
-    if (p.dtype == MFWF_F32)  // previous harmonic iterate = 0 (outside any graph capture)
+    if (p.dtype == MFWF_F32) {  // previous harmonic iterate = 0 (outside any graph capture)
         MFWF_HIP(hipMemsetAsync(p.d_s32, 0, sizeof(float) * (size_t)p.nalm * p.C2, p.stream));
+        if (p.spin == 2)
+            MFWF_HIP(hipMemsetAsync(p.d_seb32, 0, sizeof(float) * (size_t)p.nalm * 2 * p.C2, p.stream));
+    }
     long total = 0;
     for (int it : its) total += it;
     const long nchk = o.n_check > 0 ? o.n_check : 0;
@@ -995,6 +1029,12 @@ int mfwf_sht_inv(mfwf_plan plan, const double *alm, double *map, int nmaps) {
     Plan &p = plan->p;
     for (int b0 = 0; b0 < nmaps; b0 += p.max_batch) {
         const int nb = std::min(p.max_batch, nmaps - b0);
+        if (p.spin == 2 && p.dtype == MFWF_F32) {
+            MFWF_TRY(launch_alm_to_cols_pol(p, reinterpret_cast<const double2 *>(alm) + 3L * b0 * p.nalm, nb));
+            MFWF_TRY(pol_synthesis_b(p, nb));
+            MFWF_TRY(launch_fft_inv_f32(p, p.d_phf, map + 3L * b0 * p.npix, 3 * nb));
+            continue;
+        }
         if (p.spin == 2) {
             MFWF_TRY(launch_harmonic_pol(p, reinterpret_cast<const double2 *>(alm) + 3L * b0 * p.nalm,
                                          1, 1.0, 0.0, kHarmCopy, nullptr, p.d_sp, nullptr, nb));
@@ -1025,6 +1065,13 @@ int mfwf_sht_fwd(mfwf_plan plan, const double *map, double *alm, int nmaps) {
     Plan &p = plan->p;
     for (int b0 = 0; b0 < nmaps; b0 += p.max_batch) {
         const int nb = std::min(p.max_batch, nmaps - b0);
+        if (p.spin == 2 && p.dtype == MFWF_F32) {
+            MFWF_TRY(launch_fft_fwd_f32(p, map + 3L * b0 * p.npix, nullptr, 1.0, p.d_phf, 3 * nb));
+            MFWF_TRY(launch_rows_to_cols_pol(p, nb));
+            MFWF_TRY(pol_analysis_b(p, nb, 0.0, kPolRaw));
+            MFWF_TRY(launch_cols_to_alm_pol(p, reinterpret_cast<double2 *>(alm) + 3L * b0 * p.nalm, nb));
+            continue;
+        }
         if (p.spin == 2) {
             MFWF_TRY(launch_fft_fwd(p, map + 3L * b0 * p.npix, p.d_phase, 3 * nb));
             MFWF_TRY(launch_leg_analysis_pol(p, p.d_phase, p.d_apart, nb));
@@ -1061,10 +1108,19 @@ int mfwf_fluctuation_rhs(mfwf_plan plan, const double *g1, const double *h, int 
         const int nb = std::min(p.max_batch, nrhs - b0);
         // x = C^{-1/2} h, then Y x, then rho = M^{1/2} g1 + Omega Y x
         if (p.spin == 2) {
-            MFWF_TRY(launch_harmonic_pol(p, reinterpret_cast<const double2 *>(h) + 3L * b0 * p.nalm,
-                                         1, 1.0, 0.0, kHarmInvSqrtC, nullptr, p.d_sp, nullptr, nb));
-            MFWF_TRY(launch_leg_synth_pol(p, p.d_sp, p.d_phase, nb));
-            MFWF_TRY(launch_fft_inv(p, p.d_phase, p.d_t, 3 * nb));
+            if (p.dtype == MFWF_F32) {
+                // K h in FP64 (the FP32 tables carry c, so the T component is not c-scaled)
+                MFWF_TRY(launch_harmonic_pol(p, reinterpret_cast<const double2 *>(h) + 3L * b0 * p.nalm,
+                                             1, 1.0, 0.0, kHarmInvSqrtC, p.d_sp, nullptr, nullptr, nb));
+                MFWF_TRY(launch_alm_to_cols_pol(p, p.d_sp, nb));
+                MFWF_TRY(pol_synthesis_b(p, nb));
+                MFWF_TRY(launch_fft_inv_f32(p, p.d_phf, p.d_t, 3 * nb));
+            } else {
+                MFWF_TRY(launch_harmonic_pol(p, reinterpret_cast<const double2 *>(h) + 3L * b0 * p.nalm,
+                                             1, 1.0, 0.0, kHarmInvSqrtC, nullptr, p.d_sp, nullptr, nb));
+                MFWF_TRY(launch_leg_synth_pol(p, p.d_sp, p.d_phase, nb));
+                MFWF_TRY(launch_fft_inv(p, p.d_phase, p.d_t, 3 * nb));
+            }
             MFWF_TRY(launch_fluct_combine_pol(g1 + 3L * b0 * p.npix, p.d_M, p.d_t,
                                               rho + 3L * b0 * p.npix, p.npix, nb, p.omega, p.stream));
             continue;
@@ -1142,6 +1198,28 @@ int mfwf_time_kernels(mfwf_plan plan, int nmaps, int reps, double *ms_out) {
     const bool f32 = (p.dtype == MFWF_F32);
     for (int k = 0; k < 6; k++) {
         std::function<int()> f;
+        if (f32 && p.spin == 2) {
+            // 0 pixel update, 1 forward transforms + layout, 2 the three analysis GEMMs,
+            // 3 combination and filter, 4 the three synthesis GEMMs, 5 layout + inverse
+            switch (k) {
+                case 0: f = [&] { return launch_pixel_update_pol(p.d_rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, 1.0, p.tau, p.stream); }; break;
+                case 1: f = [&] { MFWF_TRY(launch_fft_fwd_f32(p, p.d_t, nullptr, 1.0, p.d_phf, 3 * nb)); return launch_rows_to_cols_pol(p, nb); }; break;
+                case 2: f = [&] {
+                    MFWF_TRY(launch_gemm_analysis_raw(p, nb, 2, p.d_lam, p.d_ph32, p.d_a32, 0));
+                    MFWF_TRY(launch_gemm_analysis_raw(p, nb, 4, p.d_fp, p.d_ph32p, p.d_ap32, 0));
+                    return launch_gemm_analysis_raw(p, nb, 4, p.d_fm, p.d_ph32p, p.d_ar32, 1); }; break;
+                case 3: f = [&] { return launch_pol_combine(p, p.tau * p.omega, kPolFilter); }; break;
+                case 4: f = [&] {
+                    MFWF_TRY(launch_gemm_synthesis_on(p, nb, 2, p.d_lam, p.d_s32, p.d_ph32, 0));
+                    MFWF_TRY(launch_gemm_synthesis_on(p, nb, 4, p.d_fp, p.d_seb32, p.d_ph32p, 0));
+                    return launch_gemm_synthesis_on(p, nb, 4, p.d_fm, p.d_seb32, p.d_ph32r, 1); }; break;
+                default: f = [&] { MFWF_TRY(launch_cols_to_rows_pol(p, nb)); return launch_fft_inv_f32(p, p.d_phf, p.d_smap, 3 * nb); }; break;
+            }
+            float ms = 0.f;
+            MFWF_TRY(time_launches(p, reps, f, ms));
+            ms_out[k] = ms / reps;
+            continue;
+        }
         if (f32) {
             switch (k) {
                 case 0: ms_out[k] = 0.0; continue;  // pixel update runs inside the forward transforms

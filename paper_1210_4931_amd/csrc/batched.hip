@@ -144,7 +144,9 @@ static constexpr int kColTile = 128;  // columns per workgroup
 // analysis: tile = (m, 128 values of l, 128 columns); K loop over chunks of 32 ring pairs.
 // Wave w: rows 64 (w & 1) .. +63 of the tile (32 even, 32 odd l + m), columns 64 (w >> 1)
 // .. +63.  Output: raw sums a (if a_out) and/or the Wiener-filtered coefficients
-// s = scale_s C_l / (C_l + lto) a (if s_out), rows [alm][C2].
+// s = scale_s C_l / (C_l + lto) a (if s_out), rows [alm][C2].  Even l + m rows contract
+// G_N + G_S and odd rows G_N - G_S (a table with lambda's mirror symmetry); flip swaps the
+// two, for a table that is odd where lambda is even (the spin-2 F-).
 __global__ void __launch_bounds__(256)
 k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
                 const int *__restrict__ Lp, const int *__restrict__ minls32,
@@ -153,7 +155,7 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
                 const double *__restrict__ cl, float *__restrict__ a_out,
                 float *__restrict__ s_out, double scale_s, double lto, int lmax, int npair,
                 int Rp, int nring, int nm, int C2, int ncols, int ncg,
-                const double *__restrict__ tau_b, double lto_per_tau) {
+                const double *__restrict__ tau_b, double lto_per_tau, int flip) {
     // lambda tile [pair][row] and X_0, X_1 tiles [pair][col]; reused by the epilogue
     __shared__ __align__(16) float lds[32 * (kAnaRows + 4) + 2 * 32 * (kColTile + 4)];
     float (*sl)[kAnaRows + 4] = reinterpret_cast<float (*)[kAnaRows + 4]>(lds);
@@ -203,9 +205,10 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const int e = threadIdx.x + 256 * u, pp = e >> 5, c4 = e & 31;
+            const floatx4 ps = rn[u] + rs[u], ms = rn[u] - rs[u];
             st4(&sl[pp][4 * c4], rl[u]);
-            st4(&sx[0][pp][4 * c4], rn[u] + rs[u]);
-            st4(&sx[1][pp][4 * c4], rn[u] - rs[u]);
+            st4(&sx[0][pp][4 * c4], flip ? ms : ps);
+            st4(&sx[1][pp][4 * c4], flip ? ps : ms);
         }
         __syncthreads();
         const int pn = next_active(pc + 1);
@@ -264,14 +267,15 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
 }
 
 // synthesis: tile = (m, 64 ring pairs, 128 columns); K loop over chunks of 64 values of l.
-// Wave w: pairs 32 (w & 1) .. +31 of the tile, columns 64 (w >> 1) .. +63.
+// Wave w: pairs 32 (w & 1) .. +31 of the tile, columns 64 (w >> 1) .. +63.  The south ring
+// gets E - O (lambda's mirror symmetry), or O - E with flip (the spin-2 F-).
 __global__ void __launch_bounds__(256, 3)
 k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
                  const int *__restrict__ Lp, const int *__restrict__ minls32,
                  const int2 *__restrict__ items, const int *__restrict__ tab, int per_xcd,
                  const float *__restrict__ s32, const long *__restrict__ mofs,
                  float *__restrict__ ph32, int lmax, int npair, int Rp, int nring, int nm,
-                 int C2, int ncols, int ncg) {
+                 int C2, int ncols, int ncg, int flip) {
     // lambda tile [pair][l] (odd stride: no bank conflicts) and coefficient tile [l][col];
     // reused by the epilogue
     __shared__ __align__(16) float lds[64 * (64 + 1) + 64 * (kColTile + 4)];
@@ -357,7 +361,7 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
         for (int r = 0; r < 16; r++) {
             const float E = acc[0][ct][r], O = acc[1][ct][r];
             stage[0][acc_row(r, lane)][lane & 31] = E + O;
-            stage[1][acc_row(r, lane)][lane & 31] = E - O;
+            stage[1][acc_row(r, lane)][lane & 31] = flip ? O - E : E - O;
         }
         __syncthreads();
         const int col = kColTile * cg + 64 * ch + 32 * ct + 4 * (lane & 7);
@@ -459,26 +463,53 @@ int launch_cols_to_rows(const Plan &p, int nb) {
     return MFWF_OK;
 }
 
-static int active_cols(int nb) { return 32 * ((2 * nb + 31) / 32); }
+// active columns of a launch: the real columns of nb maps (per map w floats) rounded up to
+// whole 32-column MFMA tiles; never beyond the padded width (w Bp, a multiple of 32)
+static int active_cols(int nb, int w) { return 32 * ((w * nb + 31) / 32); }
 
 int launch_gemm_analysis(const Plan &p, int nb, float *a_out, float *s_out, double scale_s,
                          double lto, double lto_per_tau) {
-    const int nc = active_cols(nb), ncg = (nc + kColTile - 1) / kColTile;
+    const int nc = active_cols(nb, 2), ncg = (nc + kColTile - 1) / kColTile;
     hipLaunchKernelGGL(k_gemm_analysis, dim3(8 * p.ana_per_xcd * ncg), dim3(256), 0, p.stream,
                        p.d_lam, p.d_loff, p.d_Lp, p.d_minls32, p.d_ana_items, p.d_ana_tab,
                        p.ana_per_xcd, p.d_ph32, p.d_mofs, p.d_cl, a_out, s_out, scale_s, lto,
                        p.lmax, p.npair, p.Rp, p.nring, p.nm, p.C2, nc, ncg,
-                       s_out ? p.d_tau : nullptr, lto_per_tau);
+                       s_out ? p.d_tau : nullptr, lto_per_tau, 0);
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }
 
 int launch_gemm_synthesis(const Plan &p, int nb) {
-    const int nc = active_cols(nb), ncg = (nc + kColTile - 1) / kColTile;
+    const int nc = active_cols(nb, 2), ncg = (nc + kColTile - 1) / kColTile;
     hipLaunchKernelGGL(k_gemm_synthesis, dim3(8 * p.syn_per_xcd * ncg), dim3(256), 0, p.stream,
                        p.d_lam, p.d_loff, p.d_Lp, p.d_minls32, p.d_syn_items, p.d_syn_tab,
                        p.syn_per_xcd, p.d_s32, p.d_mofs, p.d_ph32, p.lmax, p.npair, p.Rp,
-                       p.nring, p.nm, p.C2, nc, ncg);
+                       p.nring, p.nm, p.C2, nc, ncg, 0);
+    MFWF_HIP(hipGetLastError());
+    return MFWF_OK;
+}
+
+// Raw analysis sums a_out[alm][w Bp] = table x cols[m][ring][w Bp] for nb maps of w columns
+int launch_gemm_analysis_raw(const Plan &p, int nb, int w, const float *table, const float *cols,
+                             float *a_out, int flip) {
+    const int C2 = w * p.Bp, nc = active_cols(nb, w), ncg = (nc + kColTile - 1) / kColTile;
+    hipLaunchKernelGGL(k_gemm_analysis, dim3(8 * p.ana_per_xcd * ncg), dim3(256), 0, p.stream,
+                       table, p.d_loff, p.d_Lp, p.d_minls32, p.d_ana_items, p.d_ana_tab,
+                       p.ana_per_xcd, cols, p.d_mofs, p.d_cl, a_out, (float *)nullptr, 0.0, 0.0,
+                       p.lmax, p.npair, p.Rp, p.nring, p.nm, C2, nc, ncg, (const double *)nullptr,
+                       0.0, flip);
+    MFWF_HIP(hipGetLastError());
+    return MFWF_OK;
+}
+
+// Synthesis out[m][ring][w Bp] = table x s_in[alm][w Bp] for nb maps of w columns
+int launch_gemm_synthesis_on(const Plan &p, int nb, int w, const float *table, const float *s_in,
+                             float *out, int flip) {
+    const int C2 = w * p.Bp, nc = active_cols(nb, w), ncg = (nc + kColTile - 1) / kColTile;
+    hipLaunchKernelGGL(k_gemm_synthesis, dim3(8 * p.syn_per_xcd * ncg), dim3(256), 0, p.stream,
+                       table, p.d_loff, p.d_Lp, p.d_minls32, p.d_syn_items, p.d_syn_tab,
+                       p.syn_per_xcd, s_in, p.d_mofs, out, p.lmax, p.npair, p.Rp, p.nring, p.nm,
+                       C2, nc, ncg, flip);
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }

@@ -119,6 +119,14 @@ struct Plan {
     float *d_ph32 = nullptr;     // [nm][nring][C2] ring-Fourier, maps innermost
     float *d_a32 = nullptr;      // [nalm][C2] analysis output
     float *d_s32 = nullptr;      // [nalm][C2] synthesis input
+    // batched FP32 form with spin 2 (T, Q, U); T uses the arrays above
+    float *d_fp = nullptr;       // F+_lm(z_p) FP32, rows like d_lam
+    float *d_fm = nullptr;       // F-_lm(z_p) FP32
+    float *d_ph32p = nullptr;    // [nm][nring][2 C2] Q, U ring-Fourier (analysis); F+ synthesis out
+    float *d_ph32r = nullptr;    // [nm][nring][2 C2] F- synthesis out
+    float *d_ap32 = nullptr;     // [nalm][2 C2] F+ analysis sums
+    float *d_ar32 = nullptr;     // [nalm][2 C2] F- analysis sums
+    float *d_seb32 = nullptr;    // [nalm][2 C2] E, B synthesis input
 };
 
 // ---- plan internals (api.hip) used by the serving runtime -------------------------------
@@ -176,6 +184,22 @@ int launch_gemm_analysis(const Plan &p, int nb, float *a_out, float *s_out, doub
 int launch_gemm_synthesis(const Plan &p, int nb);
 int launch_alm_to_cols(const Plan &p, const double2 *alm, float *x32, int nb, int mode);
 int launch_cols_to_alm(const Plan &p, const float *x32, double2 *alm, int nb, double scale);
+// w real columns per map (width w Bp); flip: the table has the opposite mirror symmetry
+int launch_gemm_analysis_raw(const Plan &p, int nb, int w, const float *table, const float *cols,
+                             float *a_out, int flip);
+int launch_gemm_synthesis_on(const Plan &p, int nb, int w, const float *table, const float *s_in,
+                             float *out, int flip);
+
+// polbatched.hip (batched FP32 form, spin 2)
+enum PolCombineMode { kPolFilter = 0, kPolRaw = 1 };
+int launch_pol_tables(const Plan &p);
+int launch_rows_to_cols_pol(const Plan &p, int nb);            // d_phf -> d_ph32, d_ph32p
+int launch_cols_to_rows_pol(const Plan &p, int nb);            // d_ph32, d_ph32p, d_ph32r -> d_phf
+int launch_pol_combine(const Plan &p, double lto, int mode);   // -> d_s32, d_seb32
+int launch_alm_to_cols_pol(const Plan &p, const double2 *alm, int nb);  // -> d_s32, d_seb32
+int launch_cols_to_alm_pol(const Plan &p, double2 *alm, int nb);        // d_s32, d_seb32 ->
+int pol_analysis_b(const Plan &p, int nb, double lto, int mode);
+int pol_synthesis_b(const Plan &p, int nb);
 
 // polar.hip (spin 2: maps [B][3][npix], alm [B][3][nalm], rows [3B][nring][nm])
 int pol_ngroup(const Plan &p);

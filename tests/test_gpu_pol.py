@@ -134,8 +134,6 @@ def test_pol_errors(mf):
     from paper_1210_4931_amd.mfwf import MFWFError
     nside, lmax = 4, 8
     with pytest.raises(MFWFError):
-        mf.Plan(nside, lmax, spin=2, dtype="f32")
-    with pytest.raises(MFWFError):
         mf.Plan(nside, lmax, spin=1)
     plan = mf.Plan(nside, lmax, spin=2)
     w = W.config3(0, nside, lmax, ndisc=1, band_z=0.0)
