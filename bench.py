@@ -66,37 +66,72 @@ def cpu_baseline(nside, lmax, K, wl, d_host, M):
                       "extrapolated to %d iterations" % (nside, lmax, t2 - t0, per_iter, setup, K)}
 
 
-def tqu_fp64(nside, lmax, K, steps, use_graph):
-    """T, Q, U Wiener filter (FP64, one map of 3 components): Wishart 3x3 noise blocks, the
-    temperature problem's mask, EE/TE/BB spectra from TT; per-kernel times and the FP64
-    roofline position of the spin-2 Legendre analysis."""
+def tqu(nside, lmax, K, steps, use_graph, batch):
+    """T, Q, U Wiener filter: Wishart 3x3 noise blocks, the temperature problem's mask,
+    EE/TE/BB spectra from TT.  The plain FP64 path (one map) and the batched FP32 form
+    (`batch` maps: one signal, seeded noise draws), each with per-stage times and the roofline
+    position of its dominant kernel."""
     import torch
     from paper_1210_4931_amd import mfwf
     from paper_1210_4931_amd import workloads as W
     w = W.config3(0, nside, lmax)
     dev = torch.device("cuda:0")
+    ninv6, mask = torch.as_tensor(w.ninv6).to(dev), torch.as_tensor(w.mask).to(dev)
     plan = mfwf.Plan(nside, lmax, max_batch=1, spin=2)
-    plan.set_covariances(w.cl4, torch.as_tensor(w.ninv6).to(dev),
-                         torch.as_tensor(w.mask).to(dev))
+    plan.set_covariances(w.cl4, ninv6, mask)
     sig = plan.sht_inv(torch.as_tensor(w.signal_alm[None]).to(dev)).cpu().numpy()[0]
-    d = torch.as_tensor(w.data_from_signal_maps(sig)[None]).to(dev)
+    d1 = w.data_from_signal_maps(sig)
+    d = torch.as_tensor(d1[None]).to(dev)
     el, lat = timed_solves(plan, d, K, steps, 1, use_graph)
     kt = dict(zip(KERNELS, plan.time_kernels(1, 5)))
     work = plan.work()[0]
+    del plan
     # per evaluated (l, m, pair) and direction: 3 recurrence, 6 forming F+ and F- from it,
     # 4 for T and 16 for E, B (complex-by-real products with the ring-Fourier values)
     flops = 29.0 * work
     dom = max(("leg_analysis", "leg_synth"), key=lambda k: kt[k])
-    return {"workload": "T, Q, U Wiener filter, nside %d, lmax %d, %d iterations, 3x3 Wishart "
-                        "noise blocks" % (nside, lmax, K),
-            "solves_per_s": steps / el, "ms_per_solve": 1e3 * el / steps,
-            "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
-                           "p99": 1e3 * float(np.percentile(lat, 99))},
-            "kernel_ms": kt,
-            "roofline": {"bound": "alu", "kernel": dom + "_pol",
-                         "achieved": flops / (kt[dom] * 1e-3) / 1e12,
-                         "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
-                         "frac": flops / (kt[dom] * 1e-3) / PEAK_FP64_VALU}}
+    out = {"workload": "T, Q, U Wiener filter, nside %d, lmax %d, %d iterations, 3x3 Wishart "
+                       "noise blocks" % (nside, lmax, K),
+           "fp64_single": {
+               "solves_per_s": steps / el, "ms_per_solve": 1e3 * el / steps,
+               "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
+                              "p99": 1e3 * float(np.percentile(lat, 99))},
+               "kernel_ms": kt,
+               "roofline": {"bound": "alu", "kernel": dom + "_pol",
+                            "achieved": flops / (kt[dom] * 1e-3) / 1e12,
+                            "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
+                            "frac": flops / (kt[dom] * 1e-3) / PEAK_FP64_VALU}}}
+    # batched FP32 form
+    B = batch
+    p32 = mfwf.Plan(nside, lmax, max_batch=B, spin=2, dtype="f32")
+    p32.set_covariances(w.cl4, ninv6, mask)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    chol = torch.as_tensor(w.noise_chol).to(dev)
+    sig_t = torch.as_tensor(sig).to(dev)
+    dB = torch.empty((B, 3, w.npix), dtype=torch.float64, device=dev)
+    for b in range(B):
+        g = torch.randn((w.npix, 3, 1), generator=gen, device=dev, dtype=torch.float64)
+        dB[b] = sig_t + torch.matmul(chol, g)[:, :, 0].T
+    torch.cuda.synchronize()
+    el32, lat32 = timed_solves(p32, dB, K, steps, 1, use_graph)
+    names = ["pixel_update", "fft_fwd", "gemm_analysis", "combine_filter", "gemm_synthesis",
+             "fft_inv"]
+    kt32 = dict(zip(names, p32.time_kernels(B, 3)))
+    # three GEMMs per direction: lambda on 2 columns, F+ and F- on 4 columns per map
+    gflops = 2.0 * work * 10 * B
+    domg = max(("gemm_analysis", "gemm_synthesis"), key=lambda k: kt32[k])
+    out["f32_batched"] = {
+        "batch": B, "solves_per_s": B * steps / el32, "ms_per_step": 1e3 * el32 / steps,
+        "iteration_ms": 1e3 * el32 / steps / K,
+        "latency_ms": {"p50": 1e3 * float(np.percentile(lat32, 50)),
+                       "p99": 1e3 * float(np.percentile(lat32, 99))},
+        "kernel_ms": kt32,
+        "roofline": {"bound": "mfma", "kernel": domg + " (3 launches)",
+                     "achieved": gflops / (kt32[domg] * 1e-3) / 1e12,
+                     "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
+                     "frac": gflops / (kt32[domg] * 1e-3) / PEAK_FP32_MFMA}}
+    return out
 
 
 def timed_solves(plan, d, K, steps, warmup, use_graph):
@@ -128,6 +163,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-tqu", action="store_true", help="skip the T, Q, U measurement")
     ap.add_argument("--tqu-steps", type=int, default=2)
+    ap.add_argument("--tqu-batch", type=int, default=32, help="maps per batched T, Q, U solve")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--serve-requests", type=int, default=100,
                     help="requests per serving phase (saturation, Poisson at 0.8 of it)")
@@ -221,7 +257,7 @@ def main():
     }
     del p32
     if not args.no_tqu:
-        out["tqu_fp64"] = tqu_fp64(nside, lmax, K, args.tqu_steps, use_graph)
+        out["tqu"] = tqu(nside, lmax, K, args.tqu_steps, use_graph, args.tqu_batch)
     if not args.no_serve:
         from paper_1210_4931_amd.serving_bench import run_serving
         out["serving"] = run_serving(nsides=(128, 256, 512), requests=args.serve_requests,
