@@ -188,6 +188,40 @@ def solve(nside, lmax, cl, M, rho, niter=None, lam=None, direct=False, diag=Fals
     return (s_alm, s_map, dg) if diag else (s_alm, s_map)
 
 
+def _l_of_index(lmax):
+    """l of each coefficient in the m-major packing (m, l = m..lmax)."""
+    return np.concatenate([np.arange(m, lmax + 1) for m in range(lmax + 1)])
+
+
+def solve_staged(nside, lmax, cl, M, rho, stages):
+    """The messenger iteration run in stages with truncated transforms (the cooling schedule
+    of Sect. 3): stage (lmax_k, lambda_k, n_k) runs n_k iterations of Eqs. (3)-(4) at
+    lambda_k, with analysis and synthesis up to lmax_k <= lmax; the iterate passes from one
+    stage to the next as its pixel map.  tau = 1 / max M.  Returns (s_alm, s_map), s_alm in
+    the lmax packing with zeros above the last stage's lmax_k."""
+    cl, M, rho = _f64(cl), _f64(M), _f64(rho)
+    npix = 12 * nside * nside
+    tau = 1.0 / M.max()
+    omega = 4.0 * np.pi / npix
+    s_map = np.zeros(npix)
+    s_alm, lk = np.zeros(0, dtype=np.complex128), 0
+    for lk, lam, n in stages:
+        lk, n = int(lk), int(n)
+        C = cl[_l_of_index(lk)]
+        f = np.where(C > 0.0, C / np.where(C > 0.0, C + lam * tau * omega, 1.0), 0.0)
+        for _ in range(n):
+            t = (lam * tau * rho + (1.0 - tau * M) * s_map) / (1.0 + (lam - 1.0) * tau * M)
+            s_alm = f * map2alm(nside, lk, t)
+            s_map = alm2map(nside, lk, s_alm)
+    out = np.zeros(nalm(lmax), dtype=np.complex128)
+    if s_alm.size:
+        ls_full = _l_of_index(lmax)
+        ms_full = np.concatenate([np.full(lmax + 1 - m, m) for m in range(lmax + 1)])
+        keep = (ls_full <= lk) & (ms_full <= lk)
+        out[keep] = s_alm
+    return out, s_map
+
+
 def fluct_rho(nside, lmax, cl, M, g1, h, direct=False):
     """Constrained-realisation source rho = M^{1/2} g1 + Omega Y(C^{-1/2} h) (Eq. 9)."""
     cl, M, g1, h = _f64(cl), _f64(M), _f64(g1), _c128(h)

@@ -340,6 +340,55 @@ def test_wiener_gap_shrinks_with_lmax_over_nside():
     assert gaps[1] < gaps[0] < 0.2
 
 
+def test_staged_solve_without_truncation_equals_the_iteration():
+    nside, lmax = 8, 20
+    wl, d, M = small_problem(nside, lmax)
+    rho = M * d
+    a1, m1 = oracle.solve_staged(nside, lmax, wl.cl, M, rho, [(lmax, 1.0, 30)])
+    b1, n1 = oracle.solve(nside, lmax, wl.cl, M, rho, niter=30)
+    assert rel(a1, b1) < 1e-12 and rel(m1, n1) < 1e-12
+    a2, m2 = oracle.solve_staged(nside, lmax, wl.cl, M, rho, [(lmax, 3.0, 10), (lmax, 1.0, 20)])
+    b2, n2 = oracle.solve(nside, lmax, wl.cl, M, rho, lam=[3.0] * 10 + [1.0] * 20)
+    assert rel(a2, b2) < 1e-12 and rel(m2, n2) < 1e-12
+
+
+def test_staged_solve_with_truncated_transforms_vs_dense():
+    """Stages at lmax_k < lmax (Sect. 3): the same Eqs. (3)-(4) with SciPy's dense Y at each
+    stage's band limit, in the real basis."""
+    nside, lmax = 8, 24
+    wl, d, M = small_problem(nside, lmax)
+    rho = M * d
+    stages = [(10, 5.0, 7), (16, 2.0, 6), (24, 1.0, 5)]
+    got_alm, got_map = oracle.solve_staged(nside, lmax, wl.cl, M, rho, stages)
+    npix = d.size
+    tau, omega = 1.0 / M.max(), FOURPI / npix
+    s_map = np.zeros(npix)
+    for lk, lam, n in stages:
+        Y = dense.synthesis_matrix(nside, lk)
+        C = wl.cl[dense.real_ell(lk)]
+        f = np.where(C > 0, C / np.where(C > 0, C + lam * tau * omega, 1.0), 0.0)
+        for _ in range(n):
+            t = (lam * tau * rho + (1 - tau * M) * s_map) / (1 + (lam - 1) * tau * M)
+            s = f * (omega * Y.T @ t)
+            s_map = Y @ s
+    assert rel(got_map, s_map) < 1e-12
+    assert rel(got_alm, dense.real_to_alm(s, lmax)) < 1e-12
+    # ending on a truncated stage: its coefficients, zeros above its band limit
+    a_first, _ = oracle.solve_staged(nside, lmax, wl.cl, M, rho, stages[:1])
+    Y = dense.synthesis_matrix(nside, 10)
+    C = wl.cl[dense.real_ell(10)]
+    f = np.where(C > 0, C / np.where(C > 0, C + 5.0 * tau * omega, 1.0), 0.0)
+    s_map = np.zeros(npix)
+    for _ in range(7):
+        t = (5.0 * tau * rho + (1 - tau * M) * s_map) / (1 + 4.0 * tau * M)
+        s10 = f * (omega * Y.T @ t)
+        s_map = Y @ s10
+    ls, ms = W.alm_l_m(lmax)
+    low = (ls <= 10) & (ms <= 10)
+    assert np.all(a_first[~low] == 0)
+    assert rel(a_first[low], dense.real_to_alm(s10, 10)) < 1e-12
+
+
 def test_chi2_decreases_at_fixed_lambda():
     nside, lmax = 8, 16
     wl, d, M = small_problem(nside, lmax)
