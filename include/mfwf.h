@@ -188,6 +188,45 @@ int mfwf_solve(mfwf_plan plan, const double *input, int nmaps, double *s_alm_out
                double *s_map_out, const mfwf_solve_opts *opts, mfwf_solve_info *info);
 
 /*
+ * ---- Converged Wiener filter with the cooling schedule of Sect. 3 ------------------------
+ * lambda starts from the signal power at l_iter: lambda = max(1, C^TT_{l_iter} / (tau Omega))
+ * (the messenger covariance lambda T then equals the signal power at l_iter, so modes above
+ * l_iter are held back), with l_iter = l_iter0 at first.  Each stage iterates Eqs. (3)-(4)
+ * at its lambda until chi^2(lambda, s) of Eq. (6) reaches a plateau; the next stage takes
+ * l_iter' = min(2 l_iter, l_iter + l_step_max) and its lambda, never below 1.  The solve
+ * ends when the change of chi^2 at lambda = 1 over the full band limit falls below
+ * final_tol sigma_chi2 per iteration (sigma_chi2 = sqrt(2 n_dof), Sect. 2.2).  While lambda
+ * holds back the modes above l_iter, the transforms run only up to
+ * lmax_SHT = min(lmax, l_iter + l_margin) (Sect. 3): those stages run on plans of the same
+ * nside with that band limit, which the plan creates on first use and keeps (covariances
+ * copied from it), and the iterate passes between stages as its pixel map.
+ * A plateau: |chi^2_k - chi^2_{k - n_check}| / n_check < tol sigma_chi2 for every map of
+ * the batch, checked every n_check iterations.  The input is data d (rho = M d).
+ * Temperature plans (spin 0), MFWF_F64 or MFWF_F32.
+ */
+typedef struct {
+    int l_iter0;         /* first l_iter (0: 20)                                          */
+    int l_step_max;      /* largest increase of l_iter per stage (0: 500)                 */
+    int l_margin;        /* lmax_SHT = min(lmax, l_iter + l_margin) (0: 100; < 0: lmax)   */
+    int n_check;         /* iterations between chi^2 evaluations (0: 5)                   */
+    double plateau_tol;  /* stage end, in sigma_chi2 per iteration (0: 1e-2)              */
+    double final_tol;    /* end of the solve at lambda = 1, full lmax (0: 1e-4)           */
+    int max_iters;       /* cap on the iterations of all stages (0: 20000)                */
+    double *stages;      /* host [stage_rows][5] or NULL, per stage: l_iter, lambda,
+                            lmax_SHT, iterations, chi^2 / n_dof at its end (map 0)        */
+    int stage_rows;      /* capacity of stages in rows                                    */
+    int n_stages;        /* out: stages run (rows beyond stage_rows are not written)      */
+    int converged;       /* out: 1 if the final criterion was met, 0 if max_iters ended it */
+} mfwf_cool_opts;
+
+/* input, outputs and info as in mfwf_solve (nmaps maps of data; the maps of one batch of
+ * max_batch share one schedule, and stages reports the last batch's).  opts may be NULL
+ * (all defaults).  Errors: as mfwf_solve, MFWF_EINVAL for negative options or
+ * n_check = 1. */
+int mfwf_solve_cooled(mfwf_plan plan, const double *data, int nmaps, double *s_alm_out,
+                      double *s_map_out, mfwf_cool_opts *opts, mfwf_solve_info *info);
+
+/*
  * Time the plan's kernels on its stream with HIP events (diagnostic).  Runs `reps`
  * back-to-back launches of each stage of one iteration on the current workspaces for
  * nmaps maps and writes the mean duration in milliseconds of each kernel to ms_out:

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <fstream>
 #include <functional>
+#include <map>
 #include <memory>
 #include <new>
 #include <sstream>
@@ -20,6 +21,17 @@
 
 struct mfwf_plan_s {
     mfwf::Plan p;
+    // Cooling schedule (Sect. 3): its early stages run on plans of the same nside with a
+    // smaller band limit, created on first use and kept, by lmax.  cl holds the spectra
+    // given to mfwf_set_covariances ([ncl][lmax+1]); cov_gen counts those calls, so a
+    // sub-plan copies the covariances again after they change.
+    struct Sub {
+        mfwf::Plan p;
+        long gen = -1;
+    };
+    std::map<int, std::unique_ptr<Sub>> sub;
+    std::vector<double> cl;
+    long cov_gen = 0;
 };
 
 namespace mfwf {
@@ -970,6 +982,7 @@ int mfwf_plan_create(int nside, int lmax, int spin, int dtype, int max_batch, vo
 int mfwf_plan_destroy(mfwf_plan plan) {
     if (!plan) return MFWF_OK;
     (void)hipStreamSynchronize(plan->p.stream);
+    for (auto &q : plan->sub) free_plan(q.second->p);
     free_plan(plan->p);
     delete plan;
     return MFWF_OK;
@@ -991,6 +1004,8 @@ int mfwf_set_covariances(mfwf_plan plan, const double *cl, int ncl, const double
                 return fail(MFWF_EINVAL, "each S_l must be finite and positive semi-definite");
         }
         MFWF_TRY(upload(p.d_cl, c, p.stream));
+        plan->cl = c;
+        plan->cov_gen++;
         MFWF_TRY(launch_pol_covariance(ninv, mask, p.d_M, p.npix, p.d_red, p.nred_blocks, p.d_diag,
                                        p.stream));
         double r[3];
@@ -1009,6 +1024,8 @@ int mfwf_set_covariances(mfwf_plan plan, const double *cl, int ncl, const double
     for (double v : c)
         if (!(v >= 0.0) || std::isinf(v)) return fail(MFWF_EINVAL, "C_l must be finite and >= 0");
     MFWF_TRY(upload(p.d_cl, c, p.stream));
+    plan->cl = c;
+    plan->cov_gen++;
     MFWF_TRY(launch_mask_product(ninv, mask, p.d_M, p.npix, p.stream));
     MFWF_TRY(launch_reduce_max_count(p.d_M, p.npix, p.d_red, p.nred_blocks, p.d_diag, p.stream));
     double r[3];
@@ -1176,6 +1193,237 @@ int mfwf_solve(mfwf_plan plan, const double *input, int nmaps, double *s_alm_out
                              info ? info + b0 : nullptr, nmaps, b0));
     }
     MFWF_HIP(hipStreamSynchronize(p.stream));
+    return MFWF_OK;
+}
+
+}  // extern "C"
+
+namespace mfwf {
+
+// The plan of band limit lk for a cooled solve: the plan itself at lk = lmax, else a
+// cached plan of the same nside, spin, dtype and batch with the spectra truncated to lk and
+// the same M and tau.
+static int cooled_plan(mfwf_plan plan, int lk, Plan *&out) {
+    Plan &p = plan->p;
+    if (lk >= p.lmax) {
+        out = &p;
+        return MFWF_OK;
+    }
+    auto it = plan->sub.find(lk);
+    if (it == plan->sub.end()) {
+        std::unique_ptr<mfwf_plan_s::Sub> q(new mfwf_plan_s::Sub());
+        const int st = create(p.nside, lk, p.spin, p.dtype, p.max_batch, p.stream, q->p);
+        if (st != MFWF_OK) {
+            free_plan(q->p);
+            return st;
+        }
+        it = plan->sub.emplace(lk, std::move(q)).first;
+    }
+    mfwf_plan_s::Sub &q = *it->second;
+    if (q.gen != plan->cov_gen) {
+        const int ncl = p.spin == 2 ? 4 : 1;
+        const long L = p.lmax + 1, Lk = lk + 1, nmw = p.spin == 2 ? 6 : 1;
+        std::vector<double> c((size_t)ncl * Lk);
+        for (int r = 0; r < ncl; r++)
+            for (long l = 0; l < Lk; l++) c[r * Lk + l] = plan->cl[r * L + l];
+        MFWF_TRY(upload(q.p.d_cl, c, q.p.stream));
+        MFWF_HIP(hipMemcpyAsync(q.p.d_M, p.d_M, sizeof(double) * nmw * p.npix,
+                                hipMemcpyDeviceToDevice, q.p.stream));
+        MFWF_HIP(hipStreamSynchronize(q.p.stream));
+        q.p.tau = p.tau;
+        q.p.ndof = p.ndof;
+        q.p.have_cov = true;
+        q.gen = plan->cov_gen;
+    }
+    out = &q.p;
+    return MFWF_OK;
+}
+
+// chi^2 and norms of nb maps after an iteration run with keep_prev (host dg[8 nb])
+static int cooled_diag(Plan &q, const double *rho, int nb, double lam, std::vector<double> &dg) {
+    if (q.spin == 2) {
+        MFWF_TRY(launch_chi2_pix_pol(rho, q.d_M, q.d_smap, q.npix, nb, lam, q.tau, q.d_red,
+                                     q.nred_blocks, q.d_diag, q.stream));
+        MFWF_TRY(launch_harm_diag_pol(q, q.d_salm, q.d_salm_prev, nb, q.d_red, q.d_diag));
+    } else {
+        MFWF_TRY(launch_chi2_pix(rho, q.d_M, q.d_smap, q.npix, nb, lam, q.tau, q.d_red,
+                                 q.nred_blocks, q.d_diag, q.stream));
+        MFWF_TRY(launch_harm_diag(q, q.d_salm, q.d_salm_prev, nb, q.d_red, q.d_diag));
+    }
+    MFWF_HIP(hipMemcpyAsync(dg.data(), q.d_diag, sizeof(double) * 8 * nb, hipMemcpyDeviceToHost,
+                            q.stream));
+    MFWF_HIP(hipStreamSynchronize(q.stream));
+    return MFWF_OK;
+}
+
+struct CoolOpts {
+    int l0, step, margin, nchk, max_iters;
+    double plateau, final_tol;
+};
+
+static int cooled_chunk(mfwf_plan plan, const double *data, int nb, double *s_alm_out,
+                        double *s_map_out, const CoolOpts &o, std::vector<double> &stages,
+                        bool &converged, mfwf_solve_info *info) {
+    Plan &p = plan->p;
+    const long nc = p.ncomp;
+    if (p.spin == 2)
+        MFWF_TRY(launch_rho_from_data_pol(data, p.d_M, p.d_rho, p.npix, nb, p.stream));
+    else
+        MFWF_TRY(launch_rho_from_data(data, p.d_M, p.d_rho, p.npix, nb, p.stream));
+    const double *rho = p.d_rho;
+    const double sigma = std::sqrt(2.0 * (double)p.ndof), tomega = p.tau * p.omega;
+    std::vector<double> dg(8L * nb), prev(nb);
+    Plan *cur = nullptr;
+    int l_iter = std::min(o.l0, p.lmax);
+    long total = 0;
+    double lam = 1.0;
+    bool to_one = false;  // l_iter has reached lmax: the next stage is lambda = 1
+    converged = false;
+    stages.clear();
+    for (;;) {
+        // this stage: lambda from the signal power at l_iter (b_l = 1), never below 1
+        lam = to_one ? 1.0 : std::max(1.0, plan->cl[l_iter] / tomega);
+        const int lk = (o.margin < 0 || to_one) ? p.lmax : std::min(p.lmax, l_iter + o.margin);
+        const bool final_stage = (lam == 1.0 && lk == p.lmax);
+        const double tol = final_stage ? o.final_tol : o.plateau;
+        Plan *q = nullptr;
+        MFWF_TRY(cooled_plan(plan, lk, q));
+        if (q != cur) {
+            // the iterate passes as its pixel map (zero at the start)
+            if (cur)
+                MFWF_HIP(hipMemcpyAsync(q->d_smap, cur->d_smap, sizeof(double) * nc * p.npix * nb,
+                                        hipMemcpyDeviceToDevice, q->stream));
+            else
+                MFWF_TRY(launch_fill(q->d_smap, nc * p.npix * nb, 0.0, q->stream));
+            MFWF_TRY(launch_fill(reinterpret_cast<double *>(q->d_salm), 2 * nc * q->nalm * nb, 0.0, q->stream));
+            if (q->dtype == MFWF_F32) {  // harmonic iterate of the FP32 form (outside any capture)
+                MFWF_HIP(hipMemsetAsync(q->d_s32, 0, sizeof(float) * (size_t)q->nalm * q->C2, q->stream));
+                if (q->spin == 2)
+                    MFWF_HIP(hipMemsetAsync(q->d_seb32, 0, sizeof(float) * (size_t)q->nalm * 2 * q->C2, q->stream));
+            }
+            cur = q;
+        }
+        StageGraph sg;
+        bool captured = false, have_prev = false, plateau = false;
+        long its = 0;
+        while (total < o.max_iters) {
+            const long run = std::min<long>(o.nchk, o.max_iters - total);
+            const long plain = run - 1;
+            if (plain >= 2 && q->stream != nullptr) {
+                if (!captured) {
+                    MFWF_TRY(sg.capture(*q, rho, nb, lam));
+                    captured = true;
+                }
+                MFWF_TRY(sg.launch(*q, (int)plain));
+            } else {
+                for (long k = 0; k < plain; k++) MFWF_TRY(iteration(*q, rho, nb, lam, false));
+            }
+            MFWF_TRY(iteration(*q, rho, nb, lam, true));
+            MFWF_TRY(cooled_diag(*q, rho, nb, lam, dg));
+            its += run;
+            total += run;
+            double worst = 0.0;
+            for (int b = 0; b < nb; b++) {
+                const double chi = dg[8 * b] + dg[8 * b + 1];
+                if (!std::isfinite(chi))
+                    return fail(MFWF_ENAN, "chi^2 is not finite: the iteration diverged (lmax above "
+                                           "what the nside's quadrature supports?)");
+                if (have_prev) worst = std::max(worst, std::fabs(chi - prev[b]) / (double)run);
+                prev[b] = chi;
+            }
+            if (have_prev && worst < tol * sigma) {
+                plateau = true;
+                break;
+            }
+            have_prev = true;
+        }
+        stages.insert(stages.end(), {(double)l_iter, lam, (double)lk, (double)its,
+                                     (dg[0] + dg[1]) / (double)p.ndof});
+        if (plateau && final_stage) converged = true;
+        if (converged || total >= o.max_iters) break;
+        // next stage: l_iter doubles (at most + step); once a stage at l_iter = lmax has
+        // settled, lambda goes to 1 over the full band limit
+        if (l_iter >= p.lmax)
+            to_one = true;
+        else
+            l_iter = std::min({2 * l_iter, l_iter + o.step, p.lmax});
+    }
+    // outputs in this plan's packing
+    if (cur != &p) {
+        MFWF_TRY(launch_repack_alm(*cur, cur->d_salm, p, p.d_salm, (int)(nc * nb)));
+        MFWF_HIP(hipMemcpyAsync(p.d_smap, cur->d_smap, sizeof(double) * nc * p.npix * nb,
+                                hipMemcpyDeviceToDevice, p.stream));
+        MFWF_HIP(hipStreamSynchronize(cur->stream));
+    }
+    if (s_alm_out)
+        MFWF_HIP(hipMemcpyAsync(s_alm_out, p.d_salm, sizeof(double2) * nc * p.nalm * nb,
+                                hipMemcpyDeviceToDevice, p.stream));
+    if (s_map_out)
+        MFWF_HIP(hipMemcpyAsync(s_map_out, p.d_smap, sizeof(double) * nc * p.npix * nb,
+                                hipMemcpyDeviceToDevice, p.stream));
+    if (info) {
+        for (int b = 0; b < nb; b++) {
+            mfwf_solve_info &in = info[b];
+            in.iters_done = (int)total;
+            in.lambda = lam;
+            in.chi2 = dg[8 * b + 0] + dg[8 * b + 1];
+            in.chi2_harm = dg[8 * b + 1];
+            in.dnorm = std::sqrt(dg[8 * b + 2]);
+            in.snorm = std::sqrt(dg[8 * b + 3]);
+            in.tau = p.tau;
+            in.n_dof = p.ndof;
+            in.n_checks = 0;
+        }
+    }
+    return MFWF_OK;
+}
+
+}  // namespace mfwf
+
+extern "C" {
+
+int mfwf_solve_cooled(mfwf_plan plan, const double *data, int nmaps, double *s_alm_out,
+                      double *s_map_out, mfwf_cool_opts *opts, mfwf_solve_info *info) {
+    if (!plan || nmaps < 0) return fail(MFWF_EINVAL, "bad argument");
+    Plan &p = plan->p;
+    if (!p.have_cov) return fail(MFWF_ENOCOV, "covariances not set");
+    if (nmaps > 0 && !data) return fail(MFWF_EINVAL, "data is NULL");
+    if (p.spin != 0) return fail(MFWF_EINVAL, "the cooled solve is for temperature plans");
+    mfwf_cool_opts u{};
+    if (opts) u = *opts;
+    if (u.l_iter0 < 0 || u.l_step_max < 0 || u.n_check < 0 || u.max_iters < 0 ||
+        u.plateau_tol < 0.0 || u.final_tol < 0.0 || (u.stages && u.stage_rows < 0))
+        return fail(MFWF_EINVAL, "negative option");
+    CoolOpts o;
+    o.l0 = u.l_iter0 ? u.l_iter0 : 20;
+    o.step = u.l_step_max ? u.l_step_max : 500;
+    o.margin = u.l_margin ? u.l_margin : 100;
+    o.nchk = u.n_check ? u.n_check : 5;
+    o.max_iters = u.max_iters ? u.max_iters : 20000;
+    o.plateau = u.plateau_tol > 0.0 ? u.plateau_tol : 1e-2;
+    o.final_tol = u.final_tol > 0.0 ? u.final_tol : 1e-4;
+    if (o.nchk < 2) return fail(MFWF_EINVAL, "n_check must be >= 2");
+    std::vector<double> stages;
+    bool converged = true;
+    for (int b0 = 0; b0 < nmaps; b0 += p.max_batch) {
+        const int nb = std::min(p.max_batch, nmaps - b0);
+        const long nc = p.ncomp;
+        bool conv = false;
+        MFWF_TRY(cooled_chunk(plan, data + nc * b0 * p.npix, nb,
+                              s_alm_out ? s_alm_out + 2L * nc * b0 * p.nalm : nullptr,
+                              s_map_out ? s_map_out + nc * b0 * p.npix : nullptr, o, stages, conv,
+                              info ? info + b0 : nullptr));
+        converged = converged && conv;
+    }
+    MFWF_HIP(hipStreamSynchronize(p.stream));
+    if (opts) {
+        const int ns = (int)(stages.size() / 5);
+        opts->n_stages = ns;
+        opts->converged = converged ? 1 : 0;
+        if (opts->stages)
+            for (int r = 0; r < std::min(ns, opts->stage_rows); r++)
+                for (int k = 0; k < 5; k++) opts->stages[5 * r + k] = stages[5 * r + k];
+    }
     return MFWF_OK;
 }
 

@@ -117,4 +117,25 @@ int launch_harm_diag(const Plan &p, const double2 *salm, const double2 *salm_pre
     return MFWF_OK;
 }
 
+// Coefficients of rows (maps x components) from the packing of one band limit to another:
+// dst[r][m, l] = src[r][m, l] for l <= lsrc, 0 above (m-major, l = m..lmax in both).
+__global__ void k_repack_alm(const double2 *__restrict__ src, const long *__restrict__ mofs_src,
+                             long nsrc, int lsrc, double2 *__restrict__ dst,
+                             const long *__restrict__ mofs_dst, long ndst, int ldst) {
+    const int m = blockIdx.x;
+    const long r = blockIdx.y;
+    const long od = r * ndst + mofs_dst[m] - m;
+    const long os = (m <= lsrc) ? r * nsrc + mofs_src[m] - m : 0;
+    for (int l = m + threadIdx.x; l <= ldst; l += kHT)
+        dst[od + l] = (l <= lsrc) ? src[os + l] : make_double2(0.0, 0.0);
+}
+
+int launch_repack_alm(const Plan &src, const double2 *a_src, const Plan &dst, double2 *a_dst,
+                      int rows) {
+    hipLaunchKernelGGL(k_repack_alm, dim3(dst.nm, rows), dim3(kHT), 0, dst.stream, a_src,
+                       src.d_mofs, src.nalm, src.lmax, a_dst, dst.d_mofs, dst.nalm, dst.lmax);
+    MFWF_HIP(hipGetLastError());
+    return MFWF_OK;
+}
+
 }  // namespace mfwf

@@ -229,5 +229,9 @@ int launch_harmonic(const Plan &p, const double2 *in, int ngroup, double scale, 
                     double lto_per_tau = 0.0);
 int launch_harm_diag(const Plan &p, const double2 *salm, const double2 *salm_prev, int nb,
                      double *partial, double *diag);
+// coefficients of `rows` maps/components from src's band-limit packing to dst's (zeros above
+// src's lmax), on dst's stream
+int launch_repack_alm(const Plan &src, const double2 *a_src, const Plan &dst, double2 *a_dst,
+                      int rows);
 
 }  // namespace mfwf

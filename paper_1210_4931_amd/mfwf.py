@@ -37,11 +37,19 @@ class SolveInfo(ctypes.Structure):
                 ("n_checks", ctypes.c_int)]
 
 
+class CoolOpts(ctypes.Structure):
+    _fields_ = [("l_iter0", ctypes.c_int), ("l_step_max", ctypes.c_int), ("l_margin", ctypes.c_int),
+                ("n_check", ctypes.c_int), ("plateau_tol", ctypes.c_double),
+                ("final_tol", ctypes.c_double), ("max_iters", ctypes.c_int),
+                ("stages", ctypes.POINTER(ctypes.c_double)), ("stage_rows", ctypes.c_int),
+                ("n_stages", ctypes.c_int), ("converged", ctypes.c_int)]
+
+
 EXPORTED = ["mfwf_plan_create", "mfwf_plan_destroy", "mfwf_set_covariances", "mfwf_sht_inv",
             "mfwf_sht_fwd", "mfwf_fluctuation_rhs", "mfwf_solve", "mfwf_time_kernels",
             "mfwf_plan_work", "mfwf_last_error", "mfwf_server_create", "mfwf_server_submit",
             "mfwf_server_poll", "mfwf_server_wait", "mfwf_server_stats", "mfwf_server_destroy",
-            "mfwf_server_pool_bytes"]
+            "mfwf_server_pool_bytes", "mfwf_solve_cooled"]
 
 
 class Request(ctypes.Structure):
@@ -71,6 +79,8 @@ def load(path: str = LIB_PATH):
     L.mfwf_fluctuation_rhs.argtypes = [vp, vp, vp, ip, vp]
     L.mfwf_solve.argtypes = [vp, vp, ip, vp, vp, ctypes.POINTER(SolveOpts),
                              ctypes.POINTER(SolveInfo)]
+    L.mfwf_solve_cooled.argtypes = [vp, vp, ip, vp, vp, ctypes.POINTER(CoolOpts),
+                                    ctypes.POINTER(SolveInfo)]
     L.mfwf_time_kernels.argtypes = [vp, ip, ip, dp]
     L.mfwf_plan_work.argtypes = [vp, dp]
     L.mfwf_server_create.argtypes = [ip, ctypes.c_double, ctypes.POINTER(vp)]
@@ -250,6 +260,31 @@ class Plan:
         if n_check > 0:
             return s_alm, s_map, info, hist[:infos[0].n_checks] if n else hist
         return s_alm, s_map, info
+
+    def solve_cooled(self, data: torch.Tensor, l_iter0=0, l_step_max=0, l_margin=0, n_check=0,
+                     plateau_tol=0.0, final_tol=0.0, max_iters=0, want_map=True):
+        """Converged Wiener filter with the cooling schedule of Sect. 3 (0 = the default of
+        each option).  Returns (s_alm, s_map or None, [Info] * n, stages, converged), stages a
+        numpy array [n_stages][5] of (l_iter, lambda, lmax_SHT, iterations, chi^2/n_dof)."""
+        import numpy as np
+        n = self._count(data)
+        x = _dev_f64(data, (n, self.ncomp, self.npix))
+        rows = 64
+        st = np.zeros((rows, 5))
+        opts = CoolOpts(int(l_iter0), int(l_step_max), int(l_margin), int(n_check),
+                        float(plateau_tol), float(final_tol), int(max_iters),
+                        st.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), rows, 0, 0)
+        s_alm = self.zeros_alm(n)
+        s_map = self.zeros_map(n) if want_map else None
+        infos = (SolveInfo * n)()
+        self._enter()
+        _check(_lib.mfwf_solve_cooled(self._h, x.data_ptr(), n, torch.view_as_real(s_alm).data_ptr(),
+                                      None if s_map is None else s_map.data_ptr(),
+                                      ctypes.byref(opts), infos))
+        self._leave()
+        info = [Info(i.iters_done, i.lam, i.chi2, i.chi2_harm, i.dnorm, i.snorm, i.tau, i.n_dof,
+                     i.n_checks) for i in infos]
+        return s_alm, s_map, info, st[:min(opts.n_stages, rows)], bool(opts.converged)
 
     def work(self):
         """(Legendre triples evaluated, full triangle pairs*nalm, ring pairs, max FFT length)."""

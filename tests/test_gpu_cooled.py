@@ -1,0 +1,129 @@
+"""Converged Wiener filter with the cooling schedule of Sect. 3 (mfwf_solve_cooled).
+
+The schedule depends on the data through the chi^2 plateaus, so parity replays it: the GPU
+run reports its stages (l_iter, lambda, lmax_SHT, iterations) and the oracle runs the same
+stages with transforms truncated at each stage's lmax_SHT (oracle.solve_staged).  The rules
+of the schedule are checked on the stages themselves, and the converged result against the
+dense fixed point of the iteration.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import dense
+from tests.gpu_util import dev, rel, rel_alm, temperature_problem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1210_4931_amd import mfwf
+    mfwf.load()
+    return mfwf
+
+
+def _check_rules(stages, cl, tau, omega, lmax, l0, margin, step, iters_done):
+    assert int(stages[0][0]) == min(l0, lmax)
+    to_one = False
+    for k, (l_it, lam, lk, n, _) in enumerate(stages):
+        l_it, lk, n = int(l_it), int(lk), int(n)
+        assert n >= 2
+        if k:
+            lp = int(stages[k - 1][0])
+            if lp >= lmax:
+                to_one = True
+                assert l_it == lmax
+            else:
+                assert l_it == min(2 * lp, lp + step, lmax)
+        if to_one:
+            assert lam == 1.0 and lk == lmax
+        else:
+            assert lam == pytest.approx(max(1.0, cl[l_it] / (tau * omega)), rel=1e-12)
+            assert lk == min(lmax, l_it + margin)
+    assert sum(int(s[3]) for s in stages) == iters_done
+
+
+def test_cooled_schedule_rules_and_oracle_replay(mf):
+    """FP64, truncated stages: the rules of the schedule and the oracle's replay."""
+    nside, lmax, l0, margin = 32, 64, 8, 16
+    wl, d, M = temperature_problem(nside, lmax)
+    plan = mf.Plan(nside, lmax)
+    plan.set_covariances(wl.cl, dev(1.0 / wl.noise_var), dev(wl.mask, torch.uint8))
+    s_alm, s_map, info, stages, conv = plan.solve_cooled(dev(d[None]), l_iter0=l0,
+                                                          l_margin=margin, max_iters=900)
+    print("stages (l_iter, lambda, lmax_SHT, iterations, chi2/ndof):\n", stages, conv)
+    assert len(stages) >= 3 and any(int(s[2]) < lmax for s in stages)
+    _check_rules(stages, wl.cl, info[0].tau, 4 * np.pi / M.size, lmax, l0, margin, 500,
+                 info[0].iters_done)
+    ref_alm, ref_map = oracle.solve_staged(nside, lmax, wl.cl, M, M * d,
+                                           [(int(s[2]), s[1], int(s[3])) for s in stages])
+    assert rel_alm(s_alm.cpu().numpy()[0], ref_alm, lmax) < 1e-10
+    assert rel(s_map.cpu().numpy()[0], ref_map) < 1e-10
+
+
+def test_cooled_f32_batch_replay(mf):
+    """The batched FP32 form, three maps sharing one schedule, each against the replay."""
+    nside, lmax, l0, margin = 32, 64, 8, 16
+    wl, d, M = temperature_problem(nside, lmax, seed=1)
+    rng = np.random.default_rng(5)
+    ds = np.stack([d, d + rng.standard_normal(d.size) * np.sqrt(wl.noise_var),
+                   0.5 * d])
+    plan = mf.Plan(nside, lmax, max_batch=4, dtype="f32")
+    plan.set_covariances(wl.cl, dev(1.0 / wl.noise_var), dev(wl.mask, torch.uint8))
+    s_alm, s_map, info, stages, conv = plan.solve_cooled(dev(ds), l_iter0=l0, l_margin=margin,
+                                                          max_iters=300)
+    _check_rules(stages, wl.cl, info[0].tau, 4 * np.pi / M.size, lmax, l0, margin, 500,
+                 info[0].iters_done)
+    sched = [(int(s[2]), s[1], int(s[3])) for s in stages]
+    for b in range(3):
+        ref_alm, ref_map = oracle.solve_staged(nside, lmax, wl.cl, M, M * ds[b], sched)
+        assert rel_alm(s_alm.cpu().numpy()[b], ref_alm, lmax) < 1e-5
+        assert rel(s_map.cpu().numpy()[b], ref_map) < 1e-5
+
+
+def test_cooled_solve_converges_closer_than_plain_iterations(mf):
+    """At a size where the fixed point is a dense solve: the cooled solve meets its final
+    criterion, and ends nearer to the lambda = 1 fixed point than the same number of plain
+    lambda = 1 iterations from s = 0."""
+    nside, lmax = 16, 32
+    wl, d, M = temperature_problem(nside, lmax, seed=2)
+    plan = mf.Plan(nside, lmax)
+    plan.set_covariances(wl.cl, dev(1.0 / wl.noise_var), dev(wl.mask, torch.uint8))
+    s_alm, _, info, stages, conv = plan.solve_cooled(dev(d[None]), l_iter0=4, l_margin=8,
+                                                      max_iters=6000)
+    assert conv
+    n = info[0].iters_done
+    fp = dense.Problem(nside, lmax, wl.cl, M).messenger_fixed_point(M * d)
+    err_cooled = rel(dense.alm_to_real(s_alm.cpu().numpy()[0], lmax), fp)
+    s_plain, _, _ = plan.solve(dev(d[None]), iters=n)
+    err_plain = rel(dense.alm_to_real(s_plain.cpu().numpy()[0], lmax), fp)
+    print("iterations", n, "stages", len(stages), "error vs fixed point: cooled", err_cooled,
+          "plain", err_plain)
+    assert err_cooled < 0.8 * err_plain
+
+
+def test_cooled_errors(mf):
+    from paper_1210_4931_amd.mfwf import MFWFError
+    plan = mf.Plan(8, 16)
+    with pytest.raises(MFWFError, match="status -4"):
+        plan.solve_cooled(torch.zeros((1, 768), dtype=torch.float64, device="cuda"))
+    wl, d, M = temperature_problem(8, 16)
+    plan.set_covariances(wl.cl, dev(1.0 / wl.noise_var), dev(wl.mask, torch.uint8))
+    with pytest.raises(MFWFError):
+        plan.solve_cooled(dev(d[None]), n_check=1)
+    with pytest.raises(MFWFError):
+        plan.solve_cooled(dev(d[None]), l_iter0=-1)
+    # lmax = 4 nside is beyond what the quadrature supports: the iteration diverges and the
+    # solve stops with MFWF_ENAN instead of reporting a plateau
+    plan4 = mf.Plan(8, 32)
+    wl4, d4, _ = temperature_problem(8, 32)
+    plan4.set_covariances(wl4.cl, dev(1.0 / wl4.noise_var), dev(wl4.mask, torch.uint8))
+    with pytest.raises(MFWFError, match="status -6"):
+        plan4.solve_cooled(dev(d4[None]), max_iters=20000)
+    with pytest.raises(MFWFError):
+        mf.Plan(4, 8, spin=2).solve_cooled(torch.zeros((1, 3, 192), dtype=torch.float64,
+                                                       device="cuda"))
