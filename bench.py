@@ -134,6 +134,23 @@ def tqu(nside, lmax, K, steps, use_graph, batch):
     return out
 
 
+def cooled(plan, d):
+    """Converged solve with the cooling schedule of Sect. 3 (mfwf_solve_cooled, default
+    options): one untimed run creates the plans of the truncated stages, the second is
+    timed (wall clock, inputs resident)."""
+    import torch
+    plan.solve_cooled(d, want_map=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, info, st, conv = plan.solve_cooled(d, want_map=False)
+    el = time.perf_counter() - t0
+    n = d.shape[0]
+    return {"maps": n, "seconds": el, "solves_per_s": n / el, "iterations": info[0].iters_done,
+            "converged": conv, "chi2_per_dof": info[0].chi2 / info[0].n_dof,
+            "stages": [[int(x[0]), round(float(x[1]), 4), int(x[2]), int(x[3])] for x in st],
+            "stage_columns": ["l_iter", "lambda", "lmax_SHT", "iterations"]}
+
+
 def timed_solves(plan, d, K, steps, warmup, use_graph):
     import torch
     for _ in range(warmup):
@@ -165,6 +182,8 @@ def main():
     ap.add_argument("--tqu-steps", type=int, default=2)
     ap.add_argument("--tqu-batch", type=int, default=32, help="maps per batched T, Q, U solve")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-cooled", action="store_true",
+                    help="skip the converged solves with the cooling schedule")
     ap.add_argument("--serve-requests", type=int, default=100,
                     help="requests per serving phase (saturation, Poisson at 0.8 of it)")
     args = ap.parse_args()
@@ -206,6 +225,8 @@ def main():
                          "achieved": leg_flops / (kt64[dom64] * 1e-3) / 1e12,
                          "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s",
                          "frac": leg_flops / (kt64[dom64] * 1e-3) / PEAK_FP64_VALU}}
+    if not args.no_cooled:
+        fp64["cooled"] = cooled(p64, d1)
     del p64
 
     # ---- batched FP32 form (headline) --------------------------------------------------
@@ -255,6 +276,8 @@ def main():
                      "traffic": measured_traffic() if dom32 == "leg_analysis" else None},
         "fp64_single": fp64,
     }
+    if not args.no_cooled:
+        out["cooled_f32_batched"] = cooled(p32, dB)
     del p32
     if not args.no_tqu:
         out["tqu"] = tqu(nside, lmax, K, args.tqu_steps, use_graph, args.tqu_batch)
