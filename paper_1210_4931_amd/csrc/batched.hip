@@ -139,14 +139,24 @@ __device__ __forceinline__ void st4(float *q, floatx4 v) { *reinterpret_cast<flo
 __device__ __forceinline__ floatx4 keep4(bool c, floatx4 v) { return c ? v : floatx4{0.f, 0.f, 0.f, 0.f}; }
 
 static constexpr int kAnaRows = 128;  // values of l per analysis tile
-static constexpr int kColTile = 128;  // columns per workgroup
+// Columns per workgroup tile: 64 NCT (NCT column tiles of 32 per wave, two waves across).
+// Launches with at most 64 active columns (up to 32 maps) take NCT = 1, so that no wave
+// computes columns past the batch; every output column sees the same sequence of matrix
+// operations with either tile, so results do not depend on the tile.
+__host__ __device__ constexpr int col_tile(int nct) { return 64 * nct; }
+// LDS floats of a kernel: its main-loop tiles or the epilogue staging (4 waves x 64 rows x
+// 36), whichever is larger
+__host__ __device__ constexpr int lds_floats(int main_floats) {
+    return main_floats > 4 * 64 * 36 ? main_floats : 4 * 64 * 36;
+}
 
-// analysis: tile = (m, 128 values of l, 128 columns); K loop over chunks of 32 ring pairs.
-// Wave w: rows 64 (w & 1) .. +63 of the tile (32 even, 32 odd l + m), columns 64 (w >> 1)
-// .. +63.  Output: raw sums a (if a_out) and/or the Wiener-filtered coefficients
+// analysis: tile = (m, 128 values of l, 64 NCT columns); K loop over chunks of 32 ring
+// pairs.  Wave w: rows 64 (w & 1) .. +63 of the tile (32 even, 32 odd l + m), columns
+// 32 NCT (w >> 1) .. +32 NCT - 1.  Output: raw sums a (if a_out) and/or the Wiener-filtered coefficients
 // s = scale_s C_l / (C_l + lto) a (if s_out), rows [alm][C2].  Even l + m rows contract
 // G_N + G_S and odd rows G_N - G_S (a table with lambda's mirror symmetry); flip swaps the
 // two, for a table that is odd where lambda is even (the spin-2 F-).
+template <int NCT>
 __global__ void __launch_bounds__(256)
 k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
                 const int *__restrict__ Lp, const int *__restrict__ minls32,
@@ -156,10 +166,11 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
                 float *__restrict__ s_out, double scale_s, double lto, int lmax, int npair,
                 int Rp, int nring, int nm, int C2, int ncols, int ncg,
                 const double *__restrict__ tau_b, double lto_per_tau, int flip) {
+    constexpr int CT = col_tile(NCT), NX = CT / 32;  // columns; X float4 loads per thread
     // lambda tile [pair][row] and X_0, X_1 tiles [pair][col]; reused by the epilogue
-    __shared__ __align__(16) float lds[32 * (kAnaRows + 4) + 2 * 32 * (kColTile + 4)];
+    __shared__ __align__(16) float lds[lds_floats(32 * (kAnaRows + 4) + 2 * 32 * (CT + 4))];
     float (*sl)[kAnaRows + 4] = reinterpret_cast<float (*)[kAnaRows + 4]>(lds);
-    float (*sx)[32][kColTile + 4] = reinterpret_cast<float (*)[32][kColTile + 4]>(lds + 32 * (kAnaRows + 4));
+    float (*sx)[32][CT + 4] = reinterpret_cast<float (*)[32][CT + 4]>(lds + 32 * (kAnaRows + 4));
     const XcdTile xt = xcd_tile(tab, per_xcd, ncg);
     if (xt.item < 0) return;
     const int2 it = items[xt.item];
@@ -171,22 +182,27 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
     const int lhi_w = m + kAnaRows * t + 64 * lh + 63;  // last l of this wave's rows
     const int nchunk = Rp / 32;
     const int *ms = minls32 + m * nchunk;
-    floatx16 acc[2][2];  // [parity][column tile]
+    floatx16 acc[2][NCT];  // [parity][column tile]
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
-        for (int b = 0; b < 2; b++)
+        for (int b = 0; b < NCT; b++)
 #pragma unroll
             for (int r = 0; r < 16; r++) acc[a][b][r] = 0.f;
     const float *lrow = lam + loff[m] + kAnaRows * t;
-    const bool wave_on = (kColTile * cg + 64 * ch) < ncols;
-    floatx4 rl[4], rn[4], rs[4];
+    const int wcol = 32 * NCT * ch;  // first column of this wave within the tile
+    const bool wave_on = (CT * cg + wcol) < ncols;
+    floatx4 rl[4], rn[NX], rs[NX];
     auto load = [&](int pc) __attribute__((always_inline)) {
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
+        for (int u = 0; u < 4; u++) {  // lambda: 32 pairs x 128 rows
             const int e = threadIdx.x + 256 * u, pp = e >> 5, c4 = e & 31;
-            const int p = 32 * pc + pp, col = kColTile * cg + 4 * c4;
-            rl[u] = ld4(lrow + (long)p * L + 4 * c4);
+            rl[u] = ld4(lrow + (long)(32 * pc + pp) * L + 4 * c4);
+        }
+#pragma unroll
+        for (int u = 0; u < NX; u++) {  // ring-Fourier: 32 pairs x CT columns
+            const int e = threadIdx.x + 256 * u, pp = e / (CT / 4), c4 = e % (CT / 4);
+            const int p = 32 * pc + pp, col = CT * cg + 4 * c4;
             // loads from clamped in-range addresses, then a value select
             const bool on = p < npair && col < ncols, south = on && (nring - 1 - p != p);
             const int pq = min(p, npair - 1), cq = min(col, ncols - 4);
@@ -205,8 +221,12 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const int e = threadIdx.x + 256 * u, pp = e >> 5, c4 = e & 31;
-            const floatx4 ps = rn[u] + rs[u], ms = rn[u] - rs[u];
             st4(&sl[pp][4 * c4], rl[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < NX; u++) {
+            const int e = threadIdx.x + 256 * u, pp = e / (CT / 4), c4 = e % (CT / 4);
+            const floatx4 ps = rn[u] + rs[u], ms = rn[u] - rs[u];
             st4(&sx[0][pp][4 * c4], flip ? ms : ps);
             st4(&sx[1][pp][4 * c4], flip ? ps : ms);
         }
@@ -219,12 +239,12 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
             for (int kk = 0; kk < 16; kk++) {
                 const int pp = 2 * kk + kq;
                 const float2 a = *reinterpret_cast<const float2 *>(&sl[pp][64 * lh + 2 * i]);
-                const float b00 = sx[0][pp][64 * ch + i], b01 = sx[0][pp][64 * ch + 32 + i];
-                const float b10 = sx[1][pp][64 * ch + i], b11 = sx[1][pp][64 * ch + 32 + i];
-                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b00, acc[0][0], 0, 0, 0);
-                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b01, acc[0][1], 0, 0, 0);
-                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b10, acc[1][0], 0, 0, 0);
-                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b11, acc[1][1], 0, 0, 0);
+#pragma unroll
+                for (int ct = 0; ct < NCT; ct++) {
+                    const float b0 = sx[0][pp][wcol + 32 * ct + i], b1 = sx[1][pp][wcol + 32 * ct + i];
+                    acc[0][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b0, acc[0][ct], 0, 0, 0);
+                    acc[1][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b1, acc[1][ct], 0, 0, 0);
+                }
             }
         }
         pc = pn;
@@ -234,14 +254,14 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
     const long base = mofs[m] - m;
     float (*stage)[36] = reinterpret_cast<float (*)[36]>(lds) + 64 * w;
 #pragma unroll
-    for (int ct = 0; ct < 2; ct++) {
+    for (int ct = 0; ct < NCT; ct++) {
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < 16; r++)
 #pragma unroll
             for (int par = 0; par < 2; par++) stage[2 * acc_row(r, lane) + par][lane & 31] = acc[par][ct][r];
         __syncthreads();
-        const int col = kColTile * cg + 64 * ch + 32 * ct + 4 * (lane & 7);
+        const int col = CT * cg + wcol + 32 * ct + 4 * (lane & 7);
         if (!wave_on || col >= ncols) continue;
 #pragma unroll
         for (int it = 0; it < 8; it++) {
@@ -266,9 +286,10 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
     }
 }
 
-// synthesis: tile = (m, 64 ring pairs, 128 columns); K loop over chunks of 64 values of l.
-// Wave w: pairs 32 (w & 1) .. +31 of the tile, columns 64 (w >> 1) .. +63.  The south ring
+// synthesis: tile = (m, 64 ring pairs, 64 NCT columns); K loop over chunks of 64 values of
+// l.  Wave w: pairs 32 (w & 1) .. +31 of the tile, columns 32 NCT (w >> 1) .. +32 NCT - 1.  The south ring
 // gets E - O (lambda's mirror symmetry), or O - E with flip (the spin-2 F-).
+template <int NCT>
 __global__ void __launch_bounds__(256, 3)
 k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
                  const int *__restrict__ Lp, const int *__restrict__ minls32,
@@ -276,11 +297,12 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
                  const float *__restrict__ s32, const long *__restrict__ mofs,
                  float *__restrict__ ph32, int lmax, int npair, int Rp, int nring, int nm,
                  int C2, int ncols, int ncg, int flip) {
+    constexpr int CT = col_tile(NCT), NV = CT / 16;  // columns; coefficient float4 loads per thread
     // lambda tile [pair][l] (odd stride: no bank conflicts) and coefficient tile [l][col];
     // reused by the epilogue
-    __shared__ __align__(16) float lds[64 * (64 + 1) + 64 * (kColTile + 4)];
+    __shared__ __align__(16) float lds[lds_floats(64 * (64 + 1) + 64 * (CT + 4))];
     float (*sl)[64 + 1] = reinterpret_cast<float (*)[64 + 1]>(lds);
-    float (*ss)[kColTile + 4] = reinterpret_cast<float (*)[kColTile + 4]>(lds + 64 * (64 + 1));
+    float (*ss)[CT + 4] = reinterpret_cast<float (*)[CT + 4]>(lds + 64 * (64 + 1));
     const XcdTile xt = xcd_tile(tab, per_xcd, ncg);
     if (xt.item < 0) return;
     const int2 it = items[xt.item];
@@ -291,17 +313,18 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
     const int nchunk32 = Rp / 32;
     const int ls_tile = min(minls32[m * nchunk32 + 2 * pt], minls32[m * nchunk32 + 2 * pt + 1]);
     const int ls_wave = minls32[m * nchunk32 + 2 * pt + rt];
-    const bool wave_on = (kColTile * cg + 64 * ch) < ncols;
-    floatx16 acc[2][2];  // [parity][column tile]
+    const int wcol = 32 * NCT * ch;  // first column of this wave within the tile
+    const bool wave_on = (CT * cg + wcol) < ncols;
+    floatx16 acc[2][NCT];  // [parity][column tile]
 #pragma unroll
     for (int a = 0; a < 2; a++)
 #pragma unroll
-        for (int b = 0; b < 2; b++)
+        for (int b = 0; b < NCT; b++)
 #pragma unroll
             for (int r = 0; r < 16; r++) acc[a][b][r] = 0.f;
     const float *lrow = lam + loff[m] + (long)(64 * pt) * L;
     const long base = mofs[m];
-    floatx4 rl[4], rv[8];
+    floatx4 rl[4], rv[NV];
     auto load = [&](int rc) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < 4; u++) {
@@ -309,9 +332,9 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
             rl[u] = ld4(lrow + (long)pp * L + 64 * rc + 4 * c4);
         }
 #pragma unroll
-        for (int u = 0; u < 8; u++) {
-            const int e = threadIdx.x + 256 * u, rr = e >> 5, c4 = e & 31;
-            const int r = 64 * rc + rr, col = kColTile * cg + 4 * c4;
+        for (int u = 0; u < NV; u++) {  // coefficients: 64 values of l x CT columns
+            const int e = threadIdx.x + 256 * u, rr = e / (CT / 4), c4 = e % (CT / 4);
+            const int r = 64 * rc + rr, col = CT * cg + 4 * c4;
             rv[u] = keep4(r < Lm && col < ncols, ld4(s32 + (base + min(r, Lm - 1)) * C2 + min(col, ncols - 4)));
         }
     };
@@ -329,8 +352,8 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
             sl[pp][4 * c4 + 3] = rl[u].w;
         }
 #pragma unroll
-        for (int u = 0; u < 8; u++) {
-            const int e = threadIdx.x + 256 * u, rr = e >> 5, c4 = e & 31;
+        for (int u = 0; u < NV; u++) {
+            const int e = threadIdx.x + 256 * u, rr = e / (CT / 4), c4 = e % (CT / 4);
             st4(&ss[rr][4 * c4], rv[u]);
         }
         __syncthreads();
@@ -343,9 +366,10 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
                 for (int kk = 0; kk < 16; kk++) {
                     const int rr = 4 * kk + 2 * kq + par;  // two same-parity l per step
                     const float a = sl[32 * rt + i][rr];
-                    const float b0 = ss[rr][64 * ch + i], b1 = ss[rr][64 * ch + 32 + i];
-                    acc[par][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, acc[par][0], 0, 0, 0);
-                    acc[par][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, acc[par][1], 0, 0, 0);
+#pragma unroll
+                    for (int ct = 0; ct < NCT; ct++)
+                        acc[par][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                            a, ss[rr][wcol + 32 * ct + i], acc[par][ct], 0, 0, 0);
                 }
             }
         }
@@ -355,7 +379,7 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
     // Rows are relative l = m + r, so the parity of r equals the parity of l + m.
     float (*stage)[32][36] = reinterpret_cast<float (*)[32][36]>(lds) + 2 * w;
 #pragma unroll
-    for (int ct = 0; ct < 2; ct++) {
+    for (int ct = 0; ct < NCT; ct++) {
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < 16; r++) {
@@ -364,7 +388,7 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
             stage[1][acc_row(r, lane)][lane & 31] = flip ? O - E : E - O;
         }
         __syncthreads();
-        const int col = kColTile * cg + 64 * ch + 32 * ct + 4 * (lane & 7);
+        const int col = CT * cg + wcol + 32 * ct + 4 * (lane & 7);
         if (!wave_on || col >= ncols) continue;
 #pragma unroll
         for (int it = 0; it < 8; it++) {
@@ -467,51 +491,62 @@ int launch_cols_to_rows(const Plan &p, int nb) {
 // whole 32-column MFMA tiles; never beyond the padded width (w Bp, a multiple of 32)
 static int active_cols(int nb, int w) { return 32 * ((w * nb + 31) / 32); }
 
-int launch_gemm_analysis(const Plan &p, int nb, float *a_out, float *s_out, double scale_s,
-                         double lto, double lto_per_tau) {
-    const int nc = active_cols(nb, 2), ncg = (nc + kColTile - 1) / kColTile;
-    hipLaunchKernelGGL(k_gemm_analysis, dim3(8 * p.ana_per_xcd * ncg), dim3(256), 0, p.stream,
-                       p.d_lam, p.d_loff, p.d_Lp, p.d_minls32, p.d_ana_items, p.d_ana_tab,
-                       p.ana_per_xcd, p.d_ph32, p.d_mofs, p.d_cl, a_out, s_out, scale_s, lto,
-                       p.lmax, p.npair, p.Rp, p.nring, p.nm, p.C2, nc, ncg,
-                       s_out ? p.d_tau : nullptr, lto_per_tau, 0);
+static int analysis_launch(const Plan &p, int nc, int C2, const float *table, const float *cols,
+                           float *a_out, float *s_out, double scale_s, double lto,
+                           const double *tau_b, double lto_per_tau, int flip) {
+    const int nct = nc <= 64 ? 1 : 2, ncg = (nc + col_tile(nct) - 1) / col_tile(nct);
+    const dim3 grid(8 * p.ana_per_xcd * ncg), block(256);
+    if (nct == 1)
+        hipLaunchKernelGGL(k_gemm_analysis<1>, grid, block, 0, p.stream, table, p.d_loff, p.d_Lp,
+                           p.d_minls32, p.d_ana_items, p.d_ana_tab, p.ana_per_xcd, cols, p.d_mofs,
+                           p.d_cl, a_out, s_out, scale_s, lto, p.lmax, p.npair, p.Rp, p.nring,
+                           p.nm, C2, nc, ncg, tau_b, lto_per_tau, flip);
+    else
+        hipLaunchKernelGGL(k_gemm_analysis<2>, grid, block, 0, p.stream, table, p.d_loff, p.d_Lp,
+                           p.d_minls32, p.d_ana_items, p.d_ana_tab, p.ana_per_xcd, cols, p.d_mofs,
+                           p.d_cl, a_out, s_out, scale_s, lto, p.lmax, p.npair, p.Rp, p.nring,
+                           p.nm, C2, nc, ncg, tau_b, lto_per_tau, flip);
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }
 
-int launch_gemm_synthesis(const Plan &p, int nb) {
-    const int nc = active_cols(nb, 2), ncg = (nc + kColTile - 1) / kColTile;
-    hipLaunchKernelGGL(k_gemm_synthesis, dim3(8 * p.syn_per_xcd * ncg), dim3(256), 0, p.stream,
-                       p.d_lam, p.d_loff, p.d_Lp, p.d_minls32, p.d_syn_items, p.d_syn_tab,
-                       p.syn_per_xcd, p.d_s32, p.d_mofs, p.d_ph32, p.lmax, p.npair, p.Rp,
-                       p.nring, p.nm, p.C2, nc, ncg, 0);
+static int synthesis_launch(const Plan &p, int nc, int C2, const float *table, const float *s_in,
+                            float *out, int flip) {
+    const int nct = nc <= 64 ? 1 : 2, ncg = (nc + col_tile(nct) - 1) / col_tile(nct);
+    const dim3 grid(8 * p.syn_per_xcd * ncg), block(256);
+    if (nct == 1)
+        hipLaunchKernelGGL(k_gemm_synthesis<1>, grid, block, 0, p.stream, table, p.d_loff, p.d_Lp,
+                           p.d_minls32, p.d_syn_items, p.d_syn_tab, p.syn_per_xcd, s_in, p.d_mofs,
+                           out, p.lmax, p.npair, p.Rp, p.nring, p.nm, C2, nc, ncg, flip);
+    else
+        hipLaunchKernelGGL(k_gemm_synthesis<2>, grid, block, 0, p.stream, table, p.d_loff, p.d_Lp,
+                           p.d_minls32, p.d_syn_items, p.d_syn_tab, p.syn_per_xcd, s_in, p.d_mofs,
+                           out, p.lmax, p.npair, p.Rp, p.nring, p.nm, C2, nc, ncg, flip);
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
+}
+
+int launch_gemm_analysis(const Plan &p, int nb, float *a_out, float *s_out, double scale_s,
+                         double lto, double lto_per_tau) {
+    return analysis_launch(p, active_cols(nb, 2), p.C2, p.d_lam, p.d_ph32, a_out, s_out, scale_s,
+                           lto, s_out ? p.d_tau : nullptr, lto_per_tau, 0);
+}
+
+int launch_gemm_synthesis(const Plan &p, int nb) {
+    return synthesis_launch(p, active_cols(nb, 2), p.C2, p.d_lam, p.d_s32, p.d_ph32, 0);
 }
 
 // Raw analysis sums a_out[alm][w Bp] = table x cols[m][ring][w Bp] for nb maps of w columns
 int launch_gemm_analysis_raw(const Plan &p, int nb, int w, const float *table, const float *cols,
                              float *a_out, int flip) {
-    const int C2 = w * p.Bp, nc = active_cols(nb, w), ncg = (nc + kColTile - 1) / kColTile;
-    hipLaunchKernelGGL(k_gemm_analysis, dim3(8 * p.ana_per_xcd * ncg), dim3(256), 0, p.stream,
-                       table, p.d_loff, p.d_Lp, p.d_minls32, p.d_ana_items, p.d_ana_tab,
-                       p.ana_per_xcd, cols, p.d_mofs, p.d_cl, a_out, (float *)nullptr, 0.0, 0.0,
-                       p.lmax, p.npair, p.Rp, p.nring, p.nm, C2, nc, ncg, (const double *)nullptr,
-                       0.0, flip);
-    MFWF_HIP(hipGetLastError());
-    return MFWF_OK;
+    return analysis_launch(p, active_cols(nb, w), w * p.Bp, table, cols, a_out, nullptr, 0.0, 0.0,
+                           nullptr, 0.0, flip);
 }
 
 // Synthesis out[m][ring][w Bp] = table x s_in[alm][w Bp] for nb maps of w columns
 int launch_gemm_synthesis_on(const Plan &p, int nb, int w, const float *table, const float *s_in,
                              float *out, int flip) {
-    const int C2 = w * p.Bp, nc = active_cols(nb, w), ncg = (nc + kColTile - 1) / kColTile;
-    hipLaunchKernelGGL(k_gemm_synthesis, dim3(8 * p.syn_per_xcd * ncg), dim3(256), 0, p.stream,
-                       table, p.d_loff, p.d_Lp, p.d_minls32, p.d_syn_items, p.d_syn_tab,
-                       p.syn_per_xcd, s_in, p.d_mofs, out, p.lmax, p.npair, p.Rp, p.nring, p.nm,
-                       C2, nc, ncg, flip);
-    MFWF_HIP(hipGetLastError());
-    return MFWF_OK;
+    return synthesis_launch(p, active_cols(nb, w), w * p.Bp, table, s_in, out, flip);
 }
 
 int launch_alm_to_cols(const Plan &p, const double2 *alm, float *x32, int nb, int mode) {
