@@ -188,6 +188,31 @@ def solve(nside, lmax, cl, M, rho, niter=None, lam=None, direct=False, diag=Fals
     return (s_alm, s_map, dg) if diag else (s_alm, s_map)
 
 
+def template_matrix(nside, observed):
+    """V of Eq. (12): the monopole and the three dipole templates (1, x, y, z of each pixel
+    centre's unit vector) on the observed pixels, zero elsewhere; [4][npix]."""
+    z, s, start, nphi, phi0 = rings(nside)
+    npix = 12 * nside * nside
+    V = np.zeros((4, npix))
+    for k in range(len(z)):
+        phi = phi0[k] + 2.0 * np.pi * np.arange(nphi[k]) / nphi[k]
+        sl = slice(int(start[k]), int(start[k]) + int(nphi[k]))
+        V[0, sl] = 1.0
+        V[1, sl] = s[k] * np.cos(phi)
+        V[2, sl] = s[k] * np.sin(phi)
+        V[3, sl] = z[k]
+    return V * (np.asarray(observed) != 0)[None, :]
+
+
+def remove_templates(nside, observed, d):
+    """Eq. (12): d = lim_{sigma -> inf} (1 + sigma V V^T)^{-1} d_raw, V = template_matrix.
+    By the Woodbury identity, (1 + sigma V V^T)^{-1} = 1 - V (1/sigma + V^T V)^{-1} V^T, whose
+    limit is the projection d_raw - V (V^T V)^{-1} V^T d_raw."""
+    V = template_matrix(nside, observed)
+    d = _f64(d)
+    return d - V.T @ np.linalg.solve(V @ V.T, V @ d)
+
+
 def _l_of_index(lmax):
     """l of each coefficient in the m-major packing (m, l = m..lmax)."""
     return np.concatenate([np.arange(m, lmax + 1) for m in range(lmax + 1)])

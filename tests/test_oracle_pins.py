@@ -340,6 +340,33 @@ def test_wiener_gap_shrinks_with_lmax_over_nside():
     assert gaps[1] < gaps[0] < 0.2
 
 
+def test_template_removal_is_the_limit_of_eq12():
+    """Eq. (12) literally, (1 + sigma V V^T)^-1 d_raw with a dense solve at finite sigma,
+    approaches the oracle's projection like 1/sigma; the result is orthogonal to every
+    masked template, removes a pure monopole + dipole, ignores added template components,
+    leaves masked pixels unchanged and is idempotent."""
+    nside = 4
+    wl, d, M = small_problem(nside, 8)
+    obs = M > 0
+    V = oracle.template_matrix(nside, obs)
+    got = oracle.remove_templates(nside, obs, d)
+    gaps = []
+    for sigma in (1e2, 1e4, 1e6):  # (larger sigma makes the literal solve ill-conditioned)
+        lit = np.linalg.solve(np.eye(d.size) + sigma * V.T @ V, d)
+        gaps.append(rel(lit, got))
+    assert gaps[1] < 2e-2 * gaps[0] and gaps[2] < 2e-2 * gaps[1] and gaps[2] < 1e-8
+    assert np.abs(V @ got).max() < 1e-12 * np.abs(d).max() * d.size
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal(4)
+    assert rel(oracle.remove_templates(nside, obs, d + a @ V), got) < 1e-12
+    pure = a @ V
+    assert np.abs(oracle.remove_templates(nside, obs, pure)).max() < 1e-12 * np.abs(pure).max()
+    assert np.array_equal(got[~obs], d[~obs])
+    assert rel(oracle.remove_templates(nside, obs, got), got) < 1e-13
+    # the templates are the pixel unit vectors: x^2 + y^2 + z^2 = 1 on observed pixels
+    assert np.allclose((V[1:] ** 2).sum(0)[obs], 1.0, atol=1e-14)
+
+
 def test_staged_solve_without_truncation_equals_the_iteration():
     nside, lmax = 8, 20
     wl, d, M = small_problem(nside, lmax)
