@@ -104,6 +104,21 @@ int mfwf_plan_destroy(mfwf_plan plan);
 int mfwf_set_covariances(mfwf_plan plan, const double *cl, int ncl, const double *ninv,
                          const uint8_t *mask);
 
+/* As mfwf_set_covariances with an instrumental transfer function (Sect. 3): the signal
+ * covariance in the data is S_l = b_l^2 C_l (every spectrum of a spin-2 plan scaled alike),
+ * so the filter returns the beam-convolved sky.  bl: host [lmax+1] finite, or NULL (b = 1).
+ * Errors: as mfwf_set_covariances, MFWF_EINVAL for a non-finite b_l. */
+int mfwf_set_covariances_beam(mfwf_plan plan, const double *cl, int ncl, const double *bl,
+                              const double *ninv, const uint8_t *mask);
+
+/* Monopole and dipole removal of Eq. (12): d = lim_{sigma -> inf} (1 + sigma V V^T)^-1 d_raw
+ * with V the templates 1, x, y, z (unit vector of the pixel centre) on the observed pixels
+ * of the plan's covariances, i.e. d = d_raw - V (V^T V)^-1 V^T d_raw; masked pixels keep
+ * d_raw.  d_raw, d_out: device [nmaps][npix] (spin 2: [nmaps][3][npix], templates on T,
+ * Q and U copied); d_out may equal d_raw.  Errors: MFWF_ENOCOV before
+ * mfwf_set_covariances, MFWF_EINVAL if the templates are degenerate on the observed pixels. */
+int mfwf_remove_templates(mfwf_plan plan, const double *d_raw, double *d_out, int nmaps);
+
 /*
  * Synthesis map = Y alm for nmaps maps (the inverse transform that closes each
  * iteration, Sect. 2.1).  alm: device [nmaps][2*nalm]; map: device [nmaps][npix]

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libmfwf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["api.hip", "pixel.hip", "ringfft.hip", "legendre.hip", "harmonic.hip", "batched.hip",
-           "polar.hip", "server.hip", "polbatched.hip"]
+           "polar.hip", "server.hip", "polbatched.hip", "templates.hip"]
 
 HIPFLAGS = [
     "-std=c++17", "-O3", "-fPIC", "--offload-arch=gfx950",

@@ -1039,6 +1039,78 @@ int mfwf_set_covariances(mfwf_plan plan, const double *cl, int ncl, const double
     return MFWF_OK;
 }
 
+int mfwf_set_covariances_beam(mfwf_plan plan, const double *cl, int ncl, const double *bl,
+                              const double *ninv, const uint8_t *mask) {
+    if (!plan || !cl) return fail(MFWF_EINVAL, "NULL argument");
+    if (!bl) return mfwf_set_covariances(plan, cl, ncl, ninv, mask);
+    const Plan &p = plan->p;
+    if (ncl != (p.spin == 2 ? 4 : 1)) return fail(MFWF_EINVAL, "ncl must be 1 (spin 0) or 4 (spin 2)");
+    const long L1 = p.lmax + 1;
+    std::vector<double> c(cl, cl + ncl * L1);
+    for (long l = 0; l < L1; l++) {
+        if (!std::isfinite(bl[l])) return fail(MFWF_EINVAL, "beam must be finite");
+        for (int r = 0; r < ncl; r++) c[r * L1 + l] *= bl[l] * bl[l];  // S_l = b_l^2 C_l
+    }
+    return mfwf_set_covariances(plan, c.data(), ncl, ninv, mask);
+}
+
+int mfwf_remove_templates(mfwf_plan plan, const double *d_raw, double *d_out, int nmaps) {
+    if (!plan || nmaps < 0) return fail(MFWF_EINVAL, "bad argument");
+    Plan &p = plan->p;
+    if (!p.have_cov) return fail(MFWF_ENOCOV, "covariances not set (the mask comes from them)");
+    if (nmaps == 0) return MFWF_OK;
+    if (!d_raw || !d_out) return fail(MFWF_EINVAL, "NULL array");
+    const long ms = (long)p.ncomp * p.npix;
+    for (int b0 = 0; b0 < nmaps; b0 += p.max_batch) {
+        const int nb = std::min(p.max_batch, nmaps - b0);
+        double *partial = p.d_red, *out14 = p.d_red + template_partial_doubles(nb);
+        MFWF_TRY(launch_template_sums(p, d_raw + b0 * ms, nb, partial, out14));
+        std::vector<double> h(14L * nb), coef(4L * nb);
+        MFWF_HIP(hipMemcpyAsync(h.data(), out14, sizeof(double) * h.size(), hipMemcpyDeviceToHost,
+                                p.stream));
+        MFWF_HIP(hipStreamSynchronize(p.stream));
+        for (int b = 0; b < nb; b++) {
+            // G = V^T V from its upper triangle, c = V^T d; G = L L^T (Cholesky), G k = c
+            const double *u = &h[14L * b];
+            double G[4][4], L[4][4] = {}, y[4], k[4];
+            int q = 0;
+            for (int a = 0; a < 4; a++)
+                for (int e = a; e < 4; e++) G[a][e] = G[e][a] = u[q++];
+            const double tr = G[0][0] + G[1][1] + G[2][2] + G[3][3];
+            for (int i = 0; i < 4; i++) {
+                for (int j = 0; j <= i; j++) {
+                    double v = G[i][j];
+                    for (int t = 0; t < j; t++) v -= L[i][t] * L[j][t];
+                    if (i == j) {
+                        if (!(v > 1e-12 * tr))
+                            return fail(MFWF_EINVAL, "the monopole and dipole templates are "
+                                                     "degenerate on the observed pixels");
+                        L[i][i] = std::sqrt(v);
+                    } else {
+                        L[i][j] = v / L[j][j];
+                    }
+                }
+            }
+            for (int i = 0; i < 4; i++) {
+                double v = u[10 + i];
+                for (int t = 0; t < i; t++) v -= L[i][t] * y[t];
+                y[i] = v / L[i][i];
+            }
+            for (int i = 3; i >= 0; i--) {
+                double v = y[i];
+                for (int t = i + 1; t < 4; t++) v -= L[t][i] * k[t];
+                k[i] = v / L[i][i];
+            }
+            for (int i = 0; i < 4; i++) coef[4L * b + i] = k[i];
+        }
+        MFWF_HIP(hipMemcpyAsync(p.d_diag, coef.data(), sizeof(double) * coef.size(),
+                                hipMemcpyHostToDevice, p.stream));
+        MFWF_TRY(launch_template_subtract(p, d_raw + b0 * ms, d_out + b0 * ms, nb, p.d_diag));
+        MFWF_HIP(hipStreamSynchronize(p.stream));
+    }
+    return MFWF_OK;
+}
+
 int mfwf_sht_inv(mfwf_plan plan, const double *alm, double *map, int nmaps) {
     if (!plan || nmaps < 0) return fail(MFWF_EINVAL, "bad argument");
     if (nmaps == 0) return MFWF_OK;

@@ -221,6 +221,12 @@ int launch_harm_diag_pol(const Plan &p, const double2 *salm, const double2 *salm
 int launch_fluct_combine_pol(const double *g1, const double *M6, const double *ysh, double *rho,
                              long npix, int nb, double omega, hipStream_t s);
 
+// templates.hip (Eq. 12: monopole and dipole template removal)
+int launch_template_sums(const Plan &p, const double *d, int nb, double *partial, double *out14);
+int template_partial_doubles(int nb);
+int launch_template_subtract(const Plan &p, const double *d, double *dout, int nb,
+                             const double *coef);
+
 // harmonic.hip
 enum HarmMode { kHarmWiener = 0, kHarmAnalysis = 1, kHarmInvSqrtC = 2, kHarmCopy = 3 };
 // mode 0 filter: C_l / (C_l + lto), or with p.d_tau set, lto = lto_per_tau * tau_b[map]

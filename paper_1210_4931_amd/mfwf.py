@@ -49,7 +49,8 @@ EXPORTED = ["mfwf_plan_create", "mfwf_plan_destroy", "mfwf_set_covariances", "mf
             "mfwf_sht_fwd", "mfwf_fluctuation_rhs", "mfwf_solve", "mfwf_time_kernels",
             "mfwf_plan_work", "mfwf_last_error", "mfwf_server_create", "mfwf_server_submit",
             "mfwf_server_poll", "mfwf_server_wait", "mfwf_server_stats", "mfwf_server_destroy",
-            "mfwf_server_pool_bytes", "mfwf_solve_cooled"]
+            "mfwf_server_pool_bytes", "mfwf_solve_cooled", "mfwf_set_covariances_beam",
+            "mfwf_remove_templates"]
 
 
 class Request(ctypes.Structure):
@@ -74,6 +75,8 @@ def load(path: str = LIB_PATH):
     L.mfwf_plan_create.argtypes = [ip, ip, ip, ip, ip, vp, ctypes.POINTER(vp)]
     L.mfwf_plan_destroy.argtypes = [vp]
     L.mfwf_set_covariances.argtypes = [vp, dp, ip, vp, vp]
+    L.mfwf_set_covariances_beam.argtypes = [vp, dp, ip, dp, vp, vp]
+    L.mfwf_remove_templates.argtypes = [vp, vp, vp, ip]
     L.mfwf_sht_inv.argtypes = [vp, vp, vp, ip]
     L.mfwf_sht_fwd.argtypes = [vp, vp, vp, ip]
     L.mfwf_fluctuation_rhs.argtypes = [vp, vp, vp, ip, vp]
@@ -183,7 +186,10 @@ class Plan:
         return torch.zeros(self._shape(n, self.nalm), dtype=torch.complex128, device=self.device)
 
     # ---- entry points --------------------------------------------------------------------
-    def set_covariances(self, cl, ninv: torch.Tensor, mask: torch.Tensor | None = None):
+    def set_covariances(self, cl, ninv: torch.Tensor, mask: torch.Tensor | None = None,
+                        beam=None):
+        """Signal spectra C_l (spin 2: rows TT, EE, BB, TE), inverse noise, mask, and an
+        optional transfer function b_l (S_l = b_l^2 C_l)."""
         cl = np.ascontiguousarray(np.asarray(cl, dtype=np.float64).reshape(-1))
         ncl = 4 if self.spin == 2 else 1
         if cl.size != ncl * (self.lmax + 1):
@@ -193,12 +199,28 @@ class Plan:
             if mask.dtype != torch.uint8 or not mask.is_cuda or mask.numel() != self.npix:
                 raise TypeError("mask must be a CUDA uint8 tensor of npix entries")
             mask = mask.contiguous()
+        bl = None
+        if beam is not None:
+            bl = np.ascontiguousarray(np.asarray(beam, dtype=np.float64).reshape(-1))
+            if bl.size != self.lmax + 1:
+                raise ValueError("beam must have lmax + 1 entries")
         self._enter()
-        rc = _lib.mfwf_set_covariances(self._h, cl.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                       ncl, ninv.data_ptr(),
-                                       None if mask is None else mask.data_ptr())
+        rc = _lib.mfwf_set_covariances_beam(
+            self._h, cl.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ncl,
+            None if bl is None else bl.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            ninv.data_ptr(), None if mask is None else mask.data_ptr())
         _check(rc)
         self._keep = (ninv, mask)
+
+    def remove_templates(self, d: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Monopole and dipole removal of Eq. (12) on the observed pixels (T for spin 2)."""
+        n = self._count(d)
+        x = _dev_f64(d, (n, self.ncomp, self.npix))
+        out = self.zeros_map(n) if out is None else out
+        self._enter()
+        _check(_lib.mfwf_remove_templates(self._h, x.data_ptr(), out.data_ptr(), n))
+        self._leave()
+        return out
 
     def sht_inv(self, alm: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         n = self._count(alm)
