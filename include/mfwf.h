@@ -242,6 +242,46 @@ int mfwf_solve_cooled(mfwf_plan plan, const double *data, int nmaps, double *s_a
                       double *s_map_out, mfwf_cool_opts *opts, mfwf_solve_info *info);
 
 /*
+ * ---- Wiener filter under an error bound (Sect. 2.2) ----------------------------------------
+ * At fixed lambda the iteration minimises chi^2(x, lambda) of Eq. (6), whose minimum
+ * chi^2_min(lambda) lies below chi^2_min(1) for lambda > 1.  With a target b <= chi^2_min(1)
+ * (initially b = n_dof - m_sigma sigma_chi2, sigma_chi2 = sqrt(2 n_dof)): from x = 0, lambda is
+ * set so that chi^2(lambda, 0) = b; each iteration at lambda lowers chi^2(lambda, x) below b,
+ * and lambda is then lowered until chi^2(lambda, x) = b again, so chi^2(lambda, x) <= b holds
+ * throughout.  When lambda stops falling (it has converged at lambda > 1 because b lies
+ * below chi^2_min(1)), b is raised to b' = chi^2_min(lambda) + (lambda - 1) tau x^T S^-2 x
+ * (evaluated as chi^2(lambda, x) minus (lambda - 1) times the lambda-derivative of its pixel
+ * term, equal at the minimiser), which stays below chi^2_min(1) to second order.  On the
+ * pixelised sphere the iteration's fixed point misses the exact minimiser of chi^2 by the
+ * quadrature gap, so an iteration at fixed lambda can raise chi^2(lambda, x) by that
+ * margin; lambda is then raised until the bound holds again.  The solve ends with one
+ * iteration at lambda = 1 once lambda <= 1 + lam_tol.  A batch takes one lambda per
+ * iteration, the largest its maps need, so every map keeps its bound.  chi^2(lambda, x) is
+ * decreasing and convex in lambda; the new lambda comes from a safeguarded Newton search on
+ * the pixel term (one pass over the maps per step) and meets the bound exactly.
+ * Temperature plans (spin 0), MFWF_F64 or MFWF_F32; input data d (rho = M d).
+ */
+typedef struct {
+    double m_sigma;      /* initial b = n_dof - m_sigma sigma_chi2 (0: 5)                   */
+    double lam_tol;      /* end once lambda <= 1 + lam_tol (0: 1e-3)                        */
+    double stall_frac;   /* lambda stalls when it falls by less than this fraction (0: 1e-3) */
+    int stall_iters;     /* stalled iterations in a row before b is raised (0: 5)           */
+    int max_iters;       /* cap on the iterations (0: 5000)                                 */
+    double *trace;       /* host [trace_rows][3] or NULL, per iteration: lambda used,
+                            chi^2(lambda, x) after it and b (map 0)                         */
+    int trace_rows;      /* capacity of trace in rows                                       */
+    int n_iters;         /* out: iterations run                                             */
+    int n_b_updates;     /* out: times b was raised                                         */
+    int reached_one;     /* out: 1 if lambda reached 1 (0: max_iters ended the solve)       */
+} mfwf_bound_opts;
+
+/* input, outputs and info as in mfwf_solve; opts may be NULL (all defaults).  Errors: as
+ * mfwf_solve; MFWF_EINVAL for negative options or a spin-2 plan; MFWF_ENAN if chi^2 is not
+ * finite. */
+int mfwf_solve_bounded(mfwf_plan plan, const double *data, int nmaps, double *s_alm_out,
+                       double *s_map_out, mfwf_bound_opts *opts, mfwf_solve_info *info);
+
+/*
  * Time the plan's kernels on its stream with HIP events (diagnostic).  Runs `reps`
  * back-to-back launches of each stage of one iteration on the current workspaces for
  * nmaps maps and writes the mean duration in milliseconds of each kernel to ms_out:

@@ -1450,6 +1450,164 @@ static int cooled_chunk(mfwf_plan plan, const double *data, int nb, double *s_al
     return MFWF_OK;
 }
 
+// ---- the error-bound schedule of Sect. 2.2 ----------------------------------------------
+struct BoundOpts {
+    double m_sigma, lam_tol, stall_frac;
+    int stall_iters, max_iters;
+};
+
+// G(lambda) = max over maps of chi^2(lambda, s) - b (Eq. 6 at the current iterate) and its
+// derivative for the map attaining the max; chi^2 = H + P(lambda) with the harmonic part H
+// fixed and the pixel part P from one pass over the maps.
+struct BoundEval {
+    Plan &p;
+    const double *rho;
+    int nb;
+    std::vector<double> H, b, P, out;
+    int evals = 0;
+    BoundEval(Plan &q, const double *r, int n) : p(q), rho(r), nb(n), H(n, 0.0), b(n), P(n), out(2 * n) {}
+    int operator()(double lam, double &G, double &dG) {
+        double *partial = p.d_red, *o2 = p.d_red + 2L * 256 * nb;
+        MFWF_TRY(launch_chi2_pix_dlam(rho, p.d_M, p.d_smap, p.npix, nb, lam, p.tau, partial, 256,
+                                      o2, p.stream));
+        MFWF_HIP(hipMemcpyAsync(out.data(), o2, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost,
+                                p.stream));
+        MFWF_HIP(hipStreamSynchronize(p.stream));
+        evals++;
+        G = -INFINITY;
+        dG = 0.0;
+        for (int k = 0; k < nb; k++) {
+            P[k] = out[2 * k];
+            const double g = H[k] + P[k] - b[k];
+            if (!std::isfinite(g))
+                return fail(MFWF_ENAN, "chi^2 is not finite: the iteration diverged");
+            if (g > G) {
+                G = g;
+                dG = out[2 * k + 1];
+            }
+        }
+        return MFWF_OK;
+    }
+};
+
+// The smallest lambda in [1, hi] with chi^2(lambda, s) <= b for every map (G is decreasing and
+// convex in lambda): safeguarded Newton on a bracket [lo, hi] with G(lo) > 0 >= G(hi); the
+// returned value is the bracket's upper end, where the bound holds.  hi grows if G(hi) > 0.
+static int bound_lambda(BoundEval &ev, double hi, double &lam) {
+    double G, dG;
+    MFWF_TRY(ev(1.0, G, dG));
+    if (G <= 0.0) {
+        lam = 1.0;
+        return MFWF_OK;
+    }
+    double lo = 1.0, Gh, dGh;
+    MFWF_TRY(ev(hi, Gh, dGh));
+    for (int k = 0; Gh > 0.0; k++) {
+        if (k == 60) return fail(MFWF_ENAN, "no lambda meets the chi^2 bound");
+        lo = hi;
+        hi *= 4.0;
+        MFWF_TRY(ev(hi, Gh, dGh));
+    }
+    double x = hi, Gx = Gh, dGx = dGh;
+    for (int it = 0; it < 60 && hi / lo - 1.0 > 1e-12; it++) {
+        double xn = (dGx < 0.0) ? x - Gx / dGx : 0.0;
+        if (!(xn > lo && xn < hi)) xn = std::sqrt(lo * hi);
+        MFWF_TRY(ev(xn, Gx, dGx));
+        x = xn;
+        if (Gx > 0.0)
+            lo = x;
+        else
+            hi = x;
+        if (std::fabs(Gx) <= 1e-13 * std::fabs(ev.b[0]) + 1e-300 && Gx <= 0.0) break;
+    }
+    lam = hi;
+    return MFWF_OK;
+}
+
+static int bounded_chunk(Plan &p, const double *data, int nb, double *s_alm_out,
+                         double *s_map_out, const BoundOpts &o, std::vector<double> &trace,
+                         int &n_updates, bool &reached_one, mfwf_solve_info *info) {
+    MFWF_TRY(launch_rho_from_data(data, p.d_M, p.d_rho, p.npix, nb, p.stream));
+    const double *rho = p.d_rho;
+    MFWF_TRY(launch_fill(p.d_smap, p.npix * nb, 0.0, p.stream));
+    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm), 2 * p.nalm * nb, 0.0, p.stream));
+    if (p.dtype == MFWF_F32)
+        MFWF_HIP(hipMemsetAsync(p.d_s32, 0, sizeof(float) * (size_t)p.nalm * p.C2, p.stream));
+    const double sigma = std::sqrt(2.0 * (double)p.ndof);
+    BoundEval ev(p, rho, nb);
+    for (int k = 0; k < nb; k++) ev.b[k] = (double)p.ndof - o.m_sigma * sigma;
+    std::vector<double> dg(8L * nb);
+    double lam;
+    MFWF_TRY(bound_lambda(ev, 1e3, lam));  // x = 0: chi^2(lambda, 0) = b
+    n_updates = 0;
+    reached_one = false;
+    trace.clear();
+    int stall = 0;
+    for (int it = 0; it < o.max_iters; it++) {
+        MFWF_TRY(iteration(p, rho, nb, lam, true));
+        // harmonic part of chi^2 at the new iterate
+        MFWF_TRY(launch_harm_diag(p, p.d_salm, p.d_salm_prev, nb, p.d_red, p.d_diag));
+        MFWF_HIP(hipMemcpyAsync(dg.data(), p.d_diag, sizeof(double) * 8 * nb, hipMemcpyDeviceToHost,
+                                p.stream));
+        MFWF_HIP(hipStreamSynchronize(p.stream));
+        for (int k = 0; k < nb; k++) ev.H[k] = dg[8 * k + 1];
+        double G, dG;
+        MFWF_TRY(ev(lam, G, dG));
+        trace.insert(trace.end(), {lam, ev.H[0] + ev.P[0], ev.b[0]});
+        if (lam == 1.0) break;  // the last iteration ran at lambda = 1
+        // the next lambda: the smallest one with chi^2(lambda, x) <= b; it can exceed the
+        // current one when this iteration raised chi^2(lambda, x) above b, which the
+        // pixelised sphere allows by a margin of its quadrature gap (the iteration's fixed
+        // point is not exactly the minimiser of chi^2)
+        double nl;
+        MFWF_TRY(bound_lambda(ev, lam, nl));
+        if (nl > lam * (1.0 - o.stall_frac)) {
+            if (++stall >= o.stall_iters) {
+                // converged at lambda > 1 with b < chi^2_min(1): b' = chi^2_min(lambda) +
+                // (lambda - 1) tau x^T S^-2 x, the first-order expansion of the convex
+                // chi^2_min at lambda = 1.  At the minimiser S^-1 x = N'^-1 (d - x), so the
+                // increment is (lambda - 1) times minus the lambda-derivative of the pixel
+                // term at fixed x, which the pass below returns.
+                MFWF_TRY(ev(lam, G, dG));
+                for (int k = 0; k < nb; k++)
+                    ev.b[k] = ev.H[k] + ev.P[k] - (lam - 1.0) * ev.out[2 * k + 1];
+                n_updates++;
+                stall = 0;
+                MFWF_TRY(bound_lambda(ev, lam, nl));
+            }
+        } else {
+            stall = 0;
+        }
+        if (nl <= 1.0 + o.lam_tol) {
+            nl = 1.0;
+            reached_one = true;
+        }
+        lam = nl;
+    }
+    MFWF_TRY(cooled_diag(p, rho, nb, lam, dg));
+    if (s_alm_out)
+        MFWF_HIP(hipMemcpyAsync(s_alm_out, p.d_salm, sizeof(double2) * p.nalm * nb,
+                                hipMemcpyDeviceToDevice, p.stream));
+    if (s_map_out)
+        MFWF_HIP(hipMemcpyAsync(s_map_out, p.d_smap, sizeof(double) * p.npix * nb,
+                                hipMemcpyDeviceToDevice, p.stream));
+    if (info) {
+        for (int k = 0; k < nb; k++) {
+            mfwf_solve_info &in = info[k];
+            in.iters_done = (int)(trace.size() / 3);
+            in.lambda = lam;
+            in.chi2 = dg[8 * k + 0] + dg[8 * k + 1];
+            in.chi2_harm = dg[8 * k + 1];
+            in.dnorm = std::sqrt(dg[8 * k + 2]);
+            in.snorm = std::sqrt(dg[8 * k + 3]);
+            in.tau = p.tau;
+            in.n_dof = p.ndof;
+            in.n_checks = 0;
+        }
+    }
+    return MFWF_OK;
+}
+
 }  // namespace mfwf
 
 extern "C" {
@@ -1495,6 +1653,49 @@ int mfwf_solve_cooled(mfwf_plan plan, const double *data, int nmaps, double *s_a
         if (opts->stages)
             for (int r = 0; r < std::min(ns, opts->stage_rows); r++)
                 for (int k = 0; k < 5; k++) opts->stages[5 * r + k] = stages[5 * r + k];
+    }
+    return MFWF_OK;
+}
+
+int mfwf_solve_bounded(mfwf_plan plan, const double *data, int nmaps, double *s_alm_out,
+                       double *s_map_out, mfwf_bound_opts *opts, mfwf_solve_info *info) {
+    if (!plan || nmaps < 0) return fail(MFWF_EINVAL, "bad argument");
+    Plan &p = plan->p;
+    if (!p.have_cov) return fail(MFWF_ENOCOV, "covariances not set");
+    if (nmaps > 0 && !data) return fail(MFWF_EINVAL, "data is NULL");
+    if (p.spin != 0) return fail(MFWF_EINVAL, "the error-bound schedule is for temperature plans");
+    mfwf_bound_opts u{};
+    if (opts) u = *opts;
+    if (u.m_sigma < 0.0 || u.lam_tol < 0.0 || u.stall_frac < 0.0 || u.stall_iters < 0 ||
+        u.max_iters < 0 || (u.trace && u.trace_rows < 0))
+        return fail(MFWF_EINVAL, "negative option");
+    BoundOpts o;
+    o.m_sigma = u.m_sigma > 0.0 ? u.m_sigma : 5.0;
+    o.lam_tol = u.lam_tol > 0.0 ? u.lam_tol : 1e-3;
+    o.stall_frac = u.stall_frac > 0.0 ? u.stall_frac : 1e-3;
+    o.stall_iters = u.stall_iters > 0 ? u.stall_iters : 5;
+    o.max_iters = u.max_iters > 0 ? u.max_iters : 5000;
+    std::vector<double> trace;
+    int n_updates = 0;
+    bool reached = true;
+    for (int b0 = 0; b0 < nmaps; b0 += p.max_batch) {
+        const int nb = std::min(p.max_batch, nmaps - b0);
+        bool r = false;
+        MFWF_TRY(bounded_chunk(p, data + (long)b0 * p.npix, nb,
+                               s_alm_out ? s_alm_out + 2L * b0 * p.nalm : nullptr,
+                               s_map_out ? s_map_out + (long)b0 * p.npix : nullptr, o, trace,
+                               n_updates, r, info ? info + b0 : nullptr));
+        reached = reached && r;
+    }
+    MFWF_HIP(hipStreamSynchronize(p.stream));
+    if (opts) {
+        const int n = (int)(trace.size() / 3);
+        opts->n_iters = n;
+        opts->n_b_updates = n_updates;
+        opts->reached_one = reached ? 1 : 0;
+        if (opts->trace)
+            for (int r = 0; r < std::min(n, opts->trace_rows); r++)
+                for (int k = 0; k < 3; k++) opts->trace[3 * r + k] = trace[3 * r + k];
     }
     return MFWF_OK;
 }

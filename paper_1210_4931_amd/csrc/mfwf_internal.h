@@ -221,6 +221,12 @@ int launch_harm_diag_pol(const Plan &p, const double2 *salm, const double2 *salm
 int launch_fluct_combine_pol(const double *g1, const double *M6, const double *ysh, double *rho,
                              long npix, int nb, double omega, hipStream_t s);
 
+// error-bound schedule (Sect. 2.2): pixel term of chi^2 and its lambda-derivative per map
+// (out2[b][2]; partial holds nb x nblocks x 2 doubles)
+int launch_chi2_pix_dlam(const double *rho, const double *M, const double *smap, long npix,
+                         int nb, double lam, double tau, double *partial, int nblocks,
+                         double *out2, hipStream_t s);
+
 // templates.hip (Eq. 12: monopole and dipole template removal)
 int launch_template_sums(const Plan &p, const double *d, int nb, double *partial, double *out14);
 int template_partial_doubles(int nb);

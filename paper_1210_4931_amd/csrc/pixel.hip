@@ -201,6 +201,58 @@ int launch_chi2_pix(const double *rho, const double *M, const double *smap, long
     return MFWF_OK;
 }
 
+// Pixel term of chi^2(lambda, s) (Eq. 6) and its derivative in lambda, for the error-bound
+// schedule of Sect. 2.2: with r = rho - M s and u = tau M on observed pixels,
+//   P = sum r^2 / (M (1 + (lam - 1) u)),  dP/dlam = -sum r^2 tau / (1 + (lam - 1) u)^2.
+// partial[b][block][2]; k_sum_pairs adds the blocks in fixed order into out[b][2].
+__global__ void k_chi2_pix_dlam(const double *__restrict__ rho, const double *__restrict__ M,
+                                const double *__restrict__ smap, long npix, double lam,
+                                double tau, double *__restrict__ partial) {
+    __shared__ double sh[2][kThreads];
+    const long off = (long)blockIdx.y * npix;
+    double acc[2] = {0.0, 0.0};
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < npix;
+         i += (long)gridDim.x * blockDim.x) {
+        const double m = M[i];
+        if (m > 0.0) {
+            const double r = rho[off + i] - m * smap[off + i];
+            const double q = 1.0 / (1.0 + (lam - 1.0) * tau * m);
+            acc[0] += r * r / m * q;
+            acc[1] -= r * r * tau * q * q;
+        }
+    }
+    block_sum<2>(acc, sh);
+    if (threadIdx.x == 0) {
+        const long o = ((long)blockIdx.y * gridDim.x + blockIdx.x) * 2;
+        partial[o] = acc[0];
+        partial[o + 1] = acc[1];
+    }
+}
+
+__global__ void k_sum_pairs(const double *__restrict__ partial, int nblocks, int nb,
+                            double *__restrict__ out) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    double a = 0.0, c = 0.0;
+    for (int k = 0; k < nblocks; k++) {
+        a += partial[((long)b * nblocks + k) * 2];
+        c += partial[((long)b * nblocks + k) * 2 + 1];
+    }
+    out[2 * b] = a;
+    out[2 * b + 1] = c;
+}
+
+int launch_chi2_pix_dlam(const double *rho, const double *M, const double *smap, long npix,
+                         int nb, double lam, double tau, double *partial, int nblocks,
+                         double *out2, hipStream_t s) {
+    hipLaunchKernelGGL(k_chi2_pix_dlam, dim3(nblocks, nb), dim3(kThreads), 0, s, rho, M, smap,
+                       npix, lam, tau, partial);
+    MFWF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_pairs, dim3((nb + 63) / 64), dim3(64), 0, s, partial, nblocks, nb, out2);
+    MFWF_HIP(hipGetLastError());
+    return MFWF_OK;
+}
+
 // rho = M^{1/2} g1 + Omega * (Y C^{-1/2} h)  (Eq. 9 in per-pixel form)
 __global__ void k_fluct_combine(const double *__restrict__ g1, const double *__restrict__ M,
                                 const double *__restrict__ ysh, double *__restrict__ rho,

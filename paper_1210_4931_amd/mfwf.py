@@ -45,12 +45,20 @@ class CoolOpts(ctypes.Structure):
                 ("n_stages", ctypes.c_int), ("converged", ctypes.c_int)]
 
 
+class BoundOpts(ctypes.Structure):
+    _fields_ = [("m_sigma", ctypes.c_double), ("lam_tol", ctypes.c_double),
+                ("stall_frac", ctypes.c_double), ("stall_iters", ctypes.c_int),
+                ("max_iters", ctypes.c_int), ("trace", ctypes.POINTER(ctypes.c_double)),
+                ("trace_rows", ctypes.c_int), ("n_iters", ctypes.c_int),
+                ("n_b_updates", ctypes.c_int), ("reached_one", ctypes.c_int)]
+
+
 EXPORTED = ["mfwf_plan_create", "mfwf_plan_destroy", "mfwf_set_covariances", "mfwf_sht_inv",
             "mfwf_sht_fwd", "mfwf_fluctuation_rhs", "mfwf_solve", "mfwf_time_kernels",
             "mfwf_plan_work", "mfwf_last_error", "mfwf_server_create", "mfwf_server_submit",
             "mfwf_server_poll", "mfwf_server_wait", "mfwf_server_stats", "mfwf_server_destroy",
             "mfwf_server_pool_bytes", "mfwf_solve_cooled", "mfwf_set_covariances_beam",
-            "mfwf_remove_templates"]
+            "mfwf_remove_templates", "mfwf_solve_bounded"]
 
 
 class Request(ctypes.Structure):
@@ -84,6 +92,8 @@ def load(path: str = LIB_PATH):
                              ctypes.POINTER(SolveInfo)]
     L.mfwf_solve_cooled.argtypes = [vp, vp, ip, vp, vp, ctypes.POINTER(CoolOpts),
                                     ctypes.POINTER(SolveInfo)]
+    L.mfwf_solve_bounded.argtypes = [vp, vp, ip, vp, vp, ctypes.POINTER(BoundOpts),
+                                     ctypes.POINTER(SolveInfo)]
     L.mfwf_time_kernels.argtypes = [vp, ip, ip, dp]
     L.mfwf_plan_work.argtypes = [vp, dp]
     L.mfwf_server_create.argtypes = [ip, ctypes.c_double, ctypes.POINTER(vp)]
@@ -307,6 +317,32 @@ class Plan:
         info = [Info(i.iters_done, i.lam, i.chi2, i.chi2_harm, i.dnorm, i.snorm, i.tau, i.n_dof,
                      i.n_checks) for i in infos]
         return s_alm, s_map, info, st[:min(opts.n_stages, rows)], bool(opts.converged)
+
+    def solve_bounded(self, data: torch.Tensor, m_sigma=0.0, lam_tol=0.0, stall_frac=0.0,
+                      stall_iters=0, max_iters=0, want_map=True):
+        """Wiener filter under the error bound of Sect. 2.2 (0 = the default of each option).
+        Returns (s_alm, s_map or None, [Info] * n, trace, n_b_updates, reached_one), trace a
+        numpy array [iterations][3] of (lambda, chi^2(lambda, x) after the iteration, b)."""
+        import numpy as np
+        n = self._count(data)
+        x = _dev_f64(data, (n, self.ncomp, self.npix))
+        rows = max_iters if max_iters > 0 else 5000
+        tr = np.zeros((rows, 3))
+        opts = BoundOpts(float(m_sigma), float(lam_tol), float(stall_frac), int(stall_iters),
+                         int(max_iters), tr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), rows,
+                         0, 0, 0)
+        s_alm = self.zeros_alm(n)
+        s_map = self.zeros_map(n) if want_map else None
+        infos = (SolveInfo * n)()
+        self._enter()
+        _check(_lib.mfwf_solve_bounded(self._h, x.data_ptr(), n, torch.view_as_real(s_alm).data_ptr(),
+                                       None if s_map is None else s_map.data_ptr(),
+                                       ctypes.byref(opts), infos))
+        self._leave()
+        info = [Info(i.iters_done, i.lam, i.chi2, i.chi2_harm, i.dnorm, i.snorm, i.tau, i.n_dof,
+                     i.n_checks) for i in infos]
+        return (s_alm, s_map, info, tr[:min(opts.n_iters, rows)], opts.n_b_updates,
+                bool(opts.reached_one))
 
     def work(self):
         """(Legendre triples evaluated, full triangle pairs*nalm, ring pairs, max FFT length)."""
