@@ -151,6 +151,21 @@ def cooled(plan, d):
             "stage_columns": ["l_iter", "lambda", "lmax_SHT", "iterations"]}
 
 
+def bounded(plan, d):
+    """Solve under the error bound of Sect. 2.2 (mfwf_solve_bounded, default options),
+    timed after one untimed run."""
+    import torch
+    plan.solve_bounded(d, want_map=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, info, tr, nup, reached = plan.solve_bounded(d, want_map=False)
+    el = time.perf_counter() - t0
+    return {"maps": d.shape[0], "seconds": el, "iterations": len(tr), "b_updates": nup,
+            "reached_lambda_1": reached, "first_lambda": float(tr[0, 0]),
+            "chi2_per_dof": info[0].chi2 / info[0].n_dof,
+            "max_chi2_over_b": float((tr[:, 1] / tr[:, 2]).max())}
+
+
 def timed_solves(plan, d, K, steps, warmup, use_graph):
     import torch
     for _ in range(warmup):
@@ -227,6 +242,7 @@ def main():
                          "frac": leg_flops / (kt64[dom64] * 1e-3) / PEAK_FP64_VALU}}
     if not args.no_cooled:
         fp64["cooled"] = cooled(p64, d1)
+        fp64["bounded"] = bounded(p64, d1)
     del p64
 
     # ---- batched FP32 form (headline) --------------------------------------------------
