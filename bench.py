@@ -36,8 +36,8 @@ KERNELS = ["pixel_update", "fft_fwd", "leg_analysis", "harmonic", "leg_synth", "
 # from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the factors a 256 MiB copy gives
 # (x2.0 and x1.0): profiles/gemm_analysis_nside512_lmax1024_b64_hbm_traffic.md.  Valid only
 # for the kernel source they were taken on, identified by the SHA-256 of batched.hip.
-GEMM_TRAFFIC = {"bytes": 4.862e9,
-                "source_sha256": "771752b68a266fa0ffa8179e94e6de4734f980f5e62500789ca1fceffadf63f0"}
+GEMM_TRAFFIC = {"bytes": 4.868e9,
+                "source_sha256": "909868d0686837855fe18055f684f52a378bc40188db3a598c9e1ee42d05aecc"}
 
 
 def measured_traffic():
