@@ -157,7 +157,12 @@ typedef struct {
     const double *lambda;  /* host [n_stages], each >= 1 (Sect. 2.2)                     */
     const int *iters;      /* host [n_stages], iterations per stage (>= 0)              */
     int n_check;           /* diagnostics every n_check iterations (0 = only at the end) */
-    double dchi2_tol;      /* reserved, must be 0: a fixed number of iterations is run   */
+    double dchi2_tol;      /* 0: run the whole schedule; > 0 (needs n_check > 0): end
+                              early once the change of chi^2 between two checks of one
+                              stage, per iteration, is below dchi2_tol sigma_chi2 for
+                              every map of a chunk (maps are solved in chunks of at most
+                              max_batch; sigma_chi2 = sqrt(2 n_dof), Sect. 2.2);
+                              iters_done reports where each map stopped                  */
     int source_is_rho;     /* 0: input is the data d (rho = M d); 1: input is rho        */
     int use_graph;         /* 1: replay each iteration as a captured hipGraph            */
     double *history;       /* host [history_rows][nmaps][5] or NULL: at every check,

@@ -886,10 +886,17 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
                                  p.nred_blocks, p.d_diag, p.stream));
         return launch_harm_diag(p, p.d_salm, p.d_salm_prev, nb, p.d_red, p.d_diag);
     };
-    for (size_t s = 0; s < lam.size(); s++) {
+    // early end: the per-iteration change of chi^2 between two checks of one stage (one
+    // lambda) below dchi2_tol sigma_chi2 for every map (sigma_chi2 = sqrt(2 n_dof), Sect. 2.2)
+    const double stop_tol = o.dchi2_tol * std::sqrt(2.0 * (double)p.ndof);
+    std::vector<double> chi_prev(nb, 0.0);
+    long prev_at = -1;       // iteration count at the previous check of the current stage
+    bool stopped = false;
+    for (size_t s = 0; s < lam.size() && !stopped; s++) {
         long remaining = its[s];
         if (remaining <= 0) continue;
         last_lam = lam[s];
+        prev_at = -1;
         std::unique_ptr<StageGraph> sg;
         while (remaining > 0) {
             // run up to the next check point: a multiple of n_check, or the last iteration
@@ -909,6 +916,22 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
             if (check) {
                 MFWF_TRY(iteration(p, rho, nb, lam[s], true));
                 MFWF_TRY(diagnostics(lam[s]));
+                if (stop_tol > 0.0) {
+                    MFWF_HIP(hipMemcpyAsync(dg.data(), p.d_diag, sizeof(double) * dg.size(),
+                                            hipMemcpyDeviceToHost, p.stream));
+                    MFWF_HIP(hipStreamSynchronize(p.stream));
+                    const long at = done + run;
+                    double worst = 0.0;
+                    for (int b = 0; b < nb; b++) {
+                        const double chi = dg[8 * b + 0] + dg[8 * b + 1];
+                        if (!std::isfinite(chi)) return fail(MFWF_ENAN, "chi^2 is not finite");
+                        if (prev_at >= 0)
+                            worst = std::max(worst, std::fabs(chi - chi_prev[b]) / (double)(at - prev_at));
+                        chi_prev[b] = chi;
+                    }
+                    stopped = prev_at >= 0 && worst < stop_tol;
+                    prev_at = at;
+                }
                 if (o.history && rows < o.history_rows) {
                     MFWF_HIP(hipMemcpyAsync(dg.data(), p.d_diag, sizeof(double) * dg.size(),
                                             hipMemcpyDeviceToHost, p.stream));
@@ -926,6 +949,7 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
             }
             done += run;
             remaining -= run;
+            if (stopped) break;
         }
     }
     if (total == 0) MFWF_TRY(launch_fill(p.d_diag, 8L * nb, 0.0, p.stream));
@@ -941,7 +965,7 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
         MFWF_HIP(hipStreamSynchronize(p.stream));
         for (int b = 0; b < nb; b++) {
             mfwf_solve_info &in = info[b];
-            in.iters_done = (int)total;
+            in.iters_done = (int)done;
             in.lambda = last_lam;
             in.chi2 = dg[8 * b + 0] + dg[8 * b + 1];
             in.chi2_harm = dg[8 * b + 1];
@@ -1243,7 +1267,9 @@ int mfwf_solve(mfwf_plan plan, const double *input, int nmaps, double *s_alm_out
     std::vector<int> its{300};
     if (opts) {
         o = *opts;
-        if (o.dchi2_tol != 0.0) return fail(MFWF_EINVAL, "dchi2_tol must be 0 (fixed schedules only)");
+        if (!(o.dchi2_tol >= 0.0)) return fail(MFWF_EINVAL, "dchi2_tol must be >= 0");
+        if (o.dchi2_tol > 0.0 && o.n_check <= 0)
+            return fail(MFWF_EINVAL, "dchi2_tol needs n_check > 0 (chi^2 is evaluated at the checks)");
         if (o.n_stages < 0) return fail(MFWF_EINVAL, "n_stages < 0");
         if (o.n_check < 0) return fail(MFWF_EINVAL, "n_check < 0");
         if (o.history && o.history_rows < 0) return fail(MFWF_EINVAL, "history_rows < 0");

@@ -261,11 +261,14 @@ class Plan:
         return out
 
     def solve(self, inp: torch.Tensor, lam=None, iters=None, source_is_rho=False,
-              use_graph=True, out_alm=None, out_map=None, want_map=True, n_check=0):
+              use_graph=True, out_alm=None, out_map=None, want_map=True, n_check=0,
+              dchi2_tol=0.0):
         """Messenger iteration.  lam/iters: per-stage schedule (default lambda 1, 300 its).
         Returns (s_alm [n, nalm] complex128, s_map [n, npix] or None, [Info] * n); with
         n_check > 0 a fourth item, the diagnostics history as a numpy array
-        [checks][n][5] of (iteration, lambda, chi^2, |s_k - s_{k-1}|, |s_k|)."""
+        [checks][n][5] of (iteration, lambda, chi^2, |s_k - s_{k-1}|, |s_k|).  dchi2_tol > 0
+        ends the solve early once chi^2 changes by less than dchi2_tol sigma_chi2 per
+        iteration between two checks of one stage (Info.iters_done says where)."""
         import numpy as np
         n = self._count(inp)
         x = _dev_f64(inp, (n, self.ncomp, self.npix))
@@ -277,7 +280,8 @@ class Plan:
         rows = (total // n_check + 1) if n_check > 0 else 0
         hist = np.zeros((rows, n, 5)) if rows else None
         hptr = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if rows else None
-        opts = SolveOpts(len(lam), lam_a, it_a, int(n_check), 0.0, int(bool(source_is_rho)),
+        opts = SolveOpts(len(lam), lam_a, it_a, int(n_check), float(dchi2_tol),
+                         int(bool(source_is_rho)),
                          int(bool(use_graph)), hptr, rows)
         s_alm = self.zeros_alm(n) if out_alm is None else out_alm
         s_map = (self.zeros_map(n) if out_map is None else out_map) if want_map else None
@@ -290,7 +294,7 @@ class Plan:
         info = [Info(i.iters_done, i.lam, i.chi2, i.chi2_harm, i.dnorm, i.snorm, i.tau, i.n_dof,
                      i.n_checks) for i in infos]
         if n_check > 0:
-            return s_alm, s_map, info, hist[:infos[0].n_checks] if n else hist
+            return s_alm, s_map, info, hist[:max(i.n_checks for i in infos)] if n else hist
         return s_alm, s_map, info
 
     def solve_cooled(self, data: torch.Tensor, l_iter0=0, l_step_max=0, l_margin=0, n_check=0,
