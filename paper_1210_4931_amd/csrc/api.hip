@@ -442,7 +442,8 @@ static int setup_batched(Plan &p, const std::vector<int> &lstart, const std::vec
     MFWF_TRY(dalloc(&p.d_ana_tab, ana_tab.size(), "analysis XCD lists"));
     MFWF_TRY(dalloc(&p.d_syn_tab, syn_tab.size(), "synthesis XCD lists"));
     MFWF_TRY(dalloc(&p.d_lofi, lofi.size(), "l of index"));
-    MFWF_TRY(dalloc(&p.d_phf, (size_t)p.ncomp * p.max_batch * p.nring * p.nm, "ring Fourier rows FP32"));
+    p.nm32 = (p.nm + 15) / 16 * 16;
+    MFWF_TRY(dalloc(&p.d_phf, (size_t)p.ncomp * p.max_batch * p.nring * p.nm32, "ring Fourier rows FP32"));
     MFWF_TRY(dalloc(&p.d_ph32, (size_t)p.nring * p.nm * p.C2, "ring Fourier FP32"));
     MFWF_TRY(dalloc(&p.d_a32, (size_t)p.nalm * p.C2, "analysis FP32"));
     MFWF_TRY(dalloc(&p.d_s32, (size_t)p.nalm * p.C2, "synthesis input FP32"));

@@ -67,20 +67,31 @@ k_lam_table(const double *__restrict__ Atab, const double *__restrict__ ctab,
 // Layout changes between the per-map ring-Fourier rows of the ring transforms,
 // [map][ring][m] (FP32 complex), and the contraction layout [m][ring][C2] with columns 2b
 // (re) and 2b + 1 (im) of map b.  One workgroup moves a tile of 64 values of m x 64 maps
-// of one ring through LDS, so that both sides read and write 512-byte rows.
+// of one ring through LDS, so that both sides read and write 512-byte rows.  Each thread
+// issues all of its 16 loads before it stores any of them (clamped in-range addresses, values
+// selected), so that a workgroup has its whole tile in flight at once.
 // ---------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
 k_rows_to_cols(const float2 *__restrict__ phf, float *__restrict__ ph32, int nring, int nm,
-               int nb, int Bp, int C2) {
+               int rs, int nb, int Bp, int C2) {
     __shared__ float2 tile[64][64 + 1];  // [map][m]
     const int ring = blockIdx.x, m0 = 64 * blockIdx.y, b0 = 64 * blockIdx.z;
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-        const int bb = e >> 6, mm = e & 63, b = b0 + bb, m = m0 + mm;
-        tile[bb][mm] = (b < nb && m < nm) ? phf[((long)b * nring + ring) * nm + m] : make_float2(0.f, 0.f);
+    float2 v[16];
+#pragma unroll
+    for (int u = 0; u < 16; u++) {
+        const int e = threadIdx.x + 256 * u, bb = e >> 6, mm = e & 63, b = b0 + bb, m = m0 + mm;
+        const float2 x = phf[((long)min(b, nb - 1) * nring + ring) * rs + min(m, nm - 1)];
+        v[u] = (b < nb && m < nm) ? x : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; u++) {
+        const int e = threadIdx.x + 256 * u;
+        tile[e >> 6][e & 63] = v[u];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-        const int mm = e >> 6, bb = e & 63, b = b0 + bb, m = m0 + mm;
+#pragma unroll
+    for (int u = 0; u < 16; u++) {
+        const int e = threadIdx.x + 256 * u, mm = e >> 6, bb = e & 63, b = b0 + bb, m = m0 + mm;
         if (b < Bp && m < nm)
             *reinterpret_cast<float2 *>(ph32 + ((long)m * nring + ring) * C2 + 2 * b) = tile[bb][mm];
     }
@@ -88,19 +99,27 @@ k_rows_to_cols(const float2 *__restrict__ phf, float *__restrict__ ph32, int nri
 
 __global__ void __launch_bounds__(256)
 k_cols_to_rows(const float *__restrict__ ph32, float2 *__restrict__ phf, int nring, int nm,
-               int nb, int C2) {
+               int rs, int nb, int C2) {
     __shared__ float2 tile[64][64 + 1];  // [m][map]
     const int ring = blockIdx.x, m0 = 64 * blockIdx.y, b0 = 64 * blockIdx.z;
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-        const int mm = e >> 6, bb = e & 63, b = b0 + bb, m = m0 + mm;
-        tile[mm][bb] = (b < nb && m < nm)
-                           ? *reinterpret_cast<const float2 *>(ph32 + ((long)m * nring + ring) * C2 + 2 * b)
-                           : make_float2(0.f, 0.f);
+    float2 v[16];
+#pragma unroll
+    for (int u = 0; u < 16; u++) {
+        const int e = threadIdx.x + 256 * u, mm = e >> 6, bb = e & 63, b = b0 + bb, m = m0 + mm;
+        const float2 x = *reinterpret_cast<const float2 *>(
+            ph32 + ((long)min(m, nm - 1) * nring + ring) * C2 + 2 * min(b, nb - 1));
+        v[u] = (b < nb && m < nm) ? x : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < 16; u++) {
+        const int e = threadIdx.x + 256 * u;
+        tile[e >> 6][e & 63] = v[u];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-        const int bb = e >> 6, mm = e & 63, b = b0 + bb, m = m0 + mm;
-        if (b < nb && m < nm) phf[((long)b * nring + ring) * nm + m] = tile[mm][bb];
+#pragma unroll
+    for (int u = 0; u < 16; u++) {
+        const int e = threadIdx.x + 256 * u, bb = e >> 6, mm = e & 63, b = b0 + bb, m = m0 + mm;
+        if (b < nb && m < nm) phf[((long)b * nring + ring) * rs + m] = tile[mm][bb];
     }
 }
 
@@ -475,14 +494,14 @@ int launch_lam_table(const Plan &p) {
 
 int launch_rows_to_cols(const Plan &p, int nb) {
     hipLaunchKernelGGL(k_rows_to_cols, dim3(p.nring, (p.nm + 63) / 64, (p.Bp + 63) / 64), dim3(256), 0,
-                       p.stream, p.d_phf, p.d_ph32, p.nring, p.nm, nb, p.Bp, p.C2);
+                       p.stream, p.d_phf, p.d_ph32, p.nring, p.nm, p.nm32, nb, p.Bp, p.C2);
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }
 
 int launch_cols_to_rows(const Plan &p, int nb) {
     hipLaunchKernelGGL(k_cols_to_rows, dim3(p.nring, (p.nm + 63) / 64, (nb + 63) / 64), dim3(256), 0,
-                       p.stream, p.d_ph32, p.d_phf, p.nring, p.nm, nb, p.C2);
+                       p.stream, p.d_ph32, p.d_phf, p.nring, p.nm, p.nm32, nb, p.C2);
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }

@@ -115,7 +115,8 @@ struct Plan {
     int *d_syn_tab = nullptr;    // [8][syn_per_xcd]
     int ana_per_xcd = 0, syn_per_xcd = 0;
     int *d_lofi = nullptr;       // [nalm] l of each packed index
-    float2 *d_phf = nullptr;     // [B][nring][nm] ring-Fourier rows of the transforms
+    float2 *d_phf = nullptr;     // [B][nring][nm32] ring-Fourier rows of the transforms
+    int nm32 = 0;                // row stride of d_phf: nm rounded up to whole 128-byte lines
     float *d_ph32 = nullptr;     // [nm][nring][C2] ring-Fourier, maps innermost
     float *d_a32 = nullptr;      // [nalm][C2] analysis output
     float *d_s32 = nullptr;      // [nalm][C2] synthesis input

@@ -77,27 +77,37 @@ k_pol_tables(const double *__restrict__ Atab, const double *__restrict__ ctab,
 
 // ---------------------------------------------------------------------------------------
 // Layout changes between the rows [3B][ring][m] and the column layouts, through LDS tiles
-// of 64 values of m x 32 maps of one ring (T, Q, U together).
+// of 64 values of m x 32 maps of one ring (T, Q, U together).  Each thread issues all of its
+// loads before it stores any of them (clamped in-range addresses, values selected).
 // ---------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
 k_rows_to_cols_pol(const float2 *__restrict__ phf, float *__restrict__ colT,
-                   float *__restrict__ colP, int nring, int nm, int nb, int Bp) {
+                   float *__restrict__ colP, int nring, int nm, int rs, int nb, int Bp) {
     __shared__ float2 tile[3][32][64 + 1];  // [component][map][m]
     const int ring = blockIdx.x, m0 = 64 * blockIdx.y, b0 = 32 * blockIdx.z;
-    for (int e = threadIdx.x; e < 3 * 32 * 64; e += 256) {
+    float2 v[24];
+#pragma unroll
+    for (int u = 0; u < 24; u++) {
+        const int e = threadIdx.x + 256 * u;
         const int c = e >> 11, bb = (e >> 6) & 31, mm = e & 63, b = b0 + bb, m = m0 + mm;
-        tile[c][bb][mm] = (b < nb && m < nm) ? phf[((3L * b + c) * nring + ring) * nm + m]
-                                             : make_float2(0.f, 0.f);
+        const float2 x = phf[((3L * min(b, nb - 1) + c) * nring + ring) * rs + min(m, nm - 1)];
+        v[u] = (b < nb && m < nm) ? x : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < 24; u++) {
+        const int e = threadIdx.x + 256 * u;
+        tile[e >> 11][(e >> 6) & 31][e & 63] = v[u];
     }
     __syncthreads();
     const long C2 = 2L * Bp;
-    for (int e = threadIdx.x; e < 64 * 32; e += 256) {
-        const int mm = e >> 5, bb = e & 31, b = b0 + bb, m = m0 + mm;
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const int e = threadIdx.x + 256 * u, mm = e >> 5, bb = e & 31, b = b0 + bb, m = m0 + mm;
         if (b >= Bp || m >= nm) continue;
         const long row = (long)m * nring + ring;
-        const float2 t = tile[0][bb][mm], q = tile[1][bb][mm], u = tile[2][bb][mm];
+        const float2 t = tile[0][bb][mm], q = tile[1][bb][mm], u2 = tile[2][bb][mm];
         *reinterpret_cast<float2 *>(colT + row * C2 + 2 * b) = t;
-        *reinterpret_cast<float4 *>(colP + row * 2 * C2 + 4 * b) = make_float4(q.x, q.y, u.x, u.y);
+        *reinterpret_cast<float4 *>(colP + row * 2 * C2 + 4 * b) = make_float4(q.x, q.y, u2.x, u2.y);
     }
 }
 
@@ -106,30 +116,38 @@ k_rows_to_cols_pol(const float2 *__restrict__ phf, float *__restrict__ colT,
 __global__ void __launch_bounds__(256)
 k_cols_to_rows_pol(const float *__restrict__ colT, const float *__restrict__ colP,
                    const float *__restrict__ colR, float2 *__restrict__ phf, int nring, int nm,
-                   int nb, int Bp) {
+                   int rs, int nb, int Bp) {
     __shared__ float2 tile[3][64][32 + 1];  // [component][m][map]
     const int ring = blockIdx.x, m0 = 64 * blockIdx.y, b0 = 32 * blockIdx.z;
     const long C2 = 2L * Bp;
-    for (int e = threadIdx.x; e < 64 * 32; e += 256) {
-        const int mm = e >> 5, bb = e & 31, b = b0 + bb, m = m0 + mm;
-        float2 t = make_float2(0.f, 0.f), q = t, u = t;
-        if (b < nb && m < nm) {
-            const long row = (long)m * nring + ring;
-            t = *reinterpret_cast<const float2 *>(colT + row * C2 + 2 * b);
-            const float4 P = *reinterpret_cast<const float4 *>(colP + row * 2 * C2 + 4 * b);
-            const float4 R = *reinterpret_cast<const float4 *>(colR + row * 2 * C2 + 4 * b);
-            // P = (E re, E im, B re, B im) of P', likewise R
-            q = make_float2(-P.x + R.w, -P.y - R.z);
-            u = make_float2(-P.z - R.y, -P.w + R.x);
-        }
-        tile[0][mm][bb] = t;
-        tile[1][mm][bb] = q;
-        tile[2][mm][bb] = u;
+    float2 vt[8];
+    float4 vp[8], vr[8];
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const int e = threadIdx.x + 256 * u, mm = e >> 5, bb = e & 31;
+        const int b = min(b0 + bb, nb - 1), m = min(m0 + mm, nm - 1);
+        const long row = (long)m * nring + ring;
+        vt[u] = *reinterpret_cast<const float2 *>(colT + row * C2 + 2 * b);
+        vp[u] = *reinterpret_cast<const float4 *>(colP + row * 2 * C2 + 4 * b);
+        vr[u] = *reinterpret_cast<const float4 *>(colR + row * 2 * C2 + 4 * b);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++) {
+        const int e = threadIdx.x + 256 * u, mm = e >> 5, bb = e & 31;
+        const bool on = b0 + bb < nb && m0 + mm < nm;
+        const float4 P = vp[u], R = vr[u];
+        // P = (E re, E im, B re, B im) of P', likewise R
+        const float2 z = make_float2(0.f, 0.f);
+        tile[0][mm][bb] = on ? vt[u] : z;
+        tile[1][mm][bb] = on ? make_float2(-P.x + R.w, -P.y - R.z) : z;
+        tile[2][mm][bb] = on ? make_float2(-P.z - R.y, -P.w + R.x) : z;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < 3 * 32 * 64; e += 256) {
+#pragma unroll
+    for (int u = 0; u < 24; u++) {
+        const int e = threadIdx.x + 256 * u;
         const int c = e >> 11, bb = (e >> 6) & 31, mm = e & 63, b = b0 + bb, m = m0 + mm;
-        if (b < nb && m < nm) phf[((3L * b + c) * nring + ring) * nm + m] = tile[c][mm][bb];
+        if (b < nb && m < nm) phf[((3L * b + c) * nring + ring) * rs + m] = tile[c][mm][bb];
     }
 }
 
@@ -255,7 +273,8 @@ int launch_pol_tables(const Plan &p) {
 
 int launch_rows_to_cols_pol(const Plan &p, int nb) {
     hipLaunchKernelGGL(k_rows_to_cols_pol, dim3(p.nring, (p.nm + 63) / 64, (p.Bp + 31) / 32),
-                       dim3(256), 0, p.stream, p.d_phf, p.d_ph32, p.d_ph32p, p.nring, p.nm, nb, p.Bp);
+                       dim3(256), 0, p.stream, p.d_phf, p.d_ph32, p.d_ph32p, p.nring, p.nm, p.nm32,
+                       nb, p.Bp);
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }
@@ -263,7 +282,7 @@ int launch_rows_to_cols_pol(const Plan &p, int nb) {
 int launch_cols_to_rows_pol(const Plan &p, int nb) {
     hipLaunchKernelGGL(k_cols_to_rows_pol, dim3(p.nring, (p.nm + 63) / 64, (nb + 31) / 32),
                        dim3(256), 0, p.stream, p.d_ph32, p.d_ph32p, p.d_ph32r, p.d_phf, p.nring,
-                       p.nm, nb, p.Bp);
+                       p.nm, p.nm32, nb, p.Bp);
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }

@@ -258,9 +258,10 @@ size_t fft_class_lds(const Plan &p, int c) {
     return sizeof(double2) * ((size_t)fft_area(p.fft_class_len[c], tpb) + 64 + p.fft_ntwhi);
 }
 
-#define MFWF_FFT_ARGS(c)                                                                        \
+// rs: row stride of the ring-Fourier rows (nm for the FP64 rows, nm32 for the FP32 rows)
+#define MFWF_FFT_ARGS(c, rs)                                                                    \
     p.d_pfft, p.d_plist + p.fft_class_off[c], p.d_twlo, p.d_twhi, p.fft_ntwhi, p.fftmax,        \
-        p.d_chirp, p.d_bhat, p.npix, p.nring, p.nm, p.lmax, p.fft_class_len[c]
+        p.d_chirp, p.d_bhat, p.npix, p.nring, rs, p.lmax, p.fft_class_len[c]
 
 template <typename OutT, bool PIX>
 static int fwd_classes(const Plan &p, const double *maps, const double *rho, double lam,
@@ -272,12 +273,13 @@ static int fwd_classes(const Plan &p, const double *maps, const double *rho, dou
         const int tpb = fft_class_shape(p, c, ept);
         const dim3 grid(nb, cnt);  // maps of one pair adjacent: its tables and M stay in L2
         const size_t lds = fft_class_lds(p, c);
+        const int rs = sizeof(OutT) == sizeof(float2) ? p.nm32 : p.nm;
         if (tpb == 256)
-            hipLaunchKernelGGL((k_fft_fwd<256, 8, OutT, PIX>), grid, dim3(256), lds, p.stream, maps, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, out, MFWF_FFT_ARGS(c));
+            hipLaunchKernelGGL((k_fft_fwd<256, 8, OutT, PIX>), grid, dim3(256), lds, p.stream, maps, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, out, MFWF_FFT_ARGS(c, rs));
         else if (tpb == 512)
-            hipLaunchKernelGGL((k_fft_fwd<512, 8, OutT, PIX>), grid, dim3(512), lds, p.stream, maps, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, out, MFWF_FFT_ARGS(c));
+            hipLaunchKernelGGL((k_fft_fwd<512, 8, OutT, PIX>), grid, dim3(512), lds, p.stream, maps, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, out, MFWF_FFT_ARGS(c, rs));
         else
-            hipLaunchKernelGGL((k_fft_fwd<1024, 8, OutT, PIX>), grid, dim3(1024), lds, p.stream, maps, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, out, MFWF_FFT_ARGS(c));
+            hipLaunchKernelGGL((k_fft_fwd<1024, 8, OutT, PIX>), grid, dim3(1024), lds, p.stream, maps, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, out, MFWF_FFT_ARGS(c, rs));
         MFWF_HIP(hipGetLastError());
     }
     return MFWF_OK;
@@ -292,12 +294,13 @@ static int inv_classes(const Plan &p, const InT *in, double *maps, int nb) {
         const int tpb = fft_class_shape(p, c, ept);
         const dim3 grid(nb, cnt);  // maps of one pair adjacent: its tables and M stay in L2
         const size_t lds = fft_class_lds(p, c);
+        const int rs = sizeof(InT) == sizeof(float2) ? p.nm32 : p.nm;
         if (tpb == 256)
-            hipLaunchKernelGGL((k_fft_inv<256, 8, InT>), grid, dim3(256), lds, p.stream, in, maps, MFWF_FFT_ARGS(c));
+            hipLaunchKernelGGL((k_fft_inv<256, 8, InT>), grid, dim3(256), lds, p.stream, in, maps, MFWF_FFT_ARGS(c, rs));
         else if (tpb == 512)
-            hipLaunchKernelGGL((k_fft_inv<512, 8, InT>), grid, dim3(512), lds, p.stream, in, maps, MFWF_FFT_ARGS(c));
+            hipLaunchKernelGGL((k_fft_inv<512, 8, InT>), grid, dim3(512), lds, p.stream, in, maps, MFWF_FFT_ARGS(c, rs));
         else
-            hipLaunchKernelGGL((k_fft_inv<1024, 8, InT>), grid, dim3(1024), lds, p.stream, in, maps, MFWF_FFT_ARGS(c));
+            hipLaunchKernelGGL((k_fft_inv<1024, 8, InT>), grid, dim3(1024), lds, p.stream, in, maps, MFWF_FFT_ARGS(c, rs));
         MFWF_HIP(hipGetLastError());
     }
     return MFWF_OK;

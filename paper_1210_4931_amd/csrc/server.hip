@@ -132,7 +132,7 @@ static size_t estimate_pool_bytes(int nside, int lmax, int dtype, int B) {
         const double Bp = 16.0 * ((B + 15) / 16);
         b += 16.0 * nm * nring + 16.0 * groups * nalm;           // unused FP64 rows, 1 map
         b += 4.0 * npair * (nalm + 64.0 * nm) * 1.05;            // lambda table (padded)
-        b += 8.0 * B * nring * nm + 4.0 * nring * nm * 2 * Bp;   // per-map rows, column layout
+        b += 8.0 * B * nring * (nm + 15) + 4.0 * nring * nm * 2 * Bp;  // rows, column layout
         b += 2 * 4.0 * nalm * 2 * Bp;                            // coefficients in columns
     } else {
         b += 16.0 * B * nm * nring + 16.0 * groups * B * nalm;
