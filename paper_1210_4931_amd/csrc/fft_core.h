@@ -85,12 +85,19 @@ __device__ __forceinline__ void small_dft(double2 (&v)[R]) {
     }
 }
 
+// Elementwise step applied to the inputs of a first pass (Bluestein's algorithm): none;
+// times the chirp c_i for i < nv and zero beyond (the zero-padded chirped sequence); or
+// times the transformed kernel k_i, conjugated.
+enum { kPreNone = 0, kPreChirp = 1, kPreKernelConj = 2 };
+
 // One Stockham pass of radix R over buf[0..n): inputs j + r n/R, output (j/Ns) Ns R + j%Ns
 // + r Ns, twiddle exp(-2 pi i (j%Ns) r / (Ns R)).  All reads precede all writes.
-// EPT: most transform elements one thread handles (n <= EPT * TPB).
-template <int TPB, int EPT, int R>
+// EPT: most transform elements one thread handles (n <= EPT * TPB).  PRE != kPreNone only
+// on a first pass (Ns = 1, no twiddles), with its table pre.
+template <int TPB, int EPT, int R, int PRE = kPreNone>
 __device__ __forceinline__ void stockham_pass(double2 *buf, int n, int Ns, const Twiddles &tw,
-                                              int fftmax) {
+                                              int fftmax, const double2 *__restrict__ pre = nullptr,
+                                              int nv = 0) {
     constexpr int MAXB = EPT / R;
     const int nbf = n / R;
     double2 v[MAXB][R];
@@ -100,6 +107,16 @@ __device__ __forceinline__ void stockham_pass(double2 *buf, int n, int Ns, const
         if (j < nbf) {
 #pragma unroll
             for (int r = 0; r < R; r++) v[b][r] = buf[lds_ix(j + r * nbf)];
+            if constexpr (PRE == kPreChirp) {
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    const int i = j + r * nbf;
+                    v[b][r] = (i < nv) ? cmul(v[b][r], pre[min(i, nv - 1)]) : make_double2(0.0, 0.0);
+                }
+            } else if constexpr (PRE == kPreKernelConj) {
+#pragma unroll
+                for (int r = 0; r < R; r++) v[b][r] = cconj(cmul(v[b][r], pre[j + r * nbf]));
+            }
         }
     }
     __syncthreads();
@@ -109,7 +126,7 @@ __device__ __forceinline__ void stockham_pass(double2 *buf, int n, int Ns, const
         const int j = threadIdx.x + b * TPB;
         if (j < nbf) {
             const int kk = j & (Ns - 1);
-            if (Ns > 1) {
+            if (PRE == kPreNone && Ns > 1) {
                 // one table twiddle w per butterfly; w^r as products (a few ulp in FP64)
                 double2 wr[R];
                 wr[1] = tw(kk * ts);
@@ -127,10 +144,24 @@ __device__ __forceinline__ void stockham_pass(double2 *buf, int n, int Ns, const
     __syncthreads();
 }
 
-// Forward DFT of buf[0..n), n a power of two <= EPT * TPB, natural order in and out.
-template <int TPB, int EPT>
-__device__ __forceinline__ void fft_stockham(double2 *buf, int n, const Twiddles &tw, int fftmax) {
+// Forward DFT of buf[0..n), n a power of two <= EPT * TPB, natural order in and out; PRE
+// (with pre, nv) on the inputs of the first pass.
+template <int TPB, int EPT, int PRE = kPreNone>
+__device__ __forceinline__ void fft_stockham(double2 *buf, int n, const Twiddles &tw, int fftmax,
+                                             const double2 *__restrict__ pre = nullptr, int nv = 0) {
     int Ns = 1;
+    if constexpr (PRE != kPreNone) {
+        if (n >= 8) {
+            stockham_pass<TPB, EPT, 8, PRE>(buf, n, 1, tw, fftmax, pre, nv);
+            Ns = 8;
+        } else if (n == 4) {
+            stockham_pass<TPB, EPT, 4, PRE>(buf, n, 1, tw, fftmax, pre, nv);
+            Ns = 4;
+        } else {
+            stockham_pass<TPB, EPT, 2, PRE>(buf, n, 1, tw, fftmax, pre, nv);
+            Ns = 2;
+        }
+    }
     while (Ns < n) {
         const int left = n / Ns;
         if (left >= 8) {
@@ -157,15 +188,11 @@ __device__ __forceinline__ void ring_dft(double2 *buf, const PairFFT &pf, const 
         fft_stockham<TPB, EPT>(buf, n, tw, fftmax);
         return;
     }
-    const double2 *c = chirp + pf.chirp_off;
-    for (int j = threadIdx.x; j < M; j += TPB)
-        buf[lds_ix(j)] = (j < n) ? cmul(buf[lds_ix(j)], c[j]) : make_double2(0.0, 0.0);
-    __syncthreads();
-    fft_stockham<TPB, EPT>(buf, M, tw, fftmax);
-    const double2 *bh = bhat + pf.bhat_off;  // transformed conj chirp, already divided by M
-    for (int j = threadIdx.x; j < M; j += TPB) buf[lds_ix(j)] = cconj(cmul(buf[lds_ix(j)], bh[j]));
-    __syncthreads();
-    fft_stockham<TPB, EPT>(buf, M, tw, fftmax);
+    // the chirped input, zero-padded to M, transformed; times the transformed conj chirp
+    // (already divided by M) and conjugated, transformed again: the conjugated convolution.
+    // Both elementwise steps ride on the reads of the transforms' first passes.
+    fft_stockham<TPB, EPT, kPreChirp>(buf, M, tw, fftmax, chirp + pf.chirp_off, n);
+    fft_stockham<TPB, EPT, kPreKernelConj>(buf, M, tw, fftmax, bhat + pf.bhat_off, M);
 }
 
 __device__ __forceinline__ double2 dft_bin(const double2 *buf, const PairFFT &pf,

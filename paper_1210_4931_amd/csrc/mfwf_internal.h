@@ -69,7 +69,7 @@ struct Plan {
     double2 *d_twhi = nullptr;   // [fft_ntwhi] exp(-2 pi i 64 h / fftmax)
     int fft_ntwhi = 1;
     double2 *d_chirp = nullptr;  // Bluestein chirps exp(-i pi k^2 / n), per distinct n
-    double2 *d_bhat = nullptr;   // Bluestein kernels FFT_M(conj chirp), bit-reversed order
+    double2 *d_bhat = nullptr;   // Bluestein kernels FFT_M(conj chirp) / M, natural order
     int fftmax;                  // largest power-of-two transform length
     int *d_plist = nullptr;      // [npair] pair indices grouped by FFT class
     int fft_class_off[2] = {0, 0}, fft_class_count[2] = {0, 0}, fft_class_len[2] = {1, 1};

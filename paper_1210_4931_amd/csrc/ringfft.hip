@@ -98,7 +98,7 @@ k_fft_fwd(const double *__restrict__ maps, const double *__restrict__ rho,
     OutT *outN = phase + ((long)b * nring + p) * nm;
     OutT *outS = phase + ((long)b * nring + (nring - 1 - p)) * nm;
     for (int m = threadIdx.x; m <= lmax; m += TPB) {
-        const int q = m / n, k = m - q * n;
+        const int q = (n > lmax) ? 0 : m / n, k = m - q * n;  // no alias when n > lmax
         const int kr = (k == 0) ? 0 : n - k;
         const double2 X = dft_bin(buf, pf, chirp, k);
         const double2 Y = cconj(dft_bin(buf, pf, chirp, kr));
