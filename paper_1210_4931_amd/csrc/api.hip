@@ -724,8 +724,15 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
 
 // FP32 form: Legendre steps as MFMA GEMMs over the batch (Eqs. 3-4 unchanged)
 static int iteration_b(Plan &p, const double *rho, int nb, double lam, bool keep_prev) {
-    // pixel update (Eq. 3) applied inside the forward ring transforms
-    MFWF_TRY(launch_fft_fwd_f32(p, p.d_smap, rho, lam, p.d_phf, nb));
+    if (p.chain) {
+        // the previous synthesis (zero at the start) back to pixels, the pixel update (Eq. 3)
+        // and the forward ring transforms, in one kernel
+        MFWF_TRY(launch_cols_to_rows(p, nb));
+        MFWF_TRY(launch_fft_inv_fwd_f32(p, rho, lam, nullptr, nb));
+    } else {
+        // pixel update (Eq. 3) applied inside the forward ring transforms
+        MFWF_TRY(launch_fft_fwd_f32(p, p.d_smap, rho, lam, p.d_phf, nb));
+    }
     MFWF_TRY(launch_rows_to_cols(p, nb));
     if (keep_prev) MFWF_TRY(launch_cols_to_alm(p, p.d_s32, p.d_salm_prev, nb, 1.0));
     // analysis with the harmonic update (Eq. 4) applied in its epilogue
@@ -733,8 +740,10 @@ static int iteration_b(Plan &p, const double *rho, int nb, double lam, bool keep
                                   lam * p.omega));
     if (keep_prev) MFWF_TRY(launch_cols_to_alm(p, p.d_s32, p.d_salm, nb, 1.0));
     MFWF_TRY(launch_gemm_synthesis(p, nb));
-    MFWF_TRY(launch_cols_to_rows(p, nb));
-    MFWF_TRY(launch_fft_inv_f32(p, p.d_phf, p.d_smap, nb));
+    if (!p.chain || keep_prev) {  // the map s of this iteration
+        MFWF_TRY(launch_cols_to_rows(p, nb));
+        MFWF_TRY(launch_fft_inv_f32(p, p.d_phf, p.d_smap, nb));
+    }
     return MFWF_OK;
 }
 
@@ -864,6 +873,16 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
     }
     MFWF_TRY(launch_fill(p.d_smap, nc * p.npix * nb, 0.0, p.stream));
     MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm), 2 * nc * p.nalm * nb, 0.0, p.stream));
+    // batched temperature form: iterations chained through the synthesis columns, which
+    // start at zero (s = 0); the last iteration is a check, so d_smap holds the final map
+    struct ChainOff {
+        Plan &p;
+        ~ChainOff() { p.chain = false; }
+    } chain_off{p};
+    if (p.dtype == MFWF_F32 && p.spin == 0) {
+        MFWF_HIP(hipMemsetAsync(p.d_ph32, 0, sizeof(float) * (size_t)p.nring * p.nm * p.C2, p.stream));
+        p.chain = true;
+    }
     if (p.dtype == MFWF_F32) {  // previous harmonic iterate = 0 (outside any graph capture)
         MFWF_HIP(hipMemsetAsync(p.d_s32, 0, sizeof(float) * (size_t)p.nalm * p.C2, p.stream));
         if (p.spin == 2)

@@ -117,6 +117,10 @@ struct Plan {
     int *d_lofi = nullptr;       // [nalm] l of each packed index
     float2 *d_phf = nullptr;     // [B][nring][nm32] ring-Fourier rows of the transforms
     int nm32 = 0;                // row stride of d_phf: nm rounded up to whole 128-byte lines
+    // batched FP32 iterations chained through the synthesis columns d_ph32: each iteration
+    // starts with the previous one's inverse ring transforms, fused with its own pixel update
+    // and forward transforms; d_smap is written only by iterations that keep diagnostics
+    bool chain = false;
     float *d_ph32 = nullptr;     // [nm][nring][C2] ring-Fourier, maps innermost
     float *d_a32 = nullptr;      // [nalm][C2] analysis output
     float *d_s32 = nullptr;      // [nalm][C2] synthesis input
@@ -165,6 +169,9 @@ int launch_fft_inv(const Plan &p, const double2 *phase, double *maps, int nb);
 int launch_fft_fwd_f32(const Plan &p, const double *maps, const double *rho, double lam,
                        float2 *phase, int nb);
 int launch_fft_inv_f32(const Plan &p, const float2 *phase, double *maps, int nb);
+// FP32 rows d_phf of a synthesis -> maps s (to smap if not null) -> t of Eq. (3) -> rows of
+// its forward transform, in place (one iteration's ring steps without the map in memory)
+int launch_fft_inv_fwd_f32(const Plan &p, const double *rho, double lam, double *smap, int nb);
 int fft_class_shape(const Plan &p, int c, int &ept);  // threads per workgroup of class c
 size_t fft_class_lds(const Plan &p, int c);           // dynamic LDS bytes of class c
 

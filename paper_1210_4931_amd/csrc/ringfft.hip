@@ -41,6 +41,34 @@ __device__ __forceinline__ double2 get_c(const float2 *q) {
     return make_double2(v.x, v.y);
 }
 
+// Ring-Fourier rows of a transformed pair: G_r(m) = sum_j t_{r,j} e^{-i m phi_{r,j}}, m = 0..lmax,
+// for the north ring (outN) and, off the equator, the south ring (outS), from the DFT of
+// x = t_N + i t_S in buf.
+template <int TPB, typename OutT>
+__device__ __forceinline__ void store_rows(const double2 *buf, const PairFFT &pf,
+                                           const Twiddles &tw, int fftmax,
+                                           const double2 *__restrict__ chirp, int lmax,
+                                           OutT *outN, OutT *outS) {
+    const int n = pf.nphi;
+    const bool equator = (pf.startS == pf.startN);
+    for (int m = threadIdx.x; m <= lmax; m += TPB) {
+        const int q = (n > lmax) ? 0 : m / n, k = m - q * n;  // no alias when n > lmax
+        const int kr = (k == 0) ? 0 : n - k;
+        const double2 X = dft_bin(buf, pf, chirp, k);
+        const double2 Y = cconj(dft_bin(buf, pf, chirp, kr));
+        // e^{-i m phi0} = (-1)^q e^{-i pi k / n} with a half shift, 1 otherwise
+        double2 ph = make_double2(1.0, 0.0);
+        if (pf.half_shift) ph = cscale(cconj(half_bin_phase(k, n, tw, fftmax)), (q & 1) ? -1.0 : 1.0);
+        // X_N = (X_k + conj X_{-k}) / 2,  X_S = (X_k - conj X_{-k}) / (2i)
+        const double2 gN = make_double2(0.5 * (X.x + Y.x), 0.5 * (X.y + Y.y));
+        put_c(outN + m, cmul(gN, ph));
+        if (!equator) {
+            const double2 gS = make_double2(0.5 * (X.y - Y.y), -0.5 * (X.x - Y.x));
+            put_c(outS + m, cmul(gS, ph));
+        }
+    }
+}
+
 // Forward transform of maps[b] (PIX = false) or of the messenger field of Eq. (3),
 // t = [lam tau rho + (1 - tau M) s] / [1 + (lam - 1) tau M], with s = maps[b], rho = rho[b].
 template <int TPB, int EPT, typename OutT, bool PIX>
@@ -95,45 +123,21 @@ k_fft_fwd(const double *__restrict__ maps, const double *__restrict__ rho,
     }
     __syncthreads();
     ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
-    OutT *outN = phase + ((long)b * nring + p) * nm;
-    OutT *outS = phase + ((long)b * nring + (nring - 1 - p)) * nm;
-    for (int m = threadIdx.x; m <= lmax; m += TPB) {
-        const int q = (n > lmax) ? 0 : m / n, k = m - q * n;  // no alias when n > lmax
-        const int kr = (k == 0) ? 0 : n - k;
-        const double2 X = dft_bin(buf, pf, chirp, k);
-        const double2 Y = cconj(dft_bin(buf, pf, chirp, kr));
-        // e^{-i m phi0} = (-1)^q e^{-i pi k / n} with a half shift, 1 otherwise
-        double2 ph = make_double2(1.0, 0.0);
-        if (pf.half_shift) ph = cscale(cconj(half_bin_phase(k, n, tw, fftmax)), (q & 1) ? -1.0 : 1.0);
-        // X_N = (X_k + conj X_{-k}) / 2,  X_S = (X_k - conj X_{-k}) / (2i)
-        const double2 gN = make_double2(0.5 * (X.x + Y.x), 0.5 * (X.y + Y.y));
-        put_c(outN + m, cmul(gN, ph));
-        if (!equator) {
-            const double2 gS = make_double2(0.5 * (X.y - Y.y), -0.5 * (X.x - Y.x));
-            put_c(outS + m, cmul(gS, ph));
-        }
-    }
+    store_rows<TPB>(buf, pf, tw, fftmax, chirp, lmax, phase + ((long)b * nring + p) * nm,
+                    phase + ((long)b * nring + (nring - 1 - p)) * nm);
 }
 
+// Fold the ring-Fourier rows FN, FS of a pair into the bins of its inverse transform, in
+// LDS (x_j = sum_k X_k e^{+2 pi i j k / n} is then conj(DFT(conj X))_j with X = B_N + i B_S).
 template <int TPB, int EPT, typename InT>
-__global__ void __launch_bounds__(TPB)
-k_fft_inv(const InT *__restrict__ phase, double *__restrict__ maps,
-          const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
-          const double2 *__restrict__ twlo, const double2 *__restrict__ twhi, int ntwhi,
-          int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
-          long npix, int nring, int nm, int lmax, int fftlen_class) {
-    extern __shared__ double2 buf[];
-    const int p = plist[blockIdx.y], b = blockIdx.x;
-    const PairFFT pf = pfft[p];
+__device__ __forceinline__ void fold_bins(double2 *buf, const InT *FN, const InT *FS,
+                                          const PairFFT &pf, const Twiddles &tw, int fftmax,
+                                          int lmax) {
     const int n = pf.nphi;
+    const bool equator = (pf.startS == pf.startN);
     // alias-sum partials, used only with T > 1, i.e. n <= TPB / 2: after element TPB / 2
     double2 *partN = buf + lds_ix(TPB / 2);
     double2 *partS = partN + TPB;
-    const bool equator = (pf.startS == pf.startN);
-    const Twiddles tw = load_twiddles(buf, fft_area(fftlen_class, TPB), twlo, twhi, ntwhi);
-    const InT *FN = phase + ((long)b * nring + p) * nm;
-    const InT *FS = phase + ((long)b * nring + (nring - 1 - p)) * nm;
-
     // Fold harmonics into bins: S(k) = sum_q sgn_q F(k + q n) over |k + q n| <= lmax with
     // F(-m) = conj F(m) and sgn_q = (-1)^q under a half shift; then B(k) = e^{i pi k/n} S(k).
     // T threads per bin split the alias sum; partials are combined in a fixed order.
@@ -232,6 +236,24 @@ k_fft_inv(const InT *__restrict__ phase, double *__restrict__ maps,
             buf[lds_ix(k)] = cconj(make_double2(sN.x - sS.y, sN.y + sS.x));
         }
     }
+}
+
+template <int TPB, int EPT, typename InT>
+__global__ void __launch_bounds__(TPB)
+k_fft_inv(const InT *__restrict__ phase, double *__restrict__ maps,
+          const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
+          const double2 *__restrict__ twlo, const double2 *__restrict__ twhi, int ntwhi,
+          int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
+          long npix, int nring, int nm, int lmax, int fftlen_class) {
+    extern __shared__ double2 buf[];
+    const int p = plist[blockIdx.y], b = blockIdx.x;
+    const PairFFT pf = pfft[p];
+    const int n = pf.nphi;
+    const bool equator = (pf.startS == pf.startN);
+    const Twiddles tw = load_twiddles(buf, fft_area(fftlen_class, TPB), twlo, twhi, ntwhi);
+    const InT *FN = phase + ((long)b * nring + p) * nm;
+    const InT *FS = phase + ((long)b * nring + (nring - 1 - p)) * nm;
+    fold_bins<TPB, EPT>(buf, FN, FS, pf, tw, fftmax, lmax);
     __syncthreads();
     ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
     double *sNmap = maps + (long)b * npix + pf.startN;
@@ -241,6 +263,70 @@ k_fft_inv(const InT *__restrict__ phase, double *__restrict__ maps,
         sNmap[j] = x.x;
         if (!equator) sSmap[j] = x.y;
     }
+}
+
+// One iteration's ring steps in one pass over a pair (batched FP32 form): the rows F of the
+// synthesis are folded and transformed back to the pair's pixels s (optionally stored to
+// smap), the messenger field t of Eq. (3) is formed from s, rho and M on the spot, and its
+// transform overwrites the rows with G = the analysis input.  The map s never travels
+// through memory; the arithmetic is that of k_fft_inv followed by k_fft_fwd<PIX>.
+template <int TPB, int EPT>
+__global__ void __launch_bounds__(TPB)
+k_fft_inv_fwd(float2 *__restrict__ rows, double *__restrict__ smap,
+              const double *__restrict__ rho, const double *__restrict__ M, double lam,
+              double tau, long mstride, const double *__restrict__ tau_b,
+              const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
+              const double2 *__restrict__ twlo, const double2 *__restrict__ twhi, int ntwhi,
+              int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
+              long npix, int nring, int nm, int lmax, int fftlen_class) {
+    extern __shared__ double2 buf[];
+    const int p = plist[blockIdx.y], b = blockIdx.x;
+    const PairFFT pf = pfft[p];
+    const int n = pf.nphi;
+    const bool equator = (pf.startS == pf.startN);
+    const Twiddles tw = load_twiddles(buf, fft_area(fftlen_class, TPB), twlo, twhi, ntwhi);
+    float2 *FN = rows + ((long)b * nring + p) * nm;
+    float2 *FS = rows + ((long)b * nring + (nring - 1 - p)) * nm;
+    fold_bins<TPB, EPT>(buf, FN, FS, pf, tw, fftmax, lmax);
+    __syncthreads();
+    ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
+    if (tau_b) tau = tau_b[b];
+    const double lt = lam * tau, l1t = (lam - 1.0) * tau;
+    const double *rp = rho + (long)b * npix;
+    const double *mp = M + (long)b * mstride;
+    double mN[EPT], mS[EPT], rN[EPT], rS[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; u++) {
+        const int j = min((int)threadIdx.x + u * TPB, n - 1);
+        mN[u] = mp[pf.startN + j];
+        mS[u] = mp[pf.startS + j];
+        rN[u] = rp[pf.startN + j];
+        rS[u] = rp[pf.startS + j];
+    }
+    auto pix = [&](double x, double m, double r) {
+        const double num = lt * r + (1.0 - tau * m) * x;
+        return (lam == 1.0) ? num : num / (1.0 + l1t * m);
+    };
+    double2 v[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; u++) {
+        const int j = threadIdx.x + u * TPB;
+        const double2 x = cconj(dft_bin(buf, pf, chirp, min(j, n - 1)));  // (s_N, s_S) at j
+        if (smap && j < n) {
+            smap[(long)b * npix + pf.startN + j] = x.x;
+            if (!equator) smap[(long)b * npix + pf.startS + j] = x.y;
+        }
+        v[u] = make_double2(pix(x.x, mN[u], rN[u]), equator ? 0.0 : pix(x.y, mS[u], rS[u]));
+    }
+    __syncthreads();  // every read of the inverse transform is done
+#pragma unroll
+    for (int u = 0; u < EPT; u++) {
+        const int j = threadIdx.x + u * TPB;
+        if (j < n) buf[lds_ix(j)] = v[u];
+    }
+    __syncthreads();
+    ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
+    store_rows<TPB>(buf, pf, tw, fftmax, chirp, lmax, FN, FS);
 }
 
 // (threads per workgroup, elements per thread) of a class: 8 elements (one radix-8
@@ -324,6 +410,26 @@ int launch_fft_inv_f32(const Plan &p, const float2 *phase, double *maps, int nb)
     return inv_classes<float2>(p, phase, maps, nb);
 }
 
+int launch_fft_inv_fwd_f32(const Plan &p, const double *rho, double lam, double *smap, int nb) {
+    for (int c = 1; c >= 0; c--) {
+        const int cnt = p.fft_class_count[c];
+        if (cnt == 0) continue;
+        int ept;
+        const int tpb = fft_class_shape(p, c, ept);
+        const dim3 grid(nb, cnt);
+        const size_t lds = fft_class_lds(p, c);
+        const int rs = p.nm32;
+        if (tpb == 256)
+            hipLaunchKernelGGL((k_fft_inv_fwd<256, 8>), grid, dim3(256), lds, p.stream, p.d_phf, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs));
+        else if (tpb == 512)
+            hipLaunchKernelGGL((k_fft_inv_fwd<512, 8>), grid, dim3(512), lds, p.stream, p.d_phf, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs));
+        else
+            hipLaunchKernelGGL((k_fft_inv_fwd<1024, 8>), grid, dim3(1024), lds, p.stream, p.d_phf, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs));
+        MFWF_HIP(hipGetLastError());
+    }
+    return MFWF_OK;
+}
+
 int fft_max_length() { return 8 * 1024; }
 
 // Maximum dynamic LDS the FFT kernels may request (set once per process).
@@ -332,6 +438,13 @@ static int fwd_lds(int bytes) {
     const void *fns[] = {(const void *)k_fft_fwd<256, 8, OutT, PIX>,
                          (const void *)k_fft_fwd<512, 8, OutT, PIX>,
                          (const void *)k_fft_fwd<1024, 8, OutT, PIX>};
+    for (const void *f : fns)
+        MFWF_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    return MFWF_OK;
+}
+static int inv_fwd_lds(int bytes) {
+    const void *fns[] = {(const void *)k_fft_inv_fwd<256, 8>, (const void *)k_fft_inv_fwd<512, 8>,
+                         (const void *)k_fft_inv_fwd<1024, 8>};
     for (const void *f : fns)
         MFWF_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
     return MFWF_OK;
@@ -359,6 +472,7 @@ int fft_set_lds_limit(size_t bytes) {
     MFWF_TRY((fwd_lds<float2, true>((int)bytes)));
     MFWF_TRY(inv_lds<double2>((int)bytes));
     MFWF_TRY(inv_lds<float2>((int)bytes));
+    MFWF_TRY(inv_fwd_lds((int)bytes));
     return MFWF_OK;
 }
 
