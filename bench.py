@@ -283,8 +283,11 @@ def main():
         "sht_pair_tflops": 2 * gemm_flops / (pair32 * 1e-3) / 1e12,
         "kernel_ms": kt32,
         "fused": {"pixel_update": "inside fft_fwd", "harmonic": "inside leg_analysis",
-                  "note": "fft_fwd / fft_inv include the layout transposes to and from the "
-                          "matrix-core column layout"},
+                  "fft_inv": "inside fft_fwd",
+                  "note": "fft_fwd is the ring step of a chained iteration: the previous "
+                          "synthesis back to pixels, the pixel update and the forward ring "
+                          "transforms in one kernel, with the layout transposes to and from "
+                          "the matrix-core column layout"},
         "legendre_triples": {"evaluated": work, "full_triangle": full},
         "roofline": {"bound": "mfma", "kernel": "gemm_" + dom32.split("_")[1],
                      "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,

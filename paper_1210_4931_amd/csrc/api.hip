@@ -724,7 +724,7 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
 
 // FP32 form: Legendre steps as MFMA GEMMs over the batch (Eqs. 3-4 unchanged)
 static int iteration_b(Plan &p, const double *rho, int nb, double lam, bool keep_prev) {
-    if (p.chain) {
+    if (p.chain && p.chain_ready) {
         // the previous synthesis (zero at the start) back to pixels, the pixel update (Eq. 3)
         // and the forward ring transforms, in one kernel
         MFWF_TRY(launch_cols_to_rows(p, nb));
@@ -740,6 +740,7 @@ static int iteration_b(Plan &p, const double *rho, int nb, double lam, bool keep
                                   lam * p.omega));
     if (keep_prev) MFWF_TRY(launch_cols_to_alm(p, p.d_s32, p.d_salm, nb, 1.0));
     MFWF_TRY(launch_gemm_synthesis(p, nb));
+    p.chain_ready = true;
     if (!p.chain || keep_prev) {  // the map s of this iteration
         MFWF_TRY(launch_cols_to_rows(p, nb));
         MFWF_TRY(launch_fft_inv_f32(p, p.d_phf, p.d_smap, nb));
@@ -877,11 +878,11 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
     // start at zero (s = 0); the last iteration is a check, so d_smap holds the final map
     struct ChainOff {
         Plan &p;
-        ~ChainOff() { p.chain = false; }
+        ~ChainOff() { p.chain = p.chain_ready = false; }
     } chain_off{p};
     if (p.dtype == MFWF_F32 && p.spin == 0) {
         MFWF_HIP(hipMemsetAsync(p.d_ph32, 0, sizeof(float) * (size_t)p.nring * p.nm * p.C2, p.stream));
-        p.chain = true;
+        p.chain = p.chain_ready = true;
     }
     if (p.dtype == MFWF_F32) {  // previous harmonic iterate = 0 (outside any graph capture)
         MFWF_HIP(hipMemsetAsync(p.d_s32, 0, sizeof(float) * (size_t)p.nalm * p.C2, p.stream));
@@ -1392,6 +1393,14 @@ static int cooled_chunk(mfwf_plan plan, const double *data, int nb, double *s_al
     const double sigma = std::sqrt(2.0 * (double)p.ndof), tomega = p.tau * p.omega;
     std::vector<double> dg(8L * nb), prev(nb);
     Plan *cur = nullptr;
+    // chained iterations stay within this solve: every plan it used leaves without them
+    struct ChainOff {
+        mfwf_plan plan;
+        ~ChainOff() {
+            plan->p.chain = plan->p.chain_ready = false;
+            for (auto &kv : plan->sub) kv.second->p.chain = kv.second->p.chain_ready = false;
+        }
+    } chain_off{plan};
     int l_iter = std::min(o.l0, p.lmax);
     long total = 0;
     double lam = 1.0;
@@ -1419,6 +1428,10 @@ static int cooled_chunk(mfwf_plan plan, const double *data, int nb, double *s_al
                 if (q->spin == 2)
                     MFWF_HIP(hipMemsetAsync(q->d_seb32, 0, sizeof(float) * (size_t)q->nalm * 2 * q->C2, q->stream));
             }
+            // batched temperature form: chained iterations once the first one on this plan
+            // has run from the map
+            q->chain = (q->dtype == MFWF_F32 && q->spin == 0);
+            q->chain_ready = false;
             cur = q;
         }
         StageGraph sg;
@@ -1426,7 +1439,11 @@ static int cooled_chunk(mfwf_plan plan, const double *data, int nb, double *s_al
         long its = 0;
         while (total < o.max_iters) {
             const long run = std::min<long>(o.nchk, o.max_iters - total);
-            const long plain = run - 1;
+            long plain = run - 1;
+            if (q->chain && !q->chain_ready && plain > 0) {  // before any capture
+                MFWF_TRY(iteration(*q, rho, nb, lam, false));
+                plain--;
+            }
             if (plain >= 2 && q->stream != nullptr) {
                 if (!captured) {
                     MFWF_TRY(sg.capture(*q, rho, nb, lam));
@@ -1790,11 +1807,17 @@ int mfwf_time_kernels(mfwf_plan plan, int nmaps, int reps, double *ms_out) {
         if (f32) {
             switch (k) {
                 case 0: ms_out[k] = 0.0; continue;  // pixel update runs inside the forward transforms
-                case 1: f = [&] { MFWF_TRY(launch_fft_fwd_f32(p, p.d_smap, p.d_rho, 1.0, p.d_phf, nb)); return launch_rows_to_cols(p, nb); }; break;
+                // 1: the ring steps of a chained iteration: layout to rows, the previous
+                // synthesis back to pixels, pixel update and forward transforms in one kernel,
+                // layout to columns (the inverse transforms run there, so 5 is empty)
+                case 1: f = [&] {
+                    MFWF_TRY(launch_cols_to_rows(p, nb));
+                    MFWF_TRY(launch_fft_inv_fwd_f32(p, p.d_rho, 1.0, nullptr, nb));
+                    return launch_rows_to_cols(p, nb); }; break;
                 case 2: f = [&] { return launch_gemm_analysis(p, nb, nullptr, p.d_s32, p.omega, p.omega * p.tau, p.omega); }; break;
                 case 3: ms_out[k] = 0.0; continue;  // harmonic update runs inside the analysis
                 case 4: f = [&] { return launch_gemm_synthesis(p, nb); }; break;
-                default: f = [&] { MFWF_TRY(launch_cols_to_rows(p, nb)); return launch_fft_inv_f32(p, p.d_phf, p.d_smap, nb); }; break;
+                default: ms_out[k] = 0.0; continue;
             }
             float ms = 0.f;
             MFWF_TRY(time_launches(p, reps, f, ms));

@@ -121,6 +121,7 @@ struct Plan {
     // starts with the previous one's inverse ring transforms, fused with its own pixel update
     // and forward transforms; d_smap is written only by iterations that keep diagnostics
     bool chain = false;
+    bool chain_ready = false;    // d_ph32 holds the synthesis of the iterate in d_smap
     float *d_ph32 = nullptr;     // [nm][nring][C2] ring-Fourier, maps innermost
     float *d_a32 = nullptr;      // [nalm][C2] analysis output
     float *d_s32 = nullptr;      // [nalm][C2] synthesis input

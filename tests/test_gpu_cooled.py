@@ -127,3 +127,27 @@ def test_cooled_errors(mf):
     with pytest.raises(MFWFError):
         mf.Plan(4, 8, spin=2).solve_cooled(torch.zeros((1, 3, 192), dtype=torch.float64,
                                                        device="cuda"))
+
+
+def test_f32_solve_kinds_share_a_plan(mf):
+    """The batched FP32 plan runs chained iterations in plain and cooled solves; a later solve
+    of any kind on the same plan starts from its own state: every result equals the one of a
+    fresh plan, bit for bit."""
+    nside, lmax = 16, 32
+    wl, d, M = temperature_problem(nside, lmax, seed=3)
+    rng = np.random.default_rng(11)
+    ds = dev(np.stack([d, d + rng.standard_normal(d.size) * np.sqrt(wl.noise_var)]))
+
+    def fresh():
+        q = mf.Plan(nside, lmax, max_batch=2, dtype="f32")
+        q.set_covariances(wl.cl, dev(1.0 / wl.noise_var), dev(wl.mask, torch.uint8))
+        return q
+
+    plain_ref = fresh().solve(ds, iters=40)[0]
+    cooled_ref = fresh().solve_cooled(ds, l_iter0=4, l_margin=8, max_iters=400)[0]
+    bounded_ref = fresh().solve_bounded(ds, max_iters=60)[0]
+    q = fresh()
+    for _ in range(2):
+        assert torch.equal(q.solve_cooled(ds, l_iter0=4, l_margin=8, max_iters=400)[0], cooled_ref)
+        assert torch.equal(q.solve_bounded(ds, max_iters=60)[0], bounded_ref)
+        assert torch.equal(q.solve(ds, iters=40)[0], plain_ref)
