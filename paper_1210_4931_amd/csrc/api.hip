@@ -726,14 +726,13 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
 static int iteration_b(Plan &p, const double *rho, int nb, double lam, bool keep_prev) {
     if (p.chain && p.chain_ready) {
         // the previous synthesis (zero at the start) back to pixels, the pixel update (Eq. 3)
-        // and the forward ring transforms, in one kernel
-        MFWF_TRY(launch_cols_to_rows(p, nb));
-        MFWF_TRY(launch_fft_inv_fwd_f32(p, rho, lam, nullptr, nb));
+        // and the forward ring transforms, in one kernel on the matrix-core columns
+        MFWF_TRY(launch_fft_inv_fwd_cols(p, rho, lam, nullptr, nb));
     } else {
         // pixel update (Eq. 3) applied inside the forward ring transforms
         MFWF_TRY(launch_fft_fwd_f32(p, p.d_smap, rho, lam, p.d_phf, nb));
+        MFWF_TRY(launch_rows_to_cols(p, nb));
     }
-    MFWF_TRY(launch_rows_to_cols(p, nb));
     if (keep_prev) MFWF_TRY(launch_cols_to_alm(p, p.d_s32, p.d_salm_prev, nb, 1.0));
     // analysis with the harmonic update (Eq. 4) applied in its epilogue
     MFWF_TRY(launch_gemm_analysis(p, nb, nullptr, p.d_s32, p.omega, lam * p.omega * p.tau,
@@ -1807,13 +1806,10 @@ int mfwf_time_kernels(mfwf_plan plan, int nmaps, int reps, double *ms_out) {
         if (f32) {
             switch (k) {
                 case 0: ms_out[k] = 0.0; continue;  // pixel update runs inside the forward transforms
-                // 1: the ring steps of a chained iteration: layout to rows, the previous
-                // synthesis back to pixels, pixel update and forward transforms in one kernel,
-                // layout to columns (the inverse transforms run there, so 5 is empty)
-                case 1: f = [&] {
-                    MFWF_TRY(launch_cols_to_rows(p, nb));
-                    MFWF_TRY(launch_fft_inv_fwd_f32(p, p.d_rho, 1.0, nullptr, nb));
-                    return launch_rows_to_cols(p, nb); }; break;
+                // 1: the ring step of a chained iteration: the previous synthesis back to
+                // pixels, pixel update and forward transforms in one kernel on the columns
+                // (the inverse transforms run there, so 5 is empty)
+                case 1: f = [&] { return launch_fft_inv_fwd_cols(p, p.d_rho, 1.0, nullptr, nb); }; break;
                 case 2: f = [&] { return launch_gemm_analysis(p, nb, nullptr, p.d_s32, p.omega, p.omega * p.tau, p.omega); }; break;
                 case 3: ms_out[k] = 0.0; continue;  // harmonic update runs inside the analysis
                 case 4: f = [&] { return launch_gemm_synthesis(p, nb); }; break;

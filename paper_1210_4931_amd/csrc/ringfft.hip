@@ -41,14 +41,23 @@ __device__ __forceinline__ double2 get_c(const float2 *q) {
     return make_double2(v.x, v.y);
 }
 
+// The coefficients m = 0, 1, ... of one ring: a row (consecutive) or a column of the
+// matrix-core layout [m][ring][C2] (stride cs elements).
+template <typename T, bool STRIDED>
+struct RingSeq {
+    T *p;
+    long cs;
+    __device__ __forceinline__ T &operator[](int m) const { return p[STRIDED ? (long)m * cs : m]; }
+};
+
 // Ring-Fourier rows of a transformed pair: G_r(m) = sum_j t_{r,j} e^{-i m phi_{r,j}}, m = 0..lmax,
 // for the north ring (outN) and, off the equator, the south ring (outS), from the DFT of
 // x = t_N + i t_S in buf.
-template <int TPB, typename OutT>
+template <int TPB, typename OutT, bool STRIDED = false>
 __device__ __forceinline__ void store_rows(const double2 *buf, const PairFFT &pf,
                                            const Twiddles &tw, int fftmax,
                                            const double2 *__restrict__ chirp, int lmax,
-                                           OutT *outN, OutT *outS) {
+                                           RingSeq<OutT, STRIDED> outN, RingSeq<OutT, STRIDED> outS) {
     const int n = pf.nphi;
     const bool equator = (pf.startS == pf.startN);
     for (int m = threadIdx.x; m <= lmax; m += TPB) {
@@ -61,10 +70,10 @@ __device__ __forceinline__ void store_rows(const double2 *buf, const PairFFT &pf
         if (pf.half_shift) ph = cscale(cconj(half_bin_phase(k, n, tw, fftmax)), (q & 1) ? -1.0 : 1.0);
         // X_N = (X_k + conj X_{-k}) / 2,  X_S = (X_k - conj X_{-k}) / (2i)
         const double2 gN = make_double2(0.5 * (X.x + Y.x), 0.5 * (X.y + Y.y));
-        put_c(outN + m, cmul(gN, ph));
+        put_c(&outN[m], cmul(gN, ph));
         if (!equator) {
             const double2 gS = make_double2(0.5 * (X.y - Y.y), -0.5 * (X.x - Y.x));
-            put_c(outS + m, cmul(gS, ph));
+            put_c(&outS[m], cmul(gS, ph));
         }
     }
 }
@@ -123,16 +132,17 @@ k_fft_fwd(const double *__restrict__ maps, const double *__restrict__ rho,
     }
     __syncthreads();
     ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
-    store_rows<TPB>(buf, pf, tw, fftmax, chirp, lmax, phase + ((long)b * nring + p) * nm,
-                    phase + ((long)b * nring + (nring - 1 - p)) * nm);
+    store_rows<TPB>(buf, pf, tw, fftmax, chirp, lmax,
+                    RingSeq<OutT, false>{phase + ((long)b * nring + p) * nm, 1},
+                    RingSeq<OutT, false>{phase + ((long)b * nring + (nring - 1 - p)) * nm, 1});
 }
 
 // Fold the ring-Fourier rows FN, FS of a pair into the bins of its inverse transform, in
 // LDS (x_j = sum_k X_k e^{+2 pi i j k / n} is then conj(DFT(conj X))_j with X = B_N + i B_S).
-template <int TPB, int EPT, typename InT>
-__device__ __forceinline__ void fold_bins(double2 *buf, const InT *FN, const InT *FS,
-                                          const PairFFT &pf, const Twiddles &tw, int fftmax,
-                                          int lmax) {
+template <int TPB, int EPT, typename InT, bool STRIDED = false>
+__device__ __forceinline__ void fold_bins(double2 *buf, RingSeq<const InT, STRIDED> FN,
+                                          RingSeq<const InT, STRIDED> FS, const PairFFT &pf,
+                                          const Twiddles &tw, int fftmax, int lmax) {
     const int n = pf.nphi;
     const bool equator = (pf.startS == pf.startN);
     // alias-sum partials, used only with T > 1, i.e. n <= TPB / 2: after element TPB / 2
@@ -177,13 +187,13 @@ __device__ __forceinline__ void fold_bins(double2 *buf, const InT *FN, const InT
                 if (n <= lmax) {
                     double sg = sgn_step;
                     for (int m = k + n; m <= lmax; m += n, sg *= sgn_step) {
-                        sN = cadd(sN, cscale(get_c(FN + m), sg));
-                        sS = cadd(sS, cscale(get_c(FS + m), sg));
+                        sN = cadd(sN, cscale(get_c(&FN[m]), sg));
+                        sS = cadd(sS, cscale(get_c(&FS[m]), sg));
                     }
                     sg = 1.0;  // sgn_step^2
                     for (int mm = 2 * n - k; mm <= lmax; mm += n) {
-                        sN = cadd(sN, cscale(cconj(get_c(FN + mm)), sg));
-                        sS = cadd(sS, cscale(cconj(get_c(FS + mm)), sg));
+                        sN = cadd(sN, cscale(cconj(get_c(&FN[mm])), sg));
+                        sS = cadd(sS, cscale(cconj(get_c(&FS[mm])), sg));
                         sg *= sgn_step;
                     }
                 }
@@ -204,14 +214,14 @@ __device__ __forceinline__ void fold_bins(double2 *buf, const InT *FN, const InT
             // m = k + q n >= 0, q = t, t + T, ...
             double sg = (t & 1) ? sgn_step : 1.0;
             for (int m = k + t * n; m <= lmax; m += T * n, sg *= sg_stride) {
-                sN = cadd(sN, cscale(get_c(FN + m), sg));
-                if (!equator) sS = cadd(sS, cscale(get_c(FS + m), sg));
+                sN = cadd(sN, cscale(get_c(&FN[m]), sg));
+                if (!equator) sS = cadd(sS, cscale(get_c(&FS[m]), sg));
             }
             // m = k + q n < 0, q = -1 - t, -1 - t - T, ...: F(m) = conj F(-m)
             sg = ((t + 1) & 1) ? sgn_step : 1.0;
             for (int mm = (t + 1) * n - k; mm <= lmax; mm += T * n, sg *= sg_stride) {
-                sN = cadd(sN, cscale(cconj(get_c(FN + mm)), sg));
-                if (!equator) sS = cadd(sS, cscale(cconj(get_c(FS + mm)), sg));
+                sN = cadd(sN, cscale(cconj(get_c(&FN[mm])), sg));
+                if (!equator) sS = cadd(sS, cscale(cconj(get_c(&FS[mm])), sg));
             }
         }
         if (T > 1) {
@@ -251,8 +261,8 @@ k_fft_inv(const InT *__restrict__ phase, double *__restrict__ maps,
     const int n = pf.nphi;
     const bool equator = (pf.startS == pf.startN);
     const Twiddles tw = load_twiddles(buf, fft_area(fftlen_class, TPB), twlo, twhi, ntwhi);
-    const InT *FN = phase + ((long)b * nring + p) * nm;
-    const InT *FS = phase + ((long)b * nring + (nring - 1 - p)) * nm;
+    const RingSeq<const InT, false> FN{phase + ((long)b * nring + p) * nm, 1};
+    const RingSeq<const InT, false> FS{phase + ((long)b * nring + (nring - 1 - p)) * nm, 1};
     fold_bins<TPB, EPT>(buf, FN, FS, pf, tw, fftmax, lmax);
     __syncthreads();
     ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
@@ -270,9 +280,14 @@ k_fft_inv(const InT *__restrict__ phase, double *__restrict__ maps,
 // smap), the messenger field t of Eq. (3) is formed from s, rho and M on the spot, and its
 // transform overwrites the rows with G = the analysis input.  The map s never travels
 // through memory; the arithmetic is that of k_fft_inv followed by k_fft_fwd<PIX>.
-template <int TPB, int EPT>
+// COLS = false: FP32 rows [map][ring][nm], grid (maps, pairs).  COLS = true: the matrix-core
+// columns [m][ring][C2] themselves (map b at column 2b), read and written in place; a 1-D
+// grid whose workgroup L runs on XCD L mod 8 is laid out so that every XCD takes whole
+// pairs, all maps of a pair in a row, so that the maps sharing a 128-byte column segment
+// meet in one L2.
+template <int TPB, int EPT, bool COLS>
 __global__ void __launch_bounds__(TPB)
-k_fft_inv_fwd(float2 *__restrict__ rows, double *__restrict__ smap,
+k_fft_inv_fwd(float2 *__restrict__ data, int C2, int nmap, int npl, double *__restrict__ smap,
               const double *__restrict__ rho, const double *__restrict__ M, double lam,
               double tau, long mstride, const double *__restrict__ tau_b,
               const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
@@ -280,14 +295,27 @@ k_fft_inv_fwd(float2 *__restrict__ rows, double *__restrict__ smap,
               int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
               long npix, int nring, int nm, int lmax, int fftlen_class) {
     extern __shared__ double2 buf[];
-    const int p = plist[blockIdx.y], b = blockIdx.x;
+    int b, pi;
+    if constexpr (COLS) {
+        const int L = blockIdx.x, x = L & 7, sl = L >> 3, j = sl / nmap;
+        b = sl - j * nmap;
+        pi = 8 * j + x;
+        if (pi >= npl) return;  // whole workgroup, before any barrier
+    } else {
+        b = blockIdx.x;
+        pi = blockIdx.y;
+    }
+    const int p = plist[pi];
     const PairFFT pf = pfft[p];
     const int n = pf.nphi;
     const bool equator = (pf.startS == pf.startN);
     const Twiddles tw = load_twiddles(buf, fft_area(fftlen_class, TPB), twlo, twhi, ntwhi);
-    float2 *FN = rows + ((long)b * nring + p) * nm;
-    float2 *FS = rows + ((long)b * nring + (nring - 1 - p)) * nm;
-    fold_bins<TPB, EPT>(buf, FN, FS, pf, tw, fftmax, lmax);
+    const int pS = nring - 1 - p;
+    const long cs = COLS ? (long)nring * (C2 / 2) : 1;  // float2 elements from m to m + 1
+    float2 *FN = COLS ? data + (long)p * (C2 / 2) + b : data + ((long)b * nring + p) * nm;
+    float2 *FS = COLS ? data + (long)pS * (C2 / 2) + b : data + ((long)b * nring + pS) * nm;
+    fold_bins<TPB, EPT>(buf, RingSeq<const float2, COLS>{FN, cs},
+                        RingSeq<const float2, COLS>{FS, cs}, pf, tw, fftmax, lmax);
     __syncthreads();
     ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
     if (tau_b) tau = tau_b[b];
@@ -326,7 +354,8 @@ k_fft_inv_fwd(float2 *__restrict__ rows, double *__restrict__ smap,
     }
     __syncthreads();
     ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
-    store_rows<TPB>(buf, pf, tw, fftmax, chirp, lmax, FN, FS);
+    store_rows<TPB>(buf, pf, tw, fftmax, chirp, lmax, RingSeq<float2, COLS>{FN, cs},
+                    RingSeq<float2, COLS>{FS, cs});
 }
 
 // (threads per workgroup, elements per thread) of a class: 8 elements (one radix-8
@@ -410,24 +439,34 @@ int launch_fft_inv_f32(const Plan &p, const float2 *phase, double *maps, int nb)
     return inv_classes<float2>(p, phase, maps, nb);
 }
 
-int launch_fft_inv_fwd_f32(const Plan &p, const double *rho, double lam, double *smap, int nb) {
+template <bool COLS>
+static int inv_fwd_classes(const Plan &p, const double *rho, double lam, double *smap, int nb) {
     for (int c = 1; c >= 0; c--) {
         const int cnt = p.fft_class_count[c];
         if (cnt == 0) continue;
         int ept;
         const int tpb = fft_class_shape(p, c, ept);
-        const dim3 grid(nb, cnt);
+        const dim3 grid = COLS ? dim3(8 * nb * ((cnt + 7) / 8)) : dim3(nb, cnt);
         const size_t lds = fft_class_lds(p, c);
         const int rs = p.nm32;
+        float2 *data = COLS ? reinterpret_cast<float2 *>(p.d_ph32) : p.d_phf;
         if (tpb == 256)
-            hipLaunchKernelGGL((k_fft_inv_fwd<256, 8>), grid, dim3(256), lds, p.stream, p.d_phf, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs));
+            hipLaunchKernelGGL((k_fft_inv_fwd<256, 8, COLS>), grid, dim3(256), lds, p.stream, data, p.C2, nb, cnt, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs));
         else if (tpb == 512)
-            hipLaunchKernelGGL((k_fft_inv_fwd<512, 8>), grid, dim3(512), lds, p.stream, p.d_phf, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs));
+            hipLaunchKernelGGL((k_fft_inv_fwd<512, 8, COLS>), grid, dim3(512), lds, p.stream, data, p.C2, nb, cnt, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs));
         else
-            hipLaunchKernelGGL((k_fft_inv_fwd<1024, 8>), grid, dim3(1024), lds, p.stream, p.d_phf, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs));
+            hipLaunchKernelGGL((k_fft_inv_fwd<1024, 8, COLS>), grid, dim3(1024), lds, p.stream, data, p.C2, nb, cnt, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs));
         MFWF_HIP(hipGetLastError());
     }
     return MFWF_OK;
+}
+
+int launch_fft_inv_fwd_f32(const Plan &p, const double *rho, double lam, double *smap, int nb) {
+    return inv_fwd_classes<false>(p, rho, lam, smap, nb);
+}
+
+int launch_fft_inv_fwd_cols(const Plan &p, const double *rho, double lam, double *smap, int nb) {
+    return inv_fwd_classes<true>(p, rho, lam, smap, nb);
 }
 
 int fft_max_length() { return 8 * 1024; }
@@ -443,8 +482,9 @@ static int fwd_lds(int bytes) {
     return MFWF_OK;
 }
 static int inv_fwd_lds(int bytes) {
-    const void *fns[] = {(const void *)k_fft_inv_fwd<256, 8>, (const void *)k_fft_inv_fwd<512, 8>,
-                         (const void *)k_fft_inv_fwd<1024, 8>};
+    const void *fns[] = {(const void *)k_fft_inv_fwd<256, 8, false>, (const void *)k_fft_inv_fwd<512, 8, false>,
+                         (const void *)k_fft_inv_fwd<1024, 8, false>, (const void *)k_fft_inv_fwd<256, 8, true>,
+                         (const void *)k_fft_inv_fwd<512, 8, true>, (const void *)k_fft_inv_fwd<1024, 8, true>};
     for (const void *f : fns)
         MFWF_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
     return MFWF_OK;
