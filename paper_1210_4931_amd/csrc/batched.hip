@@ -222,11 +222,12 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
         for (int u = 0; u < NX; u++) {  // ring-Fourier: 32 pairs x CT columns
             const int e = threadIdx.x + 256 * u, pp = e / (CT / 4), c4 = e % (CT / 4);
             const int p = 32 * pc + pp, col = CT * cg + 4 * c4;
-            // loads from clamped in-range addresses, then a value select
-            const bool on = p < npair && col < ncols, south = on && (nring - 1 - p != p);
+            // loads from clamped in-range addresses; values outside the problem are zeroed
+            // when they are stored to LDS, so that no wait for the loads comes before the
+            // matrix products of the current chunk
             const int pq = min(p, npair - 1), cq = min(col, ncols - 4);
-            rn[u] = keep4(on, ld4(ph32 + ((long)m * nring + pq) * C2 + cq));
-            rs[u] = keep4(south, ld4(ph32 + ((long)m * nring + (nring - 1 - pq)) * C2 + cq));
+            rn[u] = ld4(ph32 + ((long)m * nring + pq) * C2 + cq);
+            rs[u] = ld4(ph32 + ((long)m * nring + (nring - 1 - pq)) * C2 + cq);
         }
     };
     auto next_active = [&](int pc) __attribute__((always_inline)) {
@@ -245,7 +246,10 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
 #pragma unroll
         for (int u = 0; u < NX; u++) {
             const int e = threadIdx.x + 256 * u, pp = e / (CT / 4), c4 = e % (CT / 4);
-            const floatx4 ps = rn[u] + rs[u], ms = rn[u] - rs[u];
+            const int p = 32 * pc + pp, col = CT * cg + 4 * c4;
+            const bool on = p < npair && col < ncols, south = on && (nring - 1 - p != p);
+            const floatx4 xn = keep4(on, rn[u]), xs = keep4(south, rs[u]);
+            const floatx4 ps = xn + xs, ms = xn - xs;
             st4(&sx[0][pp][4 * c4], flip ? ms : ps);
             st4(&sx[1][pp][4 * c4], flip ? ps : ms);
         }
@@ -354,7 +358,8 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
         for (int u = 0; u < NV; u++) {  // coefficients: 64 values of l x CT columns
             const int e = threadIdx.x + 256 * u, rr = e / (CT / 4), c4 = e % (CT / 4);
             const int r = 64 * rc + rr, col = CT * cg + 4 * c4;
-            rv[u] = keep4(r < Lm && col < ncols, ld4(s32 + (base + min(r, Lm - 1)) * C2 + min(col, ncols - 4)));
+            // zeroed outside the problem at the LDS store (no wait before the products)
+            rv[u] = ld4(s32 + (base + min(r, Lm - 1)) * C2 + min(col, ncols - 4));
         }
     };
     const int first = max(0, ls_tile - m) / 64;  // first chunk with a nonzero lambda
@@ -373,7 +378,8 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
 #pragma unroll
         for (int u = 0; u < NV; u++) {
             const int e = threadIdx.x + 256 * u, rr = e / (CT / 4), c4 = e % (CT / 4);
-            st4(&ss[rr][4 * c4], rv[u]);
+            const int r = 64 * rc + rr, col = CT * cg + 4 * c4;
+            st4(&ss[rr][4 * c4], keep4(r < Lm && col < ncols, rv[u]));
         }
         __syncthreads();
         if (rc + 1 < nrc) load(rc + 1);
