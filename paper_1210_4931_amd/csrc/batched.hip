@@ -385,17 +385,24 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
         if (rc + 1 < nrc) load(rc + 1);
         if (wave_on && ls_wave <= m + 64 * rc + 63) {
             const int i = lane & 31, kq = lane >> 5;
+            // step s = (kk, parity): operands of step s + 1 are read from LDS before the
+            // products of step s are issued
+            float a[2], bv[2][NCT];
+            auto rd = [&](int st, int q) __attribute__((always_inline)) {
+                const int rr = 4 * (st >> 1) + 2 * kq + (st & 1);  // two same-parity l per step
+                a[q] = sl[32 * rt + i][rr];
 #pragma unroll
-            for (int par = 0; par < 2; par++) {
-#pragma unroll 4
-                for (int kk = 0; kk < 16; kk++) {
-                    const int rr = 4 * kk + 2 * kq + par;  // two same-parity l per step
-                    const float a = sl[32 * rt + i][rr];
+                for (int ct = 0; ct < NCT; ct++) bv[q][ct] = ss[rr][wcol + 32 * ct + i];
+            };
+            rd(0, 0);
 #pragma unroll
-                    for (int ct = 0; ct < NCT; ct++)
-                        acc[par][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-                            a, ss[rr][wcol + 32 * ct + i], acc[par][ct], 0, 0, 0);
-                }
+            for (int st = 0; st < 32; st++) {
+                const int q = st & 1;
+                if (st + 1 < 32) rd(st + 1, q ^ 1);
+                __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the products
+#pragma unroll
+                for (int ct = 0; ct < NCT; ct++)
+                    acc[st & 1][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[q], bv[q][ct], acc[st & 1][ct], 0, 0, 0);
             }
         }
     }
