@@ -32,19 +32,28 @@ PEAK_FP64_VALU = 256 * 4 * 16 * 2 * 2.4e9     # 78.6 TFLOP/s: CUs x SIMDs x lane
 PEAK_FP32_MFMA = 157.3e12                      # dense FP32 matrix-core peak
 KERNELS = ["pixel_update", "fft_fwd", "leg_analysis", "harmonic", "leg_synth", "fft_inv"]
 
-# HBM bytes per launch of the analysis GEMM (batched FP32 form, nside 512, lmax 1024, 64 maps)
-# from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the factors a 256 MiB copy gives
-# (x2.0 and x1.0): profiles/gemm_analysis_nside512_lmax1024_b64_hbm_traffic.md.  Valid only
-# for the kernel source they were taken on, identified by the SHA-256 of batched.hip.
-GEMM_TRAFFIC = {"bytes": 4.868e9,
-                "source_sha256": "909868d0686837855fe18055f684f52a378bc40188db3a598c9e1ee42d05aecc"}
+PEAK_HBM = 8.0e12                              # HBM3E bytes/s
+
+# HBM bytes per iteration of two kernels of the batched FP32 form (nside 512, lmax 1024, 64
+# maps) from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the factors a 256 MiB copy gives:
+# profiles/ring_step_and_gemms_nside512_lmax1024_b64_hbm_traffic.md.  Valid only for the
+# kernel source they were taken on, identified by the SHA-256 of the source file.
+TRAFFIC = {
+    "ring_step": {"bytes": 4.1561e9, "source": "ringfft.hip",
+                  "sha256": "04287f090eed5a0201c17d3cbb6768a99d95d8fd629c1b548ecacf2aef77d5bf"},
+    "gemm_analysis": {"bytes": 4.8880e9, "source": "batched.hip",
+                      "sha256": "8891e3b5e1e4552c632f0aaa57c374432d79c5811d23c205dc8e3a378ec16e21"},
+}
 
 
-def measured_traffic():
+def measured_traffic(kernel):
     import hashlib
-    src = os.path.join(ROOT, "paper_1210_4931_amd", "csrc", "batched.hip")
+    t = TRAFFIC[kernel]
+    if t["bytes"] is None:
+        return None
+    src = os.path.join(ROOT, "paper_1210_4931_amd", "csrc", t["source"])
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    return GEMM_TRAFFIC["bytes"] if h == GEMM_TRAFFIC["source_sha256"] else None
+    return t["bytes"] if h == t["sha256"] else None
 
 
 def cpu_baseline(nside, lmax, K, wl, d_host, M):
@@ -259,6 +268,13 @@ def main():
     dom32 = max(("leg_analysis", "leg_synth"), key=lambda k: kt32[k])
     pair32 = kt32["fft_fwd"] + kt32["leg_analysis"] + kt32["leg_synth"] + kt32["fft_inv"]
     achieved = gemm_flops / (kt32[dom32] * 1e-3)
+    # the ring step of a chained iteration (kt32["fft_fwd"]: both transform-length classes of
+    # the fused inverse transform / pixel update / forward transform kernel) moves at least
+    # the synthesis columns in, the analysis columns out (8 B per ring and m a map), rho
+    # (8 B a pixel a map) and M (8 B a pixel, shared)
+    nring = 4 * nside - 1
+    ring_bytes = 8.0 * B * (2 * nring * (lmax + 1) + wl.npix) + 8.0 * wl.npix
+    ring_bw = ring_bytes / (kt32["fft_fwd"] * 1e-3)
 
     out = {
         "metric": METRIC,
@@ -289,10 +305,17 @@ def main():
                           "transforms in one kernel, with the layout transposes to and from "
                           "the matrix-core column layout"},
         "legendre_triples": {"evaluated": work, "full_triangle": full},
-        "roofline": {"bound": "mfma", "kernel": "gemm_" + dom32.split("_")[1],
-                     "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
-                     "traffic": measured_traffic() if dom32 == "leg_analysis" else None},
+        # the dominant kernel: the ring step (inverse transforms, pixel update, forward
+        # transforms), per iteration
+        "roofline": {"bound": "hbm", "kernel": "ring_step (k_fft_inv_fwd, both length classes)",
+                     "achieved": ring_bw / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                     "frac": ring_bw / PEAK_HBM, "algorithmic_bytes": ring_bytes,
+                     "ms": kt32["fft_fwd"], "traffic": measured_traffic("ring_step")},
+        "roofline_gemm": {"bound": "mfma", "kernel": "gemm_" + dom32.split("_")[1],
+                          "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+                          "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
+                          "ms": kt32[dom32],
+                          "traffic": measured_traffic("gemm_analysis") if dom32 == "leg_analysis" else None},
         "fp64_single": fp64,
     }
     if not args.no_cooled:
