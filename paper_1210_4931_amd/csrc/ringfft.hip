@@ -156,6 +156,51 @@ __device__ __forceinline__ void fold_bins(double2 *buf, RingSeq<const InT, STRID
     const int nbins_pass = TPB / T;
     const double sgn_step = pf.half_shift ? -1.0 : 1.0;
     const double sg_stride = (T & 1) ? sgn_step : 1.0;
+    if (n > lmax) {
+        // n > lmax: a bin k has at most two aliases, m = k (k <= lmax) and m = -(n - k)
+        // (n - k <= lmax), so the sum is made from the coefficients themselves, each read
+        // once (in the matrix-core columns a coefficient costs a cache line of its own):
+        // thread i reads m = i + u TPB, stores the positive term of bin m (zero for bins
+        // above lmax), then after a barrier adds the negative term to bin n - m.  The bin's
+        // phase and the packing x = conj(ph (B_N + i B_S)) are linear, so each term is packed
+        // on its own.
+        constexpr int MU = EPT;  // coefficients per thread per ring (lmax < n <= EPT TPB)
+        InT fN[MU], fS[MU];
+#pragma unroll
+        for (int u = 0; u < MU; u++) {
+            if (u * TPB > lmax) break;  // uniform
+            const int m = min((int)threadIdx.x + u * TPB, lmax);
+            fN[u] = FN[m];
+            fS[u] = FS[m];
+        }
+        auto term = [&](int k, double2 gN, double2 gS) {
+            if (equator) gS = make_double2(0.0, 0.0);
+            if (pf.half_shift) {
+                const double2 ph = half_bin_phase(k, n, tw, fftmax);
+                gN = cmul(gN, ph);
+                gS = cmul(gS, ph);
+            }
+            return cconj(make_double2(gN.x - gS.y, gN.y + gS.x));
+        };
+#pragma unroll
+        for (int u = 0; u < EPT; u++) {
+            const int k = threadIdx.x + u * TPB;
+            if (k < n)
+                buf[lds_ix(k)] = (k <= lmax) ? term(k, get_c(&fN[u]), get_c(&fS[u])) : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < MU; u++) {
+            const int m = threadIdx.x + u * TPB;
+            if (m >= 1 && m <= lmax) {  // negative alias of bin n - m: sgn conj F(m)
+                const int k = n - m;
+                const double2 x = term(k, cscale(cconj(get_c(&fN[u])), sgn_step),
+                                       cscale(cconj(get_c(&fS[u])), sgn_step));
+                buf[lds_ix(k)] = cadd(buf[lds_ix(k)], x);
+            }
+        }
+        return;
+    }
     if (T == 1) {
         // n > TPB / 2: thread i folds bins k = i + u TPB (n <= EPT * TPB).  The first
         // positive alias (m = k) and the first negative one (m = k - n, read as conj F(n - k))
