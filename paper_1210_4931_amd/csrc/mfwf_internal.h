@@ -170,10 +170,8 @@ int launch_fft_inv(const Plan &p, const double2 *phase, double *maps, int nb);
 int launch_fft_fwd_f32(const Plan &p, const double *maps, const double *rho, double lam,
                        float2 *phase, int nb);
 int launch_fft_inv_f32(const Plan &p, const float2 *phase, double *maps, int nb);
-// FP32 rows d_phf of a synthesis -> maps s (to smap if not null) -> t of Eq. (3) -> rows of
+// synthesis columns d_ph32 -> maps s (to smap if not null) -> t of Eq. (3) -> the columns of
 // its forward transform, in place (one iteration's ring steps without the map in memory)
-int launch_fft_inv_fwd_f32(const Plan &p, const double *rho, double lam, double *smap, int nb);
-// the same on the matrix-core columns d_ph32 in place (no layout transposes)
 int launch_fft_inv_fwd_cols(const Plan &p, const double *rho, double lam, double *smap, int nb);
 int fft_class_shape(const Plan &p, int c, int &ept);  // threads per workgroup of class c
 size_t fft_class_lds(const Plan &p, int c);           // dynamic LDS bytes of class c

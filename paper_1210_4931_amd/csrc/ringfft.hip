@@ -320,17 +320,15 @@ k_fft_inv(const InT *__restrict__ phase, double *__restrict__ maps,
     }
 }
 
-// One iteration's ring steps in one pass over a pair (batched FP32 form): the rows F of the
-// synthesis are folded and transformed back to the pair's pixels s (optionally stored to
-// smap), the messenger field t of Eq. (3) is formed from s, rho and M on the spot, and its
-// transform overwrites the rows with G = the analysis input.  The map s never travels
-// through memory; the arithmetic is that of k_fft_inv followed by k_fft_fwd<PIX>.
-// COLS = false: FP32 rows [map][ring][nm], grid (maps, pairs).  COLS = true: the matrix-core
-// columns [m][ring][C2] themselves (map b at column 2b), read and written in place; a 1-D
-// grid whose workgroup L runs on XCD L mod 8 is laid out so that every XCD takes whole
-// pairs, all maps of a pair in a row, so that the maps sharing a 128-byte column segment
-// meet in one L2.
-template <int TPB, int EPT, bool COLS>
+// One iteration's ring steps in one pass over a pair (batched FP32 form), on the
+// matrix-core columns [m][ring][C2] (map b at column 2b) in place: the synthesis F is folded
+// and transformed back to the pair's pixels s (optionally stored to smap), the messenger
+// field t of Eq. (3) is formed from s, rho and M on the spot, and its transform overwrites
+// the columns with G = the analysis input.  The map s never travels through memory; the
+// arithmetic is that of k_fft_inv followed by k_fft_fwd<PIX>.  The 1-D grid (workgroup L
+// runs on XCD L mod 8) is laid out so that every XCD takes whole pairs, all maps of a pair
+// in a row, so that the 16 maps sharing a 128-byte column segment meet in one L2.
+template <int TPB, int EPT>
 __global__ void __launch_bounds__(TPB)
 k_fft_inv_fwd(float2 *__restrict__ data, int C2, int nmap, int npl, double *__restrict__ smap,
               const double *__restrict__ rho, const double *__restrict__ M, double lam,
@@ -340,27 +338,20 @@ k_fft_inv_fwd(float2 *__restrict__ data, int C2, int nmap, int npl, double *__re
               int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
               long npix, int nring, int nm, int lmax, int fftlen_class) {
     extern __shared__ double2 buf[];
-    int b, pi;
-    if constexpr (COLS) {
-        const int L = blockIdx.x, x = L & 7, sl = L >> 3, j = sl / nmap;
-        b = sl - j * nmap;
-        pi = 8 * j + x;
-        if (pi >= npl) return;  // whole workgroup, before any barrier
-    } else {
-        b = blockIdx.x;
-        pi = blockIdx.y;
-    }
+    const int L = blockIdx.x, x = L & 7, sl = L >> 3, j = sl / nmap;
+    const int b = sl - j * nmap, pi = 8 * j + x;
+    if (pi >= npl) return;  // whole workgroup, before any barrier
     const int p = plist[pi];
     const PairFFT pf = pfft[p];
     const int n = pf.nphi;
     const bool equator = (pf.startS == pf.startN);
     const Twiddles tw = load_twiddles(buf, fft_area(fftlen_class, TPB), twlo, twhi, ntwhi);
     const int pS = nring - 1 - p;
-    const long cs = COLS ? (long)nring * (C2 / 2) : 1;  // float2 elements from m to m + 1
-    float2 *FN = COLS ? data + (long)p * (C2 / 2) + b : data + ((long)b * nring + p) * nm;
-    float2 *FS = COLS ? data + (long)pS * (C2 / 2) + b : data + ((long)b * nring + pS) * nm;
-    fold_bins<TPB, EPT>(buf, RingSeq<const float2, COLS>{FN, cs},
-                        RingSeq<const float2, COLS>{FS, cs}, pf, tw, fftmax, lmax);
+    const long cs = (long)nring * (C2 / 2);  // float2 elements from m to m + 1
+    float2 *FN = data + (long)p * (C2 / 2) + b;
+    float2 *FS = data + (long)pS * (C2 / 2) + b;
+    fold_bins<TPB, EPT>(buf, RingSeq<const float2, true>{FN, cs},
+                        RingSeq<const float2, true>{FS, cs}, pf, tw, fftmax, lmax);
     __syncthreads();
     ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
     if (tau_b) tau = tau_b[b];
@@ -399,8 +390,8 @@ k_fft_inv_fwd(float2 *__restrict__ data, int C2, int nmap, int npl, double *__re
     }
     __syncthreads();
     ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
-    store_rows<TPB>(buf, pf, tw, fftmax, chirp, lmax, RingSeq<float2, COLS>{FN, cs},
-                    RingSeq<float2, COLS>{FS, cs});
+    store_rows<TPB>(buf, pf, tw, fftmax, chirp, lmax, RingSeq<float2, true>{FN, cs},
+                    RingSeq<float2, true>{FS, cs});
 }
 
 // (threads per workgroup, elements per thread) of a class: 8 elements (one radix-8
@@ -484,35 +475,28 @@ int launch_fft_inv_f32(const Plan &p, const float2 *phase, double *maps, int nb)
     return inv_classes<float2>(p, phase, maps, nb);
 }
 
-template <bool COLS>
-static int inv_fwd_classes(const Plan &p, const double *rho, double lam, double *smap, int nb) {
+int launch_fft_inv_fwd_cols(const Plan &p, const double *rho, double lam, double *smap, int nb) {
     for (int c = 1; c >= 0; c--) {
         const int cnt = p.fft_class_count[c];
         if (cnt == 0) continue;
         int ept;
         const int tpb = fft_class_shape(p, c, ept);
-        const dim3 grid = COLS ? dim3(8 * nb * ((cnt + 7) / 8)) : dim3(nb, cnt);
+        const dim3 grid(8 * nb * ((cnt + 7) / 8));  // whole pairs per XCD
         const size_t lds = fft_class_lds(p, c);
-        const int rs = p.nm32;
-        float2 *data = COLS ? reinterpret_cast<float2 *>(p.d_ph32) : p.d_phf;
+        const int rs = p.nm32;  // unused by the kernel (no rows)
+        float2 *data = reinterpret_cast<float2 *>(p.d_ph32);
         if (tpb == 256)
-            hipLaunchKernelGGL((k_fft_inv_fwd<256, 8, COLS>), grid, dim3(256), lds, p.stream, data, p.C2, nb, cnt, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs));
+            hipLaunchKernelGGL((k_fft_inv_fwd<256, 8>), grid, dim3(256), lds, p.stream, data, p.C2, nb, cnt, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs));
         else if (tpb == 512)
-            hipLaunchKernelGGL((k_fft_inv_fwd<512, 8, COLS>), grid, dim3(512), lds, p.stream, data, p.C2, nb, cnt, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs));
+            hipLaunchKernelGGL((k_fft_inv_fwd<512, 8>), grid, dim3(512), lds, p.stream, data, p.C2, nb, cnt, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs));
         else
-            hipLaunchKernelGGL((k_fft_inv_fwd<1024, 8, COLS>), grid, dim3(1024), lds, p.stream, data, p.C2, nb, cnt, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs));
+            hipLaunchKernelGGL((k_fft_inv_fwd<1024, 8>), grid, dim3(1024), lds, p.stream, data, p.C2, nb, cnt, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs));
         MFWF_HIP(hipGetLastError());
     }
     return MFWF_OK;
 }
 
-int launch_fft_inv_fwd_f32(const Plan &p, const double *rho, double lam, double *smap, int nb) {
-    return inv_fwd_classes<false>(p, rho, lam, smap, nb);
-}
 
-int launch_fft_inv_fwd_cols(const Plan &p, const double *rho, double lam, double *smap, int nb) {
-    return inv_fwd_classes<true>(p, rho, lam, smap, nb);
-}
 
 int fft_max_length() { return 8 * 1024; }
 
@@ -527,9 +511,8 @@ static int fwd_lds(int bytes) {
     return MFWF_OK;
 }
 static int inv_fwd_lds(int bytes) {
-    const void *fns[] = {(const void *)k_fft_inv_fwd<256, 8, false>, (const void *)k_fft_inv_fwd<512, 8, false>,
-                         (const void *)k_fft_inv_fwd<1024, 8, false>, (const void *)k_fft_inv_fwd<256, 8, true>,
-                         (const void *)k_fft_inv_fwd<512, 8, true>, (const void *)k_fft_inv_fwd<1024, 8, true>};
+    const void *fns[] = {(const void *)k_fft_inv_fwd<256, 8>, (const void *)k_fft_inv_fwd<512, 8>,
+                         (const void *)k_fft_inv_fwd<1024, 8>};
     for (const void *f : fns)
         MFWF_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
     return MFWF_OK;
