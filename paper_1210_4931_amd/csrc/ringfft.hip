@@ -60,6 +60,18 @@ __device__ __forceinline__ void store_rows(const double2 *buf, const PairFFT &pf
                                            RingSeq<OutT, STRIDED> outN, RingSeq<OutT, STRIDED> outS) {
     const int n = pf.nphi;
     const bool equator = (pf.startS == pf.startN);
+    // e^{-i m phi0} = e^{-i pi m / n} with a half shift: from the twiddle table when it holds
+    // the 2n-th roots, else from the thread's first m by steps of e^{-i pi TPB / n} (a few
+    // steps, a few ulp)
+    const bool tab = fftmax % (2 * n) == 0;
+    double2 phm = make_double2(1.0, 0.0), phstep = make_double2(1.0, 0.0);
+    if (pf.half_shift && !tab) {
+        double sn, cs;
+        sincospi((double)threadIdx.x / (double)n, &sn, &cs);
+        phm = make_double2(cs, -sn);
+        sincospi((double)TPB / (double)n, &sn, &cs);
+        phstep = make_double2(cs, -sn);
+    }
     for (int m = threadIdx.x; m <= lmax; m += TPB) {
         const int q = (n > lmax) ? 0 : m / n, k = m - q * n;  // no alias when n > lmax
         const int kr = (k == 0) ? 0 : n - k;
@@ -67,7 +79,14 @@ __device__ __forceinline__ void store_rows(const double2 *buf, const PairFFT &pf
         const double2 Y = cconj(dft_bin(buf, pf, chirp, kr));
         // e^{-i m phi0} = (-1)^q e^{-i pi k / n} with a half shift, 1 otherwise
         double2 ph = make_double2(1.0, 0.0);
-        if (pf.half_shift) ph = cscale(cconj(half_bin_phase(k, n, tw, fftmax)), (q & 1) ? -1.0 : 1.0);
+        if (pf.half_shift) {
+            if (tab) {
+                ph = cscale(cconj(half_bin_phase(k, n, tw, fftmax)), (q & 1) ? -1.0 : 1.0);
+            } else {
+                ph = phm;
+                phm = cmul(phm, phstep);
+            }
+        }
         // X_N = (X_k + conj X_{-k}) / 2,  X_S = (X_k - conj X_{-k}) / (2i)
         const double2 gN = make_double2(0.5 * (X.x + Y.x), 0.5 * (X.y + Y.y));
         put_c(&outN[m], cmul(gN, ph));
@@ -173,20 +192,42 @@ __device__ __forceinline__ void fold_bins(double2 *buf, RingSeq<const InT, STRID
             fN[u] = FN[m];
             fS[u] = FS[m];
         }
-        auto term = [&](int k, double2 gN, double2 gS) {
+        auto term = [&](double2 gN, double2 gS, double2 ph) {
             if (equator) gS = make_double2(0.0, 0.0);
             if (pf.half_shift) {
-                const double2 ph = half_bin_phase(k, n, tw, fftmax);
                 gN = cmul(gN, ph);
                 gS = cmul(gS, ph);
             }
             return cconj(make_double2(gN.x - gS.y, gN.y + gS.x));
         };
+        // bin phases e^{i pi m / n} of the thread's m (table, or steps of e^{i pi TPB / n}
+        // from its first m); bin n - m has e^{i pi (n - m) / n} = -conj(e^{i pi m / n})
+        const bool tab = fftmax % (2 * n) == 0;
+        double2 ph[MU], phm = make_double2(1.0, 0.0), phstep = make_double2(1.0, 0.0);
+        if (pf.half_shift && !tab) {
+            double sn, cs;
+            sincospi((double)threadIdx.x / (double)n, &sn, &cs);
+            phm = make_double2(cs, sn);
+            sincospi((double)TPB / (double)n, &sn, &cs);
+            phstep = make_double2(cs, sn);
+        }
+#pragma unroll
+        for (int u = 0; u < MU; u++) {
+            ph[u] = make_double2(1.0, 0.0);
+            if (pf.half_shift) {
+                if (tab) {
+                    ph[u] = half_bin_phase(min((int)threadIdx.x + u * TPB, n - 1), n, tw, fftmax);
+                } else {
+                    ph[u] = phm;
+                    phm = cmul(phm, phstep);
+                }
+            }
+        }
 #pragma unroll
         for (int u = 0; u < EPT; u++) {
             const int k = threadIdx.x + u * TPB;
             if (k < n)
-                buf[lds_ix(k)] = (k <= lmax) ? term(k, get_c(&fN[u]), get_c(&fS[u])) : make_double2(0.0, 0.0);
+                buf[lds_ix(k)] = (k <= lmax) ? term(get_c(&fN[u]), get_c(&fS[u]), ph[u]) : make_double2(0.0, 0.0);
         }
         __syncthreads();
 #pragma unroll
@@ -194,8 +235,9 @@ __device__ __forceinline__ void fold_bins(double2 *buf, RingSeq<const InT, STRID
             const int m = threadIdx.x + u * TPB;
             if (m >= 1 && m <= lmax) {  // negative alias of bin n - m: sgn conj F(m)
                 const int k = n - m;
-                const double2 x = term(k, cscale(cconj(get_c(&fN[u])), sgn_step),
-                                       cscale(cconj(get_c(&fS[u])), sgn_step));
+                const double2 x = term(cscale(cconj(get_c(&fN[u])), sgn_step),
+                                       cscale(cconj(get_c(&fS[u])), sgn_step),
+                                       make_double2(-ph[u].x, ph[u].y));
                 buf[lds_ix(k)] = cadd(buf[lds_ix(k)], x);
             }
         }
