@@ -139,3 +139,26 @@ def test_f32_benchmark_size_300_iterations(mf):
     errs = [(rel_alm(sa[b], ra[b], lmax), rel(sm[b], rm[b])) for b in range(B)]
     print("FP32 form vs FP64 after 300 iterations at nside 512 (alm, map):", errs)
     assert max(max(e) for e in errs) < TOL, errs
+
+
+def test_f32_chained_iterations_chunks_checks_and_stages(mf):
+    """The batched solve chains its iterations through the synthesis columns: splitting the
+    maps into chunks of max_batch, diagnostics checks in the middle of a stage (which
+    materialise the map without touching the chain) and a change of lambda between stages
+    leave every result bitwise equal to the plain runs, and the result equals the oracle's
+    iterate with the same schedule."""
+    nside, lmax = 16, 40
+    plan, wl, d, M = _setup(mf, nside, lmax, max_batch=4)
+    rng = np.random.default_rng(12)
+    ds = np.stack([d + rng.standard_normal(d.size) for _ in range(9)])  # chunks 4, 4, 1
+    lam, its = [30.0, 1.0], [7, 23]
+    a_all, m_all, _ = plan.solve(dev(ds), lam=lam, iters=its)
+    for b in (0, 5, 8):
+        a1, m1, _ = plan.solve(dev(ds[b:b + 1]), lam=lam, iters=its)
+        assert torch.equal(a_all[b], a1[0]) and torch.equal(m_all[b], m1[0])
+    a_chk, m_chk, _, hist = plan.solve(dev(ds), lam=lam, iters=its, n_check=5)
+    assert torch.equal(a_all, a_chk) and torch.equal(m_all, m_chk)
+    assert hist.shape[0] == 6  # checks at 5, 10, ..., 30
+    ref_alm, ref_map = oracle.solve(nside, lmax, wl.cl, M, M * ds[5], lam=np.repeat(lam, its))
+    assert rel_alm(a_all.cpu().numpy()[5], ref_alm, lmax) < TOL
+    assert rel(m_all.cpu().numpy()[5], ref_map) < TOL
