@@ -162,3 +162,23 @@ def test_f32_chained_iterations_chunks_checks_and_stages(mf):
     ref_alm, ref_map = oracle.solve(nside, lmax, wl.cl, M, M * ds[5], lam=np.repeat(lam, its))
     assert rel_alm(a_all.cpu().numpy()[5], ref_alm, lmax) < TOL
     assert rel(m_all.cpu().numpy()[5], ref_map) < TOL
+
+
+def test_time_kernels_stages_and_state(mf):
+    """mfwf_time_kernels: one duration per stage (in the batched temperature form the
+    inverse transforms run inside the chained ring step, [1], so [5] reads 0), and a solve
+    after it gives the result it gave before (the timing runs leave no state behind)."""
+    nside, lmax = 16, 40
+    plan, wl, d, M = _setup(mf, nside, lmax, max_batch=4)
+    ds = dev(np.stack([d, 2.0 * d]))
+    a1, m1, _ = plan.solve(ds, iters=12)
+    ms = plan.time_kernels(2, 3)
+    assert len(ms) == 6 and all(np.isfinite(ms)) and min(ms) >= 0.0
+    assert ms[1] > 0.0 and ms[2] > 0.0 and ms[4] > 0.0 and ms[5] == 0.0
+    a2, m2, _ = plan.solve(ds, iters=12)
+    assert torch.equal(a1, a2) and torch.equal(m1, m2)
+    p64 = mf.Plan(nside, lmax)
+    p64.set_covariances(wl.cl, dev(1.0 / wl.noise_var), dev(wl.mask, torch.uint8))
+    b1 = p64.solve(ds[:1], iters=12)[0]
+    assert all(v > 0.0 for v in p64.time_kernels(1, 3))
+    assert torch.equal(p64.solve(ds[:1], iters=12)[0], b1)
