@@ -162,7 +162,8 @@ typedef struct {
                               stage, per iteration, is below dchi2_tol sigma_chi2 for
                               every map of a chunk (maps are solved in chunks of at most
                               max_batch; sigma_chi2 = sqrt(2 n_dof), Sect. 2.2);
-                              iters_done reports where each map stopped                  */
+                              iters_done reports where each map stopped; the host then
+                              waits for the stream at every check                        */
     int source_is_rho;     /* 0: input is the data d (rho = M d); 1: input is rho        */
     int use_graph;         /* 1: replay each iteration as a captured hipGraph            */
     double *history;       /* host [history_rows][nmaps][5] or NULL: at every check,
