@@ -223,7 +223,9 @@ int mfwf_solve(mfwf_plan plan, const double *input, int nmaps, double *s_alm_out
  * copied from it), and the iterate passes between stages as its pixel map.
  * A plateau: |chi^2_k - chi^2_{k - n_check}| / n_check < tol sigma_chi2 for every map of
  * the batch, checked every n_check iterations.  The input is data d (rho = M d).
- * Temperature plans (spin 0), MFWF_F64 or MFWF_F32.
+ * Spin 0 or spin 2, MFWF_F64 or MFWF_F32.  For spin 2 (the T+P analysis of Sect. 3) lambda
+ * follows the temperature spectrum, C^TT_{l_iter}, the stages truncate the (T, E, B)
+ * spectra at lmax_SHT and chi^2 is the T, Q, U form of Eq. (6) with 3 n_observed dof.
  */
 typedef struct {
     int l_iter0;         /* first l_iter (0: 20)                                          */

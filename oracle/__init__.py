@@ -319,6 +319,46 @@ def solve_pol(nside, lmax, cl4, M6, rho, niter=None, lam=None, direct=False, dia
     return (s_alm, s_map, dg) if diag else (s_alm, s_map)
 
 
+def solve_pol_staged(nside, lmax, cl4, M6, rho, stages):
+    """The T, Q, U messenger iteration in stages with truncated transforms (the cooling
+    schedule of Sect. 3 with the T+P blocks): stage (lmax_k, lambda_k, n_k) runs n_k
+    iterations of Eq. (3) with the 3x3 noise blocks and Eq. (4) with the 3x3 (T, E, B) signal
+    blocks S_l = [[TT, TE, 0], [TE, EE, 0], [0, 0, BB]], s = S_l (S_l + lambda tau Omega)^-1 a,
+    transforms up to lmax_k; the iterate passes between stages as its pixel maps.
+    tau = 1 / max_p lambda_max(M_p).  Returns (s_alm [3][nalm(lmax)] with zeros above the last
+    stage's lmax_k, s_map [3][npix])."""
+    cl4, M6, rho = _f64(cl4), _f64(M6), _f64(rho)
+    npix = 12 * nside * nside
+    assert cl4.shape == (4, lmax + 1) and M6.shape == (npix, 6) and rho.shape == (3, npix)
+    tau = tau_pol(M6)
+    omega = 4.0 * np.pi / npix
+    Mb = M6[:, [0, 1, 2, 1, 3, 4, 2, 4, 5]].reshape(npix, 3, 3)  # packed TT TQ TU QQ QU UU
+    eye = np.eye(3)
+    s_map = np.zeros((3, npix))
+    s_alm, lk = np.zeros((3, 0), dtype=np.complex128), 0
+    for lk, lam, n in stages:
+        lk, n = int(lk), int(n)
+        TT, EE, BB, TE = (cl4[c, :lk + 1] for c in range(4))
+        S = np.zeros((lk + 1, 3, 3))
+        S[:, 0, 0], S[:, 0, 1], S[:, 1, 0], S[:, 1, 1], S[:, 2, 2] = TT, TE, TE, EE, BB
+        F = S @ np.linalg.inv(S + lam * tau * omega * eye)  # S (S + mu)^-1 per l
+        Fi = F[_l_of_index(lk)]                               # per coefficient
+        A = eye + (lam - 1.0) * tau * Mb                      # [npix][3][3]
+        for _ in range(n):
+            b = lam * tau * rho.T + s_map.T - tau * np.einsum("pij,pj->pi", Mb, s_map.T)
+            t = np.linalg.solve(A, b[..., None])[..., 0].T
+            a = map2alm_pol(nside, lk, t)
+            s_alm = np.einsum("kij,jk->ik", Fi, a)
+            s_map = alm2map_pol(nside, lk, s_alm)
+    out = np.zeros((3, nalm(lmax)), dtype=np.complex128)
+    if s_alm.shape[1]:
+        ls_full = _l_of_index(lmax)
+        ms_full = np.concatenate([np.full(lmax + 1 - m, m) for m in range(lmax + 1)])
+        keep = (ls_full <= lk) & (ms_full <= lk)
+        out[:, keep] = s_alm
+    return out, s_map
+
+
 def fluct_rho_pol(nside, lmax, cl4, M6, g1, h, direct=False):
     """rho = L_p g1 + Omega Y_pol(K_l h) with M_p = L_p L_p^T and K_l K_l^T = S_l^{-1}."""
     cl4, M6, g1, h = _f64(cl4), _f64(M6), _f64(g1), _c128(h)

@@ -1680,7 +1680,6 @@ int mfwf_solve_cooled(mfwf_plan plan, const double *data, int nmaps, double *s_a
     Plan &p = plan->p;
     if (!p.have_cov) return fail(MFWF_ENOCOV, "covariances not set");
     if (nmaps > 0 && !data) return fail(MFWF_EINVAL, "data is NULL");
-    if (p.spin != 0) return fail(MFWF_EINVAL, "the cooled solve is for temperature plans");
     mfwf_cool_opts u{};
     if (opts) u = *opts;
     if (u.l_iter0 < 0 || u.l_step_max < 0 || u.n_check < 0 || u.max_iters < 0 ||

@@ -4,7 +4,7 @@ The schedule depends on the data through the chi^2 plateaus, so parity replays i
 run reports its stages (l_iter, lambda, lmax_SHT, iterations) and the oracle runs the same
 stages with transforms truncated at each stage's lmax_SHT (oracle.solve_staged).  The rules
 of the schedule are checked on the stages themselves, and the converged result against the
-dense fixed point of the iteration.
+dense fixed point of the iteration.  T, Q, U plans replay against oracle.solve_pol_staged.
 """
 import numpy as np
 import pytest
@@ -12,6 +12,7 @@ import torch
 
 import oracle
 from oracle import dense
+from paper_1210_4931_amd import workloads as W
 from tests.gpu_util import dev, rel, rel_alm, temperature_problem
 
 pytestmark = pytest.mark.gpu
@@ -124,9 +125,62 @@ def test_cooled_errors(mf):
     plan4.set_covariances(wl4.cl, dev(1.0 / wl4.noise_var), dev(wl4.mask, torch.uint8))
     with pytest.raises(MFWFError, match="status -6"):
         plan4.solve_cooled(dev(d4[None]), max_iters=20000)
-    with pytest.raises(MFWFError):
+    with pytest.raises(MFWFError, match="status -4"):
         mf.Plan(4, 8, spin=2).solve_cooled(torch.zeros((1, 3, 192), dtype=torch.float64,
                                                        device="cuda"))
+
+
+def _pol_problem(mf, nside, lmax, seed, dtype, max_batch):
+    w = W.config3(seed, nside, lmax, ndisc=10, band_z=0.15, nu=10)
+    d = w.data_from_signal_maps(oracle.alm2map_pol(nside, lmax, w.signal_alm))
+    plan = mf.Plan(nside, lmax, max_batch=max_batch, spin=2, dtype=dtype)
+    plan.set_covariances(w.cl4, dev(w.ninv6), dev(w.mask, torch.uint8))
+    M6 = w.M6()
+    Mb = M6[:, [0, 1, 2, 1, 3, 4, 2, 4, 5]].reshape(-1, 3, 3)
+    return plan, w, d, M6, lambda x: np.einsum("pij,jp->ip", Mb, x)
+
+
+def _rel_teb(a, ref, lmax):
+    _, ms = W.alm_l_m(lmax)
+    w = np.sqrt(np.where(ms == 0, 1.0, 2.0))
+    return rel(a * w, ref * w)
+
+
+def test_cooled_pol_schedule_rules_and_oracle_replay(mf):
+    """T, Q, U (spin 2), FP64: lambda from C^TT at l_iter, truncated (T, E, B) stages; the
+    replay by the staged T, Q, U oracle."""
+    nside, lmax, l0, margin = 16, 32, 4, 8
+    plan, w, d, M6, rho_of = _pol_problem(mf, nside, lmax, 0, "f64", 1)
+    s_alm, s_map, info, stages, conv = plan.solve_cooled(dev(d[None]), l_iter0=l0,
+                                                          l_margin=margin, max_iters=3000)
+    print("stages (l_iter, lambda, lmax_SHT, iterations, chi2/ndof):\n", stages, conv)
+    assert len(stages) >= 3 and any(int(s[2]) < lmax for s in stages)
+    # converged, with chi^2 near its expectation n_dof (a diverging run would also replay)
+    assert conv and 0.8 < info[0].chi2 / info[0].n_dof < 1.2
+    assert info[0].n_dof == 3 * int(w.mask.sum())
+    _check_rules(stages, w.cl4[0], info[0].tau, 4 * np.pi / w.npix, lmax, l0, margin, 500,
+                 info[0].iters_done)
+    ref_alm, ref_map = oracle.solve_pol_staged(nside, lmax, w.cl4, M6, rho_of(d),
+                                               [(int(s[2]), s[1], int(s[3])) for s in stages])
+    assert _rel_teb(s_alm.cpu().numpy()[0], ref_alm, lmax) < 1e-10
+    assert rel(s_map.cpu().numpy()[0], ref_map) < 1e-10
+
+
+def test_cooled_pol_f32_batch_replay(mf):
+    """The batched FP32 T, Q, U form, two maps sharing one schedule, each against the replay."""
+    nside, lmax, l0, margin = 16, 32, 4, 8
+    plan, w, d, M6, rho_of = _pol_problem(mf, nside, lmax, 1, "f32", 2)
+    rng = np.random.default_rng(8)
+    ds = np.stack([d, d + rng.standard_normal(d.shape)])
+    s_alm, s_map, info, stages, conv = plan.solve_cooled(dev(ds), l_iter0=l0, l_margin=margin,
+                                                          max_iters=300)
+    _check_rules(stages, w.cl4[0], info[0].tau, 4 * np.pi / w.npix, lmax, l0, margin, 500,
+                 info[0].iters_done)
+    sched = [(int(s[2]), s[1], int(s[3])) for s in stages]
+    for b in range(2):
+        ref_alm, ref_map = oracle.solve_pol_staged(nside, lmax, w.cl4, M6, rho_of(ds[b]), sched)
+        assert _rel_teb(s_alm.cpu().numpy()[b], ref_alm, lmax) < 1e-5
+        assert rel(s_map.cpu().numpy()[b], ref_map) < 1e-5
 
 
 def test_f32_solve_kinds_share_a_plan(mf):

@@ -361,3 +361,57 @@ def test_pol_fluctuation_source_quadratic_forms():
         got += wgt * (x[:, k].real @ S @ x[:, k].real + x[:, k].imag @ S @ x[:, k].imag)
         want += wgt * np.sum(np.abs(h[:, k]) ** 2)
     assert got == pytest.approx(want, rel=2e-2)
+
+
+def _pol_rho(M6, d):
+    return np.einsum("pij,jp->ip", _unpack(M6), d)
+
+
+def test_pol_staged_solve_without_truncation_equals_the_iteration():
+    """Stages at the full band limit are the plain iteration with that lambda sequence."""
+    nside, lmax = 8, 16
+    w = W.config3(3, nside, lmax, ndisc=5, band_z=0.15, nu=10)
+    M6 = w.M6()
+    d = w.data_from_signal_maps(oracle.alm2map_pol(nside, lmax, w.signal_alm))
+    rho = _pol_rho(M6, d)
+    a1, m1 = oracle.solve_pol_staged(nside, lmax, w.cl4, M6, rho, [(lmax, 4.0, 6), (lmax, 1.0, 9)])
+    b1, n1 = oracle.solve_pol(nside, lmax, w.cl4, M6, rho, lam=[4.0] * 6 + [1.0] * 9)
+    assert rel(a1, b1) < 1e-12 and rel(m1, n1) < 1e-12
+
+
+def test_pol_staged_truncated_stage_is_the_band_limited_problem():
+    """One stage at lmax_k < lmax is the iteration of the problem with band limit lmax_k
+    (spectra cut there); the coefficients above lmax_k are zero."""
+    nside, lmax, lk = 8, 20, 9
+    w = W.config3(5, nside, lmax, ndisc=5, band_z=0.15, nu=10)
+    M6 = w.M6()
+    d = w.data_from_signal_maps(oracle.alm2map_pol(nside, lmax, w.signal_alm))
+    rho = _pol_rho(M6, d)
+    a, m = oracle.solve_pol_staged(nside, lmax, w.cl4, M6, rho, [(lk, 3.0, 8)])
+    b, n = oracle.solve_pol(nside, lk, w.cl4[:, :lk + 1], M6, rho, lam=[3.0] * 8)
+    ls, ms = W.alm_l_m(lmax)
+    low = (ls <= lk) & (ms <= lk)
+    assert np.all(a[:, ~low] == 0)
+    assert rel(a[:, low], b) < 1e-12 and rel(m, n) < 1e-12
+
+
+def test_pol_staged_reduces_to_temperature_staging():
+    """With no polarized signal (EE = BB = TE = 0) and no T-P noise correlation, T decouples:
+    its stages are the temperature staged solve (itself pinned to dense harmonics) with the
+    same tau, Q and U stay zero."""
+    nside, lmax = 8, 24
+    w = W.config3(6, nside, lmax, ndisc=5, band_z=0.15, nu=10)
+    M6 = w.M6()
+    MT = M6[:, 0]
+    M6d = np.zeros_like(M6)
+    M6d[:, 0] = MT
+    M6d[:, 3] = M6d[:, 5] = 0.5 * MT   # Q, U noise weaker than T: tau is set by T alone
+    cl4 = w.cl4.copy()
+    cl4[1:] = 0.0
+    rng = np.random.default_rng(4)
+    rho = rng.standard_normal((3, w.npix)) * (MT > 0)
+    stages = [(10, 6.0, 5), (18, 2.0, 4), (24, 1.0, 6)]
+    a, m = oracle.solve_pol_staged(nside, lmax, cl4, M6d, rho, stages)
+    at, mt = oracle.solve_staged(nside, lmax, cl4[0], MT, rho[0], stages)
+    assert rel(a[0], at) < 1e-12 and rel(m[0], mt) < 1e-12
+    assert np.all(a[1:] == 0) and np.abs(m[1:]).max() == 0.0
