@@ -267,7 +267,9 @@ int mfwf_solve_cooled(mfwf_plan plan, const double *data, int nmaps, double *s_a
  * iteration, the largest its maps need, so every map keeps its bound.  chi^2(lambda, x) is
  * decreasing and convex in lambda; the new lambda comes from a safeguarded Newton search on
  * the pixel term (one pass over the maps per step) and meets the bound exactly.
- * Temperature plans (spin 0), MFWF_F64 or MFWF_F32; input data d (rho = M d).
+ * Spin 0 or spin 2, MFWF_F64 or MFWF_F32; input data d (rho = M d).  For spin 2 the pixel
+ * term is the T, Q, U form q^T B^-1 q, q = rho - M s, B = M + (lambda - 1) tau M^2 per block,
+ * with derivative -tau |M B^-1 q|^2, and n_dof counts 3 per observed pixel.
  */
 typedef struct {
     double m_sigma;      /* initial b = n_dof - m_sigma sigma_chi2 (0: 5)                   */
@@ -284,7 +286,7 @@ typedef struct {
 } mfwf_bound_opts;
 
 /* input, outputs and info as in mfwf_solve; opts may be NULL (all defaults).  Errors: as
- * mfwf_solve; MFWF_EINVAL for negative options or a spin-2 plan; MFWF_ENAN if chi^2 is not
+ * mfwf_solve; MFWF_EINVAL for negative options; MFWF_ENAN if chi^2 is not
  * finite. */
 int mfwf_solve_bounded(mfwf_plan plan, const double *data, int nmaps, double *s_alm_out,
                        double *s_map_out, mfwf_bound_opts *opts, mfwf_solve_info *info);

@@ -1530,8 +1530,12 @@ struct BoundEval {
     BoundEval(Plan &q, const double *r, int n) : p(q), rho(r), nb(n), H(n, 0.0), b(n), P(n), out(2 * n) {}
     int operator()(double lam, double &G, double &dG) {
         double *partial = p.d_red, *o2 = p.d_red + 2L * 256 * nb;
-        MFWF_TRY(launch_chi2_pix_dlam(rho, p.d_M, p.d_smap, p.npix, nb, lam, p.tau, partial, 256,
-                                      o2, p.stream));
+        if (p.spin == 2)
+            MFWF_TRY(launch_chi2_pix_dlam_pol(rho, p.d_M, p.d_smap, p.npix, nb, lam, p.tau,
+                                              partial, 256, o2, p.stream));
+        else
+            MFWF_TRY(launch_chi2_pix_dlam(rho, p.d_M, p.d_smap, p.npix, nb, lam, p.tau, partial,
+                                          256, o2, p.stream));
         MFWF_HIP(hipMemcpyAsync(out.data(), o2, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost,
                                 p.stream));
         MFWF_HIP(hipStreamSynchronize(p.stream));
@@ -1589,12 +1593,19 @@ static int bound_lambda(BoundEval &ev, double hi, double &lam) {
 static int bounded_chunk(Plan &p, const double *data, int nb, double *s_alm_out,
                          double *s_map_out, const BoundOpts &o, std::vector<double> &trace,
                          int &n_updates, bool &reached_one, mfwf_solve_info *info) {
-    MFWF_TRY(launch_rho_from_data(data, p.d_M, p.d_rho, p.npix, nb, p.stream));
+    const long nc = p.ncomp;
+    if (p.spin == 2)
+        MFWF_TRY(launch_rho_from_data_pol(data, p.d_M, p.d_rho, p.npix, nb, p.stream));
+    else
+        MFWF_TRY(launch_rho_from_data(data, p.d_M, p.d_rho, p.npix, nb, p.stream));
     const double *rho = p.d_rho;
-    MFWF_TRY(launch_fill(p.d_smap, p.npix * nb, 0.0, p.stream));
-    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm), 2 * p.nalm * nb, 0.0, p.stream));
-    if (p.dtype == MFWF_F32)
+    MFWF_TRY(launch_fill(p.d_smap, nc * p.npix * nb, 0.0, p.stream));
+    MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm), 2 * nc * p.nalm * nb, 0.0, p.stream));
+    if (p.dtype == MFWF_F32) {
         MFWF_HIP(hipMemsetAsync(p.d_s32, 0, sizeof(float) * (size_t)p.nalm * p.C2, p.stream));
+        if (p.spin == 2)
+            MFWF_HIP(hipMemsetAsync(p.d_seb32, 0, sizeof(float) * (size_t)p.nalm * 2 * p.C2, p.stream));
+    }
     const double sigma = std::sqrt(2.0 * (double)p.ndof);
     BoundEval ev(p, rho, nb);
     for (int k = 0; k < nb; k++) ev.b[k] = (double)p.ndof - o.m_sigma * sigma;
@@ -1608,7 +1619,10 @@ static int bounded_chunk(Plan &p, const double *data, int nb, double *s_alm_out,
     for (int it = 0; it < o.max_iters; it++) {
         MFWF_TRY(iteration(p, rho, nb, lam, true));
         // harmonic part of chi^2 at the new iterate
-        MFWF_TRY(launch_harm_diag(p, p.d_salm, p.d_salm_prev, nb, p.d_red, p.d_diag));
+        if (p.spin == 2)
+            MFWF_TRY(launch_harm_diag_pol(p, p.d_salm, p.d_salm_prev, nb, p.d_red, p.d_diag));
+        else
+            MFWF_TRY(launch_harm_diag(p, p.d_salm, p.d_salm_prev, nb, p.d_red, p.d_diag));
         MFWF_HIP(hipMemcpyAsync(dg.data(), p.d_diag, sizeof(double) * 8 * nb, hipMemcpyDeviceToHost,
                                 p.stream));
         MFWF_HIP(hipStreamSynchronize(p.stream));
@@ -1648,10 +1662,10 @@ static int bounded_chunk(Plan &p, const double *data, int nb, double *s_alm_out,
     }
     MFWF_TRY(cooled_diag(p, rho, nb, lam, dg));
     if (s_alm_out)
-        MFWF_HIP(hipMemcpyAsync(s_alm_out, p.d_salm, sizeof(double2) * p.nalm * nb,
+        MFWF_HIP(hipMemcpyAsync(s_alm_out, p.d_salm, sizeof(double2) * nc * p.nalm * nb,
                                 hipMemcpyDeviceToDevice, p.stream));
     if (s_map_out)
-        MFWF_HIP(hipMemcpyAsync(s_map_out, p.d_smap, sizeof(double) * p.npix * nb,
+        MFWF_HIP(hipMemcpyAsync(s_map_out, p.d_smap, sizeof(double) * nc * p.npix * nb,
                                 hipMemcpyDeviceToDevice, p.stream));
     if (info) {
         for (int k = 0; k < nb; k++) {
@@ -1724,7 +1738,6 @@ int mfwf_solve_bounded(mfwf_plan plan, const double *data, int nmaps, double *s_
     Plan &p = plan->p;
     if (!p.have_cov) return fail(MFWF_ENOCOV, "covariances not set");
     if (nmaps > 0 && !data) return fail(MFWF_EINVAL, "data is NULL");
-    if (p.spin != 0) return fail(MFWF_EINVAL, "the error-bound schedule is for temperature plans");
     mfwf_bound_opts u{};
     if (opts) u = *opts;
     if (u.m_sigma < 0.0 || u.lam_tol < 0.0 || u.stall_frac < 0.0 || u.stall_iters < 0 ||
@@ -1742,9 +1755,10 @@ int mfwf_solve_bounded(mfwf_plan plan, const double *data, int nmaps, double *s_
     for (int b0 = 0; b0 < nmaps; b0 += p.max_batch) {
         const int nb = std::min(p.max_batch, nmaps - b0);
         bool r = false;
-        MFWF_TRY(bounded_chunk(p, data + (long)b0 * p.npix, nb,
-                               s_alm_out ? s_alm_out + 2L * b0 * p.nalm : nullptr,
-                               s_map_out ? s_map_out + (long)b0 * p.npix : nullptr, o, trace,
+        const long nc = p.ncomp;
+        MFWF_TRY(bounded_chunk(p, data + nc * b0 * p.npix, nb,
+                               s_alm_out ? s_alm_out + 2L * nc * b0 * p.nalm : nullptr,
+                               s_map_out ? s_map_out + nc * b0 * p.npix : nullptr, o, trace,
                                n_updates, r, info ? info + b0 : nullptr));
         reached = reached && r;
     }

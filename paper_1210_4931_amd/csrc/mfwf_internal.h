@@ -235,6 +235,11 @@ int launch_fluct_combine_pol(const double *g1, const double *M6, const double *y
 int launch_chi2_pix_dlam(const double *rho, const double *M, const double *smap, long npix,
                          int nb, double lam, double tau, double *partial, int nblocks,
                          double *out2, hipStream_t s);
+int launch_chi2_pix_dlam_pol(const double *rho, const double *M6, const double *smap, long npix,
+                             int nb, double lam, double tau, double *partial, int nblocks,
+                             double *out2, hipStream_t s);
+// out2[b][0..1] = sum over nblocks of partial[b][block][0..1], in block order
+int launch_sum_pairs(const double *partial, int nblocks, int nb, double *out2, hipStream_t s);
 
 // templates.hip (Eq. 12: monopole and dipole template removal)
 int launch_template_sums(const Plan &p, const double *d, int nb, double *partial, double *out14);

@@ -242,15 +242,19 @@ __global__ void k_sum_pairs(const double *__restrict__ partial, int nblocks, int
     out[2 * b + 1] = c;
 }
 
+int launch_sum_pairs(const double *partial, int nblocks, int nb, double *out2, hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_pairs, dim3((nb + 63) / 64), dim3(64), 0, s, partial, nblocks, nb, out2);
+    MFWF_HIP(hipGetLastError());
+    return MFWF_OK;
+}
+
 int launch_chi2_pix_dlam(const double *rho, const double *M, const double *smap, long npix,
                          int nb, double lam, double tau, double *partial, int nblocks,
                          double *out2, hipStream_t s) {
     hipLaunchKernelGGL(k_chi2_pix_dlam, dim3(nblocks, nb), dim3(kThreads), 0, s, rho, M, smap,
                        npix, lam, tau, partial);
     MFWF_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_sum_pairs, dim3((nb + 63) / 64), dim3(64), 0, s, partial, nblocks, nb, out2);
-    MFWF_HIP(hipGetLastError());
-    return MFWF_OK;
+    return launch_sum_pairs(partial, nblocks, nb, out2, s);
 }
 
 // rho = M^{1/2} g1 + Omega * (Y C^{-1/2} h)  (Eq. 9 in per-pixel form)

@@ -625,6 +625,61 @@ int launch_chi2_pix_pol(const double *rho, const double *M6, const double *smap,
     return MFWF_OK;
 }
 
+// Pixel term of chi^2(lambda, s) for T, Q, U and its derivative in lambda (the error-bound
+// schedule of Sect. 2.2): with q = rho - M s and B = M + (lam - 1) tau M^2 per observed block,
+//   P = q^T B^-1 q,  dP/dlam = -tau |M B^-1 q|^2
+// (dB/dlam = tau M^2, and M commutes with B).  partial[b][block][2], summed by
+// launch_sum_pairs into out[b][2].
+__global__ void __launch_bounds__(kPT)
+k_chi2_pix_dlam_pol(const double *__restrict__ rho, const double *__restrict__ M6,
+                    const double *__restrict__ smap, long npix, double lam, double tau,
+                    double *__restrict__ partial) {
+    __shared__ double sh[2][kPT];
+    const long off = 3L * blockIdx.y * npix;
+    const double l1t = (lam - 1.0) * tau;
+    double acc = 0.0, dacc = 0.0;
+    for (long p = blockIdx.x * (long)blockDim.x + threadIdx.x; p < npix;
+         p += (long)gridDim.x * blockDim.x) {
+        const Sym3 M = load_sym3(M6, p);
+        if (!(sym3_det(M) > 0.0)) continue;
+        double s[3] = {smap[off + p], smap[off + npix + p], smap[off + 2 * npix + p]}, Ms[3], q[3],
+               x[3], Mx[3];
+        sym3_mv(M, s, Ms);
+        for (int k = 0; k < 3; k++) q[k] = rho[off + k * npix + p] - Ms[k];
+        const Sym3 M2 = sym3_square(M);
+        const Sym3 B{M.a + l1t * M2.a, M.b + l1t * M2.b, M.c + l1t * M2.c, M.d + l1t * M2.d,
+                     M.e + l1t * M2.e, M.f + l1t * M2.f};
+        sym3_solve(B, q, x);
+        sym3_mv(M, x, Mx);
+        acc += q[0] * x[0] + q[1] * x[1] + q[2] * x[2];
+        dacc -= tau * (Mx[0] * Mx[0] + Mx[1] * Mx[1] + Mx[2] * Mx[2]);
+    }
+    sh[0][threadIdx.x] = acc;
+    sh[1][threadIdx.x] = dacc;
+    __syncthreads();
+    for (int w = kPT / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const long o = ((long)blockIdx.y * gridDim.x + blockIdx.x) * 2;
+        partial[o] = sh[0][0];
+        partial[o + 1] = sh[1][0];
+    }
+}
+
+int launch_chi2_pix_dlam_pol(const double *rho, const double *M6, const double *smap, long npix,
+                             int nb, double lam, double tau, double *partial, int nblocks,
+                             double *out2, hipStream_t s) {
+    hipLaunchKernelGGL(k_chi2_pix_dlam_pol, dim3(nblocks, nb), dim3(kPT), 0, s, rho, M6, smap,
+                       npix, lam, tau, partial);
+    MFWF_HIP(hipGetLastError());
+    return launch_sum_pairs(partial, nblocks, nb, out2, s);
+}
+
 // Harmonic diagnostics over T, E, B (real dof, m > 0 twice):
 //   [0] s^T S^+ s (the (T, E) block inverted where both have power, else the one that has;
 //   B where BB > 0), [1] |s - prev|^2, [2] |s|^2
