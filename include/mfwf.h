@@ -64,8 +64,8 @@ typedef enum {
 } mfwf_dtype;
 
 /*
- * Create a plan for HEALPix resolution nside (power of two, 1..1024) and band limit
- * lmax (1..4*nside).  spin: 0 = temperature only, 2 = temperature and polarization (T, Q, U
+ * Create a plan for HEALPix resolution nside (power of two, 1..2048; 1..1024 for MFWF_F32)
+ * and band limit lmax (1..4*nside).  spin: 0 = temperature only, 2 = temperature and polarization (T, Q, U
  * maps, T, E, B coefficients, 3x3 noise and signal blocks).  max_batch (>= 1):
  * largest number of
  * maps one call processes at once (larger calls are split).  hip_stream: a hipStream_t
@@ -77,7 +77,11 @@ typedef enum {
  * (lmax+1)(lmax+2)/2 roughly: 2.2 GB at nside 512 / lmax 1024, and column-major work
  * arrays for max_batch maps; with spin 2 also FP32 tables of the spin-2 functions
  * F+-_lm = ((2)lambda_lm +- (-2)lambda_lm)/2, two more tables of that size).  *out receives
- * the handle.
+ * the handle.  Ring transforms whose chirp-z convolution would exceed 8192 points (polar
+ * rings of more than 4096 pixels, nside 2048) are split into four chirp-z transforms of a
+ * quarter length each, with a device scratch of 32 bytes x ring pixels of those rings per
+ * map and component; the environment variable MFWF_FFT_SPLIT_LEN (a power of two >= 16,
+ * read here) lowers that 8192 so that tests can send small plans through the split path.
  * Errors: MFWF_EINVAL for out-of-range sizes or spin not 0 or 2; MFWF_ENOMEM, MFWF_EDEVICE.
  */
 int mfwf_plan_create(int nside, int lmax, int spin, int dtype, int max_batch, void *hip_stream,

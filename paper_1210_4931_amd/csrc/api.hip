@@ -236,7 +236,8 @@ static void free_plan(Plan &p) {
                     p.d_rho,  p.d_t,    p.d_smap,  p.d_phase,  p.d_apart, p.d_salm,
                     p.d_salm_prev, p.d_sp, p.d_red, p.d_diag, p.d_lam, p.d_loff, p.d_Lp,
                     p.d_minls32, p.d_ana_items, p.d_syn_items, p.d_ana_tab, p.d_syn_tab, p.d_lofi, p.d_phf, p.d_ph32, p.d_a32,
-                    p.d_s32, p.d_fp, p.d_fm, p.d_ph32p, p.d_ph32r, p.d_ap32, p.d_ar32, p.d_seb32};
+                    p.d_s32, p.d_fp, p.d_fm, p.d_ph32p, p.d_ph32r, p.d_ap32, p.d_ar32, p.d_seb32,
+                    p.d_fftsplit};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
 }
@@ -511,8 +512,11 @@ static void build_spin2_table(int lmax, const std::vector<double> &ctab,
 
 static int create(int nside, int lmax, int spin, int dtype, int max_batch, void *stream,
                   Plan &p) {
-    if (nside < 1 || nside > 1024 || !is_pow2(nside))
-        return fail(MFWF_EINVAL, "nside must be a power of two in [1, 1024]");
+    if (nside < 1 || nside > 2048 || !is_pow2(nside))
+        return fail(MFWF_EINVAL, "nside must be a power of two in [1, 2048]");
+    if (dtype == MFWF_F32 && nside > 1024)
+        return fail(MFWF_EINVAL, "the batched FP32 form supports nside <= 1024 (its tables "
+                                 "outgrow the device above)");
     if (lmax < 1 || lmax > 4 * nside) return fail(MFWF_EINVAL, "lmax must be in [1, 4 nside]");
     if (spin != 0 && spin != 2) return fail(MFWF_EINVAL, "spin must be 0 (T) or 2 (T, Q, U)");
     if (dtype != MFWF_F64 && dtype != MFWF_F32) return fail(MFWF_EINVAL, "dtype must be MFWF_F64 or MFWF_F32");
@@ -553,7 +557,14 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     p.work_tuples = 0.0;
     for (int ls : lstart) p.work_tuples += (ls <= lmax) ? (double)(lmax - ls + 1) : 0.0;
 
-    // ring FFT tables
+    // ring FFT tables.  Chirp-z lengths above split_len take the split transform: the in-LDS
+    // limit, or a smaller power of two from MFWF_FFT_SPLIT_LEN (tests of the split path at
+    // sizes the oracle transforms whole)
+    int split_len = fft_max_length();
+    if (const char *e = std::getenv("MFWF_FFT_SPLIT_LEN")) {
+        const long v = std::strtol(e, nullptr, 10);
+        if (v >= 16 && v < split_len && is_pow2((int)v)) split_len = (int)v;
+    }
     std::vector<PairFFT> pf(p.npair);
     std::vector<double2> chirp, bhat;
     int fftmax = 1;
@@ -567,10 +578,16 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
         f.startS = (iS == q + 1) ? g.start : ring_geom(nside, iS).start;
         f.bluestein = is_pow2(g.nphi) ? 0 : 1;
         f.fftlen = f.bluestein ? next_pow2(2L * g.nphi - 1) : g.nphi;
+        // a chirp-z transform longer than the in-LDS limit: split n = 4 i into four
+        // transforms of length i (polar rings always have n = 4 i)
+        if (f.bluestein && f.fftlen > split_len && g.nphi % 4 == 0) {
+            f.bluestein = 2;
+            f.fftlen = next_pow2(2L * (g.nphi / 4) - 1);
+        }
         fftmax = std::max(fftmax, f.fftlen);
         f.chirp_off = f.bhat_off = 0;
         if (f.bluestein) {
-            const int n = g.nphi, M = f.fftlen;
+            const int n = f.bluestein == 2 ? g.nphi / 4 : g.nphi, M = f.fftlen;
             f.chirp_off = (long)chirp.size();
             for (long k = 0; k < n; k++) {  // c_k = exp(-i pi k^2 / n)
                 const long r = (k * k) % (2L * n);
@@ -605,25 +622,34 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
         const double a = -2.0 * M_PI * (double)(64L * h) / fftmax;
         twhi[h] = make_double2(std::cos(a), std::sin(a));
     }
-    // FFT classes: pairs whose transform fits half of the largest length, and the rest
+    // FFT classes: pairs whose transform fits half of the largest length, the rest, and the
+    // split rings (whose combined spectrum of n <= fftmax points passes through LDS)
     std::vector<int> plist;
     p.fft_class_len[0] = 1;
-    for (int c = 0; c < 2; c++) {
+    int nsplit_max = 0;
+    for (int c = 0; c < 3; c++) {
         p.fft_class_off[c] = (int)plist.size();
         for (int q = 0; q < p.npair; q++) {
-            const bool small = 2 * pf[q].fftlen <= fftmax;
-            if ((c == 0) == small) {
-                plist.push_back(q);
-                if (c == 0) p.fft_class_len[0] = std::max(p.fft_class_len[0], pf[q].fftlen);
+            const int cls = pf[q].bluestein == 2 ? 2 : (2 * pf[q].fftlen <= fftmax ? 0 : 1);
+            if (cls != c) continue;
+            plist.push_back(q);
+            if (c == 0) p.fft_class_len[0] = std::max(p.fft_class_len[0], pf[q].fftlen);
+            if (c == 2) {
+                nsplit_max = std::max(nsplit_max, pf[q].nphi);
+                p.fftsplit_sublen = std::max(p.fftsplit_sublen, pf[q].fftlen);
             }
         }
         p.fft_class_count[c] = (int)plist.size() - p.fft_class_off[c];
     }
     p.fft_class_len[1] = fftmax;
+    p.fft_class_len[2] = fftmax;
+    if (nsplit_max > fftmax)
+        return fail(MFWF_EINVAL, "split ring of " + std::to_string(nsplit_max) +
+                                     " pixels above the largest transform length");
     if (fftmax > fft_max_length())
         return fail(MFWF_EINVAL, "ring FFT length " + std::to_string(fftmax) + " above the supported " +
                                      std::to_string(fft_max_length()));
-    const size_t lds = std::max(fft_class_lds(p, 0), fft_class_lds(p, 1));
+    const size_t lds = std::max({fft_class_lds(p, 0), fft_class_lds(p, 1), fft_class_lds(p, 2)});
     {
         int dev = 0, maxlds = 0;
         MFWF_HIP(hipGetDevice(&dev));
@@ -655,6 +681,12 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     MFWF_TRY(dalloc(&p.d_twhi, twhi.size(), "twiddles hi"));
     MFWF_TRY(dalloc(&p.d_chirp, std::max<size_t>(1, chirp.size()), "chirp"));
     MFWF_TRY(dalloc(&p.d_bhat, std::max<size_t>(1, bhat.size()), "chirp kernel"));
+    if (p.fft_class_count[2] > 0) {  // split rings: sub-spectra parked between the passes
+        p.fftsplit_rows = (int)(nc * B);
+        p.fftsplit_stride = 2L * nsplit_max;
+        MFWF_TRY(dalloc(&p.d_fftsplit, (long)p.fftsplit_rows * p.fft_class_count[2] * p.fftsplit_stride,
+                        "split ring spectra"));
+    }
     MFWF_TRY(dalloc(&p.d_cl, ncl * (lmax + 1), "cl"));
     MFWF_TRY(dalloc(&p.d_M, nmw * p.npix, "M"));
     MFWF_TRY(dalloc(&p.d_rho, B * nc * p.npix, "rho"));

@@ -33,7 +33,9 @@ void set_error(const std::string &msg);
 struct PairFFT {
     int nphi;        // pixels per ring of this pair
     int fftlen;      // length of the power-of-two transform used (nphi or Bluestein M)
-    int bluestein;   // 1 if nphi is not a power of two
+    int bluestein;   // 0: nphi is a power of two; 1: Bluestein of length nphi; 2: split,
+                     // nphi = 4 i with four Bluestein transforms of length i (fftlen, chirp
+                     // and kernel tables of length i)
     int half_shift;  // 1 if phi_0 = pi / nphi, 0 if phi_0 = 0
     long startN;     // first pixel of the north ring
     long startS;     // first pixel of the south ring (== startN on the equator)
@@ -72,7 +74,12 @@ struct Plan {
     double2 *d_bhat = nullptr;   // Bluestein kernels FFT_M(conj chirp) / M, natural order
     int fftmax;                  // largest power-of-two transform length
     int *d_plist = nullptr;      // [npair] pair indices grouped by FFT class
-    int fft_class_off[2] = {0, 0}, fft_class_count[2] = {0, 0}, fft_class_len[2] = {1, 1};
+    // classes: 0 short transforms, 1 the longest in-LDS ones, 2 split rings (FP64 rows only)
+    int fft_class_off[3] = {0, 0, 0}, fft_class_count[3] = {0, 0, 0}, fft_class_len[3] = {1, 1, 1};
+    double2 *d_fftsplit = nullptr;  // split rings: [rows][class-2 pairs][fftsplit_stride]
+    long fftsplit_stride = 0;       // 2 x the longest split ring
+    int fftsplit_rows = 0;          // rows (maps x components) one launch may carry
+    int fftsplit_sublen = 1;        // longest Bluestein length of the split sub-transforms
     long *d_mofs = nullptr;      // [nm] packed offset of (l = m, m)
     double *d_pc = nullptr;      // [nalm][5] spin-2 coefficients of mu_l, mu_{l-1} (spin 2)
 

@@ -24,9 +24,11 @@
 // can apply the messenger pixel update (Eq. 3) to its input as it reads it.
 // Grid (map, pair): the workgroups of one ring pair run back to back, so the pair's chirp
 // tables and noise precision are fetched into L2 once for all maps.
-// Pairs are launched in two classes by transform length: most pairs need at most half the
+// Pairs are launched in classes by transform length: most pairs need at most half the
 // largest length (less LDS and fewer registers per thread, more workgroups per CU); the long
-// Bluestein transforms of the largest polar rings form the second class.
+// Bluestein transforms of the largest polar rings form the second class; polar rings whose
+// chirp-z transform would outgrow LDS (nside 2048) form a third, split into four shorter
+// transforms (below).
 #include <mutex>
 
 #include "fft_core.h"
@@ -362,6 +364,133 @@ k_fft_inv(const InT *__restrict__ phase, double *__restrict__ maps,
     }
 }
 
+// Split rings: a polar ring n = 4 i whose chirp-z transform would not fit LDS.  Decimation
+// in time splits its DFT into four of length i,
+//   X_k = sum_{r < 4} e^{-2 pi i r k / n} Z_r(k mod i),   Z_r = DFT_i(x_{4 j + r}),
+// each Z_r a Bluestein transform of length i, one workgroup each (k_fft_split_sub).  The
+// sub-spectra wait in global scratch, one area of 2 n elements per (row, pair): [0, n) holds
+// the folded bins of an inverse transform, [n, 2 n) the four sub-spectra Z[r i + k].
+// Forward: k_fft_split_sub from the pixels, then k_fft_fwd_split_combine (combined spectrum
+// in LDS, rows stored as in k_fft_fwd).  Inverse: k_fft_inv_split_fold (bins folded as in
+// k_fft_inv), k_fft_split_sub from those bins, k_fft_inv_split_combine to the pixels.
+
+// Z_r of one (row, pair, r): grid (row, pair of the class, r); FROM_MAP: x = t_N + i t_S from
+// maps, else x = the folded bins in the scratch area
+template <int TPB, int EPT, bool FROM_MAP>
+__global__ void __launch_bounds__(TPB)
+k_fft_split_sub(const double *__restrict__ maps, double2 *__restrict__ scratch, long sstride,
+                int sub_area, const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
+                const double2 *__restrict__ twlo, const double2 *__restrict__ twhi, int ntwhi,
+                int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
+                long npix) {
+    extern __shared__ double2 buf[];
+    const int p = plist[blockIdx.y], b = blockIdx.x, r = blockIdx.z;
+    const PairFFT pf = pfft[p];
+    PairFFT sub = pf;
+    sub.nphi = pf.nphi / 4;
+    sub.bluestein = 1;
+    const int n = pf.nphi, i = sub.nphi;
+    const bool equator = (pf.startS == pf.startN);
+    const Twiddles tw = load_twiddles(buf, sub_area, twlo, twhi, ntwhi);
+    double2 *G = scratch + ((long)b * gridDim.y + blockIdx.y) * sstride;
+    double2 *Z = G + sstride / 2 + (long)r * i;
+    const double *sp = maps + (long)b * npix;
+    for (int j = threadIdx.x; j < i; j += TPB) {
+        const int jj = 4 * j + r;
+        if constexpr (FROM_MAP)
+            buf[lds_ix(j)] = make_double2(sp[pf.startN + jj], equator ? 0.0 : sp[pf.startS + jj]);
+        else
+            buf[lds_ix(j)] = G[jj];
+    }
+    __syncthreads();
+    ring_dft<TPB, EPT>(buf, sub, tw, fftmax, chirp, bhat);
+    for (int k = threadIdx.x; k < i; k += TPB) Z[k] = dft_bin(buf, sub, chirp, k);
+    (void)n;
+}
+
+// X_k from the sub-spectra Z for k = threadIdx.x, +TPB, ... < n; f(k, X_k)
+template <int TPB, typename F>
+__device__ __forceinline__ void split_combine(const double2 *Z, int n, F f) {
+    const int i = n / 4;
+    for (int k = threadIdx.x; k < n; k += TPB) {
+        const int kk = k - (k / i) * i;
+        double sn, cs;  // w = e^{-2 pi i k / n}; w^2, w^3 as products (a few ulp)
+        sincospi(2.0 * (double)k / (double)n, &sn, &cs);
+        const double2 w1 = make_double2(cs, -sn), w2 = cmul(w1, w1), w3 = cmul(w2, w1);
+        double2 X = cadd(Z[kk], cmul(w1, Z[i + kk]));
+        X = cadd(X, cmul(w2, Z[2 * i + kk]));
+        X = cadd(X, cmul(w3, Z[3 * i + kk]));
+        f(k, X);
+    }
+}
+
+// forward, second step: the combined spectrum in LDS, stored as ring-Fourier rows
+template <int TPB, int EPT, typename OutT>
+__global__ void __launch_bounds__(TPB)
+k_fft_fwd_split_combine(OutT *__restrict__ phase, const double2 *__restrict__ scratch,
+                        long sstride, const PairFFT *__restrict__ pfft,
+                        const int *__restrict__ plist, const double2 *__restrict__ twlo,
+                        const double2 *__restrict__ twhi, int ntwhi, int fftmax,
+                        const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
+                        long npix, int nring, int nm, int lmax, int fftlen_class) {
+    extern __shared__ double2 buf[];
+    const int p = plist[blockIdx.y], b = blockIdx.x;
+    PairFFT pf = pfft[p];
+    const Twiddles tw = load_twiddles(buf, fft_area(fftlen_class, TPB), twlo, twhi, ntwhi);
+    const double2 *Z = scratch + ((long)b * gridDim.y + blockIdx.y) * sstride + sstride / 2;
+    split_combine<TPB>(Z, pf.nphi, [&](int k, double2 X) { buf[lds_ix(k)] = X; });
+    __syncthreads();
+    pf.bluestein = 0;  // the spectrum sits in LDS in natural order
+    store_rows<TPB>(buf, pf, tw, fftmax, chirp, lmax,
+                    RingSeq<OutT, false>{phase + ((long)b * nring + p) * nm, 1},
+                    RingSeq<OutT, false>{phase + ((long)b * nring + (nring - 1 - p)) * nm, 1});
+    (void)bhat;
+    (void)npix;
+}
+
+// inverse, first step: the folded bins (as k_fft_inv leaves them before its transform) to
+// the scratch area
+template <int TPB, int EPT, typename InT>
+__global__ void __launch_bounds__(TPB)
+k_fft_inv_split_fold(const InT *__restrict__ phase, double2 *__restrict__ scratch, long sstride,
+                     const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
+                     const double2 *__restrict__ twlo, const double2 *__restrict__ twhi,
+                     int ntwhi, int fftmax, const double2 *__restrict__ chirp,
+                     const double2 *__restrict__ bhat, long npix, int nring, int nm, int lmax,
+                     int fftlen_class) {
+    extern __shared__ double2 buf[];
+    const int p = plist[blockIdx.y], b = blockIdx.x;
+    const PairFFT pf = pfft[p];
+    const Twiddles tw = load_twiddles(buf, fft_area(fftlen_class, TPB), twlo, twhi, ntwhi);
+    const RingSeq<const InT, false> FN{phase + ((long)b * nring + p) * nm, 1};
+    const RingSeq<const InT, false> FS{phase + ((long)b * nring + (nring - 1 - p)) * nm, 1};
+    fold_bins<TPB, EPT>(buf, FN, FS, pf, tw, fftmax, lmax);
+    __syncthreads();
+    double2 *G = scratch + ((long)b * gridDim.y + blockIdx.y) * sstride;
+    for (int j = threadIdx.x; j < pf.nphi; j += TPB) G[j] = buf[lds_ix(j)];
+    (void)chirp;
+    (void)bhat;
+    (void)npix;
+}
+
+// inverse, last step: pixel k of the pair = conj(X_k)
+template <int TPB>
+__global__ void __launch_bounds__(TPB)
+k_fft_inv_split_combine(double *__restrict__ maps, const double2 *__restrict__ scratch,
+                        long sstride, const PairFFT *__restrict__ pfft,
+                        const int *__restrict__ plist, long npix) {
+    const int p = plist[blockIdx.y], b = blockIdx.x;
+    const PairFFT pf = pfft[p];
+    const bool equator = (pf.startS == pf.startN);
+    const double2 *Z = scratch + ((long)b * gridDim.y + blockIdx.y) * sstride + sstride / 2;
+    double *sNmap = maps + (long)b * npix + pf.startN;
+    double *sSmap = maps + (long)b * npix + pf.startS;
+    split_combine<TPB>(Z, pf.nphi, [&](int k, double2 X) {
+        sNmap[k] = X.x;
+        if (!equator) sSmap[k] = -X.y;
+    });
+}
+
 // One iteration's ring steps in one pass over a pair (batched FP32 form), on the
 // matrix-core columns [m][ring][C2] (map b at column 2b) in place: the synthesis F is folded
 // and transformed back to the pair's pixels s (optionally stored to smap), the messenger
@@ -442,6 +571,7 @@ k_fft_inv_fwd(float2 *__restrict__ data, int C2, int nmap, int npl, double *__re
 int fft_class_shape(const Plan &p, int c, int &ept) {
     const int len = p.fft_class_len[c];
     ept = 8;
+    if (c == 2) return 1024;  // split rings: up to 8192 points in LDS at any plan size
     return len <= 2048 ? 256 : len / 8;
 }
 
@@ -456,9 +586,70 @@ size_t fft_class_lds(const Plan &p, int c) {
     p.d_pfft, p.d_plist + p.fft_class_off[c], p.d_twlo, p.d_twhi, p.fft_ntwhi, p.fftmax,        \
         p.d_chirp, p.d_bhat, p.npix, p.nring, rs, p.lmax, p.fft_class_len[c]
 
+// split rings (class 2; FP64 rows only: plans of the FP32 form never have them)
+static constexpr int kSplitSubTPB = 512, kSplitTPB = 1024;
+
+static int split_check(const Plan &p, int nb) {
+    if (nb > p.fftsplit_rows)
+        return fail(MFWF_EINVAL, "split ring transforms of " + std::to_string(nb) +
+                                     " rows: the plan holds scratch for " +
+                                     std::to_string(p.fftsplit_rows));
+    int ept;
+    if (fft_class_shape(p, 2, ept) != kSplitTPB || p.fftsplit_sublen > kSplitSubTPB * 8)
+        return fail(MFWF_EINVAL, "split ring class shape");
+    return MFWF_OK;
+}
+
+static size_t split_sub_lds(const Plan &p) {
+    return sizeof(double2) * ((size_t)fft_area(p.fftsplit_sublen, kSplitSubTPB) + 64 + p.fft_ntwhi);
+}
+
+template <bool FROM_MAP>
+static int split_sub(const Plan &p, const double *maps, int nb) {
+    const int cnt = p.fft_class_count[2];
+    hipLaunchKernelGGL((k_fft_split_sub<kSplitSubTPB, 8, FROM_MAP>), dim3(nb, cnt, 4),
+                       dim3(kSplitSubTPB), split_sub_lds(p), p.stream, maps, p.d_fftsplit,
+                       p.fftsplit_stride, fft_area(p.fftsplit_sublen, kSplitSubTPB), p.d_pfft,
+                       p.d_plist + p.fft_class_off[2], p.d_twlo, p.d_twhi, p.fft_ntwhi, p.fftmax,
+                       p.d_chirp, p.d_bhat, p.npix);
+    MFWF_HIP(hipGetLastError());
+    return MFWF_OK;
+}
+
+static int fwd_split(const Plan &p, const double *maps, double2 *out, int nb) {
+    MFWF_TRY(split_check(p, nb));
+    MFWF_TRY(split_sub<true>(p, maps, nb));
+    hipLaunchKernelGGL((k_fft_fwd_split_combine<kSplitTPB, 8, double2>),
+                       dim3(nb, p.fft_class_count[2]), dim3(kSplitTPB), fft_class_lds(p, 2),
+                       p.stream, out, p.d_fftsplit, p.fftsplit_stride, MFWF_FFT_ARGS(2, p.nm));
+    MFWF_HIP(hipGetLastError());
+    return MFWF_OK;
+}
+
+static int inv_split(const Plan &p, const double2 *in, double *maps, int nb) {
+    MFWF_TRY(split_check(p, nb));
+    hipLaunchKernelGGL((k_fft_inv_split_fold<kSplitTPB, 8, double2>),
+                       dim3(nb, p.fft_class_count[2]), dim3(kSplitTPB), fft_class_lds(p, 2),
+                       p.stream, in, p.d_fftsplit, p.fftsplit_stride, MFWF_FFT_ARGS(2, p.nm));
+    MFWF_HIP(hipGetLastError());
+    MFWF_TRY(split_sub<false>(p, nullptr, nb));
+    hipLaunchKernelGGL((k_fft_inv_split_combine<256>), dim3(nb, p.fft_class_count[2]), dim3(256),
+                       0, p.stream, maps, p.d_fftsplit, p.fftsplit_stride, p.d_pfft,
+                       p.d_plist + p.fft_class_off[2], p.npix);
+    MFWF_HIP(hipGetLastError());
+    return MFWF_OK;
+}
+
 template <typename OutT, bool PIX>
 static int fwd_classes(const Plan &p, const double *maps, const double *rho, double lam,
                        OutT *out, int nb) {
+    if (p.fft_class_count[2] > 0) {
+        if constexpr (PIX || sizeof(OutT) != sizeof(double2)) {
+            return fail(MFWF_EINVAL, "split ring transforms run on FP64 rows only");
+        } else {
+            MFWF_TRY(fwd_split(p, maps, out, nb));
+        }
+    }
     for (int c = 1; c >= 0; c--) {  // long transforms first
         const int cnt = p.fft_class_count[c];
         if (cnt == 0) continue;
@@ -480,6 +671,13 @@ static int fwd_classes(const Plan &p, const double *maps, const double *rho, dou
 
 template <typename InT>
 static int inv_classes(const Plan &p, const InT *in, double *maps, int nb) {
+    if (p.fft_class_count[2] > 0) {
+        if constexpr (sizeof(InT) != sizeof(double2)) {
+            return fail(MFWF_EINVAL, "split ring transforms run on FP64 rows only");
+        } else {
+            MFWF_TRY(inv_split(p, in, maps, nb));
+        }
+    }
     for (int c = 1; c >= 0; c--) {
         const int cnt = p.fft_class_count[c];
         if (cnt == 0) continue;
@@ -518,6 +716,7 @@ int launch_fft_inv_f32(const Plan &p, const float2 *phase, double *maps, int nb)
 }
 
 int launch_fft_inv_fwd_cols(const Plan &p, const double *rho, double lam, double *smap, int nb) {
+    if (p.fft_class_count[2] > 0) return fail(MFWF_EINVAL, "split ring transforms run on FP64 rows only");
     for (int c = 1; c >= 0; c--) {
         const int cnt = p.fft_class_count[c];
         if (cnt == 0) continue;
@@ -583,6 +782,12 @@ int fft_set_lds_limit(size_t bytes) {
     MFWF_TRY(inv_lds<double2>((int)bytes));
     MFWF_TRY(inv_lds<float2>((int)bytes));
     MFWF_TRY(inv_fwd_lds((int)bytes));
+    const void *split_fns[] = {(const void *)k_fft_split_sub<kSplitSubTPB, 8, true>,
+                               (const void *)k_fft_split_sub<kSplitSubTPB, 8, false>,
+                               (const void *)k_fft_fwd_split_combine<kSplitTPB, 8, double2>,
+                               (const void *)k_fft_inv_split_fold<kSplitTPB, 8, double2>};
+    for (const void *f : split_fns)
+        MFWF_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     return MFWF_OK;
 }
 
