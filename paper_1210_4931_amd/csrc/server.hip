@@ -136,8 +136,20 @@ static size_t estimate_pool_bytes(int nside, int lmax, int dtype, int B) {
         b += 2 * 4.0 * nalm * 2 * Bp;                            // coefficients in columns
     } else {
         b += 16.0 * B * nm * nring + 16.0 * groups * B * nalm;
+        if (nside > 1024) b += 64.0 * B * nside * nside;  // split ring scratch
     }
     return (size_t)(1.1 * b) + (64u << 20);
+}
+
+// the plan shapes a pool can take: FP64 up to nside 2048, the FP32 form up to 1024
+static int check_shape(int nside, int lmax, int dtype) {
+    if (nside < 1 || nside > 2048 || (nside & (nside - 1)) != 0)
+        return fail(MFWF_EINVAL, "nside must be a power of two in [1, 2048]");
+    if (lmax < 1 || lmax > 4 * nside) return fail(MFWF_EINVAL, "lmax must be in [1, 4 nside]");
+    if (dtype != MFWF_F64 && dtype != MFWF_F32) return fail(MFWF_EINVAL, "bad dtype");
+    if (dtype == MFWF_F32 && nside > 1024)
+        return fail(MFWF_EINVAL, "the batched FP32 form supports nside <= 1024");
+    return MFWF_OK;
 }
 
 }  // namespace mfwf
@@ -486,10 +498,7 @@ extern "C" {
 
 int mfwf_server_pool_bytes(int nside, int lmax, int dtype, int slots, double *bytes) {
     if (!bytes) return fail(MFWF_EINVAL, "bytes is NULL");
-    if (nside < 1 || nside > 1024 || (nside & (nside - 1)) != 0)
-        return fail(MFWF_EINVAL, "nside must be a power of two in [1, 1024]");
-    if (lmax < 1 || lmax > 4 * nside) return fail(MFWF_EINVAL, "lmax must be in [1, 4 nside]");
-    if (dtype != MFWF_F64 && dtype != MFWF_F32) return fail(MFWF_EINVAL, "bad dtype");
+    MFWF_TRY(check_shape(nside, lmax, dtype));
     if (slots < 1 || slots > 512) return fail(MFWF_EINVAL, "slots must be in [1, 512]");
     *bytes = (double)estimate_pool_bytes(nside, lmax, dtype, slots);
     return MFWF_OK;
@@ -521,10 +530,7 @@ int mfwf_server_create(int slots, double hbm_budget_gb, mfwf_server *out) {
 
 int mfwf_server_submit(mfwf_server s, const mfwf_request *r, uint64_t *id) {
     if (!s || !r || !id) return fail(MFWF_EINVAL, "NULL argument");
-    if (r->nside < 1 || r->nside > 1024 || (r->nside & (r->nside - 1)))
-        return fail(MFWF_EINVAL, "nside must be a power of two in [1, 1024]");
-    if (r->lmax < 1 || r->lmax > 4 * r->nside) return fail(MFWF_EINVAL, "lmax must be in [1, 4 nside]");
-    if (r->dtype != MFWF_F64 && r->dtype != MFWF_F32) return fail(MFWF_EINVAL, "bad dtype");
+    MFWF_TRY(check_shape(r->nside, r->lmax, r->dtype));
     if (r->iters < 1) return fail(MFWF_EINVAL, "iters must be >= 1");
     if (!(r->lambda >= 1.0) || std::isinf(r->lambda)) return fail(MFWF_EINVAL, "lambda must be finite and >= 1");
     if (!r->cl || !r->ninv || !r->data) return fail(MFWF_EINVAL, "NULL array");

@@ -124,6 +124,30 @@ def test_pools_evicted_to_fit_the_budget(mf):
     assert st["pools_evicted"] >= 1 and st["completed"] == 4
 
 
+def test_served_nside2048_request_equals_standalone(mf):
+    """A 2048 / 4096 request (FP64, split ring transforms) next to a small one: bitwise the
+    standalone solve."""
+    r = W.serve_request(3, nsides=(2048,))
+    assert r.dtype == "f64"
+    z, _ = W.pixel_centres(r.nside)
+    d = np.sqrt(r.noise_var) * r.noise_white + 80.0 * z
+    ninv = 1.0 / r.noise_var
+    small = W.serve_request(5, nsides=(16,))
+    ds, ninvs = _inputs(small)
+    srv = mf.Server(slots=2, hbm_gb=120.0)
+    h_big = srv.submit(r.nside, r.lmax, r.cl, dev(ninv), dev(d), mask=dev(r.mask, torch.uint8),
+                       dtype="f64", iters=3)
+    h_small = srv.submit(small.nside, small.lmax, small.cl, dev(ninvs), dev(ds),
+                         mask=dev(small.mask, torch.uint8), dtype=small.dtype, iters=20)
+    srv.wait(h_big[0])
+    srv.wait(h_small[0])
+    srv.close()
+    a_ref, m_ref = _standalone(mf, r, d, ninv, 3)
+    assert torch.equal(h_big[1], a_ref) and torch.equal(h_big[2], m_ref)
+    a_ref, m_ref = _standalone(mf, small, ds, ninvs, 20)
+    assert torch.equal(h_small[1], a_ref) and torch.equal(h_small[2], m_ref)
+
+
 def test_bad_requests_rejected_at_submission(mf):
     from paper_1210_4931_amd.mfwf import MFWFError
     srv = mf.Server(slots=2, hbm_gb=10.0)
@@ -137,4 +161,8 @@ def test_bad_requests_rejected_at_submission(mf):
         srv.submit(r.nside, r.lmax, r.cl, dev(bad), dev(d))
     with pytest.raises(MFWFError):
         srv.submit(r.nside, r.lmax, r.cl, dev(ninv), dev(d), iters=0)
+    with pytest.raises(MFWFError, match="status -1"):  # the FP32 form stops at nside 1024
+        srv.submit(2048, 4096, np.ones(4097), torch.ones(12 * 2048 ** 2, dtype=torch.float64,
+                   device="cuda"), torch.zeros(12 * 2048 ** 2, dtype=torch.float64, device="cuda"),
+                   dtype="f32")
     srv.close()
