@@ -1,6 +1,7 @@
 """Run each kernel of one messenger iteration a few times (for hardware-counter profiles).
 
     python -m paper_1210_4931_amd.kernel_probe --nside 512 --lmax 1024 --form f64 --maps 1
+    python -m paper_1210_4931_amd.kernel_probe --nside 2048 --lmax 4096 --solve-iters 20
 
 Builds the nside/lmax temperature workload, sets the covariances, runs two solve iterations,
 then launches every stage of one iteration `--reps` times through mfwf_time_kernels.  With
@@ -25,6 +26,8 @@ def main():
     ap.add_argument("--maps", type=int, default=1)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--copy", action="store_true")
+    ap.add_argument("--solve-iters", type=int, default=0,
+                    help="also time a solve of this many iterations (wall clock, graphs on)")
     args = ap.parse_args()
 
     import torch
@@ -45,8 +48,17 @@ def main():
         for _ in range(3):
             b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"kernel_ms": dict(zip(["pixel_update", "fft_fwd", "leg_analysis",
-                                              "harmonic", "leg_synth", "fft_inv"], ms))}))
+    out = {"kernel_ms": dict(zip(["pixel_update", "fft_fwd", "leg_analysis", "harmonic",
+                                  "leg_synth", "fft_inv"], ms))}
+    if args.solve_iters > 0:
+        import time
+        plan.solve(d, iters=args.solve_iters)  # warm: graph capture, caches
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.solve(d, iters=args.solve_iters)
+        torch.cuda.synchronize()
+        out["solve_ms_per_iter"] = 1e3 * (time.perf_counter() - t0) / args.solve_iters
+    print(json.dumps(out))
 
 
 if __name__ == "__main__":
