@@ -171,6 +171,39 @@ def config2(seed: int = 0, nside: int = 512, lmax: int = 1024, lscale: float = 8
                                np.sqrt(cl[ls]) * h, g, 900.0 / hits, mask)
 
 
+def config4(seed: int = 0, nside: int = 256, lmax: int = 512, lscale: float = 800.0,
+            ndisc: int = 100, band_z: float = 0.15, parent_nside: int = 512,
+            parent_lmax: int = 1024) -> TemperatureWorkload:
+    """Downgraded large problem (nside 256, lmax 512): the mask of config 2 (the same disc
+    centres, drawn exactly as config 2 draws them at the parent resolution, and the same band)
+    evaluated at nside-256 pixel centres; M = 4 hits / 30^2, the parent pixel's inverse
+    variance as the sum over its 4 children, hits from the scan law at the nside-256 centres
+    with a jitter of their own; C_l as config 2.  The signal and noise of this workload are
+    those of config4_draws(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    white_alm(rng, parent_lmax)                  # the parent's signal and noise draws,
+    rng.standard_normal(12 * parent_nside ** 2)  # consumed so that the discs match
+    centres = _unit_vectors(rng, ndisc)
+    xi = rng.uniform(-1.0, 1.0, 12 * nside * nside)
+    z, phi = pixel_centres(nside)
+    mask = disc_mask(z, phi, centres, math.radians(3.0), band_z)
+    hits = scan_hits(z, xi)
+    cl = cl_damped(lmax, lscale)
+    h, g = config4_draws(seed, nside, lmax)
+    ls, _ = alm_l_m(lmax)
+    return TemperatureWorkload(f"nside{nside}_lmax{lmax}_T_downgraded", nside, lmax, cl,
+                               np.sqrt(cl[ls]) * h, g, 900.0 / (4.0 * hits), mask)
+
+
+def config4_draws(seed: int, nside: int = 256, lmax: int = 512):
+    """Signal (unit-white harmonic) and noise (unit-white pixel) draws of one Wiener-filter
+    data set of the downgraded workload, from seed + 2^20 (apart from the mask's stream)."""
+    rng = np.random.Generator(np.random.PCG64(seed + (1 << 20)))
+    h = white_alm(rng, lmax)
+    g = rng.standard_normal(12 * nside * nside)
+    return h, g
+
+
 def fluctuation_draws(seed: int, nside: int, lmax: int):
     """White-noise draws for one constrained-realisation source (Eq. 9): g1 per pixel and a
     unit-white harmonic draw h (real basis, complex packing)."""

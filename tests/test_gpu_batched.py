@@ -190,3 +190,45 @@ def test_time_kernels_stages_and_state(mf):
     b1 = p64.solve(ds[:1], iters=12)[0]
     assert all(v > 0.0 for v in p64.time_kernels(1, 3))
     assert torch.equal(p64.solve(ds[:1], iters=12)[0], b1)
+
+
+def test_config4_downgraded_wf_and_cr_batch_300_iterations(mf):
+    """nside 256, lmax 512, 64 maps in one batch: 32 Wiener-filter data sets (seeds 0-31)
+    and 32 fluctuation sources (seeds 32-63), 300 iterations of the FP32 form.  Every map
+    against the FP64 path on the same sources (the FP64 path is pinned to the oracle), the
+    fluctuation source against the oracle's, and one map of each kind against the oracle
+    after two iterations."""
+    nside, lmax, B = 256, 512, 64
+    w = W.config4(0)
+    M = w.mask / w.noise_var
+    ninv, mask = dev(1.0 / w.noise_var), dev(w.mask, torch.uint8)
+    p64 = mf.Plan(nside, lmax, max_batch=B)
+    p64.set_covariances(w.cl, ninv, mask)
+    ls, _ = W.alm_l_m(lmax)
+    draws_wf = [W.config4_draws(b) for b in range(32)]
+    sig = p64.sht_inv(dev(np.stack([np.sqrt(w.cl[ls]) * h for h, _ in draws_wf]),
+                          torch.complex128)).cpu().numpy()
+    d = sig + np.sqrt(w.noise_var) * np.stack([g for _, g in draws_wf])
+    draws_cr = [W.fluctuation_draws(32 + k, nside, lmax) for k in range(32)]
+    rho_cr = p64.fluctuation_rhs(dev(np.stack([g for g, _ in draws_cr])),
+                                 dev(np.stack([h for _, h in draws_cr]), torch.complex128))
+    g1, h = draws_cr[31]
+    assert rel(rho_cr[31].cpu().numpy(), oracle.fluct_rho(nside, lmax, w.cl, M, g1, h)) < 1e-12
+    rho = torch.cat([dev(M[None] * d), rho_cr], 0)
+    ref_alm, ref_map, _ = p64.solve(rho, iters=300, source_is_rho=True)
+    del p64
+    p32 = mf.Plan(nside, lmax, max_batch=B, dtype="f32")
+    p32.set_covariances(w.cl, ninv, mask)
+    s_alm, s_map, _ = p32.solve(rho, iters=300, source_is_rho=True)
+    sa, sm = s_alm.cpu().numpy(), s_map.cpu().numpy()
+    ra, rm = ref_alm.cpu().numpy(), ref_map.cpu().numpy()
+    errs = [max(rel_alm(sa[b], ra[b], lmax), rel(sm[b], rm[b])) for b in range(B)]
+    print("FP32 form vs FP64 after 300 iterations, worst WF / CR map:", max(errs[:32]),
+          max(errs[32:]))
+    assert max(errs) < TOL, (int(np.argmax(errs)), max(errs))
+    a2, m2, _ = p32.solve(rho[[0, 63]], iters=2, source_is_rho=True)
+    rho_np = rho[[0, 63]].cpu().numpy()
+    for k in range(2):
+        oa, om = oracle.solve(nside, lmax, w.cl, M, rho_np[k], niter=2)
+        assert rel_alm(a2[k].cpu().numpy(), oa, lmax) < TOL
+        assert rel(m2[k].cpu().numpy(), om) < TOL
