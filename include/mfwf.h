@@ -65,10 +65,10 @@ typedef enum {
 
 /*
  * Create a plan for HEALPix resolution nside (power of two, 1..2048; 1..1024 for MFWF_F32)
- * and band limit lmax (1..4*nside).  spin: 0 = temperature only, 2 = temperature and polarization (T, Q, U
- * maps, T, E, B coefficients, 3x3 noise and signal blocks).  max_batch (>= 1):
- * largest number of
- * maps one call processes at once (larger calls are split).  hip_stream: a hipStream_t
+ * and band limit lmax (1..4*nside).  spin: 0 = temperature only, 2 = temperature and
+ * polarization (T, Q, U maps, T, E, B coefficients, 3x3 noise and signal blocks).
+ * max_batch (>= 1): largest number of maps one call processes at once (larger calls are
+ * split).  hip_stream: a hipStream_t
  * or NULL for the null stream.  The plan precomputes the ring geometry (HEALPix,
  * Gorski et al. 2005), the Legendre recurrence coefficients and, for every (m, ring
  * pair), the first l at which the normalised associated Legendre function exceeds 2^-100
@@ -357,7 +357,8 @@ int mfwf_server_create(int slots, double hbm_budget_gb, mfwf_server *out);
  * contents when this is called and stay valid until mfwf_server_wait returns for the
  * request (they are read when it is admitted and written when it retires).  ninv * mask
  * is checked here: MFWF_ENAN (negative or non-finite) or MFWF_ENOCOV (no observed pixel);
- * MFWF_EINVAL for bad sizes or options. */
+ * MFWF_EINVAL for bad sizes or options (nside a power of two up to 2048, up to 1024 for
+ * MFWF_F32 as in mfwf_plan_create). */
 int mfwf_server_submit(mfwf_server s, const mfwf_request *req, uint64_t *id);
 
 /* *done = 1 once the request's results are in the caller's buffers. */
