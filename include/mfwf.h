@@ -350,7 +350,11 @@ typedef struct {
 int mfwf_server_pool_bytes(int nside, int lmax, int dtype, int slots, double *bytes);
 
 /* Start a server on the current device with `slots` map slots per pool and a device
- * memory budget (GB) for its pools.  Errors: MFWF_EINVAL, MFWF_ENOMEM, MFWF_EDEVICE. */
+ * memory budget (GB) for its pools.  A shape whose pool would take more than half the
+ * budget gets fewer slots: the first of slots, slots / 2, slots / 4, ..., 1 whose
+ * mfwf_server_pool_bytes fits half the budget (at least one slot, refused with
+ * MFWF_ENOMEM at submission if one slot exceeds the whole budget).
+ * Errors: MFWF_EINVAL, MFWF_ENOMEM, MFWF_EDEVICE. */
 int mfwf_server_create(int slots, double hbm_budget_gb, mfwf_server *out);
 
 /* Queue one request; *id receives its handle.  The device arrays must hold their final

@@ -82,6 +82,7 @@ struct Pool {
     double weight = 0.0;             // static cost guess used to balance pools over lanes
     double vtime = 0.0;              // GPU milliseconds charged to this pool (fair queueing)
     std::map<int, double> cost_ms;   // measured iteration time by slot count (moving average)
+    int nslots = 0;                  // map slots of this pool (the server's, or fewer: below)
 
     ~Pool() {
         // iterations and result copies may still be in flight on the lane's stream, which the
@@ -298,7 +299,12 @@ static void reap_lane(mfwf_server s, Lane &L) {
 static Pool *find_or_create_pool(mfwf_server s, const PoolKey &key, std::string &err, int &status) {
     for (auto &P : s->pools)
         if (P->key == key) return P.get();
-    const size_t need = estimate_pool_bytes(key.nside, key.lmax, key.dtype, s->slots);
+    // slots: the server's count, halved while the pool would take more than half the budget
+    // (large shapes, e.g. FP64 at nside 2048, whose Legendre partial sums grow with the slots)
+    int nslots = s->slots;
+    while (nslots > 1 && estimate_pool_bytes(key.nside, key.lmax, key.dtype, nslots) > s->budget / 2)
+        nslots /= 2;
+    const size_t need = estimate_pool_bytes(key.nside, key.lmax, key.dtype, nslots);
     if (need > s->budget) {
         status = MFWF_ENOMEM;
         err = "a pool of this shape exceeds the server's HBM budget";
@@ -333,14 +339,15 @@ static Pool *find_or_create_pool(mfwf_server s, const PoolKey &key, std::string 
     hipStream_t st = s->lanes[P->lane].stream;
     P->plan.stream = st;
     P->plan_ok = true;  // free whatever a failed creation allocated
-    status = plan_create(key.nside, key.lmax, 0, key.dtype, s->slots, st, true, P->plan);
+    P->nslots = nslots;
+    status = plan_create(key.nside, key.lmax, 0, key.dtype, nslots, st, true, P->plan);
     if (status == MFWF_OK) status = plan_set_cl(P->plan, key.cl.data());
     if (status != MFWF_OK) {
         err = std::string("pool plan: ") + mfwf_last_error();
         return nullptr;
     }
-    P->slot.assign(s->slots, nullptr);
-    P->done_iters.assign(s->slots, 0);
+    P->slot.assign(nslots, nullptr);
+    P->done_iters.assign(nslots, 0);
     P->bytes = need;
     P->last_used = Clock::now();
     s->used += need;
@@ -395,7 +402,7 @@ static void worker_main(mfwf_server s) {
                 continue;
             }
             int b = -1;
-            for (int k = 0; k < s->slots && b < 0; k++)
+            for (int k = 0; k < P->nslots && b < 0; k++)
                 if (!P->slot[k]) b = k;
             if (b < 0) {
                 ++it;
@@ -420,7 +427,7 @@ static void worker_main(mfwf_server s) {
                 if (!best) break;
                 Pool &P = *best;
                 int nb = 0;
-                for (int k = 0; k < s->slots; k++)
+                for (int k = 0; k < P.nslots; k++)
                     if (P.slot[k]) nb = k + 1;
                 hipGraphExec_t exec = nullptr;
                 int st = pool_graph(P, nb, exec);

@@ -126,7 +126,10 @@ def test_pools_evicted_to_fit_the_budget(mf):
 
 def test_served_nside2048_request_equals_standalone(mf):
     """A 2048 / 4096 request (FP64, split ring transforms) next to a small one: bitwise the
-    standalone solve."""
+    standalone solve.  16 slots per pool would put the 2048 pool at about 200 GB, so the
+    server gives that shape fewer slots (2, the first halving that fits half of 100 GB)."""
+    from paper_1210_4931_amd.mfwf import Server
+    assert Server.pool_bytes(2048, 4096, "f64", 4) > 50e9 >= Server.pool_bytes(2048, 4096, "f64", 2)
     r = W.serve_request(3, nsides=(2048,))
     assert r.dtype == "f64"
     z, _ = W.pixel_centres(r.nside)
@@ -134,7 +137,7 @@ def test_served_nside2048_request_equals_standalone(mf):
     ninv = 1.0 / r.noise_var
     small = W.serve_request(5, nsides=(16,))
     ds, ninvs = _inputs(small)
-    srv = mf.Server(slots=2, hbm_gb=120.0)
+    srv = mf.Server(slots=16, hbm_gb=100.0)
     h_big = srv.submit(r.nside, r.lmax, r.cl, dev(ninv), dev(d), mask=dev(r.mask, torch.uint8),
                        dtype="f64", iters=3)
     h_small = srv.submit(small.nside, small.lmax, small.cl, dev(ninvs), dev(ds),
