@@ -1406,6 +1406,9 @@ static int cooled_diag(Plan &q, const double *rho, int nb, double lam, std::vect
     return MFWF_OK;
 }
 
+// a rise of chi^2 at fixed lambda that no quadrature gap explains, in sigma_chi2
+static constexpr double kUnstableSigmas = 10.0;
+
 struct CoolOpts {
     int l0, step, margin, nchk, max_iters;
     double plateau, final_tol;
@@ -1468,6 +1471,12 @@ static int cooled_chunk(mfwf_plan plan, const double *data, int nb, double *s_al
         StageGraph sg;
         bool captured = false, have_prev = false, plateau = false;
         long its = 0;
+        // lowest chi^2 of this stage per map, and the last two changes between checks.  At
+        // fixed lambda the iteration lowers chi^2 up to the quadrature gap of the
+        // pixelisation; on coarse grids it can settle well above a minimum it passed through,
+        // rising by shrinking steps.  Rising by growing steps far above that minimum means an
+        // eigenvalue above 1: an unstable iteration (lmax too high for the nside's quadrature).
+        std::vector<double> smin(nb, INFINITY), d1(nb, 0.0), d2(nb, 0.0);
         while (total < o.max_iters) {
             const long run = std::min<long>(o.nchk, o.max_iters - total);
             long plain = run - 1;
@@ -1494,6 +1503,16 @@ static int cooled_chunk(mfwf_plan plan, const double *data, int nb, double *s_al
                 if (!std::isfinite(chi))
                     return fail(MFWF_ENAN, "chi^2 is not finite: the iteration diverged (lmax above "
                                            "what the nside's quadrature supports?)");
+                const double dc = have_prev ? chi - prev[b] : 0.0;
+                if (have_prev && chi > smin[b] + kUnstableSigmas * sigma && dc > d1[b] &&
+                    d1[b] > d2[b] && d2[b] > 0.0)
+                    return fail(MFWF_ENAN, "chi^2 at fixed lambda grows by increasing steps, more "
+                                           "than 10 sigma_chi2 above its minimum in this stage: the "
+                                           "iteration is unstable at this band limit (lmax too high "
+                                           "for the nside's quadrature)");
+                smin[b] = std::min(smin[b], chi);
+                d2[b] = d1[b];
+                d1[b] = dc;
                 if (have_prev) worst = std::max(worst, std::fabs(chi - prev[b]) / (double)run);
                 prev[b] = chi;
             }

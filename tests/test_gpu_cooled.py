@@ -183,6 +183,19 @@ def test_cooled_pol_f32_batch_replay(mf):
         assert rel(s_map.cpu().numpy()[b], ref_map) < 1e-5
 
 
+def test_cooled_pol_unstable_band_limit_reported(mf):
+    """T, Q, U at nside 32 / lmax 64: the plain lambda = 1 iteration is unstable on this grid
+    (the oracle's own chi^2 grows by growing steps after about 225 iterations); the cooled
+    solve stops with MFWF_ENAN once chi^2 stands 10 sigma_chi2 above its stage minimum after
+    growing rises, long before max_iters, instead of iterating into overflow.  (The FP32 and
+    FP64 replays above, on nside 16, settle above a minimum by shrinking rises and finish.)"""
+    from paper_1210_4931_amd.mfwf import MFWFError
+    nside, lmax = 32, 64
+    plan, w, d, M6, rho_of = _pol_problem(mf, nside, lmax, 0, "f64", 1)
+    with pytest.raises(MFWFError, match="unstable"):
+        plan.solve_cooled(dev(d[None]), l_iter0=8, l_margin=16, max_iters=20000)
+
+
 def test_f32_solve_kinds_share_a_plan(mf):
     """The batched FP32 plan runs chained iterations in plain and cooled solves; a later solve
     of any kind on the same plan starts from its own state: every result equals the one of a

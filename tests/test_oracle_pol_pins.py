@@ -415,3 +415,26 @@ def test_pol_staged_reduces_to_temperature_staging():
     at, mt = oracle.solve_staged(nside, lmax, cl4[0], MT, rho[0], stages)
     assert rel(a[0], at) < 1e-12 and rel(m[0], mt) < 1e-12
     assert np.all(a[1:] == 0) and np.abs(m[1:]).max() == 0.0
+
+
+def test_pol_plain_iteration_unstable_at_lmax_2nside_nside32():
+    """A property of the discretised method, not of an implementation: on the nside 32 grid
+    with lmax = 64 the T, Q, U iteration at lambda = 1 first lowers chi^2, then grows without
+    bound (an eigenvalue of the iteration above 1, from the pixelisation's quadrature; the
+    temperature iteration and T, Q, U on nside 16 / lmax 32 stay stable).  The cooled solve
+    reports such a run instead of iterating on."""
+    nside, lmax, n = 32, 64, 600
+    w = W.config3(0, nside, lmax, ndisc=10, band_z=0.15, nu=10)
+    d = w.data_from_signal_maps(oracle.alm2map_pol(nside, lmax, w.signal_alm))
+    M6 = w.M6()
+    rho = np.einsum("pij,jp->ip", _unpack(M6), d)
+    _, _, dg = oracle.solve_pol(nside, lmax, w.cl4, M6, rho, lam=[1.0] * n, diag=True)
+    chi = dg[:, 0]
+    sigma = math.sqrt(2.0 * 3 * int(w.mask.sum()))
+    k = int(np.argmin(chi))
+    assert 100 < k < 400
+    assert chi[-1] > chi[k] + 10.0 * sigma
+    assert np.all(np.diff(chi[k + 50:]) > 0.0)
+    # by growing steps (an eigenvalue above 1), unlike a run settling above a minimum it
+    # passed through, whose rises shrink
+    assert chi[-1] - chi[-51] > 2.0 * (chi[k + 150] - chi[k + 100]) > 0.0
