@@ -253,9 +253,9 @@ typedef struct {
  * 10 sigma_chi2 above its lowest value in the current stage after three rises between
  * checks, each larger than the one before (at fixed lambda the iteration lowers chi^2 up to
  * the pixelisation's quadrature gap, and may settle above a minimum it passed through by
- * shrinking rises; growing rises mean an unstable iteration: lmax too high for the nside,
- * e.g. T, Q, U at lmax = 2 nside on some grids, whose plain iteration grows after a few
- * hundred to a few thousand iterations). */
+ * shrinking rises; growing rises mean an unstable iteration: lmax too high for the nside
+ * and noise pattern, as at lmax = 2 nside for some problems, whose plain iteration grows
+ * after a few hundred to a few thousand iterations). */
 int mfwf_solve_cooled(mfwf_plan plan, const double *data, int nmaps, double *s_alm_out,
                       double *s_map_out, mfwf_cool_opts *opts, mfwf_solve_info *info);
 

@@ -184,8 +184,9 @@ def test_cooled_pol_f32_batch_replay(mf):
 
 
 def test_cooled_pol_unstable_band_limit_reported(mf):
-    """T, Q, U at nside 32 / lmax 64: the plain lambda = 1 iteration is unstable on this grid
-    (the oracle's own chi^2 grows by growing steps after about 225 iterations); the cooled
+    """T, Q, U at nside 32 / lmax 64: the plain lambda = 1 iteration is unstable for this
+    problem (the oracle's own chi^2 grows by growing steps after about 225 iterations, the
+    temperature part alone as well); the cooled
     solve stops with MFWF_ENAN once chi^2 stands 10 sigma_chi2 above its stage minimum after
     growing rises, long before max_iters, instead of iterating into overflow.  (The FP32 and
     FP64 replays above, on nside 16, settle above a minimum by shrinking rises and finish.)"""

@@ -420,9 +420,10 @@ def test_pol_staged_reduces_to_temperature_staging():
 def test_pol_plain_iteration_unstable_at_lmax_2nside_nside32():
     """A property of the discretised method, not of an implementation: on the nside 32 grid
     with lmax = 64 the T, Q, U iteration at lambda = 1 first lowers chi^2, then grows without
-    bound (an eigenvalue of the iteration above 1, from the pixelisation's quadrature; the
-    temperature iteration and T, Q, U on nside 16 / lmax 32 stay stable).  The cooled solve
-    reports such a run instead of iterating on."""
+    bound (an eigenvalue of the iteration above 1, from the pixelisation's quadrature), and so
+    does the temperature iteration alone with this problem's T noise and mask; T, Q, U on
+    nside 16 / lmax 32 and the temperature workloads stay stable.  The cooled solve reports
+    such a run instead of iterating on."""
     nside, lmax, n = 32, 64, 600
     w = W.config3(0, nside, lmax, ndisc=10, band_z=0.15, nu=10)
     d = w.data_from_signal_maps(oracle.alm2map_pol(nside, lmax, w.signal_alm))
@@ -438,3 +439,9 @@ def test_pol_plain_iteration_unstable_at_lmax_2nside_nside32():
     # by growing steps (an eigenvalue above 1), unlike a run settling above a minimum it
     # passed through, whose rises shrink
     assert chi[-1] - chi[-51] > 2.0 * (chi[k + 150] - chi[k + 100]) > 0.0
+    # not a spin-2 effect: the temperature iteration on the T noise and mask alone
+    MT = M6[:, 0]
+    _, _, dgt = oracle.solve(nside, lmax, w.cl4[0], MT, MT * d[0], lam=[1.0] * n, diag=True)
+    ct = dgt[:, 0]
+    kt = int(np.argmin(ct))
+    assert 100 < kt < 400 and ct[-1] > ct[kt] + 10.0 * math.sqrt(2.0 * int(w.mask.sum()))
