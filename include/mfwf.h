@@ -190,6 +190,12 @@ typedef struct {
     long n_dof;        /* number of observed pixels (chi^2 degrees of freedom)          */
     int n_checks;      /* diagnostic checks made (rows of opts->history filled, up to
                           its capacity)                                                 */
+    double dchi2;      /* change of chi^2 per iteration between the last two checks of
+                          the final stage (negative while chi^2 falls); 0 with fewer
+                          than two checks there, and for mfwf_solve_bounded, whose
+                          lambda changes every iteration                                */
+    double rel_change; /* dnorm / snorm: relative change of the last iteration (0 if
+                          snorm = 0)                                                    */
 } mfwf_solve_info;
 
 /*
@@ -204,6 +210,9 @@ typedef struct {
  * (Eq. 3 multiplied through by N, no inverse of Nbar), then
  *     s_lm = C_l / (C_l + lambda tau Omega) * (A t)_lm     (Eq. 4, T = tau Omega per
  * harmonic dof under A = Omega Y^T), then s = Y s_lm.  Non-convergence is not an error.
+ * Errors: MFWF_ENAN if the source holds a NaN or Inf (data on an observed pixel, or any
+ * entry of a given rho), checked before the first iteration; MFWF_ENOCOV without
+ * covariances; MFWF_EINVAL for bad options.
  * spin 2: input and s_map_out [nmaps][3][npix], s_alm_out [nmaps][3][2*nalm]; the pixel
  * update solves the 3x3 system [I + (lambda - 1) tau M_p] t = lambda tau rho +
  * (I - tau M_p) s per pixel and the harmonic update is s = S_l (S_l + lambda tau Omega I)^-1 a
@@ -292,7 +301,8 @@ typedef struct {
     int trace_rows;      /* capacity of trace in rows                                       */
     int n_iters;         /* out: iterations run                                             */
     int n_b_updates;     /* out: times b was raised                                         */
-    int reached_one;     /* out: 1 if lambda reached 1 (0: max_iters ended the solve)       */
+    int reached_one;     /* out: 1 if the last iteration ran at lambda = 1 (0: max_iters
+                            ended the solve before it)                                      */
 } mfwf_bound_opts;
 
 /* input, outputs and info as in mfwf_solve; opts may be NULL (all defaults).  Errors: as
@@ -367,6 +377,7 @@ int mfwf_server_create(int slots, double hbm_budget_gb, mfwf_server *out);
  * contents when this is called and stay valid until mfwf_server_wait returns for the
  * request (they are read when it is admitted and written when it retires).  ninv * mask
  * is checked here: MFWF_ENAN (negative or non-finite) or MFWF_ENOCOV (no observed pixel);
+ * so is the data: MFWF_ENAN if it holds a NaN or Inf on an observed pixel;
  * MFWF_EINVAL for bad sizes or options (nside a power of two up to 2048, up to 1024 for
  * MFWF_F32 as in mfwf_plan_create). */
 int mfwf_server_submit(mfwf_server s, const mfwf_request *req, uint64_t *id);

@@ -890,6 +890,21 @@ struct StageGraph {
     }
 };
 
+// MFWF_ENAN if the source rho of nb maps holds a non-finite value: a NaN or Inf in the
+// data on an observed pixel (masked pixels have rho = 0 whatever the data), or in a
+// caller's rho.  One pass over rho and a wait for the stream.
+static int check_source_finite(const Plan &p, const double *rho, int nb) {
+    const long n = (long)p.ncomp * p.npix * nb;
+    MFWF_TRY(launch_count_nonfinite(rho, n, p.d_red, p.nred_blocks, p.d_diag, p.stream));
+    double bad = 0.0;
+    MFWF_HIP(hipMemcpyAsync(&bad, p.d_diag, sizeof(double), hipMemcpyDeviceToHost, p.stream));
+    MFWF_HIP(hipStreamSynchronize(p.stream));
+    if (bad > 0.0)
+        return fail(MFWF_ENAN, "the source has " + std::to_string((long)bad) +
+                                   " non-finite values on observed pixels");
+    return MFWF_OK;
+}
+
 static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
                        double *s_map_out, const mfwf_solve_opts &o,
                        const std::vector<double> &lam, const std::vector<int> &its,
@@ -903,6 +918,7 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
             MFWF_TRY(launch_rho_from_data(input, p.d_M, p.d_rho, p.npix, nb, p.stream));
         rho = p.d_rho;
     }
+    MFWF_TRY(check_source_finite(p, rho, nb));
     MFWF_TRY(launch_fill(p.d_smap, nc * p.npix * nb, 0.0, p.stream));
     MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm), 2 * nc * p.nalm * nb, 0.0, p.stream));
     // batched temperature form: iterations chained through the synthesis columns, which
@@ -943,12 +959,16 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
     const double stop_tol = o.dchi2_tol * std::sqrt(2.0 * (double)p.ndof);
     std::vector<double> chi_prev(nb, 0.0);
     long prev_at = -1;       // iteration count at the previous check of the current stage
+    // checks of the current stage for info.dchi2: the previous check's chi^2 parts are kept
+    // in diag[b][6..7] on the device (no host wait)
+    long chk_last = -1, chk_prev = -1;
     bool stopped = false;
     for (size_t s = 0; s < lam.size() && !stopped; s++) {
         long remaining = its[s];
         if (remaining <= 0) continue;
         last_lam = lam[s];
         prev_at = -1;
+        chk_last = chk_prev = -1;
         std::unique_ptr<StageGraph> sg;
         while (remaining > 0) {
             // run up to the next check point: a multiple of n_check, or the last iteration
@@ -966,6 +986,12 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
                 for (long k = 0; k < plain; k++) MFWF_TRY(iteration(p, rho, nb, lam[s], false));
             }
             if (check) {
+                if (chk_last >= 0)  // diag[b][0..1] of the previous check -> diag[b][6..7]
+                    MFWF_HIP(hipMemcpy2DAsync(p.d_diag + 6, 8 * sizeof(double), p.d_diag,
+                                              8 * sizeof(double), 2 * sizeof(double), nb,
+                                              hipMemcpyDeviceToDevice, p.stream));
+                chk_prev = chk_last;
+                chk_last = done + run;
                 MFWF_TRY(iteration(p, rho, nb, lam[s], true));
                 MFWF_TRY(diagnostics(lam[s]));
                 if (stop_tol > 0.0) {
@@ -1026,6 +1052,10 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
             in.tau = p.tau;
             in.n_dof = p.ndof;
             in.n_checks = std::min(rows, o.history ? o.history_rows : rows);
+            in.dchi2 = chk_prev >= 0 ? (dg[8 * b + 0] + dg[8 * b + 1] - dg[8 * b + 6] - dg[8 * b + 7]) /
+                                           (double)(chk_last - chk_prev)
+                                     : 0.0;
+            in.rel_change = in.snorm > 0.0 ? in.dnorm / in.snorm : 0.0;
         }
     }
     return MFWF_OK;
@@ -1424,8 +1454,9 @@ static int cooled_chunk(mfwf_plan plan, const double *data, int nb, double *s_al
     else
         MFWF_TRY(launch_rho_from_data(data, p.d_M, p.d_rho, p.npix, nb, p.stream));
     const double *rho = p.d_rho;
+    MFWF_TRY(check_source_finite(p, rho, nb));
     const double sigma = std::sqrt(2.0 * (double)p.ndof), tomega = p.tau * p.omega;
-    std::vector<double> dg(8L * nb), prev(nb);
+    std::vector<double> dg(8L * nb), prev(nb), last_dchi2(nb, 0.0);
     Plan *cur = nullptr;
     // chained iterations stay within this solve: every plan it used leaves without them
     struct ChainOff {
@@ -1477,6 +1508,7 @@ static int cooled_chunk(mfwf_plan plan, const double *data, int nb, double *s_al
         // rising by shrinking steps.  Rising by growing steps far above that minimum means an
         // eigenvalue above 1: an unstable iteration (lmax too high for the nside's quadrature).
         std::vector<double> smin(nb, INFINITY), d1(nb, 0.0), d2(nb, 0.0);
+        std::fill(last_dchi2.begin(), last_dchi2.end(), 0.0);
         while (total < o.max_iters) {
             const long run = std::min<long>(o.nchk, o.max_iters - total);
             long plain = run - 1;
@@ -1514,6 +1546,7 @@ static int cooled_chunk(mfwf_plan plan, const double *data, int nb, double *s_al
                 d2[b] = d1[b];
                 d1[b] = dc;
                 if (have_prev) worst = std::max(worst, std::fabs(chi - prev[b]) / (double)run);
+                last_dchi2[b] = have_prev ? (chi - prev[b]) / (double)run : 0.0;
                 prev[b] = chi;
             }
             if (have_prev && worst < tol * sigma) {
@@ -1558,6 +1591,8 @@ static int cooled_chunk(mfwf_plan plan, const double *data, int nb, double *s_al
             in.tau = p.tau;
             in.n_dof = p.ndof;
             in.n_checks = 0;
+            in.dchi2 = last_dchi2[b];
+            in.rel_change = in.snorm > 0.0 ? in.dnorm / in.snorm : 0.0;
         }
     }
     return MFWF_OK;
@@ -1650,6 +1685,7 @@ static int bounded_chunk(Plan &p, const double *data, int nb, double *s_alm_out,
     else
         MFWF_TRY(launch_rho_from_data(data, p.d_M, p.d_rho, p.npix, nb, p.stream));
     const double *rho = p.d_rho;
+    MFWF_TRY(check_source_finite(p, rho, nb));
     MFWF_TRY(launch_fill(p.d_smap, nc * p.npix * nb, 0.0, p.stream));
     MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm), 2 * nc * p.nalm * nb, 0.0, p.stream));
     if (p.dtype == MFWF_F32) {
@@ -1667,8 +1703,10 @@ static int bounded_chunk(Plan &p, const double *data, int nb, double *s_alm_out,
     reached_one = false;
     trace.clear();
     int stall = 0;
+    double last_lam = lam;  // lambda of the last iteration run
     for (int it = 0; it < o.max_iters; it++) {
         MFWF_TRY(iteration(p, rho, nb, lam, true));
+        last_lam = lam;
         // harmonic part of chi^2 at the new iterate
         if (p.spin == 2)
             MFWF_TRY(launch_harm_diag_pol(p, p.d_salm, p.d_salm_prev, nb, p.d_red, p.d_diag));
@@ -1681,7 +1719,10 @@ static int bounded_chunk(Plan &p, const double *data, int nb, double *s_alm_out,
         double G, dG;
         MFWF_TRY(ev(lam, G, dG));
         trace.insert(trace.end(), {lam, ev.H[0] + ev.P[0], ev.b[0]});
-        if (lam == 1.0) break;  // the last iteration ran at lambda = 1
+        if (lam == 1.0) {  // the last iteration ran at lambda = 1
+            reached_one = true;
+            break;
+        }
         // the next lambda: the smallest one with chi^2(lambda, x) <= b; it can exceed the
         // current one when this iteration raised chi^2(lambda, x) above b, which the
         // pixelised sphere allows by a margin of its quadrature gap (the iteration's fixed
@@ -1705,13 +1746,10 @@ static int bounded_chunk(Plan &p, const double *data, int nb, double *s_alm_out,
         } else {
             stall = 0;
         }
-        if (nl <= 1.0 + o.lam_tol) {
-            nl = 1.0;
-            reached_one = true;
-        }
+        if (nl <= 1.0 + o.lam_tol) nl = 1.0;
         lam = nl;
     }
-    MFWF_TRY(cooled_diag(p, rho, nb, lam, dg));
+    MFWF_TRY(cooled_diag(p, rho, nb, last_lam, dg));
     if (s_alm_out)
         MFWF_HIP(hipMemcpyAsync(s_alm_out, p.d_salm, sizeof(double2) * nc * p.nalm * nb,
                                 hipMemcpyDeviceToDevice, p.stream));
@@ -1722,7 +1760,7 @@ static int bounded_chunk(Plan &p, const double *data, int nb, double *s_alm_out,
         for (int k = 0; k < nb; k++) {
             mfwf_solve_info &in = info[k];
             in.iters_done = (int)(trace.size() / 3);
-            in.lambda = lam;
+            in.lambda = last_lam;
             in.chi2 = dg[8 * k + 0] + dg[8 * k + 1];
             in.chi2_harm = dg[8 * k + 1];
             in.dnorm = std::sqrt(dg[8 * k + 2]);
@@ -1730,6 +1768,8 @@ static int bounded_chunk(Plan &p, const double *data, int nb, double *s_alm_out,
             in.tau = p.tau;
             in.n_dof = p.ndof;
             in.n_checks = 0;
+            in.dchi2 = 0.0;
+            in.rel_change = in.snorm > 0.0 ? in.dnorm / in.snorm : 0.0;
         }
     }
     return MFWF_OK;

@@ -160,6 +160,9 @@ int launch_reduce_max_count(const double *M, long npix, double *partial, int nbl
                             double *out2, hipStream_t s);
 int launch_rho_from_data(const double *d, const double *M, double *rho, long npix, int nb,
                          hipStream_t s);
+// out[0] = number of non-finite entries of x[0..n) (partial: nblocks doubles)
+int launch_count_nonfinite(const double *x, long n, double *partial, int nblocks, double *out,
+                           hipStream_t s);
 int launch_pixel_update(const double *rho, const double *M, const double *smap, double *t,
                         long npix, int nb, double lam, double tau, hipStream_t s,
                         long mstride = 0, const double *tau_b = nullptr);

@@ -111,6 +111,39 @@ int launch_reduce_max_count(const double *M, long npix, double *partial, int nbl
     return MFWF_OK;
 }
 
+// Non-finite entries of x[0..n) per block (a solve's source rho: data on masked pixels has
+// already been dropped there, so only observed pixels count), then their total.
+__global__ void k_count_nonfinite(const double *__restrict__ x, long n, double *__restrict__ partial) {
+    __shared__ double sh[kThreads];
+    double bad = 0.0;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+         i += (long)gridDim.x * blockDim.x)
+        bad += isfinite(x[i]) ? 0.0 : 1.0;
+    sh[threadIdx.x] = bad;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void k_sum_final(const double *__restrict__ partial, int nblocks, double *__restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; b++) s += partial[b];
+    out[0] = s;
+}
+
+int launch_count_nonfinite(const double *x, long n, double *partial, int nblocks, double *out,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_count_nonfinite, dim3(nblocks), dim3(kThreads), 0, s, x, n, partial);
+    MFWF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, s, partial, nblocks, out);
+    MFWF_HIP(hipGetLastError());
+    return MFWF_OK;
+}
+
 __global__ void k_rho_from_data(const double *__restrict__ d, const double *__restrict__ M,
                                 double *__restrict__ rho, long npix, long n) {
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;

@@ -554,16 +554,22 @@ int mfwf_server_submit(mfwf_server s, const mfwf_request *r, uint64_t *id) {
             if (s->vscratch) (void)hipFree(s->vscratch);
             s->vscratch = nullptr;
             s->vcap = 0;
-            if (hipMalloc((void **)&s->vscratch, sizeof(double) * npix) != hipSuccess)
+            if (hipMalloc((void **)&s->vscratch, 2 * sizeof(double) * npix) != hipSuccess)
                 return fail(MFWF_ENOMEM, "validation scratch");
             s->vcap = npix;
         }
         MFWF_TRY(launch_mask_product(r->ninv, r->mask, s->vscratch, npix, s->vstream));
         MFWF_TRY(launch_reduce_max_count(s->vscratch, npix, s->vpart, 1024, s->vout, s->vstream));
-        double st[3];
+        // the source M d behind M (masked pixels give 0 whatever d holds there), and its
+        // non-finite entries: NaN or Inf data on an observed pixel
+        double *rho = s->vscratch + npix;
+        MFWF_TRY(launch_rho_from_data(r->data, s->vscratch, rho, npix, 1, s->vstream));
+        MFWF_TRY(launch_count_nonfinite(rho, npix, s->vpart, 1024, s->vout + 3, s->vstream));
+        double st[4];
         MFWF_HIP(hipMemcpyAsync(st, s->vout, sizeof(st), hipMemcpyDeviceToHost, s->vstream));
         MFWF_HIP(hipStreamSynchronize(s->vstream));
         if (st[2] > 0.0) return fail(MFWF_ENAN, "inverse noise has negative or non-finite entries");
+        if (st[3] > 0.0) return fail(MFWF_ENAN, "data has non-finite values on observed pixels");
         if (!(st[0] > 0.0)) return fail(MFWF_ENOCOV, "no observed pixel: tau undefined");
         q->tau = 1.0 / st[0];
     }

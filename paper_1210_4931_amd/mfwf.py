@@ -34,7 +34,8 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("iters_done", ctypes.c_int), ("lam", ctypes.c_double), ("chi2", ctypes.c_double),
                 ("chi2_harm", ctypes.c_double), ("dnorm", ctypes.c_double),
                 ("snorm", ctypes.c_double), ("tau", ctypes.c_double), ("n_dof", ctypes.c_long),
-                ("n_checks", ctypes.c_int)]
+                ("n_checks", ctypes.c_int), ("dchi2", ctypes.c_double),
+                ("rel_change", ctypes.c_double)]
 
 
 class CoolOpts(ctypes.Structure):
@@ -139,6 +140,13 @@ class Info:
     tau: float
     n_dof: int
     n_checks: int = 0
+    dchi2: float = 0.0
+    rel_change: float = 0.0
+
+
+def _info(i: SolveInfo) -> Info:
+    return Info(i.iters_done, i.lam, i.chi2, i.chi2_harm, i.dnorm, i.snorm, i.tau, i.n_dof,
+                i.n_checks, i.dchi2, i.rel_change)
 
 
 class Plan:
@@ -291,8 +299,7 @@ class Plan:
                                None if s_map is None else s_map.data_ptr(), ctypes.byref(opts),
                                infos))
         self._leave()
-        info = [Info(i.iters_done, i.lam, i.chi2, i.chi2_harm, i.dnorm, i.snorm, i.tau, i.n_dof,
-                     i.n_checks) for i in infos]
+        info = [_info(i) for i in infos]
         if n_check > 0:
             return s_alm, s_map, info, hist[:max(i.n_checks for i in infos)] if n else hist
         return s_alm, s_map, info
@@ -318,8 +325,7 @@ class Plan:
                                       None if s_map is None else s_map.data_ptr(),
                                       ctypes.byref(opts), infos))
         self._leave()
-        info = [Info(i.iters_done, i.lam, i.chi2, i.chi2_harm, i.dnorm, i.snorm, i.tau, i.n_dof,
-                     i.n_checks) for i in infos]
+        info = [_info(i) for i in infos]
         return s_alm, s_map, info, st[:min(opts.n_stages, rows)], bool(opts.converged)
 
     def solve_bounded(self, data: torch.Tensor, m_sigma=0.0, lam_tol=0.0, stall_frac=0.0,
@@ -343,8 +349,7 @@ class Plan:
                                        None if s_map is None else s_map.data_ptr(),
                                        ctypes.byref(opts), infos))
         self._leave()
-        info = [Info(i.iters_done, i.lam, i.chi2, i.chi2_harm, i.dnorm, i.snorm, i.tau, i.n_dof,
-                     i.n_checks) for i in infos]
+        info = [_info(i) for i in infos]
         return (s_alm, s_map, info, tr[:min(opts.n_iters, rows)], opts.n_b_updates,
                 bool(opts.reached_one))
 
