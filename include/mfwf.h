@@ -123,6 +123,16 @@ int mfwf_set_covariances_beam(mfwf_plan plan, const double *cl, int ncl, const d
  * mfwf_set_covariances, MFWF_EINVAL if the templates are degenerate on the observed pixels. */
 int mfwf_remove_templates(mfwf_plan plan, const double *d_raw, double *d_out, int nmaps);
 
+/* For callers that cannot allocate device memory (code under stream capture, serving loops
+ * that forbid hipMalloc): mfwf_remove_templates with no allocation and no use of the plan's
+ * workspaces.  The partial sums, the 4 x 4 solves (done on the device) and a status flag per
+ * map live in one static device array of 467,968 bytes that each device holds for the life
+ * of the process.  At most 64 maps per call (more -> MFWF_EINVAL, nothing launched).  Calls
+ * that overlap on one device (from two streams or threads) race on that array and must be
+ * serialised by the caller.  Same arguments, results and errors as mfwf_remove_templates;
+ * waits for the plan's stream before returning. */
+int mfwf_remove_templates_noalloc(mfwf_plan plan, const double *d_raw, double *d_out, int nmaps);
+
 /*
  * Synthesis map = Y alm for nmaps maps (the inverse transform that closes each
  * iteration, Sect. 2.1).  alm: device [nmaps][2*nalm]; map: device [nmaps][npix]

@@ -524,6 +524,7 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     if (dtype == MFWF_F32 && max_batch > 512) return fail(MFWF_EINVAL, "MFWF_F32 plans take max_batch <= 512");
     std::string devname;
     MFWF_TRY(device_name(devname));
+    MFWF_HIP(hipGetDevice(&p.device));
 
     p.nside = nside;
     p.lmax = lmax;
@@ -1215,6 +1216,15 @@ int mfwf_remove_templates(mfwf_plan plan, const double *d_raw, double *d_out, in
         MFWF_HIP(hipStreamSynchronize(p.stream));
     }
     return MFWF_OK;
+}
+
+int mfwf_remove_templates_noalloc(mfwf_plan plan, const double *d_raw, double *d_out, int nmaps) {
+    if (!plan || nmaps < 0) return fail(MFWF_EINVAL, "bad argument");
+    const Plan &p = plan->p;
+    if (!p.have_cov) return fail(MFWF_ENOCOV, "covariances not set (the mask comes from them)");
+    if (nmaps == 0) return MFWF_OK;
+    if (!d_raw || !d_out) return fail(MFWF_EINVAL, "NULL array");
+    return remove_templates_noalloc(p, d_raw, d_out, nmaps);
 }
 
 int mfwf_sht_inv(mfwf_plan plan, const double *alm, double *map, int nmaps) {

@@ -48,6 +48,7 @@ struct PairFFT {
 // two values (lambda_{l_s - 1, m}, lambda_{l_s, m}); l_s = lmax + 1 if never reached.
 struct Plan {
     int nside, lmax, spin, dtype, max_batch;
+    int device = 0;  // HIP device current when the plan was created
     int ncomp = 1;  // components per map: 1 (T) or 3 (T, Q, U / T, E, B)
     hipStream_t stream;
     long npix;
@@ -256,6 +257,10 @@ int launch_template_sums(const Plan &p, const double *d, int nb, double *partial
 int template_partial_doubles(int nb);
 int launch_template_subtract(const Plan &p, const double *d, double *dout, int nb,
                              const double *coef);
+// the same removal with every intermediate in the library's static device array (no
+// allocation, no plan workspace); at most kNoAllocMaxMaps maps per call
+constexpr int kNoAllocMaxMaps = 64;
+int remove_templates_noalloc(const Plan &p, const double *d_raw, double *d_out, int nmaps);
 
 // harmonic.hip
 enum HarmMode { kHarmWiener = 0, kHarmAnalysis = 1, kHarmInvSqrtC = 2, kHarmCopy = 3 };

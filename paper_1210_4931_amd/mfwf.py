@@ -59,7 +59,7 @@ EXPORTED = ["mfwf_plan_create", "mfwf_plan_destroy", "mfwf_set_covariances", "mf
             "mfwf_plan_work", "mfwf_last_error", "mfwf_server_create", "mfwf_server_submit",
             "mfwf_server_poll", "mfwf_server_wait", "mfwf_server_stats", "mfwf_server_destroy",
             "mfwf_server_pool_bytes", "mfwf_solve_cooled", "mfwf_set_covariances_beam",
-            "mfwf_remove_templates", "mfwf_solve_bounded"]
+            "mfwf_remove_templates", "mfwf_solve_bounded", "mfwf_remove_templates_noalloc"]
 
 
 class Request(ctypes.Structure):
@@ -86,6 +86,7 @@ def load(path: str = LIB_PATH):
     L.mfwf_set_covariances.argtypes = [vp, dp, ip, vp, vp]
     L.mfwf_set_covariances_beam.argtypes = [vp, dp, ip, dp, vp, vp]
     L.mfwf_remove_templates.argtypes = [vp, vp, vp, ip]
+    L.mfwf_remove_templates_noalloc.argtypes = [vp, vp, vp, ip]
     L.mfwf_sht_inv.argtypes = [vp, vp, vp, ip]
     L.mfwf_sht_fwd.argtypes = [vp, vp, vp, ip]
     L.mfwf_fluctuation_rhs.argtypes = [vp, vp, vp, ip, vp]
@@ -237,6 +238,19 @@ class Plan:
         out = self.zeros_map(n) if out is None else out
         self._enter()
         _check(_lib.mfwf_remove_templates(self._h, x.data_ptr(), out.data_ptr(), n))
+        self._leave()
+        return out
+
+    def remove_templates_noalloc(self, d: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """remove_templates into a caller-provided output, with no device allocation in the
+        library (at most 64 maps per call)."""
+        n = self._count(d)
+        x = _dev_f64(d, (n, self.ncomp, self.npix))
+        if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous()
+                and out.numel() == x.numel()):
+            raise TypeError("out must be a contiguous CUDA float64 tensor shaped like d")
+        self._enter()
+        _check(_lib.mfwf_remove_templates_noalloc(self._h, x.data_ptr(), out.data_ptr(), n))
         self._leave()
         return out
 
