@@ -135,3 +135,57 @@ class Problem:
         """Eigenvalues of Omega Y^T Y (all modes); 1 where the pixel sum is an exact
         quadrature."""
         return np.linalg.eigvalsh(self.omega * (self.Y.T @ self.Y))
+
+
+# ---- polarization: (T, Q, U) from (T, E, B) written from the definition ------------------
+
+def pol_synthesis_direct(nside, lmax, alm3):
+    """(T, Q, U) maps [3][npix] of (T, E, B) coefficients [3][nalm] summed term by term from
+    the definition: T = sum a^T_lm Y_lm (SciPy), Q + iU = sum_{l, |m| <= l} 2a_lm 2Y_lm with
+    2a_lm = -(a^E_lm + i a^B_lm), the reality of the scalar E and B fields
+    a_{l,-m} = (-1)^m conj(a_lm), 2Y_lm = 2lambda_lm(theta) e^{i m phi} and
+    2lambda_{l,-m} = (-1)^m (-2)lambda_lm.  The spin-weighted functions 2lambda, (-2)lambda
+    are the oracle's (oracle.spin2, pinned separately to the spin-raising definition)."""
+    from . import spin2
+    alm3 = np.asarray(alm3, dtype=np.complex128)
+    th, ph = pixel_angles(nside)
+    npix = th.size
+    ls, ms = lm_arrays(lmax)
+    out = np.zeros((3, npix))
+    # T: sum over m >= 0 with the m < 0 terms as conjugates (real field)
+    for k, (l, m) in enumerate(zip(ls, ms)):
+        y = sph_harm_y(l, m, th, ph)
+        out[0] += (alm3[0, k] * y).real * (1.0 if m == 0 else 2.0)
+    P = np.zeros(npix, dtype=np.complex128)
+    zs, inv = np.unique(np.cos(th), return_inverse=True)
+    for m in range(lmax + 1):
+        lp = np.zeros((zs.size, lmax - m + 1))
+        lm_ = np.zeros((zs.size, lmax - m + 1))
+        for u, z in enumerate(zs):
+            fp, fm = spin2(lmax, m, z)
+            lp[u], lm_[u] = fp + fm, fp - fm           # 2lambda, (-2)lambda, l = m..lmax
+        e = np.exp(1j * m * ph)
+        sel = ms == m
+        aE, aB = alm3[1, sel], alm3[2, sel]
+        P += (lp[inv] @ (-(aE + 1j * aB))) * e        # the +m term
+        if m > 0:
+            # the -m term: 2a_{l,-m} 2lambda_{l,-m} e^{-i m phi}
+            #   = -(conj aE + i conj aB) (-2)lambda_lm e^{-i m phi}
+            P += (lm_[inv] @ (-(np.conj(aE) + 1j * np.conj(aB)))) * np.conj(e)
+    out[1], out[2] = P.real, P.imag
+    return out
+
+
+def pol_synthesis_matrix(nside, lmax):
+    """The same synthesis as a real matrix [3 npix, 3 (lmax+1)^2]: rows (T, Q, U) pixels,
+    columns the real-basis coordinates (alm_to_real) of T, then E, then B."""
+    n = (lmax + 1) ** 2
+    cols = []
+    for c in range(3):
+        for j in range(n):
+            x = np.zeros(n)
+            x[j] = 1.0
+            a = np.zeros((3, nalm(lmax)), dtype=np.complex128)
+            a[c] = real_to_alm(x, lmax)
+            cols.append(pol_synthesis_direct(nside, lmax, a).ravel())
+    return np.stack(cols, axis=1)

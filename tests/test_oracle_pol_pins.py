@@ -445,3 +445,173 @@ def test_pol_plain_iteration_unstable_at_lmax_2nside_nside32():
     ct = dgt[:, 0]
     kt = int(np.argmin(ct))
     assert 100 < kt < 400 and ct[-1] > ct[kt] + 10.0 * math.sqrt(2.0 * int(w.mask.sum()))
+
+
+# ----------------------------------------------------------------------------------------
+# The polarized transform against its definition, and the sampled forms against the full
+# ones; the T, Q, U iteration at lambda > 1 with correlated noise blocks.
+# ----------------------------------------------------------------------------------------
+from oracle import dense  # noqa: E402
+
+
+@pytest.mark.parametrize("nside,lmax", [(2, 8), (4, 9), (4, 16)])
+def test_pol_synthesis_equals_the_definition(nside, lmax):
+    """The oracle's (T, Q, U) synthesis (ring pairs, FFT, alias folds up to lmax = 4 nside,
+    half-pixel phases) equals the term-by-term sum of Q + iU = sum 2a_lm 2Y_lm over m = -l..l
+    with the E/B reality conditions (oracle.dense.pol_synthesis_direct); the analysis equals
+    Omega times the transpose of that sum."""
+    rng = np.random.default_rng(nside * 31 + lmax)
+    a = _rand_teb(rng, lmax)
+    ref = dense.pol_synthesis_direct(nside, lmax, a)
+    got = oracle.alm2map_pol(nside, lmax, a)
+    for c in range(3):
+        assert rel(got[c], ref[c]) < 1e-13, c
+    Y = dense.pol_synthesis_matrix(nside, lmax)
+    npix = 12 * nside * nside
+    mp = rng.standard_normal((3, npix))
+    ana = (FOURPI / npix) * (Y.T @ mp.ravel())
+    n = (lmax + 1) ** 2
+    back = oracle.map2alm_pol(nside, lmax, mp)
+    for c in range(3):
+        assert rel(dense.alm_to_real(back[c], lmax), ana[c * n:(c + 1) * n]) < 1e-13, c
+
+
+@pytest.mark.parametrize("nside,lmax", [(4, 8), (4, 16), (8, 20), (8, 32)])
+def test_pol_sampled_ring_and_m_equal_the_full_transforms(nside, lmax):
+    """T, Q, U of one ring and T, E, B of one m (the forms the large-size GPU checks use)
+    equal the rows and columns of the full polarized synthesis and analysis on every ring
+    and every m, lmax up to 4 nside (all alias folds)."""
+    rng = np.random.default_rng(nside + 7 * lmax)
+    a = _rand_teb(rng, lmax)
+    full = oracle.alm2map_pol(nside, lmax, a)
+    z, s, start, nphi, phi0 = oracle.rings(nside)
+    scale = np.linalg.norm(full)
+    for r in range(1, 4 * nside):
+        got = oracle.alm2map_pol_ring(nside, lmax, a, r)
+        sl = slice(int(start[r - 1]), int(start[r - 1] + nphi[r - 1]))
+        assert np.abs(got - full[:, sl]).max() < 1e-13 * scale, r
+    mp = rng.standard_normal((3, 12 * nside * nside))
+    ana = oracle.map2alm_pol(nside, lmax, mp)
+    _, ms = W.alm_l_m(lmax)
+    ascale = np.abs(ana).max()
+    for m in range(lmax + 1):
+        got = oracle.map2alm_pol_m(nside, lmax, mp, m)
+        assert np.abs(got - ana[:, ms == m]).max() < 1e-13 * ascale, m
+
+
+def _pol_dense_problem(nside, lmax, seed, nu=4):
+    """A T, Q, U problem with correlated 3x3 noise blocks (Wishart with nu degrees of
+    freedom), the definition-based synthesis matrix Y [3 npix, 3 (lmax+1)^2], the noise
+    precision blocks Mb [npix][3][3] and the real-basis signal blocks S."""
+    w = W.config3(seed, nside, lmax, ndisc=3, band_z=0.1, nu=nu)
+    d = w.data_from_signal_maps(dense.pol_synthesis_direct(nside, lmax, w.signal_alm))
+    M6 = w.M6()
+    n = (lmax + 1) ** 2
+    Y = dense.pol_synthesis_matrix(nside, lmax)
+    Mb = _unpack(M6)
+    ell = dense.real_ell(lmax)
+    S = np.zeros((3 * n, 3 * n))
+    TT, EE, BB, TE = (w.cl4[c][ell] for c in range(4))
+    k = np.arange(n)
+    S[k, k], S[n + k, n + k], S[2 * n + k, 2 * n + k] = TT, EE, BB
+    S[k, n + k] = S[n + k, k] = TE
+    keep = np.diag(S) > 0.0
+    return w, d, M6, Y, Mb, S, keep
+
+
+def _blocks(Mb, V):
+    """Per-pixel 3x3 blocks applied to pixel vectors: V [3 npix, ...] (component-major)."""
+    npix = Mb.shape[0]
+    Vr = V.reshape((3, npix) + V.shape[1:])
+    return np.einsum("pij,jp...->ip...", Mb, Vr).reshape(V.shape)
+
+
+def _pol_fixed_point(Y, Mb, S, keep, rho, lam, tau, omega):
+    """The s that one T, Q, U iteration at constant lambda maps to itself:
+    s = D Omega Y^T B^-1 [lam tau rho + (1 - tau M) Y s], B = 1 + (lam - 1) tau M per pixel
+    block (inverted by numpy), D = S (S + lam tau Omega)^-1, on the coefficients with power."""
+    eye = np.eye(3)
+    Bi = np.linalg.inv(eye + (lam - 1.0) * tau * Mb)
+    Yk = Y[:, keep]
+    Sk = S[np.ix_(keep, keep)]
+    D = Sk @ np.linalg.inv(Sk + lam * tau * omega * np.eye(Sk.shape[0]))
+    G = D @ (omega * Yk.T @ _blocks(Bi @ (eye - tau * Mb), Yk))
+    b = D @ (omega * Yk.T @ _blocks(Bi, lam * tau * rho))
+    return np.linalg.solve(np.eye(G.shape[0]) - G, b), G
+
+
+def _real3(a, lmax):
+    return np.concatenate([dense.alm_to_real(a[c], lmax) for c in range(3)])
+
+
+@pytest.mark.parametrize("lam", [3.0, 10.0])
+def test_pol_fixed_point_at_lambda_above_one_with_correlated_blocks(lam):
+    """The oracle's T, Q, U iteration at constant lambda > 1 converges to the dense fixed
+    point of Eqs. (3)-(4) with full 3x3 blocks: B^-1 = [1 + (lam - 1) tau M_p]^-1 per pixel
+    by numpy, the (T, E, B) signal blocks per l, the definition-based synthesis.  A
+    transposed block, a wrong B^-1 or a lambda on the wrong term moves the fixed point."""
+    nside, lmax = 4, 4
+    w, d, M6, Y, Mb, S, keep = _pol_dense_problem(nside, lmax, seed=11)
+    npix = 12 * nside * nside
+    omega, tau = FOURPI / npix, oracle.tau_pol(M6)
+    Mo = M6[w.mask > 0]
+    corr = np.abs(Mo[:, [1, 2, 4]]) / np.sqrt(Mo[:, [0, 0, 3]] * Mo[:, [3, 5, 5]])
+    assert np.median(corr) > 0.2  # strongly correlated blocks
+    rho = _blocks(Mb, d.ravel()).reshape(3, npix)
+    x, G = _pol_fixed_point(Y, Mb, S, keep, rho.ravel(), lam, tau, omega)
+    radius = np.max(np.abs(np.linalg.eigvals(G)))
+    assert radius < 0.999
+    k = int(math.ceil(math.log(1e-14) / math.log(radius))) + 20
+    s, _ = oracle.solve_pol(nside, lmax, w.cl4, M6, rho, lam=[lam] * k)
+    got = _real3(s, lmax)
+    assert np.all(got[~keep] == 0.0)
+    assert rel(got[keep], x) < 1e-10
+
+
+@pytest.mark.parametrize("lam", [3.0, 10.0])
+def test_pol_chi2_decreases_at_fixed_lambda_above_one(lam):
+    """At fixed lambda the iteration lowers chi^2(x, lambda) of Eq. (6) (Sect. 2.2), here with
+    lambda > 1 and strongly correlated noise blocks; nside 8 / lmax 8 keeps the quadrature
+    gap of the pixelisation far below the decrease."""
+    nside, lmax = 8, 8
+    w = W.config3(12, nside, lmax, ndisc=5, band_z=0.2, nu=4)
+    d = w.data_from_signal_maps(oracle.alm2map_pol(nside, lmax, w.signal_alm))
+    M6 = w.M6()
+    rho = np.einsum("pij,jp->ip", _unpack(M6), d)
+    _, _, dg = oracle.solve_pol(nside, lmax, w.cl4, M6, rho, lam=[lam] * 40, diag=True)
+    assert np.all(np.diff(dg[:, 0]) < 0.0), np.diff(dg[:, 0]).max()
+    assert dg[-1, 0] < 0.5 * dg[0, 0]
+
+
+def test_pol_s_lambda_closed_form_within_the_quadrature_bound():
+    """Sect. 2.2: at constant lambda the iteration converges to s(lambda) =
+    S (S + N + (lambda - 1) T)^-1 d, the minimiser of chi^2(x, lambda): in harmonic form
+    (S^-1 + Y^T M_lam Y) x = Y^T M_lam d, M_lam = M [1 + (lam - 1) tau M]^-1 per block.  The
+    messenger fixed point solves the same system with E = (1 - Omega Y^T Y)/(lam tau Omega)
+    added to the matrix, so their distance is at most |(A + E)^-1| |E| (an exact perturbation
+    bound, A the closed form's matrix), which the check takes as its tolerance; E vanishes
+    where the pixel sum is an exact quadrature, and the distance shrinks with it (nside 8 ->
+    16 at lmax 4)."""
+    lmax = 4
+    gaps = {}
+    for nside in (8, 16):
+        w, d, M6, Y, Mb, S, keep = _pol_dense_problem(nside, lmax, seed=13, nu=10)
+        npix = 12 * nside * nside
+        omega, tau = FOURPI / npix, oracle.tau_pol(M6)
+        Yk = Y[:, keep]
+        Sk = S[np.ix_(keep, keep)]
+        Gk = omega * Yk.T @ Yk
+        for lam in (3.0, 10.0):
+            Ml = Mb @ np.linalg.inv(np.eye(3) + (lam - 1.0) * tau * Mb)
+            A = np.linalg.inv(Sk) + Yk.T @ _blocks(Ml, Yk)
+            x_closed = np.linalg.solve(A, Yk.T @ _blocks(Ml, d.ravel()))
+            x_fp, _ = _pol_fixed_point(Y, Mb, S, keep, _blocks(Mb, d.ravel()), lam, tau, omega)
+            E = (np.eye(Gk.shape[0]) - Gk) / (lam * tau * omega)
+            bound = np.linalg.norm(np.linalg.inv(A + E), 2) * np.linalg.norm(E, 2)
+            gaps[nside, lam] = rel(x_fp, x_closed)
+            print("nside", nside, "lambda", lam, "gap", gaps[nside, lam], "bound", bound)
+            assert gaps[nside, lam] <= bound
+            if nside == 16:
+                assert bound < 0.2
+    for lam in (3.0, 10.0):
+        assert gaps[16, lam] < 0.25 * gaps[8, lam]
