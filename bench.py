@@ -190,6 +190,85 @@ def timed_solves(plan, d, K, steps, warmup, use_graph):
     return time.perf_counter() - t0, lat
 
 
+def kernel_mode(args):
+    """--kernels FORM: run each stage of one messenger iteration `--reps` times through
+    mfwf_time_kernels (after two solve iterations), on the temperature workload at --nside /
+    --lmax with --batch maps (FP32 form) or one map (FP64); with --copy also a 256 MiB device
+    copy three times, the reference for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes;
+    with --solve-iters N also a timed solve of N iterations.  For hardware-counter runs."""
+    import torch
+    from paper_1210_4931_amd import mfwf
+    from paper_1210_4931_amd import workloads as W
+    maps = args.batch if args.kernels == "f32" else 1
+    wl = W.config2(0, args.nside, args.lmax)
+    t = lambda x, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(x)).to("cuda", dt)  # noqa
+    plan = mfwf.Plan(args.nside, args.lmax, max_batch=maps, dtype=args.kernels)
+    plan.set_covariances(wl.cl, t(1.0 / wl.noise_var), t(wl.mask, torch.uint8))
+    sig = plan.sht_inv(t(wl.signal_alm[None], torch.complex128))
+    d = (sig + t(np.sqrt(wl.noise_var) * wl.noise_white)[None]).expand(maps, -1).contiguous()
+    plan.solve(d, iters=2, use_graph=False)
+    ms = plan.time_kernels(maps, args.reps)
+    if args.copy:
+        a = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+    torch.cuda.synchronize()
+    out = {"mode": "kernels", "form": args.kernels, "nside": args.nside, "lmax": args.lmax,
+           "maps": maps, "kernel_ms": dict(zip(KERNELS, ms))}
+    if args.solve_iters > 0:
+        plan.solve(d, iters=args.solve_iters)  # warm: graph capture, caches
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.solve(d, iters=args.solve_iters)
+        torch.cuda.synchronize()
+        out["solve_ms_per_iter"] = 1e3 * (time.perf_counter() - t0) / args.solve_iters
+    print(json.dumps(out), flush=True)
+
+
+def tqu_cooled_mode(args):
+    """--tqu-cooled: converged T, Q, U solves with the cooling schedule (Sect. 3) on the T, Q,
+    U workload (Wishart 3x3 noise, EE/BB/TE tied to TT, the nside 512 mask): data from its
+    signal with the FP64 path, then mfwf_solve_cooled twice (the second run timed) on one map
+    with the FP64 path and on --tqu-batch maps (the first map and noisier copies) with the
+    batched FP32 form.  One JSON line per form."""
+    import torch
+    from paper_1210_4931_amd import mfwf
+    from paper_1210_4931_amd import workloads as W
+
+    def dev(x, dt=torch.float64):
+        return torch.as_tensor(np.ascontiguousarray(x)).to("cuda", dt)
+
+    w = W.config3(0, args.nside, args.lmax)
+    ninv6, mask = dev(w.ninv6), dev(w.mask, torch.uint8)
+
+    def run(plan, x, tag, nmaps):
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, info, stages, conv = plan.solve_cooled(x)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        print(json.dumps({"mode": "tqu_cooled", "form": tag, "nside": args.nside,
+                          "lmax": args.lmax, "maps": nmaps, "seconds": el,
+                          "solves_per_s": nmaps / el, "iterations": info[0].iters_done,
+                          "converged": conv, "chi2_per_dof": info[0].chi2 / info[0].n_dof,
+                          "stages": stages[:, :4].tolist()}), flush=True)
+
+    p64 = mfwf.Plan(args.nside, args.lmax, max_batch=1, spin=2)
+    p64.set_covariances(w.cl4, ninv6, mask)
+    sig = p64.sht_inv(dev(w.signal_alm[None], torch.complex128)).cpu().numpy()[0]
+    d1 = w.data_from_signal_maps(sig)
+    run(p64, dev(d1[None]), "fp64", 1)
+    del p64
+    rng = np.random.default_rng(5)
+    B = args.tqu_batch
+    ds = np.stack([d1] + [d1 + rng.standard_normal(d1.shape) for _ in range(B - 1)])
+    p32 = mfwf.Plan(args.nside, args.lmax, max_batch=B, spin=2, dtype="f32")
+    p32.set_covariances(w.cl4, ninv6, mask)
+    run(p32, dev(ds), "f32_batched", B)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,11 +289,22 @@ def main():
                     help="skip the converged solves with the cooling schedule")
     ap.add_argument("--serve-requests", type=int, default=100,
                     help="requests per serving phase (saturation, Poisson at 0.8 of it)")
+    ap.add_argument("--kernels", choices=["f64", "f32"], default=None,
+                    help="profiling mode: run each kernel of one iteration --reps times")
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--copy", action="store_true")
+    ap.add_argument("--solve-iters", type=int, default=0)
+    ap.add_argument("--tqu-cooled", action="store_true",
+                    help="mode: converged T, Q, U solves (cooling schedule), FP64 and FP32")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs the solver on a single MI355X "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.kernels:
+        return kernel_mode(args)
+    if args.tqu_cooled:
+        return tqu_cooled_mode(args)
 
     import torch
     from paper_1210_4931_amd import mfwf
@@ -252,17 +342,30 @@ def main():
     if not args.no_cooled:
         fp64["cooled"] = cooled(p64, d1)
         fp64["bounded"] = bounded(p64, d1)
-    del p64
 
     # ---- batched FP32 form (headline) --------------------------------------------------
     p32 = mfwf.Plan(nside, lmax, max_batch=B, dtype="f32")
     p32.set_covariances(wl.cl, ninv, mask)
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(1)
-    dB = sig + sigma[None] * torch.randn((B, wl.npix), generator=gen, device=dev,
-                                         dtype=torch.float64)
+    # map b: the signal plus its own seeded noise draw (workloads.batch_noise(b))
+    dB = torch.empty((B, wl.npix), dtype=torch.float64, device=dev)
+    for b in range(B):
+        dB[b] = sig[0] + sigma * t(W.batch_noise(b, wl.npix))
     torch.cuda.synchronize()
     el32, lat32 = timed_solves(p32, dB, K, args.steps, args.warmup, use_graph)
+    # accuracy of the timed form: two maps of the batch against the plain FP64 path (itself
+    # checked against the CPU oracle by the GPU tests), relative 2-norm over the real
+    # harmonic dof (m > 0 twice) and over the map
+    a32, m32, _ = p32.solve(dB, iters=K, use_graph=use_graph)
+    acc = {}
+    for b in (0, B // 2 + 5 if B > 1 else 0):
+        a64, m64, _ = p64.solve(dB[b:b + 1].contiguous(), iters=K, use_graph=use_graph)
+        w = torch.ones(a64.shape[-1], dtype=torch.float64, device=dev)
+        w[lmax + 1:] = 2.0 ** 0.5
+        ea = (torch.linalg.norm(w * (a32[b] - a64[0])) / torch.linalg.norm(w * a64[0])).item()
+        em = (torch.linalg.norm(m32[b] - m64[0]) / torch.linalg.norm(m64[0])).item()
+        acc["map%d" % b] = {"rel_err_alm": ea, "rel_err_map": em}
+    del a32, m32
+    del p64
     kt32 = dict(zip(KERNELS, p32.time_kernels(B, 5)))
     gemm_flops = 2.0 * work * 2 * B   # one FMA per (l, m, ring pair) and column, 2 columns a map
     dom32 = max(("leg_analysis", "leg_synth"), key=lambda k: kt32[k])
@@ -305,6 +408,7 @@ def main():
                           "transforms in one kernel, with the layout transposes to and from "
                           "the matrix-core column layout"},
         "legendre_triples": {"evaluated": work, "full_triangle": full},
+        "accuracy_vs_fp64_path": dict(acc, tolerance=1e-5, iterations=K),
         # the dominant kernel: the ring step (inverse transforms, pixel update, forward
         # transforms), per iteration
         "roofline": {"bound": "hbm", "kernel": "ring_step (k_fft_inv_fwd, both length classes)",

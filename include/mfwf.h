@@ -343,6 +343,23 @@ int mfwf_time_kernels(mfwf_plan plan, int nmaps, int reps, double *ms_out);
 int mfwf_plan_work(mfwf_plan plan, double *out4);
 
 /*
+ * Kernel shapes the plan uses (host, 8 ints): [0] FP64 Legendre synthesis variant (0..8),
+ * [1] analysis variant (0..5), [2] maps per workgroup of the batched form's ring step for
+ * the shorter transforms and [3] for the longest (1, 2, 4), [4] largest column tile of the
+ * analysis GEMM and [5] of the synthesis GEMM, in units of 64 columns (1, 2), [6] how they
+ * were set: 0 defaults, 1 by the autotuner at plan creation (timed, or read from its cache),
+ * 3 from the environment variable MFWF_TUNE_FORCE; [7] 0.  None of them changes a result of
+ * the batched form; the FP64 Legendre variants add the ring pairs' partial sums in different
+ * groupings.  The autotuner (MFWF_AUTOTUNE unset or not "0", plans of 256 ring pairs or
+ * more) times every applicable value of each at plan creation and caches the choice per
+ * (device, library build, nside, lmax, max_batch, dtype, spin) in $MFWF_TUNE_CACHE (default
+ * $XDG_CACHE_HOME/mfwf/tune.txt or ~/.cache/mfwf/tune.txt).  MFWF_TUNE_FORCE =
+ * "synth=3,ana=1,g0=2,g1=1,cta=1,cts=2" (any subset) sets them at plan creation for any
+ * plan size; a malformed value makes mfwf_plan_create fail with MFWF_EINVAL.
+ */
+int mfwf_plan_tuning(mfwf_plan plan, int *out8);
+
+/*
  * ---- Serving: many independent requests on one GPU (continuous batching) --------------
  * Each request is one temperature Wiener-filter solve with its own data, noise variance
  * map and mask.  Requests with the same (nside, lmax, dtype, lambda, C_l) share a pool: a

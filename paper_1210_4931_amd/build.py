@@ -38,10 +38,23 @@ def torch_lib_dir() -> str:
     return os.path.join(os.path.dirname(spec.origin), "lib")
 
 
-def _compile(src: str) -> str:
+def source_hash() -> str:
+    """SHA-256 (first 16 hex digits) of the library sources: keys the autotuner's cache, so
+    that choices timed on other kernels are not reused."""
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".h")))
+    for f in files:
+        h.update(f.encode())
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    h.update(open(os.path.join(INCLUDE, "mfwf.h"), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _compile(src: str, src_hash: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *HIPFLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj,
-           "-Rpass-analysis=kernel-resource-usage"]
+    cmd = [HIPCC, *HIPFLAGS, "-I", INCLUDE, "-I", CSRC, "-DMFWF_SRC_HASH=\"%s\"" % src_hash,
+           "-c", os.path.join(CSRC, src), "-o", obj, "-Rpass-analysis=kernel-resource-usage"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr))
@@ -72,8 +85,9 @@ def resource_usage() -> dict:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    src_hash = source_hash()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda f: _compile(f, src_hash), SOURCES))
     tl = torch_lib_dir()
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = ["g++", "-shared", "-o", tmp, *objs, "-L" + tl, "-l:libamdhip64.so",

@@ -253,38 +253,89 @@ static int device_name(std::string &name) {
     return MFWF_OK;
 }
 
-// ---- kernel-variant autotuning ----------------------------------------------------------
-// The Legendre kernels come in variants (ring pairs per lane, coefficient block length,
-// prefetch of the next block).  With MFWF_AUTOTUNE != 0 (default) the plan times every
-// variant on its own stream and keeps the fastest; the choice is cached per
-// (device, nside, lmax) in $MFWF_TUNE_CACHE (default ~/.cache/mfwf/legendre_tune.txt), so
-// later plans of the same shape reuse it without timing.
+// ---- autotuning ---------------------------------------------------------------------------
+// Kernel shapes the plan chooses by timing (none changes what a result is, only how the work
+// is laid out; the Legendre variants of the FP64 path also change the order in which the
+// ring pairs' partial sums are added):
+//   synth, ana  FP64 Legendre kernels: ring pairs per lane 1/2/4, coefficient block 4/8,
+//               prefetch of the next block (9 synthesis, 6 analysis variants)
+//   g0, g1      maps per workgroup of the batched form's ring step, short-transform class
+//               and longest-transform class (1, 2 or 4; as LDS and 1024 threads allow)
+//   cta, cts    largest column tile of the analysis / synthesis GEMMs, x 64 columns (1 or 2)
+// With MFWF_AUTOTUNE != 0 (default) a plan of at least 256 ring pairs times every value of
+// each knob that applies to it on its own stream (3 launches after a warm-up, on filled
+// work arrays) and keeps the fastest.  Choices are cached per (device, library source hash,
+// nside, lmax, max_batch, dtype, spin) in $MFWF_TUNE_CACHE, default
+// $XDG_CACHE_HOME/mfwf/tune.txt or ~/.cache/mfwf/tune.txt, so later plans of the same shape
+// reuse them.  MFWF_TUNE_FORCE="synth=3,ana=1,g0=2,g1=1,cta=1,cts=2" (any subset) sets knobs
+// directly, for every plan size, and skips timing.
+#ifndef MFWF_SRC_HASH
+#define MFWF_SRC_HASH "unversioned"
+#endif
+
+enum { kKnobSynth = 0, kKnobAna, kKnobG0, kKnobG1, kKnobCtA, kKnobCtS, kNumKnobs };
+static const char *const kKnobName[kNumKnobs] = {"synth", "ana", "g0", "g1", "cta", "cts"};
+
+static void get_knobs(const Plan &p, int k[kNumKnobs]) {
+    k[kKnobSynth] = p.synth_variant;
+    k[kKnobAna] = p.ana_variant;
+    k[kKnobG0] = p.ring_group[0];
+    k[kKnobG1] = p.ring_group[1];
+    k[kKnobCtA] = p.gemm_ct[0];
+    k[kKnobCtS] = p.gemm_ct[1];
+}
+
+static bool knob_valid(int knob, int v) {
+    switch (knob) {
+        case kKnobSynth: return v >= 0 && v < leg_synth_variants();
+        case kKnobAna: return v >= 0 && v < leg_analysis_variants();
+        case kKnobG0: case kKnobG1: return v == 1 || v == 2 || v == 4;
+        default: return v == 1 || v == 2;
+    }
+}
+
+static void set_knobs(Plan &p, const int k[kNumKnobs]) {
+    p.synth_variant = k[kKnobSynth];
+    p.ana_variant = k[kKnobAna];
+    p.ring_group[0] = k[kKnobG0];
+    p.ring_group[1] = k[kKnobG1];
+    p.gemm_ct[0] = k[kKnobCtA];
+    p.gemm_ct[1] = k[kKnobCtS];
+}
 
 static std::string tune_cache_path() {
     if (const char *e = std::getenv("MFWF_TUNE_CACHE")) return e;
+    if (const char *x = std::getenv("XDG_CACHE_HOME")) return std::string(x) + "/mfwf/tune.txt";
     const char *home = std::getenv("HOME");
-    return std::string(home ? home : "/tmp") + "/.cache/mfwf/legendre_tune.txt";
+    return std::string(home ? home : "/tmp") + "/.cache/mfwf/tune.txt";
 }
 
-static bool tune_lookup(const std::string &key, int &sv, int &av) {
+static std::string tune_key(const Plan &p, const std::string &devname) {
+    return devname.substr(0, 6) + ":" + MFWF_SRC_HASH + ":n" + std::to_string(p.nside) + ":l" +
+           std::to_string(p.lmax) + ":b" + std::to_string(p.max_batch) + ":" +
+           (p.dtype == MFWF_F32 ? "f32" : "f64") + ":s" + std::to_string(p.spin);
+}
+
+static bool tune_lookup(const std::string &key, int k[kNumKnobs]) {
     std::ifstream f(tune_cache_path());
     std::string line;
     bool found = false;
     while (std::getline(f, line)) {
         std::istringstream is(line);
-        std::string k;
-        int s, a;
-        if (is >> k >> s >> a && k == key && s >= 0 && s < leg_synth_variants() && a >= 0 &&
-            a < leg_analysis_variants()) {
-            sv = s;
-            av = a;
+        std::string kk;
+        int v[kNumKnobs];
+        if (!(is >> kk) || kk != key) continue;
+        bool ok = true;
+        for (int q = 0; q < kNumKnobs && ok; q++) ok = (is >> v[q]) && knob_valid(q, v[q]);
+        if (ok) {
+            for (int q = 0; q < kNumKnobs; q++) k[q] = v[q];
             found = true;
         }
     }
     return found;
 }
 
-static void tune_store(const std::string &key, int sv, int av) {
+static void tune_store(const std::string &key, const int k[kNumKnobs]) {
     const std::string path = tune_cache_path();
     const size_t slash = path.find_last_of('/');
     if (slash != std::string::npos) {
@@ -293,7 +344,33 @@ static void tune_store(const std::string &key, int sv, int av) {
             if (i == dir.size() || dir[i] == '/') (void)mkdir(dir.substr(0, i).c_str(), 0755);
     }
     std::ofstream f(path, std::ios::app);
-    if (f) f << key << " " << sv << " " << av << "\n";
+    if (!f) return;
+    f << key;
+    for (int q = 0; q < kNumKnobs; q++) f << " " << k[q];
+    f << "\n";
+}
+
+// MFWF_TUNE_FORCE: "name=value" pairs separated by commas; returns false (with the error set)
+// on a malformed string, an unknown name or a value out of range
+static bool tune_force(const char *env, Plan &p) {
+    int k[kNumKnobs];
+    get_knobs(p, k);
+    std::istringstream is(env);
+    std::string tok;
+    while (std::getline(is, tok, ',')) {
+        const size_t eq = tok.find('=');
+        if (eq == std::string::npos) return fail(MFWF_EINVAL, "MFWF_TUNE_FORCE: expected name=value"), false;
+        const std::string name = tok.substr(0, eq);
+        int q = 0;
+        while (q < kNumKnobs && name != kKnobName[q]) q++;
+        char *end = nullptr;
+        const long v = std::strtol(tok.c_str() + eq + 1, &end, 10);
+        if (q == kNumKnobs || !end || *end != '\0' || !knob_valid(q, (int)v))
+            return fail(MFWF_EINVAL, "MFWF_TUNE_FORCE: bad entry '" + tok + "'"), false;
+        k[q] = (int)v;
+    }
+    set_knobs(p, k);
+    return true;
 }
 
 static int time_launches(Plan &p, int reps, const std::function<int()> &launch, float &ms) {
@@ -312,38 +389,69 @@ static int time_launches(Plan &p, int reps, const std::function<int()> &launch, 
     return st;
 }
 
+// the fastest value of one knob for the launch it shapes (the others held)
+static int tune_knob(Plan &p, int knob, const std::vector<int> &values,
+                     const std::function<int()> &launch) {
+    int k[kNumKnobs];
+    get_knobs(p, k);
+    float best = INFINITY;
+    int bestv = k[knob];
+    for (int v : values) {
+        k[knob] = v;
+        set_knobs(p, k);
+        float ms = 0.f;
+        MFWF_TRY(time_launches(p, 3, launch, ms));
+        if (ms < best) {
+            best = ms;
+            bestv = v;
+        }
+    }
+    k[knob] = bestv;
+    set_knobs(p, k);
+    return MFWF_OK;
+}
+
 static int autotune(Plan &p, const std::string &devname) {
-    const std::string key = devname.substr(0, 6) + ":" + std::to_string(p.nside) + ":" +
-                            std::to_string(p.lmax);
-    int sv, av;
-    if (tune_lookup(key, sv, av)) {
-        p.synth_variant = sv;
-        p.ana_variant = av;
+    const std::string key = tune_key(p, devname);
+    int k[kNumKnobs];
+    get_knobs(p, k);
+    if (tune_lookup(key, k)) {
+        set_knobs(p, k);
         return MFWF_OK;
     }
-    float best = INFINITY;
-    for (int v = 0; v < leg_synth_variants(); v++) {
-        p.synth_variant = v;
-        float ms = 0.f;
-        MFWF_TRY(time_launches(p, 3, [&] { return launch_leg_synth(p, p.d_sp, p.d_phase, 1); }, ms));
-        if (ms < best) {
-            best = ms;
-            sv = v;
+    const int B = p.max_batch;
+    if (p.dtype == MFWF_F64 && p.spin == 0) {
+        // timing inputs: a fixed non-zero pattern (all variants do the same arithmetic on it)
+        MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_sp), 2 * p.nalm, 0.25, p.stream));
+        MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_phase), 2L * p.nm * p.nring, 0.5, p.stream));
+        std::vector<int> sv(leg_synth_variants()), av(leg_analysis_variants());
+        for (int v = 0; v < (int)sv.size(); v++) sv[v] = v;
+        for (int v = 0; v < (int)av.size(); v++) av[v] = v;
+        MFWF_TRY(tune_knob(p, kKnobSynth, sv, [&] { return launch_leg_synth(p, p.d_sp, p.d_phase, 1); }));
+        MFWF_TRY(tune_knob(p, kKnobAna, av, [&] { return launch_leg_analysis(p, p.d_phase, p.d_apart, 1); }));
+        MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_sp), 2 * p.nalm, 0.0, p.stream));
+        MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_phase), 2L * p.nm * p.nring, 0.0, p.stream));
+    }
+    if (p.dtype == MFWF_F32) {
+        // on zeroed work arrays: the batched kernels' work does not depend on the values
+        if (p.spin == 0) {
+            for (int c = 1; c >= 0; c--) {
+                std::vector<int> gv;
+                for (int g = 1; g <= fft_cols_group_max(p, c, B); g *= 2) gv.push_back(g);
+                if (gv.size() > 1)
+                    MFWF_TRY(tune_knob(p, c == 0 ? kKnobG0 : kKnobG1, gv, [&] {
+                        return launch_fft_inv_fwd_cols(p, p.d_rho, 1.0, nullptr, B);
+                    }));
+            }
+        }
+        if (2 * B > 64) {  // more than 64 active columns: both column tiles apply
+            const std::vector<int> cv = {1, 2};
+            MFWF_TRY(tune_knob(p, kKnobCtA, cv, [&] { return launch_gemm_analysis(p, B, p.d_a32, nullptr, 1.0, 1.0); }));
+            MFWF_TRY(tune_knob(p, kKnobCtS, cv, [&] { return launch_gemm_synthesis(p, B); }));
         }
     }
-    best = INFINITY;
-    for (int v = 0; v < leg_analysis_variants(); v++) {
-        p.ana_variant = v;
-        float ms = 0.f;
-        MFWF_TRY(time_launches(p, 3, [&] { return launch_leg_analysis(p, p.d_phase, p.d_apart, 1); }, ms));
-        if (ms < best) {
-            best = ms;
-            av = v;
-        }
-    }
-    p.synth_variant = sv;
-    p.ana_variant = av;
-    tune_store(key, sv, av);
+    get_knobs(p, k);
+    tune_store(key, k);
     return MFWF_OK;
 }
 
@@ -650,7 +758,10 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     if (fftmax > fft_max_length())
         return fail(MFWF_EINVAL, "ring FFT length " + std::to_string(fftmax) + " above the supported " +
                                      std::to_string(fft_max_length()));
-    const size_t lds = std::max({fft_class_lds(p, 0), fft_class_lds(p, 1), fft_class_lds(p, 2)});
+    size_t lds = std::max({fft_class_lds(p, 0), fft_class_lds(p, 1), fft_class_lds(p, 2)});
+    if (dtype == MFWF_F32)  // the columns ring step of the batched form, G maps per workgroup
+        for (int c = 0; c < 2; c++)
+            lds = std::max(lds, fft_cols_lds(p, c, fft_cols_group_max(p, c, max_batch)));
     {
         int dev = 0, maxlds = 0;
         MFWF_HIP(hipGetDevice(&dev));
@@ -734,19 +845,17 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_sp), 2 * B * nc * p.nalm, 0.0, p.stream));
 
     default_variants(p);
-    if (f32) {
-        MFWF_TRY(setup_batched(p, lstart, mofs));
-    } else if (const char *env = std::getenv("MFWF_LEG_VARIANTS")) {  // "synth,analysis" override
-        int sv = -1, av = -1;
-        if (std::sscanf(env, "%d,%d", &sv, &av) != 2 || sv < 0 || sv >= leg_synth_variants() ||
-            av < 0 || av >= leg_analysis_variants())
-            return fail(MFWF_EINVAL, "MFWF_LEG_VARIANTS must be 'synth,analysis' variant indices");
-        p.synth_variant = sv;
-        p.ana_variant = av;
+    if (f32) MFWF_TRY(setup_batched(p, lstart, mofs));
+    p.tune_source = 0;
+    if (const char *env = std::getenv("MFWF_TUNE_FORCE")) {
+        if (!tune_force(env, p)) return MFWF_EINVAL;
+        p.tune_source = 3;
     } else {
         const char *at = std::getenv("MFWF_AUTOTUNE");
-        if (!(at && std::strcmp(at, "0") == 0) && p.npair >= 256 && spin == 0)
+        if (!(at && std::strcmp(at, "0") == 0) && p.npair >= 256) {
             MFWF_TRY(autotune(p, devname));
+            p.tune_source = 1;
+        }
     }
     MFWF_TRY(set_groups(p));
     MFWF_HIP(hipStreamSynchronize(p.stream));
@@ -1883,6 +1992,17 @@ int mfwf_plan_work(mfwf_plan plan, double *out4) {
     out4[1] = (double)p.npair * (double)p.nalm;
     out4[2] = p.npair;
     out4[3] = p.fftmax;
+    return MFWF_OK;
+}
+
+int mfwf_plan_tuning(mfwf_plan plan, int *out8) {
+    if (!plan || !out8) return fail(MFWF_EINVAL, "NULL argument");
+    const Plan &p = plan->p;
+    int k[kNumKnobs];
+    get_knobs(p, k);
+    for (int q = 0; q < kNumKnobs; q++) out8[q] = k[q];
+    out8[6] = p.tune_source;
+    out8[7] = 0;
     return MFWF_OK;
 }
 

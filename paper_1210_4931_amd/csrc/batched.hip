@@ -526,7 +526,7 @@ static int active_cols(int nb, int w) { return 32 * ((w * nb + 31) / 32); }
 static int analysis_launch(const Plan &p, int nc, int C2, const float *table, const float *cols,
                            float *a_out, float *s_out, double scale_s, double lto,
                            const double *tau_b, double lto_per_tau, int flip) {
-    const int nct = nc <= 64 ? 1 : 2, ncg = (nc + col_tile(nct) - 1) / col_tile(nct);
+    const int nct = (nc <= 64 || p.gemm_ct[0] == 1) ? 1 : 2, ncg = (nc + col_tile(nct) - 1) / col_tile(nct);
     const dim3 grid(8 * p.ana_per_xcd * ncg), block(256);
     if (nct == 1)
         hipLaunchKernelGGL(k_gemm_analysis<1>, grid, block, 0, p.stream, table, p.d_loff, p.d_Lp,
@@ -544,7 +544,7 @@ static int analysis_launch(const Plan &p, int nc, int C2, const float *table, co
 
 static int synthesis_launch(const Plan &p, int nc, int C2, const float *table, const float *s_in,
                             float *out, int flip) {
-    const int nct = nc <= 64 ? 1 : 2, ncg = (nc + col_tile(nct) - 1) / col_tile(nct);
+    const int nct = (nc <= 64 || p.gemm_ct[1] == 1) ? 1 : 2, ncg = (nc + col_tile(nct) - 1) / col_tile(nct);
     const dim3 grid(8 * p.syn_per_xcd * ncg), block(256);
     if (nct == 1)
         hipLaunchKernelGGL(k_gemm_synthesis<1>, grid, block, 0, p.stream, table, p.d_loff, p.d_Lp,

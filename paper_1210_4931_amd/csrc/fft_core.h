@@ -91,7 +91,9 @@ __device__ __forceinline__ void small_dft(double2 (&v)[R]) {
 enum { kPreNone = 0, kPreChirp = 1, kPreKernelConj = 2 };
 
 // One Stockham pass of radix R over buf[0..n): inputs j + r n/R, output (j/Ns) Ns R + j%Ns
-// + r Ns, twiddle exp(-2 pi i (j%Ns) r / (Ns R)).  All reads precede all writes.
+// + r Ns, twiddle exp(-2 pi i (j%Ns) r / (Ns R)).  All reads precede all writes.  The
+// transform belongs to the TPB threads of the thread's group (threadIdx.x mod TPB; a
+// workgroup may hold several groups, one transform each, which pass the barriers together).
 // EPT: most transform elements one thread handles (n <= EPT * TPB).  PRE != kPreNone only
 // on a first pass (Ns = 1, no twiddles), with its table pre.
 template <int TPB, int EPT, int R, int PRE = kPreNone>
@@ -103,7 +105,7 @@ __device__ __forceinline__ void stockham_pass(double2 *buf, int n, int Ns, const
     double2 v[MAXB][R];
 #pragma unroll
     for (int b = 0; b < MAXB; b++) {
-        const int j = threadIdx.x + b * TPB;
+        const int j = (threadIdx.x & (TPB - 1)) + b * TPB;
         if (j < nbf) {
 #pragma unroll
             for (int r = 0; r < R; r++) v[b][r] = buf[lds_ix(j + r * nbf)];
@@ -123,7 +125,7 @@ __device__ __forceinline__ void stockham_pass(double2 *buf, int n, int Ns, const
     const int ts = fftmax / (Ns * R);
 #pragma unroll
     for (int b = 0; b < MAXB; b++) {
-        const int j = threadIdx.x + b * TPB;
+        const int j = (threadIdx.x & (TPB - 1)) + b * TPB;
         if (j < nbf) {
             const int kk = j & (Ns - 1);
             if (PRE == kPreNone && Ns > 1) {
@@ -177,6 +179,113 @@ __device__ __forceinline__ void fft_stockham(double2 *buf, int n, const Twiddles
     }
 }
 
+// ---- compile-time transform lengths ---------------------------------------------------
+// The same Stockham passes with the length N, the radix and the stride Ns of every pass known
+// at compile time: a thread's LDS slots are one base plus constant offsets (the pad slot
+// every 8 elements folds into the constant), the butterfly-count guard disappears when the
+// threads divide the butterflies, and the twiddle index is a shift.  Arithmetic and its
+// order are those of stockham_pass / fft_stockham, so results are bitwise the same.
+
+__device__ __forceinline__ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
+
+template <int TPB, int N, int R, int Ns, int PRE>
+__device__ __forceinline__ void stockham_pass_c(double2 *buf, const Twiddles &tw, int lgmax,
+                                                const double2 *__restrict__ pre, int nv) {
+    constexpr int NBF = N / R;
+    constexpr int MAXB = (NBF + TPB - 1) / TPB;
+    constexpr bool ALL = (NBF % TPB == 0);
+    double2 v[MAXB][R];
+#pragma unroll
+    for (int b = 0; b < MAXB; b++) {
+        const int j = (threadIdx.x & (TPB - 1)) + b * TPB;
+        if (ALL || j < NBF) {
+            if constexpr (NBF % 8 == 0) {
+                const int jb = lds_ix(j);
+#pragma unroll
+                for (int r = 0; r < R; r++) v[b][r] = buf[jb + r * (NBF / 8) * 9];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; r++) v[b][r] = buf[lds_ix(j + r * NBF)];
+            }
+            if constexpr (PRE == kPreChirp) {
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    const int i = j + r * NBF;
+                    v[b][r] = (i < nv) ? cmul(v[b][r], pre[min(i, nv - 1)]) : make_double2(0.0, 0.0);
+                }
+            } else if constexpr (PRE == kPreKernelConj) {
+#pragma unroll
+                for (int r = 0; r < R; r++) v[b][r] = cconj(cmul(v[b][r], pre[j + r * NBF]));
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < MAXB; b++) {
+        const int j = (threadIdx.x & (TPB - 1)) + b * TPB;
+        if (ALL || j < NBF) {
+            const int kk = j & (Ns - 1);
+            if constexpr (PRE == kPreNone && Ns > 1) {
+                double2 wr[R];
+                wr[1] = tw(kk << (lgmax - ilog2c(Ns * R)));
+#pragma unroll
+                for (int r = 2; r < R; r++) wr[r] = cmul(wr[r / 2], wr[r - r / 2]);
+#pragma unroll
+                for (int r = 1; r < R; r++) v[b][r] = cmul(v[b][r], wr[r]);
+            }
+            small_dft<R>(v[b]);
+            const int base = (j - kk) * R + kk;
+            if constexpr (Ns % 8 == 0) {
+                const int bb = lds_ix(base);
+#pragma unroll
+                for (int r = 0; r < R; r++) buf[bb + r * (Ns / 8) * 9] = v[b][r];
+            } else if constexpr (Ns == 1 && R == 8) {
+#pragma unroll
+                for (int r = 0; r < R; r++) buf[9 * j + r] = v[b][r];  // lds_ix(8 j + r)
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; r++) buf[lds_ix(base + r * Ns)] = v[b][r];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// The passes of fft_stockham for length N: radix 8 while at least 8 remain, then 4 or 2.
+template <int TPB, int N, int Ns, int PRE>
+__device__ __forceinline__ void fft_passes_c(double2 *buf, const Twiddles &tw, int lgmax,
+                                             const double2 *__restrict__ pre, int nv) {
+    if constexpr (Ns < N) {
+        constexpr int left = N / Ns;
+        constexpr int R = left >= 8 ? 8 : left;
+        stockham_pass_c<TPB, N, R, Ns, (Ns == 1 ? PRE : kPreNone)>(buf, tw, lgmax, pre, nv);
+        fft_passes_c<TPB, N, Ns * R, PRE>(buf, tw, lgmax, pre, nv);
+    }
+}
+
+// ring_dft with the power-of-two length of the pair's transform (n itself, or Bluestein's M)
+// dispatched to compile-time lengths from TPB EPT down to MINC; shorter lengths take the
+// run-time passes.
+template <int TPB, int EPT, int N, int MINC>
+__device__ __forceinline__ bool ring_dft_fixed(double2 *buf, const PairFFT &pf, const Twiddles &tw,
+                                               int lgmax, const double2 *__restrict__ chirp,
+                                               const double2 *__restrict__ bhat) {
+    if constexpr (N < MINC) {
+        return false;
+    } else {
+        if (pf.fftlen == N) {
+            if (!pf.bluestein) {
+                fft_passes_c<TPB, N, 1, kPreNone>(buf, tw, lgmax, nullptr, 0);
+            } else {
+                fft_passes_c<TPB, N, 1, kPreChirp>(buf, tw, lgmax, chirp + pf.chirp_off, pf.nphi);
+                fft_passes_c<TPB, N, 1, kPreKernelConj>(buf, tw, lgmax, bhat + pf.bhat_off, N);
+            }
+            return true;
+        }
+        return ring_dft_fixed<TPB, EPT, N / 2, MINC>(buf, pf, tw, lgmax, chirp, bhat);
+    }
+}
+
 // Length-n forward DFT of elements 0..n-1 in place.  On return the transform value of bin k
 // is read with dft_bin(): element k for power-of-two n, c_k conj(element k) for Bluestein.
 template <int TPB, int EPT>
@@ -193,6 +302,17 @@ __device__ __forceinline__ void ring_dft(double2 *buf, const PairFFT &pf, const 
     // Both elementwise steps ride on the reads of the transforms' first passes.
     fft_stockham<TPB, EPT, kPreChirp>(buf, M, tw, fftmax, chirp + pf.chirp_off, n);
     fft_stockham<TPB, EPT, kPreKernelConj>(buf, M, tw, fftmax, bhat + pf.bhat_off, M);
+}
+
+// ring_dft on compile-time lengths where the pair's transform length allows (the results
+// equal ring_dft's bit for bit)
+template <int TPB, int EPT>
+__device__ __forceinline__ void ring_dft_c(double2 *buf, const PairFFT &pf, const Twiddles &tw,
+                                           int fftmax, const double2 *__restrict__ chirp,
+                                           const double2 *__restrict__ bhat) {
+    const int lgmax = __builtin_ctz(fftmax);
+    if (!ring_dft_fixed<TPB, EPT, TPB * EPT, 64>(buf, pf, tw, lgmax, chirp, bhat))
+        ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
 }
 
 __device__ __forceinline__ double2 dft_bin(const double2 *buf, const PairFFT &pf,

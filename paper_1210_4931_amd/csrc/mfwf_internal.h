@@ -58,6 +58,9 @@ struct Plan {
     int synth_variant = 0;  // index into the Legendre synthesis kernel variants
     int ana_variant = 0;    // index into the Legendre analysis kernel variants
     int ngroup;             // pair groups (waves per m) of the chosen analysis variant
+    int ring_group[2] = {1, 1};  // maps per workgroup of the columns ring step, per class
+    int gemm_ct[2] = {2, 2};     // largest column tile (x 64) of the analysis / synthesis GEMM
+    int tune_source = 0;         // 0 defaults, 1 autotuned (timed or cached), 3 forced
     int ngroup_max;         // largest pair-group count of any analysis variant
 
     // plan tables (device)
@@ -186,6 +189,10 @@ int launch_fft_inv_f32(const Plan &p, const float2 *phase, double *maps, int nb)
 int launch_fft_inv_fwd_cols(const Plan &p, const double *rho, double lam, double *smap, int nb);
 int fft_class_shape(const Plan &p, int c, int &ept);  // threads per workgroup of class c
 size_t fft_class_lds(const Plan &p, int c);           // dynamic LDS bytes of class c
+// maps per workgroup of the columns ring step of class c for nb maps, and its dynamic LDS
+int fft_cols_group(const Plan &p, int c, int nb);
+int fft_cols_group_max(const Plan &p, int c, int nb);
+size_t fft_cols_lds(const Plan &p, int c, int g);
 
 // legendre.hip (alm_scaled: c_lm-scaled coefficients; apart: sums of mu_lm X)
 int launch_leg_synth(const Plan &p, const double2 *alm_scaled, double2 *phase, int nb);

@@ -60,7 +60,7 @@ __device__ __forceinline__ void store_rows(const double2 *buf, const PairFFT &pf
                                            const Twiddles &tw, int fftmax,
                                            const double2 *__restrict__ chirp, int lmax,
                                            RingSeq<OutT, STRIDED> outN, RingSeq<OutT, STRIDED> outS) {
-    const int n = pf.nphi;
+    const int n = pf.nphi, tid = threadIdx.x & (TPB - 1);
     const bool equator = (pf.startS == pf.startN);
     // e^{-i m phi0} = e^{-i pi m / n} with a half shift: from the twiddle table when it holds
     // the 2n-th roots, else from the thread's first m by steps of e^{-i pi TPB / n} (a few
@@ -69,12 +69,12 @@ __device__ __forceinline__ void store_rows(const double2 *buf, const PairFFT &pf
     double2 phm = make_double2(1.0, 0.0), phstep = make_double2(1.0, 0.0);
     if (pf.half_shift && !tab) {
         double sn, cs;
-        sincospi((double)threadIdx.x / (double)n, &sn, &cs);
+        sincospi((double)tid / (double)n, &sn, &cs);
         phm = make_double2(cs, -sn);
         sincospi((double)TPB / (double)n, &sn, &cs);
         phstep = make_double2(cs, -sn);
     }
-    for (int m = threadIdx.x; m <= lmax; m += TPB) {
+    for (int m = tid; m <= lmax; m += TPB) {
         const int q = (n > lmax) ? 0 : m / n, k = m - q * n;  // no alias when n > lmax
         const int kr = (k == 0) ? 0 : n - k;
         const double2 X = dft_bin(buf, pf, chirp, k);
@@ -164,7 +164,7 @@ template <int TPB, int EPT, typename InT, bool STRIDED = false>
 __device__ __forceinline__ void fold_bins(double2 *buf, RingSeq<const InT, STRIDED> FN,
                                           RingSeq<const InT, STRIDED> FS, const PairFFT &pf,
                                           const Twiddles &tw, int fftmax, int lmax) {
-    const int n = pf.nphi;
+    const int n = pf.nphi, tid = threadIdx.x & (TPB - 1);
     const bool equator = (pf.startS == pf.startN);
     // alias-sum partials, used only with T > 1, i.e. n <= TPB / 2: after element TPB / 2
     double2 *partN = buf + lds_ix(TPB / 2);
@@ -190,7 +190,7 @@ __device__ __forceinline__ void fold_bins(double2 *buf, RingSeq<const InT, STRID
 #pragma unroll
         for (int u = 0; u < MU; u++) {
             if (u * TPB > lmax) break;  // uniform
-            const int m = min((int)threadIdx.x + u * TPB, lmax);
+            const int m = min(tid + u * TPB, lmax);
             fN[u] = FN[m];
             fS[u] = FS[m];
         }
@@ -208,7 +208,7 @@ __device__ __forceinline__ void fold_bins(double2 *buf, RingSeq<const InT, STRID
         double2 ph[MU], phm = make_double2(1.0, 0.0), phstep = make_double2(1.0, 0.0);
         if (pf.half_shift && !tab) {
             double sn, cs;
-            sincospi((double)threadIdx.x / (double)n, &sn, &cs);
+            sincospi((double)tid / (double)n, &sn, &cs);
             phm = make_double2(cs, sn);
             sincospi((double)TPB / (double)n, &sn, &cs);
             phstep = make_double2(cs, sn);
@@ -218,7 +218,7 @@ __device__ __forceinline__ void fold_bins(double2 *buf, RingSeq<const InT, STRID
             ph[u] = make_double2(1.0, 0.0);
             if (pf.half_shift) {
                 if (tab) {
-                    ph[u] = half_bin_phase(min((int)threadIdx.x + u * TPB, n - 1), n, tw, fftmax);
+                    ph[u] = half_bin_phase(min(tid + u * TPB, n - 1), n, tw, fftmax);
                 } else {
                     ph[u] = phm;
                     phm = cmul(phm, phstep);
@@ -227,14 +227,14 @@ __device__ __forceinline__ void fold_bins(double2 *buf, RingSeq<const InT, STRID
         }
 #pragma unroll
         for (int u = 0; u < EPT; u++) {
-            const int k = threadIdx.x + u * TPB;
+            const int k = tid + u * TPB;
             if (k < n)
                 buf[lds_ix(k)] = (k <= lmax) ? term(get_c(&fN[u]), get_c(&fS[u]), ph[u]) : make_double2(0.0, 0.0);
         }
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < MU; u++) {
-            const int m = threadIdx.x + u * TPB;
+            const int m = tid + u * TPB;
             if (m >= 1 && m <= lmax) {  // negative alias of bin n - m: sgn conj F(m)
                 const int k = n - m;
                 const double2 x = term(cscale(cconj(get_c(&fN[u])), sgn_step),
@@ -259,7 +259,7 @@ __device__ __forceinline__ void fold_bins(double2 *buf, RingSeq<const InT, STRID
             InT aN[CH], aS[CH], cN[CH], cS[CH];
 #pragma unroll
             for (int v = 0; v < CH; v++) {
-                const int kc = min((int)threadIdx.x + (u0 + v) * TPB, n - 1);
+                const int kc = min(tid + (u0 + v) * TPB, n - 1);
                 const int mpos = min(kc, lmax), mneg = min(n - kc, lmax);
                 aN[v] = FN[mpos];
                 aS[v] = FS[mpos];
@@ -268,7 +268,7 @@ __device__ __forceinline__ void fold_bins(double2 *buf, RingSeq<const InT, STRID
             }
 #pragma unroll
             for (int v = 0; v < CH; v++) {
-                const int k = threadIdx.x + (u0 + v) * TPB;
+                const int k = tid + (u0 + v) * TPB;
                 if (k >= n) continue;
                 const bool vp = k <= lmax, vn = n - k <= lmax;
                 double2 sN = cadd(vp ? get_c(&aN[v]) : zero, vn ? cscale(cconj(get_c(&cN[v])), sgn_step) : zero);
@@ -297,9 +297,9 @@ __device__ __forceinline__ void fold_bins(double2 *buf, RingSeq<const InT, STRID
         }
     }
     for (int k0 = 0; T > 1 && k0 < n; k0 += nbins_pass) {
-        const int k = k0 + threadIdx.x / T, t = threadIdx.x % T;
+        const int k = k0 + tid / T, t = tid % T;
         double2 sN = make_double2(0.0, 0.0), sS = make_double2(0.0, 0.0);
-        if (k < n && (int)threadIdx.x < nbins_pass * T) {
+        if (k < n && tid < nbins_pass * T) {
             // m = k + q n >= 0, q = t, t + T, ...
             double sg = (t & 1) ? sgn_step : 1.0;
             for (int m = k + t * n; m <= lmax; m += T * n, sg *= sg_stride) {
@@ -314,13 +314,13 @@ __device__ __forceinline__ void fold_bins(double2 *buf, RingSeq<const InT, STRID
             }
         }
         if (T > 1) {
-            partN[threadIdx.x] = sN;
-            partS[threadIdx.x] = sS;
+            partN[tid] = sN;
+            partS[tid] = sS;
             __syncthreads();
             if (t == 0 && k < n) {
                 for (int u = 1; u < T; u++) {
-                    sN = cadd(sN, partN[threadIdx.x + u]);
-                    sS = cadd(sS, partS[threadIdx.x + u]);
+                    sN = cadd(sN, partN[tid + u]);
+                    sS = cadd(sS, partS[tid + u]);
                 }
             }
             __syncthreads();
@@ -496,73 +496,267 @@ k_fft_inv_split_combine(double *__restrict__ maps, const double2 *__restrict__ s
 // and transformed back to the pair's pixels s (optionally stored to smap), the messenger
 // field t of Eq. (3) is formed from s, rho and M on the spot, and its transform overwrites
 // the columns with G = the analysis input.  The map s never travels through memory; the
-// arithmetic is that of k_fft_inv followed by k_fft_fwd<PIX>.  The 1-D grid (workgroup L
-// runs on XCD L mod 8) is laid out so that every XCD takes whole pairs, all maps of a pair
-// in a row, so that the 16 maps sharing a 128-byte column segment meet in one L2.
-template <int TPB, int EPT>
-__global__ void __launch_bounds__(TPB)
-k_fft_inv_fwd(float2 *__restrict__ data, int C2, int nmap, int npl, double *__restrict__ smap,
+// arithmetic is that of k_fft_inv followed by k_fft_fwd<PIX>, value for value.
+//
+// A workgroup takes G maps b0 .. b0 + G - 1 of one pair (G groups of TPB threads, one
+// transform each in its own LDS area): the column entries of those maps for one (m, ring)
+// are adjacent (8 G bytes), so the fold of the rings longer than lmax and the stores of the
+// analysis input move them with one vector access per (m, ring) instead of G separate
+// 8-byte pieces of one cache line from G workgroups.  The 1-D grid (workgroup L runs on XCD
+// L mod 8) hands every XCD whole pairs, all map groups of a pair in a row, so that the
+// groups sharing a 128-byte column segment meet in one L2.
+
+// e^{s i pi (tid + u' TPB) / n}, u' = sub + u G, as the per-map code forms it: a sincospi of
+// tid / n times u' steps of e^{s i pi TPB / n}, multiplied in order
+template <int TPB, int G>
+struct PhaseChain {
+    double2 cur, step;
+    __device__ __forceinline__ PhaseChain(int tid, int sub, int n, double sign) {
+        double sn, cs;
+        sincospi((double)tid / (double)n, &sn, &cs);
+        cur = make_double2(cs, sign * sn);
+        sincospi((double)TPB / (double)n, &sn, &cs);
+        step = make_double2(cs, sign * sn);
+        for (int k = 0; k < sub; k++) cur = cmul(cur, step);  // wave-uniform count
+    }
+    __device__ __forceinline__ double2 next() {  // value for u, then advance to u + 1
+        const double2 v = cur;
+#pragma unroll
+        for (int k = 0; k < G; k++) cur = cmul(cur, step);
+        return v;
+    }
+};
+
+template <int G>
+__device__ __forceinline__ void load_g(const float2 *p, float2 (&v)[G]) {
+    if constexpr (G == 1) {
+        v[0] = *p;
+    } else {
+#pragma unroll
+        for (int h = 0; h < G / 2; h++) {
+            const float4 q = reinterpret_cast<const float4 *>(p)[h];
+            v[2 * h] = make_float2(q.x, q.y);
+            v[2 * h + 1] = make_float2(q.z, q.w);
+        }
+    }
+}
+
+template <int G>
+__device__ __forceinline__ void store_g(float2 *p, const float2 (&v)[G]) {
+    if constexpr (G == 1) {
+        *p = v[0];
+    } else {
+#pragma unroll
+        for (int h = 0; h < G / 2; h++)
+            reinterpret_cast<float4 *>(p)[h] = make_float4(v[2 * h].x, v[2 * h].y, v[2 * h + 1].x, v[2 * h + 1].y);
+    }
+}
+
+// fold_bins for rings longer than lmax, for the G transforms of the workgroup at once
+// (buf + s area for map s): a thread reads the G maps' coefficients of its m together
+template <int TPB, int EPT, int G>
+__device__ __forceinline__ void fold_cols_group(double2 *buf, int area, const float2 *FN,
+                                                const float2 *FS, long cs, const PairFFT &pf,
+                                                const Twiddles &tw, int fftmax, int lmax) {
+    constexpr int MU = (EPT + G - 1) / G;  // bins per thread (n <= EPT TPB)
+    const int n = pf.nphi, tid = threadIdx.x & (TPB - 1), sub = threadIdx.x / TPB;
+    const bool equator = (pf.startS == pf.startN);
+    const double sgn_step = pf.half_shift ? -1.0 : 1.0;
+    float2 fN[MU][G], fS[MU][G];
+#pragma unroll
+    for (int u = 0; u < MU; u++) {
+        const int m = min((int)threadIdx.x + u * G * TPB, lmax);
+        load_g<G>(FN + (long)m * cs, fN[u]);
+        load_g<G>(FS + (long)m * cs, fS[u]);
+    }
+    auto term = [&](double2 gN, double2 gS, double2 ph) {
+        if (equator) gS = make_double2(0.0, 0.0);
+        if (pf.half_shift) {
+            gN = cmul(gN, ph);
+            gS = cmul(gS, ph);
+        }
+        return cconj(make_double2(gN.x - gS.y, gN.y + gS.x));
+    };
+    const bool tab = fftmax % (2 * n) == 0;
+    double2 ph[MU];
+    if (pf.half_shift && !tab) {
+        PhaseChain<TPB, G> chain(tid, sub, n, 1.0);
+#pragma unroll
+        for (int u = 0; u < MU; u++) ph[u] = chain.next();
+    } else {
+#pragma unroll
+        for (int u = 0; u < MU; u++)
+            ph[u] = pf.half_shift ? half_bin_phase(min((int)threadIdx.x + u * G * TPB, n - 1), n, tw, fftmax)
+                                  : make_double2(1.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < MU; u++) {
+        const int k = threadIdx.x + u * G * TPB;
+        if (k < n) {
+#pragma unroll
+            for (int s = 0; s < G; s++)
+                buf[s * area + lds_ix(k)] =
+                    (k <= lmax) ? term(get_c(&fN[u][s]), get_c(&fS[u][s]), ph[u]) : make_double2(0.0, 0.0);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < MU; u++) {
+        const int m = threadIdx.x + u * G * TPB;
+        if (m >= 1 && m <= lmax) {  // negative alias of bin n - m: sgn conj F(m)
+            const int k = n - m;
+#pragma unroll
+            for (int s = 0; s < G; s++) {
+                const double2 x = term(cscale(cconj(get_c(&fN[u][s])), sgn_step),
+                                       cscale(cconj(get_c(&fS[u][s])), sgn_step),
+                                       make_double2(-ph[u].x, ph[u].y));
+                buf[s * area + lds_ix(k)] = cadd(buf[s * area + lds_ix(k)], x);
+            }
+        }
+    }
+}
+
+// store_rows for the G transforms of the workgroup, into the columns (G maps adjacent)
+template <int TPB, int G>
+__device__ __forceinline__ void store_cols_group(const double2 *buf, int area, const PairFFT &pf,
+                                                 const Twiddles &tw, int fftmax,
+                                                 const double2 *__restrict__ chirp, int lmax,
+                                                 float2 *outN, float2 *outS, long cs) {
+    const int n = pf.nphi, tid = threadIdx.x & (TPB - 1), sub = threadIdx.x / TPB;
+    const bool equator = (pf.startS == pf.startN);
+    const bool tab = fftmax % (2 * n) == 0;
+    PhaseChain<TPB, G> chain(tid, sub, n, -1.0);  // used only with a half shift and !tab
+    for (int m = threadIdx.x; m <= lmax; m += G * TPB) {
+        const int q = (n > lmax) ? 0 : m / n, k = m - q * n;  // no alias when n > lmax
+        const int kr = (k == 0) ? 0 : n - k;
+        double2 ph = make_double2(1.0, 0.0);
+        if (pf.half_shift) {
+            if (tab) {
+                ph = cscale(cconj(half_bin_phase(k, n, tw, fftmax)), (q & 1) ? -1.0 : 1.0);
+            } else {
+                ph = chain.next();
+            }
+        }
+        double2 ck = make_double2(1.0, 0.0), ckr = ck;
+        if (pf.bluestein) {
+            ck = chirp[pf.chirp_off + k];
+            ckr = chirp[pf.chirp_off + kr];
+        }
+        float2 vN[G], vS[G];
+#pragma unroll
+        for (int s = 0; s < G; s++) {
+            const double2 bk = buf[s * area + lds_ix(k)], bkr = buf[s * area + lds_ix(kr)];
+            const double2 X = pf.bluestein ? cmul(ck, cconj(bk)) : bk;
+            const double2 Y = cconj(pf.bluestein ? cmul(ckr, cconj(bkr)) : bkr);
+            // X_N = (X_k + conj X_{-k}) / 2,  X_S = (X_k - conj X_{-k}) / (2i)
+            const double2 gN = make_double2(0.5 * (X.x + Y.x), 0.5 * (X.y + Y.y));
+            const double2 gS = make_double2(0.5 * (X.y - Y.y), -0.5 * (X.x - Y.x));
+            put_c(&vN[s], cmul(gN, ph));
+            put_c(&vS[s], cmul(gS, ph));
+        }
+        store_g<G>(outN + (long)m * cs, vN);
+        if (!equator) store_g<G>(outS + (long)m * cs, vS);
+    }
+}
+
+template <int TPB, int EPT, int G>
+__global__ void __launch_bounds__(TPB * G)
+k_fft_inv_fwd(float2 *__restrict__ data, int C2, int nmap, int ngrp, int npl, double *__restrict__ smap,
               const double *__restrict__ rho, const double *__restrict__ M, double lam,
               double tau, long mstride, const double *__restrict__ tau_b,
               const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
               const double2 *__restrict__ twlo, const double2 *__restrict__ twhi, int ntwhi,
               int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
               long npix, int nring, int nm, int lmax, int fftlen_class) {
-    extern __shared__ double2 buf[];
-    const int L = blockIdx.x, x = L & 7, sl = L >> 3, j = sl / nmap;
-    const int b = sl - j * nmap, pi = 8 * j + x;
+    extern __shared__ double2 lds[];
+    const int L = blockIdx.x, x = L & 7, sl = L >> 3, j = sl / ngrp;
+    const int g = sl - j * ngrp, pi = 8 * j + x;
     if (pi >= npl) return;  // whole workgroup, before any barrier
     const int p = plist[pi];
     const PairFFT pf = pfft[p];
     const int n = pf.nphi;
     const bool equator = (pf.startS == pf.startN);
-    const Twiddles tw = load_twiddles(buf, fft_area(fftlen_class, TPB), twlo, twhi, ntwhi);
+    const int area = fft_area(fftlen_class, TPB);
+    const Twiddles tw = load_twiddles(lds, G * area, twlo, twhi, ntwhi);
+    const int sub = threadIdx.x / TPB, tid = threadIdx.x & (TPB - 1);
+    double2 *buf = lds + sub * area;
+    const int b0 = g * G, b = b0 + sub;
+    const bool live = b < nmap;  // maps past the batch: zero columns, no pixel arrays
     const int pS = nring - 1 - p;
     const long cs = (long)nring * (C2 / 2);  // float2 elements from m to m + 1
-    float2 *FN = data + (long)p * (C2 / 2) + b;
-    float2 *FS = data + (long)pS * (C2 / 2) + b;
-    fold_bins<TPB, EPT>(buf, RingSeq<const float2, true>{FN, cs},
-                        RingSeq<const float2, true>{FS, cs}, pf, tw, fftmax, lmax);
+    float2 *FN = data + (long)p * (C2 / 2) + b0;
+    float2 *FS = data + (long)pS * (C2 / 2) + b0;
+    if (n > lmax) {
+        fold_cols_group<TPB, EPT, G>(lds, area, FN, FS, cs, pf, tw, fftmax, lmax);
+    } else {
+        fold_bins<TPB, EPT>(buf, RingSeq<const float2, true>{FN + sub, cs},
+                            RingSeq<const float2, true>{FS + sub, cs}, pf, tw, fftmax, lmax);
+    }
     __syncthreads();
-    ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
-    if (tau_b) tau = tau_b[b];
+    ring_dft_c<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
+    if (tau_b && live) tau = tau_b[b];
     const double lt = lam * tau, l1t = (lam - 1.0) * tau;
     const double *rp = rho + (long)b * npix;
     const double *mp = M + (long)b * mstride;
     double mN[EPT], mS[EPT], rN[EPT], rS[EPT];
 #pragma unroll
     for (int u = 0; u < EPT; u++) {
-        const int j = min((int)threadIdx.x + u * TPB, n - 1);
-        mN[u] = mp[pf.startN + j];
-        mS[u] = mp[pf.startS + j];
-        rN[u] = rp[pf.startN + j];
-        rS[u] = rp[pf.startS + j];
+        const int jj = min(tid + u * TPB, n - 1);
+        mN[u] = live ? mp[pf.startN + jj] : 0.0;
+        mS[u] = live ? mp[pf.startS + jj] : 0.0;
+        rN[u] = live ? rp[pf.startN + jj] : 0.0;
+        rS[u] = live ? rp[pf.startS + jj] : 0.0;
     }
-    auto pix = [&](double x, double m, double r) {
-        const double num = lt * r + (1.0 - tau * m) * x;
+    auto pix = [&](double xx, double m, double r) {
+        const double num = lt * r + (1.0 - tau * m) * xx;
         return (lam == 1.0) ? num : num / (1.0 + l1t * m);
     };
     double2 v[EPT];
 #pragma unroll
     for (int u = 0; u < EPT; u++) {
-        const int j = threadIdx.x + u * TPB;
-        const double2 x = cconj(dft_bin(buf, pf, chirp, min(j, n - 1)));  // (s_N, s_S) at j
-        if (smap && j < n) {
-            smap[(long)b * npix + pf.startN + j] = x.x;
-            if (!equator) smap[(long)b * npix + pf.startS + j] = x.y;
+        const int jj = tid + u * TPB;
+        const double2 xs = cconj(dft_bin(buf, pf, chirp, min(jj, n - 1)));  // (s_N, s_S) at jj
+        if (smap && live && jj < n) {
+            smap[(long)b * npix + pf.startN + jj] = xs.x;
+            if (!equator) smap[(long)b * npix + pf.startS + jj] = xs.y;
         }
-        v[u] = make_double2(pix(x.x, mN[u], rN[u]), equator ? 0.0 : pix(x.y, mS[u], rS[u]));
+        v[u] = make_double2(pix(xs.x, mN[u], rN[u]), equator ? 0.0 : pix(xs.y, mS[u], rS[u]));
     }
     __syncthreads();  // every read of the inverse transform is done
 #pragma unroll
     for (int u = 0; u < EPT; u++) {
-        const int j = threadIdx.x + u * TPB;
-        if (j < n) buf[lds_ix(j)] = v[u];
+        const int jj = tid + u * TPB;
+        if (jj < n) buf[lds_ix(jj)] = v[u];
     }
     __syncthreads();
-    ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
-    store_rows<TPB>(buf, pf, tw, fftmax, chirp, lmax, RingSeq<float2, true>{FN, cs},
-                    RingSeq<float2, true>{FS, cs});
+    ring_dft_c<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
+    store_cols_group<TPB, G>(lds, area, pf, tw, fftmax, chirp, lmax, FN, FS, cs);
+}
+
+// Largest number of maps per workgroup of the columns ring step for class c: as many
+// transforms as fit one CU's LDS and 1024 threads, at most 4, no more than the batch needs.
+int fft_cols_group_max(const Plan &p, int c, int nb) {
+    int ept;
+    const int tpb = fft_class_shape(p, c, ept);
+    const size_t area = sizeof(double2) * fft_area(p.fft_class_len[c], tpb);
+    const size_t tw = sizeof(double2) * (64 + p.fft_ntwhi);
+    int g = 1;
+    while (2 * g <= 4 && 2 * g * tpb <= 1024 && 2 * g * area + tw <= 160 * 1024 && g < nb) g *= 2;
+    return g;
+}
+
+// Maps per workgroup used: the plan's (tuned) choice, within what this batch allows.
+int fft_cols_group(const Plan &p, int c, int nb) {
+    const int gmax = fft_cols_group_max(p, c, nb);
+    int g = 1;
+    while (2 * g <= gmax && 2 * g <= p.ring_group[c]) g *= 2;
+    return g;
+}
+
+size_t fft_cols_lds(const Plan &p, int c, int g) {
+    int ept;
+    const int tpb = fft_class_shape(p, c, ept);
+    return sizeof(double2) * ((size_t)g * fft_area(p.fft_class_len[c], tpb) + 64 + p.fft_ntwhi);
 }
 
 // (threads per workgroup, elements per thread) of a class: 8 elements (one radix-8
@@ -722,16 +916,22 @@ int launch_fft_inv_fwd_cols(const Plan &p, const double *rho, double lam, double
         if (cnt == 0) continue;
         int ept;
         const int tpb = fft_class_shape(p, c, ept);
-        const dim3 grid(8 * nb * ((cnt + 7) / 8));  // whole pairs per XCD
-        const size_t lds = fft_class_lds(p, c);
+        const int g = fft_cols_group(p, c, nb);
+        const int ngrp = (nb + g - 1) / g;
+        const dim3 grid(8 * ngrp * ((cnt + 7) / 8));  // whole pairs per XCD
+        const size_t lds = fft_cols_lds(p, c, g);
         const int rs = p.nm32;  // unused by the kernel (no rows)
         float2 *data = reinterpret_cast<float2 *>(p.d_ph32);
-        if (tpb == 256)
-            hipLaunchKernelGGL((k_fft_inv_fwd<256, 8>), grid, dim3(256), lds, p.stream, data, p.C2, nb, cnt, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs));
-        else if (tpb == 512)
-            hipLaunchKernelGGL((k_fft_inv_fwd<512, 8>), grid, dim3(512), lds, p.stream, data, p.C2, nb, cnt, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs));
-        else
-            hipLaunchKernelGGL((k_fft_inv_fwd<1024, 8>), grid, dim3(1024), lds, p.stream, data, p.C2, nb, cnt, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs));
+#define MFWF_INVFWD(T, G)                                                                           \
+    hipLaunchKernelGGL((k_fft_inv_fwd<T, 8, G>), grid, dim3(T * G), lds, p.stream, data, p.C2, nb,  \
+                       ngrp, cnt, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs))
+        if (tpb == 256 && g == 4) MFWF_INVFWD(256, 4);
+        else if (tpb == 256 && g == 2) MFWF_INVFWD(256, 2);
+        else if (tpb == 256) MFWF_INVFWD(256, 1);
+        else if (tpb == 512 && g == 2) MFWF_INVFWD(512, 2);
+        else if (tpb == 512) MFWF_INVFWD(512, 1);
+        else MFWF_INVFWD(1024, 1);
+#undef MFWF_INVFWD
         MFWF_HIP(hipGetLastError());
     }
     return MFWF_OK;
@@ -752,8 +952,9 @@ static int fwd_lds(int bytes) {
     return MFWF_OK;
 }
 static int inv_fwd_lds(int bytes) {
-    const void *fns[] = {(const void *)k_fft_inv_fwd<256, 8>, (const void *)k_fft_inv_fwd<512, 8>,
-                         (const void *)k_fft_inv_fwd<1024, 8>};
+    const void *fns[] = {(const void *)k_fft_inv_fwd<256, 8, 1>, (const void *)k_fft_inv_fwd<256, 8, 2>,
+                         (const void *)k_fft_inv_fwd<256, 8, 4>, (const void *)k_fft_inv_fwd<512, 8, 1>,
+                         (const void *)k_fft_inv_fwd<512, 8, 2>, (const void *)k_fft_inv_fwd<1024, 8, 1>};
     for (const void *f : fns)
         MFWF_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
     return MFWF_OK;

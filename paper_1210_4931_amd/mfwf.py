@@ -59,7 +59,7 @@ EXPORTED = ["mfwf_plan_create", "mfwf_plan_destroy", "mfwf_set_covariances", "mf
             "mfwf_plan_work", "mfwf_last_error", "mfwf_server_create", "mfwf_server_submit",
             "mfwf_server_poll", "mfwf_server_wait", "mfwf_server_stats", "mfwf_server_destroy",
             "mfwf_server_pool_bytes", "mfwf_solve_cooled", "mfwf_set_covariances_beam",
-            "mfwf_remove_templates", "mfwf_solve_bounded", "mfwf_remove_templates_noalloc"]
+            "mfwf_remove_templates", "mfwf_solve_bounded", "mfwf_remove_templates_noalloc", "mfwf_plan_tuning"]
 
 
 class Request(ctypes.Structure):
@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH):
                                      ctypes.POINTER(SolveInfo)]
     L.mfwf_time_kernels.argtypes = [vp, ip, ip, dp]
     L.mfwf_plan_work.argtypes = [vp, dp]
+    L.mfwf_plan_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     L.mfwf_server_create.argtypes = [ip, ctypes.c_double, ctypes.POINTER(vp)]
     L.mfwf_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
     L.mfwf_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
@@ -372,6 +373,13 @@ class Plan:
         out = (ctypes.c_double * 4)()
         _check(_lib.mfwf_plan_work(self._h, out))
         return tuple(out)
+
+    def tuning(self) -> dict:
+        """Kernel shapes in use (autotuned, default or forced by MFWF_TUNE_FORCE)."""
+        out = (ctypes.c_int * 8)()
+        _check(_lib.mfwf_plan_tuning(self._h, out))
+        keys = ["synth", "ana", "g0", "g1", "cta", "cts", "source"]
+        return dict(zip(keys, list(out)[:7]))
 
     def time_kernels(self, nmaps=1, reps=10):
         """Mean ms per launch of [pixel, fft_fwd, leg_analysis, harmonic, leg_synth, fft_inv]."""

@@ -171,6 +171,13 @@ def config2(seed: int = 0, nside: int = 512, lmax: int = 1024, lscale: float = 8
                                np.sqrt(cl[ls]) * h, g, 900.0 / hits, mask)
 
 
+def batch_noise(b: int, npix: int) -> np.ndarray:
+    """Unit-white pixel noise of map b of the batched nside 512 benchmark (one signal, B noise
+    realisations): PCG64 seeded with 1000 + b.  Map b's data is sig + sqrt(noise_var) *
+    batch_noise(b), sig the synthesis of config2(0).signal_alm."""
+    return np.random.Generator(np.random.PCG64(1000 + b)).standard_normal(npix)
+
+
 def config4(seed: int = 0, nside: int = 256, lmax: int = 512, lscale: float = 800.0,
             ndisc: int = 100, band_z: float = 0.15, parent_nside: int = 512,
             parent_lmax: int = 1024) -> TemperatureWorkload:
