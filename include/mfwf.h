@@ -64,7 +64,8 @@ typedef enum {
 } mfwf_dtype;
 
 /*
- * Create a plan for HEALPix resolution nside (power of two, 1..2048; 1..1024 for MFWF_F32)
+ * Create a plan for HEALPix resolution nside (power of two, 1..2048; 1..1024 for MFWF_F32
+ * with spin 2)
  * and band limit lmax (1..4*nside).  spin: 0 = temperature only, 2 = temperature and
  * polarization (T, Q, U maps, T, E, B coefficients, 3x3 noise and signal blocks).
  * max_batch (>= 1): largest number of maps one call processes at once (larger calls are
@@ -74,9 +75,12 @@ typedef enum {
  * pair), the first l at which the normalised associated Legendre function exceeds 2^-100
  * together with its two starting values, and ring-FFT tables.  It allocates its device
  * workspaces up front (MFWF_F32 adds the FP32 lambda table, 4 bytes x ring pairs x
- * (lmax+1)(lmax+2)/2 roughly: 2.2 GB at nside 512 / lmax 1024, and column-major work
- * arrays for max_batch maps; with spin 2 also FP32 tables of the spin-2 functions
- * F+-_lm = ((2)lambda_lm +- (-2)lambda_lm)/2, two more tables of that size).  *out receives
+ * (lmax+1)(lmax+2)/2 roughly: 2.2 GB at nside 512 / lmax 1024, for nside <= 1024, and for
+ * temperature plans the FP64 state of the Legendre recurrence at every 16th l of each
+ * (m, ring pair), a quarter of the table's size, from which the contractions can generate
+ * lambda themselves (the only form above nside 1024: 36 GB at nside 2048 / lmax 4096);
+ * column-major work arrays for max_batch maps; with spin 2 also FP32 tables of the spin-2
+ * functions F+-_lm = ((2)lambda_lm +- (-2)lambda_lm)/2, two more tables of that size).  *out receives
  * the handle.  Ring transforms whose chirp-z convolution would exceed 8192 points (polar
  * rings of more than 4096 pixels, nside 2048) are split into four chirp-z transforms of a
  * quarter length each, with a device scratch of 32 bytes x ring pixels of those rings per
@@ -186,6 +190,12 @@ typedef struct {
                               at the last iteration; rows beyond history_rows are not
                               written                                                    */
     int history_rows;      /* capacity of history in rows                                */
+    int order;             /* FP32 form: 0 = chained iterations (each starts from the
+                              previous synthesis in the matrix-core columns; T, and T, Q,
+                              U up to nside 512), 1 = every iteration from the pixel map
+                              (forward transforms, layout change, contractions, layout
+                              change, inverse transforms).  Same values either way; 1
+                              exists to check that.  Ignored by FP64 plans.              */
 } mfwf_solve_opts;
 
 /* Per-map diagnostics after the last iteration (Eq. 6 and Sect. 2.2). */
@@ -346,15 +356,17 @@ int mfwf_plan_work(mfwf_plan plan, double *out4);
  * Kernel shapes the plan uses (host, 8 ints): [0] FP64 Legendre synthesis variant (0..8),
  * [1] analysis variant (0..5), [2] maps per workgroup of the batched form's ring step for
  * the shorter transforms and [3] for the longest (1, 2, 4), [4] largest column tile of the
- * analysis GEMM and [5] of the synthesis GEMM, in units of 64 columns (1, 2), [6] how they
- * were set: 0 defaults, 1 by the autotuner at plan creation (timed, or read from its cache),
- * 3 from the environment variable MFWF_TUNE_FORCE; [7] 0.  None of them changes a result of
- * the batched form; the FP64 Legendre variants add the ring pairs' partial sums in different
- * groupings.  The autotuner (MFWF_AUTOTUNE unset or not "0", plans of 256 ring pairs or
+ * analysis GEMM and [5] of the synthesis GEMM, in units of 64 columns (1, 2), [6] 1 if the
+ * temperature GEMMs generate lambda_lm from the FP64 recurrence (its state every 16 values
+ * of l, tabulated per plan) instead of reading the FP32 table (0; no table above nside 1024),
+ * [7] how they were set: 0 defaults, 1 by the autotuner at plan creation (timed, or read
+ * from its cache), 3 from the environment variable MFWF_TUNE_FORCE.  None of them changes a
+ * result of the batched form; the FP64 Legendre variants add the ring pairs' partial sums
+ * in different groupings.  The autotuner (MFWF_AUTOTUNE unset or not "0", plans of 256 ring pairs or
  * more) times every applicable value of each at plan creation and caches the choice per
  * (device, library build, nside, lmax, max_batch, dtype, spin) in $MFWF_TUNE_CACHE (default
  * $XDG_CACHE_HOME/mfwf/tune.txt or ~/.cache/mfwf/tune.txt).  MFWF_TUNE_FORCE =
- * "synth=3,ana=1,g0=2,g1=1,cta=1,cts=2" (any subset) sets them at plan creation for any
+ * "synth=3,ana=1,g0=2,g1=1,cta=1,cts=2,lamgen=1" (any subset) sets them at plan creation for any
  * plan size; a malformed value makes mfwf_plan_create fail with MFWF_EINVAL.
  */
 int mfwf_plan_tuning(mfwf_plan plan, int *out8);
@@ -405,8 +417,7 @@ int mfwf_server_create(int slots, double hbm_budget_gb, mfwf_server *out);
  * request (they are read when it is admitted and written when it retires).  ninv * mask
  * is checked here: MFWF_ENAN (negative or non-finite) or MFWF_ENOCOV (no observed pixel);
  * so is the data: MFWF_ENAN if it holds a NaN or Inf on an observed pixel;
- * MFWF_EINVAL for bad sizes or options (nside a power of two up to 2048, up to 1024 for
- * MFWF_F32 as in mfwf_plan_create). */
+ * MFWF_EINVAL for bad sizes or options (nside a power of two up to 2048). */
 int mfwf_server_submit(mfwf_server s, const mfwf_request *req, uint64_t *id);
 
 /* *done = 1 once the request's results are in the caller's buffers. */

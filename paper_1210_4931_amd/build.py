@@ -38,6 +38,13 @@ def torch_lib_dir() -> str:
     return os.path.join(os.path.dirname(spec.origin), "lib")
 
 
+# The ring transforms run in several kernels that must round alike (the per-map forward and
+# inverse transforms, the chained ring steps on the matrix-core columns, the split
+# transforms): no floating-point contraction there, only the fused multiply-adds the code
+# writes out.
+FILE_FLAGS = {"ringfft.hip": ["-ffp-contract=off"]}
+
+
 def source_hash() -> str:
     """SHA-256 (first 16 hex digits) of the library sources: keys the autotuner's cache, so
     that choices timed on other kernels are not reused."""
@@ -48,12 +55,14 @@ def source_hash() -> str:
         h.update(f.encode())
         h.update(open(os.path.join(CSRC, f), "rb").read())
     h.update(open(os.path.join(INCLUDE, "mfwf.h"), "rb").read())
+    h.update(repr((HIPFLAGS, FILE_FLAGS)).encode())  # the compile flags shape the kernels too
     return h.hexdigest()[:16]
 
 
 def _compile(src: str, src_hash: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *HIPFLAGS, "-I", INCLUDE, "-I", CSRC, "-DMFWF_SRC_HASH=\"%s\"" % src_hash,
+    cmd = [HIPCC, *HIPFLAGS, *FILE_FLAGS.get(src, []), "-I", INCLUDE, "-I", CSRC,
+           "-DMFWF_SRC_HASH=\"%s\"" % src_hash,
            "-c", os.path.join(CSRC, src), "-o", obj, "-Rpass-analysis=kernel-resource-usage"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -234,9 +234,9 @@ static void free_plan(Plan &p) {
     void *ptrs[] = {p.d_z,    p.d_A,    p.d_c,     p.d_lstart, p.d_seed,  p.d_pfft, p.d_plist,
                     p.d_tw,   p.d_twlo, p.d_twhi, p.d_chirp, p.d_bhat, p.d_mofs,   p.d_cl,    p.d_M, p.d_pc, p.d_tau,
                     p.d_rho,  p.d_t,    p.d_smap,  p.d_phase,  p.d_apart, p.d_salm,
-                    p.d_salm_prev, p.d_sp, p.d_red, p.d_diag, p.d_lam, p.d_loff, p.d_Lp,
+                    p.d_salm_prev, p.d_sp, p.d_red, p.d_diag, p.d_lam, p.d_lck, p.d_segoff, p.d_loff, p.d_Lp,
                     p.d_minls32, p.d_ana_items, p.d_syn_items, p.d_ana_tab, p.d_syn_tab, p.d_lofi, p.d_phf, p.d_ph32, p.d_a32,
-                    p.d_s32, p.d_fp, p.d_fm, p.d_ph32p, p.d_ph32r, p.d_ap32, p.d_ar32, p.d_seb32,
+                    p.d_s32, p.d_fp, p.d_fm, p.d_ph32p, p.d_ap32, p.d_ar32, p.d_seb32,
                     p.d_fftsplit};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
@@ -262,19 +262,21 @@ static int device_name(std::string &name) {
 //   g0, g1      maps per workgroup of the batched form's ring step, short-transform class
 //               and longest-transform class (1, 2 or 4; as LDS and 1024 threads allow)
 //   cta, cts    largest column tile of the analysis / synthesis GEMMs, x 64 columns (1 or 2)
+//   lamgen      temperature GEMMs: lambda read from the FP32 table (0) or generated from the
+//               FP64 recurrence's segment states (1; the only choice above nside 1024)
 // With MFWF_AUTOTUNE != 0 (default) a plan of at least 256 ring pairs times every value of
 // each knob that applies to it on its own stream (3 launches after a warm-up, on filled
 // work arrays) and keeps the fastest.  Choices are cached per (device, library source hash,
 // nside, lmax, max_batch, dtype, spin) in $MFWF_TUNE_CACHE, default
 // $XDG_CACHE_HOME/mfwf/tune.txt or ~/.cache/mfwf/tune.txt, so later plans of the same shape
-// reuse them.  MFWF_TUNE_FORCE="synth=3,ana=1,g0=2,g1=1,cta=1,cts=2" (any subset) sets knobs
+// reuse them.  MFWF_TUNE_FORCE="synth=3,ana=1,cta=1,lamgen=1" (any subset) sets knobs
 // directly, for every plan size, and skips timing.
 #ifndef MFWF_SRC_HASH
 #define MFWF_SRC_HASH "unversioned"
 #endif
 
-enum { kKnobSynth = 0, kKnobAna, kKnobG0, kKnobG1, kKnobCtA, kKnobCtS, kNumKnobs };
-static const char *const kKnobName[kNumKnobs] = {"synth", "ana", "g0", "g1", "cta", "cts"};
+enum { kKnobSynth = 0, kKnobAna, kKnobG0, kKnobG1, kKnobCtA, kKnobCtS, kKnobLamGen, kNumKnobs };
+static const char *const kKnobName[kNumKnobs] = {"synth", "ana", "g0", "g1", "cta", "cts", "lamgen"};
 
 static void get_knobs(const Plan &p, int k[kNumKnobs]) {
     k[kKnobSynth] = p.synth_variant;
@@ -283,6 +285,7 @@ static void get_knobs(const Plan &p, int k[kNumKnobs]) {
     k[kKnobG1] = p.ring_group[1];
     k[kKnobCtA] = p.gemm_ct[0];
     k[kKnobCtS] = p.gemm_ct[1];
+    k[kKnobLamGen] = p.lam_gen ? 1 : 0;
 }
 
 static bool knob_valid(int knob, int v) {
@@ -290,6 +293,7 @@ static bool knob_valid(int knob, int v) {
         case kKnobSynth: return v >= 0 && v < leg_synth_variants();
         case kKnobAna: return v >= 0 && v < leg_analysis_variants();
         case kKnobG0: case kKnobG1: return v == 1 || v == 2 || v == 4;
+        case kKnobLamGen: return v == 0 || v == 1;
         default: return v == 1 || v == 2;
     }
 }
@@ -301,6 +305,8 @@ static void set_knobs(Plan &p, const int k[kNumKnobs]) {
     p.ring_group[1] = k[kKnobG1];
     p.gemm_ct[0] = k[kKnobCtA];
     p.gemm_ct[1] = k[kKnobCtS];
+    // generation needs the segment states, the table the table; otherwise the one there is
+    p.lam_gen = p.d_lck != nullptr && (k[kKnobLamGen] || p.d_lam == nullptr);
 }
 
 static std::string tune_cache_path() {
@@ -444,6 +450,13 @@ static int autotune(Plan &p, const std::string &devname) {
                     }));
             }
         }
+        if (p.spin == 0 && p.d_lam && p.d_lck) {  // lambda read from the table or generated
+            const std::vector<int> gv = {0, 1};
+            MFWF_TRY(tune_knob(p, kKnobLamGen, gv, [&] {
+                MFWF_TRY(launch_gemm_analysis(p, B, p.d_a32, nullptr, 1.0, 1.0));
+                return launch_gemm_synthesis(p, B);
+            }));
+        }
         if (2 * B > 64) {  // more than 64 active columns: both column tiles apply
             const std::vector<int> cv = {1, 2};
             MFWF_TRY(tune_knob(p, kKnobCtA, cv, [&] { return launch_gemm_analysis(p, B, p.d_a32, nullptr, 1.0, 1.0); }));
@@ -542,7 +555,23 @@ static int setup_batched(Plan &p, const std::vector<int> &lstart, const std::vec
     std::vector<int> lofi(p.nalm);
     for (int m = 0; m < p.nm; m++)
         for (int l = m; l <= p.lmax; l++) lofi[mofs[m] + l - m] = l;
-    MFWF_TRY(dalloc(&p.d_lam, tot, "lambda table"));
+    // temperature: segment states for generating lambda inside the GEMMs (a quarter of the
+    // table's bytes); the table itself only where it fits comfortably (nside <= 1024), so
+    // that the autotuner can choose between reading it and generating
+    std::vector<long> segoff(p.nm);
+    long nseg = 0;
+    for (int m = 0; m < p.nm; m++) {
+        segoff[m] = nseg;
+        nseg += Lp[m] / 16;
+    }
+    const bool table = p.spin == 2 || p.nside <= 1024;
+    p.lam_gen = !table;
+    if (p.spin == 0) {
+        MFWF_TRY(dalloc(&p.d_lck, (size_t)nseg * p.Rp, "lambda segment states"));
+        MFWF_TRY(dalloc(&p.d_segoff, segoff.size(), "lambda segment offsets"));
+        MFWF_TRY(upload(p.d_segoff, segoff, p.stream));
+    }
+    if (table) MFWF_TRY(dalloc(&p.d_lam, tot, "lambda table"));
     MFWF_TRY(dalloc(&p.d_loff, loff.size(), "lambda offsets"));
     MFWF_TRY(dalloc(&p.d_Lp, Lp.size(), "lambda row lengths"));
     MFWF_TRY(dalloc(&p.d_minls32, mn32.size(), "start table 32"));
@@ -573,17 +602,16 @@ static int setup_batched(Plan &p, const std::vector<int> &lstart, const std::vec
         MFWF_TRY(dalloc(&p.d_fp, tot, "F+ table"));
         MFWF_TRY(dalloc(&p.d_fm, tot, "F- table"));
         MFWF_TRY(dalloc(&p.d_ph32p, ph, "Q, U ring Fourier FP32"));
-        MFWF_TRY(dalloc(&p.d_ph32r, ph, "F- synthesis FP32"));
         MFWF_TRY(dalloc(&p.d_ap32, al, "F+ analysis FP32"));
         MFWF_TRY(dalloc(&p.d_ar32, al, "F- analysis FP32"));
         MFWF_TRY(dalloc(&p.d_seb32, al, "E, B synthesis input FP32"));
-        float *zs[] = {p.d_ph32p, p.d_ph32r};
-        for (float *q : zs) MFWF_HIP(hipMemsetAsync(q, 0, sizeof(float) * ph, p.stream));
+        MFWF_HIP(hipMemsetAsync(p.d_ph32p, 0, sizeof(float) * ph, p.stream));
         float *za[] = {p.d_ap32, p.d_ar32, p.d_seb32};
         for (float *q : za) MFWF_HIP(hipMemsetAsync(q, 0, sizeof(float) * al, p.stream));
         MFWF_TRY(launch_pol_tables(p));
     } else {
-        MFWF_TRY(launch_lam_table(p));
+        if (p.d_lam) MFWF_TRY(launch_lam_table(p));
+        MFWF_TRY(launch_lam_ckpt(p));
     }
     return MFWF_OK;
 }
@@ -622,9 +650,9 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
                   Plan &p) {
     if (nside < 1 || nside > 2048 || !is_pow2(nside))
         return fail(MFWF_EINVAL, "nside must be a power of two in [1, 2048]");
-    if (dtype == MFWF_F32 && nside > 1024)
-        return fail(MFWF_EINVAL, "the batched FP32 form supports nside <= 1024 (its tables "
-                                 "outgrow the device above)");
+    if (dtype == MFWF_F32 && spin == 2 && nside > 1024)
+        return fail(MFWF_EINVAL, "the batched FP32 form with spin 2 supports nside <= 1024 (its "
+                                 "three function tables outgrow the device above)");
     if (lmax < 1 || lmax > 4 * nside) return fail(MFWF_EINVAL, "lmax must be in [1, 4 nside]");
     if (spin != 0 && spin != 2) return fail(MFWF_EINVAL, "spin must be 0 (T) or 2 (T, Q, U)");
     if (dtype != MFWF_F64 && dtype != MFWF_F32) return fail(MFWF_EINVAL, "dtype must be MFWF_F64 or MFWF_F32");
@@ -904,14 +932,22 @@ static int iteration_pol(Plan &p, const double *rho, int nb, double lam, bool ke
 // T, Q, U in the batched FP32 form: FP64 3x3 pixel update, transforms of 3 nb maps with FP32
 // rows, three analysis GEMMs and the 3x3 filter, three synthesis GEMMs
 static int iteration_pol_b(Plan &p, const double *rho, int nb, double lam, bool keep_prev) {
-    MFWF_TRY(launch_pixel_update_pol(rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, lam, p.tau, p.stream));
-    MFWF_TRY(launch_fft_fwd_f32(p, p.d_t, nullptr, 1.0, p.d_phf, 3 * nb));
-    MFWF_TRY(launch_rows_to_cols_pol(p, nb));
+    if (p.chain && p.chain_ready) {
+        // the previous synthesis (zero at the start) back to pixels, the 3x3 pixel update
+        // (Eq. 3) and the forward transforms, in one kernel on the matrix-core columns
+        MFWF_TRY(launch_fft_inv_fwd_pol_cols(p, rho, lam, nb));
+    } else {
+        MFWF_TRY(launch_pixel_update_pol(rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, lam, p.tau, p.stream));
+        MFWF_TRY(launch_fft_fwd_f32(p, p.d_t, nullptr, 1.0, p.d_phf, 3 * nb));
+        MFWF_TRY(launch_rows_to_cols_pol(p, nb));
+    }
     if (keep_prev) MFWF_TRY(launch_cols_to_alm_pol(p, p.d_salm_prev, nb));
     MFWF_TRY(pol_analysis_b(p, nb, lam * p.tau * p.omega, kPolFilter));
     if (keep_prev) MFWF_TRY(launch_cols_to_alm_pol(p, p.d_salm, nb));
-    MFWF_TRY(pol_synthesis_b(p, nb));
-    MFWF_TRY(launch_fft_inv_f32(p, p.d_phf, p.d_smap, 3 * nb));
+    const bool map = !p.chain || keep_prev;  // the map s of this iteration
+    MFWF_TRY(pol_synthesis_b(p, nb, map));
+    p.chain_ready = true;
+    if (map) MFWF_TRY(launch_fft_inv_f32(p, p.d_phf, p.d_smap, 3 * nb));
     return MFWF_OK;
 }
 
@@ -960,9 +996,16 @@ int plan_iteration(Plan &p, const double *rho, int nb, double lam) {
 }
 
 // After the last iteration: the FP32 form keeps s in its column layout; bring maps 0..nb-1
-// back to the FP64 per-map alm array (the FP64 path writes it every iteration).
+// back to the FP64 per-map alm array (the FP64 path writes it every iteration) and, when the
+// iterations are chained (the map s is never formed on the way), transform the last
+// synthesis back to the pixels of d_smap, as the last iteration of a standalone solve does.
 int plan_finish_alm(Plan &p, int nb) {
-    if (p.dtype == MFWF_F32) return launch_cols_to_alm(p, p.d_s32, p.d_salm, nb, 1.0);
+    if (p.dtype != MFWF_F32) return MFWF_OK;
+    MFWF_TRY(launch_cols_to_alm(p, p.d_s32, p.d_salm, nb, 1.0));
+    if (p.chain && p.spin == 0) {
+        MFWF_TRY(launch_cols_to_rows(p, nb));
+        MFWF_TRY(launch_fft_inv_f32(p, p.d_phf, p.d_smap, nb));
+    }
     return MFWF_OK;
 }
 
@@ -1031,14 +1074,22 @@ static int solve_chunk(Plan &p, const double *input, int nb, double *s_alm_out,
     MFWF_TRY(check_source_finite(p, rho, nb));
     MFWF_TRY(launch_fill(p.d_smap, nc * p.npix * nb, 0.0, p.stream));
     MFWF_TRY(launch_fill(reinterpret_cast<double *>(p.d_salm), 2 * nc * p.nalm * nb, 0.0, p.stream));
-    // batched temperature form: iterations chained through the synthesis columns, which
-    // start at zero (s = 0); the last iteration is a check, so d_smap holds the final map
+    // batched FP32 form (T; T, Q, U where the chained ring step fits): iterations chained
+    // through the synthesis columns, which start at zero (s = 0); the last iteration is a
+    // check, so d_smap holds the final map
     struct ChainOff {
         Plan &p;
         ~ChainOff() { p.chain = p.chain_ready = false; }
     } chain_off{p};
-    if (p.dtype == MFWF_F32 && p.spin == 0) {
+    if (o.order == 1) {
+        // every iteration from the pixel map
+    } else if (p.dtype == MFWF_F32 && p.spin == 0) {
         MFWF_HIP(hipMemsetAsync(p.d_ph32, 0, sizeof(float) * (size_t)p.nring * p.nm * p.C2, p.stream));
+        p.chain = p.chain_ready = true;
+    } else if (p.dtype == MFWF_F32 && fft_pol_chain_ok(p)) {  // T, Q, U: the synthesis of s = 0
+        const size_t cols = (size_t)p.nring * p.nm * p.C2;
+        MFWF_HIP(hipMemsetAsync(p.d_ph32, 0, sizeof(float) * cols, p.stream));
+        MFWF_HIP(hipMemsetAsync(p.d_ph32p, 0, sizeof(float) * 2 * cols, p.stream));
         p.chain = p.chain_ready = true;
     }
     if (p.dtype == MFWF_F32) {  // previous harmonic iterate = 0 (outside any graph capture)
@@ -1474,6 +1525,7 @@ int mfwf_solve(mfwf_plan plan, const double *input, int nmaps, double *s_alm_out
         if (o.n_stages < 0) return fail(MFWF_EINVAL, "n_stages < 0");
         if (o.n_check < 0) return fail(MFWF_EINVAL, "n_check < 0");
         if (o.history && o.history_rows < 0) return fail(MFWF_EINVAL, "history_rows < 0");
+        if (o.order != 0 && o.order != 1) return fail(MFWF_EINVAL, "order must be 0 or 1");
         if (o.n_stages > 0) {
             if (!o.lambda || !o.iters) return fail(MFWF_EINVAL, "schedule arrays are NULL");
             lam.assign(o.lambda, o.lambda + o.n_stages);
@@ -1612,9 +1664,9 @@ static int cooled_chunk(mfwf_plan plan, const double *data, int nb, double *s_al
                 if (q->spin == 2)
                     MFWF_HIP(hipMemsetAsync(q->d_seb32, 0, sizeof(float) * (size_t)q->nalm * 2 * q->C2, q->stream));
             }
-            // batched temperature form: chained iterations once the first one on this plan
-            // has run from the map
-            q->chain = (q->dtype == MFWF_F32 && q->spin == 0);
+            // batched FP32 form: chained iterations once the first one on this plan has run
+            // from the map
+            q->chain = (q->dtype == MFWF_F32 && (q->spin == 0 || fft_pol_chain_ok(*q)));
             q->chain_ready = false;
             cur = q;
         }
@@ -2001,8 +2053,7 @@ int mfwf_plan_tuning(mfwf_plan plan, int *out8) {
     int k[kNumKnobs];
     get_knobs(p, k);
     for (int q = 0; q < kNumKnobs; q++) out8[q] = k[q];
-    out8[6] = p.tune_source;
-    out8[7] = 0;
+    out8[7] = p.tune_source;
     return MFWF_OK;
 }
 
@@ -2029,7 +2080,7 @@ int mfwf_time_kernels(mfwf_plan plan, int nmaps, int reps, double *ms_out) {
                 case 4: f = [&] {
                     MFWF_TRY(launch_gemm_synthesis_on(p, nb, 2, p.d_lam, p.d_s32, p.d_ph32, 0));
                     MFWF_TRY(launch_gemm_synthesis_on(p, nb, 4, p.d_fp, p.d_seb32, p.d_ph32p, 0));
-                    return launch_gemm_synthesis_on(p, nb, 4, p.d_fm, p.d_seb32, p.d_ph32r, 1); }; break;
+                    return launch_gemm_synthesis_on(p, nb, 4, p.d_fm, p.d_seb32, p.d_ph32p, 1, 1); }; break;
                 default: f = [&] { MFWF_TRY(launch_cols_to_rows_pol(p, nb)); return launch_fft_inv_f32(p, p.d_phf, p.d_smap, 3 * nb); }; break;
             }
             float ms = 0.f;

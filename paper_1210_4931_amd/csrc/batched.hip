@@ -64,6 +64,93 @@ k_lam_table(const double *__restrict__ Atab, const double *__restrict__ ctab,
 }
 
 // ---------------------------------------------------------------------------------------
+// lambda rows generated inside the GEMMs (temperature batched form): instead of reading
+// the FP32 table the GEMMs run the FP64 recurrence of k_lam_table themselves, 16 rows at a
+// time, from its state at the start of every 16-row segment of a row, tabulated once per
+// plan (16 bytes per 16 table entries: a quarter of the table's size, and the only
+// per-(m, pair, l) data the GEMMs read).  The arithmetic and its order are k_lam_table's,
+// so the generated values equal the table's bit for bit.
+// ---------------------------------------------------------------------------------------
+// lck[(segoff[m] + s) Rp + p] = (mu_{l-1}, mu_{l-2}) entering row l = m + 16 s of pair p,
+// zero before the pair's start index (and for the padding pairs)
+__global__ void __launch_bounds__(64)
+k_lam_ckpt(const double *__restrict__ Atab, const long *__restrict__ mofs,
+           const int *__restrict__ lstart, const double2 *__restrict__ seed,
+           const double *__restrict__ zp, const int *__restrict__ Lp,
+           const long *__restrict__ segoff, double2 *__restrict__ lck, int lmax, int npair,
+           int Rp) {
+    const int p = blockIdx.x * 64 + threadIdx.x, m = blockIdx.y;
+    const int L = Lp[m];
+    double2 *out = lck + segoff[m] * Rp + p;
+    if (p >= npair) {
+        for (int r = 0; r < L; r += 16) out[(long)(r / 16) * Rp] = make_double2(0.0, 0.0);
+        return;
+    }
+    const long off = mofs[m] - m;
+    const int ls = lstart[(long)m * npair + p];
+    const double2 sd = seed[(long)m * npair + p];
+    const double z = zp[p];
+    double u1 = 0.0, u2 = 0.0;
+    for (int r = 0; r < L; r++) {
+        if ((r & 15) == 0) out[(long)(r / 16) * Rp] = make_double2(u1, u2);
+        const int l = m + r;
+        if (l <= lmax && l >= ls) {
+            double mu;
+            if (l == ls) {
+                mu = sd.y;
+                u1 = sd.x;
+            } else {
+                mu = fma(Atab[off + l] * z, u1, -u2);
+            }
+            u2 = u1;
+            u1 = mu;
+        }
+    }
+}
+
+// Rows l0 .. l0 + 15 of one pair from the segment state st = (u1, u2): the steps of
+// k_lam_table; A(r), c(r) give the coefficients A_lm, c_lm of row l0 + r; sink(q, v4)
+// receives rows 4 q .. 4 q + 3 as they are ready.
+template <typename FA, typename FC, typename FS>
+__device__ __forceinline__ void lam_rows16(double2 st, int ls, double2 sd, double z, int l0,
+                                           int lmax, FA A, FC c, FS sink) {
+    double u1 = st.x, u2 = st.y;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        float v[4];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int r = 4 * q + i, l = l0 + r;
+            float x = 0.f;
+            if (l <= lmax && l >= ls) {
+                double mu;
+                if (l == ls) {
+                    mu = sd.y;
+                    u1 = sd.x;
+                } else {
+                    mu = fma(A(r) * z, u1, -u2);
+                }
+                u2 = u1;
+                u1 = mu;
+                x = (float)(c(r) * mu);
+            }
+            v[i] = x;
+        }
+        sink(q, v);
+    }
+}
+
+// what a GEMM needs to generate its lambda rows
+struct LamGen {
+    const double2 *lck;    // segment states (k_lam_ckpt)
+    const long *segoff;    // [nm] first segment of each m
+    const int *lstart;     // [nm][npair]
+    const double2 *seed;   // [nm][npair]
+    const double *z;       // [npair]
+    const double *A, *c;   // [nalm]
+};
+
+// ---------------------------------------------------------------------------------------
 // Layout changes between the per-map ring-Fourier rows of the ring transforms,
 // [map][ring][m] (FP32 complex), and the contraction layout [m][ring][C2] with columns 2b
 // (re) and 2b + 1 (im) of map b.  One workgroup moves a tile of 64 values of m x 64 maps
@@ -95,6 +182,14 @@ k_rows_to_cols(const float2 *__restrict__ phf, float *__restrict__ ph32, int nri
         if (b < Bp && m < nm)
             *reinterpret_cast<float2 *>(ph32 + ((long)m * nring + ring) * C2 + 2 * b) = tile[bb][mm];
     }
+}
+
+// map b's two columns (2b, 2b + 1) of every (m, ring) row of the columns [m][ring][C2] set
+// to zero: a map whose chained iterations start from s = 0
+__global__ void __launch_bounds__(256)
+k_zero_map_cols(float *__restrict__ ph32, long nrows, int C2, int b) {
+    for (long i = blockIdx.x * 256L + threadIdx.x; i < nrows; i += (long)gridDim.x * 256)
+        *reinterpret_cast<float2 *>(ph32 + i * C2 + 2 * b) = make_float2(0.f, 0.f);
 }
 
 __global__ void __launch_bounds__(256)
@@ -175,9 +270,9 @@ __host__ __device__ constexpr int lds_floats(int main_floats) {
 // s = scale_s C_l / (C_l + lto) a (if s_out), rows [alm][C2].  Even l + m rows contract
 // G_N + G_S and odd rows G_N - G_S (a table with lambda's mirror symmetry); flip swaps the
 // two, for a table that is odd where lambda is even (the spin-2 F-).
-template <int NCT>
-__global__ void __launch_bounds__(256)
-k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
+template <int NCT, bool GEN>
+__global__ void __launch_bounds__(256, 3)
+k_gemm_analysis(const float *__restrict__ lam, LamGen gen, const long *__restrict__ loff,
                 const int *__restrict__ Lp, const int *__restrict__ minls32,
                 const int2 *__restrict__ items, const int *__restrict__ tab, int per_xcd,
                 const float *__restrict__ ph32, const long *__restrict__ mofs,
@@ -188,6 +283,7 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
     constexpr int CT = col_tile(NCT), NX = CT / 32;  // columns; X float4 loads per thread
     // lambda tile [pair][row] and X_0, X_1 tiles [pair][col]; reused by the epilogue
     __shared__ __align__(16) float lds[lds_floats(32 * (kAnaRows + 4) + 2 * 32 * (CT + 4))];
+    __shared__ double sAc[2][GEN ? kAnaRows : 1];  // A_lm, c_lm of the tile's rows (GEN)
     float (*sl)[kAnaRows + 4] = reinterpret_cast<float (*)[kAnaRows + 4]>(lds);
     float (*sx)[32][CT + 4] = reinterpret_cast<float (*)[32][CT + 4]>(lds + 32 * (kAnaRows + 4));
     const XcdTile xt = xcd_tile(tab, per_xcd, ncg);
@@ -208,15 +304,37 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
         for (int b = 0; b < NCT; b++)
 #pragma unroll
             for (int r = 0; r < 16; r++) acc[a][b][r] = 0.f;
-    const float *lrow = lam + loff[m] + kAnaRows * t;
+    const float *lrow = GEN ? nullptr : lam + loff[m] + kAnaRows * t;
     const int wcol = 32 * NCT * ch;  // first column of this wave within the tile
     const bool wave_on = (CT * cg + wcol) < ncols;
     floatx4 rl[4], rn[NX], rs[NX];
+    // GEN: thread (pair gpp = tid / 8, rows 16 (tid % 8) ..) of a chunk; its segment state,
+    // start index, seeds and z, loaded with the chunk's other operands
+    const int gpp = threadIdx.x >> 3, gk = threadIdx.x & 7;
+    double2 gst = make_double2(0.0, 0.0), gsd = gst;
+    double gz = 0.0;
+    int gls = lmax + 1;
+    if constexpr (GEN) {
+        const long aoff = mofs[m] - m;
+        if (threadIdx.x < kAnaRows) {
+            const int l = min(m + kAnaRows * t + (int)threadIdx.x, lmax);
+            sAc[0][threadIdx.x] = gen.A[aoff + l];
+            sAc[1][threadIdx.x] = gen.c[aoff + l];
+        }  // visible after the first barrier of the K loop
+    }
     auto load = [&](int pc) __attribute__((always_inline)) {
+        if constexpr (GEN) {
+            const int p = 32 * pc + gpp, pq = min(p, npair - 1);
+            gst = gen.lck[(gen.segoff[m] + 8 * t + gk) * (long)Rp + p];
+            gsd = gen.seed[(long)m * npair + pq];
+            gz = gen.z[pq];
+            gls = p < npair ? gen.lstart[(long)m * npair + pq] : lmax + 1;  // padding: zero rows
+        } else {
 #pragma unroll
-        for (int u = 0; u < 4; u++) {  // lambda: 32 pairs x 128 rows
-            const int e = threadIdx.x + 256 * u, pp = e >> 5, c4 = e & 31;
-            rl[u] = ld4(lrow + (long)(32 * pc + pp) * L + 4 * c4);
+            for (int u = 0; u < 4; u++) {  // lambda: 32 pairs x 128 rows
+                const int e = threadIdx.x + 256 * u, pp = e >> 5, c4 = e & 31;
+                rl[u] = ld4(lrow + (long)(32 * pc + pp) * L + 4 * c4);
+            }
         }
 #pragma unroll
         for (int u = 0; u < NX; u++) {  // ring-Fourier: 32 pairs x CT columns
@@ -238,10 +356,18 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
     if (pc < nchunk) load(pc);
     while (pc < nchunk) {
         __syncthreads();
+        if constexpr (GEN) {
+            lam_rows16(gst, gls, gsd, gz, m + kAnaRows * t + 16 * gk, lmax,
+                       [&](int r) { return sAc[0][16 * gk + r]; }, [&](int r) { return sAc[1][16 * gk + r]; },
+                       [&](int q, const float (&v)[4]) {
+                           st4(&sl[gpp][16 * gk + 4 * q], floatx4{v[0], v[1], v[2], v[3]});
+                       });
+        } else {
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const int e = threadIdx.x + 256 * u, pp = e >> 5, c4 = e & 31;
-            st4(&sl[pp][4 * c4], rl[u]);
+            for (int u = 0; u < 4; u++) {
+                const int e = threadIdx.x + 256 * u, pp = e >> 5, c4 = e & 31;
+                st4(&sl[pp][4 * c4], rl[u]);
+            }
         }
 #pragma unroll
         for (int u = 0; u < NX; u++) {
@@ -312,14 +438,14 @@ k_gemm_analysis(const float *__restrict__ lam, const long *__restrict__ loff,
 // synthesis: tile = (m, 64 ring pairs, 64 NCT columns); K loop over chunks of 64 values of
 // l.  Wave w: pairs 32 (w & 1) .. +31 of the tile, columns 32 NCT (w >> 1) .. +32 NCT - 1.  The south ring
 // gets E - O (lambda's mirror symmetry), or O - E with flip (the spin-2 F-).
-template <int NCT>
+template <int NCT, bool GEN>
 __global__ void __launch_bounds__(256, 3)
-k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
+k_gemm_synthesis(const float *__restrict__ lam, LamGen gen, const long *__restrict__ loff,
                  const int *__restrict__ Lp, const int *__restrict__ minls32,
                  const int2 *__restrict__ items, const int *__restrict__ tab, int per_xcd,
                  const float *__restrict__ s32, const long *__restrict__ mofs,
                  float *__restrict__ ph32, int lmax, int npair, int Rp, int nring, int nm,
-                 int C2, int ncols, int ncg, int flip) {
+                 int C2, int ncols, int ncg, int flip, int comb) {
     constexpr int CT = col_tile(NCT), NV = CT / 16;  // columns; coefficient float4 loads per thread
     // lambda tile [pair][l] (odd stride: no bank conflicts) and coefficient tile [l][col];
     // reused by the epilogue
@@ -345,14 +471,30 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
         for (int b = 0; b < NCT; b++)
 #pragma unroll
             for (int r = 0; r < 16; r++) acc[a][b][r] = 0.f;
-    const float *lrow = lam + loff[m] + (long)(64 * pt) * L;
+    const float *lrow = GEN ? nullptr : lam + loff[m] + (long)(64 * pt) * L;
     const long base = mofs[m];
     floatx4 rl[4], rv[NV];
+    // GEN: wave w generates rows 16 w .. 16 w + 15 of the chunk for pair 64 pt + lane; the
+    // rows' coefficients are the same for the whole wave (scalar loads)
+    const int gw = __builtin_amdgcn_readfirstlane(w);
+    double2 gst = make_double2(0.0, 0.0), gsd = gst;
+    double gz = 0.0;
+    int gls = lmax + 1;
+    if constexpr (GEN) {
+        const int p = 64 * pt + lane, pq = min(p, npair - 1);
+        gsd = gen.seed[(long)m * npair + pq];
+        gz = gen.z[pq];
+        gls = p < npair ? gen.lstart[(long)m * npair + pq] : lmax + 1;  // padding: zero rows
+    }
     auto load = [&](int rc) __attribute__((always_inline)) {
+        if constexpr (GEN) {
+            gst = gen.lck[(gen.segoff[m] + 4 * rc + gw) * (long)Rp + 64 * pt + lane];
+        } else {
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const int e = threadIdx.x + 256 * u, pp = e >> 4, c4 = e & 15;
-            rl[u] = ld4(lrow + (long)pp * L + 64 * rc + 4 * c4);
+            for (int u = 0; u < 4; u++) {
+                const int e = threadIdx.x + 256 * u, pp = e >> 4, c4 = e & 15;
+                rl[u] = ld4(lrow + (long)pp * L + 64 * rc + 4 * c4);
+            }
         }
 #pragma unroll
         for (int u = 0; u < NV; u++) {  // coefficients: 64 values of l x CT columns
@@ -367,13 +509,25 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
     if (first < nrc) load(first);
     for (int rc = first; rc < nrc; rc++) {
         __syncthreads();
+        if constexpr (GEN) {
+            const int l0 = m + 64 * rc + 16 * gw;
+            const long aoff = mofs[m] - m;
+            lam_rows16(gst, gls, gsd, gz, l0, lmax,
+                       [&](int r) { return gen.A[aoff + min(l0 + r, lmax)]; },
+                       [&](int r) { return gen.c[aoff + min(l0 + r, lmax)]; },
+                       [&](int q, const float (&v)[4]) {
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const int e = threadIdx.x + 256 * u, pp = e >> 4, c4 = e & 15;
-            sl[pp][4 * c4] = rl[u].x;
-            sl[pp][4 * c4 + 1] = rl[u].y;
-            sl[pp][4 * c4 + 2] = rl[u].z;
-            sl[pp][4 * c4 + 3] = rl[u].w;
+                           for (int i = 0; i < 4; i++) sl[lane][16 * gw + 4 * q + i] = v[i];
+                       });
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int e = threadIdx.x + 256 * u, pp = e >> 4, c4 = e & 15;
+                sl[pp][4 * c4] = rl[u].x;
+                sl[pp][4 * c4 + 1] = rl[u].y;
+                sl[pp][4 * c4 + 2] = rl[u].z;
+                sl[pp][4 * c4 + 3] = rl[u].w;
+            }
         }
 #pragma unroll
         for (int u = 0; u < NV; u++) {
@@ -430,8 +584,15 @@ k_gemm_synthesis(const float *__restrict__ lam, const long *__restrict__ loff,
             if (p >= npair) continue;
             const int ring = hs ? nring - 1 - p : p;
             if (hs && ring == p) continue;  // equator: one ring
-            const float4 v = *reinterpret_cast<const float4 *>(&stage[hs][row][4 * (lane & 7)]);
-            *reinterpret_cast<float4 *>(ph32 + ((long)m * nring + ring) * C2 + col) = v;
+            float4 v = *reinterpret_cast<const float4 *>(&stage[hs][row][4 * (lane & 7)]);
+            float *o = ph32 + ((long)m * nring + ring) * C2 + col;
+            if (comb) {
+                // spin 2: v = R' = F- x s_EB of one map (E re, E im, B re, B im) and o holds
+                // P' = F+ x s_EB: Q = -(P'_E + i R'_B), U = -(P'_B - i R'_E) over P'
+                const float4 P = *reinterpret_cast<const float4 *>(o);
+                v = make_float4(-P.x + v.w, -P.y - v.z, -P.z - v.y, -P.w + v.x);
+            }
+            *reinterpret_cast<float4 *>(o) = v;
         }
     }
 }
@@ -505,9 +666,25 @@ int launch_lam_table(const Plan &p) {
     return MFWF_OK;
 }
 
+int launch_lam_ckpt(const Plan &p) {
+    hipLaunchKernelGGL(k_lam_ckpt, dim3(p.Rp / 64, p.nm), dim3(64), 0, p.stream, p.d_A, p.d_mofs,
+                       p.d_lstart, p.d_seed, p.d_z, p.d_Lp, p.d_segoff, p.d_lck, p.lmax, p.npair,
+                       p.Rp);
+    MFWF_HIP(hipGetLastError());
+    return MFWF_OK;
+}
+
 int launch_rows_to_cols(const Plan &p, int nb) {
     hipLaunchKernelGGL(k_rows_to_cols, dim3(p.nring, (p.nm + 63) / 64, (p.Bp + 63) / 64), dim3(256), 0,
                        p.stream, p.d_phf, p.d_ph32, p.nring, p.nm, p.nm32, nb, p.Bp, p.C2);
+    MFWF_HIP(hipGetLastError());
+    return MFWF_OK;
+}
+
+int launch_zero_map_cols(const Plan &p, int b) {
+    const long nrows = (long)p.nm * p.nring;
+    hipLaunchKernelGGL(k_zero_map_cols, dim3((unsigned)std::min<long>((nrows + 255) / 256, 4096)), dim3(256),
+                       0, p.stream, p.d_ph32, nrows, p.C2, b);
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }
@@ -523,49 +700,67 @@ int launch_cols_to_rows(const Plan &p, int nb) {
 // whole 32-column MFMA tiles; never beyond the padded width (w Bp, a multiple of 32)
 static int active_cols(int nb, int w) { return 32 * ((w * nb + 31) / 32); }
 
+static LamGen lam_gen(const Plan &p) {
+    return LamGen{p.d_lck, p.d_segoff, p.d_lstart, p.d_seed, p.d_z, p.d_A, p.d_c};
+}
+
+// table == nullptr: lambda rows generated in the kernels (the plan's segment states)
 static int analysis_launch(const Plan &p, int nc, int C2, const float *table, const float *cols,
                            float *a_out, float *s_out, double scale_s, double lto,
                            const double *tau_b, double lto_per_tau, int flip) {
     const int nct = (nc <= 64 || p.gemm_ct[0] == 1) ? 1 : 2, ncg = (nc + col_tile(nct) - 1) / col_tile(nct);
     const dim3 grid(8 * p.ana_per_xcd * ncg), block(256);
-    if (nct == 1)
-        hipLaunchKernelGGL(k_gemm_analysis<1>, grid, block, 0, p.stream, table, p.d_loff, p.d_Lp,
-                           p.d_minls32, p.d_ana_items, p.d_ana_tab, p.ana_per_xcd, cols, p.d_mofs,
-                           p.d_cl, a_out, s_out, scale_s, lto, p.lmax, p.npair, p.Rp, p.nring,
-                           p.nm, C2, nc, ncg, tau_b, lto_per_tau, flip);
-    else
-        hipLaunchKernelGGL(k_gemm_analysis<2>, grid, block, 0, p.stream, table, p.d_loff, p.d_Lp,
-                           p.d_minls32, p.d_ana_items, p.d_ana_tab, p.ana_per_xcd, cols, p.d_mofs,
-                           p.d_cl, a_out, s_out, scale_s, lto, p.lmax, p.npair, p.Rp, p.nring,
-                           p.nm, C2, nc, ncg, tau_b, lto_per_tau, flip);
+    const LamGen g = lam_gen(p);
+#define MFWF_ANA(NCT, GEN)                                                                         \
+    hipLaunchKernelGGL((k_gemm_analysis<NCT, GEN>), grid, block, 0, p.stream, table, g, p.d_loff,   \
+                       p.d_Lp, p.d_minls32, p.d_ana_items, p.d_ana_tab, p.ana_per_xcd, cols,         \
+                       p.d_mofs, p.d_cl, a_out, s_out, scale_s, lto, p.lmax, p.npair, p.Rp,          \
+                       p.nring, p.nm, C2, nc, ncg, tau_b, lto_per_tau, flip)
+    if (table == nullptr) {
+        if (!p.d_lck) return fail(MFWF_EINVAL, "no lambda segment states in this plan");
+        if (nct == 1) MFWF_ANA(1, true);
+        else MFWF_ANA(2, true);
+    } else {
+        if (nct == 1) MFWF_ANA(1, false);
+        else MFWF_ANA(2, false);
+    }
+#undef MFWF_ANA
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }
 
 static int synthesis_launch(const Plan &p, int nc, int C2, const float *table, const float *s_in,
-                            float *out, int flip) {
+                            float *out, int flip, int comb) {
     const int nct = (nc <= 64 || p.gemm_ct[1] == 1) ? 1 : 2, ncg = (nc + col_tile(nct) - 1) / col_tile(nct);
     const dim3 grid(8 * p.syn_per_xcd * ncg), block(256);
-    if (nct == 1)
-        hipLaunchKernelGGL(k_gemm_synthesis<1>, grid, block, 0, p.stream, table, p.d_loff, p.d_Lp,
-                           p.d_minls32, p.d_syn_items, p.d_syn_tab, p.syn_per_xcd, s_in, p.d_mofs,
-                           out, p.lmax, p.npair, p.Rp, p.nring, p.nm, C2, nc, ncg, flip);
-    else
-        hipLaunchKernelGGL(k_gemm_synthesis<2>, grid, block, 0, p.stream, table, p.d_loff, p.d_Lp,
-                           p.d_minls32, p.d_syn_items, p.d_syn_tab, p.syn_per_xcd, s_in, p.d_mofs,
-                           out, p.lmax, p.npair, p.Rp, p.nring, p.nm, C2, nc, ncg, flip);
+    const LamGen g = lam_gen(p);
+#define MFWF_SYN(NCT, GEN)                                                                          \
+    hipLaunchKernelGGL((k_gemm_synthesis<NCT, GEN>), grid, block, 0, p.stream, table, g, p.d_loff,   \
+                       p.d_Lp, p.d_minls32, p.d_syn_items, p.d_syn_tab, p.syn_per_xcd, s_in,          \
+                       p.d_mofs, out, p.lmax, p.npair, p.Rp, p.nring, p.nm, C2, nc, ncg, flip, comb)
+    if (table == nullptr) {
+        if (!p.d_lck) return fail(MFWF_EINVAL, "no lambda segment states in this plan");
+        if (nct == 1) MFWF_SYN(1, true);
+        else MFWF_SYN(2, true);
+    } else {
+        if (nct == 1) MFWF_SYN(1, false);
+        else MFWF_SYN(2, false);
+    }
+#undef MFWF_SYN
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }
 
 int launch_gemm_analysis(const Plan &p, int nb, float *a_out, float *s_out, double scale_s,
                          double lto, double lto_per_tau) {
-    return analysis_launch(p, active_cols(nb, 2), p.C2, p.d_lam, p.d_ph32, a_out, s_out, scale_s,
+    return analysis_launch(p, active_cols(nb, 2), p.C2, p.lam_gen ? nullptr : p.d_lam, p.d_ph32,
+                           a_out, s_out, scale_s,
                            lto, s_out ? p.d_tau : nullptr, lto_per_tau, 0);
 }
 
 int launch_gemm_synthesis(const Plan &p, int nb) {
-    return synthesis_launch(p, active_cols(nb, 2), p.C2, p.d_lam, p.d_s32, p.d_ph32, 0);
+    return synthesis_launch(p, active_cols(nb, 2), p.C2, p.lam_gen ? nullptr : p.d_lam, p.d_s32,
+                            p.d_ph32, 0, 0);
 }
 
 // Raw analysis sums a_out[alm][w Bp] = table x cols[m][ring][w Bp] for nb maps of w columns
@@ -575,10 +770,12 @@ int launch_gemm_analysis_raw(const Plan &p, int nb, int w, const float *table, c
                            nullptr, 0.0, flip);
 }
 
-// Synthesis out[m][ring][w Bp] = table x s_in[alm][w Bp] for nb maps of w columns
+// Synthesis out[m][ring][w Bp] = table x s_in[alm][w Bp] for nb maps of w columns; comb
+// (w = 4): out holds P' and receives (Q, U) formed from it and this product R'
 int launch_gemm_synthesis_on(const Plan &p, int nb, int w, const float *table, const float *s_in,
-                             float *out, int flip) {
-    return synthesis_launch(p, active_cols(nb, w), w * p.Bp, table, s_in, out, flip);
+                             float *out, int flip, int comb) {
+    if (comb && w != 4) return fail(MFWF_EINVAL, "combined synthesis needs four columns per map");
+    return synthesis_launch(p, active_cols(nb, w), w * p.Bp, table, s_in, out, flip, comb);
 }
 
 int launch_alm_to_cols(const Plan &p, const double2 *alm, float *x32, int nb, int mode) {

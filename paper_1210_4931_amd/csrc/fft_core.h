@@ -8,8 +8,11 @@
 
 namespace mfwf {
 
+// complex product with its two fused multiply-adds written out: the ring transforms are
+// compiled without floating-point contraction, so that every kernel that runs them (per-map,
+// chained on the columns, split) rounds each operation alike
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return make_double2(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) {

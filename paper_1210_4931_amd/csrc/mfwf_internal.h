@@ -117,6 +117,11 @@ struct Plan {
     int Bp = 0;                  // maps padded to 16
     int C2 = 0;                  // columns = 2 Bp (re, im of each map)
     float *d_lam = nullptr;      // lambda_lm(z_p) FP32, rows [m][pair][l - m] padded to 128
+                                 // (null when the temperature GEMMs generate their rows)
+    bool lam_gen = false;        // temperature GEMMs generate lambda from d_lck instead of d_lam
+    double2 *d_lck = nullptr;    // recurrence state entering every 16-row segment of the rows,
+                                 // [(segoff[m] + seg) Rp + pair] (temperature FP32 plans)
+    long *d_segoff = nullptr;    // [nm] first segment of m
     long *d_loff = nullptr;      // [nm] offset of m's rows
     int *d_Lp = nullptr;         // [nm] padded row length
     int *d_minls32 = nullptr;    // [nm][Rp/32] smallest start index in each 32-pair chunk
@@ -139,8 +144,7 @@ struct Plan {
     // batched FP32 form with spin 2 (T, Q, U); T uses the arrays above
     float *d_fp = nullptr;       // F+_lm(z_p) FP32, rows like d_lam
     float *d_fm = nullptr;       // F-_lm(z_p) FP32
-    float *d_ph32p = nullptr;    // [nm][nring][2 C2] Q, U ring-Fourier (analysis); F+ synthesis out
-    float *d_ph32r = nullptr;    // [nm][nring][2 C2] F- synthesis out
+    float *d_ph32p = nullptr;    // [nm][nring][2 C2] Q, U ring-Fourier (analysis input; synthesis out)
     float *d_ap32 = nullptr;     // [nalm][2 C2] F+ analysis sums
     float *d_ar32 = nullptr;     // [nalm][2 C2] F- analysis sums
     float *d_seb32 = nullptr;    // [nalm][2 C2] E, B synthesis input
@@ -187,6 +191,10 @@ int launch_fft_inv_f32(const Plan &p, const float2 *phase, double *maps, int nb)
 // synthesis columns d_ph32 -> maps s (to smap if not null) -> t of Eq. (3) -> the columns of
 // its forward transform, in place (one iteration's ring steps without the map in memory)
 int launch_fft_inv_fwd_cols(const Plan &p, const double *rho, double lam, double *smap, int nb);
+// T, Q, U batched form: one iteration's ring steps on the columns d_ph32 / d_ph32p from the
+// synthesis columns d_ph32 / d_ph32p (chained iterations), where fft_pol_chain_ok
+bool fft_pol_chain_ok(const Plan &p);
+int launch_fft_inv_fwd_pol_cols(const Plan &p, const double *rho, double lam, int nb);
 int fft_class_shape(const Plan &p, int c, int &ept);  // threads per workgroup of class c
 size_t fft_class_lds(const Plan &p, int c);           // dynamic LDS bytes of class c
 // maps per workgroup of the columns ring step of class c for nb maps, and its dynamic LDS
@@ -204,8 +212,10 @@ int leg_analysis_pairs_per_lane(int v);
 
 // batched.hip (FP32 form)
 int launch_lam_table(const Plan &p);
+int launch_lam_ckpt(const Plan &p);  // d_lck from the recurrence
 int launch_rows_to_cols(const Plan &p, int nb);  // d_phf -> d_ph32
 int launch_cols_to_rows(const Plan &p, int nb);  // d_ph32 -> d_phf
+int launch_zero_map_cols(const Plan &p, int b);  // map b's columns of d_ph32 = 0
 int launch_gemm_analysis(const Plan &p, int nb, float *a_out, float *s_out, double scale_s,
                          double lto, double lto_per_tau = 0.0);
 int launch_gemm_synthesis(const Plan &p, int nb);
@@ -215,18 +225,18 @@ int launch_cols_to_alm(const Plan &p, const float *x32, double2 *alm, int nb, do
 int launch_gemm_analysis_raw(const Plan &p, int nb, int w, const float *table, const float *cols,
                              float *a_out, int flip);
 int launch_gemm_synthesis_on(const Plan &p, int nb, int w, const float *table, const float *s_in,
-                             float *out, int flip);
+                             float *out, int flip, int comb = 0);
 
 // polbatched.hip (batched FP32 form, spin 2)
 enum PolCombineMode { kPolFilter = 0, kPolRaw = 1 };
 int launch_pol_tables(const Plan &p);
 int launch_rows_to_cols_pol(const Plan &p, int nb);            // d_phf -> d_ph32, d_ph32p
-int launch_cols_to_rows_pol(const Plan &p, int nb);            // d_ph32, d_ph32p, d_ph32r -> d_phf
+int launch_cols_to_rows_pol(const Plan &p, int nb);            // d_ph32, d_ph32p -> d_phf
 int launch_pol_combine(const Plan &p, double lto, int mode);   // -> d_s32, d_seb32
 int launch_alm_to_cols_pol(const Plan &p, const double2 *alm, int nb);  // -> d_s32, d_seb32
 int launch_cols_to_alm_pol(const Plan &p, double2 *alm, int nb);        // d_s32, d_seb32 ->
 int pol_analysis_b(const Plan &p, int nb, double lto, int mode);
-int pol_synthesis_b(const Plan &p, int nb);
+int pol_synthesis_b(const Plan &p, int nb, bool rows = true);
 
 // polar.hip (spin 2: maps [B][3][npix], alm [B][3][nalm], rows [3B][nring][nm])
 int pol_ngroup(const Plan &p);

@@ -23,6 +23,7 @@
 // [3B][nring][m] (the per-map transforms run on 3B maps); M [npix][6] packed symmetric
 // (TT, TQ, TU, QQ, QU, UU); spectra [4][lmax+1] (TT, EE, BB, TE).
 #include "leg_core.h"
+#include "sym3.h"
 
 namespace mfwf {
 
@@ -391,21 +392,6 @@ static int pgrid(long n) {
     return (int)g;
 }
 
-struct Sym3 {
-    double a, b, c, d, e, f;  // [[a, b, c], [b, d, e], [c, e, f]]
-};
-
-__device__ __forceinline__ Sym3 load_sym3(const double *__restrict__ M6, long p) {
-    const double *q = M6 + 6 * p;
-    return Sym3{q[0], q[1], q[2], q[3], q[4], q[5]};
-}
-
-__device__ __forceinline__ void sym3_mv(const Sym3 &M, const double x[3], double y[3]) {
-    y[0] = M.a * x[0] + M.b * x[1] + M.c * x[2];
-    y[1] = M.b * x[0] + M.d * x[1] + M.e * x[2];
-    y[2] = M.c * x[0] + M.e * x[1] + M.f * x[2];
-}
-
 __device__ __forceinline__ double sym3_det(const Sym3 &M) {
     return M.a * (M.d * M.f - M.e * M.e) - M.b * (M.b * M.f - M.e * M.c) + M.c * (M.b * M.e - M.d * M.c);
 }
@@ -541,16 +527,11 @@ __global__ void k_pixel_update_pol(const double *__restrict__ rho, const double 
         const long b = i / npix, p = i - b * npix;
         const Sym3 M = load_sym3(M6, p);
         const long o = 3 * b * npix + p;
-        double s[3] = {smap[o], smap[o + npix], smap[o + 2 * npix]}, Ms[3], r[3];
-        sym3_mv(M, s, Ms);
-        for (int k = 0; k < 3; k++) r[k] = lt * rho[o + k * npix] + s[k] - tau * Ms[k];
-        if (lam != 1.0) {
-            const Sym3 A{1.0 + l1t * M.a, l1t * M.b, l1t * M.c, 1.0 + l1t * M.d, l1t * M.e, 1.0 + l1t * M.f};
-            double x[3];
-            sym3_solve(A, r, x);
-            for (int k = 0; k < 3; k++) r[k] = x[k];
-        }
-        for (int k = 0; k < 3; k++) t[o + k * npix] = r[k];
+        const double s[3] = {smap[o], smap[o + npix], smap[o + 2 * npix]};
+        const double r[3] = {rho[o], rho[o + npix], rho[o + 2 * npix]};
+        double x[3];
+        pol_messenger_pixel(M, s, r, lam, lt, l1t, tau, x);
+        for (int k = 0; k < 3; k++) t[o + k * npix] = x[k];
     }
 }
 

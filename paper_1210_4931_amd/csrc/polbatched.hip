@@ -111,36 +111,32 @@ k_rows_to_cols_pol(const float2 *__restrict__ phf, float *__restrict__ colT,
     }
 }
 
-// T rows from colT; Q = -(P'_E + i R'_B), U = -(P'_B - i R'_E) from the F+ and F- synthesis
-// outputs colP = (P'_E, P'_B) and colR = (R'_E, R'_B).
+// T rows from colT; Q and U rows from colQU = (Q, U) per map (formed by the F- synthesis's
+// epilogue from P' and R').
 __global__ void __launch_bounds__(256)
-k_cols_to_rows_pol(const float *__restrict__ colT, const float *__restrict__ colP,
-                   const float *__restrict__ colR, float2 *__restrict__ phf, int nring, int nm,
-                   int rs, int nb, int Bp) {
+k_cols_to_rows_pol(const float *__restrict__ colT, const float *__restrict__ colQU,
+                   float2 *__restrict__ phf, int nring, int nm, int rs, int nb, int Bp) {
     __shared__ float2 tile[3][64][32 + 1];  // [component][m][map]
     const int ring = blockIdx.x, m0 = 64 * blockIdx.y, b0 = 32 * blockIdx.z;
     const long C2 = 2L * Bp;
     float2 vt[8];
-    float4 vp[8], vr[8];
+    float4 vq[8];
 #pragma unroll
     for (int u = 0; u < 8; u++) {
         const int e = threadIdx.x + 256 * u, mm = e >> 5, bb = e & 31;
         const int b = min(b0 + bb, nb - 1), m = min(m0 + mm, nm - 1);
         const long row = (long)m * nring + ring;
         vt[u] = *reinterpret_cast<const float2 *>(colT + row * C2 + 2 * b);
-        vp[u] = *reinterpret_cast<const float4 *>(colP + row * 2 * C2 + 4 * b);
-        vr[u] = *reinterpret_cast<const float4 *>(colR + row * 2 * C2 + 4 * b);
+        vq[u] = *reinterpret_cast<const float4 *>(colQU + row * 2 * C2 + 4 * b);
     }
 #pragma unroll
     for (int u = 0; u < 8; u++) {
         const int e = threadIdx.x + 256 * u, mm = e >> 5, bb = e & 31;
         const bool on = b0 + bb < nb && m0 + mm < nm;
-        const float4 P = vp[u], R = vr[u];
-        // P = (E re, E im, B re, B im) of P', likewise R
         const float2 z = make_float2(0.f, 0.f);
         tile[0][mm][bb] = on ? vt[u] : z;
-        tile[1][mm][bb] = on ? make_float2(-P.x + R.w, -P.y - R.z) : z;
-        tile[2][mm][bb] = on ? make_float2(-P.z - R.y, -P.w + R.x) : z;
+        tile[1][mm][bb] = on ? make_float2(vq[u].x, vq[u].y) : z;  // Q
+        tile[2][mm][bb] = on ? make_float2(vq[u].z, vq[u].w) : z;  // U
     }
     __syncthreads();
 #pragma unroll
@@ -281,7 +277,7 @@ int launch_rows_to_cols_pol(const Plan &p, int nb) {
 
 int launch_cols_to_rows_pol(const Plan &p, int nb) {
     hipLaunchKernelGGL(k_cols_to_rows_pol, dim3(p.nring, (p.nm + 63) / 64, (nb + 31) / 32),
-                       dim3(256), 0, p.stream, p.d_ph32, p.d_ph32p, p.d_ph32r, p.d_phf, p.nring,
+                       dim3(256), 0, p.stream, p.d_ph32, p.d_ph32p, p.d_phf, p.nring,
                        p.nm, p.nm32, nb, p.Bp);
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
@@ -319,12 +315,14 @@ int pol_analysis_b(const Plan &p, int nb, double lto, int mode) {
     return launch_pol_combine(p, lto, mode);
 }
 
-// The three synthesis GEMMs from d_s32, d_seb32 and the regrouping into T, Q, U rows d_phf.
-int pol_synthesis_b(const Plan &p, int nb) {
+// The three synthesis GEMMs from d_s32, d_seb32: T into d_ph32, P' into d_ph32p, then R' with
+// (Q, U) formed from P' and R' in its epilogue over d_ph32p; rows: then the regrouping into
+// T, Q, U rows d_phf.
+int pol_synthesis_b(const Plan &p, int nb, bool rows) {
     MFWF_TRY(launch_gemm_synthesis_on(p, nb, 2, p.d_lam, p.d_s32, p.d_ph32, 0));
     MFWF_TRY(launch_gemm_synthesis_on(p, nb, 4, p.d_fp, p.d_seb32, p.d_ph32p, 0));
-    MFWF_TRY(launch_gemm_synthesis_on(p, nb, 4, p.d_fm, p.d_seb32, p.d_ph32r, 1));
-    return launch_cols_to_rows_pol(p, nb);
+    MFWF_TRY(launch_gemm_synthesis_on(p, nb, 4, p.d_fm, p.d_seb32, p.d_ph32p, 1, 1));
+    return rows ? launch_cols_to_rows_pol(p, nb) : MFWF_OK;
 }
 
 }  // namespace mfwf

@@ -30,8 +30,10 @@
 // chirp-z transform would outgrow LDS (nside 2048) form a third, split into four shorter
 // transforms (below).
 #include <mutex>
+#include <type_traits>
 
 #include "fft_core.h"
+#include "sym3.h"
 
 namespace mfwf {
 
@@ -41,6 +43,18 @@ __device__ __forceinline__ double2 get_c(const double2 *q) { return *q; }
 __device__ __forceinline__ double2 get_c(const float2 *q) {
     const float2 v = *q;
     return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ double2 get_v(const double2 &v) { return v; }
+__device__ __forceinline__ double2 get_v(const float2 &v) { return make_double2(v.x, v.y); }
+
+// Eq. (3) at one pixel: t = [lam tau rho + (1 - tau M) s] / [1 + (lam - 1) tau M] with
+// lt = lam tau, l1t = (lam - 1) tau.  Every product-sum is an explicit fma, so that each
+// kernel that forms t (the forward transforms with the update fused, the chained ring step,
+// the split transforms) rounds it alike whatever the compiler contracts around it.
+__device__ __forceinline__ double messenger_pixel(double s, double m, double r, double lam,
+                                                  double lt, double l1t, double tau) {
+    const double num = fma(fma(-tau, m, 1.0), s, lt * r);
+    return (lam == 1.0) ? num : num / fma(l1t, m, 1.0);
 }
 
 // The coefficients m = 0, 1, ... of one ring: a row (consecutive) or a column of the
@@ -141,8 +155,7 @@ k_fft_fwd(const double *__restrict__ maps, const double *__restrict__ rho,
         if constexpr (!PIX) {
             return x;
         } else {
-            const double num = lt * r + (1.0 - tau * m) * x;
-            return (lam == 1.0) ? num : num / (1.0 + l1t * m);
+            return messenger_pixel(x, m, r, lam, lt, l1t, tau);
         }
     };
 #pragma unroll
@@ -160,10 +173,10 @@ k_fft_fwd(const double *__restrict__ maps, const double *__restrict__ rho,
 
 // Fold the ring-Fourier rows FN, FS of a pair into the bins of its inverse transform, in
 // LDS (x_j = sum_k X_k e^{+2 pi i j k / n} is then conj(DFT(conj X))_j with X = B_N + i B_S).
-template <int TPB, int EPT, typename InT, bool STRIDED = false>
-__device__ __forceinline__ void fold_bins(double2 *buf, RingSeq<const InT, STRIDED> FN,
-                                          RingSeq<const InT, STRIDED> FS, const PairFFT &pf,
+template <int TPB, int EPT, typename Seq>
+__device__ __forceinline__ void fold_bins(double2 *buf, Seq FN, Seq FS, const PairFFT &pf,
                                           const Twiddles &tw, int fftmax, int lmax) {
+    using InT = std::remove_cv_t<std::remove_reference_t<decltype(FN[0])>>;
     const int n = pf.nphi, tid = threadIdx.x & (TPB - 1);
     const bool equator = (pf.startS == pf.startN);
     // alias-sum partials, used only with T > 1, i.e. n <= TPB / 2: after element TPB / 2
@@ -276,13 +289,13 @@ __device__ __forceinline__ void fold_bins(double2 *buf, RingSeq<const InT, STRID
                 if (n <= lmax) {
                     double sg = sgn_step;
                     for (int m = k + n; m <= lmax; m += n, sg *= sgn_step) {
-                        sN = cadd(sN, cscale(get_c(&FN[m]), sg));
-                        sS = cadd(sS, cscale(get_c(&FS[m]), sg));
+                        sN = cadd(sN, cscale(get_v(FN[m]), sg));
+                        sS = cadd(sS, cscale(get_v(FS[m]), sg));
                     }
                     sg = 1.0;  // sgn_step^2
                     for (int mm = 2 * n - k; mm <= lmax; mm += n) {
-                        sN = cadd(sN, cscale(cconj(get_c(&FN[mm])), sg));
-                        sS = cadd(sS, cscale(cconj(get_c(&FS[mm])), sg));
+                        sN = cadd(sN, cscale(cconj(get_v(FN[mm])), sg));
+                        sS = cadd(sS, cscale(cconj(get_v(FS[mm])), sg));
                         sg *= sgn_step;
                     }
                 }
@@ -303,14 +316,14 @@ __device__ __forceinline__ void fold_bins(double2 *buf, RingSeq<const InT, STRID
             // m = k + q n >= 0, q = t, t + T, ...
             double sg = (t & 1) ? sgn_step : 1.0;
             for (int m = k + t * n; m <= lmax; m += T * n, sg *= sg_stride) {
-                sN = cadd(sN, cscale(get_c(&FN[m]), sg));
-                if (!equator) sS = cadd(sS, cscale(get_c(&FS[m]), sg));
+                sN = cadd(sN, cscale(get_v(FN[m]), sg));
+                if (!equator) sS = cadd(sS, cscale(get_v(FS[m]), sg));
             }
             // m = k + q n < 0, q = -1 - t, -1 - t - T, ...: F(m) = conj F(-m)
             sg = ((t + 1) & 1) ? sgn_step : 1.0;
             for (int mm = (t + 1) * n - k; mm <= lmax; mm += T * n, sg *= sg_stride) {
-                sN = cadd(sN, cscale(cconj(get_c(&FN[mm])), sg));
-                if (!equator) sS = cadd(sS, cscale(cconj(get_c(&FS[mm])), sg));
+                sN = cadd(sN, cscale(cconj(get_v(FN[mm])), sg));
+                if (!equator) sS = cadd(sS, cscale(cconj(get_v(FS[mm])), sg));
             }
         }
         if (T > 1) {
@@ -375,14 +388,17 @@ k_fft_inv(const InT *__restrict__ phase, double *__restrict__ maps,
 // k_fft_inv), k_fft_split_sub from those bins, k_fft_inv_split_combine to the pixels.
 
 // Z_r of one (row, pair, r): grid (row, pair of the class, r); FROM_MAP: x = t_N + i t_S from
-// maps, else x = the folded bins in the scratch area
-template <int TPB, int EPT, bool FROM_MAP>
+// maps (PIX: t the messenger field of Eq. (3) formed from s = maps, rho and M, as k_fft_fwd
+// forms it), else x = the folded bins in the scratch area
+template <int TPB, int EPT, bool FROM_MAP, bool PIX = false>
 __global__ void __launch_bounds__(TPB)
 k_fft_split_sub(const double *__restrict__ maps, double2 *__restrict__ scratch, long sstride,
                 int sub_area, const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
                 const double2 *__restrict__ twlo, const double2 *__restrict__ twhi, int ntwhi,
                 int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
-                long npix) {
+                long npix, const double *__restrict__ rho = nullptr,
+                const double *__restrict__ M = nullptr, double lam = 1.0, double tau = 0.0,
+                long mstride = 0, const double *__restrict__ tau_b = nullptr) {
     extern __shared__ double2 buf[];
     const int p = plist[blockIdx.y], b = blockIdx.x, r = blockIdx.z;
     const PairFFT pf = pfft[p];
@@ -395,10 +411,21 @@ k_fft_split_sub(const double *__restrict__ maps, double2 *__restrict__ scratch, 
     double2 *G = scratch + ((long)b * gridDim.y + blockIdx.y) * sstride;
     double2 *Z = G + sstride / 2 + (long)r * i;
     const double *sp = maps + (long)b * npix;
+    if (PIX && tau_b) tau = tau_b[b];
+    const double lt = lam * tau, l1t = (lam - 1.0) * tau;
+    const double *rp = rho + (long)b * npix;
+    const double *mp = M + (long)b * mstride;
+    auto pix = [&](long q) {
+        if constexpr (!PIX) {
+            return sp[q];
+        } else {
+            return messenger_pixel(sp[q], mp[q], rp[q], lam, lt, l1t, tau);
+        }
+    };
     for (int j = threadIdx.x; j < i; j += TPB) {
         const int jj = 4 * j + r;
         if constexpr (FROM_MAP)
-            buf[lds_ix(j)] = make_double2(sp[pf.startN + jj], equator ? 0.0 : sp[pf.startS + jj]);
+            buf[lds_ix(j)] = make_double2(pix(pf.startN + jj), equator ? 0.0 : pix(pf.startS + jj));
         else
             buf[lds_ix(j)] = G[jj];
     }
@@ -425,14 +452,15 @@ __device__ __forceinline__ void split_combine(const double2 *Z, int n, F f) {
 }
 
 // forward, second step: the combined spectrum in LDS, stored as ring-Fourier rows
-template <int TPB, int EPT, typename OutT>
+// ([row][ring][nm]) or, COLS, into the matrix-core columns ([m][ring][C2], map b at 2b)
+template <int TPB, int EPT, typename OutT, bool COLS = false>
 __global__ void __launch_bounds__(TPB)
 k_fft_fwd_split_combine(OutT *__restrict__ phase, const double2 *__restrict__ scratch,
                         long sstride, const PairFFT *__restrict__ pfft,
                         const int *__restrict__ plist, const double2 *__restrict__ twlo,
                         const double2 *__restrict__ twhi, int ntwhi, int fftmax,
                         const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
-                        long npix, int nring, int nm, int lmax, int fftlen_class) {
+                        long npix, int nring, int nm, int lmax, int fftlen_class, int C2 = 0) {
     extern __shared__ double2 buf[];
     const int p = plist[blockIdx.y], b = blockIdx.x;
     PairFFT pf = pfft[p];
@@ -441,30 +469,44 @@ k_fft_fwd_split_combine(OutT *__restrict__ phase, const double2 *__restrict__ sc
     split_combine<TPB>(Z, pf.nphi, [&](int k, double2 X) { buf[lds_ix(k)] = X; });
     __syncthreads();
     pf.bluestein = 0;  // the spectrum sits in LDS in natural order
-    store_rows<TPB>(buf, pf, tw, fftmax, chirp, lmax,
-                    RingSeq<OutT, false>{phase + ((long)b * nring + p) * nm, 1},
-                    RingSeq<OutT, false>{phase + ((long)b * nring + (nring - 1 - p)) * nm, 1});
+    if constexpr (COLS) {
+        const long cs = (long)nring * (C2 / 2);
+        store_rows<TPB>(buf, pf, tw, fftmax, chirp, lmax,
+                        RingSeq<OutT, true>{phase + (long)p * (C2 / 2) + b, cs},
+                        RingSeq<OutT, true>{phase + (long)(nring - 1 - p) * (C2 / 2) + b, cs});
+    } else {
+        store_rows<TPB>(buf, pf, tw, fftmax, chirp, lmax,
+                        RingSeq<OutT, false>{phase + ((long)b * nring + p) * nm, 1},
+                        RingSeq<OutT, false>{phase + ((long)b * nring + (nring - 1 - p)) * nm, 1});
+    }
     (void)bhat;
     (void)npix;
 }
 
 // inverse, first step: the folded bins (as k_fft_inv leaves them before its transform) to
 // the scratch area
-template <int TPB, int EPT, typename InT>
+template <int TPB, int EPT, typename InT, bool COLS = false>
 __global__ void __launch_bounds__(TPB)
 k_fft_inv_split_fold(const InT *__restrict__ phase, double2 *__restrict__ scratch, long sstride,
                      const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
                      const double2 *__restrict__ twlo, const double2 *__restrict__ twhi,
                      int ntwhi, int fftmax, const double2 *__restrict__ chirp,
                      const double2 *__restrict__ bhat, long npix, int nring, int nm, int lmax,
-                     int fftlen_class) {
+                     int fftlen_class, int C2 = 0) {
     extern __shared__ double2 buf[];
     const int p = plist[blockIdx.y], b = blockIdx.x;
     const PairFFT pf = pfft[p];
     const Twiddles tw = load_twiddles(buf, fft_area(fftlen_class, TPB), twlo, twhi, ntwhi);
-    const RingSeq<const InT, false> FN{phase + ((long)b * nring + p) * nm, 1};
-    const RingSeq<const InT, false> FS{phase + ((long)b * nring + (nring - 1 - p)) * nm, 1};
-    fold_bins<TPB, EPT>(buf, FN, FS, pf, tw, fftmax, lmax);
+    if constexpr (COLS) {  // the matrix-core columns [m][ring][C2], map b at 2b
+        const long cs = (long)nring * (C2 / 2);
+        fold_bins<TPB, EPT>(buf, RingSeq<const InT, true>{phase + (long)p * (C2 / 2) + b, cs},
+                            RingSeq<const InT, true>{phase + (long)(nring - 1 - p) * (C2 / 2) + b, cs},
+                            pf, tw, fftmax, lmax);
+    } else {
+        const RingSeq<const InT, false> FN{phase + ((long)b * nring + p) * nm, 1};
+        const RingSeq<const InT, false> FS{phase + ((long)b * nring + (nring - 1 - p)) * nm, 1};
+        fold_bins<TPB, EPT>(buf, FN, FS, pf, tw, fftmax, lmax);
+    }
     __syncthreads();
     double2 *G = scratch + ((long)b * gridDim.y + blockIdx.y) * sstride;
     for (int j = threadIdx.x; j < pf.nphi; j += TPB) G[j] = buf[lds_ix(j)];
@@ -708,8 +750,7 @@ k_fft_inv_fwd(float2 *__restrict__ data, int C2, int nmap, int ngrp, int npl, do
         rS[u] = live ? rp[pf.startS + jj] : 0.0;
     }
     auto pix = [&](double xx, double m, double r) {
-        const double num = lt * r + (1.0 - tau * m) * xx;
-        return (lam == 1.0) ? num : num / (1.0 + l1t * m);
+        return messenger_pixel(xx, m, r, lam, lt, l1t, tau);
     };
     double2 v[EPT];
 #pragma unroll
@@ -731,6 +772,97 @@ k_fft_inv_fwd(float2 *__restrict__ data, int C2, int nmap, int ngrp, int npl, do
     __syncthreads();
     ring_dft_c<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
     store_cols_group<TPB, G>(lds, area, pf, tw, fftmax, chirp, lmax, FN, FS, cs);
+}
+
+// One T, Q, U iteration's ring steps in one pass over a pair and map b (batched FP32 form),
+// on the matrix-core columns: T [m][ring][C2] (map b at float2 b) and (Q, U) [m][ring][2 C2]
+// (map b at float2 2b, 2b + 1).  The synthesis (T, Q, U) is folded and transformed back to
+// the pair's pixels one component at a time, the three s values of each pixel kept in
+// registers; the 3x3 messenger update of Eq. (3) forms t; each component of t is transformed
+// forward and overwrites its columns with the analysis input.  The arithmetic is that of the
+// regrouping into rows, k_fft_inv, k_pixel_update_pol and k_fft_fwd, value for value.  One
+// transform area of LDS; TPB <= 512 (registers).
+template <int TPB, int EPT>
+__global__ void __launch_bounds__(TPB)
+k_fft_inv_fwd_pol(float *__restrict__ colT, float *__restrict__ colP, int C2, int nmap, int npl, const double *__restrict__ rho,
+                  const double *__restrict__ M6, double lam, double tau,
+                  const PairFFT *__restrict__ pfft, const int *__restrict__ plist,
+                  const double2 *__restrict__ twlo, const double2 *__restrict__ twhi, int ntwhi,
+                  int fftmax, const double2 *__restrict__ chirp, const double2 *__restrict__ bhat,
+                  long npix, int nring, int nm, int lmax, int fftlen_class) {
+    extern __shared__ double2 lds[];
+    const int L = blockIdx.x, x = L & 7, sl = L >> 3, j = sl / nmap;
+    const int b = sl - j * nmap, pi = 8 * j + x;
+    if (pi >= npl) return;  // whole workgroup, before any barrier
+    const int p = plist[pi];
+    const PairFFT pf = pfft[p];
+    const int n = pf.nphi, tid = threadIdx.x;
+    const bool equator = (pf.startS == pf.startN);
+    const Twiddles tw = load_twiddles(lds, fft_area(fftlen_class, TPB), twlo, twhi, ntwhi);
+    double2 *buf = lds;
+    const int pS = nring - 1 - p;
+    const long csT = (long)nring * (C2 / 2), csP = (long)nring * C2;  // float2 per step of m
+    float2 *TN = reinterpret_cast<float2 *>(colT) + (long)p * (C2 / 2) + b;
+    float2 *TS = reinterpret_cast<float2 *>(colT) + (long)pS * (C2 / 2) + b;
+    float2 *QN = reinterpret_cast<float2 *>(colP) + (long)p * C2 + 2 * b;
+    float2 *QS = reinterpret_cast<float2 *>(colP) + (long)pS * C2 + 2 * b;
+    // (s_N, s_S) of the thread's pixels per component, then (t_N, t_S)
+    double2 sT[EPT], sQ[EPT], sU[EPT];
+    auto inverse = [&](RingSeq<const float2, true> FN, RingSeq<const float2, true> FS,
+                       double2 (&sv)[EPT]) __attribute__((always_inline)) {
+        fold_bins<TPB, EPT>(buf, FN, FS, pf, tw, fftmax, lmax);
+        __syncthreads();
+        ring_dft_c<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
+#pragma unroll
+        for (int u = 0; u < EPT; u++) sv[u] = cconj(dft_bin(buf, pf, chirp, min(tid + u * TPB, n - 1)));
+        __syncthreads();  // every read of this component's transform is done
+    };
+    inverse(RingSeq<const float2, true>{TN, csT}, RingSeq<const float2, true>{TS, csT}, sT);
+    inverse(RingSeq<const float2, true>{QN, csP}, RingSeq<const float2, true>{QS, csP}, sQ);
+    inverse(RingSeq<const float2, true>{QN + 1, csP}, RingSeq<const float2, true>{QS + 1, csP}, sU);
+    const double lt = lam * tau, l1t = (lam - 1.0) * tau;
+    const double *rp = rho + 3L * b * npix;
+#pragma unroll
+    for (int u = 0; u < EPT; u++) {
+        const int jj = tid + u * TPB;
+        if (jj >= n) continue;
+        {
+            const long q = pf.startN + jj;
+            const double s3[3] = {sT[u].x, sQ[u].x, sU[u].x};
+            const double r3[3] = {rp[q], rp[q + npix], rp[q + 2 * npix]};
+            double t3[3];
+            pol_messenger_pixel(load_sym3(M6, q), s3, r3, lam, lt, l1t, tau, t3);
+            sT[u].x = t3[0];
+            sQ[u].x = t3[1];
+            sU[u].x = t3[2];
+        }
+        if (!equator) {
+            const long q = pf.startS + jj;
+            const double s3[3] = {sT[u].y, sQ[u].y, sU[u].y};
+            const double r3[3] = {rp[q], rp[q + npix], rp[q + 2 * npix]};
+            double t3[3];
+            pol_messenger_pixel(load_sym3(M6, q), s3, r3, lam, lt, l1t, tau, t3);
+            sT[u].y = t3[0];
+            sQ[u].y = t3[1];
+            sU[u].y = t3[2];
+        }
+    }
+    auto forward = [&](const double2 (&tv)[EPT], RingSeq<float2, true> GN, RingSeq<float2, true> GS)
+                       __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < EPT; u++) {
+            const int jj = tid + u * TPB;
+            if (jj < n) buf[lds_ix(jj)] = make_double2(tv[u].x, equator ? 0.0 : tv[u].y);
+        }
+        __syncthreads();
+        ring_dft_c<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
+        store_rows<TPB>(buf, pf, tw, fftmax, chirp, lmax, GN, GS);
+        __syncthreads();  // every read of this transform is done before the next is written
+    };
+    forward(sT, RingSeq<float2, true>{TN, csT}, RingSeq<float2, true>{TS, csT});
+    forward(sQ, RingSeq<float2, true>{QN, csP}, RingSeq<float2, true>{QS, csP});
+    forward(sU, RingSeq<float2, true>{QN + 1, csP}, RingSeq<float2, true>{QS + 1, csP});
+    (void)nm;
 }
 
 // Largest number of maps per workgroup of the columns ring step for class c: as many
@@ -798,33 +930,39 @@ static size_t split_sub_lds(const Plan &p) {
     return sizeof(double2) * ((size_t)fft_area(p.fftsplit_sublen, kSplitSubTPB) + 64 + p.fft_ntwhi);
 }
 
-template <bool FROM_MAP>
-static int split_sub(const Plan &p, const double *maps, int nb) {
+template <bool FROM_MAP, bool PIX = false>
+static int split_sub(const Plan &p, const double *maps, int nb, const double *rho = nullptr,
+                     double lam = 1.0) {
     const int cnt = p.fft_class_count[2];
-    hipLaunchKernelGGL((k_fft_split_sub<kSplitSubTPB, 8, FROM_MAP>), dim3(nb, cnt, 4),
+    hipLaunchKernelGGL((k_fft_split_sub<kSplitSubTPB, 8, FROM_MAP, PIX>), dim3(nb, cnt, 4),
                        dim3(kSplitSubTPB), split_sub_lds(p), p.stream, maps, p.d_fftsplit,
                        p.fftsplit_stride, fft_area(p.fftsplit_sublen, kSplitSubTPB), p.d_pfft,
                        p.d_plist + p.fft_class_off[2], p.d_twlo, p.d_twhi, p.fft_ntwhi, p.fftmax,
-                       p.d_chirp, p.d_bhat, p.npix);
+                       p.d_chirp, p.d_bhat, p.npix, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau);
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }
 
-static int fwd_split(const Plan &p, const double *maps, double2 *out, int nb) {
+// forward split transforms of nb maps (PIX: of the messenger field formed from maps, rho and
+// M) into rows of OutT (row stride rs) or, COLS, into the matrix-core columns
+template <typename OutT, bool PIX, bool COLS>
+static int fwd_split(const Plan &p, const double *maps, const double *rho, double lam, OutT *out,
+                     int rs, int nb) {
     MFWF_TRY(split_check(p, nb));
-    MFWF_TRY(split_sub<true>(p, maps, nb));
-    hipLaunchKernelGGL((k_fft_fwd_split_combine<kSplitTPB, 8, double2>),
+    MFWF_TRY((split_sub<true, PIX>(p, maps, nb, rho, lam)));
+    hipLaunchKernelGGL((k_fft_fwd_split_combine<kSplitTPB, 8, OutT, COLS>),
                        dim3(nb, p.fft_class_count[2]), dim3(kSplitTPB), fft_class_lds(p, 2),
-                       p.stream, out, p.d_fftsplit, p.fftsplit_stride, MFWF_FFT_ARGS(2, p.nm));
+                       p.stream, out, p.d_fftsplit, p.fftsplit_stride, MFWF_FFT_ARGS(2, rs), p.C2);
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }
 
-static int inv_split(const Plan &p, const double2 *in, double *maps, int nb) {
+template <typename InT, bool COLS>
+static int inv_split(const Plan &p, const InT *in, int rs, double *maps, int nb) {
     MFWF_TRY(split_check(p, nb));
-    hipLaunchKernelGGL((k_fft_inv_split_fold<kSplitTPB, 8, double2>),
+    hipLaunchKernelGGL((k_fft_inv_split_fold<kSplitTPB, 8, InT, COLS>),
                        dim3(nb, p.fft_class_count[2]), dim3(kSplitTPB), fft_class_lds(p, 2),
-                       p.stream, in, p.d_fftsplit, p.fftsplit_stride, MFWF_FFT_ARGS(2, p.nm));
+                       p.stream, in, p.d_fftsplit, p.fftsplit_stride, MFWF_FFT_ARGS(2, rs), p.C2);
     MFWF_HIP(hipGetLastError());
     MFWF_TRY(split_sub<false>(p, nullptr, nb));
     hipLaunchKernelGGL((k_fft_inv_split_combine<256>), dim3(nb, p.fft_class_count[2]), dim3(256),
@@ -837,13 +975,9 @@ static int inv_split(const Plan &p, const double2 *in, double *maps, int nb) {
 template <typename OutT, bool PIX>
 static int fwd_classes(const Plan &p, const double *maps, const double *rho, double lam,
                        OutT *out, int nb) {
-    if (p.fft_class_count[2] > 0) {
-        if constexpr (PIX || sizeof(OutT) != sizeof(double2)) {
-            return fail(MFWF_EINVAL, "split ring transforms run on FP64 rows only");
-        } else {
-            MFWF_TRY(fwd_split(p, maps, out, nb));
-        }
-    }
+    if (p.fft_class_count[2] > 0)
+        MFWF_TRY((fwd_split<OutT, PIX, false>(p, maps, rho, lam, out,
+                                              sizeof(OutT) == sizeof(float2) ? p.nm32 : p.nm, nb)));
     for (int c = 1; c >= 0; c--) {  // long transforms first
         const int cnt = p.fft_class_count[c];
         if (cnt == 0) continue;
@@ -865,13 +999,8 @@ static int fwd_classes(const Plan &p, const double *maps, const double *rho, dou
 
 template <typename InT>
 static int inv_classes(const Plan &p, const InT *in, double *maps, int nb) {
-    if (p.fft_class_count[2] > 0) {
-        if constexpr (sizeof(InT) != sizeof(double2)) {
-            return fail(MFWF_EINVAL, "split ring transforms run on FP64 rows only");
-        } else {
-            MFWF_TRY(inv_split(p, in, maps, nb));
-        }
-    }
+    if (p.fft_class_count[2] > 0)
+        MFWF_TRY((inv_split<InT, false>(p, in, sizeof(InT) == sizeof(float2) ? p.nm32 : p.nm, maps, nb)));
     for (int c = 1; c >= 0; c--) {
         const int cnt = p.fft_class_count[c];
         if (cnt == 0) continue;
@@ -910,7 +1039,15 @@ int launch_fft_inv_f32(const Plan &p, const float2 *phase, double *maps, int nb)
 }
 
 int launch_fft_inv_fwd_cols(const Plan &p, const double *rho, double lam, double *smap, int nb) {
-    if (p.fft_class_count[2] > 0) return fail(MFWF_EINVAL, "split ring transforms run on FP64 rows only");
+    if (p.fft_class_count[2] > 0) {
+        // split rings (nside 2048): the synthesis columns folded and transformed back to the
+        // pixels of those rings (into smap, or the plan's map workspace t), then the
+        // messenger field's split transforms into the columns
+        float2 *data = reinterpret_cast<float2 *>(p.d_ph32);
+        double *maps = smap ? smap : p.d_t;
+        MFWF_TRY((inv_split<float2, true>(p, data, p.nm32, maps, nb)));
+        MFWF_TRY((fwd_split<float2, true, true>(p, maps, rho, lam, data, p.nm32, nb)));
+    }
     for (int c = 1; c >= 0; c--) {
         const int cnt = p.fft_class_count[c];
         if (cnt == 0) continue;
@@ -938,6 +1075,37 @@ int launch_fft_inv_fwd_cols(const Plan &p, const double *rho, double lam, double
 }
 
 
+
+// The chained T, Q, U ring step runs where every ring class fits its register budget
+// (workgroups of at most 512 threads) and no ring needs the split transforms.
+bool fft_pol_chain_ok(const Plan &p) {
+    if (p.fft_class_count[2] > 0) return false;
+    for (int c = 0; c < 2; c++) {
+        int ept;
+        if (p.fft_class_count[c] > 0 && fft_class_shape(p, c, ept) > 512) return false;
+    }
+    return true;
+}
+
+int launch_fft_inv_fwd_pol_cols(const Plan &p, const double *rho, double lam, int nb) {
+    if (!fft_pol_chain_ok(p)) return fail(MFWF_EINVAL, "chained T, Q, U ring step: ring class too long");
+    for (int c = 1; c >= 0; c--) {
+        const int cnt = p.fft_class_count[c];
+        if (cnt == 0) continue;
+        int ept;
+        const int tpb = fft_class_shape(p, c, ept);
+        const dim3 grid(8 * nb * ((cnt + 7) / 8));  // whole pairs per XCD
+        const size_t lds = fft_cols_lds(p, c, 1);
+#define MFWF_INVFWD_POL(T)                                                                          \
+    hipLaunchKernelGGL((k_fft_inv_fwd_pol<T, 8>), grid, dim3(T), lds, p.stream, p.d_ph32, p.d_ph32p, \
+                       p.C2, nb, cnt, rho, p.d_M, lam, p.tau, MFWF_FFT_ARGS(c, p.nm32))
+        if (tpb == 256) MFWF_INVFWD_POL(256);
+        else MFWF_INVFWD_POL(512);
+#undef MFWF_INVFWD_POL
+        MFWF_HIP(hipGetLastError());
+    }
+    return MFWF_OK;
+}
 
 int fft_max_length() { return 8 * 1024; }
 
@@ -983,10 +1151,19 @@ int fft_set_lds_limit(size_t bytes) {
     MFWF_TRY(inv_lds<double2>((int)bytes));
     MFWF_TRY(inv_lds<float2>((int)bytes));
     MFWF_TRY(inv_fwd_lds((int)bytes));
-    const void *split_fns[] = {(const void *)k_fft_split_sub<kSplitSubTPB, 8, true>,
-                               (const void *)k_fft_split_sub<kSplitSubTPB, 8, false>,
-                               (const void *)k_fft_fwd_split_combine<kSplitTPB, 8, double2>,
-                               (const void *)k_fft_inv_split_fold<kSplitTPB, 8, double2>};
+    MFWF_HIP(hipFuncSetAttribute((const void *)k_fft_inv_fwd_pol<256, 8>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    MFWF_HIP(hipFuncSetAttribute((const void *)k_fft_inv_fwd_pol<512, 8>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    const void *split_fns[] = {(const void *)k_fft_split_sub<kSplitSubTPB, 8, true, false>,
+                               (const void *)k_fft_split_sub<kSplitSubTPB, 8, true, true>,
+                               (const void *)k_fft_split_sub<kSplitSubTPB, 8, false, false>,
+                               (const void *)k_fft_fwd_split_combine<kSplitTPB, 8, double2, false>,
+                               (const void *)k_fft_fwd_split_combine<kSplitTPB, 8, float2, false>,
+                               (const void *)k_fft_fwd_split_combine<kSplitTPB, 8, float2, true>,
+                               (const void *)k_fft_inv_split_fold<kSplitTPB, 8, double2, false>,
+                               (const void *)k_fft_inv_split_fold<kSplitTPB, 8, float2, false>,
+                               (const void *)k_fft_inv_split_fold<kSplitTPB, 8, float2, true>};
     for (const void *f : split_fns)
         MFWF_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
     return MFWF_OK;

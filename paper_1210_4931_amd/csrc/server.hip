@@ -6,7 +6,9 @@
 //   - admits queued requests into free slots at iteration boundaries (M = N^-1 mask,
 //     tau = 1 / max M, rho = M d and s = 0 written into the slot on the pool's stream),
 //   - launches messenger iterations (Eqs. 3-4) over the occupied slot range of busy pools (the
-//     iteration is captured once per slot count and replayed as a hipGraph).  Pools run on a
+//     iteration is captured once per slot count and replayed as a hipGraph; FP32 pools chain
+//     their iterations through the synthesis columns as a standalone solve does, a new
+//     slot's columns zeroed at admission).  Pools run on a
 //     few server-owned lanes (streams), so that pools on different lanes overlap on the GPU.
 //     Within a lane the worker picks the busy pool that has used the least GPU time (start-
 //     time fair queueing on each iteration's measured duration), so a small pool runs many
@@ -132,7 +134,10 @@ static size_t estimate_pool_bytes(int nside, int lmax, int dtype, int B) {
     if (dtype == MFWF_F32) {
         const double Bp = 16.0 * ((B + 15) / 16);
         b += 16.0 * nm * nring + 16.0 * groups * nalm;           // unused FP64 rows, 1 map
-        b += 4.0 * npair * (nalm + 64.0 * nm) * 1.05;            // lambda table (padded)
+        const double table = 4.0 * npair * (nalm + 64.0 * nm) * 1.05;  // lambda table (padded)
+        b += table / 4.0;                                        // recurrence segment states
+        if (nside <= 1024) b += table;
+        else b += 64.0 * B * nside * nside;                      // split ring scratch
         b += 8.0 * B * nring * (nm + 15) + 4.0 * nring * nm * 2 * Bp;  // rows, column layout
         b += 2 * 4.0 * nalm * 2 * Bp;                            // coefficients in columns
     } else {
@@ -142,14 +147,12 @@ static size_t estimate_pool_bytes(int nside, int lmax, int dtype, int B) {
     return (size_t)(1.1 * b) + (64u << 20);
 }
 
-// the plan shapes a pool can take: FP64 up to nside 2048, the FP32 form up to 1024
+// the plan shapes a pool can take: FP64 and the FP32 form up to nside 2048
 static int check_shape(int nside, int lmax, int dtype) {
     if (nside < 1 || nside > 2048 || (nside & (nside - 1)) != 0)
         return fail(MFWF_EINVAL, "nside must be a power of two in [1, 2048]");
     if (lmax < 1 || lmax > 4 * nside) return fail(MFWF_EINVAL, "lmax must be in [1, 4 nside]");
     if (dtype != MFWF_F64 && dtype != MFWF_F32) return fail(MFWF_EINVAL, "bad dtype");
-    if (dtype == MFWF_F32 && nside > 1024)
-        return fail(MFWF_EINVAL, "the batched FP32 form supports nside <= 1024");
     return MFWF_OK;
 }
 
@@ -237,6 +240,7 @@ static int admit(mfwf_server s, Pool &P, int b, const std::shared_ptr<SrvRequest
     MFWF_TRY(launch_fill(p.d_tau + b, 1, q->tau, p.stream));
     MFWF_TRY(launch_rho_from_data(q->r.data, p.d_M + off, p.d_rho + off, p.npix, 1, p.stream));
     MFWF_TRY(launch_fill(p.d_smap + off, p.npix, 0.0, p.stream));
+    if (p.chain) MFWF_TRY(launch_zero_map_cols(p, b));  // the slot's synthesis columns: s = 0
     P.slot[b] = q;
     P.done_iters[b] = 0;
     P.active++;
@@ -342,6 +346,15 @@ static Pool *find_or_create_pool(mfwf_server s, const PoolKey &key, std::string 
     P->nslots = nslots;
     status = plan_create(key.nside, key.lmax, 0, key.dtype, nslots, st, true, P->plan);
     if (status == MFWF_OK) status = plan_set_cl(P->plan, key.cl.data());
+    if (status == MFWF_OK && key.dtype == MFWF_F32) {
+        // FP32 pools chain their iterations as a standalone solve does: each iteration's ring
+        // step starts from the previous synthesis in the columns (zero for a new slot), and
+        // the maps are formed only when a request retires
+        Plan &p = P->plan;
+        status = launch_fill(reinterpret_cast<double *>(p.d_ph32), (long)p.nring * p.nm * p.C2 / 2,
+                             0.0, p.stream);
+        p.chain = p.chain_ready = true;
+    }
     if (status != MFWF_OK) {
         err = std::string("pool plan: ") + mfwf_last_error();
         return nullptr;

@@ -27,7 +27,7 @@ class SolveOpts(ctypes.Structure):
                 ("iters", ctypes.POINTER(ctypes.c_int)), ("n_check", ctypes.c_int),
                 ("dchi2_tol", ctypes.c_double), ("source_is_rho", ctypes.c_int),
                 ("use_graph", ctypes.c_int), ("history", ctypes.POINTER(ctypes.c_double)),
-                ("history_rows", ctypes.c_int)]
+                ("history_rows", ctypes.c_int), ("order", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -285,8 +285,9 @@ class Plan:
 
     def solve(self, inp: torch.Tensor, lam=None, iters=None, source_is_rho=False,
               use_graph=True, out_alm=None, out_map=None, want_map=True, n_check=0,
-              dchi2_tol=0.0):
+              dchi2_tol=0.0, chained=True):
         """Messenger iteration.  lam/iters: per-stage schedule (default lambda 1, 300 its).
+        chained=False runs the FP32 form's iterations from the pixel map (same values).
         Returns (s_alm [n, nalm] complex128, s_map [n, npix] or None, [Info] * n); with
         n_check > 0 a fourth item, the diagnostics history as a numpy array
         [checks][n][5] of (iteration, lambda, chi^2, |s_k - s_{k-1}|, |s_k|).  dchi2_tol > 0
@@ -305,7 +306,7 @@ class Plan:
         hptr = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if rows else None
         opts = SolveOpts(len(lam), lam_a, it_a, int(n_check), float(dchi2_tol),
                          int(bool(source_is_rho)),
-                         int(bool(use_graph)), hptr, rows)
+                         int(bool(use_graph)), hptr, rows, 0 if chained else 1)
         s_alm = self.zeros_alm(n) if out_alm is None else out_alm
         s_map = (self.zeros_map(n) if out_map is None else out_map) if want_map else None
         infos = (SolveInfo * n)()
@@ -378,8 +379,8 @@ class Plan:
         """Kernel shapes in use (autotuned, default or forced by MFWF_TUNE_FORCE)."""
         out = (ctypes.c_int * 8)()
         _check(_lib.mfwf_plan_tuning(self._h, out))
-        keys = ["synth", "ana", "g0", "g1", "cta", "cts", "source"]
-        return dict(zip(keys, list(out)[:7]))
+        keys = ["synth", "ana", "g0", "g1", "cta", "cts", "lamgen", "source"]
+        return dict(zip(keys, list(out)))
 
     def time_kernels(self, nmaps=1, reps=10):
         """Mean ms per launch of [pixel, fft_fwd, leg_analysis, harmonic, leg_synth, fft_inv]."""

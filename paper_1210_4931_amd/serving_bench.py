@@ -3,7 +3,7 @@
 Each request is drawn from its id (workloads.serve_request): nside uniform over the given
 set with lmax = 2 nside, C_l = 6000/(l(l+1)) exp(-(l/1500)^2), noise variance 30^2/hits with
 hits log-uniform over a 1000x span, a 10-30 % sky cut (band plus 50 discs), FP32 or FP64
-with probability 1/2 (FP64 above nside 1024), K messenger iterations at lambda = 1.  Inputs come from a small bank of
+with probability 1/2, K messenger iterations at lambda = 1.  Inputs come from a small bank of
 such requests per nside (generated once, data = Y(sqrt(C) h) + sigma g made on the GPU):
 the cost of a request does not depend on its values, only on its shape, dtype and K.
 
@@ -53,7 +53,7 @@ def _draw(seed, count, nsides, per_nside):
         g = np.random.Generator(np.random.PCG64(rid))
         n = int(nsides[g.integers(len(nsides))])
         dt = "f32" if g.random() < 0.5 else "f64"
-        out.append((n, dt if n <= 1024 else "f64", int(g.integers(per_nside))))  # FP32 form: <= 1024
+        out.append((n, dt, int(g.integers(per_nside))))
     return out
 
 
@@ -121,7 +121,7 @@ def run_serving(nsides=(128, 256, 512), requests=120, loads=(0.8,), K=300, slots
     srv = mf.Server(slots=slots, hbm_gb=hbm_gb)
     try:
         _log("warm-up: one pool per (nside, dtype)")
-        warm = [(n, dt, 0) for n in nsides for dt in ("f32", "f64") if n <= 1024 or dt == "f64"]
+        warm = [(n, dt, 0) for n in nsides for dt in ("f32", "f64")]
         _run(srv, bank, warm, 2)
         reqs = _draw(seed, requests, nsides, per_nside)
         lat, span = _run(srv, bank, reqs, K, tag="saturation")

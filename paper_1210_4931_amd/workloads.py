@@ -317,14 +317,11 @@ def serve_request(rid: int, nsides=(128, 256, 512, 1024), lscale: float = 1500.0
     C_l = 6000/(l(l+1)) exp(-(l/1500)^2), hits = 10^(3u) (a 1000x span), noise variance
     30^2/hits, a sky cut f ~ U[0.10, 0.30] made of the band |z| < 0.75 f and `ndisc` discs
     whose common radius gives the rest, 2 pi (1 - cos r) ndisc = 0.25 f 4 pi (overlaps
-    ignored), dtype FP32 or FP64 with probability 1/2 (FP64 above nside 1024, where the
-    batched FP32 form does not run; the draw is made all the same).  Draw order: shape,
-    dtype, cut, signal, noise, disc centres, hits."""
+    ignored), dtype FP32 or FP64 with probability 1/2.  Draw order: shape, dtype, cut,
+    signal, noise, disc centres, hits."""
     rng = np.random.Generator(np.random.PCG64(rid))
     nside = int(nsides[rng.integers(len(nsides))])
     dtype = "f32" if rng.random() < 0.5 else "f64"
-    if nside > 1024:
-        dtype = "f64"
     f = rng.uniform(0.10, 0.30)
     lmax = 2 * nside
     npix = 12 * nside * nside

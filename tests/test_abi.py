@@ -79,7 +79,10 @@ def test_server_pool_bytes_is_host_only_and_validates(lib):
     assert Server.pool_bytes(512, 1024, "f64", 64) > Server.pool_bytes(512, 1024, "f64", 8)
     assert Server.pool_bytes(256, 512, "f32", 16) > Server.pool_bytes(128, 256, "f32", 16)
     assert Server.pool_bytes(2048, 4096, "f64", 1) > 4 * Server.pool_bytes(1024, 2048, "f64", 1)
+    # the FP32 form at 2048 keeps lambda segment states (16 bytes per 16 table entries, about
+    # 36 GB), not the FP32 table of about 140 GB
+    assert 30e9 < Server.pool_bytes(2048, 4096, "f32", 1) < 100e9
     for args in [(24, 48, "f64", 2), (16, 65, "f64", 2), (16, 32, "f64", 0), (4096, 8192, "f64", 1),
-                 (2048, 4096, "f32", 1)]:
+                 (4096, 8192, "f32", 1), (2048, 4096, "f32", 0)]:
         with pytest.raises(MFWFError):
             Server.pool_bytes(*args)

@@ -167,6 +167,10 @@ def test_f32_chained_iterations_chunks_checks_and_stages(mf):
     a_chk, m_chk, _, hist = plan.solve(dev(ds), lam=lam, iters=its, n_check=5)
     assert torch.equal(a_all, a_chk) and torch.equal(m_all, m_chk)
     assert hist.shape[0] == 6  # checks at 5, 10, ..., 30
+    # the same iterations from the pixel map (forward transforms, layout changes, inverse
+    # transforms every iteration): the same values
+    a_map, m_map, _ = plan.solve(dev(ds), lam=lam, iters=its, chained=False)
+    assert torch.equal(a_all, a_map) and torch.equal(m_all, m_map)
     ref_alm, ref_map = oracle.solve(nside, lmax, wl.cl, M, M * ds[5], lam=np.repeat(lam, its))
     assert rel_alm(a_all.cpu().numpy()[5], ref_alm, lmax) < TOL
     assert rel(m_all.cpu().numpy()[5], ref_map) < TOL

@@ -113,10 +113,91 @@ def test_split_transform_small_solve(mf):
     assert rel(s_map.cpu().numpy()[0], ref_map) < 1e-11
 
 
-def test_split_transform_rejects_fp32_above_1024(mf):
+def test_split_transform_rejects_fp32_spin2_above_1024(mf):
     from paper_1210_4931_amd.mfwf import MFWFError
     with pytest.raises(MFWFError, match="FP32"):
-        mf.Plan(2048, 4096, dtype="f32")
+        mf.Plan(2048, 4096, dtype="f32", spin=2)
+
+
+def test_split_transform_small_f32(mf):
+    """The batched FP32 form on a split plan (threshold 32): its transforms (FP32 rows through
+    the split kernels) and 30 chained iterations (the split rings folded from and stored into
+    the matrix-core columns, with the pixel update inside the split sub-transforms) against
+    the oracle; a served request on the same shape equals the standalone solve bitwise."""
+    nside, lmax, B = 32, 64, 3
+    wl = W.config1(seed=3, nside=nside, lmax=lmax)
+    sig = oracle.alm2map(nside, lmax, wl.signal_alm)
+    M = wl.mask / wl.noise_var
+    rng = np.random.default_rng(8)
+    d = np.stack([sig + np.sqrt(wl.noise_var) * (wl.noise_white if b == 0 else rng.standard_normal(sig.size))
+                  for b in range(B)])
+    with split_len(32):
+        plan = mf.Plan(nside, lmax, max_batch=B, dtype="f32")
+    plan.set_covariances(wl.cl, dev(1.0 / wl.noise_var), dev(wl.mask, torch.uint8))
+    a = np.stack([W.white_alm(rng, lmax) for _ in range(B)])
+    mp = plan.sht_inv(dev(a, torch.complex128)).cpu().numpy()
+    back = plan.sht_fwd(dev(d)).cpu().numpy()
+    for b in range(B):
+        assert rel(mp[b], oracle.alm2map(nside, lmax, a[b])) < 1e-5
+        assert _rel_alm(back[b], oracle.map2alm(nside, lmax, d[b]), lmax) < 1e-5
+    s_alm, s_map, _ = plan.solve(dev(d), iters=30)
+    for b in range(B):
+        ref_alm, ref_map = oracle.solve(nside, lmax, wl.cl, M, M * d[b], niter=30)
+        assert _rel_alm(s_alm.cpu().numpy()[b], ref_alm, lmax) < 1e-5
+        assert rel(s_map.cpu().numpy()[b], ref_map) < 1e-5
+    with split_len(32):  # the server creates the pool's plan when it admits the request
+        srv = mf.Server(slots=2, hbm_gb=8.0)
+        try:
+            rid, sa, sm = srv.submit(nside, lmax, wl.cl, dev(1.0 / wl.noise_var), dev(d[0]),
+                                     mask=dev(wl.mask, torch.uint8), dtype="f32", iters=30)
+            srv.wait(rid)
+        finally:
+            srv.close()
+    with split_len(32):
+        p1 = mf.Plan(nside, lmax, max_batch=1, dtype="f32")
+    p1.set_covariances(wl.cl, dev(1.0 / wl.noise_var), dev(wl.mask, torch.uint8))
+    a1, m1, _ = p1.solve(dev(d[:1]), iters=30)
+    assert torch.equal(sa, a1[0]) and torch.equal(sm, m1[0])
+
+
+def test_nside2048_f32_batched_sampled(mf):
+    """The batched FP32 form at nside 2048 / lmax 4096, where the contractions generate
+    lambda from the FP64 recurrence (no table) and the split rings run on the columns: the
+    synthesis on single rings and the analysis of single m against the oracle, and two
+    chained iterations on two maps against the FP64 path after the same iterations."""
+    rng = np.random.default_rng(47)
+    plan = mf.Plan(NSIDE, LMAX, max_batch=2, dtype="f32")
+    assert plan.tuning()["lamgen"] == 1
+    a = np.stack([W.white_alm(rng, LMAX) for _ in range(2)])
+    mp = plan.sht_inv(dev(a, torch.complex128)).cpu().numpy()
+    z, s, start, nphi, phi0 = oracle.rings(NSIDE)
+    for r in (3, 1500, 2047, 4096, 6145):
+        ref = oracle.alm2map_ring(NSIDE, LMAX, a[1], r)
+        got = mp[1, start[r - 1]:start[r - 1] + nphi[r - 1]]
+        print("FP32 ring", r, "rel", rel(got, ref), flush=True)
+        assert rel(got, ref) < 1e-5, (r, rel(got, ref))
+    del mp
+    x = rng.standard_normal((2, 12 * NSIDE * NSIDE))
+    back = plan.sht_fwd(dev(x)).cpu().numpy()
+    _, ms = W.alm_l_m(LMAX)
+    for m in (0, 1500, 4096):
+        ref = oracle.map2alm_m(NSIDE, LMAX, x[0], m)
+        print("FP32 m", m, "rel", rel(back[0][ms == m], ref), flush=True)
+        assert rel(back[0][ms == m], ref) < 1e-5, (m, rel(back[0][ms == m], ref))
+    del back
+    wl = W.config2(0, NSIDE, LMAX)
+    d = np.sqrt(wl.noise_var) * np.stack([wl.noise_white, W.batch_noise(1, wl.npix)])
+    plan.set_covariances(wl.cl, dev(1.0 / wl.noise_var), dev(wl.mask, torch.uint8))
+    s32, m32, _ = plan.solve(dev(d), iters=2)
+    del plan
+    p64 = mf.Plan(NSIDE, LMAX, max_batch=2)
+    p64.set_covariances(wl.cl, dev(1.0 / wl.noise_var), dev(wl.mask, torch.uint8))
+    s64, m64, _ = p64.solve(dev(d), iters=2)
+    for b in range(2):
+        ea = _rel_alm(s32[b].cpu().numpy(), s64[b].cpu().numpy(), LMAX)
+        em = rel(m32[b].cpu().numpy(), m64[b].cpu().numpy())
+        print("FP32 vs FP64 after 2 iterations, map", b, ea, em, flush=True)
+        assert ea < 1e-5 and em < 1e-5
 
 
 def test_nside2048_sht_sampled(mf):
@@ -167,9 +248,9 @@ def test_nside2048_first_iteration_sampled(mf):
 
 def test_nside2048_pol_sht_sampled(mf):
     """T, Q, U at nside 2048 / lmax 4096 (the split rings carry three rows per map): the
-    synthesis on single rings against the oracle, and the analysis through the adjoint
-    identity <Y a, x> = <a, A x> / Omega with the same synthesis (the oracle's one-m spin-2
-    analysis takes a minute per m at this size)."""
+    synthesis on single rings and the analysis of one m (2500: polar and belt rings, 1597
+    values of l) against the oracle (whose one-m spin-2 analysis takes about a minute at
+    this size), and the adjoint identity <Y a, x> = <a, A x> / Omega over all coefficients."""
     rng = np.random.default_rng(43)
     a = _teb(rng, LMAX)
     plan = mf.Plan(NSIDE, LMAX, spin=2)
@@ -188,3 +269,10 @@ def test_nside2048_pol_sht_sampled(mf):
     rhs = float(np.sum(wgt * (np.conj(a) * back).real)) / (4.0 * np.pi / x.shape[1])
     print("adjoint", lhs, rhs)
     assert lhs == pytest.approx(rhs, rel=1e-11)
+    m = 2500
+    print("oracle spin-2 analysis of m = %d at nside %d (about a minute)" % (m, NSIDE), flush=True)
+    ref = oracle.map2alm_pol_m(NSIDE, LMAX, x, m)
+    got = back[:, ms == m]
+    for c in range(3):
+        print("m", m, "component", c, "rel", rel(got[c], ref[c]))
+        assert rel(got[c], ref[c]) < 3e-11, (c, rel(got[c], ref[c]))

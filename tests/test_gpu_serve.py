@@ -130,7 +130,7 @@ def test_served_nside2048_request_equals_standalone(mf):
     server gives that shape fewer slots (2, the first halving that fits half of 100 GB)."""
     from paper_1210_4931_amd.mfwf import Server
     assert Server.pool_bytes(2048, 4096, "f64", 4) > 50e9 >= Server.pool_bytes(2048, 4096, "f64", 2)
-    r = W.serve_request(3, nsides=(2048,))
+    r = W.serve_request(4, nsides=(2048,))
     assert r.dtype == "f64"
     z, _ = W.pixel_centres(r.nside)
     d = np.sqrt(r.noise_var) * r.noise_white + 80.0 * z
@@ -151,6 +151,24 @@ def test_served_nside2048_request_equals_standalone(mf):
     assert torch.equal(h_small[1], a_ref) and torch.equal(h_small[2], m_ref)
 
 
+def test_served_nside2048_f32_request_equals_standalone(mf):
+    """A 2048 / 4096 request in the batched FP32 form (lambda generated in the contractions,
+    split ring transforms on the columns, iterations chained as in a standalone solve, the
+    map formed when the request retires): bitwise the standalone solve."""
+    r = W.serve_request(3, nsides=(2048,))
+    assert r.dtype == "f32"
+    z, _ = W.pixel_centres(r.nside)
+    d = np.sqrt(r.noise_var) * r.noise_white + 80.0 * z
+    ninv = 1.0 / r.noise_var
+    srv = mf.Server(slots=2, hbm_gb=200.0)
+    h = srv.submit(r.nside, r.lmax, r.cl, dev(ninv), dev(d), mask=dev(r.mask, torch.uint8),
+                   dtype="f32", iters=3)
+    srv.wait(h[0])
+    srv.close()
+    a_ref, m_ref = _standalone(mf, r, d, ninv, 3)
+    assert torch.equal(h[1], a_ref) and torch.equal(h[2], m_ref)
+
+
 def test_bad_requests_rejected_at_submission(mf):
     from paper_1210_4931_amd.mfwf import MFWFError
     srv = mf.Server(slots=2, hbm_gb=10.0)
@@ -164,8 +182,7 @@ def test_bad_requests_rejected_at_submission(mf):
         srv.submit(r.nside, r.lmax, r.cl, dev(bad), dev(d))
     with pytest.raises(MFWFError):
         srv.submit(r.nside, r.lmax, r.cl, dev(ninv), dev(d), iters=0)
-    with pytest.raises(MFWFError, match="status -1"):  # the FP32 form stops at nside 1024
-        srv.submit(2048, 4096, np.ones(4097), torch.ones(12 * 2048 ** 2, dtype=torch.float64,
-                   device="cuda"), torch.zeros(12 * 2048 ** 2, dtype=torch.float64, device="cuda"),
+    with pytest.raises(MFWFError, match="status -1"):  # lmax above 4 nside
+        srv.submit(r.nside, 4 * r.nside + 1, np.ones(4 * r.nside + 2), dev(ninv), dev(d),
                    dtype="f32")
     srv.close()

@@ -65,21 +65,24 @@ def test_every_fp64_legendre_variant_matches_the_oracle(mf, nside, lmax):
 
 
 def test_batched_shapes_do_not_change_results(mf):
-    """Maps per ring-step workgroup (1, 2, 4 per transform class) and GEMM column tiles
-    (64 or 128 columns) on a 40-map batch (80 active columns): 6 iterations, bitwise equal
-    to the default shapes; the default run against the oracle."""
+    """Maps per ring-step workgroup (1, 2, 4 per transform class), GEMM column tiles (64 or
+    128 columns) and lambda read from the FP32 table or generated in the GEMMs from the
+    FP64 recurrence's segment states, on a 40-map batch (80 active columns): 6 iterations,
+    bitwise equal to each other; one run against the oracle."""
     nside, lmax, nmaps, iters = 32, 64, 40, 6
     wl, d, M = temperature_problem(nside, lmax)
     rng = np.random.default_rng(9)
     x = np.stack([d + 3.0 * rng.standard_normal(d.size) * (b % 3) for b in range(nmaps)])
     results = {}
-    for spec in ["g0=1,g1=1,cta=2,cts=2", "g0=2,g1=2,cta=1,cts=1", "g0=4,g1=1,cta=2,cts=1",
-                 "g0=4,g1=4,cta=1,cts=2"]:
+    for spec in ["g0=1,g1=1,cta=2,cts=2,lamgen=0", "g0=2,g1=2,cta=1,cts=1,lamgen=1",
+                 "g0=4,g1=1,cta=2,cts=1,lamgen=1", "g0=4,g1=4,cta=1,cts=2,lamgen=0",
+                 "cta=2,cts=2,lamgen=1"]:
         print("forced", spec, flush=True)
         with forced(spec):
             plan = mf.Plan(nside, lmax, max_batch=nmaps, dtype="f32")
         plan.set_covariances(wl.cl, dev(1.0 / wl.noise_var), dev(wl.mask, torch.uint8))
         assert plan.tuning()["source"] == 3
+        assert plan.tuning()["lamgen"] == int(spec.split("lamgen=")[1][0])
         a, m, _ = plan.solve(dev(x), iters=iters)
         results[spec] = (a.cpu(), m.cpu())
         del plan
