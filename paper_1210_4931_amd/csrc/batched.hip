@@ -271,7 +271,7 @@ __host__ __device__ constexpr int lds_floats(int main_floats) {
 // G_N + G_S and odd rows G_N - G_S (a table with lambda's mirror symmetry); flip swaps the
 // two, for a table that is odd where lambda is even (the spin-2 F-).
 template <int NCT, bool GEN>
-__global__ void __launch_bounds__(256, 3)
+__global__ void __launch_bounds__(256, NCT == 1 ? (GEN ? 3 : 4) : 2)
 k_gemm_analysis(const float *__restrict__ lam, LamGen gen, const long *__restrict__ loff,
                 const int *__restrict__ Lp, const int *__restrict__ minls32,
                 const int2 *__restrict__ items, const int *__restrict__ tab, int per_xcd,
@@ -384,17 +384,28 @@ k_gemm_analysis(const float *__restrict__ lam, LamGen gen, const long *__restric
         if (pn < nchunk) load(pn);
         if (wave_on && ms[pc] <= lhi_w) {
             const int i = lane & 31, kq = lane >> 5;
-#pragma unroll 4
-            for (int kk = 0; kk < 16; kk++) {
+            // the chunk's 32 pairs summed from zero, then added to the running sums: the
+            // FP32 rounding of a sum over all rings grows with the chain of additions, and
+            // chunked it grows with 32 + the number of chunks instead of their product
+            floatx16 part[2][NCT];
+            auto step = [&](int kk, bool first) __attribute__((always_inline)) {
                 const int pp = 2 * kk + kq;
                 const float2 a = *reinterpret_cast<const float2 *>(&sl[pp][64 * lh + 2 * i]);
 #pragma unroll
                 for (int ct = 0; ct < NCT; ct++) {
                     const float b0 = sx[0][pp][wcol + 32 * ct + i], b1 = sx[1][pp][wcol + 32 * ct + i];
-                    acc[0][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b0, acc[0][ct], 0, 0, 0);
-                    acc[1][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b1, acc[1][ct], 0, 0, 0);
+                    const floatx16 z = {};
+                    part[0][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b0, first ? z : part[0][ct], 0, 0, 0);
+                    part[1][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, b1, first ? z : part[1][ct], 0, 0, 0);
                 }
-            }
+            };
+            step(0, true);
+#pragma unroll 5
+            for (int kk = 1; kk < 16; kk++) step(kk, false);
+#pragma unroll
+            for (int a = 0; a < 2; a++)
+#pragma unroll
+                for (int ct = 0; ct < NCT; ct++) acc[a][ct] += part[a][ct];
         }
         pc = pn;
     }
@@ -439,7 +450,7 @@ k_gemm_analysis(const float *__restrict__ lam, LamGen gen, const long *__restric
 // l.  Wave w: pairs 32 (w & 1) .. +31 of the tile, columns 32 NCT (w >> 1) .. +32 NCT - 1.  The south ring
 // gets E - O (lambda's mirror symmetry), or O - E with flip (the spin-2 F-).
 template <int NCT, bool GEN>
-__global__ void __launch_bounds__(256, 3)
+__global__ void __launch_bounds__(256, NCT == 1 ? 4 : 2)
 k_gemm_synthesis(const float *__restrict__ lam, LamGen gen, const long *__restrict__ loff,
                  const int *__restrict__ Lp, const int *__restrict__ minls32,
                  const int2 *__restrict__ items, const int *__restrict__ tab, int per_xcd,
@@ -549,15 +560,23 @@ k_gemm_synthesis(const float *__restrict__ lam, LamGen gen, const long *__restri
                 for (int ct = 0; ct < NCT; ct++) bv[q][ct] = ss[rr][wcol + 32 * ct + i];
             };
             rd(0, 0);
+            // the chunk's 64 values of l summed from zero, then added to the running sums
+            // (shorter chains of FP32 additions, as in the analysis)
+            floatx16 part[2][NCT];
 #pragma unroll
             for (int st = 0; st < 32; st++) {
                 const int q = st & 1;
                 if (st + 1 < 32) rd(st + 1, q ^ 1);
                 __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the products
+                const floatx16 z = {};
 #pragma unroll
                 for (int ct = 0; ct < NCT; ct++)
-                    acc[st & 1][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[q], bv[q][ct], acc[st & 1][ct], 0, 0, 0);
+                    part[st & 1][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[q], bv[q][ct], st >= 2 ? part[st & 1][ct] : z, 0, 0, 0);
             }
+#pragma unroll
+            for (int a2 = 0; a2 < 2; a2++)
+#pragma unroll
+                for (int ct = 0; ct < NCT; ct++) acc[a2][ct] += part[a2][ct];
         }
     }
     // Epilogue through LDS: per column half, every wave parks F_N = E + O and F_S = E - O
