@@ -252,6 +252,14 @@ __device__ __forceinline__ void st4(float *q, floatx4 v) { *reinterpret_cast<flo
 // selected pointer and force a stack copy)
 __device__ __forceinline__ floatx4 keep4(bool c, floatx4 v) { return c ? v : floatx4{0.f, 0.f, 0.f, 0.f}; }
 
+// threadIdx.x read anew: an epilogue that forms its lane indices from it keeps them out of
+// the registers of the main loop (the compiler would otherwise hold or spill them there)
+__device__ __forceinline__ int fresh_tid() {
+    int t;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+    return t;
+}
+
 static constexpr int kAnaRows = 128;  // values of l per analysis tile
 // Columns per workgroup tile: 64 NCT (NCT column tiles of 32 per wave, two waves across).
 // Launches with at most 64 active columns (up to 32 maps) take NCT = 1, so that no wave
@@ -269,7 +277,9 @@ __host__ __device__ constexpr int lds_floats(int main_floats) {
 // 32 NCT (w >> 1) .. +32 NCT - 1.  Output: raw sums a (if a_out) and/or the Wiener-filtered coefficients
 // s = scale_s C_l / (C_l + lto) a (if s_out), rows [alm][C2].  Even l + m rows contract
 // G_N + G_S and odd rows G_N - G_S (a table with lambda's mirror symmetry); flip swaps the
-// two, for a table that is odd where lambda is even (the spin-2 F-).
+// two, for a table that is odd where lambda is even (the spin-2 F-).  Waves per SIMD: 4
+// for the one-tile table kernel (128 registers, the chunk sums included), 3 where lambda is
+// generated (its recurrence state needs more), 2 for two column tiles.
 template <int NCT, bool GEN>
 __global__ void __launch_bounds__(256, NCT == 1 ? (GEN ? 3 : 4) : 2)
 k_gemm_analysis(const float *__restrict__ lam, LamGen gen, const long *__restrict__ loff,
@@ -410,25 +420,29 @@ k_gemm_analysis(const float *__restrict__ lam, LamGen gen, const long *__restric
         pc = pn;
     }
     // Epilogue through LDS: per column half, every wave parks its 64 rows x 32 columns
-    // ([row][36]) and stores whole 128-byte row segments with 16-byte stores.
+    // ([row][36]) and stores whole 128-byte row segments with 16-byte stores.  Its lane
+    // indices are formed anew from the thread id, so that none of them holds a register
+    // through the main loop.
     const long base = mofs[m] - m;
-    float (*stage)[36] = reinterpret_cast<float (*)[36]>(lds) + 64 * w;
+    const int te = fresh_tid();
+    const int we = te >> 6, le = te & 63, lhe = we & 1, wcole = 32 * NCT * (we >> 1);
+    float (*stage)[36] = reinterpret_cast<float (*)[36]>(lds) + 64 * we;
 #pragma unroll
     for (int ct = 0; ct < NCT; ct++) {
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < 16; r++)
 #pragma unroll
-            for (int par = 0; par < 2; par++) stage[2 * acc_row(r, lane) + par][lane & 31] = acc[par][ct][r];
+            for (int par = 0; par < 2; par++) stage[2 * acc_row(r, le) + par][le & 31] = acc[par][ct][r];
         __syncthreads();
-        const int col = CT * cg + wcol + 32 * ct + 4 * (lane & 7);
-        if (!wave_on || col >= ncols) continue;
+        const int col = CT * cg + wcole + 32 * ct + 4 * (le & 7);
+        if (CT * cg + wcole >= ncols || col >= ncols) continue;
 #pragma unroll
         for (int it = 0; it < 8; it++) {
-            const int row = 8 * it + (lane >> 3);
-            const int l = m + kAnaRows * t + 64 * lh + row;
+            const int row = 8 * it + (le >> 3);
+            const int l = m + kAnaRows * t + 64 * lhe + row;
             if (l > lmax) continue;
-            const float4 v = *reinterpret_cast<const float4 *>(&stage[row][4 * (lane & 7)]);
+            const float4 v = *reinterpret_cast<const float4 *>(&stage[row][4 * (le & 7)]);
             const long idx = (base + l) * C2 + col;
             if (a_out) *reinterpret_cast<float4 *>(a_out + idx) = v;
             if (s_out) {
@@ -560,50 +574,45 @@ k_gemm_synthesis(const float *__restrict__ lam, LamGen gen, const long *__restri
                 for (int ct = 0; ct < NCT; ct++) bv[q][ct] = ss[rr][wcol + 32 * ct + i];
             };
             rd(0, 0);
-            // the chunk's 64 values of l summed from zero, then added to the running sums
-            // (shorter chains of FP32 additions, as in the analysis)
-            floatx16 part[2][NCT];
 #pragma unroll
             for (int st = 0; st < 32; st++) {
                 const int q = st & 1;
                 if (st + 1 < 32) rd(st + 1, q ^ 1);
                 __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the products
-                const floatx16 z = {};
 #pragma unroll
                 for (int ct = 0; ct < NCT; ct++)
-                    part[st & 1][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[q], bv[q][ct], st >= 2 ? part[st & 1][ct] : z, 0, 0, 0);
+                    acc[st & 1][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[q], bv[q][ct], acc[st & 1][ct], 0, 0, 0);
             }
-#pragma unroll
-            for (int a2 = 0; a2 < 2; a2++)
-#pragma unroll
-                for (int ct = 0; ct < NCT; ct++) acc[a2][ct] += part[a2][ct];
         }
     }
     // Epilogue through LDS: per column half, every wave parks F_N = E + O and F_S = E - O
     // of its 32 pairs x 32 columns ([2][pair][36]) and stores whole 128-byte row segments.
-    // Rows are relative l = m + r, so the parity of r equals the parity of l + m.
-    float (*stage)[32][36] = reinterpret_cast<float (*)[32][36]>(lds) + 2 * w;
+    // Rows are relative l = m + r, so the parity of r equals the parity of l + m.  Lane
+    // indices formed anew from the thread id (no registers held through the main loop).
+    const int te = fresh_tid();
+    const int we = te >> 6, le = te & 63, rte = we & 1, wcole = 32 * NCT * (we >> 1);
+    float (*stage)[32][36] = reinterpret_cast<float (*)[32][36]>(lds) + 2 * we;
 #pragma unroll
     for (int ct = 0; ct < NCT; ct++) {
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < 16; r++) {
             const float E = acc[0][ct][r], O = acc[1][ct][r];
-            stage[0][acc_row(r, lane)][lane & 31] = E + O;
-            stage[1][acc_row(r, lane)][lane & 31] = flip ? O - E : E - O;
+            stage[0][acc_row(r, le)][le & 31] = E + O;
+            stage[1][acc_row(r, le)][le & 31] = flip ? O - E : E - O;
         }
         __syncthreads();
-        const int col = CT * cg + wcol + 32 * ct + 4 * (lane & 7);
-        if (!wave_on || col >= ncols) continue;
+        const int col = CT * cg + wcole + 32 * ct + 4 * (le & 7);
+        if (CT * cg + wcole >= ncols || col >= ncols) continue;
 #pragma unroll
         for (int it = 0; it < 8; it++) {
-            const int q = 8 * it + (lane >> 3);  // 0..63: hemisphere q / 32, pair row q % 32
+            const int q = 8 * it + (le >> 3);  // 0..63: hemisphere q / 32, pair row q % 32
             const int hs = q >> 5, row = q & 31;
-            const int p = 64 * pt + 32 * rt + row;
+            const int p = 64 * pt + 32 * rte + row;
             if (p >= npair) continue;
             const int ring = hs ? nring - 1 - p : p;
             if (hs && ring == p) continue;  // equator: one ring
-            float4 v = *reinterpret_cast<const float4 *>(&stage[hs][row][4 * (lane & 7)]);
+            float4 v = *reinterpret_cast<const float4 *>(&stage[hs][row][4 * (le & 7)]);
             float *o = ph32 + ((long)m * nring + ring) * C2 + col;
             if (comb) {
                 // spin 2: v = R' = F- x s_EB of one map (E re, E im, B re, B im) and o holds
