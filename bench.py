@@ -46,6 +46,14 @@ TRAFFIC = {
 }
 
 
+_T0 = time.perf_counter()
+
+
+def note(msg):
+    """Progress of a long run on stderr (the JSON result line stays alone on stdout)."""
+    print("[bench %6.1f s] %s" % (time.perf_counter() - _T0, msg), file=sys.stderr, flush=True)
+
+
 def measured_traffic(kernel):
     import hashlib
     t = TRAFFIC[kernel]
@@ -56,9 +64,38 @@ def measured_traffic(kernel):
     return t["bytes"] if h == t["sha256"] else None
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_ORACLE_ONE_ITER = """
+import json, sys, time
+import numpy as np
+sys.path.insert(0, %r)
+import oracle
+from paper_1210_4931_amd import workloads as W
+wl = W.config2(0, %d, %d)
+d = np.load(%r)
+M = wl.mask / wl.noise_var
+t0 = time.perf_counter()
+oracle.solve(%d, %d, wl.cl, M, M * d, niter=1)
+print(json.dumps({"seconds": time.perf_counter() - t0, "threads": oracle.num_threads()}))
+"""
+
+
 def cpu_baseline(nside, lmax, K, wl, d_host, M):
-    """The FP64 oracle as it stands, all host cores: one solve with 1 and with 3 iterations;
-    the difference gives the cost of an iteration, the rest the set-up; extrapolated to K."""
+    """The FP64 oracle as it stands, timed on the host: with all cores, one solve with 1 and
+    with 3 iterations (the difference gives the cost of an iteration, the rest the set-up);
+    with OMP_NUM_THREADS=1 (a child process), one solve of 1 iteration, set-up included.
+    Both extrapolated to K iterations; value = the all-core rate."""
+    import subprocess
+    import tempfile
     import oracle
     oracle.build()
     t0 = time.perf_counter()
@@ -68,11 +105,76 @@ def cpu_baseline(nside, lmax, K, wl, d_host, M):
     t2 = time.perf_counter()
     per_iter = max((t2 - t1) - (t1 - t0), 1e-9) / 2.0
     setup = max((t1 - t0) - per_iter, 0.0)
-    return {"value": 1.0 / (setup + K * per_iter), "unit": "solves/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "one solve of the nside %d / lmax %d problem with 1 and with 3 messenger "
-                      "iterations (%.1f s in all; %.2f s per iteration, %.2f s set-up), "
-                      "extrapolated to %d iterations" % (nside, lmax, t2 - t0, per_iter, setup, K)}
+    one = None
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "d.npy")
+        np.save(path, d_host)
+        code = _ORACLE_ONE_ITER % (ROOT, nside, lmax, path, nside, lmax)
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                           env=dict(os.environ, OMP_NUM_THREADS="1"), timeout=600)
+        if r.returncode == 0:
+            one = json.loads(r.stdout.strip().splitlines()[-1])
+    out = {"value": 1.0 / (setup + K * per_iter), "unit": "solves/s", "cores": oracle.num_threads(),
+           "kind": "oracle", "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+           "sample": "one solve of the nside %d / lmax %d problem with 1 and with 3 messenger "
+                     "iterations on %d threads (%.1f s in all; %.2f s per iteration, %.2f s "
+                     "set-up), extrapolated to %d iterations"
+                     % (nside, lmax, oracle.num_threads(), t2 - t0, per_iter, setup, K)}
+    if one is not None:
+        out["single_core"] = {"value": 1.0 / (K * one["seconds"]), "unit": "solves/s",
+                              "cores": one["threads"],
+                              "sample": "one solve of 1 messenger iteration, set-up included "
+                                        "(%.1f s), extrapolated to %d iterations"
+                                        % (one["seconds"], K)}
+    return out
+
+
+def batched_extras(K, use_graph):
+    """Other batched FP32 forms at 300 iterations: the nside 512 problem with B = 1 and
+    B = 16 maps (the matrix-core kernels on 2 and 32 real columns), and the downgraded nside
+    256 / lmax 512 problem with 64 right-hand sides, 32 Wiener-filter data sets and 32
+    constrained-realisation fluctuation sources (Eq. 9), in one batch."""
+    import torch
+    from paper_1210_4931_amd import mfwf
+    from paper_1210_4931_amd import workloads as W
+    dev = torch.device("cuda:0")
+    t = lambda x, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(x)).to(dev, dt)  # noqa
+    out = {}
+    wl = W.config2(0, 512, 1024)
+    for B in (1, 16):
+        p = mfwf.Plan(512, 1024, max_batch=B, dtype="f32")
+        p.set_covariances(wl.cl, t(1.0 / wl.noise_var), t(wl.mask, torch.uint8))
+        sig = p.sht_inv(t(wl.signal_alm[None], torch.complex128))[0]
+        d = torch.stack([sig + t(np.sqrt(wl.noise_var) * W.batch_noise(b, wl.npix)) for b in range(B)])
+        el, lat = timed_solves(p, d, K, 2, 1, use_graph)
+        out["nside512_f32_b%d" % B] = {"solves_per_s": 2 * B / el, "ms_per_solve_call": 1e3 * el / 2,
+                                       "iteration_ms": 1e3 * el / 2 / K}
+        del p
+    w = W.config4(0)
+    nside, lmax, B = 256, 512, 64
+    ninv, mask = t(1.0 / w.noise_var), t(w.mask, torch.uint8)
+    p = mfwf.Plan(nside, lmax, max_batch=B, dtype="f32")
+    p.set_covariances(w.cl, ninv, mask)
+    ls, _ = W.alm_l_m(lmax)
+    draws_wf = [W.config4_draws(b) for b in range(32)]
+    sig = p.sht_inv(t(np.stack([np.sqrt(w.cl[ls]) * h for h, _ in draws_wf]), torch.complex128))
+    M = t(w.mask / w.noise_var)
+    d = sig + t(np.sqrt(w.noise_var))[None] * t(np.stack([g for _, g in draws_wf]))
+    draws_cr = [W.fluctuation_draws(32 + k, nside, lmax) for k in range(32)]
+    rho_cr = p.fluctuation_rhs(t(np.stack([g for g, _ in draws_cr])),
+                               t(np.stack([h for _, h in draws_cr]), torch.complex128))
+    rho = torch.cat([M[None] * d, rho_cr], 0)
+    p.solve(rho, iters=K, source_is_rho=True, use_graph=use_graph, want_map=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(2):
+        p.solve(rho, iters=K, source_is_rho=True, use_graph=use_graph, want_map=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["config4_nside256_b64_wf32_cr32"] = {"solves_per_s": 2 * B / el, "ms_per_solve_call": 1e3 * el / 2,
+                                             "iteration_ms": 1e3 * el / 2 / K}
+    del p
+    return out
 
 
 def tqu(nside, lmax, K, steps, use_graph, batch):
@@ -287,8 +389,11 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-cooled", action="store_true",
                     help="skip the converged solves with the cooling schedule")
-    ap.add_argument("--serve-requests", type=int, default=100,
-                    help="requests per serving phase (saturation, Poisson at 0.8 of it)")
+    ap.add_argument("--serve-requests", type=int, default=8,
+                    help="requests per serving phase (saturation, Poisson at 0.5, 0.8 and 0.95 "
+                         "of it)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other batched forms (B = 1, 16; the nside 256 64-RHS batch)")
     ap.add_argument("--kernels", choices=["f64", "f32"], default=None,
                     help="profiling mode: run each kernel of one iteration --reps times")
     ap.add_argument("--reps", type=int, default=3)
@@ -324,6 +429,7 @@ def main():
     sigma = t(np.sqrt(wl.noise_var))
     d1 = sig + sigma[None] * t(wl.noise_white)[None]
     el64, lat64 = timed_solves(p64, d1, K, args.fp64_steps, 1, use_graph)
+    note("FP64 single-map solves timed")
     kt64 = dict(zip(KERNELS, p64.time_kernels(1, 20)))
     work, full, npair, fftmax = p64.work()
     leg_flops = 7.0 * work          # per map and direction: 3 recurrence + 4 complex-by-real FMA
@@ -342,6 +448,7 @@ def main():
     if not args.no_cooled:
         fp64["cooled"] = cooled(p64, d1)
         fp64["bounded"] = bounded(p64, d1)
+        note("FP64 converged solves done")
 
     # ---- batched FP32 form (headline) --------------------------------------------------
     p32 = mfwf.Plan(nside, lmax, max_batch=B, dtype="f32")
@@ -352,6 +459,7 @@ def main():
         dB[b] = sig[0] + sigma * t(W.batch_noise(b, wl.npix))
     torch.cuda.synchronize()
     el32, lat32 = timed_solves(p32, dB, K, args.steps, args.warmup, use_graph)
+    note("batched FP32 solves timed (headline)")
     # accuracy of the timed form: two maps of the batch against the plain FP64 path (itself
     # checked against the CPU oracle by the GPU tests), relative 2-norm over the real
     # harmonic dof (m > 0 twice) and over the map
@@ -366,7 +474,7 @@ def main():
         acc["map%d" % b] = {"rel_err_alm": ea, "rel_err_map": em}
     del a32, m32
     del p64
-    kt32 = dict(zip(KERNELS, p32.time_kernels(B, 5)))
+    kt32 = dict(zip(KERNELS, p32.time_kernels(B, 20)))
     gemm_flops = 2.0 * work * 2 * B   # one FMA per (l, m, ring pair) and column, 2 columns a map
     dom32 = max(("leg_analysis", "leg_synth"), key=lambda k: kt32[k])
     pair32 = kt32["fft_fwd"] + kt32["leg_analysis"] + kt32["leg_synth"] + kt32["fft_inv"]
@@ -422,15 +530,24 @@ def main():
                           "traffic": measured_traffic("gemm_analysis") if dom32 == "leg_analysis" else None},
         "fp64_single": fp64,
     }
+    note("accuracy and kernel times done")
     if not args.no_cooled:
         out["cooled_f32_batched"] = cooled(p32, dB)
+        note("FP32 converged solves done")
     del p32
     if not args.no_tqu:
         out["tqu"] = tqu(nside, lmax, K, args.tqu_steps, use_graph, args.tqu_batch)
+        note("T, Q, U done")
+    if not args.no_extras:
+        out["batched_extras"] = batched_extras(K, use_graph)
+        note("batched extras done")
     if not args.no_serve:
         from paper_1210_4931_amd.serving_bench import run_serving
-        out["serving"] = run_serving(nsides=(128, 256, 512), requests=args.serve_requests,
-                                     loads=(0.8,), K=K)
+        del dB
+        torch.cuda.empty_cache()  # the serving pools take their memory from the same device
+        out["serving"] = run_serving(nsides=(128, 256, 512, 1024, 2048),
+                                     requests=args.serve_requests, loads=(0.5, 0.8, 0.95), K=K)
+        note("serving done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nside, lmax, K, wl, d1.cpu().numpy()[0],
                                            wl.mask / wl.noise_var)

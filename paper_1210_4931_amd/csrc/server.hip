@@ -18,6 +18,7 @@
 //   - creates a pool when a request needs a new shape and its estimated footprint fits the
 //     HBM budget, evicting idle pools (least recently used first) to make room.
 // Latency runs from submission to the completion of the copies into the caller's buffers.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -85,6 +86,7 @@ struct Pool {
     double vtime = 0.0;              // GPU milliseconds charged to this pool (fair queueing)
     std::map<int, double> cost_ms;   // measured iteration time by slot count (moving average)
     int nslots = 0;                  // map slots of this pool (the server's, or fewer: below)
+    bool draining = false;           // admits no new request: a blocked new pool needs its memory
 
     ~Pool() {
         // iterations and result copies may still be in flight on the lane's stream, which the
@@ -320,7 +322,22 @@ static Pool *find_or_create_pool(mfwf_server s, const PoolKey &key, std::string 
             Pool &Q = *s->pools[i];
             if (Q.active == 0 && (victim < 0 || Q.last_used < s->pools[victim]->last_used)) victim = (int)i;
         }
-        if (victim < 0) return nullptr;  // wait for slots to drain
+        if (victim < 0) {
+            // no idle pool to evict: the least recently used pools that would make room stop
+            // admitting requests, so that they drain and the blocked request is served next
+            // (otherwise steady arrivals for existing pools could hold it back without bound)
+            std::vector<Pool *> order;
+            for (auto &Q : s->pools) order.push_back(Q.get());
+            std::sort(order.begin(), order.end(),
+                      [](const Pool *a, const Pool *b) { return a->last_used < b->last_used; });
+            size_t freed = 0;
+            for (Pool *Q : order) {
+                if (s->used - freed + need <= s->budget) break;
+                Q->draining = true;
+                freed += Q->bytes;
+            }
+            return nullptr;  // wait for slots to drain
+        }
         // drain the victim's lane so that no launch record refers to it any more
         Lane &L = s->lanes[s->pools[victim]->lane];
         (void)hipStreamSynchronize(L.stream);
@@ -332,6 +349,7 @@ static Pool *find_or_create_pool(mfwf_server s, const PoolKey &key, std::string 
         s->stat[3] = (double)s->pools.size();
         s->stat[4] = (double)s->used;
     }
+    for (auto &Q : s->pools) Q->draining = false;  // room made: admission as usual again
     std::unique_ptr<Pool> P(new Pool());
     P->key = key;
     // the lane with the least static load (maps x pixels x l per slot, FP64 counted twice)
@@ -415,7 +433,7 @@ static void worker_main(mfwf_server s) {
                 continue;
             }
             int b = -1;
-            for (int k = 0; k < P->nslots && b < 0; k++)
+            for (int k = 0; k < P->nslots && b < 0 && !P->draining; k++)
                 if (!P->slot[k]) b = k;
             if (b < 0) {
                 ++it;

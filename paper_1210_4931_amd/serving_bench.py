@@ -76,12 +76,23 @@ def _run(srv, bank, reqs, K, arrivals=None, tag=""):
     t_start = time.perf_counter()
 
     def waiter():
-        for i in range(len(reqs)):
-            ready.acquire()
-            lat[i] = srv.wait(ids[i])
-            if tag and (i + 1) % 25 == 0:
-                _log("%s: %d/%d done after %.1f s" % (tag, i + 1, len(reqs),
-                                                     time.perf_counter() - t_start))
+        # completions in the order they happen, each one logged as it is seen
+        submitted, open_ids, done = 0, [], 0
+        while done < len(reqs):
+            while ready.acquire(blocking=not open_ids):
+                open_ids.append(submitted)
+                submitted += 1
+                if submitted == len(reqs):
+                    break
+            for i in [i for i in open_ids if srv.done(ids[i])]:
+                lat[i] = srv.wait(ids[i])
+                open_ids.remove(i)
+                done += 1
+                if tag:
+                    _log("%s: request %d (nside %d, %s) done, %d/%d after %.1f s"
+                         % (tag, i, reqs[i][0], reqs[i][1], done, len(reqs),
+                            time.perf_counter() - t_start))
+            time.sleep(0.02)
 
     th = threading.Thread(target=waiter)
     th.start()
@@ -120,9 +131,13 @@ def run_serving(nsides=(128, 256, 512), requests=120, loads=(0.8,), K=300, slots
     bank = _bank(mf, dev, nsides, per_nside)
     srv = mf.Server(slots=slots, hbm_gb=hbm_gb)
     try:
-        _log("warm-up: one pool per (nside, dtype)")
-        warm = [(n, dt, 0) for n in nsides for dt in ("f32", "f64")]
-        _run(srv, bank, warm, 2)
+        # one pool per (nside, dtype), created (plan set-up and kernel-shape tuning) one at a
+        # time so that each one's set-up time is logged
+        for n in nsides:
+            for dt in ("f32", "f64"):
+                t0 = time.perf_counter()
+                _run(srv, bank, [(n, dt, 0)], 2)
+                _log("warm-up: pool nside %d %s ready in %.1f s" % (n, dt, time.perf_counter() - t0))
         reqs = _draw(seed, requests, nsides, per_nside)
         lat, span = _run(srv, bank, reqs, K, tag="saturation")
         sat = _summary(reqs, lat, span)

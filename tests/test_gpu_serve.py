@@ -124,6 +124,51 @@ def test_pools_evicted_to_fit_the_budget(mf):
     assert st["pools_evicted"] >= 1 and st["completed"] == 4
 
 
+def test_request_for_a_new_pool_is_not_starved(mf):
+    """A budget that holds two pools, both kept busy by a steady stream of requests: a
+    request of a third shape still completes while the stream goes on (the pools that must
+    make room stop admitting, drain and are evicted), and every request gets the standalone
+    result."""
+    from paper_1210_4931_amd.mfwf import Server
+    a, b, c = (Server.pool_bytes(16, 32, "f64", 2), Server.pool_bytes(32, 64, "f64", 2),
+               Server.pool_bytes(16, 32, "f32", 2))
+    budget = 1.01 * max(a + b, c + max(a, b))
+    assert a + b + c > budget
+    srv = Server(slots=2, hbm_gb=budget / 1e9)
+    shapes = [(16, "f64"), (32, "f64")]
+    reqs, k = [], 0
+
+    def submit(nside, dtype):
+        nonlocal k
+        r = W.serve_request(400 + k, nsides=(nside,))
+        k += 1
+        r.dtype = dtype
+        d, ninv = _inputs(r)
+        h = srv.submit(r.nside, r.lmax, r.cl, dev(ninv), dev(d), mask=dev(r.mask, torch.uint8),
+                       dtype=dtype, iters=15)
+        reqs.append((r, d, ninv, h))
+        return h
+
+    for j in range(4):
+        submit(*shapes[j % 2])
+    hc = submit(16, "f32")
+    t0 = time.perf_counter()
+    while not srv.done(hc[0]) and time.perf_counter() - t0 < 60.0:
+        outstanding = sum(not srv.done(h[0]) for *_, h in reqs)
+        if outstanding < 6:
+            submit(*shapes[k % 2])
+        time.sleep(0.002)
+    assert srv.done(hc[0]), "the new-shape request waited behind a steady stream"
+    for *_, h in reqs:
+        srv.wait(h[0])
+    st = srv.stats()
+    srv.close()
+    assert st["pools_evicted"] >= 1 and st["completed"] == len(reqs)
+    for r, d, ninv, (rid, alm, m) in reqs[:6] + [reqs[-1]]:
+        a_ref, m_ref = _standalone(mf, r, d, ninv, 15)
+        assert torch.equal(alm, a_ref), (r.rid, r.dtype)
+
+
 def test_served_nside2048_request_equals_standalone(mf):
     """A 2048 / 4096 request (FP64, split ring transforms) next to a small one: bitwise the
     standalone solve.  16 slots per pool would put the 2048 pool at about 200 GB, so the
