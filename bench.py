@@ -39,11 +39,16 @@ PEAK_HBM = 8.0e12                              # HBM3E bytes/s
 # profiles/ring_step_and_gemms_nside512_lmax1024_b64_hbm_traffic.md.  Valid only for the
 # kernel source they were taken on, identified by the SHA-256 of the source file.
 TRAFFIC = {
-    "ring_step": {"bytes": 3.9279e9, "source": "ringfft.hip",
-                  "sha256": "56160d4a0d7b51965f7d620db837230de31e9b440372df2608eea27eb6f05e9a"},
-    "gemm_analysis": {"bytes": 4.8820e9, "source": "batched.hip",
-                      "sha256": "8891e3b5e1e4552c632f0aaa57c374432d79c5811d23c205dc8e3a378ec16e21"},
+    "ring_step": {"bytes": 4.2555e9, "source": "ringfft.hip",
+                  "sha256": "5e95b1de4421d59762b544ddfc2aa1843730d9839ae8435b75a4fa209cbdcf65"},
+    "gemm_analysis": {"bytes": 5.2346e9, "source": "batched.hip",
+                      "sha256": "8bd2e3caae67d6cf641199c6191a4a44c025c540f296972b6414b9be485eebf9"},
 }
+# What the shader counters say limits the ring step (VALU issue and LDS bank conflicts, not
+# HBM): profiles/batched_nside512_lmax1024_b64_shader_counters.md, same kernel sources.
+RING_COUNTERS = {"valu_busy": [0.44, 0.49], "lds_bank_conflict_share": [0.26, 0.27],
+                 "mfma_busy": 0.0, "hbm_traffic_over_algorithmic": 1.12,
+                 "profile": "profiles/batched_nside512_lmax1024_b64_shader_counters.md"}
 
 
 _T0 = time.perf_counter()
@@ -522,7 +527,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "ring_step (k_fft_inv_fwd, both length classes)",
                      "achieved": ring_bw / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                      "frac": ring_bw / PEAK_HBM, "algorithmic_bytes": ring_bytes,
-                     "ms": kt32["fft_fwd"], "traffic": measured_traffic("ring_step")},
+                     "ms": kt32["fft_fwd"], "traffic": measured_traffic("ring_step"),
+                     "counters": RING_COUNTERS if measured_traffic("ring_step") else None},
         "roofline_gemm": {"bound": "mfma", "kernel": "gemm_" + dom32.split("_")[1],
                           "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
                           "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
