@@ -355,8 +355,9 @@ int mfwf_plan_work(mfwf_plan plan, double *out4);
 /*
  * Kernel shapes the plan uses (host, 8 ints): [0] FP64 Legendre synthesis variant (0..8),
  * [1] analysis variant (0..5), [2] maps per workgroup of the batched form's ring step for
- * the shorter transforms and [3] for the longest (1, 2, 4), [4] largest column tile of the
- * analysis GEMM and [5] of the synthesis GEMM, in units of 64 columns (1, 2), [6] 1 if the
+ * the shorter transforms and [3] for the longest (1, 2, 4), [4] column tile of the analysis
+ * GEMM (1: 64 columns in 4 waves, 2: 128 columns in 4 waves, 3: 128 columns in 8 waves) and
+ * [5] largest column tile of the synthesis GEMM, in units of 64 columns (1, 2), [6] 1 if the
  * temperature GEMMs generate lambda_lm from the FP64 recurrence (its state every 16 values
  * of l, tabulated per plan) instead of reading the FP32 table (0; no table above nside 1024),
  * [7] how they were set: 0 defaults, 1 by the autotuner at plan creation (timed, or read

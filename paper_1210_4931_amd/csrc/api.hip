@@ -294,6 +294,7 @@ static bool knob_valid(int knob, int v) {
         case kKnobAna: return v >= 0 && v < leg_analysis_variants();
         case kKnobG0: case kKnobG1: return v == 1 || v == 2 || v == 4;
         case kKnobLamGen: return v == 0 || v == 1;
+        case kKnobCtA: return v >= 1 && v <= 3;
         default: return v == 1 || v == 2;
     }
 }
@@ -458,8 +459,8 @@ static int autotune(Plan &p, const std::string &devname) {
             }));
         }
         if (2 * B > 64) {  // more than 64 active columns: both column tiles apply
-            const std::vector<int> cv = {1, 2};
-            MFWF_TRY(tune_knob(p, kKnobCtA, cv, [&] { return launch_gemm_analysis(p, B, p.d_a32, nullptr, 1.0, 1.0); }));
+            const std::vector<int> cv = {1, 2}, cva = {1, 2, 3};
+            MFWF_TRY(tune_knob(p, kKnobCtA, cva, [&] { return launch_gemm_analysis(p, B, p.d_a32, nullptr, 1.0, 1.0); }));
             MFWF_TRY(tune_knob(p, kKnobCtS, cv, [&] { return launch_gemm_synthesis(p, B); }));
         }
     }

@@ -279,9 +279,11 @@ __host__ __device__ constexpr int lds_floats(int main_floats) {
 // G_N + G_S and odd rows G_N - G_S (a table with lambda's mirror symmetry); flip swaps the
 // two, for a table that is odd where lambda is even (the spin-2 F-).  Waves per SIMD: 4
 // for the one-tile table kernel (128 registers, the chunk sums included), 3 where lambda is
-// generated (its recurrence state needs more), 2 for two column tiles.
-template <int NCT, bool GEN>
-__global__ void __launch_bounds__(256, NCT == 1 ? (GEN ? 3 : 4) : 2)
+// generated (its recurrence state needs more), 2 for two column tiles.  NW = 8: eight
+// waves (128 columns of one-tile waves) share each lambda tile, which a launch of more than
+// 64 active columns otherwise reads once per 64-column group.
+template <int NCT, bool GEN, int NW = 4>
+__global__ void __launch_bounds__(64 * NW, NCT == 1 ? (GEN ? 3 : 4) : 2)
 k_gemm_analysis(const float *__restrict__ lam, LamGen gen, const long *__restrict__ loff,
                 const int *__restrict__ Lp, const int *__restrict__ minls32,
                 const int2 *__restrict__ items, const int *__restrict__ tab, int per_xcd,
@@ -290,7 +292,9 @@ k_gemm_analysis(const float *__restrict__ lam, LamGen gen, const long *__restric
                 float *__restrict__ s_out, double scale_s, double lto, int lmax, int npair,
                 int Rp, int nring, int nm, int C2, int ncols, int ncg,
                 const double *__restrict__ tau_b, double lto_per_tau, int flip) {
-    constexpr int CT = col_tile(NCT), NX = CT / 32;  // columns; X float4 loads per thread
+    static_assert(NW == 4 || (NW == 8 && NCT == 1), "eight waves only with one-tile waves");
+    // threads; columns; lambda and X float4 loads per thread
+    constexpr int NTH = 64 * NW, CT = col_tile(NCT) * NW / 4, NL = 1024 / NTH, NX = 8 * CT / NTH;
     // lambda tile [pair][row] and X_0, X_1 tiles [pair][col]; reused by the epilogue
     __shared__ __align__(16) float lds[lds_floats(32 * (kAnaRows + 4) + 2 * 32 * (CT + 4))];
     __shared__ double sAc[2][GEN ? kAnaRows : 1];  // A_lm, c_lm of the tile's rows (GEN)
@@ -317,10 +321,11 @@ k_gemm_analysis(const float *__restrict__ lam, LamGen gen, const long *__restric
     const float *lrow = GEN ? nullptr : lam + loff[m] + kAnaRows * t;
     const int wcol = 32 * NCT * ch;  // first column of this wave within the tile
     const bool wave_on = (CT * cg + wcol) < ncols;
-    floatx4 rl[4], rn[NX], rs[NX];
-    // GEN: thread (pair gpp = tid / 8, rows 16 (tid % 8) ..) of a chunk; its segment state,
-    // start index, seeds and z, loaded with the chunk's other operands
+    floatx4 rl[NL], rn[NX], rs[NX];
+    // GEN: thread (pair gpp = tid / 8, rows 16 (tid % 8) ..) of a chunk, threads 0..255; its
+    // segment state, start index, seeds and z, loaded with the chunk's other operands
     const int gpp = threadIdx.x >> 3, gk = threadIdx.x & 7;
+    const bool gen_thread = NW == 4 || threadIdx.x < 256;
     double2 gst = make_double2(0.0, 0.0), gsd = gst;
     double gz = 0.0;
     int gls = lmax + 1;
@@ -334,21 +339,23 @@ k_gemm_analysis(const float *__restrict__ lam, LamGen gen, const long *__restric
     }
     auto load = [&](int pc) __attribute__((always_inline)) {
         if constexpr (GEN) {
-            const int p = 32 * pc + gpp, pq = min(p, npair - 1);
-            gst = gen.lck[(gen.segoff[m] + 8 * t + gk) * (long)Rp + p];
-            gsd = gen.seed[(long)m * npair + pq];
-            gz = gen.z[pq];
-            gls = p < npair ? gen.lstart[(long)m * npair + pq] : lmax + 1;  // padding: zero rows
+            if (gen_thread) {
+                const int p = 32 * pc + gpp, pq = min(p, npair - 1);
+                gst = gen.lck[(gen.segoff[m] + 8 * t + gk) * (long)Rp + p];
+                gsd = gen.seed[(long)m * npair + pq];
+                gz = gen.z[pq];
+                gls = p < npair ? gen.lstart[(long)m * npair + pq] : lmax + 1;  // padding: zero rows
+            }
         } else {
 #pragma unroll
-            for (int u = 0; u < 4; u++) {  // lambda: 32 pairs x 128 rows
-                const int e = threadIdx.x + 256 * u, pp = e >> 5, c4 = e & 31;
+            for (int u = 0; u < NL; u++) {  // lambda: 32 pairs x 128 rows
+                const int e = threadIdx.x + NTH * u, pp = e >> 5, c4 = e & 31;
                 rl[u] = ld4(lrow + (long)(32 * pc + pp) * L + 4 * c4);
             }
         }
 #pragma unroll
         for (int u = 0; u < NX; u++) {  // ring-Fourier: 32 pairs x CT columns
-            const int e = threadIdx.x + 256 * u, pp = e / (CT / 4), c4 = e % (CT / 4);
+            const int e = threadIdx.x + NTH * u, pp = e / (CT / 4), c4 = e % (CT / 4);
             const int p = 32 * pc + pp, col = CT * cg + 4 * c4;
             // loads from clamped in-range addresses; values outside the problem are zeroed
             // when they are stored to LDS, so that no wait for the loads comes before the
@@ -367,21 +374,22 @@ k_gemm_analysis(const float *__restrict__ lam, LamGen gen, const long *__restric
     while (pc < nchunk) {
         __syncthreads();
         if constexpr (GEN) {
-            lam_rows16(gst, gls, gsd, gz, m + kAnaRows * t + 16 * gk, lmax,
-                       [&](int r) { return sAc[0][16 * gk + r]; }, [&](int r) { return sAc[1][16 * gk + r]; },
-                       [&](int q, const float (&v)[4]) {
-                           st4(&sl[gpp][16 * gk + 4 * q], floatx4{v[0], v[1], v[2], v[3]});
-                       });
+            if (gen_thread)
+                lam_rows16(gst, gls, gsd, gz, m + kAnaRows * t + 16 * gk, lmax,
+                           [&](int r) { return sAc[0][16 * gk + r]; }, [&](int r) { return sAc[1][16 * gk + r]; },
+                           [&](int q, const float (&v)[4]) {
+                               st4(&sl[gpp][16 * gk + 4 * q], floatx4{v[0], v[1], v[2], v[3]});
+                           });
         } else {
 #pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const int e = threadIdx.x + 256 * u, pp = e >> 5, c4 = e & 31;
+            for (int u = 0; u < NL; u++) {
+                const int e = threadIdx.x + NTH * u, pp = e >> 5, c4 = e & 31;
                 st4(&sl[pp][4 * c4], rl[u]);
             }
         }
 #pragma unroll
         for (int u = 0; u < NX; u++) {
-            const int e = threadIdx.x + 256 * u, pp = e / (CT / 4), c4 = e % (CT / 4);
+            const int e = threadIdx.x + NTH * u, pp = e / (CT / 4), c4 = e % (CT / 4);
             const int p = 32 * pc + pp, col = CT * cg + 4 * c4;
             const bool on = p < npair && col < ncols, south = on && (nring - 1 - p != p);
             const floatx4 xn = keep4(on, rn[u]), xs = keep4(south, rs[u]);
@@ -419,24 +427,27 @@ k_gemm_analysis(const float *__restrict__ lam, LamGen gen, const long *__restric
         }
         pc = pn;
     }
-    // Epilogue through LDS: per column half, every wave parks its 64 rows x 32 columns
-    // ([row][36]) and stores whole 128-byte row segments with 16-byte stores.  Its lane
-    // indices are formed anew from the thread id, so that none of them holds a register
-    // through the main loop.
+    // Epilogue through LDS: per column tile, every wave parks its 64 rows x 32 columns
+    // ([row][36]) and stores whole 128-byte row segments with 16-byte stores (with eight
+    // waves, four at a time).  Its lane indices are formed anew from the thread id, so that
+    // none of them holds a register through the main loop.
     const long base = mofs[m] - m;
     const int te = fresh_tid();
     const int we = te >> 6, le = te & 63, lhe = we & 1, wcole = 32 * NCT * (we >> 1);
-    float (*stage)[36] = reinterpret_cast<float (*)[36]>(lds) + 64 * we;
+    float (*stage)[36] = reinterpret_cast<float (*)[36]>(lds) + 64 * (we & 3);
 #pragma unroll
-    for (int ct = 0; ct < NCT; ct++) {
+    for (int ct = 0; ct < NCT; ct++)
+#pragma unroll
+    for (int rnd = 0; rnd < NW / 4; rnd++) {
         __syncthreads();
+        if ((we >> 2) == rnd)
 #pragma unroll
-        for (int r = 0; r < 16; r++)
+            for (int r = 0; r < 16; r++)
 #pragma unroll
-            for (int par = 0; par < 2; par++) stage[2 * acc_row(r, le) + par][le & 31] = acc[par][ct][r];
+                for (int par = 0; par < 2; par++) stage[2 * acc_row(r, le) + par][le & 31] = acc[par][ct][r];
         __syncthreads();
         const int col = CT * cg + wcole + 32 * ct + 4 * (le & 7);
-        if (CT * cg + wcole >= ncols || col >= ncols) continue;
+        if ((we >> 2) != rnd || CT * cg + wcole >= ncols || col >= ncols) continue;
 #pragma unroll
         for (int it = 0; it < 8; it++) {
             const int row = 8 * it + (le >> 3);
@@ -736,21 +747,27 @@ static LamGen lam_gen(const Plan &p) {
 static int analysis_launch(const Plan &p, int nc, int C2, const float *table, const float *cols,
                            float *a_out, float *s_out, double scale_s, double lto,
                            const double *tau_b, double lto_per_tau, int flip) {
-    const int nct = (nc <= 64 || p.gemm_ct[0] == 1) ? 1 : 2, ncg = (nc + col_tile(nct) - 1) / col_tile(nct);
-    const dim3 grid(8 * p.ana_per_xcd * ncg), block(256);
+    // column tile choice 1: 64 columns (4 waves), 2: 128 columns (4 waves of two tiles), 3:
+    // 128 columns (8 waves of one tile); at most 64 active columns always take 1
+    const int choice = nc <= 64 ? 1 : p.gemm_ct[0];
+    const int nct = choice == 2 ? 2 : 1, nw = choice == 3 ? 8 : 4;
+    const int ct = col_tile(nct) * nw / 4, ncg = (nc + ct - 1) / ct;
+    const dim3 grid(8 * p.ana_per_xcd * ncg), block(64 * nw);
     const LamGen g = lam_gen(p);
-#define MFWF_ANA(NCT, GEN)                                                                         \
-    hipLaunchKernelGGL((k_gemm_analysis<NCT, GEN>), grid, block, 0, p.stream, table, g, p.d_loff,   \
+#define MFWF_ANA(NCT, GEN, NW)                                                                     \
+    hipLaunchKernelGGL((k_gemm_analysis<NCT, GEN, NW>), grid, block, 0, p.stream, table, g, p.d_loff, \
                        p.d_Lp, p.d_minls32, p.d_ana_items, p.d_ana_tab, p.ana_per_xcd, cols,         \
                        p.d_mofs, p.d_cl, a_out, s_out, scale_s, lto, p.lmax, p.npair, p.Rp,          \
                        p.nring, p.nm, C2, nc, ncg, tau_b, lto_per_tau, flip)
     if (table == nullptr) {
         if (!p.d_lck) return fail(MFWF_EINVAL, "no lambda segment states in this plan");
-        if (nct == 1) MFWF_ANA(1, true);
-        else MFWF_ANA(2, true);
+        if (nw == 8) MFWF_ANA(1, true, 8);
+        else if (nct == 1) MFWF_ANA(1, true, 4);
+        else MFWF_ANA(2, true, 4);
     } else {
-        if (nct == 1) MFWF_ANA(1, false);
-        else MFWF_ANA(2, false);
+        if (nw == 8) MFWF_ANA(1, false, 8);
+        else if (nct == 1) MFWF_ANA(1, false, 4);
+        else MFWF_ANA(2, false, 4);
     }
 #undef MFWF_ANA
     MFWF_HIP(hipGetLastError());

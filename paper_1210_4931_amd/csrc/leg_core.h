@@ -70,4 +70,26 @@ struct PairState {
     }
 };
 
+// (x, y) of every lane after exchanging lanes 32..63 of x with lanes 0..31 of y (SWAP32),
+// or the odd 16-lane rows of x with the even rows of y (v_permlane{32,16}_swap, one 32-bit
+// half at a time): x + y then holds x summed over lanes L and L + 32 (L + 16) in the lower
+// lanes (even rows) and y summed over L - 32 (L - 16) and L in the upper lanes (odd rows).
+template <bool SWAP32>
+__device__ __forceinline__ double swap_add(double x, double y) {
+    const unsigned long long a = __double_as_longlong(x), b = __double_as_longlong(y);
+    const unsigned alo = (unsigned)a, ahi = (unsigned)(a >> 32), blo = (unsigned)b, bhi = (unsigned)(b >> 32);
+    unsigned xl, yl, xh, yh;
+    if constexpr (SWAP32) {
+        const auto l = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+        xl = l[0], yl = l[1], xh = h[0], yh = h[1];
+    } else {
+        const auto l = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+        xl = l[0], yl = l[1], xh = h[0], yh = h[1];
+    }
+    return __longlong_as_double(((unsigned long long)xh << 32) | xl) +
+           __longlong_as_double(((unsigned long long)yh << 32) | yl);
+}
+
 }  // namespace mfwf

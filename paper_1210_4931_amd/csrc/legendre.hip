@@ -181,7 +181,8 @@ template <int NB>
 struct AnaChunk {
     static constexpr int C = 16 / NB;      // values of l per reduction
     static constexpr int V = 2 * NB * C;   // doubles reduced per lane per chunk (= 32)
-    static constexpr int LD = V + 2;       // LDS row stride (keeps 16-byte alignment)
+    static constexpr int LD = V + 2;       // LDS row stride of the plain transpose-reduce
+    static constexpr int Q = V / 4;        // doubles per lane after the two lane swaps
 };
 
 // acc[2 (c NB + j) + comp] += sum_k mu_{c0+c}(pair k) X_{parity(c)}[k][j]
@@ -218,7 +219,7 @@ __device__ __forceinline__ void analysis_one_m(int m, int g, const double2 *__re
                                                double2 *__restrict__ apart, long nalm,
                                                int nb_total, int lmax, int npair, int b0,
                                                double *red) {
-    constexpr int C = AnaChunk<NB>::C, V = AnaChunk<NB>::V, LD = AnaChunk<NB>::LD;
+    constexpr int C = AnaChunk<NB>::C, V = AnaChunk<NB>::V, LD = AnaChunk<NB>::LD, Q = AnaChunk<NB>::Q;
     static_assert(V == 32, "reduction assumes 32 values per lane");
     PairState<P> st;
     st.load(m, g, npair, lmax, zp, lstart, seed);
@@ -280,15 +281,34 @@ __device__ __forceinline__ void analysis_one_m(int m, int g, const double2 *__re
             for (int c = 0; c < C; c++) Acur[c] = (c0 + c <= lmax) ? Am[c0 + c] : 0.0;
             analysis_chunk<NB, P, true, false>(c0, lmax, st, Acur, Xe, Xo, acc);
         }
-        // transpose-reduce across the 64 lanes: lane L sums value v = L/2 over half L%2
-#pragma unroll
-        for (int v = 0; v < V; v += 2)
-            *reinterpret_cast<double2 *>(&red[threadIdx.x * LD + v]) = make_double2(acc[v], acc[v + 1]);
-        __syncthreads();
+        // sum over the 64 lanes.  P < 4: two lane swaps halve the values a lane holds twice
+        // (the 16-lane row r = L / 16 then holds values Q r .. Q r + Q - 1, each summed over
+        // four lanes), then through LDS lane L sums value v = L / 2 over half L % 2 of its
+        // row.  P = 4 (whose registers the swaps would exceed): all values through LDS, lane
+        // L summing value L / 2 over half L % 2 of the wave.
         const int v = threadIdx.x >> 1, h = threadIdx.x & 1;
         double s = 0.0;
+        if constexpr (P < 4) {
+            double h1[V / 2], h2[Q];
+#pragma unroll
+            for (int i = 0; i < V / 2; i++) h1[i] = swap_add<true>(acc[i], acc[i + V / 2]);
+#pragma unroll
+            for (int i = 0; i < Q; i++) h2[i] = swap_add<false>(h1[i], h1[i + Q]);
+#pragma unroll
+            for (int i = 0; i < Q; i += 2)
+                *reinterpret_cast<double2 *>(&red[threadIdx.x * Q + i]) = make_double2(h2[i], h2[i + 1]);
+            __syncthreads();
+            const int r = v / Q, jq = v - Q * r;
+#pragma unroll
+            for (int q = 0; q < 8; q++) s += red[(16 * r + 8 * h + q) * Q + jq];
+        } else {
+#pragma unroll
+            for (int i = 0; i < V; i += 2)
+                *reinterpret_cast<double2 *>(&red[threadIdx.x * LD + i]) = make_double2(acc[i], acc[i + 1]);
+            __syncthreads();
 #pragma unroll 8
-        for (int q = 0; q < 32; q++) s += red[(h * 32 + q) * LD + v];
+            for (int q = 0; q < 32; q++) s += red[(h * 32 + q) * LD + v];
+        }
         s += __shfl_xor(s, 1);
         __syncthreads();
         // v = 2 (c NB + j) + comp
@@ -306,7 +326,7 @@ k_leg_analysis(const double2 *__restrict__ phase, int nring, int nm,
                const int *__restrict__ lstart, const double2 *__restrict__ seed,
                const double *__restrict__ zp, double2 *__restrict__ apart, long nalm,
                int nb_total, int lmax, int npair) {
-    __shared__ double red[kW * AnaChunk<NB>::LD];
+    __shared__ __align__(16) double red[kW * (P < 4 ? AnaChunk<NB>::Q : AnaChunk<NB>::LD)];
     const int g = blockIdx.x, mi = blockIdx.y, b0 = blockIdx.z * NB;
     const int npass = (lmax - mi > mi) ? 2 : 1;
     for (int pass = 0; pass < npass; pass++)

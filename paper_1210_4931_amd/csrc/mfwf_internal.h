@@ -59,7 +59,8 @@ struct Plan {
     int ana_variant = 0;    // index into the Legendre analysis kernel variants
     int ngroup;             // pair groups (waves per m) of the chosen analysis variant
     int ring_group[2] = {1, 1};  // maps per workgroup of the columns ring step, per class
-    int gemm_ct[2] = {2, 2};     // largest column tile (x 64) of the analysis / synthesis GEMM
+    int gemm_ct[2] = {2, 2};     // column tiles of the analysis GEMM (1: 64 columns, 2: 128 in
+                                 // 4 waves, 3: 128 in 8 waves) and the synthesis GEMM (1, 2)
     int tune_source = 0;         // 0 defaults, 1 autotuned (timed or cached), 3 forced
     int ngroup_max;         // largest pair-group count of any analysis variant
 

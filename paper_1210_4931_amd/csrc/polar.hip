@@ -145,35 +145,42 @@ k_leg_synth_pol(const double2 *__restrict__ alm, long nalm, const double *__rest
 // ---------------------------------------------------------------------------------------
 static constexpr int kPC = 4;              // values of l per reduction chunk
 static constexpr int kPV = 6 * kPC;        // doubles per lane per chunk
-static constexpr int kPLD = kPV + 2;       // LDS row stride
+static constexpr int kPQ = kPV / 4;        // doubles per lane after the two lane swaps
+static_assert(kW == 64 && kPV % 4 == 0, "the chunk reduction assumes one wave of 64 lanes");
+
 
 struct PolAnaIn {
     double2 Xe, Xo;          // T: G_N + G_S, G_N - G_S
     double2 QP, QM, UP, UM;  // (G_N +- G_S) / s^2 for Q and U
 };
 
-template <bool INJ, int PAR>
-__device__ __forceinline__ void pol_ana_step(int l, int c, PairState<1> &st, double z, double zz,
+template <bool INJ, int PAR, int P>
+__device__ __forceinline__ void pol_ana_step(int l, int c, PairState<P> &st, const double (&zz)[P],
                                              double A, const double *__restrict__ pc,
-                                             const PolAnaIn &in, double (&acc)[kPV]) {
-    double cur[1];
+                                             const PolAnaIn (&in)[P], double (&acc)[kPV]) {
+    double cur[P];
     st.template step<INJ>(l, A, cur);
-    const double mu = cur[0], mup = st.u2[0];
-    const double fp = fma(fma(pc[1], zz, pc[0]), mu, pc[2] * z * mup);
-    const double fm = fma(pc[3], mup, pc[4] * z * mu);
-    const double2 X = PAR ? in.Xo : in.Xe;
-    // even l + m: E -= F+ QP + i F- UM, B -= F+ UP - i F- QM; odd: QP <-> QM, UP <-> UM
-    const double2 Qa = PAR ? in.QM : in.QP, Ub = PAR ? in.UP : in.UM;
-    const double2 Ua = PAR ? in.UM : in.UP, Qb = PAR ? in.QP : in.QM;
     double *a = acc + 6 * c;
-    a[0] = fma(mu, X.x, a[0]);
-    a[1] = fma(mu, X.y, a[1]);
-    a[2] -= fma(fp, Qa.x, -fm * Ub.y);
-    a[3] -= fma(fp, Qa.y, fm * Ub.x);
-    a[4] -= fma(fp, Ua.x, fm * Qb.y);
-    a[5] -= fma(fp, Ua.y, -fm * Qb.x);
+#pragma unroll
+    for (int k = 0; k < P; k++) {  // the lane's pairs, summed in order
+        const double mu = cur[k], mup = st.u2[k], z = st.z[k];
+        const double fp = fma(fma(pc[1], zz[k], pc[0]), mu, pc[2] * z * mup);
+        const double fm = fma(pc[3], mup, pc[4] * z * mu);
+        const double2 X = PAR ? in[k].Xo : in[k].Xe;
+        // even l + m: E -= F+ QP + i F- UM, B -= F+ UP - i F- QM; odd: QP <-> QM, UP <-> UM
+        const double2 Qa = PAR ? in[k].QM : in[k].QP, Ub = PAR ? in[k].UP : in[k].UM;
+        const double2 Ua = PAR ? in[k].UM : in[k].UP, Qb = PAR ? in[k].QP : in[k].QM;
+        a[0] = fma(mu, X.x, a[0]);
+        a[1] = fma(mu, X.y, a[1]);
+        a[2] -= fma(fp, Qa.x, -fm * Ub.y);
+        a[3] -= fma(fp, Qa.y, fm * Ub.x);
+        a[4] -= fma(fp, Ua.x, fm * Qb.y);
+        a[5] -= fma(fp, Ua.y, -fm * Qb.x);
+    }
 }
 
+// P ring pairs per lane: pairs g kW P + k kW + lane, k < P (the pairs of PairState)
+template <int P>
 __device__ __forceinline__ void pol_analysis_one_m(int m, int g, int b,
                                                    const double2 *__restrict__ phase, int nring,
                                                    int nm, const double *__restrict__ Atab,
@@ -185,16 +192,20 @@ __device__ __forceinline__ void pol_analysis_one_m(int m, int g, int b,
                                                    double2 *__restrict__ apart, long nalm,
                                                    int nb_total, int lmax, int npair,
                                                    double *red) {
-    PairState<1> st;
+    PairState<P> st;
     st.load(m, g, npair, lmax, zp, lstart, seed);
-    const double z = st.z[0], zz = z * z;
+    double zz[P];
+#pragma unroll
+    for (int k = 0; k < P; k++) zz[k] = st.z[k] * st.z[k];
     const long off = mofs[m] - m;
     const double *Am = Atab + off;
     const double *pcm = pctab + 5 * off;
-    PolAnaIn in;
-    {
-        const int p = g * kW + (int)threadIdx.x;
+    PolAnaIn in[P];
+#pragma unroll
+    for (int k = 0; k < P; k++) {
+        const int p = g * kW * P + k * kW + (int)threadIdx.x;
         const bool valid = p < npair;
+        const double z = st.z[k];
         const int rN = p, rS = nring - 1 - p;
         const bool south = valid && rS != rN;
         auto G = [&](int c, int r, bool ok) {
@@ -204,12 +215,12 @@ __device__ __forceinline__ void pol_analysis_one_m(int m, int g, int b,
         const double2 qN = G(1, rN, valid), qS = G(1, rS, south);
         const double2 uN = G(2, rN, valid), uS = G(2, rS, south);
         const double is2 = valid ? 1.0 / ((1.0 - z) * (1.0 + z)) : 0.0;
-        in.Xe = make_double2(tN.x + tS.x, tN.y + tS.y);
-        in.Xo = make_double2(tN.x - tS.x, tN.y - tS.y);
-        in.QP = make_double2(is2 * (qN.x + qS.x), is2 * (qN.y + qS.y));
-        in.QM = make_double2(is2 * (qN.x - qS.x), is2 * (qN.y - qS.y));
-        in.UP = make_double2(is2 * (uN.x + uS.x), is2 * (uN.y + uS.y));
-        in.UM = make_double2(is2 * (uN.x - uS.x), is2 * (uN.y - uS.y));
+        in[k].Xe = make_double2(tN.x + tS.x, tN.y + tS.y);
+        in[k].Xo = make_double2(tN.x - tS.x, tN.y - tS.y);
+        in[k].QP = make_double2(is2 * (qN.x + qS.x), is2 * (qN.y + qS.y));
+        in[k].QM = make_double2(is2 * (qN.x - qS.x), is2 * (qN.y - qS.y));
+        in[k].UP = make_double2(is2 * (uN.x + uS.x), is2 * (uN.y + uS.y));
+        in[k].UM = make_double2(is2 * (uN.x - uS.x), is2 * (uN.y - uS.y));
     }
     double2 *outg = apart + (long)g * nb_total * 3 * nalm;
     const int lo = st.lo - ((st.lo + m) & 1);
@@ -224,27 +235,41 @@ __device__ __forceinline__ void pol_analysis_one_m(int m, int g, int b,
         if (c0 + kPC - 1 <= lmax && !inj) {
 #pragma unroll
             for (int c = 0; c < kPC; c++) {
-                if (c & 1) pol_ana_step<false, 1>(c0 + c, c, st, z, zz, Am[c0 + c], pcm + 5 * (c0 + c), in, acc);
-                else pol_ana_step<false, 0>(c0 + c, c, st, z, zz, Am[c0 + c], pcm + 5 * (c0 + c), in, acc);
+                if (c & 1) pol_ana_step<false, 1>(c0 + c, c, st, zz, Am[c0 + c], pcm + 5 * (c0 + c), in, acc);
+                else pol_ana_step<false, 0>(c0 + c, c, st, zz, Am[c0 + c], pcm + 5 * (c0 + c), in, acc);
             }
         } else {
 #pragma unroll
             for (int c = 0; c < kPC; c++) {
                 if (c0 + c > lmax) break;
-                if (c & 1) pol_ana_step<true, 1>(c0 + c, c, st, z, zz, Am[c0 + c], pcm + 5 * (c0 + c), in, acc);
-                else pol_ana_step<true, 0>(c0 + c, c, st, z, zz, Am[c0 + c], pcm + 5 * (c0 + c), in, acc);
+                if (c & 1) pol_ana_step<true, 1>(c0 + c, c, st, zz, Am[c0 + c], pcm + 5 * (c0 + c), in, acc);
+                else pol_ana_step<true, 0>(c0 + c, c, st, zz, Am[c0 + c], pcm + 5 * (c0 + c), in, acc);
             }
         }
-        // transpose-reduce across the 64 lanes: lane t < 2 kPV sums value t/2 over half t%2
+        // sum over the 64 lanes: two lane swaps halve the values a lane holds twice (the
+        // 16-lane row r = L / 16 then holds values kPQ r .. kPQ r + kPQ - 1, each summed over
+        // four lanes), then through LDS lane t < 2 kPV sums value t / 2 over half t % 2 of its
+        // row
+        double h1[kPV / 2], h2[kPQ];
 #pragma unroll
-        for (int v = 0; v < kPV; v += 2)
-            *reinterpret_cast<double2 *>(&red[threadIdx.x * kPLD + v]) = make_double2(acc[v], acc[v + 1]);
+        for (int i = 0; i < kPV / 2; i++) h1[i] = swap_add<true>(acc[i], acc[i + kPV / 2]);
+#pragma unroll
+        for (int i = 0; i < kPQ; i++) h2[i] = swap_add<false>(h1[i], h1[i + kPQ]);
+        if constexpr (kPQ % 2 == 0) {
+#pragma unroll
+            for (int i = 0; i < kPQ; i += 2)
+                *reinterpret_cast<double2 *>(&red[threadIdx.x * kPQ + i]) = make_double2(h2[i], h2[i + 1]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kPQ; i++) red[threadIdx.x * kPQ + i] = h2[i];
+        }
         __syncthreads();
         const int v = threadIdx.x >> 1, h = threadIdx.x & 1;
         double s = 0.0;
         if (v < kPV) {
-#pragma unroll 8
-            for (int q = 0; q < 32; q++) s += red[(h * 32 + q) * kPLD + v];
+            const int r = v / kPQ, j = v - kPQ * r;
+#pragma unroll
+            for (int q = 0; q < 8; q++) s += red[(16 * r + 8 * h + q) * kPQ + j];
         }
         s += __shfl_xor(s, 1);
         __syncthreads();
@@ -256,22 +281,30 @@ __device__ __forceinline__ void pol_analysis_one_m(int m, int g, int b,
     }
 }
 
+template <int P>
 __global__ void __launch_bounds__(kW)
 k_leg_analysis_pol(const double2 *__restrict__ phase, int nring, int nm,
                    const double *__restrict__ Atab, const double *__restrict__ pctab,
                    const long *__restrict__ mofs, const int *__restrict__ lstart,
                    const double2 *__restrict__ seed, const double *__restrict__ zp,
                    double2 *__restrict__ apart, long nalm, int nb_total, int lmax, int npair) {
-    __shared__ double red[kW * kPLD];
+    __shared__ __align__(16) double red[kW * kPQ];
     const int g = blockIdx.x, mi = blockIdx.y, b = blockIdx.z;
     const int npass = (lmax - mi > mi) ? 2 : 1;
     for (int pass = 0; pass < npass; pass++)
-        pol_analysis_one_m(pass == 0 ? mi : lmax - mi, g, b, phase, nring, nm, Atab, pctab, mofs,
-                           lstart, seed, zp, apart, nalm, nb_total, lmax, npair, red);
+        pol_analysis_one_m<P>(pass == 0 ? mi : lmax - mi, g, b, phase, nring, nm, Atab, pctab, mofs,
+                              lstart, seed, zp, apart, nalm, nb_total, lmax, npair, red);
 }
 
 static int pol_groups(int npair) { return (npair + kW - 1) / kW; }
-int pol_ngroup(const Plan &p) { return pol_groups(p.npair); }
+// ring pairs per lane of the analysis: two where there are pairs for more than one wave
+// (each lane sums its pairs before the sum over lanes, whose cost is per value of l)
+static int pol_ana_pairs(const Plan &p) { return p.npair > kW ? 2 : 1; }
+static int pol_ana_groups(const Plan &p) {
+    const int P = pol_ana_pairs(p);
+    return (p.npair + kW * P - 1) / (kW * P);
+}
+int pol_ngroup(const Plan &p) { return pol_ana_groups(p); }
 
 int launch_leg_synth_pol(const Plan &p, const double2 *alm_scaled, double2 *phase, int nb) {
     dim3 grid(pol_groups(p.npair), (p.lmax + 2) / 2, nb);
@@ -283,10 +316,15 @@ int launch_leg_synth_pol(const Plan &p, const double2 *alm_scaled, double2 *phas
 }
 
 int launch_leg_analysis_pol(const Plan &p, const double2 *phase, double2 *apart, int nb) {
-    dim3 grid(pol_groups(p.npair), (p.lmax + 2) / 2, nb);
-    hipLaunchKernelGGL(k_leg_analysis_pol, grid, dim3(kW), 0, p.stream, phase, p.nring, p.nm,
-                       p.d_A, p.d_pc, p.d_mofs, p.d_lstart, p.d_seed, p.d_z, apart, p.nalm, nb,
-                       p.lmax, p.npair);
+    dim3 grid(pol_ana_groups(p), (p.lmax + 2) / 2, nb);
+    if (pol_ana_pairs(p) == 2)
+        hipLaunchKernelGGL(k_leg_analysis_pol<2>, grid, dim3(kW), 0, p.stream, phase, p.nring, p.nm,
+                           p.d_A, p.d_pc, p.d_mofs, p.d_lstart, p.d_seed, p.d_z, apart, p.nalm, nb,
+                           p.lmax, p.npair);
+    else
+        hipLaunchKernelGGL(k_leg_analysis_pol<1>, grid, dim3(kW), 0, p.stream, phase, p.nring, p.nm,
+                           p.d_A, p.d_pc, p.d_mofs, p.d_lstart, p.d_seed, p.d_z, apart, p.nalm, nb,
+                           p.lmax, p.npair);
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }

@@ -65,8 +65,8 @@ def test_every_fp64_legendre_variant_matches_the_oracle(mf, nside, lmax):
 
 
 def test_batched_shapes_do_not_change_results(mf):
-    """Maps per ring-step workgroup (1, 2, 4 per transform class), GEMM column tiles (64 or
-    128 columns) and lambda read from the FP32 table or generated in the GEMMs from the
+    """Maps per ring-step workgroup (1, 2, 4 per transform class), GEMM column tiles (64
+    columns, or 128 in four or, for the analysis, eight waves) and lambda read from the FP32 table or generated in the GEMMs from the
     FP64 recurrence's segment states, on a 40-map batch (80 active columns): 6 iterations,
     bitwise equal to each other; one run against the oracle."""
     nside, lmax, nmaps, iters = 32, 64, 40, 6
@@ -74,7 +74,8 @@ def test_batched_shapes_do_not_change_results(mf):
     rng = np.random.default_rng(9)
     x = np.stack([d + 3.0 * rng.standard_normal(d.size) * (b % 3) for b in range(nmaps)])
     results = {}
-    for spec in ["g0=1,g1=1,cta=2,cts=2,lamgen=0", "g0=2,g1=2,cta=1,cts=1,lamgen=1",
+    for spec in ["g0=1,g1=1,cta=2,cts=2,lamgen=0", "g0=2,g1=2,cta=1,cts=1,lamgen=1", "cta=3,lamgen=0",
+                 "g0=2,g1=1,cta=3,cts=1,lamgen=1",
                  "g0=4,g1=1,cta=2,cts=1,lamgen=1", "g0=4,g1=4,cta=1,cts=2,lamgen=0",
                  "cta=2,cts=2,lamgen=1"]:
         print("forced", spec, flush=True)
@@ -95,7 +96,7 @@ def test_batched_shapes_do_not_change_results(mf):
 
 def test_malformed_force_is_an_error(mf):
     from paper_1210_4931_amd.mfwf import MFWFError
-    for spec in ["synth=99", "g0=3", "bogus=1", "synth"]:
+    for spec in ["synth=99", "g0=3", "cta=4", "cts=3", "bogus=1", "synth"]:
         with forced(spec), pytest.raises(MFWFError, match="MFWF_TUNE_FORCE"):
             mf.Plan(8, 16)
 
