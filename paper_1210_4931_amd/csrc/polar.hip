@@ -143,7 +143,7 @@ k_leg_synth_pol(const double2 *__restrict__ alm, long nalm, const double *__rest
 // ---------------------------------------------------------------------------------------
 // Legendre analysis, ring-Fourier rows of T, Q, U -> partial sums of T (mu-scaled), E, B
 // ---------------------------------------------------------------------------------------
-static constexpr int kPC = 4;              // values of l per reduction chunk
+static constexpr int kPC = 2;              // values of l per reduction chunk
 static constexpr int kPV = 6 * kPC;        // doubles per lane per chunk
 static constexpr int kPQ = kPV / 4;        // doubles per lane after the two lane swaps
 static_assert(kW == 64 && kPV % 4 == 0, "the chunk reduction assumes one wave of 64 lanes");
@@ -227,7 +227,24 @@ __device__ __forceinline__ void pol_analysis_one_m(int m, int g, int b,
     for (int l = m + (int)threadIdx.x; l < min(lo, lmax + 1); l += kW)
         for (int c = 0; c < 3; c++) outg[(3L * b + c) * nalm + off + l] = make_double2(0.0, 0.0);
 
+    // the recurrence and F+- coefficients of a chunk's values of l (wave-uniform), loaded one
+    // chunk ahead so that their latency passes behind the current chunk's arithmetic
+    struct Coef {
+        double A, pc[5];
+    };
+    auto load_coef = [&](int l0, Coef (&cf)[kPC]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int c = 0; c < kPC; c++) {
+            const int l = min(l0 + c, lmax);
+            cf[c].A = Am[l];
+#pragma unroll
+            for (int j = 0; j < 5; j++) cf[c].pc[j] = pcm[5 * l + j];
+        }
+    };
+    Coef cf[kPC], nf[kPC];
+    load_coef(lo, cf);
     for (int c0 = lo; c0 <= lmax; c0 += kPC) {
+        if (c0 + kPC <= lmax) load_coef(c0 + kPC, nf);
         double acc[kPV];
 #pragma unroll
         for (int v = 0; v < kPV; v++) acc[v] = 0.0;
@@ -235,15 +252,15 @@ __device__ __forceinline__ void pol_analysis_one_m(int m, int g, int b,
         if (c0 + kPC - 1 <= lmax && !inj) {
 #pragma unroll
             for (int c = 0; c < kPC; c++) {
-                if (c & 1) pol_ana_step<false, 1>(c0 + c, c, st, zz, Am[c0 + c], pcm + 5 * (c0 + c), in, acc);
-                else pol_ana_step<false, 0>(c0 + c, c, st, zz, Am[c0 + c], pcm + 5 * (c0 + c), in, acc);
+                if (c & 1) pol_ana_step<false, 1>(c0 + c, c, st, zz, cf[c].A, cf[c].pc, in, acc);
+                else pol_ana_step<false, 0>(c0 + c, c, st, zz, cf[c].A, cf[c].pc, in, acc);
             }
         } else {
 #pragma unroll
             for (int c = 0; c < kPC; c++) {
                 if (c0 + c > lmax) break;
-                if (c & 1) pol_ana_step<true, 1>(c0 + c, c, st, zz, Am[c0 + c], pcm + 5 * (c0 + c), in, acc);
-                else pol_ana_step<true, 0>(c0 + c, c, st, zz, Am[c0 + c], pcm + 5 * (c0 + c), in, acc);
+                if (c & 1) pol_ana_step<true, 1>(c0 + c, c, st, zz, cf[c].A, cf[c].pc, in, acc);
+                else pol_ana_step<true, 0>(c0 + c, c, st, zz, cf[c].A, cf[c].pc, in, acc);
             }
         }
         // sum over the 64 lanes: two lane swaps halve the values a lane holds twice (the
@@ -278,6 +295,8 @@ __device__ __forceinline__ void pol_analysis_one_m(int m, int g, int b,
         const int l = c0 + c;
         if (h == 0 && v < kPV && l <= lmax)
             reinterpret_cast<double *>(outg + (3L * b + comp) * nalm + off + l)[ri] = s;
+#pragma unroll
+        for (int c = 0; c < kPC; c++) cf[c] = nf[c];
     }
 }
 
