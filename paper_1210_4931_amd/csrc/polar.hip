@@ -39,24 +39,28 @@ __device__ __forceinline__ void cfma(double2 &acc, double f, double2 a) {
     acc.y = fma(f, a.y, acc.y);
 }
 
-template <bool INJ, int PAR>
-__device__ __forceinline__ void pol_synth_step(int l, PairState<1> &st, double z, double zz,
+template <bool INJ, int PAR, int P>
+__device__ __forceinline__ void pol_synth_step(int l, PairState<P> &st, const double (&zz)[P],
                                                double A, const double *__restrict__ pc,
                                                double2 aT, double2 aE, double2 aB,
-                                               PolSynthAcc &acc) {
-    double cur[1];
+                                               PolSynthAcc (&acc)[P]) {
+    double cur[P];
     st.template step<INJ>(l, A, cur);
-    const double mu = cur[0], mup = st.u2[0];
-    const double fp = fma(fma(pc[1], zz, pc[0]), mu, pc[2] * z * mup);
-    const double fm = fma(pc[3], mup, pc[4] * z * mu);
-    cfma(acc.T[PAR], mu, aT);
-    cfma(acc.P[PAR], fp, aE);
-    cfma(acc.R[PAR], fm, aB);
-    cfma(acc.X[PAR], fp, aB);
-    cfma(acc.Y[PAR], fm, aE);
+#pragma unroll
+    for (int k = 0; k < P; k++) {
+        const double mu = cur[k], mup = st.u2[k], z = st.z[k];
+        const double fp = fma(fma(pc[1], zz[k], pc[0]), mu, pc[2] * z * mup);
+        const double fm = fma(pc[3], mup, pc[4] * z * mu);
+        cfma(acc[k].T[PAR], mu, aT);
+        cfma(acc[k].P[PAR], fp, aE);
+        cfma(acc[k].R[PAR], fm, aB);
+        cfma(acc[k].X[PAR], fp, aB);
+        cfma(acc[k].Y[PAR], fm, aE);
+    }
 }
 
-template <int U>
+// P ring pairs per lane: pairs g kW P + k kW + lane, k < P (the pairs of PairState)
+template <int U, int P>
 __device__ __forceinline__ void pol_synth_one_m(int m, int g, int b, const double2 *__restrict__ alm,
                                                 long nalm, const double *__restrict__ Atab,
                                                 const double *__restrict__ pctab,
@@ -66,19 +70,23 @@ __device__ __forceinline__ void pol_synth_one_m(int m, int g, int b, const doubl
                                                 const double *__restrict__ zp,
                                                 double2 *__restrict__ phase, int lmax,
                                                 int npair, int nring, int nm) {
-    PairState<1> st;
+    PairState<P> st;
     st.load(m, g, npair, lmax, zp, lstart, seed);
-    const double z = st.z[0], zz = z * z;
+    double zz[P];
+#pragma unroll
+    for (int k = 0; k < P; k++) zz[k] = st.z[k] * st.z[k];
     const long off = mofs[m] - m;
     const double *Am = Atab + off;
     const double *pcm = pctab + 5 * off;
     const double2 *aT = alm + (3L * b + 0) * nalm + off;
     const double2 *aE = alm + (3L * b + 1) * nalm + off;
     const double2 *aB = alm + (3L * b + 2) * nalm + off;
-    PolSynthAcc acc;
+    PolSynthAcc acc[P];
 #pragma unroll
-    for (int q = 0; q < 2; q++)
-        acc.T[q] = acc.P[q] = acc.R[q] = acc.X[q] = acc.Y[q] = make_double2(0.0, 0.0);
+    for (int k = 0; k < P; k++)
+#pragma unroll
+        for (int q = 0; q < 2; q++)
+            acc[k].T[q] = acc[k].P[q] = acc[k].R[q] = acc[k].X[q] = acc[k].Y[q] = make_double2(0.0, 0.0);
 
     int l = st.lo - ((st.lo + m) & 1);  // blocks start at even l + m
     for (; l + U - 1 <= lmax; l += U) {
@@ -87,46 +95,51 @@ __device__ __forceinline__ void pol_synth_one_m(int m, int g, int b, const doubl
         for (int u = 0; u < U; u++) {
             const int lu = l + u;
             if (inj) {
-                if (u & 1) pol_synth_step<true, 1>(lu, st, z, zz, Am[lu], pcm + 5 * lu, aT[lu], aE[lu], aB[lu], acc);
-                else pol_synth_step<true, 0>(lu, st, z, zz, Am[lu], pcm + 5 * lu, aT[lu], aE[lu], aB[lu], acc);
+                if (u & 1) pol_synth_step<true, 1>(lu, st, zz, Am[lu], pcm + 5 * lu, aT[lu], aE[lu], aB[lu], acc);
+                else pol_synth_step<true, 0>(lu, st, zz, Am[lu], pcm + 5 * lu, aT[lu], aE[lu], aB[lu], acc);
             } else {
-                if (u & 1) pol_synth_step<false, 1>(lu, st, z, zz, Am[lu], pcm + 5 * lu, aT[lu], aE[lu], aB[lu], acc);
-                else pol_synth_step<false, 0>(lu, st, z, zz, Am[lu], pcm + 5 * lu, aT[lu], aE[lu], aB[lu], acc);
+                if (u & 1) pol_synth_step<false, 1>(lu, st, zz, Am[lu], pcm + 5 * lu, aT[lu], aE[lu], aB[lu], acc);
+                else pol_synth_step<false, 0>(lu, st, zz, Am[lu], pcm + 5 * lu, aT[lu], aE[lu], aB[lu], acc);
             }
         }
     }
     for (; l <= lmax; l++) {
-        if ((l + m) & 1) pol_synth_step<true, 1>(l, st, z, zz, Am[l], pcm + 5 * l, aT[l], aE[l], aB[l], acc);
-        else pol_synth_step<true, 0>(l, st, z, zz, Am[l], pcm + 5 * l, aT[l], aE[l], aB[l], acc);
+        if ((l + m) & 1) pol_synth_step<true, 1>(l, st, zz, Am[l], pcm + 5 * l, aT[l], aE[l], aB[l], acc);
+        else pol_synth_step<true, 0>(l, st, zz, Am[l], pcm + 5 * l, aT[l], aE[l], aB[l], acc);
     }
 
-    const int p = g * kW + (int)threadIdx.x;
-    if (p >= npair) return;
-    const int rN = p, rS = nring - 1 - p;
-    const double is2 = 1.0 / ((1.0 - z) * (1.0 + z));
-    auto row = [&](int c, int r) { return phase + ((3L * b + c) * nring + r) * nm + m; };
-    const double2 Ts = make_double2(acc.T[0].x + acc.T[1].x, acc.T[0].y + acc.T[1].y);
-    const double2 Td = make_double2(acc.T[0].x - acc.T[1].x, acc.T[0].y - acc.T[1].y);
-    const double2 Ps = make_double2(acc.P[0].x + acc.P[1].x, acc.P[0].y + acc.P[1].y);
-    const double2 Pd = make_double2(acc.P[0].x - acc.P[1].x, acc.P[0].y - acc.P[1].y);
-    const double2 Rs = make_double2(acc.R[0].x + acc.R[1].x, acc.R[0].y + acc.R[1].y);
-    const double2 Rd = make_double2(acc.R[0].x - acc.R[1].x, acc.R[0].y - acc.R[1].y);
-    const double2 Xs = make_double2(acc.X[0].x + acc.X[1].x, acc.X[0].y + acc.X[1].y);
-    const double2 Xd = make_double2(acc.X[0].x - acc.X[1].x, acc.X[0].y - acc.X[1].y);
-    const double2 Ys = make_double2(acc.Y[0].x + acc.Y[1].x, acc.Y[0].y + acc.Y[1].y);
-    const double2 Yd = make_double2(acc.Y[0].x - acc.Y[1].x, acc.Y[0].y - acc.Y[1].y);
-    // Q_N = -(P + iR), Q_S = -(P' - iR'), U_N = -(X - iY), U_S = -(X' + iY')
-    *row(0, rN) = Ts;
-    *row(1, rN) = make_double2(is2 * (-Ps.x + Rs.y), is2 * (-Ps.y - Rs.x));
-    *row(2, rN) = make_double2(is2 * (-Xs.x - Ys.y), is2 * (-Xs.y + Ys.x));
-    if (rS != rN) {
-        *row(0, rS) = Td;
-        *row(1, rS) = make_double2(is2 * (-Pd.x - Rd.y), is2 * (-Pd.y + Rd.x));
-        *row(2, rS) = make_double2(is2 * (-Xd.x + Yd.y), is2 * (-Xd.y - Yd.x));
+#pragma unroll
+    for (int k = 0; k < P; k++) {
+        const int p = g * kW * P + k * kW + (int)threadIdx.x;
+        if (p >= npair) continue;
+        const int rN = p, rS = nring - 1 - p;
+        const double z = st.z[k];
+        const double is2 = 1.0 / ((1.0 - z) * (1.0 + z));
+        auto row = [&](int c, int r) { return phase + ((3L * b + c) * nring + r) * nm + m; };
+        const PolSynthAcc &a = acc[k];
+        const double2 Ts = make_double2(a.T[0].x + a.T[1].x, a.T[0].y + a.T[1].y);
+        const double2 Td = make_double2(a.T[0].x - a.T[1].x, a.T[0].y - a.T[1].y);
+        const double2 Ps = make_double2(a.P[0].x + a.P[1].x, a.P[0].y + a.P[1].y);
+        const double2 Pd = make_double2(a.P[0].x - a.P[1].x, a.P[0].y - a.P[1].y);
+        const double2 Rs = make_double2(a.R[0].x + a.R[1].x, a.R[0].y + a.R[1].y);
+        const double2 Rd = make_double2(a.R[0].x - a.R[1].x, a.R[0].y - a.R[1].y);
+        const double2 Xs = make_double2(a.X[0].x + a.X[1].x, a.X[0].y + a.X[1].y);
+        const double2 Xd = make_double2(a.X[0].x - a.X[1].x, a.X[0].y - a.X[1].y);
+        const double2 Ys = make_double2(a.Y[0].x + a.Y[1].x, a.Y[0].y + a.Y[1].y);
+        const double2 Yd = make_double2(a.Y[0].x - a.Y[1].x, a.Y[0].y - a.Y[1].y);
+        // Q_N = -(P + iR), Q_S = -(P' - iR'), U_N = -(X - iY), U_S = -(X' + iY')
+        *row(0, rN) = Ts;
+        *row(1, rN) = make_double2(is2 * (-Ps.x + Rs.y), is2 * (-Ps.y - Rs.x));
+        *row(2, rN) = make_double2(is2 * (-Xs.x - Ys.y), is2 * (-Xs.y + Ys.x));
+        if (rS != rN) {
+            *row(0, rS) = Td;
+            *row(1, rS) = make_double2(is2 * (-Pd.x - Rd.y), is2 * (-Pd.y + Rd.x));
+            *row(2, rS) = make_double2(is2 * (-Xd.x + Yd.y), is2 * (-Xd.y - Yd.x));
+        }
     }
 }
 
-template <int U>
+template <int U, int P>
 __global__ void __launch_bounds__(kW)
 k_leg_synth_pol(const double2 *__restrict__ alm, long nalm, const double *__restrict__ Atab,
                 const double *__restrict__ pctab, const long *__restrict__ mofs,
@@ -136,8 +149,8 @@ k_leg_synth_pol(const double2 *__restrict__ alm, long nalm, const double *__rest
     const int g = blockIdx.x, mi = blockIdx.y, b = blockIdx.z;
     const int npass = (lmax - mi > mi) ? 2 : 1;
     for (int pass = 0; pass < npass; pass++)
-        pol_synth_one_m<U>(pass == 0 ? mi : lmax - mi, g, b, alm, nalm, Atab, pctab, mofs, lstart,
-                           seed, zp, phase, lmax, npair, nring, nm);
+        pol_synth_one_m<U, P>(pass == 0 ? mi : lmax - mi, g, b, alm, nalm, Atab, pctab, mofs, lstart,
+                              seed, zp, phase, lmax, npair, nring, nm);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -326,10 +339,17 @@ static int pol_ana_groups(const Plan &p) {
 int pol_ngroup(const Plan &p) { return pol_ana_groups(p); }
 
 int launch_leg_synth_pol(const Plan &p, const double2 *alm_scaled, double2 *phase, int nb) {
-    dim3 grid(pol_groups(p.npair), (p.lmax + 2) / 2, nb);
-    hipLaunchKernelGGL(k_leg_synth_pol<4>, grid, dim3(kW), 0, p.stream, alm_scaled, p.nalm, p.d_A,
-                       p.d_pc, p.d_mofs, p.d_lstart, p.d_seed, p.d_z, phase, p.lmax, p.npair,
-                       p.nring, p.nm);
+    // two ring pairs per lane where there are pairs for more than one wave: each value of l's
+    // coefficients and harmonics (wave-uniform loads) then serve twice the arithmetic
+    const int P = p.npair > kW ? 2 : 1;
+    dim3 grid((p.npair + kW * P - 1) / (kW * P), (p.lmax + 2) / 2, nb);
+#define MFWF_SYNPOL(PP)                                                                          \
+    hipLaunchKernelGGL((k_leg_synth_pol<4, PP>), grid, dim3(kW), 0, p.stream, alm_scaled, p.nalm,   \
+                       p.d_A, p.d_pc, p.d_mofs, p.d_lstart, p.d_seed, p.d_z, phase, p.lmax,         \
+                       p.npair, p.nring, p.nm)
+    if (P == 2) MFWF_SYNPOL(2);
+    else MFWF_SYNPOL(1);
+#undef MFWF_SYNPOL
     MFWF_HIP(hipGetLastError());
     return MFWF_OK;
 }
