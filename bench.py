@@ -31,6 +31,8 @@ METRIC = "WF solves/s & SHT-pair FLOP/s at nside=512; p50/p99 latency at 1e-5 re
 PEAK_FP64_VALU = 256 * 4 * 16 * 2 * 2.4e9     # 78.6 TFLOP/s: CUs x SIMDs x lanes x FMA x clock
 PEAK_FP32_MFMA = 157.3e12                      # dense FP32 matrix-core peak
 KERNELS = ["pixel_update", "fft_fwd", "leg_analysis", "harmonic", "leg_synth", "fft_inv"]
+# the stages of the batched T, Q, U form, in the order mfwf_time_kernels reports them
+POL_B_KERNELS = ["pixel_update", "fft_fwd", "gemm_analysis", "combine_filter", "gemm_synthesis", "fft_inv"]
 
 PEAK_HBM = 8.0e12                              # HBM3E bytes/s
 
@@ -231,8 +233,7 @@ def tqu(nside, lmax, K, steps, use_graph, batch):
         dB[b] = sig_t + torch.matmul(chol, g)[:, :, 0].T
     torch.cuda.synchronize()
     el32, lat32 = timed_solves(p32, dB, K, steps, 1, use_graph)
-    names = ["pixel_update", "fft_fwd", "gemm_analysis", "combine_filter", "gemm_synthesis",
-             "fft_inv"]
+    names = POL_B_KERNELS
     kt32 = dict(zip(names, p32.time_kernels(B, 3)))
     # three GEMMs per direction: lambda on 2 columns, F+ and F- on 4 columns per map
     gflops = 2.0 * work * 10 * B
@@ -302,17 +303,24 @@ def kernel_mode(args):
     mfwf_time_kernels (after two solve iterations), on the temperature workload at --nside /
     --lmax with --batch maps (FP32 form) or one map (FP64); with --copy also a 256 MiB device
     copy three times, the reference for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes;
-    with --solve-iters N also a timed solve of N iterations.  For hardware-counter runs."""
+    with --solve-iters N also a timed solve of N iterations; with --spin 2 the T, Q, U
+    workload instead (Wishart 3x3 noise, the temperature mask).  For hardware-counter runs."""
     import torch
     from paper_1210_4931_amd import mfwf
     from paper_1210_4931_amd import workloads as W
     maps = args.batch if args.kernels == "f32" else 1
-    wl = W.config2(0, args.nside, args.lmax)
     t = lambda x, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(x)).to("cuda", dt)  # noqa
-    plan = mfwf.Plan(args.nside, args.lmax, max_batch=maps, dtype=args.kernels)
-    plan.set_covariances(wl.cl, t(1.0 / wl.noise_var), t(wl.mask, torch.uint8))
-    sig = plan.sht_inv(t(wl.signal_alm[None], torch.complex128))
-    d = (sig + t(np.sqrt(wl.noise_var) * wl.noise_white)[None]).expand(maps, -1).contiguous()
+    plan = mfwf.Plan(args.nside, args.lmax, max_batch=maps, dtype=args.kernels, spin=args.spin)
+    if args.spin == 2:
+        w = W.config3(0, args.nside, args.lmax)
+        plan.set_covariances(w.cl4, t(w.ninv6), t(w.mask, torch.uint8))
+        sig = plan.sht_inv(t(w.signal_alm[None], torch.complex128)).cpu().numpy()[0]
+        d = t(w.data_from_signal_maps(sig)[None]).expand(maps, -1, -1).contiguous()
+    else:
+        wl = W.config2(0, args.nside, args.lmax)
+        plan.set_covariances(wl.cl, t(1.0 / wl.noise_var), t(wl.mask, torch.uint8))
+        sig = plan.sht_inv(t(wl.signal_alm[None], torch.complex128))
+        d = (sig + t(np.sqrt(wl.noise_var) * wl.noise_white)[None]).expand(maps, -1).contiguous()
     plan.solve(d, iters=2, use_graph=False)
     ms = plan.time_kernels(maps, args.reps)
     if args.copy:
@@ -321,8 +329,9 @@ def kernel_mode(args):
         for _ in range(3):
             b.copy_(a)
     torch.cuda.synchronize()
-    out = {"mode": "kernels", "form": args.kernels, "nside": args.nside, "lmax": args.lmax,
-           "maps": maps, "kernel_ms": dict(zip(KERNELS, ms))}
+    out = {"mode": "kernels", "form": args.kernels, "spin": args.spin, "nside": args.nside, "lmax": args.lmax,
+           "maps": maps, "kernel_ms": dict(zip(POL_B_KERNELS if args.spin == 2 and args.kernels == "f32"
+                                               else KERNELS, ms))}
     if args.solve_iters > 0:
         plan.solve(d, iters=args.solve_iters)  # warm: graph capture, caches
         torch.cuda.synchronize()
@@ -402,6 +411,8 @@ def main():
     ap.add_argument("--kernels", choices=["f64", "f32"], default=None,
                     help="profiling mode: run each kernel of one iteration --reps times")
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--spin", type=int, choices=[0, 2], default=0,
+                    help="with --kernels: 2 for the T, Q, U workload")
     ap.add_argument("--copy", action="store_true")
     ap.add_argument("--solve-iters", type=int, default=0)
     ap.add_argument("--tqu-cooled", action="store_true",
