@@ -132,6 +132,23 @@ def test_pol_f32_chained_iterations_equal_the_map_order(mf, nside, lmax):
     assert rel(m_ch.cpu().numpy()[4], ref_map) < TOL
 
 
+def test_pol_f32_chained_equals_map_order_at_nside_512(mf):
+    """At nside 512 the polar rings of more than 1024 pixels take chirp-z transforms of 4096
+    points in 512-thread workgroups, the other rings 256-thread ones: a chained T, Q, U solve
+    through both ring-step shapes equals the map-order solve bit for bit."""
+    nside, lmax = 512, 64
+    w = W.config3(6, nside, lmax, ndisc=10, band_z=0.15, nu=10)
+    plan = mf.Plan(nside, lmax, max_batch=2, spin=2, dtype="f32")
+    plan.set_covariances(w.cl4, dev(w.ninv6), dev(w.mask, torch.uint8))
+    rng = np.random.default_rng(7)
+    ds = 30.0 * rng.standard_normal((2, 3, w.npix))  # any data: the two orders must agree
+    lam, its = [5.0, 1.0], [2, 3]
+    a_ch, m_ch, _ = plan.solve(dev(ds), lam=lam, iters=its)
+    a_map, m_map, _ = plan.solve(dev(ds), lam=lam, iters=its, chained=False)
+    assert torch.equal(a_ch, a_map) and torch.equal(m_ch, m_map)
+    assert torch.isfinite(a_ch).all() and float(a_ch.abs().max()) > 0.0
+
+
 def test_pol_f32_schedule_and_diagnostics(mf):
     nside, lmax = 16, 40
     plan, w, d, M6 = _problem(mf, nside, lmax, max_batch=2, seed=2)
