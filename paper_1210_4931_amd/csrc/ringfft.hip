@@ -912,7 +912,7 @@ size_t fft_class_lds(const Plan &p, int c) {
     p.d_pfft, p.d_plist + p.fft_class_off[c], p.d_twlo, p.d_twhi, p.fft_ntwhi, p.fftmax,        \
         p.d_chirp, p.d_bhat, p.npix, p.nring, rs, p.lmax, p.fft_class_len[c]
 
-// split rings (class 2; FP64 rows only: plans of the FP32 form never have them)
+// split rings (class 2): FP64 rows, FP32 rows, or the matrix-core columns of the FP32 form
 static constexpr int kSplitSubTPB = 512, kSplitTPB = 1024;
 
 static int split_check(const Plan &p, int nb) {
