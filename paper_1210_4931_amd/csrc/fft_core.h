@@ -191,9 +191,10 @@ __device__ __forceinline__ void fft_stockham(double2 *buf, int n, const Twiddles
 
 __device__ __forceinline__ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
 
+// nout: outputs that are read afterwards; the last pass (Ns R = N) stores only those
 template <int TPB, int N, int R, int Ns, int PRE>
 __device__ __forceinline__ void stockham_pass_c(double2 *buf, const Twiddles &tw, int lgmax,
-                                                const double2 *__restrict__ pre, int nv) {
+                                                const double2 *__restrict__ pre, int nv, int nout) {
     constexpr int NBF = N / R;
     constexpr int MAXB = (NBF + TPB - 1) / TPB;
     constexpr bool ALL = (NBF % TPB == 0);
@@ -202,7 +203,15 @@ __device__ __forceinline__ void stockham_pass_c(double2 *buf, const Twiddles &tw
     for (int b = 0; b < MAXB; b++) {
         const int j = (threadIdx.x & (TPB - 1)) + b * TPB;
         if (ALL || j < NBF) {
-            if constexpr (NBF % 8 == 0) {
+            if constexpr (PRE == kPreChirp) {
+                // the chirped sequence, zero from nv on: only its first nv elements are read
+#pragma unroll
+                for (int r = 0; r < R; r++) {
+                    const int i = j + r * NBF;
+                    v[b][r] = make_double2(0.0, 0.0);
+                    if (i < nv) v[b][r] = cmul(buf[lds_ix(i)], pre[i]);
+                }
+            } else if constexpr (NBF % 8 == 0) {
                 const int jb = lds_ix(j);
 #pragma unroll
                 for (int r = 0; r < R; r++) v[b][r] = buf[jb + r * (NBF / 8) * 9];
@@ -210,13 +219,7 @@ __device__ __forceinline__ void stockham_pass_c(double2 *buf, const Twiddles &tw
 #pragma unroll
                 for (int r = 0; r < R; r++) v[b][r] = buf[lds_ix(j + r * NBF)];
             }
-            if constexpr (PRE == kPreChirp) {
-#pragma unroll
-                for (int r = 0; r < R; r++) {
-                    const int i = j + r * NBF;
-                    v[b][r] = (i < nv) ? cmul(v[b][r], pre[min(i, nv - 1)]) : make_double2(0.0, 0.0);
-                }
-            } else if constexpr (PRE == kPreKernelConj) {
+            if constexpr (PRE == kPreKernelConj) {
 #pragma unroll
                 for (int r = 0; r < R; r++) v[b][r] = cconj(cmul(v[b][r], pre[j + r * NBF]));
             }
@@ -241,7 +244,8 @@ __device__ __forceinline__ void stockham_pass_c(double2 *buf, const Twiddles &tw
             if constexpr (Ns % 8 == 0) {
                 const int bb = lds_ix(base);
 #pragma unroll
-                for (int r = 0; r < R; r++) buf[bb + r * (Ns / 8) * 9] = v[b][r];
+                for (int r = 0; r < R; r++)
+                    if (Ns * R < N || base + r * Ns < nout) buf[bb + r * (Ns / 8) * 9] = v[b][r];
             } else if constexpr (Ns == 1 && R == 8) {
 #pragma unroll
                 for (int r = 0; r < R; r++) buf[9 * j + r] = v[b][r];  // lds_ix(8 j + r)
@@ -254,15 +258,16 @@ __device__ __forceinline__ void stockham_pass_c(double2 *buf, const Twiddles &tw
     __syncthreads();
 }
 
-// The passes of fft_stockham for length N: radix 8 while at least 8 remain, then 4 or 2.
+// The passes of fft_stockham for length N: radix 8 while at least 8 remain, then 4 or 2;
+// outputs from nout on are not stored (where nothing reads them).
 template <int TPB, int N, int Ns, int PRE>
 __device__ __forceinline__ void fft_passes_c(double2 *buf, const Twiddles &tw, int lgmax,
-                                             const double2 *__restrict__ pre, int nv) {
+                                             const double2 *__restrict__ pre, int nv, int nout = N) {
     if constexpr (Ns < N) {
         constexpr int left = N / Ns;
         constexpr int R = left >= 8 ? 8 : left;
-        stockham_pass_c<TPB, N, R, Ns, (Ns == 1 ? PRE : kPreNone)>(buf, tw, lgmax, pre, nv);
-        fft_passes_c<TPB, N, Ns * R, PRE>(buf, tw, lgmax, pre, nv);
+        stockham_pass_c<TPB, N, R, Ns, (Ns == 1 ? PRE : kPreNone)>(buf, tw, lgmax, pre, nv, nout);
+        fft_passes_c<TPB, N, Ns * R, PRE>(buf, tw, lgmax, pre, nv, nout);
     }
 }
 
@@ -280,8 +285,9 @@ __device__ __forceinline__ bool ring_dft_fixed(double2 *buf, const PairFFT &pf, 
             if (!pf.bluestein) {
                 fft_passes_c<TPB, N, 1, kPreNone>(buf, tw, lgmax, nullptr, 0);
             } else {
+                // only the first n bins of the convolution are read (dft_bin, k < n)
                 fft_passes_c<TPB, N, 1, kPreChirp>(buf, tw, lgmax, chirp + pf.chirp_off, pf.nphi);
-                fft_passes_c<TPB, N, 1, kPreKernelConj>(buf, tw, lgmax, bhat + pf.bhat_off, N);
+                fft_passes_c<TPB, N, 1, kPreKernelConj>(buf, tw, lgmax, bhat + pf.bhat_off, N, pf.nphi);
             }
             return true;
         }

@@ -269,9 +269,11 @@ __device__ __forceinline__ void fold_bins(double2 *buf, Seq FN, Seq FS, const Pa
         const double2 zero = make_double2(0.0, 0.0);
 #pragma unroll
         for (int u0 = 0; u0 < EPT; u0 += CH) {
+            if (u0 * TPB >= n) break;  // uniform: no bins from here on
             InT aN[CH], aS[CH], cN[CH], cS[CH];
 #pragma unroll
             for (int v = 0; v < CH; v++) {
+                if ((u0 + v) * TPB >= n) break;  // uniform
                 const int kc = min(tid + (u0 + v) * TPB, n - 1);
                 const int mpos = min(kc, lmax), mneg = min(n - kc, lmax);
                 aN[v] = FN[mpos];
@@ -607,6 +609,7 @@ __device__ __forceinline__ void fold_cols_group(double2 *buf, int area, const fl
     float2 fN[MU][G], fS[MU][G];
 #pragma unroll
     for (int u = 0; u < MU; u++) {
+        if (u * G * TPB > lmax) break;  // uniform: no thread has a coefficient from here on
         const int m = min((int)threadIdx.x + u * G * TPB, lmax);
         load_g<G>(FN + (long)m * cs, fN[u]);
         load_g<G>(FS + (long)m * cs, fS[u]);
@@ -743,6 +746,7 @@ k_fft_inv_fwd(float2 *__restrict__ data, int C2, int nmap, int ngrp, int npl, do
     double mN[EPT], mS[EPT], rN[EPT], rS[EPT];
 #pragma unroll
     for (int u = 0; u < EPT; u++) {
+        if (u * TPB >= n) break;  // uniform: the ring's pixels end here
         const int jj = min(tid + u * TPB, n - 1);
         mN[u] = live ? mp[pf.startN + jj] : 0.0;
         mS[u] = live ? mp[pf.startS + jj] : 0.0;
@@ -755,6 +759,7 @@ k_fft_inv_fwd(float2 *__restrict__ data, int C2, int nmap, int ngrp, int npl, do
     double2 v[EPT];
 #pragma unroll
     for (int u = 0; u < EPT; u++) {
+        if (u * TPB >= n) break;
         const int jj = tid + u * TPB;
         const double2 xs = cconj(dft_bin(buf, pf, chirp, min(jj, n - 1)));  // (s_N, s_S) at jj
         if (smap && live && jj < n) {
