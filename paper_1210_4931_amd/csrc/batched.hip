@@ -320,7 +320,9 @@ k_gemm_analysis(const float *__restrict__ lam, LamGen gen, const long *__restric
             for (int r = 0; r < 16; r++) acc[a][b][r] = 0.f;
     const float *lrow = GEN ? nullptr : lam + loff[m] + kAnaRows * t;
     const int wcol = 32 * NCT * ch;  // first column of this wave within the tile
-    const bool wave_on = (CT * cg + wcol) < ncols;
+    // a wave whose columns are past the batch or whose rows are all past lmax (the padding
+    // of a tile that ends beyond lmax) does no products
+    const bool wave_on = (CT * cg + wcol) < ncols && m + kAnaRows * t + 64 * lh <= lmax;
     floatx4 rl[NL], rn[NX], rs[NX];
     // GEN: thread (pair gpp = tid / 8, rows 16 (tid % 8) ..) of a chunk, threads 0..255; its
     // segment state, start index, seeds and z, loaded with the chunk's other operands
