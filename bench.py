@@ -38,18 +38,21 @@ PEAK_HBM = 8.0e12                              # HBM3E bytes/s
 
 # HBM bytes per iteration of two kernels of the batched FP32 form (nside 512, lmax 1024, 64
 # maps) from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by the factors a 256 MiB copy gives:
-# profiles/ring_step_and_gemms_nside512_lmax1024_b64_hbm_traffic.md.  Valid only for the
-# kernel source they were taken on, identified by the SHA-256 of the source file.
+# profiles/ring_step_and_gemms_nside512_lmax1024_b64_hbm_traffic.md.  The ring step's bytes
+# depend on how many maps share a workgroup of each transform class (the tuned "g0", "g1":
+# more maps per workgroup write larger column pieces), so they are kept per (g0, g1).  Valid only
+# for the kernel source they were taken on, identified by the SHA-256 of the source file.
 TRAFFIC = {
-    "ring_step": {"bytes": 4.2555e9, "source": "ringfft.hip",
-                  "sha256": "5e95b1de4421d59762b544ddfc2aa1843730d9839ae8435b75a4fa209cbdcf65"},
-    "gemm_analysis": {"bytes": 5.2346e9, "source": "batched.hip",
-                      "sha256": "8bd2e3caae67d6cf641199c6191a4a44c025c540f296972b6414b9be485eebf9"},
+    "ring_step": {"bytes": {(1, 1): 4.3517e9, (2, 1): 3.9599e9}, "source": "ringfft.hip",
+                  "sha256": "c0e6088f71f3d804ded6031de4af9cd5e394c4d13576ad9ca633d9eb413239f0"},
+    # the analysis GEMM's, per (column tile choice "cta", lambda generated "lamgen")
+    "gemm_analysis": {"bytes": {(1, 0): 5.3676e9}, "source": "batched.hip",
+                      "sha256": "cf741d30ae83034de945d059f9844b1e0fee8f93c8168cea03ce9daf44a0597d"},
 }
 # What the shader counters say limits the ring step (VALU issue and LDS bank conflicts, not
 # HBM): profiles/batched_nside512_lmax1024_b64_shader_counters.md, same kernel sources.
-RING_COUNTERS = {"valu_busy": [0.44, 0.49], "lds_bank_conflict_share": [0.26, 0.27],
-                 "mfma_busy": 0.0, "hbm_traffic_over_algorithmic": 1.12,
+RING_COUNTERS = {"valu_busy": [0.43, 0.53], "lds_bank_conflict_share": [0.25, 0.27],
+                 "mfma_busy": 0.0, "hbm_traffic_over_algorithmic": {"g0=1,g1=1": 1.15, "g0=2,g1=1": 1.05},
                  "profile": "profiles/batched_nside512_lmax1024_b64_shader_counters.md"}
 
 
@@ -61,14 +64,17 @@ def note(msg):
     print("[bench %6.1f s] %s" % (time.perf_counter() - _T0, msg), file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, shape=None):
+    """Counter-measured bytes per launch of `kernel` (per iteration for the ring step, for the
+    plan's tuned (g0, g1)), or None where the source changed since or no figure was taken."""
     import hashlib
     t = TRAFFIC[kernel]
-    if t["bytes"] is None:
+    b = t["bytes"].get(shape) if isinstance(t["bytes"], dict) else t["bytes"]
+    if b is None:
         return None
     src = os.path.join(ROOT, "paper_1210_4931_amd", "csrc", t["source"])
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    return t["bytes"] if h == t["sha256"] else None
+    return b if h == t["sha256"] else None
 
 
 def _cpu_model():
@@ -491,6 +497,8 @@ def main():
     del a32, m32
     del p64
     kt32 = dict(zip(KERNELS, p32.time_kernels(B, 20)))
+    tun = p32.tuning()
+    ring_shape = (tun["g0"], tun["g1"])  # maps per workgroup of the ring step's two classes
     gemm_flops = 2.0 * work * 2 * B   # one FMA per (l, m, ring pair) and column, 2 columns a map
     dom32 = max(("leg_analysis", "leg_synth"), key=lambda k: kt32[k])
     pair32 = kt32["fft_fwd"] + kt32["leg_analysis"] + kt32["leg_synth"] + kt32["fft_inv"]
@@ -538,13 +546,15 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "ring_step (k_fft_inv_fwd, both length classes)",
                      "achieved": ring_bw / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                      "frac": ring_bw / PEAK_HBM, "algorithmic_bytes": ring_bytes,
-                     "ms": kt32["fft_fwd"], "traffic": measured_traffic("ring_step"),
-                     "counters": RING_COUNTERS if measured_traffic("ring_step") else None},
+                     "ms": kt32["fft_fwd"], "traffic": measured_traffic("ring_step", ring_shape),
+                     "ring_step_maps_per_workgroup": list(ring_shape),
+                     "counters": RING_COUNTERS if measured_traffic("ring_step", ring_shape) else None},
         "roofline_gemm": {"bound": "mfma", "kernel": "gemm_" + dom32.split("_")[1],
                           "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
                           "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
                           "ms": kt32[dom32],
-                          "traffic": measured_traffic("gemm_analysis") if dom32 == "leg_analysis" else None},
+                          "traffic": measured_traffic("gemm_analysis", (tun["cta"], tun["lamgen"]))
+                          if dom32 == "leg_analysis" else None},
         "fp64_single": fp64,
     }
     note("accuracy and kernel times done")
