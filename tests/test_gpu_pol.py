@@ -37,10 +37,9 @@ def _rel_teb(a, ref, lmax):
     return rel(a * w, ref * w)
 
 
-# nside 40 and 48 (80 and 96 ring pairs): the Legendre kernels carry two pairs per lane, and
-# the last lane group is partly empty
+# nside 64 (128 ring pairs): the Legendre kernels carry two pairs per lane
 @pytest.mark.parametrize("nside,lmax", [(2, 6), (4, 12), (8, 20), (8, 32), (16, 40), (32, 64),
-                                        (40, 100), (48, 96)])
+                                        (64, 128), (64, 201)])
 def test_pol_sht_parity(mf, nside, lmax):
     rng = np.random.default_rng(nside * 1000 + lmax)
     a = _teb(rng, lmax, 2)
