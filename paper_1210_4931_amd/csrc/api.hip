@@ -458,10 +458,18 @@ static int autotune(Plan &p, const std::string &devname) {
                 return launch_gemm_synthesis(p, B);
             }));
         }
-        if (2 * B > 64) {  // more than 64 active columns: both column tiles apply
+        // the widest GEMM launches: 2 columns a map (temperature), 4 (the spin-2 F+- tables)
+        const int w = p.spin == 2 ? 4 : 2;
+        if (w * B > 64) {  // more than 64 active columns: every column tile applies
             const std::vector<int> cv = {1, 2}, cva = {1, 2, 3};
-            MFWF_TRY(tune_knob(p, kKnobCtA, cva, [&] { return launch_gemm_analysis(p, B, p.d_a32, nullptr, 1.0, 1.0); }));
-            MFWF_TRY(tune_knob(p, kKnobCtS, cv, [&] { return launch_gemm_synthesis(p, B); }));
+            MFWF_TRY(tune_knob(p, kKnobCtA, cva, [&] {
+                return p.spin == 2 ? launch_gemm_analysis_raw(p, B, 4, p.d_fp, p.d_ph32p, p.d_ap32, 0)
+                                   : launch_gemm_analysis(p, B, p.d_a32, nullptr, 1.0, 1.0);
+            }));
+            MFWF_TRY(tune_knob(p, kKnobCtS, cv, [&] {
+                return p.spin == 2 ? launch_gemm_synthesis_on(p, B, 4, p.d_fp, p.d_seb32, p.d_ph32p, 0, 0)
+                                   : launch_gemm_synthesis(p, B);
+            }));
         }
     }
     get_knobs(p, k);
