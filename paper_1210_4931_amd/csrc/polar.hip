@@ -328,7 +328,6 @@ k_leg_analysis_pol(const double2 *__restrict__ phase, int nring, int nm,
                               lstart, seed, zp, apart, nalm, nb_total, lmax, npair, red);
 }
 
-static int pol_groups(int npair) { return (npair + kW - 1) / kW; }
 // ring pairs per lane of the analysis: two where there are pairs for more than one wave
 // (each lane sums its pairs before the sum over lanes, whose cost is per value of l)
 static int pol_ana_pairs(const Plan &p) { return p.npair > kW ? 2 : 1; }
