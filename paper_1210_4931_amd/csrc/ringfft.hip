@@ -165,7 +165,7 @@ k_fft_fwd(const double *__restrict__ maps, const double *__restrict__ rho,
             buf[lds_ix(j)] = make_double2(pix(xN[u], mN[u], rN[u]), equator ? 0.0 : pix(xS[u], mS[u], rS[u]));
     }
     __syncthreads();
-    ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
+    ring_dft_c<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
     store_rows<TPB>(buf, pf, tw, fftmax, chirp, lmax,
                     RingSeq<OutT, false>{phase + ((long)b * nring + p) * nm, 1},
                     RingSeq<OutT, false>{phase + ((long)b * nring + (nring - 1 - p)) * nm, 1});
@@ -369,7 +369,7 @@ k_fft_inv(const InT *__restrict__ phase, double *__restrict__ maps,
     const RingSeq<const InT, false> FS{phase + ((long)b * nring + (nring - 1 - p)) * nm, 1};
     fold_bins<TPB, EPT>(buf, FN, FS, pf, tw, fftmax, lmax);
     __syncthreads();
-    ring_dft<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
+    ring_dft_c<TPB, EPT>(buf, pf, tw, fftmax, chirp, bhat);
     double *sNmap = maps + (long)b * npix + pf.startN;
     double *sSmap = maps + (long)b * npix + pf.startS;
     for (int j = threadIdx.x; j < n; j += TPB) {
