@@ -337,7 +337,8 @@ int mfwf_solve_bounded(mfwf_plan plan, const double *data, int nmaps, double *s_
  * nmaps maps and writes the mean duration in milliseconds of each kernel to ms_out:
  * [0] pixel update, [1] forward ring FFT, [2] Legendre analysis, [3] harmonic update,
  * [4] Legendre synthesis, [5] inverse ring FFT.  A stage that runs inside another kernel
- * reads 0: in the batched FP32 temperature form the pixel update runs in [1] and the
+ * reads 0: in the FP64 temperature path the pixel update runs in [1]; in the batched FP32
+ * temperature form the pixel update runs in [1] and the
  * harmonic update in [2], and [1] is the whole ring step of a chained iteration (layout
  * transposes, the previous synthesis back to pixels, pixel update, forward transforms), so
  * [5] is 0 as well.  Requires mfwf_set_covariances.

@@ -964,9 +964,8 @@ static int iteration(Plan &p, const double *rho, int nb, double lam, bool keep_p
     if (p.dtype == MFWF_F32 && p.spin == 2) return iteration_pol_b(p, rho, nb, lam, keep_prev);
     if (p.dtype == MFWF_F32) return iteration_b(p, rho, nb, lam, keep_prev);
     if (p.spin == 2) return iteration_pol(p, rho, nb, lam, keep_prev);
-    MFWF_TRY(launch_pixel_update(rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, lam, p.tau, p.stream,
-                                 p.mstride, p.d_tau));
-    MFWF_TRY(launch_fft_fwd(p, p.d_t, p.d_phase, nb));
+    // the pixel update (Eq. 3) inside the forward ring transforms: t never goes to memory
+    MFWF_TRY(launch_fft_fwd_pix(p, p.d_smap, rho, lam, p.d_phase, nb));
     MFWF_TRY(launch_leg_analysis(p, p.d_phase, p.d_apart, nb));
     MFWF_TRY(launch_harmonic(p, p.d_apart, p.ngroup, p.omega, lam * p.omega * p.tau, kHarmWiener,
                              p.d_salm, p.d_sp, keep_prev ? p.d_salm_prev : nullptr, nb,
@@ -2129,8 +2128,8 @@ int mfwf_time_kernels(mfwf_plan plan, int nmaps, int reps, double *ms_out) {
             continue;
         }
         switch (k) {
-            case 0: f = [&] { return launch_pixel_update(p.d_rho, p.d_M, p.d_smap, p.d_t, p.npix, nb, 1.0, p.tau, p.stream, p.mstride, p.d_tau); }; break;
-            case 1: f = [&] { return launch_fft_fwd(p, p.d_t, p.d_phase, nb); }; break;
+            case 0: ms_out[k] = 0.0; continue;  // pixel update runs inside the forward transforms
+            case 1: f = [&] { return launch_fft_fwd_pix(p, p.d_smap, p.d_rho, 1.0, p.d_phase, nb); }; break;
             case 2: f = [&] { return launch_leg_analysis(p, p.d_phase, p.d_apart, nb); }; break;
             case 3: f = [&] { return launch_harmonic(p, p.d_apart, p.ngroup, p.omega, p.omega * p.tau, kHarmWiener, p.d_salm, p.d_sp, nullptr, nb, p.omega); }; break;
             case 4: f = [&] { return launch_leg_synth(p, p.d_sp, p.d_phase, nb); }; break;

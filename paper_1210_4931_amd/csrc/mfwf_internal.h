@@ -172,9 +172,6 @@ int launch_rho_from_data(const double *d, const double *M, double *rho, long npi
 // out[0] = number of non-finite entries of x[0..n) (partial: nblocks doubles)
 int launch_count_nonfinite(const double *x, long n, double *partial, int nblocks, double *out,
                            hipStream_t s);
-int launch_pixel_update(const double *rho, const double *M, const double *smap, double *t,
-                        long npix, int nb, double lam, double tau, hipStream_t s,
-                        long mstride = 0, const double *tau_b = nullptr);
 int launch_chi2_pix(const double *rho, const double *M, const double *smap, long npix, int nb,
                     double lam, double tau, double *partial, int nblocks, double *diag,
                     hipStream_t s);
@@ -183,6 +180,10 @@ int launch_fluct_combine(const double *g1, const double *M, const double *ysh, d
 
 // ringfft.hip
 int launch_fft_fwd(const Plan &p, const double *maps, double2 *phase, int nb);
+// the forward transforms of the messenger field t of Eq. (3), formed from rho, M and s = maps
+// on the fly (FP64 rows)
+int launch_fft_fwd_pix(const Plan &p, const double *maps, const double *rho, double lam,
+                       double2 *phase, int nb);
 int launch_fft_inv(const Plan &p, const double2 *phase, double *maps, int nb);
 // FP32 rows [map][ring][m]; with rho the input is the messenger field of Eq. (3) built from
 // rho, M and s = maps on the fly

@@ -163,34 +163,6 @@ int launch_rho_from_data(const double *d, const double *M, double *rho, long npi
     return MFWF_OK;
 }
 
-// Eq. (3) per pixel, multiplied through by N (Nbar^-1 never formed):
-//   t = [lam tau rho + (1 - tau M) s] / [1 + (lam - 1) tau M]
-// M is shared by the maps (mstride = 0) or one row per map (mstride = npix, with tau_b[b]
-// per map: independent requests batched in serving slots).
-__global__ void k_pixel_update(const double *__restrict__ rho, const double *__restrict__ M,
-                               const double *__restrict__ smap, double *__restrict__ t,
-                               long npix, long n, double lam, double tau, long mstride,
-                               const double *__restrict__ tau_b) {
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
-         i += (long)gridDim.x * blockDim.x) {
-        const long b = i / npix, q = i - b * npix;
-        const double tq = tau_b ? tau_b[b] : tau;
-        const double m = M[b * mstride + q];
-        const double num = lam * tq * rho[i] + (1.0 - tq * m) * smap[i];
-        t[i] = (lam == 1.0) ? num : num / (1.0 + (lam - 1.0) * tq * m);
-    }
-}
-
-int launch_pixel_update(const double *rho, const double *M, const double *smap, double *t,
-                        long npix, int nb, double lam, double tau, hipStream_t s, long mstride,
-                        const double *tau_b) {
-    long n = npix * nb;
-    hipLaunchKernelGGL(k_pixel_update, dim3(grid_for(n)), dim3(kThreads), 0, s, rho, M, smap,
-                       t, npix, n, lam, tau, mstride, tau_b);
-    MFWF_HIP(hipGetLastError());
-    return MFWF_OK;
-}
-
 // chi^2 pixel term of Eq. (6): sum over observed pixels of (d - s)^2 / (N + (lam - 1) tau)
 // with d = rho / M, i.e. (rho - M s)^2 / (M (1 + (lam - 1) tau M)).
 // grid (nblocks, nb): partial[b][block]

@@ -1029,6 +1029,11 @@ int launch_fft_fwd(const Plan &p, const double *maps, double2 *phase, int nb) {
     return fwd_classes<double2, false>(p, maps, nullptr, 1.0, phase, nb);
 }
 
+int launch_fft_fwd_pix(const Plan &p, const double *maps, const double *rho, double lam,
+                       double2 *phase, int nb) {
+    return fwd_classes<double2, true>(p, maps, rho, lam, phase, nb);
+}
+
 int launch_fft_fwd_f32(const Plan &p, const double *maps, const double *rho, double lam,
                        float2 *phase, int nb) {
     if (rho) return fwd_classes<float2, true>(p, maps, rho, lam, phase, nb);
@@ -1151,6 +1156,7 @@ int fft_set_lds_limit(size_t bytes) {
     if (bytes <= current) return MFWF_OK;
     current = bytes;
     MFWF_TRY((fwd_lds<double2, false>((int)bytes)));
+    MFWF_TRY((fwd_lds<double2, true>((int)bytes)));
     MFWF_TRY((fwd_lds<float2, false>((int)bytes)));
     MFWF_TRY((fwd_lds<float2, true>((int)bytes)));
     MFWF_TRY(inv_lds<double2>((int)bytes));

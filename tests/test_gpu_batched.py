@@ -178,7 +178,8 @@ def test_f32_chained_iterations_chunks_checks_and_stages(mf):
 
 def test_time_kernels_stages_and_state(mf):
     """mfwf_time_kernels: one duration per stage (in the batched temperature form the
-    inverse transforms run inside the chained ring step, [1], so [5] reads 0), and a solve
+    inverse transforms run inside the chained ring step, [1], so [5] reads 0; in the FP64
+    path the pixel update runs inside the forward transforms, so [0] reads 0), and a solve
     after it gives the result it gave before (the timing runs leave no state behind)."""
     nside, lmax = 16, 40
     plan, wl, d, M = _setup(mf, nside, lmax, max_batch=4)
@@ -192,7 +193,8 @@ def test_time_kernels_stages_and_state(mf):
     p64 = mf.Plan(nside, lmax)
     p64.set_covariances(wl.cl, dev(1.0 / wl.noise_var), dev(wl.mask, torch.uint8))
     b1 = p64.solve(ds[:1], iters=12)[0]
-    assert all(v > 0.0 for v in p64.time_kernels(1, 3))
+    ms64 = p64.time_kernels(1, 3)  # the FP64 pixel update runs inside the forward transforms
+    assert ms64[0] == 0.0 and all(v > 0.0 for v in ms64[1:])
     assert torch.equal(p64.solve(ds[:1], iters=12)[0], b1)
 
 
