@@ -240,6 +240,11 @@ static void free_plan(Plan &p) {
                     p.d_fftsplit};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
+    if (p.side_fork) (void)hipEventDestroy(p.side_fork);
+    if (p.side_join) (void)hipEventDestroy(p.side_join);
+    if (p.side) (void)hipStreamDestroy(p.side);
+    p.side = nullptr;
+    p.side_fork = p.side_join = nullptr;
 }
 
 static int device_name(std::string &name) {
@@ -830,6 +835,13 @@ static int create(int nside, int lmax, int spin, int dtype, int max_batch, void 
     MFWF_TRY(dalloc(&p.d_twhi, twhi.size(), "twiddles hi"));
     MFWF_TRY(dalloc(&p.d_chirp, std::max<size_t>(1, chirp.size()), "chirp"));
     MFWF_TRY(dalloc(&p.d_bhat, std::max<size_t>(1, bhat.size()), "chirp kernel"));
+    if (f32 && p.fft_class_count[0] > 0 && p.fft_class_count[1] > 0) {
+        // the two in-LDS ring classes of the chained ring step run side by side (default
+        // priority, non-blocking: it orders only against the fork and join events)
+        MFWF_HIP(hipStreamCreateWithFlags(&p.side, hipStreamNonBlocking));
+        MFWF_HIP(hipEventCreateWithFlags(&p.side_fork, hipEventDisableTiming));
+        MFWF_HIP(hipEventCreateWithFlags(&p.side_join, hipEventDisableTiming));
+    }
     if (p.fft_class_count[2] > 0) {  // split rings: sub-spectra parked between the passes
         p.fftsplit_rows = (int)(nc * B);
         p.fftsplit_stride = 2L * nsplit_max;

@@ -81,6 +81,10 @@ struct Plan {
     int *d_plist = nullptr;      // [npair] pair indices grouped by FFT class
     // classes: 0 short transforms, 1 the longest in-LDS ones, 2 split rings (FP64 rows only)
     int fft_class_off[3] = {0, 0, 0}, fft_class_count[3] = {0, 0, 0}, fft_class_len[3] = {1, 1, 1};
+    // FP32 ring step: the longest ring class runs on a side stream forked from `stream` (and
+    // joined back) while the short class runs on `stream`; the classes touch disjoint rings
+    hipStream_t side = nullptr;
+    hipEvent_t side_fork = nullptr, side_join = nullptr;
     double2 *d_fftsplit = nullptr;  // split rings: [rows][class-2 pairs][fftsplit_stride]
     long fftsplit_stride = 0;       // 2 x the longest split ring
     int fftsplit_rows = 0;          // rows (maps x components) one launch may carry
@@ -192,6 +196,10 @@ int launch_fft_fwd_f32(const Plan &p, const double *maps, const double *rho, dou
 int launch_fft_inv_f32(const Plan &p, const float2 *phase, double *maps, int nb);
 // synthesis columns d_ph32 -> maps s (to smap if not null) -> t of Eq. (3) -> the columns of
 // its forward transform, in place (one iteration's ring steps without the map in memory)
+// Fork the plan's side stream from its stream before the two in-LDS ring classes of the
+// chained FP32 ring step, and join it back after them (no-ops without a side stream).
+int ring_fork(const Plan &p);
+int ring_join(const Plan &p);
 int launch_fft_inv_fwd_cols(const Plan &p, const double *rho, double lam, double *smap, int nb);
 // T, Q, U batched form: one iteration's ring steps on the columns d_ph32 / d_ph32p from the
 // synthesis columns d_ph32 / d_ph32p (chained iterations), where fft_pol_chain_ok

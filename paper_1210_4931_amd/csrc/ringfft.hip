@@ -1048,6 +1048,20 @@ int launch_fft_inv_f32(const Plan &p, const float2 *phase, double *maps, int nb)
     return inv_classes<float2>(p, phase, maps, nb);
 }
 
+int ring_fork(const Plan &p) {
+    if (!p.side) return MFWF_OK;
+    MFWF_HIP(hipEventRecord(p.side_fork, p.stream));
+    MFWF_HIP(hipStreamWaitEvent(p.side, p.side_fork, 0));
+    return MFWF_OK;
+}
+
+int ring_join(const Plan &p) {
+    if (!p.side) return MFWF_OK;
+    MFWF_HIP(hipEventRecord(p.side_join, p.side));
+    MFWF_HIP(hipStreamWaitEvent(p.stream, p.side_join, 0));
+    return MFWF_OK;
+}
+
 int launch_fft_inv_fwd_cols(const Plan &p, const double *rho, double lam, double *smap, int nb) {
     if (p.fft_class_count[2] > 0) {
         // split rings (nside 2048): the synthesis columns folded and transformed back to the
@@ -1058,9 +1072,11 @@ int launch_fft_inv_fwd_cols(const Plan &p, const double *rho, double lam, double
         MFWF_TRY((inv_split<float2, true>(p, data, p.nm32, maps, nb)));
         MFWF_TRY((fwd_split<float2, true, true>(p, maps, rho, lam, data, p.nm32, nb)));
     }
+    MFWF_TRY(ring_fork(p));  // class 1 on the side stream, class 0 on the plan's stream
     for (int c = 1; c >= 0; c--) {
         const int cnt = p.fft_class_count[c];
         if (cnt == 0) continue;
+        const hipStream_t st = (c == 1 && p.side) ? p.side : p.stream;
         int ept;
         const int tpb = fft_class_shape(p, c, ept);
         const int g = fft_cols_group(p, c, nb);
@@ -1070,7 +1086,7 @@ int launch_fft_inv_fwd_cols(const Plan &p, const double *rho, double lam, double
         const int rs = p.nm32;  // unused by the kernel (no rows)
         float2 *data = reinterpret_cast<float2 *>(p.d_ph32);
 #define MFWF_INVFWD(T, G)                                                                           \
-    hipLaunchKernelGGL((k_fft_inv_fwd<T, 8, G>), grid, dim3(T * G), lds, p.stream, data, p.C2, nb,  \
+    hipLaunchKernelGGL((k_fft_inv_fwd<T, 8, G>), grid, dim3(T * G), lds, st, data, p.C2, nb,        \
                        ngrp, cnt, smap, rho, p.d_M, lam, p.tau, p.mstride, p.d_tau, MFWF_FFT_ARGS(c, rs))
         if (tpb == 256 && g == 4) MFWF_INVFWD(256, 4);
         else if (tpb == 256 && g == 2) MFWF_INVFWD(256, 2);
@@ -1081,7 +1097,7 @@ int launch_fft_inv_fwd_cols(const Plan &p, const double *rho, double lam, double
 #undef MFWF_INVFWD
         MFWF_HIP(hipGetLastError());
     }
-    return MFWF_OK;
+    return ring_join(p);
 }
 
 
@@ -1099,22 +1115,24 @@ bool fft_pol_chain_ok(const Plan &p) {
 
 int launch_fft_inv_fwd_pol_cols(const Plan &p, const double *rho, double lam, int nb) {
     if (!fft_pol_chain_ok(p)) return fail(MFWF_EINVAL, "chained T, Q, U ring step: ring class too long");
+    MFWF_TRY(ring_fork(p));  // class 1 on the side stream, class 0 on the plan's stream
     for (int c = 1; c >= 0; c--) {
         const int cnt = p.fft_class_count[c];
         if (cnt == 0) continue;
+        const hipStream_t st = (c == 1 && p.side) ? p.side : p.stream;
         int ept;
         const int tpb = fft_class_shape(p, c, ept);
         const dim3 grid(8 * nb * ((cnt + 7) / 8));  // whole pairs per XCD
         const size_t lds = fft_cols_lds(p, c, 1);
 #define MFWF_INVFWD_POL(T)                                                                          \
-    hipLaunchKernelGGL((k_fft_inv_fwd_pol<T, 8>), grid, dim3(T), lds, p.stream, p.d_ph32, p.d_ph32p, \
+    hipLaunchKernelGGL((k_fft_inv_fwd_pol<T, 8>), grid, dim3(T), lds, st, p.d_ph32, p.d_ph32p,       \
                        p.C2, nb, cnt, rho, p.d_M, lam, p.tau, MFWF_FFT_ARGS(c, p.nm32))
         if (tpb == 256) MFWF_INVFWD_POL(256);
         else MFWF_INVFWD_POL(512);
 #undef MFWF_INVFWD_POL
         MFWF_HIP(hipGetLastError());
     }
-    return MFWF_OK;
+    return ring_join(p);
 }
 
 int fft_max_length() { return 8 * 1024; }
