@@ -542,8 +542,9 @@ def main():
         "legendre_triples": {"evaluated": work, "full_triangle": full},
         "accuracy_vs_fp64_path": dict(acc, tolerance=1e-5, iterations=K),
         # the dominant kernel: the ring step (inverse transforms, pixel update, forward
-        # transforms), per iteration
-        "roofline": {"bound": "hbm", "kernel": "ring_step (k_fft_inv_fwd, both length classes)",
+        # transforms), per iteration: HIP events on the plan's stream around the fork of the
+        # long class onto the side stream and the join back
+        "roofline": {"bound": "hbm", "kernel": "ring_step (k_fft_inv_fwd, both length classes side by side on two streams)",
                      "achieved": ring_bw / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                      "frac": ring_bw / PEAK_HBM, "algorithmic_bytes": ring_bytes,
                      "ms": kt32["fft_fwd"], "traffic": measured_traffic("ring_step", ring_shape),
