@@ -26,8 +26,12 @@
  *     keeps no reference to it after the call returns.  Host pointers are read during the
  *     call only.
  *   - All device work is enqueued on the plan's stream (the stream given at plan creation,
- *     or the null stream).  mfwf_solve and mfwf_set_covariances synchronise that stream
- *     before returning; the transforms and mfwf_fluctuation_rhs return without waiting.
+ *     or the null stream).  An MFWF_F32 plan also owns one non-blocking stream and two
+ *     events: its iterations fork part of the ring step onto that stream from the plan's
+ *     stream and join it back before the next launch, so the work stays ordered on the
+ *     plan's stream as seen by the caller (graph capture of that stream records both).
+ *     mfwf_solve and mfwf_set_covariances synchronise the plan's stream before returning;
+ *     the transforms and mfwf_fluctuation_rhs return without waiting.
  *   - Status: 0 on success, a negative mfwf_status on failure; mfwf_last_error() then
  *     describes the failure (per calling thread).  On failure, outputs are undefined.
  *   - A plan serves one host thread / stream at a time; distinct plans are independent.
