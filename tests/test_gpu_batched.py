@@ -86,6 +86,24 @@ def test_f32_batch_invariance_and_graph(mf):
     assert torch.equal(a_all, a_eg) and torch.equal(m_all, m_eg)
 
 
+def test_f32_two_stream_ring_step_at_nside_512(mf):
+    """At nside 512 the ring step's two transform classes (4096-point chirp-z transforms in
+    512-thread workgroups, the other rings in 256-thread ones) run side by side, the first on
+    the plan's second stream: graph-replayed, eager, repeated and map-order solves (the last
+    without the chained ring step) give the same bits."""
+    nside, lmax = 512, 128
+    plan, wl, d, M = _setup(mf, nside, lmax, max_batch=3)
+    rng = np.random.default_rng(9)
+    ds = np.stack([d + rng.standard_normal(d.size) for _ in range(3)])
+    a_g, m_g, _ = plan.solve(dev(ds), iters=8)
+    a_e, m_e, _ = plan.solve(dev(ds), iters=8, use_graph=False)
+    a_r, m_r, _ = plan.solve(dev(ds), iters=8)
+    a_m, m_m, _ = plan.solve(dev(ds), iters=8, chained=False)
+    for a, m in ((a_e, m_e), (a_r, m_r), (a_m, m_m)):
+        assert torch.equal(a_g, a) and torch.equal(m_g, m)
+    assert torch.isfinite(a_g).all() and float(a_g.abs().max()) > 0.0
+
+
 def test_f32_diagnostics(mf):
     nside, lmax = 16, 40
     plan, wl, d, M = _setup(mf, nside, lmax, max_batch=4)
